@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the DOCH hot path on one MI355X.
+
+A step is one pass of the whole path over the ultra-large lattice workload:
+parameter setting (eq:alphabeta, Wigner estimate), ``iters`` DOCH iterations
+(eq:FPE / Alg. 1) with the objective and stopping statistics, sign rounding
+and the Ising energy (eq:IsingModel).  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line: edge-updates/s of the whole step, the roofline of the
+dominant kernel (the fused CSR step, HBM-bound) and the CPU oracle's rate on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=10000, help="lattice side (n = L*L spins)")
+    ap.add_argument("--iters", type=int, default=2000)
+    ap.add_argument("--x-dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--cpu-iters", type=int, default=3,
+                    help="oracle iterations timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels_csr.hip", "step_common.h", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2509_01928_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if they were taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(f"{kernel}/{workload}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+                                   "design note, not an implemented path", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import paper_2509_01928_amd as L
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seed, xseed = gen.SEEDS["torus1e4"]
+    t0 = time.time()
+    A = gen.torus_csr(args.L, seed, h_std=0.1)
+    x0 = gen.uniform_x0(A.n + 1, 1, xseed)[:, 0]
+    log(f"generated torus L={args.L}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
+
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    col = torch.from_numpy(A.col).to(dev)
+    val = torch.from_numpy(A.val).to(dev)
+    h = torch.from_numpy(A.h).to(dev)
+    xd = torch.from_numpy(x0).to(dev)
+    ctx = L.ising_create_csr(A.n, A.nnz, rp, col, val, L.ISING_F32, h, L.ISING_F32)
+    del rp, col, val, h
+    torch.cuda.empty_cache()
+    s_out = torch.empty(A.n, dtype=torch.int8, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    x_dtype = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
+    log("context created")
+
+    solve_ms = []
+
+    def step(record):
+        p, lam = L.ising_default_params(ctx, 1.0, 0)          # a1
+        p.x_dtype = x_dtype
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        L.ising_solve(ctx, xd, 1, args.iters, p, None, s_out, want_stats=False)   # a2-a6
+        ev1.record()
+        L.ising_energy(ctx, s_out, 1, E)                       # a7
+        if record:
+            solve_ms.append((ev0, ev1))
+        return p, lam
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        p, lam = step(True)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    elapsed = t_end - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    per_iter_ms = float(np.mean([a.elapsed_time(b) for a, b in solve_ms])) / args.iters
+    energy = float(E.cpu()[0])
+    log(f"{ms_per_step:.1f} ms/step, {per_iter_ms * 1e3:.1f} us/iteration, E={energy:.1f}")
+
+    n, nnz, np1 = A.n, A.nnz, A.n + 1
+    xb = 4 if args.x_dtype == "f32" else 8
+    # algorithmic bytes of one fused iteration: row offsets, column indices and
+    # values once, iterate read once and written once, field once
+    bytes_iter = 4 * (n + 1) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
+    achieved = bytes_iter / (per_iter_ms * 1e-3) / 1e9
+    workload = f"torus{args.L}"
+    traffic = load_traffic("csr_step_kernel", f"{workload}_{args.x_dtype}")
+    edge_updates = float(nnz) * args.iters * args.steps
+    out = {
+        "metric": "edge-updates/s",
+        "value": edge_updates / elapsed,
+        "unit": "edge-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded torus lattice generator)",
+        "config": {
+            "workload": f"2D periodic lattice {args.L}x{args.L} ({n} spins, {nnz} stored "
+                        f"couplings +-1), field h~N(0,0.1^2) as an extra spin, "
+                        f"{args.iters} DOCH iterations per step + parameter setting + "
+                        f"sign rounding + Ising energy",
+            "n": n, "nnz": nnz, "iters": args.iters, "restarts": 1,
+            "x_storage": args.x_dtype, "couplings": "f32 CSR, int32 indices",
+            "arithmetic": "f64", "parallelism": "single GPU",
+        },
+        "iteration_us": per_iter_ms * 1e3,
+        "energy": energy,
+        "lambda_hat": lam,
+        "roofline": {
+            "kernel": "csr_step_kernel",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (traffic["hbm_bytes_per_launch"] if traffic else None),
+            "algorithmic_bytes_per_launch": bytes_iter,
+        },
+    }
+    L.ising_destroy(ctx)
+    del xd, s_out
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline and args.cpu_iters > 0:
+        import oracle as orc
+        log("CPU baseline: building the oracle's matrix")
+        B = orc.problem_matrix(A)
+        del A
+        a_ref, b_ref, _ = orc.default_params(B, 1.0, method="wigner")
+        t0 = time.perf_counter()
+        orc.doch(B, x0, a_ref, b_ref, args.cpu_iters)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": float(nnz) * args.cpu_iters / dt,
+            "unit": "edge-updates/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"full {n}-spin instance, {args.cpu_iters} DOCH iterations of the "
+                      f"single-threaded FP64 oracle ({dt:.1f} s), iteration loop only",
+            "host_cpus": os.cpu_count(),
+        }
+        log(f"CPU baseline {out['cpu_baseline']['value']:.3e} edge-updates/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * ising.h -- C ABI of the MI355X (gfx950) DOCH library.
+ *
+ * DOCH (arXiv 2509.01928, Methods, Alg. 1) minimises the Hamiltonian
+ *   H(x) = beta/4 sum_i x_i^4 - alpha/2 sum_i x_i^2 - 1/2 x^T J x   (eq:Hamilton)
+ * by the fixed-point map
+ *   x^(k+1) = T(x^(k)),  T(x) = cbrt((J + alpha I) x / beta)          (eq:FPE)
+ * and returns s = sign(x^(N)).  The Ising energy of eq:IsingModel,
+ *   E(s) = -1/2 sum_ij J_ij s_i s_j - sum_i h_i s_i,
+ * scores the result.  A field h is handled through the homogeneous model of
+ * Supp. Note 1 (eq:zero_field_ising): one extra spin t couples to spin i with
+ * weight h_i, the iteration runs on n' = n + 1 variables and the answer is
+ * s_i = sign(t) sign(x_i) (Prop. S1).
+ *
+ * Conventions for every entry point
+ *   - Pointers named *_dev are device pointers on the current HIP device;
+ *     pointers named *_host are host pointers.  The caller owns them all.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it asynchronously unless stated otherwise.
+ *   - Every call returns an ising_status and never aborts the process.
+ *     Arguments are validated before any device write, so a failed call
+ *     leaves outputs untouched.  ising_last_error() gives the detail text of
+ *     the last failure on the calling thread.
+ *   - A context is not thread-safe: one solve at a time per context.
+ *     Distinct contexts are independent.
+ *   - Iterates use restart-interleaved storage: a block of R start vectors
+ *     is an n' x R row-major array, element (i, r) at index i*R + r.
+ *     When the problem has a field, row n holds the extra spin t.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ising_ctx ising_ctx;   /* opaque, owned by the library */
+
+typedef enum {
+    ISING_OK = 0,
+    ISING_E_INVALID_ARG = 1,     /* bad size, NULL pointer, bad enum        */
+    ISING_E_NONZERO_DIAG = 2,    /* J_ii != 0 (eq:IsingModel needs J_ii = 0) */
+    ISING_E_NOT_SYMMETRIC = 3,   /* J != J^T (checked by ising_check_symmetric) */
+    ISING_E_OUT_OF_MEMORY = 4,
+    ISING_E_HIP = 5,             /* a HIP runtime call failed               */
+    ISING_E_UNSUPPORTED = 6,     /* valid request this build does not serve */
+    ISING_E_NONFINITE = 7        /* H or r became non-finite during a solve */
+} ising_status;
+
+typedef enum {
+    ISING_F64 = 0,
+    ISING_F32 = 1,
+    ISING_BF16 = 2,
+    ISING_FP8_E4M3 = 3,
+    ISING_I32 = 4
+} ising_dtype;
+
+/* Solver parameters.  alpha and beta are the attractor parameters of
+ * eq:attractor (the "potential params"); eq:alphabeta gives the recommended
+ * values, see ising_default_params. */
+typedef struct {
+    double alpha;          /* > 0                                            */
+    double beta;           /* > 0                                            */
+    double eps;            /* Remark S2 tolerance on r^(k); 0 = run `iters`   */
+    int32_t algo;          /* 0 = DOCH (Alg. 1); 1 = ADOCH (Alg. 2)          */
+    int32_t q;             /* ADOCH look-back window (Alg. 2), >= 1          */
+    int32_t x_dtype;       /* ising_dtype storing the iterate: ISING_F64 or
+                              ISING_F32 (arithmetic is FP64 in both)          */
+    int32_t reserved;      /* must be 0                                      */
+} ising_params;
+
+/* Per-restart result of a solve. */
+typedef struct {
+    int64_t iters_done;    /* iterations performed (<= iters)                */
+    int32_t converged;     /* 1 if r^(k) < eps stopped the run               */
+    int32_t nonfinite;     /* 1 if H or r became non-finite                  */
+    double H_last;         /* H(x^(iters_done-1)), eq:Hamilton               */
+    double r_last;         /* r^(iters_done-1), Remark S2                    */
+} ising_stats;
+
+/* Facts about a context. */
+typedef struct {
+    int64_t n;             /* spins                                          */
+    int64_t n_iter;        /* n' = n + (field ? 1 : 0), length of an iterate */
+    int64_t nnz;           /* stored couplings (CSR) or n*(n-1) (dense)      */
+    int32_t is_dense;
+    int32_t has_field;
+    int32_t integer_J;     /* all couplings are integers (exact int64 energy) */
+    int32_t val_dtype;     /* ising_dtype the couplings are stored in        */
+} ising_info;
+
+/* ---------------------------------------------------------------- create
+ * Copy a symmetric coupling matrix J (J_ii = 0) and an optional field h into
+ * library-owned device memory.  Synchronises `stream` before returning; the
+ * caller may free its buffers afterwards.
+ *
+ * ising_create_csr: CSR of the full matrix (both triangles), as used for the
+ * sparse instances of Supp. Note 9.
+ *   n            spins, 1 <= n < 2^31 - 1
+ *   nnz          stored entries, 0 <= nnz < 2^31
+ *   row_ptr_dev  int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_dev      int32[nnz], 0 <= col < n, ascending within each row
+ *   val_dev      nnz values of type vt (ISING_F32 or ISING_F64)
+ *   h_dev        NULL (no field) or n values of type ht (ISING_F32 / F64)
+ * Errors: ISING_E_INVALID_ARG for a malformed CSR (checked on the device),
+ * ISING_E_NONZERO_DIAG if a stored diagonal entry is nonzero.
+ * Symmetry is not checked here (see ising_check_symmetric). */
+ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev,
+                              const int32_t* col_dev, const void* val_dev,
+                              int32_t vt, const void* h_dev, int32_t ht,
+                              void* stream, ising_ctx** out);
+
+/* ising_create_dense: row-major dense J with leading dimension ld >= n.
+ *   J_dev  n x ld values of type jt (ISING_F64)
+ *   h_dev  as above.
+ * Errors: ISING_E_INVALID_ARG, ISING_E_NONZERO_DIAG. */
+ising_status ising_create_dense(int64_t n, const void* J_dev, int32_t jt, int64_t ld,
+                                const void* h_dev, int32_t ht, void* stream,
+                                ising_ctx** out);
+
+/* Release a context and all its device memory (NULL is ignored). */
+void ising_destroy(ising_ctx* ctx);
+
+ising_status ising_get_info(const ising_ctx* ctx, ising_info* out);
+
+/* Check J == J^T exactly on the device (CSR: every (i,j,v) has a matching
+ * (j,i,v)).  Synchronous.  ISING_OK or ISING_E_NOT_SYMMETRIC. */
+ising_status ising_check_symmetric(ising_ctx* ctx, void* stream);
+
+/* ------------------------------------------------------- parameter setting
+ * eq:alphabeta with Supp. Note 6, on the homogeneous matrix Jhat (n' spins):
+ *   lambda = lambda_max(-Jhat): power iteration on c I - Jhat,
+ *            c = max_i sum_j |Jhat_ij|, when n' < 10^4 (stops when the
+ *            Rayleigh quotient changes by <= 1e-12 relative, at most 1e5
+ *            iterations); otherwise Wigner's estimate 2 <Jhat> sqrt(n') with
+ *            <Jhat>^2 the sample variance of the n'(n'-1) off-diagonal
+ *            entries (eq:estimate_eig_J)
+ *   alpha  = eta * lambda
+ *   beta   = n'^(3/2) * (alpha + max_i sum_{j != i} |Jhat_ij|)
+ * Fills *out (eps = 0, algo = 0, q = 5, x_dtype = ISING_F64) and writes the
+ * lambda used to *lambda_out when non-NULL.  Synchronous on `stream`.
+ * method: 0 = as above, 1 = always power iteration, 2 = always Wigner. */
+ising_status ising_default_params(ising_ctx* ctx, double eta, int32_t method,
+                                  void* stream, ising_params* out,
+                                  double* lambda_out);
+
+/* ------------------------------------------------------------------ solve
+ * Run `iters` iterations of DOCH (Alg. 1) -- or ADOCH (Alg. 2) when
+ * params->algo == 1 -- from R start vectors at once, then round.
+ *   x0_dev    double[n' * R] start vectors (interleaved, see above)
+ *   R         restarts, 1 <= R <= 1024
+ *   iters     >= 0
+ *   x_out_dev NULL or double[n' * R]: the final iterates x^(iters_done)
+ *   s_out_dev NULL or int8[n * R]: spins s_i = sign(x_i) (sign(0) = +1),
+ *             multiplied by sign(t) when there is a field
+ *   stats_host NULL or ising_stats[R]; when given, the call synchronises
+ *             `stream` and fills it.
+ * Each restart stops on its own when params->eps > 0 and r^(k) < eps.
+ * H(x^(k)) and r^(k) of every iteration are kept for ising_get_log.
+ * Errors: ISING_E_INVALID_ARG; ISING_E_NONFINITE (only detectable when
+ * stats_host is given) if H or r became non-finite -- the restart then
+ * stops at that iteration. */
+ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R,
+                         int64_t iters, const ising_params* params,
+                         double* x_out_dev, int8_t* s_out_dev,
+                         ising_stats* stats_host, void* stream);
+
+/* Copy the per-iteration log of the last solve of restart `restart`:
+ * H_host[k] = H(x^(first+k)), r_host[k] = r^(first+k) for k < count.
+ * Either output may be NULL.  Synchronous on `stream`.  Entries past the
+ * restart's iters_done are undefined. */
+ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first,
+                           int64_t count, double* H_host, double* r_host,
+                           void* stream);
+
+/* ----------------------------------------------------------------- energy
+ * eq:IsingModel for R spin vectors:
+ *   s_dev     int8[n * R] (interleaved, values +-1)
+ *   E_dev     NULL or double[R]: -1/2 s^T J s - h^T s in FP64
+ *   E_int_dev NULL or int64[R]: exact -1/2 s^T J s in integer arithmetic;
+ *             requires integer couplings (ISING_E_UNSUPPORTED otherwise);
+ *             the field term is not included.
+ * Asynchronous on `stream`. */
+ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
+                          double* E_dev, int64_t* E_int_dev, void* stream);
+
+/* ------------------------------------------------------------------ misc */
+const char* ising_status_string(ising_status s);
+const char* ising_last_error(void);
+/* Library version as "major.minor.patch". */
+const char* ising_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISING_H */

@@ -1,0 +1,203 @@
+"""Python binding of the gfx950 DOCH library (``libising.so``, include/ising.h).
+
+The functions below have the C names and the C argument order; they only
+marshal arguments (device pointers as integers, torch tensors via
+``data_ptr()``, the current torch stream as ``hipStream_t``).  Every step of
+the hot path runs in the library's HIP kernels.  Importing this module fails
+loudly if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+__all__ = [
+    "ISING_OK", "ISING_F64", "ISING_F32", "ISING_BF16", "ISING_FP8_E4M3", "ISING_I32",
+    "IsingError", "ising_params", "ising_stats", "ising_info", "lib", "LIB_PATH",
+    "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
+    "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
+    "ising_energy", "ising_status_string", "ising_last_error", "ising_version",
+    "ptr", "current_stream",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libising.so")
+
+ISING_OK = 0
+ISING_E_INVALID_ARG = 1
+ISING_E_NONZERO_DIAG = 2
+ISING_E_NOT_SYMMETRIC = 3
+ISING_E_OUT_OF_MEMORY = 4
+ISING_E_HIP = 5
+ISING_E_UNSUPPORTED = 6
+ISING_E_NONFINITE = 7
+
+ISING_F64 = 0
+ISING_F32 = 1
+ISING_BF16 = 2
+ISING_FP8_E4M3 = 3
+ISING_I32 = 4
+
+
+class ising_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("eps", ctypes.c_double),
+                ("algo", ctypes.c_int32), ("q", ctypes.c_int32), ("x_dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ising_stats(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int64), ("converged", ctypes.c_int32),
+                ("nonfinite", ctypes.c_int32), ("H_last", ctypes.c_double),
+                ("r_last", ctypes.c_double)]
+
+
+class ising_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_iter", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("is_dense", ctypes.c_int32), ("has_field", ctypes.c_int32),
+                ("integer_J", ctypes.c_int32), ("val_dtype", ctypes.c_int32)]
+
+
+class IsingError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {ising_status_string(status)} ({status}): {ising_last_error()}")
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2509_01928_amd.build "
+                      "or __graft_entry__.build()); there is no fallback path")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_d = ctypes.c_double
+_st = ctypes.c_int
+
+_SIGS = {
+    "ising_create_csr": (_st, [_i64, _i64, _p, _p, _p, _i32, _p, _i32, _p, ctypes.POINTER(_p)]),
+    "ising_create_dense": (_st, [_i64, _p, _i32, _i64, _p, _i32, _p, ctypes.POINTER(_p)]),
+    "ising_destroy": (None, [_p]),
+    "ising_get_info": (_st, [_p, ctypes.POINTER(ising_info)]),
+    "ising_check_symmetric": (_st, [_p, _p]),
+    "ising_default_params": (_st, [_p, _d, _i32, _p, ctypes.POINTER(ising_params), ctypes.POINTER(_d)]),
+    "ising_solve": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
+    "ising_get_log": (_st, [_p, _i32, _i64, _i64, _p, _p, _p]),
+    "ising_energy": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "ising_status_string": (ctypes.c_char_p, [_st]),
+    "ising_last_error": (ctypes.c_char_p, []),
+    "ising_version": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def ising_status_string(status: int) -> str:
+    return lib.ising_status_string(int(status)).decode()
+
+
+def ising_last_error() -> str:
+    return lib.ising_last_error().decode()
+
+
+def ising_version() -> str:
+    return lib.ising_version().decode()
+
+
+def ptr(t) -> Optional[int]:
+    """Device (or host) address of a torch tensor / numpy array, None for None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def current_stream() -> int:
+    """hipStream_t of torch's current stream on the current device."""
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check(status: int, where: str) -> int:
+    if status != ISING_OK:
+        raise IsingError(status, where)
+    return status
+
+
+def ising_create_csr(n, nnz, row_ptr, col, val, vt, h=None, ht=ISING_F32, stream=None):
+    """Returns the context handle (int).  row_ptr/col/val/h: device pointers or tensors."""
+    out = _p()
+    _check(lib.ising_create_csr(int(n), int(nnz), ptr(row_ptr), ptr(col), ptr(val), int(vt),
+                                ptr(h), int(ht), stream if stream is not None else current_stream(),
+                                ctypes.byref(out)), "ising_create_csr")
+    return out.value
+
+
+def ising_create_dense(n, J, jt, ld, h=None, ht=ISING_F32, stream=None):
+    out = _p()
+    _check(lib.ising_create_dense(int(n), ptr(J), int(jt), int(ld), ptr(h), int(ht),
+                                  stream if stream is not None else current_stream(),
+                                  ctypes.byref(out)), "ising_create_dense")
+    return out.value
+
+
+def ising_destroy(ctx) -> None:
+    if ctx:
+        lib.ising_destroy(ctx)
+
+
+def ising_get_info(ctx) -> ising_info:
+    info = ising_info()
+    _check(lib.ising_get_info(ctx, ctypes.byref(info)), "ising_get_info")
+    return info
+
+
+def ising_check_symmetric(ctx, stream=None) -> bool:
+    st = lib.ising_check_symmetric(ctx, stream if stream is not None else current_stream())
+    if st == ISING_E_NOT_SYMMETRIC:
+        return False
+    _check(st, "ising_check_symmetric")
+    return True
+
+
+def ising_default_params(ctx, eta=1.0, method=0, stream=None):
+    """Returns (ising_params, lambda)."""
+    p = ising_params()
+    lam = _d(0.0)
+    _check(lib.ising_default_params(ctx, float(eta), int(method),
+                                    stream if stream is not None else current_stream(),
+                                    ctypes.byref(p), ctypes.byref(lam)), "ising_default_params")
+    return p, lam.value
+
+
+def ising_solve(ctx, x0, R, iters, params, x_out=None, s_out=None, want_stats=True,
+                stream=None, check=True):
+    """Returns a list of ising_stats (empty if want_stats is False)."""
+    stats = (ising_stats * int(R))() if want_stats else None
+    st = lib.ising_solve(ctx, ptr(x0), int(R), int(iters), ctypes.byref(params), ptr(x_out),
+                         ptr(s_out), ctypes.cast(stats, _p) if stats is not None else None,
+                         stream if stream is not None else current_stream())
+    if check:
+        _check(st, "ising_solve")
+    return list(stats) if stats is not None else []
+
+
+def ising_get_log(ctx, restart, first, count, stream=None):
+    """Returns (H, r) as numpy arrays."""
+    import numpy as np
+    H = np.empty(int(count), dtype=np.float64)
+    r = np.empty(int(count), dtype=np.float64)
+    _check(lib.ising_get_log(ctx, int(restart), int(first), int(count), H.ctypes.data,
+                             r.ctypes.data, stream if stream is not None else current_stream()),
+           "ising_get_log")
+    return H, r
+
+
+def ising_energy(ctx, s, R, E=None, E_int=None, stream=None):
+    _check(lib.ising_energy(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
+                            stream if stream is not None else current_stream()), "ising_energy")

@@ -1,0 +1,581 @@
+// api.hip -- the C ABI of include/ising.h: argument checking, ownership of
+// device memory, the host-side DOCH loop (one kernel launch per iteration on
+// the caller's stream) and the parameter setting of eq:alphabeta.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ising_internal.h"
+
+using doch::CsrView;
+using doch::DenseView;
+using doch::MatrixStats;
+using doch::RestartState;
+using doch::StepArgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ising_status fail(ising_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+ising_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? ISING_E_OUT_OF_MEMORY : ISING_E_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIP_OK(call, what)                                       \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what);         \
+    } while (0)
+
+size_t dtype_size(int t) {
+    switch (t) {
+        case ISING_F64: return 8;
+        case ISING_F32: return 4;
+        case ISING_BF16: return 2;
+        case ISING_FP8_E4M3: return 1;
+        case ISING_I32: return 4;
+        default: return 0;
+    }
+}
+
+bool float_dtype(int t) { return t == ISING_F32 || t == ISING_F64; }
+
+template <typename T>
+hipError_t dev_alloc(T** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    return hipMalloc(reinterpret_cast<void**>(p), bytes);
+}
+
+template <typename T>
+void dev_free(T*& p) {
+    if (p) (void)hipFree(static_cast<void*>(p));
+    p = nullptr;
+}
+
+// Grow a workspace buffer to at least `bytes` (contents are not preserved).
+template <typename T>
+hipError_t ensure(T** p, size_t* cap, size_t bytes) {
+    if (*p && *cap >= bytes) return hipSuccess;
+    dev_free(*p);
+    *cap = 0;
+    hipError_t e = dev_alloc(p, bytes);
+    if (e == hipSuccess) *cap = bytes;
+    return e;
+}
+
+CsrView csr_view(const ising_ctx* c) {
+    CsrView v;
+    v.n = c->n;
+    v.nnz = c->nnz;
+    v.rp = c->rp;
+    v.col = c->col;
+    v.val = c->val;
+    v.vt = c->vt;
+    v.h = c->h;
+    v.ht = c->ht;
+    return v;
+}
+
+DenseView dense_view(const ising_ctx* c) {
+    DenseView v;
+    v.n = c->n;
+    v.ld = c->ld;
+    v.J = c->J;
+    v.h = c->h;
+    v.ht = c->ht;
+    return v;
+}
+
+// Row blocks for the CSR kernels: consecutive rows, at most kBlockThreads
+// rows and kBlockNnz stored entries each; a longer row stands alone.
+std::vector<int32_t> make_blocks(const std::vector<int32_t>& rp, int64_t n) {
+    std::vector<int32_t> blk;
+    blk.reserve(static_cast<size_t>(n / 64 + 2));
+    int64_t r = 0;
+    blk.push_back(0);
+    while (r < n) {
+        int64_t r0 = r;
+        int64_t e0 = rp[r];
+        if (rp[r + 1] - e0 > doch::kBlockNnz) {
+            r = r0 + 1;
+        } else {
+            while (r < n && r - r0 < doch::kBlockThreads && rp[r + 1] - e0 <= doch::kBlockNnz) ++r;
+        }
+        blk.push_back(static_cast<int32_t>(r));
+    }
+    return blk;
+}
+
+void free_ctx(ising_ctx* c) {
+    if (!c) return;
+    dev_free(c->rp);
+    dev_free(c->col);
+    dev_free(c->val);
+    dev_free(c->h);
+    dev_free(c->J);
+    dev_free(c->blk);
+    dev_free(c->xbuf[0]);
+    dev_free(c->xbuf[1]);
+    dev_free(c->partials);
+    dev_free(c->ticket);
+    dev_free(c->state);
+    dev_free(c->log);
+    dev_free(c->scratch);
+    delete c;
+}
+
+ising_status copy_field(ising_ctx* c, const void* h_dev, int32_t ht, hipStream_t s) {
+    if (!h_dev) return ISING_OK;
+    if (!float_dtype(ht)) return fail(ISING_E_INVALID_ARG, "field dtype must be ISING_F32 or ISING_F64");
+    const size_t bytes = static_cast<size_t>(c->n) * dtype_size(ht);
+    HIP_OK(dev_alloc(&c->h, bytes), "hipMalloc(h)");
+    HIP_OK(hipMemcpyAsync(c->h, h_dev, bytes, hipMemcpyDeviceToDevice, s), "copy h");
+    c->ht = ht;
+    c->has_field = true;
+    c->np = c->n + 1;
+    return ISING_OK;
+}
+
+// Scratch of the context (setup, energy): flags, tickets and partial sums.
+struct Scratch {
+    int32_t* flags;           // 8 ints
+    unsigned int* tickets;    // 1024
+    MatrixStats* stats;       // 1
+    double* mu_log;           // 2 * kPowerChunk
+    double* vecs;             // 2 * np (power iteration)
+    double* partials;         // rest
+    size_t partial_doubles;
+};
+
+constexpr int kPowerChunk = 64;
+constexpr int kMaxR = 1024;
+
+ising_status ensure_scratch(ising_ctx* c, size_t partial_doubles, Scratch* out) {
+    const size_t head = 256 + kMaxR * sizeof(unsigned int) + sizeof(MatrixStats) +
+                        2 * kPowerChunk * sizeof(double);
+    const size_t vec_bytes = 2 * static_cast<size_t>(c->np) * sizeof(double);
+    const size_t need = head + vec_bytes + partial_doubles * sizeof(double) + 256;
+    if (!c->scratch || c->scratch_bytes < need) {
+        dev_free(c->scratch);
+        c->scratch_bytes = 0;
+        HIP_OK(dev_alloc(&c->scratch, need), "hipMalloc(scratch)");
+        HIP_OK(hipMemset(c->scratch, 0, need), "hipMemset(scratch)");
+        c->scratch_bytes = need;
+    }
+    char* base = reinterpret_cast<char*>(c->scratch);
+    out->flags = reinterpret_cast<int32_t*>(base);
+    out->tickets = reinterpret_cast<unsigned int*>(base + 256);
+    out->stats = reinterpret_cast<MatrixStats*>(base + 256 + kMaxR * sizeof(unsigned int));
+    out->mu_log = reinterpret_cast<double*>(base + 256 + kMaxR * sizeof(unsigned int) +
+                                            sizeof(MatrixStats));
+    out->vecs = out->mu_log + 2 * kPowerChunk;
+    out->partials = out->vecs + 2 * c->np;
+    out->partial_doubles = partial_doubles;
+    return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ising_version(void) { return "0.1.0"; }
+
+const char* ising_last_error(void) { return g_last_error.c_str(); }
+
+const char* ising_status_string(ising_status s) {
+    switch (s) {
+        case ISING_OK: return "ok";
+        case ISING_E_INVALID_ARG: return "invalid argument";
+        case ISING_E_NONZERO_DIAG: return "nonzero diagonal coupling";
+        case ISING_E_NOT_SYMMETRIC: return "coupling matrix is not symmetric";
+        case ISING_E_OUT_OF_MEMORY: return "out of device memory";
+        case ISING_E_HIP: return "HIP runtime error";
+        case ISING_E_UNSUPPORTED: return "unsupported request";
+        case ISING_E_NONFINITE: return "non-finite objective";
+    }
+    return "unknown status";
+}
+
+ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev,
+                              const int32_t* col_dev, const void* val_dev, int32_t vt,
+                              const void* h_dev, int32_t ht, void* stream, ising_ctx** out) {
+    if (!out) return fail(ISING_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= 2147483647LL) return fail(ISING_E_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (nnz < 0 || nnz >= 2147483647LL) return fail(ISING_E_INVALID_ARG, "nnz=%lld out of range", (long long)nnz);
+    if (!row_ptr_dev) return fail(ISING_E_INVALID_ARG, "row_ptr is NULL");
+    if (nnz > 0 && (!col_dev || !val_dev)) return fail(ISING_E_INVALID_ARG, "col/val NULL with nnz > 0");
+    if (!float_dtype(vt)) return fail(ISING_E_INVALID_ARG, "CSR values must be ISING_F32 or ISING_F64");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ising_ctx* c = new ising_ctx();
+    ising_status st = ISING_OK;
+    auto bail = [&](ising_status e) { free_ctx(c); return e; };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(ISING_E_HIP, "no HIP device"));
+    c->dense = false;
+    c->n = n;
+    c->np = n;
+    c->nnz = nnz;
+    c->vt = vt;
+    hipError_t e;
+    if ((e = dev_alloc(&c->rp, (n + 1) * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(rp)"));
+    if ((e = dev_alloc(&c->col, nnz * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(col)"));
+    if ((e = dev_alloc(&c->val, nnz * dtype_size(vt))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(val)"));
+    if ((e = hipMemcpyAsync(c->rp, row_ptr_dev, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return bail(hip_fail(e, "copy row_ptr"));
+    if (nnz > 0) {
+        if ((e = hipMemcpyAsync(c->col, col_dev, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return bail(hip_fail(e, "copy col"));
+        if ((e = hipMemcpyAsync(c->val, val_dev, nnz * dtype_size(vt), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return bail(hip_fail(e, "copy val"));
+    }
+    if ((st = copy_field(c, h_dev, ht, s)) != ISING_OK) return bail(st);
+    Scratch sc;
+    if ((st = ensure_scratch(c, 0, &sc)) != ISING_OK) return bail(st);
+    if ((e = hipMemsetAsync(sc.flags, 0, 8 * sizeof(int32_t), s)) != hipSuccess) return bail(hip_fail(e, "memset"));
+    if ((e = doch::launch_csr_validate(csr_view(c), sc.flags, s)) != hipSuccess) return bail(hip_fail(e, "validate"));
+    int32_t flags[8];
+    if ((e = hipMemcpyAsync(flags, sc.flags, sizeof(flags), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return bail(hip_fail(e, "copy flags"));
+    std::vector<int32_t> rp_host(static_cast<size_t>(n + 1));
+    if ((e = hipMemcpyAsync(rp_host.data(), c->rp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return bail(hip_fail(e, "copy row_ptr to host"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sync"));
+    if (rp_host[0] != 0 || rp_host[n] != nnz) flags[0] = 1;
+    for (int64_t i = 0; i < n && !flags[0]; ++i)
+        if (rp_host[i + 1] < rp_host[i]) flags[0] = 1;
+    if (flags[0]) return bail(fail(ISING_E_INVALID_ARG, "malformed CSR (offsets, column range or order)"));
+    if (flags[1]) return bail(fail(ISING_E_NONZERO_DIAG, "a diagonal coupling J_ii is nonzero"));
+    c->integer_J = flags[2] == 0;
+    std::vector<int32_t> blk = make_blocks(rp_host, n);
+    c->nblk = static_cast<int64_t>(blk.size()) - 1;
+    if ((e = dev_alloc(&c->blk, blk.size() * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(blk)"));
+    if ((e = hipMemcpy(c->blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "copy blocks"));
+    *out = c;
+    return ISING_OK;
+}
+
+ising_status ising_create_dense(int64_t n, const void* J_dev, int32_t jt, int64_t ld,
+                                const void* h_dev, int32_t ht, void* stream, ising_ctx** out) {
+    if (!out) return fail(ISING_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 1000000) return fail(ISING_E_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (ld < n) return fail(ISING_E_INVALID_ARG, "ld < n");
+    if (!J_dev) return fail(ISING_E_INVALID_ARG, "J is NULL");
+    if (jt != ISING_F64) return fail(ISING_E_UNSUPPORTED, "dense J must be ISING_F64");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ising_ctx* c = new ising_ctx();
+    ising_status st = ISING_OK;
+    auto bail = [&](ising_status e) { free_ctx(c); return e; };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(ISING_E_HIP, "no HIP device"));
+    c->dense = true;
+    c->n = n;
+    c->np = n;
+    c->nnz = n * (n - 1);
+    c->vt = ISING_F64;
+    c->ld = n;
+    hipError_t e;
+    if ((e = dev_alloc(&c->J, static_cast<size_t>(n) * n * sizeof(double))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc(J)"));
+    if ((e = hipMemcpy2DAsync(c->J, n * sizeof(double), J_dev, ld * sizeof(double), n * sizeof(double), n,
+                              hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return bail(hip_fail(e, "copy J"));
+    if ((st = copy_field(c, h_dev, ht, s)) != ISING_OK) return bail(st);
+    Scratch sc;
+    if ((st = ensure_scratch(c, 0, &sc)) != ISING_OK) return bail(st);
+    if ((e = hipMemsetAsync(sc.flags, 0, 8 * sizeof(int32_t), s)) != hipSuccess) return bail(hip_fail(e, "memset"));
+    if ((e = doch::launch_dense_validate(dense_view(c), sc.flags, s)) != hipSuccess) return bail(hip_fail(e, "validate"));
+    int32_t flags[8];
+    if ((e = hipMemcpyAsync(flags, sc.flags, sizeof(flags), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return bail(hip_fail(e, "copy flags"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sync"));
+    if (flags[0]) return bail(fail(ISING_E_INVALID_ARG, "J has a non-finite entry"));
+    if (flags[1]) return bail(fail(ISING_E_NONZERO_DIAG, "a diagonal coupling J_ii is nonzero"));
+    c->integer_J = flags[2] == 0;
+    *out = c;
+    return ISING_OK;
+}
+
+void ising_destroy(ising_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_ctx(ctx);
+}
+
+ising_status ising_get_info(const ising_ctx* ctx, ising_info* out) {
+    if (!ctx || !out) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    out->n = ctx->n;
+    out->n_iter = ctx->np;
+    out->nnz = ctx->nnz;
+    out->is_dense = ctx->dense ? 1 : 0;
+    out->has_field = ctx->has_field ? 1 : 0;
+    out->integer_J = ctx->integer_J ? 1 : 0;
+    out->val_dtype = ctx->vt;
+    return ISING_OK;
+}
+
+ising_status ising_check_symmetric(ising_ctx* ctx, void* stream) {
+    if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    ising_status st = ensure_scratch(ctx, 0, &sc);
+    if (st != ISING_OK) return st;
+    HIP_OK(hipMemsetAsync(sc.flags, 0, sizeof(int32_t), s), "memset");
+    if (ctx->dense) HIP_OK(doch::launch_dense_symcheck(dense_view(ctx), sc.flags, s), "symcheck");
+    else HIP_OK(doch::launch_csr_symcheck(csr_view(ctx), sc.flags, s), "symcheck");
+    int32_t bad = 0;
+    HIP_OK(hipMemcpyAsync(&bad, sc.flags, sizeof(bad), hipMemcpyDeviceToHost, s), "copy");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    return bad ? fail(ISING_E_NOT_SYMMETRIC, "J != J^T") : ISING_OK;
+}
+
+ising_status ising_default_params(ising_ctx* ctx, double eta, int32_t method, void* stream,
+                                  ising_params* out, double* lambda_out) {
+    if (!ctx || !out) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(ISING_E_INVALID_ARG, "eta must be > 0");
+    if (method < 0 || method > 2) return fail(ISING_E_INVALID_ARG, "method must be 0, 1 or 2");
+    if (ctx->np < 2) return fail(ISING_E_INVALID_ARG, "parameter setting needs n' >= 2");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int grid = 1024;
+    Scratch sc;
+    ising_status st = ensure_scratch(ctx, static_cast<size_t>(2048) * 4, &sc);
+    if (st != ISING_OK) return st;
+    HIP_OK(hipMemsetAsync(sc.tickets, 0, sizeof(unsigned int), s), "memset");
+    // pass 0: row sums, sum, count; pass 1: squared deviations from the mean
+    const double np = static_cast<double>(ctx->np);
+    const double m = np * (np - 1.0);
+    MatrixStats ms;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double mean = pass == 0 ? 0.0 : ms.s1 / m;
+        if (ctx->dense)
+            HIP_OK(doch::launch_dense_stats(dense_view(ctx), mean, pass, sc.partials, sc.tickets, grid, sc.stats, s), "stats");
+        else
+            HIP_OK(doch::launch_csr_stats(csr_view(ctx), mean, pass, sc.partials, sc.tickets, grid, sc.stats, s), "stats");
+        HIP_OK(hipMemcpyAsync(&ms, sc.stats, sizeof(ms), hipMemcpyDeviceToHost, s), "copy stats");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+    }
+    const double jbar = ms.s1 / m;
+    // entries not stored are zeros: each adds (0 - jbar)^2
+    const double ss = ms.ss + (m - ms.stored) * jbar * jbar;
+    const double wigner = 2.0 * std::sqrt(ss / m) * std::sqrt(np);
+    double lambda = wigner;
+    const bool power = method == 1 || (method == 0 && ctx->np < 10000);
+    if (power) {
+        // power iteration on c I - Jhat from a fixed pseudo-random start
+        const double c = ms.abs_max;
+        const int64_t nv = ctx->np;
+        std::vector<double> v0(static_cast<size_t>(nv));
+        uint64_t z = 0x9E3779B97F4A7C15ULL;
+        double nrm = 0.0;
+        for (int64_t i = 0; i < nv; ++i) {
+            z += 0x9E3779B97F4A7C15ULL;   // SplitMix64 (Steele, Lea, Flood 2014)
+            uint64_t q = z;
+            q = (q ^ (q >> 30)) * 0xBF58476D1CE4E5B9ULL;
+            q = (q ^ (q >> 27)) * 0x94D049BB133111EBULL;
+            q ^= q >> 31;
+            v0[i] = 2.0 * (static_cast<double>(q >> 11) * 0x1.0p-53) - 1.0;
+            nrm += v0[i] * v0[i];
+        }
+        nrm = std::sqrt(nrm);
+        for (auto& x : v0) x /= nrm;
+        double* v = sc.vecs;
+        double* w = sc.vecs + nv;
+        HIP_OK(hipMemcpyAsync(v, v0.data(), nv * sizeof(double), hipMemcpyHostToDevice, s), "copy v0");
+        const int64_t maxit = 100000;
+        const double tol = 1e-12;
+        double mu = 0.0, mu_prev = 0.0;
+        bool conv = false;
+        std::vector<double> mlog(2 * kPowerChunk);
+        for (int64_t k0 = 0; k0 < maxit && !conv; k0 += kPowerChunk) {
+            const int64_t cnt = std::min<int64_t>(kPowerChunk, maxit - k0);
+            for (int64_t j = 0; j < cnt; ++j) {
+                if (ctx->dense)
+                    HIP_OK(doch::launch_dense_power_step(dense_view(ctx), c, v, w, sc.partials, sc.tickets,
+                                                         doch::dense_step_grid(ctx->n), sc.mu_log, j, s), "power");
+                else
+                    HIP_OK(doch::launch_csr_power_step(csr_view(ctx), c, v, w, sc.partials, sc.tickets, grid,
+                                                       sc.mu_log, j, s), "power");
+                HIP_OK(doch::launch_normalize(w, v, sc.mu_log, j, nv, s), "normalize");
+            }
+            HIP_OK(hipMemcpyAsync(mlog.data(), sc.mu_log, 2 * cnt * sizeof(double), hipMemcpyDeviceToHost, s),
+                   "copy mu");
+            HIP_OK(hipStreamSynchronize(s), "sync");
+            for (int64_t j = 0; j < cnt; ++j) {
+                mu = mlog[2 * j];
+                if (!std::isfinite(mu)) return fail(ISING_E_NONFINITE, "power iteration diverged");
+                if ((k0 + j) > 0 && std::fabs(mu - mu_prev) <= tol * std::fabs(mu)) {
+                    conv = true;
+                    break;
+                }
+                mu_prev = mu;
+                if (mlog[2 * j + 1] == 0.0) { conv = true; break; }
+            }
+        }
+        lambda = mu - c;
+    }
+    ising_params p;
+    p.alpha = eta * lambda;
+    p.beta = std::pow(np, 1.5) * (p.alpha + ms.rowsum_max);
+    p.eps = 0.0;
+    p.algo = 0;
+    p.q = 5;
+    p.x_dtype = ISING_F64;
+    p.reserved = 0;
+    *out = p;
+    if (lambda_out) *lambda_out = lambda;
+    return ISING_OK;
+}
+
+ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t iters,
+                         const ising_params* params, double* x_out_dev, int8_t* s_out_dev,
+                         ising_stats* stats_host, void* stream) {
+    if (!ctx || !params) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (!x0_dev) return fail(ISING_E_INVALID_ARG, "x0 is NULL");
+    if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
+    if (iters < 0) return fail(ISING_E_INVALID_ARG, "iters < 0");
+    const ising_params& p = *params;
+    if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return fail(ISING_E_INVALID_ARG, "alpha must be finite and > 0");
+    if (!(p.beta > 0.0) || !std::isfinite(p.beta)) return fail(ISING_E_INVALID_ARG, "beta must be finite and > 0");
+    if (!(p.eps >= 0.0)) return fail(ISING_E_INVALID_ARG, "eps must be >= 0");
+    if (p.x_dtype != ISING_F64 && p.x_dtype != ISING_F32) return fail(ISING_E_INVALID_ARG, "x_dtype must be F64 or F32");
+    if (p.reserved != 0) return fail(ISING_E_INVALID_ARG, "reserved must be 0");
+    if (p.algo != 0 && p.algo != 1) return fail(ISING_E_INVALID_ARG, "algo must be 0 or 1");
+    if (p.algo == 1) return fail(ISING_E_UNSUPPORTED, "ADOCH is not available in this build");
+    if (R != 1) return fail(ISING_E_UNSUPPORTED, "R > 1 is not available in this build");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t elt = p.x_dtype == ISING_F64 ? 8 : 4;
+    const size_t xbytes = static_cast<size_t>(ctx->np) * R * elt;
+    if (!ctx->xbuf[0] || ctx->xbuf_bytes < xbytes) {
+        dev_free(ctx->xbuf[0]);
+        dev_free(ctx->xbuf[1]);
+        ctx->xbuf_bytes = 0;
+        HIP_OK(dev_alloc(&ctx->xbuf[0], xbytes), "hipMalloc(x)");
+        HIP_OK(dev_alloc(&ctx->xbuf[1], xbytes), "hipMalloc(x)");
+        ctx->xbuf_bytes = xbytes;
+    }
+    const int grid = ctx->dense ? doch::dense_step_grid(ctx->n) : doch::csr_step_grid(ctx->nblk);
+    HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
+                  static_cast<size_t>(grid) * R * doch::kNumPartials * sizeof(double)), "hipMalloc(partials)");
+    if (!ctx->ticket) {
+        HIP_OK(dev_alloc(&ctx->ticket, kMaxR * sizeof(unsigned int)), "hipMalloc(ticket)");
+        HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
+        ctx->state_cap = kMaxR;
+    }
+    HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)),
+           "hipMalloc(log)");
+    HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, s), "init");
+    HIP_OK(doch::launch_load_x0(x0_dev, ctx->xbuf[0], p.x_dtype, ctx->np * R, s), "load x0");
+    StepArgs a;
+    a.x_dtype = p.x_dtype;
+    a.R = R;
+    a.alpha = p.alpha;
+    a.beta = p.beta;
+    a.eps = p.eps;
+    a.partials = ctx->partials;
+    a.ticket = ctx->ticket;
+    a.state = ctx->state;
+    a.all_done_flag = 0;
+    const CsrView cv = csr_view(ctx);
+    const DenseView dv = dense_view(ctx);
+    for (int64_t k = 0; k < iters; ++k) {
+        a.x_old = ctx->xbuf[k & 1];
+        a.x_new = ctx->xbuf[(k + 1) & 1];
+        a.k = k;
+        a.log = ctx->log;
+        hipError_t e = ctx->dense ? doch::launch_dense_step(dv, a, grid, s)
+                                  : doch::launch_csr_step(cv, ctx->blk, ctx->nblk, a, grid, s);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+    ctx->last_R = R;
+    ctx->last_iters = iters;
+    if (x_out_dev || s_out_dev)
+        HIP_OK(doch::launch_finish(ctx->xbuf[0], ctx->xbuf[1], p.x_dtype, ctx->state, ctx->n, ctx->np, R,
+                                   ctx->has_field, x_out_dev, s_out_dev, s), "finish");
+    if (stats_host) {
+        std::vector<RestartState> hs(static_cast<size_t>(R));
+        HIP_OK(hipMemcpyAsync(hs.data(), ctx->state, R * sizeof(RestartState), hipMemcpyDeviceToHost, s),
+               "copy state");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+        bool bad = false;
+        for (int r = 0; r < R; ++r) {
+            stats_host[r].iters_done = hs[r].iters_done;
+            stats_host[r].converged = hs[r].converged;
+            stats_host[r].nonfinite = hs[r].nonfinite;
+            stats_host[r].H_last = hs[r].H_last;
+            stats_host[r].r_last = hs[r].r_last;
+            bad = bad || hs[r].nonfinite;
+        }
+        if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
+    }
+    return ISING_OK;
+}
+
+ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first, int64_t count,
+                           double* H_host, double* r_host, void* stream) {
+    if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
+    if (restart < 0 || restart >= std::max(ctx->last_R, 1)) return fail(ISING_E_INVALID_ARG, "bad restart");
+    if (first < 0 || count < 0 || first + count > ctx->last_iters)
+        return fail(ISING_E_INVALID_ARG, "log range outside the last solve");
+    if (count == 0) return ISING_OK;
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int R = ctx->last_R;
+    std::vector<double> buf(static_cast<size_t>(count) * R * 2);
+    HIP_OK(hipMemcpyAsync(buf.data(), ctx->log + static_cast<size_t>(first) * R * 2,
+                          buf.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy log");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    for (int64_t k = 0; k < count; ++k) {
+        if (H_host) H_host[k] = buf[(static_cast<size_t>(k) * R + restart) * 2];
+        if (r_host) r_host[k] = buf[(static_cast<size_t>(k) * R + restart) * 2 + 1];
+    }
+    return ISING_OK;
+}
+
+ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
+                          int64_t* E_int_dev, void* stream) {
+    if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
+    if (!s_dev) return fail(ISING_E_INVALID_ARG, "s is NULL");
+    if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
+    if (!E_dev && !E_int_dev) return fail(ISING_E_INVALID_ARG, "no output requested");
+    if (E_int_dev && !ctx->integer_J) return fail(ISING_E_UNSUPPORTED, "integer energy needs integer couplings");
+    if (E_int_dev && ctx->dense) return fail(ISING_E_UNSUPPORTED, "integer energy is CSR-only in this build");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int grid = ctx->dense ? std::min<int64_t>(1024, (ctx->n + 3) / 4)
+                                : std::min<int64_t>(1024, (ctx->n + 255) / 256);
+    Scratch sc;
+    ising_status st = ensure_scratch(ctx, static_cast<size_t>(grid) * R * 3, &sc);
+    if (st != ISING_OK) return st;
+    if (ctx->dense) {
+        if (!E_dev) return fail(ISING_E_INVALID_ARG, "E is NULL");
+        HIP_OK(doch::launch_dense_energy(dense_view(ctx), s_dev, R, sc.partials, sc.tickets, grid, E_dev, s), "energy");
+    } else {
+        HIP_OK(doch::launch_csr_energy(csr_view(ctx), s_dev, R, sc.partials, sc.tickets, grid, E_dev, E_int_dev, s),
+               "energy");
+    }
+    return ISING_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// device_common.h -- device helpers shared by the gfx950 kernels:
+// deterministic wavefront/workgroup reductions, the coherent last-workgroup
+// hand-off, IEEE-exact scalar arithmetic and streaming loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace doch {
+
+constexpr int kWave = 64;
+
+// Round-to-nearest double operations that the compiler may not contract into
+// FMAs, so the update matches its defining expression operation by operation.
+__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ double dsub(double a, double b) { return __dsub_rn(a, b); }
+__device__ __forceinline__ double ddiv(double a, double b) { return __ddiv_rn(a, b); }
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) { return static_cast<double>(v); }
+
+template <typename XT>
+__device__ __forceinline__ void store_x(XT* p, double v) { *p = static_cast<XT>(v); }
+
+// Butterfly sum over the 64 lanes of a wavefront.  Lane 0 always performs the
+// same sequence of additions, so its result is reproducible run to run.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = dadd(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Sum K values over a workgroup of NT threads in a fixed order; the result
+// is valid in thread 0.  `lds` must hold K * (NT / 64) doubles.
+template <int K, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* lds) {
+    constexpr int NW = NT / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) lds[q * NW + wave] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s = dadd(s, lds[q * NW + w]);
+            v[q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Coherent (agent-scope) accesses used for the partial sums that cross
+// workgroups -- and therefore XCDs and their private L2 caches.
+__device__ __forceinline__ void store_agent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by thread 0 after it stored its workgroup's partials: returns true
+// in the one workgroup that arrives last.  Release/acquire at agent scope
+// orders every workgroup's partial stores before the last one's loads.
+__device__ __forceinline__ bool arrive_last(unsigned int* ticket, unsigned int count) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned int prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    bool last = (prev == count - 1);
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return last;
+}
+
+__device__ __forceinline__ void reset_ticket(unsigned int* ticket) {
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace doch

@@ -1,0 +1,165 @@
+// ising_internal.h -- shared host-side declarations of the gfx950 DOCH
+// library: the context object, the per-restart solver state and the kernel
+// launchers implemented in the kernels_*.hip translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ising.h"
+
+namespace doch {
+
+// Rows per row block of the CSR kernels and the LDS budget (in products) of a
+// block.  A row longer than kBlockNnz gets a block of its own and is reduced
+// by the whole workgroup.
+constexpr int kBlockThreads = 256;
+constexpr int kBlockNnz = 2048;
+// Number of FP64 partial sums each workgroup contributes per restart and
+// iteration: sum x^4, sum x^2, sum x*z, sum (x_new - x)^2, sum h*x.
+constexpr int kNumPartials = 5;
+
+// Device-resident state of one restart (one per column of an iterate block).
+struct RestartState {
+    int64_t iters_done;
+    int32_t done;        // converged or failed: later iterations are skipped
+    int32_t converged;
+    int32_t nonfinite;
+    int32_t pad;
+    double H_last;
+    double r_last;
+};
+
+// Reduced statistics of the coupling matrix (setup, eq:alphabeta).
+struct MatrixStats {
+    double rowsum_max;   // max_i sum_{j != i} |Jhat_ij|
+    double abs_max;      // max_i sum_j |Jhat_ij| (power-method shift)
+    double s1;           // sum_{i != j} Jhat_ij
+    double ss;           // sum_{i != j} (Jhat_ij - mean)^2 over stored entries
+    double stored;       // number of stored off-diagonal entries
+    double pad[3];
+};
+
+struct CsrView {
+    int64_t n;
+    int64_t nnz;
+    const int32_t* rp;
+    const int32_t* col;
+    const void* val;
+    int vt;                 // ISING_F32 or ISING_F64
+    const void* h;          // nullptr: no field
+    int ht;
+};
+
+struct DenseView {
+    int64_t n;
+    int64_t ld;
+    const double* J;
+    const void* h;
+    int ht;
+};
+
+// Parameters of one DOCH iteration launch.
+struct StepArgs {
+    const void* x_old;      // n' * R, type x_dtype
+    void* x_new;
+    int x_dtype;            // ISING_F64 / ISING_F32
+    int R;
+    double alpha, beta, eps;
+    int64_t k;              // iteration index
+    double* partials;       // [grid][R][kNumPartials]
+    unsigned int* ticket;
+    double* log;            // [iters][R][2]: (H, r)
+    RestartState* state;    // [R]
+    int all_done_flag;      // unused placeholder
+};
+
+}  // namespace doch
+
+struct ising_ctx {
+    int device = 0;
+    bool dense = false;
+    int64_t n = 0;
+    int64_t np = 0;          // n' = n + has_field
+    bool has_field = false;
+    bool integer_J = false;
+    // CSR storage (library-owned)
+    int64_t nnz = 0;
+    int32_t* rp = nullptr;
+    int32_t* col = nullptr;
+    void* val = nullptr;
+    int vt = ISING_F32;
+    void* h = nullptr;
+    int ht = ISING_F32;
+    // dense storage
+    double* J = nullptr;
+    int64_t ld = 0;
+    // row blocks of the CSR kernels for R = 1
+    int32_t* blk = nullptr;  // block b covers rows [blk[b], blk[b+1])
+    int64_t nblk = 0;
+    // solve workspace
+    void* xbuf[2] = {nullptr, nullptr};
+    size_t xbuf_bytes = 0;
+    double* partials = nullptr;
+    size_t partials_bytes = 0;
+    unsigned int* ticket = nullptr;
+    doch::RestartState* state = nullptr;
+    int state_cap = 0;
+    double* log = nullptr;
+    size_t log_bytes = 0;
+    int last_R = 0;
+    int64_t last_iters = 0;
+    // setup scratch
+    double* scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+namespace doch {
+
+// ---- launchers (kernels_csr.hip) ----
+hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s);
+hipError_t launch_csr_step(const CsrView& A, const int32_t* blk, int64_t nblk,
+                           const StepArgs& a, int grid, hipStream_t s);
+int csr_step_grid(int64_t nblk);
+hipError_t launch_csr_energy(const CsrView& A, const int8_t* s_spins, int R,
+                             double* partials, unsigned int* ticket, int grid,
+                             double* E, int64_t* E_int, hipStream_t s);
+hipError_t launch_csr_stats(const CsrView& A, double mean, int pass,
+                            double* partials, unsigned int* ticket, int grid,
+                            MatrixStats* out, hipStream_t s);
+hipError_t launch_csr_power_step(const CsrView& A, double c, const double* v,
+                                 double* w, double* partials, unsigned int* ticket,
+                                 int grid, double* mu_log, int64_t k, hipStream_t s);
+hipError_t launch_csr_symcheck(const CsrView& A, int32_t* bad, hipStream_t s);
+
+// ---- launchers (kernels_dense.hip) ----
+hipError_t launch_dense_validate(const DenseView& A, int32_t* flags, hipStream_t s);
+hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid,
+                             hipStream_t s);
+int dense_step_grid(int64_t n);
+hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
+                               double* partials, unsigned int* ticket, int grid,
+                               double* E, hipStream_t s);
+hipError_t launch_dense_stats(const DenseView& A, double mean, int pass,
+                              double* partials, unsigned int* ticket, int grid,
+                              MatrixStats* out, hipStream_t s);
+hipError_t launch_dense_power_step(const DenseView& A, double c, const double* v,
+                                   double* w, double* partials, unsigned int* ticket,
+                                   int grid, double* mu_log, int64_t k, hipStream_t s);
+hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s);
+
+// ---- launchers (kernels_common.hip) ----
+hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,
+                          hipStream_t s);
+hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket,
+                             hipStream_t s);
+hipError_t launch_finish(const void* xb0, const void* xb1, int x_dtype,
+                         const RestartState* st, int64_t n, int64_t np, int R,
+                         bool field, double* x_out, int8_t* s_out, hipStream_t s);
+hipError_t launch_normalize(const double* w, double* v, const double* mu_log,
+                            int64_t k, int64_t n, hipStream_t s);
+
+}  // namespace doch

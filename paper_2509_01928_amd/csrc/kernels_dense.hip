@@ -1,0 +1,384 @@
+// kernels_dense.hip -- dense FP64 kernels of the DOCH hot path for gfx950.
+//
+// One wavefront owns one row of J: its 64 lanes stream the row with
+// unit-stride 8-byte loads (512 contiguous bytes per instruction), multiply by
+// the iterate, and a butterfly reduction gives (J x)_i; lane 0 then applies
+// the cube-root update of eq:FPE.  Four wavefronts (four rows) share a
+// workgroup.  A single-vector FP64 product has no data reuse, so it runs on
+// the vector ALUs, not on the matrix cores.
+#include "device_common.h"
+#include "ising_internal.h"
+#include "step_common.h"
+
+namespace doch {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / kWave;
+
+template <typename XT, typename HT, bool FIELD>
+__global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, int64_t ld,
+                                                        const double* __restrict__ J,
+                                                        const HT* __restrict__ h, StepArgs a) {
+    if (a.state->done) return;
+    __shared__ double red[kNumPartials * NW];
+    const XT* __restrict__ x = static_cast<const XT*>(a.x_old);
+    XT* __restrict__ xn = static_cast<XT*>(a.x_new);
+    const double t_old = FIELD ? static_cast<double>(x[n]) : 0.0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double acc[kNumPartials];
+#pragma unroll
+    for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+         i += static_cast<int64_t>(gridDim.x) * NW) {
+        const double* __restrict__ row = J + i * ld;
+        double p = 0.0;
+        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(row[j], static_cast<double>(x[j])));
+        const double z0 = wave_sum(p);
+        if (lane == 0) {
+            double z = z0;
+            double hv = 0.0;
+            if (FIELD) {
+                hv = static_cast<double>(h[i]);
+                z = dadd(z, dmul(hv, t_old));
+            }
+            update_row<XT>(z, static_cast<double>(x[i]), hv, FIELD, a, xn, i, acc);
+        }
+    }
+    step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
+}
+
+template <typename HT, bool FIELD>
+__global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, int64_t ld,
+                                                          const double* __restrict__ J,
+                                                          const HT* __restrict__ h,
+                                                          const int8_t* __restrict__ s, int R,
+                                                          double* partials, unsigned int* tickets,
+                                                          double* E) {
+    __shared__ double red[2 * NW];
+    __shared__ int last_flag;
+    const int r = blockIdx.y;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+         i += static_cast<int64_t>(gridDim.x) * NW) {
+        const double* __restrict__ row = J + i * ld;
+        double p = 0.0;
+        for (int64_t j = lane; j < n; j += kWave)
+            p = dadd(p, dmul(row[j], static_cast<double>(s[j * R + r])));
+        const double z = wave_sum(p);
+        if (lane == 0) {
+            const double si = static_cast<double>(s[i * R + r]);
+            v[0] = dadd(v[0], dmul(si, z));
+            if (FIELD) v[1] = dadd(v[1], dmul(static_cast<double>(h[i]), si));
+        }
+    }
+    block_sum<2, NT>(v, red);
+    double* p = partials + (static_cast<size_t>(r) * gridDim.x + blockIdx.x) * 2;
+    if (threadIdx.x == 0) {
+        store_agent(p + 0, v[0]);
+        store_agent(p + 1, v[1]);
+        last_flag = arrive_last(tickets + r, gridDim.x) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last_flag) return;
+    double u[2] = {0.0, 0.0};
+    const double* pr = partials + static_cast<size_t>(r) * gridDim.x * 2;
+    for (unsigned g = threadIdx.x; g < gridDim.x; g += NT) {
+        u[0] = dadd(u[0], load_agent(pr + g * 2 + 0));
+        u[1] = dadd(u[1], load_agent(pr + g * 2 + 1));
+    }
+    block_sum<2, NT>(u, red);
+    if (threadIdx.x == 0) {
+        E[r] = dsub(dmul(-0.5, u[0]), u[1]);
+        reset_ticket(tickets + r);
+    }
+}
+
+// flags[0]: non-finite entry, flags[1]: nonzero diagonal, flags[2]: an entry
+// is not an integer of magnitude < 2^31.
+__global__ __launch_bounds__(NT) void dense_validate_kernel(int64_t n, int64_t ld,
+                                                            const double* __restrict__ J,
+                                                            int32_t* flags) {
+    const int64_t total = n * n;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * NT) {
+        const int64_t i = t / n, j = t % n;
+        const double v = J[i * ld + j];
+        if (!isfinite(v)) atomicOr(flags + 0, 1);
+        if (i == j && v != 0.0) atomicOr(flags + 1, 1);
+        if (!(v == floor(v)) || fabs(v) >= 2147483648.0) atomicOr(flags + 2, 1);
+    }
+}
+
+__global__ __launch_bounds__(NT) void dense_symcheck_kernel(int64_t n, int64_t ld,
+                                                            const double* __restrict__ J,
+                                                            int32_t* bad) {
+    const int64_t total = n * n;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * NT) {
+        const int64_t i = t / n, j = t % n;
+        if (J[i * ld + j] != J[j * ld + i]) atomicOr(bad, 1);
+    }
+}
+
+template <typename HT, bool FIELD>
+__global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, int64_t ld,
+                                                         const double* __restrict__ J,
+                                                         const HT* __restrict__ h, double mean,
+                                                         int pass, double* partials,
+                                                         unsigned int* ticket, MatrixStats* out) {
+    __shared__ double red[3 * NW];
+    __shared__ double redm[NW];
+    __shared__ int last_flag;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double v[3] = {0.0, 0.0, 0.0};
+    double pmax = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+         i += static_cast<int64_t>(gridDim.x) * NW) {
+        const double* __restrict__ row = J + i * ld;
+        double a0 = 0.0, a1 = 0.0;
+        for (int64_t j = lane; j < n; j += kWave) {
+            if (j == i) continue;
+            const double x = row[j];
+            if (pass == 0) {
+                a0 = dadd(a0, fabs(x));
+                a1 = dadd(a1, x);
+            } else {
+                const double d = dsub(x, mean);
+                a0 = dadd(a0, dmul(d, d));
+            }
+        }
+        const double rs = wave_sum(a0);
+        const double sm = wave_sum(a1);
+        if (lane == 0) {
+            if (pass == 0) {
+                double rsum = rs;
+                v[0] = dadd(v[0], sm);
+                v[1] += static_cast<double>(n - 1);
+                if (FIELD) {
+                    const double hv = static_cast<double>(h[i]);
+                    rsum = dadd(rsum, fabs(hv));
+                    v[0] = dadd(v[0], dmul(2.0, hv));
+                    v[1] += 2.0;
+                    v[2] = dadd(v[2], fabs(hv));
+                }
+                pmax = fmax(pmax, rsum);
+            } else {
+                v[0] = dadd(v[0], rs);
+                if (FIELD) {
+                    const double d = dsub(static_cast<double>(h[i]), mean);
+                    v[0] = dadd(v[0], dmul(2.0, dmul(d, d)));
+                }
+            }
+        }
+    }
+    block_sum<3, NT>(v, red);
+    const double wm = wave_max(pmax);
+    if (lane == 0) redm[wave] = wm;
+    __syncthreads();
+    double* p = partials + static_cast<size_t>(blockIdx.x) * 4;
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < NW; ++w) m = fmax(m, redm[w]);
+        store_agent(p + 0, v[0]);
+        store_agent(p + 1, v[1]);
+        store_agent(p + 2, v[2]);
+        store_agent(p + 3, m);
+        last_flag = arrive_last(ticket, gridDim.x) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last_flag) return;
+    double u[3] = {0.0, 0.0, 0.0};
+    double um = 0.0;
+    for (unsigned g = threadIdx.x; g < gridDim.x; g += NT) {
+        u[0] = dadd(u[0], load_agent(partials + g * 4 + 0));
+        u[1] = dadd(u[1], load_agent(partials + g * 4 + 1));
+        u[2] = dadd(u[2], load_agent(partials + g * 4 + 2));
+        um = fmax(um, load_agent(partials + g * 4 + 3));
+    }
+    block_sum<3, NT>(u, red);
+    const double wum = wave_max(um);
+    if (lane == 0) redm[wave] = wum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < NW; ++w) m = fmax(m, redm[w]);
+        if (pass == 0) {
+            const double rmax = FIELD ? fmax(m, u[2]) : m;
+            out->rowsum_max = rmax;
+            out->abs_max = rmax;
+            out->s1 = u[0];
+            out->stored = u[1];
+        } else {
+            out->ss = u[0];
+        }
+        reset_ticket(ticket);
+    }
+}
+
+template <typename HT, bool FIELD>
+__global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, int64_t ld,
+                                                         const double* __restrict__ J,
+                                                         const HT* __restrict__ h, double c,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ w, double* partials,
+                                                         unsigned int* ticket, double* mu_log,
+                                                         int64_t k) {
+    __shared__ double red[3 * NW];
+    __shared__ int last_flag;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const double vn = FIELD ? v[n] : 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+         i += static_cast<int64_t>(gridDim.x) * NW) {
+        const double* __restrict__ row = J + i * ld;
+        double p = 0.0;
+        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(row[j], v[j]));
+        const double z0 = wave_sum(p);
+        if (lane == 0) {
+            double z = z0;
+            if (FIELD) {
+                const double hv = static_cast<double>(h[i]);
+                z = dadd(z, dmul(hv, vn));
+                acc[2] = dadd(acc[2], dmul(hv, v[i]));
+            }
+            const double wi = dsub(dmul(c, v[i]), z);
+            w[i] = wi;
+            acc[0] = dadd(acc[0], dmul(v[i], wi));
+            acc[1] = dadd(acc[1], dmul(wi, wi));
+        }
+    }
+    block_sum<3, NT>(acc, red);
+    if (threadIdx.x == 0) {
+        double* p = partials + static_cast<size_t>(blockIdx.x) * 3;
+        for (int q = 0; q < 3; ++q) store_agent(p + q, acc[q]);
+        last_flag = arrive_last(ticket, gridDim.x) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last_flag) return;
+    double u[3] = {0.0, 0.0, 0.0};
+    for (unsigned g = threadIdx.x; g < gridDim.x; g += NT)
+        for (int q = 0; q < 3; ++q) u[q] = dadd(u[q], load_agent(partials + g * 3 + q));
+    block_sum<3, NT>(u, red);
+    if (threadIdx.x == 0) {
+        double vw = u[0], ww = u[1];
+        if (FIELD) {
+            const double wn = dsub(dmul(c, vn), u[2]);
+            w[n] = wn;
+            vw = dadd(vw, dmul(vn, wn));
+            ww = dadd(ww, dmul(wn, wn));
+        }
+        mu_log[2 * k] = vw;
+        mu_log[2 * k + 1] = sqrt(ww);
+        reset_ticket(ticket);
+    }
+}
+
+int grid_for_rows(int64_t n) {
+    int64_t g = (n + NW - 1) / NW;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return static_cast<int>(g);
+}
+
+int grid_for_elems(int64_t total) {
+    int64_t g = (total + NT - 1) / NT;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return static_cast<int>(g);
+}
+
+}  // namespace
+
+int dense_step_grid(int64_t n) { return grid_for_rows(n); }
+
+hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid, hipStream_t s) {
+    const bool field = A.h != nullptr;
+#define DOCH_DENSE_STEP(XT, HT, F)                                                         \
+    hipLaunchKernelGGL((dense_step_kernel<XT, HT, F>), dim3(grid), dim3(NT), 0, s, A.n, A.ld, \
+                       A.J, static_cast<const HT*>(A.h), a)
+    if (a.x_dtype == ISING_F64) {
+        if (!field) DOCH_DENSE_STEP(double, double, false);
+        else if (A.ht == ISING_F64) DOCH_DENSE_STEP(double, double, true);
+        else DOCH_DENSE_STEP(double, float, true);
+    } else {
+        if (!field) DOCH_DENSE_STEP(float, double, false);
+        else if (A.ht == ISING_F64) DOCH_DENSE_STEP(float, double, true);
+        else DOCH_DENSE_STEP(float, float, true);
+    }
+#undef DOCH_DENSE_STEP
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
+                               double* partials, unsigned int* ticket, int grid, double* E,
+                               hipStream_t s) {
+    if (A.h == nullptr)
+        hipLaunchKernelGGL((dense_energy_kernel<double, false>), dim3(grid, R), dim3(NT), 0, s,
+                           A.n, A.ld, A.J, static_cast<const double*>(nullptr), s_spins, R,
+                           partials, ticket, E);
+    else if (A.ht == ISING_F64)
+        hipLaunchKernelGGL((dense_energy_kernel<double, true>), dim3(grid, R), dim3(NT), 0, s,
+                           A.n, A.ld, A.J, static_cast<const double*>(A.h), s_spins, R, partials,
+                           ticket, E);
+    else
+        hipLaunchKernelGGL((dense_energy_kernel<float, true>), dim3(grid, R), dim3(NT), 0, s,
+                           A.n, A.ld, A.J, static_cast<const float*>(A.h), s_spins, R, partials,
+                           ticket, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_validate(const DenseView& A, int32_t* flags, hipStream_t s) {
+    hipLaunchKernelGGL(dense_validate_kernel, dim3(grid_for_elems(A.n * A.n)), dim3(NT), 0, s,
+                       A.n, A.ld, A.J, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s) {
+    hipLaunchKernelGGL(dense_symcheck_kernel, dim3(grid_for_elems(A.n * A.n)), dim3(NT), 0, s,
+                       A.n, A.ld, A.J, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_stats(const DenseView& A, double mean, int pass, double* partials,
+                              unsigned int* ticket, int grid, MatrixStats* out, hipStream_t s) {
+    if (A.h == nullptr)
+        hipLaunchKernelGGL((dense_stats_kernel<double, false>), dim3(grid), dim3(NT), 0, s, A.n,
+                           A.ld, A.J, static_cast<const double*>(nullptr), mean, pass, partials,
+                           ticket, out);
+    else if (A.ht == ISING_F64)
+        hipLaunchKernelGGL((dense_stats_kernel<double, true>), dim3(grid), dim3(NT), 0, s, A.n,
+                           A.ld, A.J, static_cast<const double*>(A.h), mean, pass, partials,
+                           ticket, out);
+    else
+        hipLaunchKernelGGL((dense_stats_kernel<float, true>), dim3(grid), dim3(NT), 0, s, A.n,
+                           A.ld, A.J, static_cast<const float*>(A.h), mean, pass, partials,
+                           ticket, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_power_step(const DenseView& A, double c, const double* v, double* w,
+                                   double* partials, unsigned int* ticket, int grid,
+                                   double* mu_log, int64_t k, hipStream_t s) {
+    if (A.h == nullptr)
+        hipLaunchKernelGGL((dense_power_kernel<double, false>), dim3(grid), dim3(NT), 0, s, A.n,
+                           A.ld, A.J, static_cast<const double*>(nullptr), c, v, w, partials,
+                           ticket, mu_log, k);
+    else if (A.ht == ISING_F64)
+        hipLaunchKernelGGL((dense_power_kernel<double, true>), dim3(grid), dim3(NT), 0, s, A.n,
+                           A.ld, A.J, static_cast<const double*>(A.h), c, v, w, partials, ticket,
+                           mu_log, k);
+    else
+        hipLaunchKernelGGL((dense_power_kernel<float, true>), dim3(grid), dim3(NT), 0, s, A.n,
+                           A.ld, A.J, static_cast<const float*>(A.h), c, v, w, partials, ticket,
+                           mu_log, k);
+    return hipGetLastError();
+}
+
+}  // namespace doch

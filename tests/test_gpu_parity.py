@@ -1,0 +1,328 @@
+"""GPU-vs-oracle parity of the DOCH hot path through the C ABI.
+
+Every case runs the same seeded instance, start vector, alpha and beta on
+both sides.  alpha and beta always come from the oracle (eq:alphabeta) or a
+closed form, never from the GPU.  FP64 bar: iterates within 1e-9 max abs
+(absolute and relative to |x|_inf), spins identical except |x_i| < 1e-6
+|x|_inf, H log within 1e-12 relative, exact integer energies.
+"""
+import numpy as np
+import pytest
+
+import ising_inputs as gen
+import oracle as orc
+from tests._util import (GpuProblem, assert_iterate_parity, assert_log_parity,
+                         assert_spin_parity)
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(A, x0, iters, eta=1.0, method="auto", eps=0.0, val_dtype="f32"):
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B, eta, method=method)
+    tr = orc.doch(B, x0, alpha, beta, iters, eps=eps)
+    P = GpuProblem(A=A, val_dtype=val_dtype)
+    try:
+        x, s, st = P.solve(x0, alpha, beta, iters, eps=eps)
+        H, r = P.log(st[0].iters_done)
+    finally:
+        P.close()
+    return B, tr, x[:, 0], s[:, 0], st[0], H, r
+
+
+def check_all(A, tr, x, s, st, H, r, label):
+    assert st.iters_done == tr.iters, label
+    assert_iterate_parity(x, tr.x, label)
+    s_ref = orc.spins_with_field(tr.x) if A.h is not None else orc.sign(tr.x)
+    assert_spin_parity(s, tr.x, s_ref, label)
+    assert_log_parity(H, r, tr, label)
+
+
+@pytest.mark.parametrize("n,d,seed,iters", [(3000, 6.0, 11, 300), (777, 3.0, 12, 200),
+                                            (5000, 20.0, 13, 150)])
+def test_er_fp64_parity(n, d, seed, iters):
+    A = gen.er_csr(n, d, seed)
+    x0 = gen.uniform_x0(n, 1, seed + 100)[:, 0]
+    B, tr, x, s, st, H, r = run_both(A, x0, iters, method="wigner")
+    check_all(A, tr, x, s, st, H, r, f"ER n={n}")
+
+
+def test_er_c2_full_config():
+    """Sparse ER n=20000, mean degree 6, +-1, h=0, 5000 iterations."""
+    seed, xseed = gen.SEEDS["er20000"]
+    A = gen.er_csr(20000, 6.0, seed)
+    x0 = gen.uniform_x0(20000, 1, xseed)[:, 0]
+    B, tr, x, s, st, H, r = run_both(A, x0, 5000)
+    check_all(A, tr, x, s, st, H, r, "C2")
+    P = GpuProblem(A=A)
+    try:
+        E, Ei = P.energy(s, want_int=True)
+    finally:
+        P.close()
+    assert int(Ei[0]) == orc.energy_i64(B, s)
+    assert E[0] == orc.energy(A, s)
+
+
+@pytest.mark.parametrize("L,iters", [(64, 300), (97, 120)])
+def test_torus_with_field_fp64_parity(L, iters):
+    """Lattice with h ~ N(0, 0.1^2): the extra spin of Supp. Note 1."""
+    A = gen.torus_csr(L, 1003, h_std=0.1)
+    x0 = gen.uniform_x0(L * L + 1, 1, 2003)[:, 0]
+    B, tr, x, s, st, H, r = run_both(A, x0, iters)
+    check_all(A, tr, x, s, st, H, r, f"torus L={L}")
+
+
+def test_values_in_fp64_storage():
+    A = gen.er_csr(2000, 5.0, 21)
+    A.val = A.val * np.float32(0.37)          # non-integer couplings
+    x0 = gen.uniform_x0(2000, 1, 22)[:, 0]
+    B, tr, x, s, st, H, r = run_both(A, x0, 200, val_dtype="f64")
+    check_all(A, tr, x, s, st, H, r, "f64 values")
+
+
+def test_long_rows_and_empty_rows():
+    """Rows longer than one row block (a hub joined to every other spin)
+    and rows with no couplings at all."""
+    n = 6000
+    rng = np.random.default_rng(31)
+    J = np.zeros((n, n), dtype=np.float32)
+    hub = 17
+    J[hub, :] = rng.choice([-1.0, 1.0], n).astype(np.float32)
+    J[:, hub] = J[hub, :]
+    J[hub, hub] = 0.0
+    lo = gen.er_csr(n, 4.0, 32)
+    Jd = gen.dense_from_csr(lo).astype(np.float32)
+    Jd[hub, :] = 0
+    Jd[:, hub] = 0
+    J = J + Jd
+    J[4000:4100, :] = 0
+    J[:, 4000:4100] = 0
+    A = gen.csr_from_dense(J.astype(np.float64))
+    assert np.diff(A.row_ptr).max() > 2048 and np.sum(np.diff(A.row_ptr) == 0) >= 100
+    x0 = gen.uniform_x0(n, 1, 33)[:, 0]
+    B, tr, x, s, st, H, r = run_both(A, x0, 150)
+    check_all(A, tr, x, s, st, H, r, "long rows")
+
+
+@pytest.mark.parametrize("n,iters", [(300, 400), (1024, 1000)])
+def test_dense_sk_parity(n, iters):
+    """Dense SK (n=1024 with 1000 iterations is the dense FP64 workload)."""
+    seed, xseed = gen.SEEDS["sk1024"] if n == 1024 else (41, 42)
+    J = gen.sk_dense(n, seed)
+    x0 = gen.uniform_x0(n, 1, xseed)[:, 0]
+    alpha = -np.linalg.eigvalsh(J)[0]
+    beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    tr = orc.doch_dense(J, x0, alpha, beta, iters)
+    P = GpuProblem(J=J)
+    try:
+        x, s, st = P.solve(x0, alpha, beta, iters)
+        H, r = P.log(iters)
+        E, _ = P.energy(s[:, 0])
+    finally:
+        P.close()
+    assert st[0].iters_done == iters
+    assert_iterate_parity(x[:, 0], tr.x, f"dense n={n}")
+    assert_spin_parity(s[:, 0], tr.x, orc.sign(tr.x), f"dense n={n}")
+    assert_log_parity(H, r, tr, f"dense n={n}")
+    assert E[0] == pytest.approx(orc.energy_dense(J, s[:, 0]), rel=1e-12)
+
+
+def test_dense_with_field():
+    n = 200
+    J = gen.sk_dense(n, 51)
+    h = np.random.default_rng(52).standard_normal(n) * 0.5
+    A = gen.csr_from_dense(J, h)
+    B = orc.augment_field(orc.csr_of_dense(J), h)
+    alpha, beta, _ = orc.default_params(B, 1.0, method="power")
+    x0 = gen.uniform_x0(n + 1, 1, 53)[:, 0]
+    tr = orc.doch(B, x0, alpha, beta, 300)
+    P = GpuProblem(J=J, h=h)
+    try:
+        x, s, st = P.solve(x0, alpha, beta, 300)
+        H, r = P.log(300)
+        E, _ = P.energy(s[:, 0])
+    finally:
+        P.close()
+    assert_iterate_parity(x[:, 0], tr.x, "dense+h")
+    assert_spin_parity(s[:, 0], tr.x, orc.spins_with_field(tr.x), "dense+h")
+    assert_log_parity(H, r, tr, "dense+h")
+    assert E[0] == pytest.approx(orc.energy_dense(J, s[:, 0], h), rel=1e-12)
+    del A
+
+
+def test_early_stop_matches_oracle():
+    A = gen.er_csr(4000, 8.0, 61)
+    x0 = gen.uniform_x0(4000, 1, 62)[:, 0]
+    B, tr, x, s, st, H, r = run_both(A, x0, 3000, eps=1e-3)
+    assert tr.iters < 3000
+    assert st.converged == 1
+    check_all(A, tr, x, s, st, H, r, "eps=1e-3")
+
+
+def test_zero_iterations_and_zero_start():
+    A = gen.er_csr(500, 4.0, 71)
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B)
+    x0 = gen.uniform_x0(500, 1, 72)[:, 0]
+    P = GpuProblem(A=A)
+    try:
+        x, s, st = P.solve(x0, alpha, beta, 0)
+        assert st[0].iters_done == 0
+        np.testing.assert_array_equal(x[:, 0], x0)
+        np.testing.assert_array_equal(s[:, 0], orc.sign(x0))
+        x, s, st = P.solve(np.zeros(500), alpha, beta, 5, eps=1e-3)
+        assert st[0].iters_done == 1 and st[0].converged == 1 and st[0].r_last == 0.0
+        assert np.all(x == 0) and np.all(s == 1)
+    finally:
+        P.close()
+
+
+def test_fp32_iterate_storage():
+    """Iterate stored in FP32 (arithmetic FP64): a precision path, compared
+    with a bound derived from FP32 rounding of every stored iterate."""
+    L = 128
+    A = gen.torus_csr(L, 81, h_std=0.1)
+    x0 = gen.uniform_x0(L * L + 1, 1, 82)[:, 0]
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B)
+    tr = orc.doch(B, x0, alpha, beta, 100)
+    P = GpuProblem(A=A)
+    try:
+        import paper_2509_01928_amd as Lb
+        x, s, st = P.solve(x0, alpha, beta, 100, x_dtype=Lb.ISING_F32)
+        H, r = P.log(100)
+    finally:
+        P.close()
+    scale = np.abs(tr.x).max()
+    assert np.abs(x[:, 0] - tr.x).max() <= 1e-5 * scale
+    assert np.abs(H - tr.H).max() <= 1e-5 * np.abs(tr.H).max()
+    s_ref = orc.spins_with_field(tr.x)
+    diff = np.nonzero(s[:, 0] != s_ref)[0]
+    assert all(abs(tr.x[i]) < 1e-4 * scale for i in diff)
+
+
+def test_energy_many_restarts_and_integer():
+    A = gen.er_csr(3000, 7.0, 91)
+    B = orc.to_oracle_csr(A)
+    rng = np.random.default_rng(92)
+    S = np.where(rng.random((3000, 6)) < 0.5, 1, -1).astype(np.int8)
+    P = GpuProblem(A=A)
+    try:
+        E, Ei = P.energy(S, want_int=True)
+    finally:
+        P.close()
+    for r in range(6):
+        assert int(Ei[r]) == orc.energy_i64(B, S[:, r])
+        assert E[r] == float(Ei[r])
+
+
+def test_energy_field_and_dense_gaussian():
+    A = gen.torus_csr(50, 93, h_std=0.1)
+    rng = np.random.default_rng(94)
+    S = np.where(rng.random((2500, 3)) < 0.5, 1, -1).astype(np.int8)
+    P = GpuProblem(A=A)
+    try:
+        E, _ = P.energy(S)
+    finally:
+        P.close()
+    for r in range(3):
+        assert E[r] == pytest.approx(orc.energy(A, S[:, r]), rel=1e-12, abs=1e-9)
+    J = gen.sk_dense(700, 95)
+    S = np.where(rng.random((700, 4)) < 0.5, 1, -1).astype(np.int8)
+    P = GpuProblem(J=J)
+    try:
+        E, _ = P.energy(S)
+    finally:
+        P.close()
+    for r in range(4):
+        assert E[r] == pytest.approx(orc.energy_dense(J, S[:, r]), rel=1e-12)
+
+
+# ------------------------------------------------------ setup (eq:alphabeta)
+def test_default_params_wigner_matches_oracle():
+    import paper_2509_01928_amd as Lb
+    for A in (gen.er_csr(20000, 6.0, 1002), gen.torus_csr(120, 1003, h_std=0.1)):
+        B = orc.problem_matrix(A)
+        a_ref, b_ref, lam_ref = orc.default_params(B, 1.0, method="wigner")
+        P = GpuProblem(A=A)
+        try:
+            p, lam = Lb.ising_default_params(P.ctx, 1.0, 2)
+        finally:
+            P.close()
+        assert lam == pytest.approx(lam_ref, rel=1e-12)
+        assert p.alpha == pytest.approx(a_ref, rel=1e-12)
+        assert p.beta == pytest.approx(b_ref, rel=1e-12)
+
+
+def test_default_params_power_matches_eigvalsh():
+    import paper_2509_01928_amd as Lb
+    n = 256
+    J = gen.sk_dense(n, 101)
+    lam_true = -np.linalg.eigvalsh(J)[0]
+    P = GpuProblem(J=J)
+    try:
+        p, lam = Lb.ising_default_params(P.ctx, 1.5, 0)
+    finally:
+        P.close()
+    assert lam == pytest.approx(lam_true, rel=1e-8)
+    assert p.alpha == pytest.approx(1.5 * lam_true, rel=1e-8)
+    assert p.beta == pytest.approx(n ** 1.5 * (p.alpha + np.abs(J).sum(axis=1).max()), rel=1e-12)
+    A = gen.er_csr(1500, 8.0, 102)
+    B = orc.to_oracle_csr(A)
+    lam_o, _ = orc.power_lambda_max_neg(B, gen.uniform_x0(1500, 1, 103)[:, 0])
+    lam_true = -np.linalg.eigvalsh(gen.dense_from_csr(A))[0]
+    P = GpuProblem(A=A)
+    try:
+        p, lam = Lb.ising_default_params(P.ctx, 1.0, 1)
+    finally:
+        P.close()
+    assert lam == pytest.approx(lam_true, rel=1e-7)
+    assert lam_o == pytest.approx(lam_true, rel=1e-7)
+
+
+# --------------------------------------------------------------- errors
+def test_error_paths():
+    import torch
+    import paper_2509_01928_amd as Lb
+    dev = "cuda:0"
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32, device=dev)
+    col = torch.tensor([0, 0], dtype=torch.int32, device=dev)     # (0,0) diagonal
+    val = torch.tensor([1.0, 1.0], dtype=torch.float32, device=dev)
+    with pytest.raises(Lb.IsingError) as e:
+        Lb.ising_create_csr(2, 2, rp, col, val, Lb.ISING_F32)
+    assert e.value.status == Lb.ISING_E_NONZERO_DIAG
+    bad_col = torch.tensor([1, 5], dtype=torch.int32, device=dev)
+    with pytest.raises(Lb.IsingError) as e:
+        Lb.ising_create_csr(2, 2, rp, bad_col, val, Lb.ISING_F32)
+    assert e.value.status == Lb.ISING_E_INVALID_ARG
+    col3 = torch.tensor([1, 0, 1], dtype=torch.int32, device=dev)
+    val3 = torch.tensor([1.0, 1.0, 1.0], dtype=torch.float32, device=dev)
+    with pytest.raises(Lb.IsingError) as e:
+        Lb.ising_create_csr(2, 3, rp, col3, val3, Lb.ISING_F32)        # rp[n] != nnz
+    assert e.value.status == Lb.ISING_E_INVALID_ARG
+    A = gen.er_csr(300, 4.0, 111)
+    P = GpuProblem(A=A)
+    try:
+        x0 = gen.uniform_x0(300, 1, 112)[:, 0]
+        x0[7] = np.nan
+        xd = torch.from_numpy(x0).to(dev)
+        with pytest.raises(Lb.IsingError) as e:
+            Lb.ising_solve(P.ctx, xd, 1, 10, P.params(1.0, 1e5))
+        assert e.value.status == Lb.ISING_E_NONFINITE
+        st = Lb.ising_solve(P.ctx, xd, 1, 10, P.params(1.0, 1e5), check=False)
+        assert st[0].iters_done == 1 and st[0].nonfinite == 1
+        with pytest.raises(Lb.IsingError) as e:
+            Lb.ising_solve(P.ctx, xd, 1, 10, P.params(-1.0, 1e5))
+        assert e.value.status == Lb.ISING_E_INVALID_ARG
+        assert Lb.ising_check_symmetric(P.ctx)
+    finally:
+        P.close()
+    # asymmetric CSR is detected on request
+    rp = torch.tensor([0, 1, 1], dtype=torch.int32, device=dev)
+    col = torch.tensor([1], dtype=torch.int32, device=dev)
+    val = torch.tensor([1.0], dtype=torch.float32, device=dev)
+    ctx = Lb.ising_create_csr(2, 1, rp, col, val, Lb.ISING_F32)
+    try:
+        assert not Lb.ising_check_symmetric(ctx)
+    finally:
+        Lb.ising_destroy(ctx)
