@@ -68,6 +68,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2509_01928_amd.build "
                       "or __graft_entry__.build()); there is no fallback path")
 
+# PyTorch ships its own HIP runtime.  Load it first so that the library binds
+# to the same runtime instance (same devices, streams and allocations) rather
+# than to a second copy from the system ROCm.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 _p = ctypes.c_void_p
