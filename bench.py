@@ -98,6 +98,12 @@ def main():
     E = torch.empty(1, dtype=torch.float64, device=dev)
     x_dtype = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
     log("context created")
+    # launch-shape tuning is setup, outside the timed region
+    p0, _ = L.ising_default_params(ctx, 1.0, 0)
+    p0.x_dtype = x_dtype
+    geometry, wg_per_cu, tune_ms = L.ising_autotune(ctx, xd, 10, p0)
+    log(f"autotune: geometry {geometry}, {wg_per_cu} workgroups/CU "
+        f"({', '.join(f'{m * 1e3:.0f}' for m in tune_ms)} us/iteration per geometry)")
 
     solve_ms = []
 
@@ -159,6 +165,7 @@ def main():
             "n": n, "nnz": nnz, "iters": args.iters, "restarts": 1,
             "x_storage": args.x_dtype, "couplings": "f32 CSR, int32 indices",
             "arithmetic": "f64", "parallelism": "single GPU",
+            "kernel_geometry": geometry, "workgroups_per_cu": wg_per_cu,
         },
         "iteration_us": per_iter_ms * 1e3,
         "energy": energy,

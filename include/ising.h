@@ -186,6 +186,31 @@ ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first,
 ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
                           double* E_dev, int64_t* E_int_dev, void* stream);
 
+/* ----------------------------------------------------------------- tuning
+ * The CSR step kernel has several row-block geometries (see
+ * ising_set_geometry).  They give identical results -- every row is summed
+ * in ascending column order whatever the geometry -- and differ in speed.
+ *
+ * ising_set_geometry: 0 = 256-row blocks, 1024-entry spans; 1 = 512-row
+ * blocks, 2048-entry spans; 2 = 512-row blocks, 4096-entry spans; 3 and 4 =
+ * one row per lane, two rows in flight, rows of up to one (3) or two (4)
+ * aligned 4-entry chunks loaded at once (longer rows take a slower path);
+ * -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
+ * workgroups launched per compute unit, 0 = as many as fit.  CSR contexts
+ * only.
+ *
+ * ising_autotune: time `iters` DOCH iterations (params as for ising_solve,
+ * from x0_dev with R = 1) for every geometry and workgroups-per-CU setting
+ * in {1, 2, 3, 4, all}, and keep the fastest pair for later solves.
+ * *geometry_out and *wg_per_cu_out (nullable) receive it, ms_per_iter_out
+ * (nullable, 5 entries) the best time of each geometry.  Synchronous.
+ * Overwrites the log of the last solve. */
+ising_status ising_set_geometry(ising_ctx* ctx, int32_t geometry, int32_t wg_per_cu);
+ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,
+                            const ising_params* params, void* stream,
+                            int32_t* geometry_out, int32_t* wg_per_cu_out,
+                            double* ms_per_iter_out);
+
 /* ------------------------------------------------------------------ misc */
 const char* ising_status_string(ising_status s);
 const char* ising_last_error(void);

@@ -17,7 +17,8 @@ __all__ = [
     "IsingError", "ising_params", "ising_stats", "ising_info", "lib", "LIB_PATH",
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
-    "ising_energy", "ising_status_string", "ising_last_error", "ising_version",
+    "ising_energy", "ising_set_geometry", "ising_autotune",
+    "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
 ]
 
@@ -91,6 +92,8 @@ _SIGS = {
     "ising_solve": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
     "ising_get_log": (_st, [_p, _i32, _i64, _i64, _p, _p, _p]),
     "ising_energy": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "ising_set_geometry": (_st, [_p, _i32, _i32]),
+    "ising_autotune": (_st, [_p, _p, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
     "ising_status_string": (ctypes.c_char_p, [_st]),
     "ising_last_error": (ctypes.c_char_p, []),
     "ising_version": (ctypes.c_char_p, []),
@@ -206,3 +209,19 @@ def ising_get_log(ctx, restart, first, count, stream=None):
 def ising_energy(ctx, s, R, E=None, E_int=None, stream=None):
     _check(lib.ising_energy(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
                             stream if stream is not None else current_stream()), "ising_energy")
+
+
+def ising_set_geometry(ctx, geometry, wg_per_cu=0) -> None:
+    _check(lib.ising_set_geometry(ctx, int(geometry), int(wg_per_cu)), "ising_set_geometry")
+
+
+def ising_autotune(ctx, x0, iters, params, stream=None):
+    """Returns (best geometry, best workgroups per CU, [best ms/iteration per geometry])."""
+    g = ctypes.c_int32(-1)
+    w = ctypes.c_int32(-1)
+    ms = (ctypes.c_double * 5)()
+    _check(lib.ising_autotune(ctx, ptr(x0), int(iters), ctypes.byref(params),
+                              stream if stream is not None else current_stream(),
+                              ctypes.byref(g), ctypes.byref(w), ctypes.cast(ms, _p)),
+           "ising_autotune")
+    return g.value, w.value, list(ms)

@@ -104,24 +104,60 @@ DenseView dense_view(const ising_ctx* c) {
     return v;
 }
 
-// Row blocks for the CSR kernels: consecutive rows, at most kBlockThreads
-// rows and kBlockNnz stored entries each; a longer row stands alone.
-std::vector<int32_t> make_blocks(const std::vector<int32_t>& rp, int64_t n) {
-    std::vector<int32_t> blk;
-    blk.reserve(static_cast<size_t>(n / 64 + 2));
+// Row blocks of the CSR step kernel for one geometry: consecutive rows, at
+// most `rows` of them, whose entries end within `span` entries of the first
+// entry rounded down to a multiple of 4; a row that does not fit alone is a
+// block of its own.  Block b is stored as (first row, first entry) at b, with
+// a sentinel (n, nnz) at the end.
+std::vector<int2> make_blocks(const std::vector<int32_t>& rp, int64_t n, int rows, int span) {
+    std::vector<int2> blk;
+    blk.reserve(static_cast<size_t>(n / (rows / 2 + 1) + 2));
     int64_t r = 0;
-    blk.push_back(0);
     while (r < n) {
-        int64_t r0 = r;
-        int64_t e0 = rp[r];
-        if (rp[r + 1] - e0 > doch::kBlockNnz) {
+        const int64_t r0 = r;
+        const int64_t ea = rp[r] & ~3;
+        blk.push_back(make_int2(static_cast<int>(r0), rp[r0]));
+        if (rp[r + 1] - ea > span) {
             r = r0 + 1;
         } else {
-            while (r < n && r - r0 < doch::kBlockThreads && rp[r + 1] - e0 <= doch::kBlockNnz) ++r;
+            while (r < n && r - r0 < rows && rp[r + 1] - ea <= span) ++r;
         }
-        blk.push_back(static_cast<int32_t>(r));
     }
+    blk.push_back(make_int2(static_cast<int>(n), rp[n]));
     return blk;
+}
+
+// Geometry from the mean row length: short rows favour 256-row blocks with
+// one 16-byte chunk per thread, longer rows wider spans.
+int default_geometry(int64_t n, int64_t nnz) {
+    const double d = static_cast<double>(nnz) / static_cast<double>(n);
+    if (d <= 4.0) return 0;
+    if (d <= 8.0) return 1;
+    return 2;
+}
+
+// Two resident workgroups per CU stream the read-mostly mix of the step
+// kernel faster than a full device (measured on gfx950); the row-block
+// kernels need at least that many to hide their barriers.
+int default_wg_per_cu(int geometry) { return geometry <= 2 ? 0 : 2; }
+
+ising_status ensure_plan(ising_ctx* c, int geometry, doch::CsrPlan** out) {
+    doch::CsrPlan& p = c->plans[geometry];
+    int rows = 0, span = 0;
+    doch::csr_geometry(geometry, &rows, &span);
+    if (rows == 0) {                 // lane-per-row kernels need no block table
+        p.geometry = geometry;
+        p.nblk = c->n;
+    } else if (!p.binfo) {
+        std::vector<int2> blk = make_blocks(c->rp_host, c->n, rows, span);
+        p.geometry = geometry;
+        p.nblk = static_cast<int64_t>(blk.size()) - 1;
+        HIP_OK(dev_alloc(&p.binfo, blk.size() * sizeof(int2)), "hipMalloc(blocks)");
+        HIP_OK(hipMemcpy(p.binfo, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice),
+               "copy blocks");
+    }
+    *out = &p;
+    return ISING_OK;
 }
 
 void free_ctx(ising_ctx* c) {
@@ -131,7 +167,7 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->val);
     dev_free(c->h);
     dev_free(c->J);
-    dev_free(c->blk);
+    for (auto& p : c->plans) dev_free(p.binfo);
     dev_free(c->xbuf[0]);
     dev_free(c->xbuf[1]);
     dev_free(c->partials);
@@ -236,8 +272,14 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
     c->vt = vt;
     hipError_t e;
     if ((e = dev_alloc(&c->rp, (n + 1) * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(rp)"));
-    if ((e = dev_alloc(&c->col, nnz * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(col)"));
-    if ((e = dev_alloc(&c->val, nnz * dtype_size(vt))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(val)"));
+    const int64_t padded = nnz + doch::kCsrPad;
+    if ((e = dev_alloc(&c->col, padded * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(col)"));
+    if ((e = dev_alloc(&c->val, padded * dtype_size(vt))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(val)"));
+    if ((e = hipMemsetAsync(c->col + nnz, 0, doch::kCsrPad * sizeof(int32_t), s)) != hipSuccess)
+        return bail(hip_fail(e, "memset pad"));
+    if ((e = hipMemsetAsync(static_cast<char*>(c->val) + nnz * dtype_size(vt), 0, doch::kCsrPad * dtype_size(vt), s)) !=
+        hipSuccess)
+        return bail(hip_fail(e, "memset pad"));
     if ((e = hipMemcpyAsync(c->rp, row_ptr_dev, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
         return bail(hip_fail(e, "copy row_ptr"));
     if (nnz > 0) {
@@ -264,11 +306,11 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
     if (flags[0]) return bail(fail(ISING_E_INVALID_ARG, "malformed CSR (offsets, column range or order)"));
     if (flags[1]) return bail(fail(ISING_E_NONZERO_DIAG, "a diagonal coupling J_ii is nonzero"));
     c->integer_J = flags[2] == 0;
-    std::vector<int32_t> blk = make_blocks(rp_host, n);
-    c->nblk = static_cast<int64_t>(blk.size()) - 1;
-    if ((e = dev_alloc(&c->blk, blk.size() * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(blk)"));
-    if ((e = hipMemcpy(c->blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
-        return bail(hip_fail(e, "copy blocks"));
+    c->rp_host = std::move(rp_host);
+    c->geometry = default_geometry(n, nnz);
+    c->wg_per_cu = default_wg_per_cu(c->geometry);
+    doch::CsrPlan* plan = nullptr;
+    if ((st = ensure_plan(c, c->geometry, &plan)) != ISING_OK) return bail(st);
     *out = c;
     return ISING_OK;
 }
@@ -475,9 +517,18 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
         HIP_OK(dev_alloc(&ctx->xbuf[1], xbytes), "hipMalloc(x)");
         ctx->xbuf_bytes = xbytes;
     }
-    const int grid = ctx->dense ? doch::dense_step_grid(ctx->n) : doch::csr_step_grid(ctx->nblk);
+    doch::CsrPlan* plan = nullptr;
+    if (!ctx->dense) {
+        ising_status pst = ensure_plan(ctx, ctx->geometry, &plan);
+        if (pst != ISING_OK) return pst;
+        plan->wg_per_cu = ctx->wg_per_cu;
+    }
+    // upper bound of the step kernels' grids: every workgroup that can be
+    // resident at once (256 CUs x at most 8 workgroups of 256 threads)
+    const int grid = ctx->dense ? doch::dense_step_grid(ctx->n) : 0;
+    const size_t max_grid = ctx->dense ? static_cast<size_t>(grid) : static_cast<size_t>(doch::kMaxStepGrid);
     HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
-                  static_cast<size_t>(grid) * R * doch::kNumPartials * sizeof(double)), "hipMalloc(partials)");
+                  max_grid * R * doch::kNumPartials * sizeof(double)), "hipMalloc(partials)");
     if (!ctx->ticket) {
         HIP_OK(dev_alloc(&ctx->ticket, kMaxR * sizeof(unsigned int)), "hipMalloc(ticket)");
         HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
@@ -505,7 +556,7 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
         a.k = k;
         a.log = ctx->log;
         hipError_t e = ctx->dense ? doch::launch_dense_step(dv, a, grid, s)
-                                  : doch::launch_csr_step(cv, ctx->blk, ctx->nblk, a, grid, s);
+                                  : doch::launch_csr_step(cv, *plan, a, s);
         if (e != hipSuccess) return hip_fail(e, "step launch");
     }
     ctx->last_R = R;
@@ -529,6 +580,67 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
         }
         if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
     }
+    return ISING_OK;
+}
+
+ising_status ising_set_geometry(ising_ctx* ctx, int32_t geometry, int32_t wg_per_cu) {
+    if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
+    if (ctx->dense) return fail(ISING_E_UNSUPPORTED, "geometries apply to CSR contexts");
+    if (geometry < -1 || geometry >= doch::kNumGeometries) return fail(ISING_E_INVALID_ARG, "bad geometry");
+    if (wg_per_cu < 0 || wg_per_cu > 32) return fail(ISING_E_INVALID_ARG, "wg_per_cu out of range");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    const int g = geometry < 0 ? default_geometry(ctx->n, ctx->nnz) : geometry;
+    doch::CsrPlan* plan = nullptr;
+    ising_status st = ensure_plan(ctx, g, &plan);
+    if (st != ISING_OK) return st;
+    ctx->geometry = g;
+    ctx->wg_per_cu = geometry < 0 ? default_wg_per_cu(g) : wg_per_cu;
+    return ISING_OK;
+}
+
+ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,
+                            const ising_params* params, void* stream, int32_t* geometry_out,
+                            int32_t* wg_per_cu_out, double* ms_per_iter_out) {
+    if (!ctx || !params || !x0_dev) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (ctx->dense) return fail(ISING_E_UNSUPPORTED, "geometries apply to CSR contexts");
+    if (iters < 1) return fail(ISING_E_INVALID_ARG, "iters < 1");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0), "event");
+    HIP_OK(hipEventCreate(&e1), "event");
+    int best = -1, best_wpc = 0;
+    float best_ms = 0.0f;
+    ising_params p = *params;
+    p.eps = 0.0;                     // time exactly `iters` iterations
+    ising_status st = ISING_OK;
+    // workgroups per CU to try (0 = as many as fit)
+    const int wpcs[] = {1, 2, 3, 4, 0};
+    for (int g = 0; g < doch::kNumGeometries && st == ISING_OK; ++g) {
+        float g_best = 0.0f;
+        for (int w : wpcs) {
+            if ((st = ising_set_geometry(ctx, g, w)) != ISING_OK) break;
+            if ((st = ising_solve(ctx, x0_dev, 1, 1, &p, nullptr, nullptr, nullptr, stream)) != ISING_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { st = fail(ISING_E_HIP, "event record"); break; }
+            if ((st = ising_solve(ctx, x0_dev, 1, iters, &p, nullptr, nullptr, nullptr, stream)) != ISING_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(ISING_E_HIP, "event sync");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (g_best == 0.0f || ms < g_best) g_best = ms;
+            if (best < 0 || ms < best_ms) { best = g; best_wpc = w; best_ms = ms; }
+        }
+        if (ms_per_iter_out) ms_per_iter_out[g] = g_best / static_cast<double>(iters);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ISING_OK) return st;
+    ctx->geometry = best;
+    ctx->wg_per_cu = best_wpc;
+    if (geometry_out) *geometry_out = best;
+    if (wg_per_cu_out) *wg_per_cu_out = best_wpc;
     return ISING_OK;
 }
 

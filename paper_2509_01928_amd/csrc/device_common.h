@@ -11,6 +11,23 @@ namespace doch {
 
 constexpr int kWave = 64;
 
+// Native 16/32-byte vectors for wide streaming loads.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Vec4;
+template <> struct Vec4<int> { using type = i32x4; };
+template <> struct Vec4<float> { using type = f32x4; };
+template <> struct Vec4<double> { using type = f64x4; };
+
+// Four consecutive elements starting at a 4-element-aligned index, streamed
+// past the caches.
+template <typename T>
+__device__ __forceinline__ typename Vec4<T>::type ld_stream4(const T* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const typename Vec4<T>::type*>(p));
+}
+
 // Round-to-nearest double operations that the compiler may not contract into
 // FMAs, so the update matches its defining expression operation by operation.
 __device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }

@@ -13,11 +13,15 @@
 
 namespace doch {
 
-// Rows per row block of the CSR kernels and the LDS budget (in products) of a
-// block.  A row longer than kBlockNnz gets a block of its own and is reduced
-// by the whole workgroup.
+// Row blocks of the CSR step kernel: a 256-thread workgroup handles up to
+// `rows` consecutive rows whose stored entries lie within `span` entries of
+// the block's first entry rounded down to a multiple of 4 (so they can be
+// streamed as aligned 16-byte chunks).  A row that does not fit gets a block
+// of its own and is reduced by the whole workgroup.
 constexpr int kBlockThreads = 256;
-constexpr int kBlockNnz = 2048;
+// Column and value arrays are padded by this many entries so that a 16-byte
+// chunk that starts before the last entry never reads past the allocation.
+constexpr int kCsrPad = 4;
 // Number of FP64 partial sums each workgroup contributes per restart and
 // iteration: sum x^4, sum x^2, sum x*z, sum (x_new - x)^2, sum h*x.
 constexpr int kNumPartials = 5;
@@ -62,6 +66,23 @@ struct DenseView {
     int ht;
 };
 
+// A launch plan of the CSR step kernel.  Geometries 0-2 are row-block
+// kernels (0: 256 rows and 1024-entry spans, 1: 512 rows / 2048, 2: 512 rows
+// / 4096) whose blocks are stored as (first row, first entry) pairs;
+// geometries 3 and 4 are lane-per-row kernels holding two rows per lane with
+// rows of up to one (3) or two (4) aligned 16-byte chunks in registers.
+// wg_per_cu caps the workgroups launched per CU (fewer resident workgroups
+// interleave reads and writes less and can stream faster).
+constexpr int kNumGeometries = 5;
+// Upper bound of a step kernel's grid (partial-sum buffers are sized for it).
+constexpr int kMaxStepGrid = 8192;
+struct CsrPlan {
+    int geometry = 1;
+    int2* binfo = nullptr;     // nblk + 1 entries
+    int64_t nblk = 0;
+    int wg_per_cu = 0;         // resident workgroups per CU to launch (0 = all that fit)
+};
+
 // Parameters of one DOCH iteration launch.
 struct StepArgs {
     const void* x_old;      // n' * R, type x_dtype
@@ -97,9 +118,12 @@ struct ising_ctx {
     // dense storage
     double* J = nullptr;
     int64_t ld = 0;
-    // row blocks of the CSR kernels for R = 1
-    int32_t* blk = nullptr;  // block b covers rows [blk[b], blk[b+1])
-    int64_t nblk = 0;
+    // launch plans of the CSR step kernel, one per block geometry (built on
+    // first use), and the geometry solves use (-1: chosen from the row lengths)
+    doch::CsrPlan plans[doch::kNumGeometries];
+    int geometry = -1;
+    int wg_per_cu = 0;
+    std::vector<int32_t> rp_host;
     // solve workspace
     void* xbuf[2] = {nullptr, nullptr};
     size_t xbuf_bytes = 0;
@@ -121,9 +145,9 @@ namespace doch {
 
 // ---- launchers (kernels_csr.hip) ----
 hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s);
-hipError_t launch_csr_step(const CsrView& A, const int32_t* blk, int64_t nblk,
-                           const StepArgs& a, int grid, hipStream_t s);
-int csr_step_grid(int64_t nblk);
+void csr_geometry(int geometry, int* rows, int* span);
+hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs& a,
+                           hipStream_t s);
 hipError_t launch_csr_energy(const CsrView& A, const int8_t* s_spins, int R,
                              double* partials, unsigned int* ticket, int grid,
                              double* E, int64_t* E_int, hipStream_t s);

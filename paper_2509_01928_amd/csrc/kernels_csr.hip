@@ -1,14 +1,15 @@
 // kernels_csr.hip -- sparse (CSR) kernels of the DOCH hot path for gfx950.
 //
 // One DOCH iteration (Methods, eq:FPE / Alg. 1) on a CSR coupling matrix is a
-// single streaming pass: row blocks of up to 256 rows and 2048 stored
+// single streaming pass: row blocks of up to 512 rows and 2045 stored
 // entries are assigned to workgroups; a workgroup streams the block's column
-// indices and values with non-temporal loads (they are used once per
-// iteration, so they should not evict the iterate from L2), gathers the
-// iterate, parks the products in LDS, and then one thread per row sums its
-// products in ascending column order, applies the cube-root update and adds
-// to the iteration's FP64 partial sums.  The last workgroup finishes the
-// iteration (H, r, the field spin) -- see step_common.h.
+// indices and values as 16-byte non-temporal chunks (they are used once per
+// iteration, so they should not evict the iterate from L2), all requested
+// before the first is used, gathers the iterate, parks the products in LDS,
+// and then one thread per row sums its products in ascending column order,
+// applies the cube-root update and adds to the iteration's FP64 partial
+// sums.  The last workgroup finishes the iteration (H, r, the field spin) --
+// see step_common.h.
 //
 // Blocks are dealt out XCD-aware: workgroup w runs on XCD w mod 8, and XCD c
 // owns the contiguous c-th eighth of the blocks, so the rows being gathered
@@ -41,13 +42,154 @@ __device__ __forceinline__ void block_range(int64_t nblk, int64_t& b, int64_t& b
     }
 }
 
-template <typename XT, typename VT, typename HT, bool FIELD>
+// Registers of one row block in flight: its bounds and every value the
+// block's rows need from HBM, requested by issue_block() one block ahead of
+// its use.
+template <typename XT, typename VT, typename HT, int CH, int RPT>
+struct Stage {
+    int r0, r1, e0, e1;
+    typename Vec4<int>::type cv[CH];
+    typename Vec4<VT>::type vv[CH];
+    int rpv[RPT];
+    XT xi[RPT];
+    HT hv[RPT];
+};
+
+template <int CH, int RPT>
+struct Geometry {
+    static constexpr int rows = NT * RPT;
+    static constexpr int span = 4 * NT * CH;
+};
+
+template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT>
+__device__ __forceinline__ void issue_block(Stage<XT, VT, HT, CH, RPT>& s, int64_t b,
+                                            const int2* __restrict__ binfo,
+                                            const int32_t* __restrict__ rp,
+                                            const int32_t* __restrict__ col,
+                                            const VT* __restrict__ val,
+                                            const HT* __restrict__ h, const XT* __restrict__ x) {
+    const int2 m0 = binfo[b], m1 = binfo[b + 1];
+    s.r0 = m0.x;
+    s.e0 = m0.y;
+    s.r1 = m1.x;
+    s.e1 = m1.y;
+    const int ea = s.e0 & ~3;
+    if (s.e1 - ea > Geometry<CH, RPT>::span) return;      // long row: loaded on its own
+    const int t = static_cast<int>(threadIdx.x);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int base = ea + 4 * (t + NT * u);
+        if (base < s.e1) {
+            s.cv[u] = ld_stream4(col + base);
+            s.vv[u] = ld_stream4(val + base);
+        }
+    }
+    const int nr = s.r1 - s.r0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int rr = t + q * NT;
+        if (rr < nr) {
+            s.rpv[q] = ld_stream(rp + s.r0 + rr);
+            s.xi[q] = x[s.r0 + rr];
+            if (FIELD) s.hv[q] = ld_stream(h + s.r0 + rr);
+        }
+    }
+}
+
+// Process the block held in `cur`; the loads of the next block (if any) are
+// issued into `nxt` after the current gathers, so they overlap this block's
+// gathers, LDS traffic and arithmetic without delaying them.
+template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT>
+__device__ __forceinline__ void process_block(
+    Stage<XT, VT, HT, CH, RPT>& cur, Stage<XT, VT, HT, CH, RPT>& nxt, bool has_next,
+    int64_t nb, const int2* __restrict__ binfo, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ col, const VT* __restrict__ val, const HT* __restrict__ h,
+    const XT* __restrict__ x, XT* __restrict__ xn, double t_old, const StepArgs& a,
+    double* prod, int* rps, double* red, double (&acc)[kNumPartials]) {
+    using G = Geometry<CH, RPT>;
+    const int t = static_cast<int>(threadIdx.x);
+    const int cnt = cur.e1 - cur.e0;
+    const int ea = cur.e0 & ~3;
+    if (cur.e1 - ea <= G::span) {
+        XT g[CH][4];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int base = ea + 4 * (t + NT * u);
+            if (base < cur.e1) {
+                g[u][0] = x[cur.cv[u].x];
+                g[u][1] = x[cur.cv[u].y];
+                g[u][2] = x[cur.cv[u].z];
+                g[u][3] = x[cur.cv[u].w];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (has_next) issue_block<XT, VT, HT, FIELD, CH, RPT>(nxt, nb, binfo, rp, col, val, h, x);
+        __builtin_amdgcn_sched_barrier(0);
+        const int nr = cur.r1 - cur.r0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int rr = t + q * NT;
+            if (rr < nr) rps[rr] = cur.rpv[q];
+        }
+        if (t == 0) rps[nr] = cur.e1;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int base = ea + 4 * (t + NT * u);
+            if (base < cur.e1) {
+                double* p = prod + (base - ea);
+                p[0] = dmul(static_cast<double>(cur.vv[u].x), static_cast<double>(g[u][0]));
+                p[1] = dmul(static_cast<double>(cur.vv[u].y), static_cast<double>(g[u][1]));
+                p[2] = dmul(static_cast<double>(cur.vv[u].z), static_cast<double>(g[u][2]));
+                p[3] = dmul(static_cast<double>(cur.vv[u].w), static_cast<double>(g[u][3]));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int rr = t + q * NT;
+            if (rr < nr) {
+                const int lo = rps[rr] - ea, hi = rps[rr + 1] - ea;
+                double z = 0.0;
+                for (int e = lo; e < hi; ++e) z = dadd(z, prod[e]);
+                const double hq = FIELD ? static_cast<double>(cur.hv[q]) : 0.0;
+                if (FIELD) z = dadd(z, dmul(hq, t_old));
+                update_row<XT>(z, static_cast<double>(cur.xi[q]), hq, FIELD, a, xn, cur.r0 + rr, acc);
+            }
+        }
+        __syncthreads();
+    } else {
+        if (has_next) issue_block<XT, VT, HT, FIELD, CH, RPT>(nxt, nb, binfo, rp, col, val, h, x);
+        // one long row: the whole workgroup reduces it
+        const int r0 = cur.r0, e0 = cur.e0;
+        double part[1] = {0.0};
+        for (int e = t; e < cnt; e += NT) {
+            const int c = ld_stream(col + e0 + e);
+            const double v = static_cast<double>(ld_stream(val + e0 + e));
+            part[0] = dadd(part[0], dmul(v, static_cast<double>(x[c])));
+        }
+        block_sum<1, NT>(part, red);
+        if (t == 0) {
+            double z = part[0];
+            double hr = 0.0;
+            if (FIELD) {
+                hr = static_cast<double>(h[r0]);
+                z = dadd(z, dmul(hr, t_old));
+            }
+            update_row<XT>(z, static_cast<double>(x[r0]), hr, FIELD, a, xn, r0, acc);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT>
 __global__ __launch_bounds__(NT) void csr_step_kernel(
     int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const VT* __restrict__ val, const HT* __restrict__ h,
-    const int32_t* __restrict__ blk, int64_t nblk, StepArgs a) {
+    const int2* __restrict__ binfo, int64_t nblk, StepArgs a) {
     if (a.state->done) return;
-    __shared__ double prod[kBlockNnz];
+    using G = Geometry<CH, RPT>;
+    __shared__ double prod[G::span];
+    __shared__ int rps[G::rows + 1];
     __shared__ double red[kNumPartials * NW];
     const XT* __restrict__ x = static_cast<const XT*>(a.x_old);
     XT* __restrict__ xn = static_cast<XT*>(a.x_new);
@@ -58,49 +200,127 @@ __global__ __launch_bounds__(NT) void csr_step_kernel(
 
     int64_t b, bend, bstep;
     block_range(nblk, b, bend, bstep);
-    for (; b < bend; b += bstep) {
-        const int r0 = blk[b], r1 = blk[b + 1];
-        const int e0 = rp[r0], e1 = rp[r1];
-        const int cnt = e1 - e0;
-        if (cnt <= kBlockNnz) {
-            for (int e = threadIdx.x; e < cnt; e += NT) {
-                const int c = ld_stream(col + e0 + e);
-                const double v = static_cast<double>(ld_stream(val + e0 + e));
-                prod[e] = dmul(v, static_cast<double>(x[c]));
+    Stage<XT, VT, HT, CH, RPT> sa, sb;
+    if (b < bend) issue_block<XT, VT, HT, FIELD, CH, RPT>(sa, b, binfo, rp, col, val, h, x);
+    // two stages alternate roles, so no register copy waits on a load
+    while (b < bend) {
+        int64_t nb = b + bstep;
+        process_block<XT, VT, HT, FIELD, CH, RPT>(sa, sb, nb < bend, nb, binfo, rp, col, val, h, x,
+                                                  xn, t_old, a, prod, rps, red, acc);
+        b = nb;
+        if (b >= bend) break;
+        nb = b + bstep;
+        process_block<XT, VT, HT, FIELD, CH, RPT>(sb, sa, nb < bend, nb, binfo, rp, col, val, h, x,
+                                                  xn, t_old, a, prod, rps, red, acc);
+        b = nb;
+    }
+    step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
+}
+
+// Lane-per-row variant for short rows.  Each lane owns U rows at a time
+// (rows i, i + S, ..., S = threads per XCD share) and loads a row's entries
+// as up to MAXC aligned 16-byte chunks straight into registers -- no LDS, no
+// barriers, no block table.  Rows that need more chunks fall back to an
+// element loop.  Sums still run in ascending column order.
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC>
+__global__ __launch_bounds__(NT) void csr_rowlane_kernel(
+    int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const VT* __restrict__ val, const HT* __restrict__ h, StepArgs a) {
+    if (a.state->done) return;
+    __shared__ double red[kNumPartials * NW];
+    const XT* __restrict__ x = static_cast<const XT*>(a.x_old);
+    XT* __restrict__ xn = static_cast<XT*>(a.x_new);
+    const double t_old = FIELD ? static_cast<double>(x[n]) : 0.0;
+    double acc[kNumPartials];
+#pragma unroll
+    for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+
+    // XCD c (workgroups w with w mod 8 = c) owns the c-th eighth of the rows
+    const unsigned G = gridDim.x;
+    int64_t lo, hi, first, stride;
+    if ((G & 7u) == 0) {
+        const unsigned xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
+        lo = n * xcd / 8;
+        hi = n * (xcd + 1) / 8;
+        first = lo + static_cast<int64_t>(slot) * NT + threadIdx.x;
+        stride = static_cast<int64_t>(G >> 3) * NT;
+    } else {
+        lo = 0;
+        hi = n;
+        first = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+        stride = static_cast<int64_t>(G) * NT;
+    }
+    for (int64_t base = first; base < hi; base += stride * U) {
+        int s[U], e[U], a0[U];
+        XT xi[U];
+        HT hv[U];
+        typename Vec4<int>::type cv[U][MAXC];
+        typename Vec4<VT>::type vv[U][MAXC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * stride;
+            if (i < hi) {
+                s[u] = rp[i];
+                e[u] = rp[i + 1];
+                xi[u] = x[i];
+                if (FIELD) hv[u] = ld_stream(h + i);
             }
-            __syncthreads();
-            const int i = r0 + static_cast<int>(threadIdx.x);
-            if (i < r1) {
-                const int lo = rp[i] - e0, hi = rp[i + 1] - e0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * stride;
+            if (i < hi) {
+                a0[u] = s[u] & ~3;
+#pragma unroll
+                for (int c = 0; c < MAXC; ++c) {
+                    if (a0[u] + 4 * c < e[u]) {
+                        cv[u][c] = ld_stream4(col + a0[u] + 4 * c);
+                        vv[u][c] = ld_stream4(val + a0[u] + 4 * c);
+                    }
+                }
+            }
+        }
+        XT g[U][MAXC][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * stride;
+            if (i < hi) {
+#pragma unroll
+                for (int c = 0; c < MAXC; ++c) {
+                    const int b0 = a0[u] + 4 * c;
+                    if (b0 < e[u]) {
+                        const int cc[4] = {cv[u][c].x, cv[u][c].y, cv[u][c].z, cv[u][c].w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (b0 + q >= s[u] && b0 + q < e[u]) g[u][c][q] = x[cc[q]];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * stride;
+            if (i < hi) {
                 double z = 0.0;
-                for (int e = lo; e < hi; ++e) z = dadd(z, prod[e]);
-                double hv = 0.0;
-                if (FIELD) {
-                    hv = static_cast<double>(ld_stream(h + i));
-                    z = dadd(z, dmul(hv, t_old));
+                if (e[u] - a0[u] <= 4 * MAXC) {
+#pragma unroll
+                    for (int c = 0; c < MAXC; ++c) {
+                        const int b0 = a0[u] + 4 * c;
+                        const double vd[4] = {static_cast<double>(vv[u][c].x), static_cast<double>(vv[u][c].y),
+                                              static_cast<double>(vv[u][c].z), static_cast<double>(vv[u][c].w)};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (b0 + q >= s[u] && b0 + q < e[u])
+                                z = dadd(z, dmul(vd[q], static_cast<double>(g[u][c][q])));
+                    }
+                } else {
+                    for (int k = s[u]; k < e[u]; ++k)
+                        z = dadd(z, dmul(static_cast<double>(val[k]), static_cast<double>(x[col[k]])));
                 }
-                update_row<XT>(z, static_cast<double>(x[i]), hv, FIELD, a, xn, i, acc);
+                const double hq = FIELD ? static_cast<double>(hv[u]) : 0.0;
+                if (FIELD) z = dadd(z, dmul(hq, t_old));
+                update_row<XT>(z, static_cast<double>(xi[u]), hq, FIELD, a, xn, i, acc);
             }
-            __syncthreads();
-        } else {
-            // one long row: the whole workgroup reduces it
-            double part[1] = {0.0};
-            for (int e = threadIdx.x; e < cnt; e += NT) {
-                const int c = ld_stream(col + e0 + e);
-                const double v = static_cast<double>(ld_stream(val + e0 + e));
-                part[0] = dadd(part[0], dmul(v, static_cast<double>(x[c])));
-            }
-            block_sum<1, NT>(part, red);
-            if (threadIdx.x == 0) {
-                double z = part[0];
-                double hv = 0.0;
-                if (FIELD) {
-                    hv = static_cast<double>(h[r0]);
-                    z = dadd(z, dmul(hv, t_old));
-                }
-                update_row<XT>(z, static_cast<double>(x[r0]), hv, FIELD, a, xn, r0, acc);
-            }
-            __syncthreads();
         }
     }
     step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
@@ -373,48 +593,111 @@ int grid_for_rows(int64_t n) {
 
 }  // namespace
 
-int csr_step_grid(int64_t nblk) {
-    if (nblk < 64) return static_cast<int>(nblk < 1 ? 1 : nblk);
-    int64_t g = nblk < 2048 ? nblk : 2048;
-    return static_cast<int>(g & ~static_cast<int64_t>(7));
-}
-
-#define DOCH_DISPATCH_VT_HT(A, BODY)                                              \
+#define DOCH_DISPATCH_VT_HT(A, ...)                                               \
     do {                                                                          \
         if ((A).vt == ISING_F64 && (A).ht == ISING_F64) {                         \
-            using VT = double; using HT = double; BODY;                           \
+            using VT = double; using HT = double; __VA_ARGS__;                    \
         } else if ((A).vt == ISING_F64) {                                         \
-            using VT = double; using HT = float; BODY;                            \
+            using VT = double; using HT = float; __VA_ARGS__;                     \
         } else if ((A).ht == ISING_F64) {                                         \
-            using VT = float; using HT = double; BODY;                            \
+            using VT = float; using HT = double; __VA_ARGS__;                     \
         } else {                                                                  \
-            using VT = float; using HT = float; BODY;                             \
+            using VT = float; using HT = float; __VA_ARGS__;                      \
         }                                                                         \
     } while (0)
 
-hipError_t launch_csr_step(const CsrView& A, const int32_t* blk, int64_t nblk,
-                           const StepArgs& a, int grid, hipStream_t s) {
-    const bool field = A.h != nullptr;
-    DOCH_DISPATCH_VT_HT(A, {
-        const VT* val = static_cast<const VT*>(A.val);
-        const HT* h = static_cast<const HT*>(A.h);
-        if (a.x_dtype == ISING_F64) {
-            if (field)
-                hipLaunchKernelGGL((csr_step_kernel<double, VT, HT, true>), dim3(grid), dim3(NT), 0, s,
-                                   A.n, A.rp, A.col, val, h, blk, nblk, a);
-            else
-                hipLaunchKernelGGL((csr_step_kernel<double, VT, HT, false>), dim3(grid), dim3(NT), 0, s,
-                                   A.n, A.rp, A.col, val, h, blk, nblk, a);
-        } else {
-            if (field)
-                hipLaunchKernelGGL((csr_step_kernel<float, VT, HT, true>), dim3(grid), dim3(NT), 0, s,
-                                   A.n, A.rp, A.col, val, h, blk, nblk, a);
-            else
-                hipLaunchKernelGGL((csr_step_kernel<float, VT, HT, false>), dim3(grid), dim3(NT), 0, s,
-                                   A.n, A.rp, A.col, val, h, blk, nblk, a);
-        }
-    });
+namespace {
+
+template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT>
+hipError_t launch_step_t(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    auto kern = csr_step_kernel<XT, VT, HT, FIELD, CH, RPT>;
+    static int per_cu = 0;      // resident workgroups per CU for this instantiation
+    static int cus = 0;
+    if (per_cu == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        int occ = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, 0);
+        if (e != hipSuccess) return e;
+        per_cu = occ < 1 ? 1 : occ;
+    }
+    const int wpc = (plan.wg_per_cu > 0 && plan.wg_per_cu < per_cu) ? plan.wg_per_cu : per_cu;
+    int64_t grid = static_cast<int64_t>(wpc) * cus;
+    if (grid > kMaxStepGrid) grid = kMaxStepGrid;
+    if (grid >= 8) grid &= ~static_cast<int64_t>(7);
+    if (grid > plan.nblk) grid = plan.nblk;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NT), 0, s, A.n, A.rp, A.col,
+                       static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), plan.binfo,
+                       plan.nblk, a);
     return hipGetLastError();
+}
+
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC>
+hipError_t launch_rowlane_t(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    auto kern = csr_rowlane_kernel<XT, VT, HT, FIELD, U, MAXC>;
+    static int per_cu = 0;
+    static int cus = 0;
+    if (per_cu == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        int occ = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, 0);
+        if (e != hipSuccess) return e;
+        per_cu = occ < 1 ? 1 : occ;
+    }
+    const int wpc = (plan.wg_per_cu > 0 && plan.wg_per_cu < per_cu) ? plan.wg_per_cu : per_cu;
+    int64_t grid = static_cast<int64_t>(wpc) * cus;
+    if (grid > kMaxStepGrid) grid = kMaxStepGrid;
+    const int64_t need = (A.n + NT - 1) / NT;           // one row per thread at most
+    if (grid > need) grid = need;
+    if (grid >= 8) grid &= ~static_cast<int64_t>(7);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NT), 0, s, A.n, A.rp, A.col,
+                       static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), a);
+    return hipGetLastError();
+}
+
+template <typename XT, typename VT, typename HT, bool FIELD>
+hipError_t launch_step_geo(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    switch (plan.geometry) {
+        case 0: return launch_step_t<XT, VT, HT, FIELD, 1, 1>(A, plan, a, s);
+        case 1: return launch_step_t<XT, VT, HT, FIELD, 2, 2>(A, plan, a, s);
+        case 2: return launch_step_t<XT, VT, HT, FIELD, 4, 2>(A, plan, a, s);
+        case 3: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 1>(A, plan, a, s);
+        default: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 2>(A, plan, a, s);
+    }
+}
+
+template <typename XT, typename VT, typename HT>
+hipError_t launch_step_field(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    if (A.h) return launch_step_geo<XT, VT, HT, true>(A, plan, a, s);
+    return launch_step_geo<XT, VT, HT, false>(A, plan, a, s);
+}
+
+}  // namespace
+
+void csr_geometry(int geometry, int* rows, int* span) {
+    switch (geometry) {
+        case 0: *rows = Geometry<1, 1>::rows; *span = Geometry<1, 1>::span; break;
+        case 1: *rows = Geometry<2, 2>::rows; *span = Geometry<2, 2>::span; break;
+        case 2: *rows = Geometry<4, 2>::rows; *span = Geometry<4, 2>::span; break;
+        default: *rows = 0; *span = 0; break;      // lane-per-row kernels use no blocks
+    }
+}
+
+hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    DOCH_DISPATCH_VT_HT(A, {
+        if (a.x_dtype == ISING_F64) return launch_step_field<double, VT, HT>(A, plan, a, s);
+        return launch_step_field<float, VT, HT>(A, plan, a, s);
+    });
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_csr_energy(const CsrView& A, const int8_t* s_spins, int R,

@@ -23,7 +23,8 @@ __device__ __forceinline__ void update_row(double z, double xi, double hi,
     double y = ddiv(dadd(z, dmul(a.alpha, xi)), a.beta);
     double xn = cbrt(y);
     XT xs = static_cast<XT>(xn);
-    x_new[i] = xs;
+    // streamed out past the caches: the next read of it is an iteration away
+    __builtin_nontemporal_store(xs, x_new + i);
     double d = dsub(static_cast<double>(xs), xi);
     double x2 = dmul(xi, xi);
     acc[P_X4] = dadd(acc[P_X4], dmul(x2, x2));

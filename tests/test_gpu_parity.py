@@ -17,12 +17,14 @@ from tests._util import (GpuProblem, assert_iterate_parity, assert_log_parity,
 pytestmark = pytest.mark.gpu
 
 
-def run_both(A, x0, iters, eta=1.0, method="auto", eps=0.0, val_dtype="f32"):
+def run_both(A, x0, iters, eta=1.0, method="auto", eps=0.0, val_dtype="f32", geometry=-1):
     B = orc.problem_matrix(A)
     alpha, beta, _ = orc.default_params(B, eta, method=method)
     tr = orc.doch(B, x0, alpha, beta, iters, eps=eps)
     P = GpuProblem(A=A, val_dtype=val_dtype)
     try:
+        if geometry >= 0:
+            P.L.ising_set_geometry(P.ctx, geometry, 1 if geometry % 2 else 0)
         x, s, st = P.solve(x0, alpha, beta, iters, eps=eps)
         H, r = P.log(st[0].iters_done)
     finally:
@@ -38,13 +40,15 @@ def check_all(A, tr, x, s, st, H, r, label):
     assert_log_parity(H, r, tr, label)
 
 
+@pytest.mark.parametrize("geometry", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("n,d,seed,iters", [(3000, 6.0, 11, 300), (777, 3.0, 12, 200),
                                             (5000, 20.0, 13, 150)])
-def test_er_fp64_parity(n, d, seed, iters):
+def test_er_fp64_parity(n, d, seed, iters, geometry):
+    """Every row-block geometry gives the oracle's trajectory."""
     A = gen.er_csr(n, d, seed)
     x0 = gen.uniform_x0(n, 1, seed + 100)[:, 0]
-    B, tr, x, s, st, H, r = run_both(A, x0, iters, method="wigner")
-    check_all(A, tr, x, s, st, H, r, f"ER n={n}")
+    B, tr, x, s, st, H, r = run_both(A, x0, iters, method="wigner", geometry=geometry)
+    check_all(A, tr, x, s, st, H, r, f"ER n={n} geometry {geometry}")
 
 
 def test_er_c2_full_config():
@@ -63,13 +67,14 @@ def test_er_c2_full_config():
     assert E[0] == orc.energy(A, s)
 
 
+@pytest.mark.parametrize("geometry", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("L,iters", [(64, 300), (97, 120)])
-def test_torus_with_field_fp64_parity(L, iters):
+def test_torus_with_field_fp64_parity(L, iters, geometry):
     """Lattice with h ~ N(0, 0.1^2): the extra spin of Supp. Note 1."""
     A = gen.torus_csr(L, 1003, h_std=0.1)
     x0 = gen.uniform_x0(L * L + 1, 1, 2003)[:, 0]
-    B, tr, x, s, st, H, r = run_both(A, x0, iters)
-    check_all(A, tr, x, s, st, H, r, f"torus L={L}")
+    B, tr, x, s, st, H, r = run_both(A, x0, iters, geometry=geometry)
+    check_all(A, tr, x, s, st, H, r, f"torus L={L} geometry {geometry}")
 
 
 def test_values_in_fp64_storage():
@@ -98,10 +103,11 @@ def test_long_rows_and_empty_rows():
     J[4000:4100, :] = 0
     J[:, 4000:4100] = 0
     A = gen.csr_from_dense(J.astype(np.float64))
-    assert np.diff(A.row_ptr).max() > 2048 and np.sum(np.diff(A.row_ptr) == 0) >= 100
+    assert np.diff(A.row_ptr).max() > 4096 and np.sum(np.diff(A.row_ptr) == 0) >= 100
     x0 = gen.uniform_x0(n, 1, 33)[:, 0]
-    B, tr, x, s, st, H, r = run_both(A, x0, 150)
-    check_all(A, tr, x, s, st, H, r, "long rows")
+    for geometry in (0, 1, 2, 3, 4):
+        B, tr, x, s, st, H, r = run_both(A, x0, 150, geometry=geometry)
+        check_all(A, tr, x, s, st, H, r, f"long rows geometry {geometry}")
 
 
 @pytest.mark.parametrize("n,iters", [(300, 400), (1024, 1000)])
@@ -326,3 +332,23 @@ def test_error_paths():
         assert not Lb.ising_check_symmetric(ctx)
     finally:
         Lb.ising_destroy(ctx)
+
+
+def test_autotune_keeps_results():
+    """The autotuner only picks among geometries; the answer does not change."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    A = gen.torus_csr(200, 121, h_std=0.1)
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B)
+    x0 = gen.uniform_x0(A.n + 1, 1, 122)[:, 0]
+    tr = orc.doch(B, x0, alpha, beta, 60)
+    P = GpuProblem(A=A)
+    try:
+        xd = torch.from_numpy(x0).to("cuda:0")
+        g, w, ms = Lb.ising_autotune(P.ctx, xd, 5, P.params(alpha, beta))
+        assert g in (0, 1, 2, 3, 4) and w in (0, 1, 2, 3, 4) and all(m > 0 for m in ms)
+        x, s, st = P.solve(x0, alpha, beta, 60)
+    finally:
+        P.close()
+    assert_iterate_parity(x[:, 0], tr.x, "after autotune")
