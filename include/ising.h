@@ -195,7 +195,8 @@ ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
  * blocks, 2048-entry spans; 2 = 512-row blocks, 4096-entry spans; 3 and 4 =
  * one row per lane, two rows in flight, rows of up to one (3) or two (4)
  * aligned 4-entry chunks loaded at once (longer rows take a slower path);
- * -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
+ * 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in order from a
+ * per-XCD counter; -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
  * workgroups launched per compute unit, 0 = as many as fit.  CSR contexts
  * only.
  *
@@ -203,7 +204,7 @@ ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
  * from x0_dev with R = 1) for every geometry and workgroups-per-CU setting
  * in {1, 2, 3, 4, all}, and keep the fastest pair for later solves.
  * *geometry_out and *wg_per_cu_out (nullable) receive it, ms_per_iter_out
- * (nullable, 5 entries) the best time of each geometry.  Synchronous.
+ * (nullable, 8 entries) the best time of each geometry.  Synchronous.
  * Overwrites the log of the last solve. */
 ising_status ising_set_geometry(ising_ctx* ctx, int32_t geometry, int32_t wg_per_cu);
 ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,

@@ -219,7 +219,7 @@ def ising_autotune(ctx, x0, iters, params, stream=None):
     """Returns (best geometry, best workgroups per CU, [best ms/iteration per geometry])."""
     g = ctypes.c_int32(-1)
     w = ctypes.c_int32(-1)
-    ms = (ctypes.c_double * 5)()
+    ms = (ctypes.c_double * 8)()
     _check(lib.ising_autotune(ctx, ptr(x0), int(iters), ctypes.byref(params),
                               stream if stream is not None else current_stream(),
                               ctypes.byref(g), ctypes.byref(w), ctypes.cast(ms, _p)),

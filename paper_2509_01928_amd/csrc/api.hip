@@ -530,13 +530,15 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
                   max_grid * R * doch::kNumPartials * sizeof(double)), "hipMalloc(partials)");
     if (!ctx->ticket) {
-        HIP_OK(dev_alloc(&ctx->ticket, kMaxR * sizeof(unsigned int)), "hipMalloc(ticket)");
+        HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)),
+               "hipMalloc(ticket)");
         HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
         ctx->state_cap = kMaxR;
     }
     HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)),
            "hipMalloc(log)");
-    HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, s), "init");
+    unsigned int* sched = ctx->ticket + kMaxR;
+    HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, sched, s), "init");
     HIP_OK(doch::launch_load_x0(x0_dev, ctx->xbuf[0], p.x_dtype, ctx->np * R, s), "load x0");
     StepArgs a;
     a.x_dtype = p.x_dtype;
@@ -546,6 +548,7 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     a.eps = p.eps;
     a.partials = ctx->partials;
     a.ticket = ctx->ticket;
+    a.sched = ctx->dense ? nullptr : sched;
     a.state = ctx->state;
     a.all_done_flag = 0;
     const CsrView cv = csr_view(ctx);

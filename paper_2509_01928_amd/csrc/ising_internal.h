@@ -70,10 +70,15 @@ struct DenseView {
 // kernels (0: 256 rows and 1024-entry spans, 1: 512 rows / 2048, 2: 512 rows
 // / 4096) whose blocks are stored as (first row, first entry) pairs;
 // geometries 3 and 4 are lane-per-row kernels holding two rows per lane with
-// rows of up to one (3) or two (4) aligned 16-byte chunks in registers.
+// rows of up to one (3) or two (4) aligned 16-byte chunks in registers;
+// geometries 5-7 are 0-2 with blocks handed out in order by a per-XCD
+// counter instead of a fixed stride.
 // wg_per_cu caps the workgroups launched per CU (fewer resident workgroups
 // interleave reads and writes less and can stream faster).
-constexpr int kNumGeometries = 5;
+constexpr int kNumGeometries = 8;
+// Block counters of the dynamically scheduled kernels sit this many uints
+// apart (one 128-byte line each).
+constexpr int kSchedStride = 32;
 // Upper bound of a step kernel's grid (partial-sum buffers are sized for it).
 constexpr int kMaxStepGrid = 8192;
 struct CsrPlan {
@@ -93,6 +98,7 @@ struct StepArgs {
     int64_t k;              // iteration index
     double* partials;       // [grid][R][kNumPartials]
     unsigned int* ticket;
+    unsigned int* sched;    // per-XCD block counters (kSchedStride apart), or nullptr
     double* log;            // [iters][R][2]: (H, r)
     RestartState* state;    // [R]
     int all_done_flag;      // unused placeholder
@@ -179,7 +185,7 @@ hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s
 hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,
                           hipStream_t s);
 hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket,
-                             hipStream_t s);
+                             unsigned int* sched, hipStream_t s);
 hipError_t launch_finish(const void* xb0, const void* xb1, int x_dtype,
                          const RestartState* st, int64_t n, int64_t np, int R,
                          bool field, double* x_out, int8_t* s_out, hipStream_t s);

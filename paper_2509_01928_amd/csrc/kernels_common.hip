@@ -26,7 +26,9 @@ __global__ __launch_bounds__(NT) void load_x0_kernel(const double* __restrict__ 
         x[t] = static_cast<XT>(x0[t]);
 }
 
-__global__ void init_state_kernel(RestartState* st, int R, unsigned int* ticket) {
+__global__ void init_state_kernel(RestartState* st, int R, unsigned int* ticket,
+                                  unsigned int* sched) {
+    if (sched && threadIdx.x < 8) sched[threadIdx.x * kSchedStride] = 0u;
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
         st[r].iters_done = 0;
         st[r].done = 0;
@@ -91,8 +93,9 @@ hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket, hipStream_t s) {
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, s, st, R, ticket);
+hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket, unsigned int* sched,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, s, st, R, ticket, sched);
     return hipGetLastError();
 }
 

@@ -181,7 +181,12 @@ __device__ __forceinline__ void process_block(
     }
 }
 
-template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT>
+// DYN = false: workgroup w takes every (G/8)-th block of its XCD's range.
+// DYN = true: the workgroups of an XCD take the blocks of its range in order
+// from a shared counter, each claiming the block after next while it works,
+// so an XCD's workgroups stay on neighbouring blocks (their gathered iterate
+// entries stay in that XCD's L2) and finish together.
+template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT, bool DYN>
 __global__ __launch_bounds__(NT) void csr_step_kernel(
     int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const VT* __restrict__ val, const HT* __restrict__ h,
@@ -191,6 +196,7 @@ __global__ __launch_bounds__(NT) void csr_step_kernel(
     __shared__ double prod[G::span];
     __shared__ int rps[G::rows + 1];
     __shared__ double red[kNumPartials * NW];
+    __shared__ int64_t queue[2];
     const XT* __restrict__ x = static_cast<const XT*>(a.x_old);
     XT* __restrict__ xn = static_cast<XT*>(a.x_new);
     const double t_old = FIELD ? static_cast<double>(x[n]) : 0.0;
@@ -198,21 +204,43 @@ __global__ __launch_bounds__(NT) void csr_step_kernel(
 #pragma unroll
     for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
 
-    int64_t b, bend, bstep;
+    int64_t b, bend, bstep, nb;
     block_range(nblk, b, bend, bstep);
+    unsigned int* counter = nullptr;
+    int64_t start = 0;
+    if (DYN) {
+        const bool chunked = (gridDim.x & 7u) == 0 && nblk >= static_cast<int64_t>(gridDim.x);
+        const unsigned xcd = chunked ? (blockIdx.x & 7u) : 0u;
+        start = chunked ? nblk * xcd / 8 : 0;
+        counter = a.sched + xcd * kSchedStride;
+        if (threadIdx.x == 0) {
+            queue[0] = start + atomicAdd(counter, 1u);
+            queue[1] = start + atomicAdd(counter, 1u);
+        }
+        __syncthreads();
+        b = queue[0];
+        nb = queue[1];
+        __syncthreads();
+    } else {
+        nb = b + bstep;
+    }
     Stage<XT, VT, HT, CH, RPT> sa, sb;
     if (b < bend) issue_block<XT, VT, HT, FIELD, CH, RPT>(sa, b, binfo, rp, col, val, h, x);
-    // two stages alternate roles, so no register copy waits on a load
+    // two stages alternate roles, so no register copy waits on a load; with
+    // DYN each half publishes its claim through its own LDS slot, read after
+    // process_block's closing barrier
     while (b < bend) {
-        int64_t nb = b + bstep;
+        if (DYN && threadIdx.x == 0) queue[0] = nb < bend ? start + atomicAdd(counter, 1u) : bend;
         process_block<XT, VT, HT, FIELD, CH, RPT>(sa, sb, nb < bend, nb, binfo, rp, col, val, h, x,
                                                   xn, t_old, a, prod, rps, red, acc);
         b = nb;
+        nb = DYN ? queue[0] : b + bstep;
         if (b >= bend) break;
-        nb = b + bstep;
+        if (DYN && threadIdx.x == 0) queue[1] = nb < bend ? start + atomicAdd(counter, 1u) : bend;
         process_block<XT, VT, HT, FIELD, CH, RPT>(sb, sa, nb < bend, nb, binfo, rp, col, val, h, x,
                                                   xn, t_old, a, prod, rps, red, acc);
         b = nb;
+        nb = DYN ? queue[1] : b + bstep;
     }
     step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
 }
@@ -608,9 +636,9 @@ int grid_for_rows(int64_t n) {
 
 namespace {
 
-template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT>
+template <typename XT, typename VT, typename HT, bool FIELD, int CH, int RPT, bool DYN>
 hipError_t launch_step_t(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
-    auto kern = csr_step_kernel<XT, VT, HT, FIELD, CH, RPT>;
+    auto kern = csr_step_kernel<XT, VT, HT, FIELD, CH, RPT, DYN>;
     static int per_cu = 0;      // resident workgroups per CU for this instantiation
     static int cus = 0;
     if (per_cu == 0) {
@@ -667,11 +695,14 @@ hipError_t launch_rowlane_t(const CsrView& A, const CsrPlan& plan, const StepArg
 template <typename XT, typename VT, typename HT, bool FIELD>
 hipError_t launch_step_geo(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
     switch (plan.geometry) {
-        case 0: return launch_step_t<XT, VT, HT, FIELD, 1, 1>(A, plan, a, s);
-        case 1: return launch_step_t<XT, VT, HT, FIELD, 2, 2>(A, plan, a, s);
-        case 2: return launch_step_t<XT, VT, HT, FIELD, 4, 2>(A, plan, a, s);
+        case 0: return launch_step_t<XT, VT, HT, FIELD, 1, 1, false>(A, plan, a, s);
+        case 1: return launch_step_t<XT, VT, HT, FIELD, 2, 2, false>(A, plan, a, s);
+        case 2: return launch_step_t<XT, VT, HT, FIELD, 4, 2, false>(A, plan, a, s);
         case 3: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 1>(A, plan, a, s);
-        default: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 2>(A, plan, a, s);
+        case 4: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 2>(A, plan, a, s);
+        case 5: return launch_step_t<XT, VT, HT, FIELD, 1, 1, true>(A, plan, a, s);
+        case 6: return launch_step_t<XT, VT, HT, FIELD, 2, 2, true>(A, plan, a, s);
+        default: return launch_step_t<XT, VT, HT, FIELD, 4, 2, true>(A, plan, a, s);
     }
 }
 
@@ -685,9 +716,9 @@ hipError_t launch_step_field(const CsrView& A, const CsrPlan& plan, const StepAr
 
 void csr_geometry(int geometry, int* rows, int* span) {
     switch (geometry) {
-        case 0: *rows = Geometry<1, 1>::rows; *span = Geometry<1, 1>::span; break;
-        case 1: *rows = Geometry<2, 2>::rows; *span = Geometry<2, 2>::span; break;
-        case 2: *rows = Geometry<4, 2>::rows; *span = Geometry<4, 2>::span; break;
+        case 0: case 5: *rows = Geometry<1, 1>::rows; *span = Geometry<1, 1>::span; break;
+        case 1: case 6: *rows = Geometry<2, 2>::rows; *span = Geometry<2, 2>::span; break;
+        case 2: case 7: *rows = Geometry<4, 2>::rows; *span = Geometry<4, 2>::span; break;
         default: *rows = 0; *span = 0; break;      // lane-per-row kernels use no blocks
     }
 }

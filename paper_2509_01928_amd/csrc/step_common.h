@@ -93,6 +93,9 @@ __device__ void step_epilogue(const StepArgs& a, double (&acc)[kNumPartials],
         st->converged = 1;
         st->done = 1;
     }
+    // every workgroup has stopped claiming blocks: rearm the counters
+    if (a.sched)
+        for (int c = 0; c < 8; ++c) reset_ticket(a.sched + c * kSchedStride);
     reset_ticket(a.ticket);
 }
 
