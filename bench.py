@@ -38,6 +38,11 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=3,
                     help="oracle iterations timed for the CPU baseline (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--geometry", type=int, default=-2,
+                    help="step-kernel geometry (default: autotune)")
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
+                    help="record HBM traffic from rocprofv3 counter files and exit")
     return ap.parse_args()
 
 
@@ -62,12 +67,59 @@ def load_traffic(kernel: str, workload: str):
     return rec
 
 
+def ingest_pmc(paths, workload):
+    """Turn four rocprofv3 --pmc counter_collection.csv files (step kernel
+    FETCH_SIZE, step kernel WRITE_SIZE, copy kernel FETCH_SIZE, copy kernel
+    WRITE_SIZE; values in KiB per dispatch) into HBM bytes per launch of the
+    step kernel, scaled by what the counters read for a copy of known size,
+    and store them in profiles/traffic.json under the current source hash."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel(paths[0], "FETCH_SIZE")
+    write = per_kernel(paths[1], "WRITE_SIZE")
+    cf = per_kernel(paths[2], "FETCH_SIZE")
+    cw = per_kernel(paths[3], "WRITE_SIZE")
+    copy_name = next(k for k in cf if k.startswith("copy_kernel"))
+    copy_bytes = float(os.environ.get("COPY_BYTES", 1024 * 1024 * 1024))   # stream_bw 1024 MiB
+    fetch_scale = copy_bytes / (1024.0 * sum(cf[copy_name]) / len(cf[copy_name]))
+    write_scale = copy_bytes / (1024.0 * sum(cw[copy_name]) / len(cw[copy_name]))
+    # the timed kernel is the step-kernel variant dispatched most often
+    steps = [k for k in fetch if "csr_step_kernel" in k or "csr_rowlane_kernel" in k]
+    step = max(steps, key=lambda k: len(fetch[k]))
+    f_kib = sum(fetch[step]) / len(fetch[step])
+    w_kib = sum(write[step]) / len(write[step])
+    rec = {
+        "kernel": step, "source_hash": kernel_source_hash(),
+        "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "hbm_bytes_per_launch": 1024.0 * (f_kib * fetch_scale + w_kib * write_scale),
+    }
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data[f"csr_step_kernel/{workload}"] = rec
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
     args = parse()
+    if args.ingest_pmc:
+        ingest_pmc(args.ingest_pmc, f"torus{args.L}_{args.x_dtype}")
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
                                    "design note, not an implemented path", "n_gpus": args.gpus}))
@@ -99,11 +151,15 @@ def main():
     x_dtype = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
     log("context created")
     # launch-shape tuning is setup, outside the timed region
-    p0, _ = L.ising_default_params(ctx, 1.0, 0)
-    p0.x_dtype = x_dtype
-    geometry, wg_per_cu, tune_ms = L.ising_autotune(ctx, xd, 10, p0)
-    log(f"autotune: geometry {geometry}, {wg_per_cu} workgroups/CU "
-        f"({', '.join(f'{m * 1e3:.0f}' for m in tune_ms)} us/iteration per geometry)")
+    if args.geometry >= -1:
+        L.ising_set_geometry(ctx, args.geometry, args.wg_per_cu)
+        geometry, wg_per_cu = args.geometry, args.wg_per_cu
+    else:
+        p0, _ = L.ising_default_params(ctx, 1.0, 0)
+        p0.x_dtype = x_dtype
+        geometry, wg_per_cu, tune_ms = L.ising_autotune(ctx, xd, 10, p0)
+        log(f"autotune: geometry {geometry}, {wg_per_cu} workgroups/CU "
+            f"({', '.join(f'{m * 1e3:.0f}' for m in tune_ms)} us/iteration per geometry)")
 
     solve_ms = []
 

@@ -127,19 +127,18 @@ std::vector<int2> make_blocks(const std::vector<int32_t>& rp, int64_t n, int row
     return blk;
 }
 
-// Geometry from the mean row length: short rows favour 256-row blocks with
-// one 16-byte chunk per thread, longer rows wider spans.
+// Geometry from the mean row length: in-order scheduled row blocks of 512
+// rows, 2048-entry spans for short rows and 4096-entry spans for long ones
+// (the fastest on the lattice and random-graph workloads measured).
 int default_geometry(int64_t n, int64_t nnz) {
     const double d = static_cast<double>(nnz) / static_cast<double>(n);
-    if (d <= 4.0) return 0;
-    if (d <= 8.0) return 1;
-    return 2;
+    return d <= 8.0 ? 6 : 7;
 }
 
-// Two resident workgroups per CU stream the read-mostly mix of the step
-// kernel faster than a full device (measured on gfx950); the row-block
-// kernels need at least that many to hide their barriers.
-int default_wg_per_cu(int geometry) { return geometry <= 2 ? 0 : 2; }
+// Two resident workgroups per CU stream the read-mostly mix of the
+// lane-per-row kernels faster than a full device (measured on gfx950); the
+// row-block kernels need every workgroup that fits to hide their barriers.
+int default_wg_per_cu(int geometry) { return (geometry == 3 || geometry == 4) ? 2 : 0; }
 
 ising_status ensure_plan(ising_ctx* c, int geometry, doch::CsrPlan** out) {
     doch::CsrPlan& p = c->plans[geometry];
