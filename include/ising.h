@@ -186,6 +186,51 @@ ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first,
 ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
                           double* E_dev, int64_t* E_int_dev, void* stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent instances solved together (the benchmark setting of the
+ * paper's small and medium models: many instances and many random
+ * initialisations).  The instances are the diagonal blocks of one CSR
+ * matrix; instance k owns rows [r_k, r_k + n_k), r_k = n_0 + ... + n_{k-1},
+ * and every coupling of those rows must lie in the same block.  No field.
+ *
+ * ising_create_batch: count >= 1 instances with n_host[k] >= 2 rows each;
+ * row_ptr_dev / col_dev / val_dev / vt as for ising_create_csr over all
+ * sum(n) rows with global column indices.  ISING_E_INVALID_ARG also when a
+ * coupling leaves its block.  Synchronous.
+ *
+ * ising_default_params_batch: eq:alphabeta per instance (same rules as
+ * ising_default_params, applied to each instance); alpha_host, beta_host
+ * (and lambda_host when non-NULL) receive `count` values.  Synchronous.
+ *
+ * ising_solve_batch: DOCH on every instance with R restarts each (R in
+ * {1, 2, 4, 8, 16, 32}) in one persistent kernel launch, replayed from a
+ * captured HIP graph while the arguments repeat.  x0_dev is double[sum(n)*R]
+ * (restart-interleaved), alpha_host / beta_host give each instance's
+ * parameters, eps > 0 stops a restart at r^(k) < eps (its iterate is then
+ * frozen) and an instance when all its restarts stopped, max_iters caps the
+ * iterations; x_dtype stores the iterate in ISING_F64 or ISING_F32.
+ * x_out_dev (double[sum(n)*R]) and s_out_dev (int8[sum(n)*R]) are optional.
+ * stats_host (count*R entries, index k*R + r) and tts_ms_host (count
+ * entries: milliseconds from the launch until instance k finished, from the
+ * device clock) make the call synchronous.  No per-iteration log.
+ *
+ * ising_energy_batch: eq:IsingModel of each instance and restart,
+ * E_dev[k*R + r] in FP64 and E_int_dev[k*R + r] exactly (integer couplings
+ * only).  Asynchronous. */
+ising_status ising_create_batch(int32_t count, const int64_t* n_host, const int32_t* row_ptr_dev,
+                                const int32_t* col_dev, const void* val_dev, int32_t vt,
+                                void* stream, ising_ctx** out);
+ising_status ising_default_params_batch(ising_ctx* ctx, double eta, int32_t method,
+                                        void* stream, double* alpha_host, double* beta_host,
+                                        double* lambda_host);
+ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R,
+                               int64_t max_iters, const double* alpha_host,
+                               const double* beta_host, double eps, int32_t x_dtype,
+                               double* x_out_dev, int8_t* s_out_dev, ising_stats* stats_host,
+                               double* tts_ms_host, void* stream);
+ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
+                                int64_t* E_int_dev, void* stream);
+
 /* ----------------------------------------------------------------- tuning
  * The CSR step kernel has several row-block geometries (see
  * ising_set_geometry).  They give identical results -- every row is summed

@@ -17,7 +17,8 @@ __all__ = [
     "IsingError", "ising_params", "ising_stats", "ising_info", "lib", "LIB_PATH",
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
-    "ising_energy", "ising_set_geometry", "ising_autotune",
+    "ising_energy", "ising_set_geometry", "ising_autotune", "ising_create_batch",
+    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch",
     "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
 ]
@@ -94,6 +95,10 @@ _SIGS = {
     "ising_energy": (_st, [_p, _p, _i32, _p, _p, _p]),
     "ising_set_geometry": (_st, [_p, _i32, _i32]),
     "ising_autotune": (_st, [_p, _p, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
+    "ising_create_batch": (_st, [_i32, _p, _p, _p, _p, _i32, _p, ctypes.POINTER(_p)]),
+    "ising_default_params_batch": (_st, [_p, _d, _i32, _p, _p, _p, _p]),
+    "ising_solve_batch": (_st, [_p, _p, _i32, _i64, _p, _p, _d, _i32, _p, _p, _p, _p, _p]),
+    "ising_energy_batch": (_st, [_p, _p, _i32, _p, _p, _p]),
     "ising_status_string": (ctypes.c_char_p, [_st]),
     "ising_last_error": (ctypes.c_char_p, []),
     "ising_version": (ctypes.c_char_p, []),
@@ -225,3 +230,53 @@ def ising_autotune(ctx, x0, iters, params, stream=None):
                               ctypes.byref(g), ctypes.byref(w), ctypes.cast(ms, _p)),
            "ising_autotune")
     return g.value, w.value, list(ms)
+
+
+def ising_create_batch(n_list, row_ptr, col, val, vt, stream=None):
+    """Block-diagonal batch of len(n_list) instances; returns the context handle."""
+    import numpy as np
+    n_arr = np.ascontiguousarray(np.asarray(n_list, dtype=np.int64))
+    out = _p()
+    _check(lib.ising_create_batch(int(n_arr.shape[0]), n_arr.ctypes.data, ptr(row_ptr), ptr(col),
+                                  ptr(val), int(vt),
+                                  stream if stream is not None else current_stream(),
+                                  ctypes.byref(out)), "ising_create_batch")
+    return out.value
+
+
+def ising_default_params_batch(ctx, count, eta=1.0, method=0, stream=None):
+    """Returns numpy arrays (alpha, beta, lambda) of the batch's instances."""
+    import numpy as np
+    a = np.empty(int(count), dtype=np.float64)
+    b = np.empty(int(count), dtype=np.float64)
+    lam = np.empty(int(count), dtype=np.float64)
+    _check(lib.ising_default_params_batch(ctx, float(eta), int(method),
+                                          stream if stream is not None else current_stream(),
+                                          a.ctypes.data, b.ctypes.data, lam.ctypes.data),
+           "ising_default_params_batch")
+    return a, b, lam
+
+
+def ising_solve_batch(ctx, x0, R, max_iters, alpha, beta, eps=0.0, x_dtype=ISING_F64, x_out=None,
+                      s_out=None, want_stats=True, stream=None, check=True):
+    """Returns (stats list of count*R entries, numpy time-to-solution in ms) or ([], None)."""
+    import numpy as np
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    count = int(alpha.shape[0])
+    stats = (ising_stats * (count * int(R)))() if want_stats else None
+    tts = np.empty(count, dtype=np.float64) if want_stats else None
+    st = lib.ising_solve_batch(ctx, ptr(x0), int(R), int(max_iters), alpha.ctypes.data,
+                               beta.ctypes.data, float(eps), int(x_dtype), ptr(x_out), ptr(s_out),
+                               ctypes.cast(stats, _p) if stats is not None else None,
+                               tts.ctypes.data if tts is not None else None,
+                               stream if stream is not None else current_stream())
+    if check:
+        _check(st, "ising_solve_batch")
+    return (list(stats), tts) if want_stats else ([], None)
+
+
+def ising_energy_batch(ctx, s, R, E=None, E_int=None, stream=None):
+    _check(lib.ising_energy_batch(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
+                                  stream if stream is not None else current_stream()),
+           "ising_energy_batch")

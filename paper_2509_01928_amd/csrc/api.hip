@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,6 +19,9 @@ using doch::DenseView;
 using doch::MatrixStats;
 using doch::RestartState;
 using doch::StepArgs;
+using doch::BatchInstance;
+using doch::BatchRestartStat;
+using doch::BatchView;
 
 namespace {
 
@@ -174,6 +178,14 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->state);
     dev_free(c->log);
     dev_free(c->scratch);
+    dev_free(c->inst);
+    dev_free(c->order);
+    dev_free(c->bparams);
+    dev_free(c->bstats);
+    dev_free(c->bclock);
+    dev_free(c->bqueue);
+    if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
+    if (c->bgraph_src) (void)hipGraphDestroy(c->bgraph_src);
     delete c;
 }
 
@@ -643,6 +655,251 @@ ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,
     ctx->wg_per_cu = best_wpc;
     if (geometry_out) *geometry_out = best;
     if (wg_per_cu_out) *wg_per_cu_out = best_wpc;
+    return ISING_OK;
+}
+
+namespace {
+
+BatchView batch_view(const ising_ctx* c) {
+    BatchView b;
+    b.count = c->count;
+    b.rp = c->rp;
+    b.col = c->col;
+    b.val = c->val;
+    b.vt = c->vt;
+    b.inst = c->inst;
+    b.order = c->order;
+    return b;
+}
+
+}  // namespace
+
+ising_status ising_create_batch(int32_t count, const int64_t* n_host, const int32_t* row_ptr_dev,
+                                const int32_t* col_dev, const void* val_dev, int32_t vt,
+                                void* stream, ising_ctx** out) {
+    if (!out) return fail(ISING_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !n_host) return fail(ISING_E_INVALID_ARG, "count < 1 or n is NULL");
+    int64_t total = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        if (n_host[k] < 2) return fail(ISING_E_INVALID_ARG, "instance %d has n < 2", k);
+        total += n_host[k];
+    }
+    if (total >= 2147483647LL) return fail(ISING_E_INVALID_ARG, "total rows out of range");
+    if (!row_ptr_dev) return fail(ISING_E_INVALID_ARG, "row_ptr is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t nnz32 = 0;
+    HIP_OK(hipMemcpyAsync(&nnz32, row_ptr_dev + total, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read nnz");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    ising_ctx* c = nullptr;
+    ising_status st = ising_create_csr(total, nnz32, row_ptr_dev, col_dev, val_dev, vt, nullptr, ISING_F32,
+                                       stream, &c);
+    if (st != ISING_OK) return st;
+    auto bail = [&](ising_status e) { free_ctx(c); return e; };
+    c->batch = true;
+    c->count = count;
+    c->inst_host.resize(static_cast<size_t>(count));
+    int64_t row = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        BatchInstance& I = c->inst_host[k];
+        I.row0 = static_cast<int32_t>(row);
+        I.n = static_cast<int32_t>(n_host[k]);
+        I.e0 = c->rp_host[row];
+        I.nnz = c->rp_host[row + n_host[k]] - I.e0;
+        row += n_host[k];
+    }
+    // largest instances first
+    std::vector<int32_t> order(static_cast<size_t>(count));
+    for (int32_t k = 0; k < count; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const int64_t wa = static_cast<int64_t>(c->inst_host[a].nnz) + c->inst_host[a].n;
+        const int64_t wb = static_cast<int64_t>(c->inst_host[b].nnz) + c->inst_host[b].n;
+        return wa > wb;
+    });
+    hipError_t e;
+    if ((e = dev_alloc(&c->inst, count * sizeof(BatchInstance))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(inst)"));
+    if ((e = dev_alloc(&c->order, count * sizeof(int32_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(order)"));
+    if ((e = dev_alloc(&c->bparams, 2 * count * sizeof(double))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(params)"));
+    if ((e = dev_alloc(&c->bclock, (count + 1) * sizeof(uint64_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(clock)"));
+    if ((e = dev_alloc(&c->bqueue, 256)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(queue)"));
+    if ((e = hipMemcpy(c->inst, c->inst_host.data(), count * sizeof(BatchInstance), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "copy inst"));
+    if ((e = hipMemcpy(c->order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "copy order"));
+    Scratch sc;
+    if ((st = ensure_scratch(c, 0, &sc)) != ISING_OK) return bail(st);
+    if ((e = hipMemsetAsync(sc.flags, 0, sizeof(int32_t), s)) != hipSuccess) return bail(hip_fail(e, "memset"));
+    if ((e = doch::launch_batch_validate(batch_view(c), total, sc.flags, s)) != hipSuccess)
+        return bail(hip_fail(e, "validate blocks"));
+    int32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, sc.flags, sizeof(bad), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return bail(hip_fail(e, "copy flag"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sync"));
+    if (bad) return bail(fail(ISING_E_INVALID_ARG, "a coupling leaves its instance's diagonal block"));
+    *out = c;
+    return ISING_OK;
+}
+
+ising_status ising_default_params_batch(ising_ctx* ctx, double eta, int32_t method, void* stream,
+                                        double* alpha_host, double* beta_host, double* lambda_host) {
+    if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
+    if (!alpha_host || !beta_host) return fail(ISING_E_INVALID_ARG, "NULL output");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(ISING_E_INVALID_ARG, "eta must be > 0");
+    if (method < 0 || method > 2) return fail(ISING_E_INVALID_ARG, "method must be 0, 1 or 2");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int count = ctx->count;
+    // scratch: stats[4*count], shift[count], lam[count], jobs[count], v[np], w[np]
+    Scratch sc;
+    ising_status st = ensure_scratch(ctx, static_cast<size_t>(7) * count + 16, &sc);
+    if (st != ISING_OK) return st;
+    double* dstats = sc.partials;
+    double* dshift = dstats + 4 * count;
+    double* dlam = dshift + count;
+    int32_t* djobs = reinterpret_cast<int32_t*>(dlam + count);
+    HIP_OK(doch::launch_batch_stats(batch_view(ctx), dstats, s), "batch stats");
+    std::vector<double> hs(4 * static_cast<size_t>(count));
+    HIP_OK(hipMemcpyAsync(hs.data(), dstats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy stats");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    std::vector<double> lam(static_cast<size_t>(count));
+    std::vector<int32_t> jobs;
+    std::vector<double> shift(static_cast<size_t>(count));
+    for (int k = 0; k < count; ++k) {
+        const double n = ctx->inst_host[k].n;
+        const double m = n * (n - 1.0);
+        const double jbar = hs[4 * k + 1] / m;
+        const double ss = hs[4 * k + 3] + (m - hs[4 * k + 2]) * jbar * jbar;
+        lam[k] = 2.0 * std::sqrt(ss / m) * std::sqrt(n);
+        shift[k] = hs[4 * k + 0];
+        if (method == 1 || (method == 0 && ctx->inst_host[k].n < 10000)) jobs.push_back(k);
+    }
+    if (!jobs.empty()) {
+        HIP_OK(hipMemcpyAsync(dshift, shift.data(), count * sizeof(double), hipMemcpyHostToDevice, s), "copy shift");
+        HIP_OK(hipMemcpyAsync(djobs, jobs.data(), jobs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+               "copy jobs");
+        HIP_OK(doch::launch_batch_power(batch_view(ctx), djobs, static_cast<int>(jobs.size()), dshift, 1e-12,
+                                        100000, sc.vecs, sc.vecs + ctx->np, dlam, s), "batch power");
+        std::vector<double> pl(static_cast<size_t>(count));
+        HIP_OK(hipMemcpyAsync(pl.data(), dlam, count * sizeof(double), hipMemcpyDeviceToHost, s), "copy lambda");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+        for (int32_t k : jobs) lam[k] = pl[k];
+    }
+    for (int k = 0; k < count; ++k) {
+        const double n = ctx->inst_host[k].n;
+        alpha_host[k] = eta * lam[k];
+        beta_host[k] = std::pow(n, 1.5) * (alpha_host[k] + hs[4 * k + 0]);
+        if (lambda_host) lambda_host[k] = lam[k];
+    }
+    return ISING_OK;
+}
+
+ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t max_iters,
+                               const double* alpha_host, const double* beta_host, double eps,
+                               int32_t x_dtype, double* x_out_dev, int8_t* s_out_dev,
+                               ising_stats* stats_host, double* tts_ms_host, void* stream) {
+    if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
+    if (!x0_dev || !alpha_host || !beta_host) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (!doch::batch_restarts_supported(R)) return fail(ISING_E_INVALID_ARG, "R must be 1, 2, 4, 8, 16 or 32");
+    if (max_iters < 0) return fail(ISING_E_INVALID_ARG, "max_iters < 0");
+    if (!(eps >= 0.0)) return fail(ISING_E_INVALID_ARG, "eps must be >= 0");
+    if (x_dtype != ISING_F64 && x_dtype != ISING_F32) return fail(ISING_E_INVALID_ARG, "x_dtype must be F64 or F32");
+    const int count = ctx->count;
+    for (int k = 0; k < count; ++k)
+        if (!(alpha_host[k] > 0.0) || !(beta_host[k] > 0.0) || !std::isfinite(alpha_host[k]) ||
+            !std::isfinite(beta_host[k]))
+            return fail(ISING_E_INVALID_ARG, "instance %d: alpha and beta must be finite and > 0", k);
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t elt = x_dtype == ISING_F64 ? 8 : 4;
+    const size_t xbytes = static_cast<size_t>(ctx->np) * R * elt;
+    if (!ctx->xbuf[0] || ctx->xbuf_bytes < xbytes) {
+        dev_free(ctx->xbuf[0]);
+        dev_free(ctx->xbuf[1]);
+        ctx->xbuf_bytes = 0;
+        HIP_OK(dev_alloc(&ctx->xbuf[0], xbytes), "hipMalloc(x)");
+        HIP_OK(dev_alloc(&ctx->xbuf[1], xbytes), "hipMalloc(x)");
+        ctx->xbuf_bytes = xbytes;
+    }
+    HIP_OK(ensure(&ctx->bstats, &ctx->bstats_bytes, static_cast<size_t>(count) * R * sizeof(BatchRestartStat)),
+           "hipMalloc(stats)");
+    std::vector<double> ab(2 * static_cast<size_t>(count));
+    std::copy(alpha_host, alpha_host + count, ab.begin());
+    std::copy(beta_host, beta_host + count, ab.begin() + count);
+    HIP_OK(hipMemcpyAsync(ctx->bparams, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, s),
+           "copy alpha/beta");
+    // the whole solve is one persistent kernel (after a small init kernel),
+    // captured once into a graph and replayed while the arguments repeat
+    const std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(max_iters),
+                                       static_cast<uint64_t>(x_dtype), reinterpret_cast<uint64_t>(x0_dev),
+                                       reinterpret_cast<uint64_t>(x_out_dev), reinterpret_cast<uint64_t>(s_out_dev),
+                                       reinterpret_cast<uint64_t>(ctx->xbuf[0]), reinterpret_cast<uint64_t>(ctx->bstats),
+                                       reinterpret_cast<uint64_t>(s), static_cast<uint64_t>(std::hash<double>{}(eps))};
+    if (!ctx->bgraph || ctx->bgraph_key != key) {
+        if (ctx->bgraph) { (void)hipGraphExecDestroy(ctx->bgraph); ctx->bgraph = nullptr; }
+        if (ctx->bgraph_src) { (void)hipGraphDestroy(ctx->bgraph_src); ctx->bgraph_src = nullptr; }
+        hipStream_t cs;
+        HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            e = doch::launch_batch_solve(batch_view(ctx), R, max_iters, ctx->bparams, ctx->bparams + count, eps,
+                                         x_dtype, x0_dev, ctx->xbuf[0], ctx->xbuf[1], ctx->bqueue, ctx->bstats,
+                                         ctx->bclock, ctx->bclock + 1, x_out_dev, s_out_dev, cs);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ctx->bgraph, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) ctx->bgraph_src = g;
+            else if (g) (void)hipGraphDestroy(g);
+        }
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            ctx->bgraph = nullptr;
+            return hip_fail(e, "batch graph capture");
+        }
+        ctx->bgraph_key = key;
+    }
+    HIP_OK(hipGraphLaunch(ctx->bgraph, s), "batch graph launch");
+    if (stats_host || tts_ms_host) {
+        std::vector<BatchRestartStat> hs(static_cast<size_t>(count) * R);
+        std::vector<uint64_t> clk(static_cast<size_t>(count) + 1);
+        HIP_OK(hipMemcpyAsync(hs.data(), ctx->bstats, hs.size() * sizeof(BatchRestartStat), hipMemcpyDeviceToHost, s),
+               "copy stats");
+        HIP_OK(hipMemcpyAsync(clk.data(), ctx->bclock, clk.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
+               "copy clocks");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+        bool bad = false;
+        if (stats_host) {
+            for (size_t q = 0; q < hs.size(); ++q) {
+                stats_host[q].iters_done = hs[q].iters_done;
+                stats_host[q].converged = hs[q].converged;
+                stats_host[q].nonfinite = hs[q].nonfinite;
+                stats_host[q].H_last = hs[q].H_last;
+                stats_host[q].r_last = hs[q].r_last;
+                bad = bad || hs[q].nonfinite;
+            }
+        }
+        if (tts_ms_host) {
+            int rate_khz = 0;
+            HIP_OK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device), "clock rate");
+            const double ms_per_tick = rate_khz > 0 ? 1.0 / rate_khz : 1e-5;
+            for (int k = 0; k < count; ++k)
+                tts_ms_host[k] = static_cast<double>(clk[1 + k] - clk[0]) * ms_per_tick;
+        }
+        if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
+    }
+    return ISING_OK;
+}
+
+ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
+                                int64_t* E_int_dev, void* stream) {
+    if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
+    if (!s_dev) return fail(ISING_E_INVALID_ARG, "s is NULL");
+    if (!doch::batch_restarts_supported(R)) return fail(ISING_E_INVALID_ARG, "R must be 1, 2, 4, 8, 16 or 32");
+    if (!E_dev && !E_int_dev) return fail(ISING_E_INVALID_ARG, "no output requested");
+    if (E_int_dev && !ctx->integer_J) return fail(ISING_E_UNSUPPORTED, "integer energy needs integer couplings");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    HIP_OK(doch::launch_batch_energy(batch_view(ctx), s_dev, R, E_dev, E_int_dev, static_cast<hipStream_t>(stream)),
+           "batch energy");
     return ISING_OK;
 }
 

@@ -104,6 +104,36 @@ struct StepArgs {
     int all_done_flag;      // unused placeholder
 };
 
+// ---- batches of independent instances (kernels_batch.hip) ----
+constexpr int kBatchThreads = 512;
+
+// Instance k of a batch: rows [row0, row0 + n) of the block-diagonal CSR.
+struct BatchInstance {
+    int32_t row0;
+    int32_t n;
+    int32_t e0;
+    int32_t nnz;
+};
+
+// Result of one restart of one instance.
+struct BatchRestartStat {
+    int64_t iters_done;
+    int32_t converged;
+    int32_t nonfinite;
+    double H_last;
+    double r_last;
+};
+
+struct BatchView {
+    int count;
+    const int32_t* rp;
+    const int32_t* col;
+    const void* val;
+    int vt;
+    const BatchInstance* inst;
+    const int32_t* order;     // instances by decreasing size
+};
+
 }  // namespace doch
 
 struct ising_ctx {
@@ -145,6 +175,21 @@ struct ising_ctx {
     // setup scratch
     double* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // batch of instances (ising_create_batch)
+    bool batch = false;
+    int count = 0;
+    doch::BatchInstance* inst = nullptr;
+    int32_t* order = nullptr;
+    std::vector<doch::BatchInstance> inst_host;
+    double* bparams = nullptr;           // alpha[count], beta[count]
+    doch::BatchRestartStat* bstats = nullptr;
+    size_t bstats_bytes = 0;
+    uint64_t* bclock = nullptr;          // [0] = start, [1 + k] = end of instance k
+    unsigned int* bqueue = nullptr;
+    // cached graph of the batch solve
+    hipGraphExec_t bgraph = nullptr;
+    hipGraph_t bgraph_src = nullptr;
+    std::vector<uint64_t> bgraph_key;
 };
 
 namespace doch {
@@ -180,6 +225,21 @@ hipError_t launch_dense_power_step(const DenseView& A, double c, const double* v
                                    double* w, double* partials, unsigned int* ticket,
                                    int grid, double* mu_log, int64_t k, hipStream_t s);
 hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s);
+
+// ---- launchers (kernels_batch.hip) ----
+bool batch_restarts_supported(int R);
+hipError_t launch_batch_validate(const BatchView& B, int64_t n, int32_t* bad, hipStream_t s);
+hipError_t launch_batch_solve(const BatchView& B, int R, int64_t max_iters, const double* alpha,
+                              const double* beta, double eps, int x_dtype, const double* x0,
+                              void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
+                              uint64_t* clock_start, uint64_t* clock_end, double* x_out,
+                              int8_t* s_out, hipStream_t s);
+hipError_t launch_batch_energy(const BatchView& B, const int8_t* s_spins, int R, double* E,
+                               int64_t* E_int, hipStream_t s);
+hipError_t launch_batch_stats(const BatchView& B, double* out, hipStream_t s);
+hipError_t launch_batch_power(const BatchView& B, const int32_t* jobs, int njobs,
+                              const double* cshift, double tol, int64_t maxit, double* v, double* w,
+                              double* lam, hipStream_t s);
 
 // ---- launchers (kernels_common.hip) ----
 hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,

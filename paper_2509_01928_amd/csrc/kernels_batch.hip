@@ -1,0 +1,499 @@
+// kernels_batch.hip -- many independent instances x many restarts in one
+// persistent launch.
+//
+// The instances are the diagonal blocks of one CSR matrix.  A workgroup pulls
+// a whole instance from a work queue (instances ordered by decreasing size,
+// so the long ones start first and the short ones fill the gaps) and runs
+// the complete DOCH loop (eq:FPE / Alg. 1) on it for all R restarts at once:
+// thread (slot, r) owns restart r of rows slot, slot + S, ... (S = threads /
+// R), so the R iterate entries a coupling multiplies are contiguous
+// (restart-interleaved storage) and J x for the R restarts is one pass over
+// the instance's couplings -- a sparse matrix times an n x R block.  Every
+// synchronisation is a workgroup barrier: instances never wait for each
+// other.  Each restart stops on its own when r^(k) < eps (Remark S2): its
+// iterate is frozen (copied forward) while the others go on; the instance
+// ends when all its restarts have stopped or after max_iters iterations,
+// and stamps the device clock for its time to solution.
+#include <algorithm>
+
+#include "device_common.h"
+#include "ising_internal.h"
+
+namespace doch {
+
+namespace {
+
+constexpr int BT = kBatchThreads;
+constexpr int BW = BT / kWave;
+
+__device__ __forceinline__ uint64_t device_clock() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Sum v over the threads of the workgroup that share tid % R (R divides 64);
+// thread r < R receives the total for restart r.  Fixed order.
+template <int R, int K>
+__device__ __forceinline__ void restart_sum(double (&v)[K], double* lds /* K*BW*R */) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+#pragma unroll
+        for (int off = kWave / 2; off >= R; off >>= 1) v[q] = dadd(v[q], __shfl_xor(v[q], off, kWave));
+    }
+    if (lane < R) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) lds[(q * BW + wave) * R + lane] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < BW; ++w) s = dadd(s, lds[(q * BW + w) * R + threadIdx.x]);
+            v[q] = s;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename XT, typename VT, int R>
+__global__ __launch_bounds__(BT) void batch_solve_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const VT* __restrict__ val,
+    const BatchInstance* __restrict__ inst, const int32_t* __restrict__ order, int count,
+    const double* __restrict__ alpha, const double* __restrict__ beta, double eps,
+    int64_t max_iters, const double* __restrict__ x0, XT* __restrict__ xa, XT* __restrict__ xb,
+    unsigned int* queue, BatchRestartStat* __restrict__ stats, uint64_t* __restrict__ clock_start,
+    uint64_t* __restrict__ clock_end, double* __restrict__ x_out, int8_t* __restrict__ s_out) {
+    constexpr int S = BT / R;                 // row slots
+    __shared__ double red[4 * BW * R];
+    __shared__ int conv[R];
+    __shared__ int s_job;
+    __shared__ int s_all;
+    const int r = threadIdx.x % R;
+    const int slot = threadIdx.x / R;
+    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned long long*>(clock_start),
+                                    static_cast<unsigned long long>(device_clock()));
+    for (;;) {
+        if (threadIdx.x == 0) s_job = static_cast<int>(atomicAdd(queue, 1u));
+        if (threadIdx.x < R) conv[threadIdx.x] = 0;
+        __syncthreads();
+        const int job = s_job;
+        if (job >= count) break;
+        const int k = order[job];
+        const BatchInstance I = inst[k];
+        const double a = alpha[k], b = beta[k];
+        const int64_t base = static_cast<int64_t>(I.row0) * R;
+        // start vectors into buffer a
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(I.n) * R; t += BT)
+            xa[base + t] = static_cast<XT>(x0[base + t]);
+        __syncthreads();
+        const XT* xo = xa;
+        XT* xw = xb;
+        int64_t it = 0;
+        int nonfinite = 0;
+        for (; it < max_iters; ++it) {
+            const bool frozen = conv[r] != 0;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};   // x^4, x^2, x z, (dx)^2
+            for (int i = I.row0 + slot; i < I.row0 + I.n; i += S) {
+                const int s = rp[i], e = rp[i + 1];
+                double z = 0.0;
+                int q = s;
+                for (; q + 4 <= e; q += 4) {
+                    const int c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
+                    const double v0 = static_cast<double>(val[q]), v1 = static_cast<double>(val[q + 1]);
+                    const double v2 = static_cast<double>(val[q + 2]), v3 = static_cast<double>(val[q + 3]);
+                    const double g0 = static_cast<double>(xo[static_cast<int64_t>(c0) * R + r]);
+                    const double g1 = static_cast<double>(xo[static_cast<int64_t>(c1) * R + r]);
+                    const double g2 = static_cast<double>(xo[static_cast<int64_t>(c2) * R + r]);
+                    const double g3 = static_cast<double>(xo[static_cast<int64_t>(c3) * R + r]);
+                    z = dadd(z, dmul(v0, g0));
+                    z = dadd(z, dmul(v1, g1));
+                    z = dadd(z, dmul(v2, g2));
+                    z = dadd(z, dmul(v3, g3));
+                }
+                for (; q < e; ++q)
+                    z = dadd(z, dmul(static_cast<double>(val[q]),
+                                     static_cast<double>(xo[static_cast<int64_t>(col[q]) * R + r])));
+                const int64_t ix = static_cast<int64_t>(i) * R + r;
+                const double xi = static_cast<double>(xo[ix]);
+                if (frozen) {
+                    xw[ix] = xo[ix];
+                } else {
+                    const double xn = cbrt(ddiv(dadd(z, dmul(a, xi)), b));
+                    const XT xs = static_cast<XT>(xn);
+                    xw[ix] = xs;
+                    const double d = dsub(static_cast<double>(xs), xi);
+                    const double x2 = dmul(xi, xi);
+                    acc[0] = dadd(acc[0], dmul(x2, x2));
+                    acc[1] = dadd(acc[1], x2);
+                    acc[2] = dadd(acc[2], dmul(xi, z));
+                    acc[3] = dadd(acc[3], dmul(d, d));
+                }
+            }
+            restart_sum<R, 4>(acc, red);
+            if (threadIdx.x < R && !conv[threadIdx.x]) {
+                const double H = dsub(dsub(dmul(ddiv(b, 4.0), acc[0]), dmul(ddiv(a, 2.0), acc[1])),
+                                      dmul(0.5, acc[2]));
+                const double rr = acc[1] == 0.0 ? 0.0 : ddiv(sqrt(acc[3]), sqrt(acc[1]));
+                BatchRestartStat& st = stats[static_cast<int64_t>(k) * R + threadIdx.x];
+                st.iters_done = it + 1;
+                st.H_last = H;
+                st.r_last = rr;
+                if (!isfinite(H) || !isfinite(rr)) {
+                    st.nonfinite = 1;
+                    conv[threadIdx.x] = 1;
+                } else if (eps > 0.0 && rr < eps) {
+                    st.converged = 1;
+                    conv[threadIdx.x] = 1;
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int all = 1;
+                for (int q = 0; q < R; ++q) all &= conv[q];
+                s_all = all;
+            }
+            const XT* t = xo;
+            xo = xw;
+            xw = const_cast<XT*>(t);
+            __syncthreads();
+            if (s_all) {
+                ++it;
+                break;
+            }
+        }
+        (void)nonfinite;
+        // outputs from the buffer that holds x^(it)
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(I.n) * R; t += BT) {
+            const double v = static_cast<double>(xo[base + t]);
+            if (x_out) x_out[base + t] = v;
+            if (s_out) s_out[base + t] = v >= 0.0 ? 1 : -1;
+        }
+        if (threadIdx.x == 0) clock_end[k] = device_clock();
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ void batch_init_kernel(BatchRestartStat* stats, int count, unsigned int* queue,
+                                  uint64_t* clock_start) {
+    const int64_t total = static_cast<int64_t>(count) * R;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        stats[t].iters_done = 0;
+        stats[t].converged = 0;
+        stats[t].nonfinite = 0;
+        stats[t].H_last = 0.0;
+        stats[t].r_last = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *queue = 0u;
+        *clock_start = ~0ull;
+    }
+}
+
+// eq:IsingModel per instance and restart (workgroup per instance).
+template <typename VT, int R>
+__global__ __launch_bounds__(BT) void batch_energy_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const VT* __restrict__ val,
+    const BatchInstance* __restrict__ inst, int count, const int8_t* __restrict__ s,
+    int want_int, double* __restrict__ E, int64_t* __restrict__ E_int) {
+    constexpr int S = BT / R;
+    __shared__ double red[BW * R];
+    const int r = threadIdx.x % R;
+    const int slot = threadIdx.x / R;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const BatchInstance I = inst[k];
+        double eJ = 0.0;
+        int64_t eI = 0;
+        for (int i = I.row0 + slot; i < I.row0 + I.n; i += S) {
+            double acc = 0.0;
+            int64_t iacc = 0;
+            for (int q = rp[i]; q < rp[i + 1]; ++q) {
+                const double sj = static_cast<double>(s[static_cast<int64_t>(col[q]) * R + r]);
+                const double v = static_cast<double>(val[q]);
+                acc = dadd(acc, dmul(v, sj));
+                if (want_int) iacc += static_cast<int64_t>(v) * static_cast<int64_t>(sj);
+            }
+            const double si = static_cast<double>(s[static_cast<int64_t>(i) * R + r]);
+            eJ = dadd(eJ, dmul(si, acc));
+            eI += static_cast<int64_t>(si) * iacc;
+        }
+        // the int64 sum travels exactly as two doubles (high and low 32 bits)
+        double v[1] = {eJ};
+        restart_sum<R, 1>(v, red);
+        double hi[1] = {static_cast<double>(eI >> 32)};
+        double lo[1] = {static_cast<double>(eI & 0xffffffffLL)};
+        restart_sum<R, 1>(hi, red);
+        restart_sum<R, 1>(lo, red);
+        if (threadIdx.x < R) {
+            const int64_t tot = static_cast<int64_t>(hi[0]) * 4294967296LL + static_cast<int64_t>(lo[0]);
+            if (E) E[static_cast<int64_t>(k) * R + threadIdx.x] = dmul(-0.5, v[0]);
+            if (E_int) E_int[static_cast<int64_t>(k) * R + threadIdx.x] = -(tot / 2);
+        }
+        __syncthreads();
+    }
+}
+
+// Per-instance matrix statistics for eq:alphabeta (workgroup per instance):
+// out[k] = {max_i sum_j |J_ij|, sum J_ij, #stored, sum (J_ij - mean)^2}.
+template <typename VT>
+__global__ __launch_bounds__(BT) void batch_stats_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const VT* __restrict__ val,
+    const BatchInstance* __restrict__ inst, int count, double* __restrict__ out) {
+    __shared__ double red[3 * BW];
+    __shared__ double redm[BW];
+    __shared__ double s_mean;
+    for (int k = blockIdx.x; k < count; k += gridDim.x) {
+        const BatchInstance I = inst[k];
+        double v[3] = {0.0, 0.0, 0.0};
+        double pmax = 0.0;
+        for (int i = I.row0 + threadIdx.x; i < I.row0 + I.n; i += BT) {
+            double rs = 0.0;
+            for (int q = rp[i]; q < rp[i + 1]; ++q) {
+                if (col[q] == i) continue;
+                const double x = static_cast<double>(val[q]);
+                rs = dadd(rs, fabs(x));
+                v[0] = dadd(v[0], x);
+                v[1] += 1.0;
+            }
+            pmax = fmax(pmax, rs);
+        }
+        double v2[2] = {v[0], v[1]};
+        block_sum<2, BT>(v2, red);
+        v[0] = v2[0];
+        v[1] = v2[1];
+        const double wm = wave_max(pmax);
+        if ((threadIdx.x & (kWave - 1)) == 0) redm[threadIdx.x / kWave] = wm;
+        __syncthreads();
+        const double nn = static_cast<double>(I.n);
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            for (int w = 0; w < BW; ++w) m = fmax(m, redm[w]);
+            out[4 * k + 0] = m;
+            out[4 * k + 1] = v[0];
+            out[4 * k + 2] = v[1];
+            s_mean = nn > 1.0 ? v[0] / (nn * (nn - 1.0)) : 0.0;
+        }
+        __syncthreads();
+        const double mean = s_mean;
+        double ss[1] = {0.0};
+        for (int i = I.row0 + threadIdx.x; i < I.row0 + I.n; i += BT)
+            for (int q = rp[i]; q < rp[i + 1]; ++q) {
+                if (col[q] == i) continue;
+                const double d = dsub(static_cast<double>(val[q]), mean);
+                ss[0] = dadd(ss[0], dmul(d, d));
+            }
+        block_sum<1, BT>(ss, red);
+        if (threadIdx.x == 0) out[4 * k + 3] = ss[0];
+        __syncthreads();
+    }
+}
+
+// lambda_max(-J) of each selected instance by power iteration on cI - J
+// (workgroup per instance, no host round trips).  v and w are scratch of the
+// batch's total row count; lam[k] receives mu - c.
+template <typename VT>
+__global__ __launch_bounds__(BT) void batch_power_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const VT* __restrict__ val,
+    const BatchInstance* __restrict__ inst, const int32_t* __restrict__ jobs, int njobs,
+    const double* __restrict__ cshift, double tol, int64_t maxit, double* __restrict__ v,
+    double* __restrict__ w, double* __restrict__ lam) {
+    __shared__ double red[2 * BW];
+    __shared__ double s_bcast[2];
+    for (int jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+        const int k = jobs[jb];
+        const BatchInstance I = inst[k];
+        const double c = cshift[k];
+        // start vector: a fixed SplitMix64 sequence, normalised
+        double nrm[1] = {0.0};
+        for (int i = threadIdx.x; i < I.n; i += BT) {
+            uint64_t q = 0x9E3779B97F4A7C15ULL * static_cast<uint64_t>(i + 1);
+            q = (q ^ (q >> 30)) * 0xBF58476D1CE4E5B9ULL;
+            q = (q ^ (q >> 27)) * 0x94D049BB133111EBULL;
+            q ^= q >> 31;
+            const double u = 2.0 * (static_cast<double>(q >> 11) * 0x1.0p-53) - 1.0;
+            v[I.row0 + i] = u;
+            nrm[0] = dadd(nrm[0], dmul(u, u));
+        }
+        block_sum<1, BT>(nrm, red);
+        if (threadIdx.x == 0) s_bcast[0] = sqrt(nrm[0]);
+        __syncthreads();
+        const double n0 = s_bcast[0];
+        for (int i = threadIdx.x; i < I.n; i += BT) v[I.row0 + i] = ddiv(v[I.row0 + i], n0);
+        __syncthreads();
+        double mu = 0.0, mu_prev = 0.0;
+        for (int64_t it = 0; it < maxit; ++it) {
+            double acc[2] = {0.0, 0.0};
+            for (int i = I.row0 + threadIdx.x; i < I.row0 + I.n; i += BT) {
+                double z = 0.0;
+                for (int q = rp[i]; q < rp[i + 1]; ++q)
+                    z = dadd(z, dmul(static_cast<double>(val[q]), v[col[q]]));
+                const double wi = dsub(dmul(c, v[i]), z);
+                w[i] = wi;
+                acc[0] = dadd(acc[0], dmul(v[i], wi));
+                acc[1] = dadd(acc[1], dmul(wi, wi));
+            }
+            block_sum<2, BT>(acc, red);
+            if (threadIdx.x == 0) {
+                s_bcast[0] = acc[0];
+                s_bcast[1] = sqrt(acc[1]);
+            }
+            __syncthreads();
+            mu = s_bcast[0];
+            const double wn = s_bcast[1];
+            if (wn == 0.0) break;
+            for (int i = I.row0 + threadIdx.x; i < I.row0 + I.n; i += BT) v[i] = ddiv(w[i], wn);
+            __syncthreads();
+            if (it > 0 && fabs(mu - mu_prev) <= tol * fabs(mu)) break;
+            mu_prev = mu;
+        }
+        if (threadIdx.x == 0) lam[k] = mu - c;
+        __syncthreads();
+    }
+}
+
+// Every coupling of a row must stay inside its instance's diagonal block.
+__global__ __launch_bounds__(256) void batch_validate_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const BatchInstance* __restrict__ inst, int count, int64_t n, int32_t* bad) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {                      // last instance with row0 <= i
+            const int mid = (lo + hi + 1) >> 1;
+            if (inst[mid].row0 <= i) lo = mid; else hi = mid - 1;
+        }
+        const int a = inst[lo].row0, b = inst[lo].row0 + inst[lo].n;
+        for (int q = rp[i]; q < rp[i + 1]; ++q)
+            if (col[q] < a || col[q] >= b) atomicOr(bad, 1);
+    }
+}
+
+template <typename T>
+int resident_grid(T kern, int threads) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, 0) != hipSuccess || occ < 1) occ = 1;
+    return cus * occ;
+}
+
+}  // namespace
+
+#define DOCH_BATCH_R(R, ...)                                  \
+    switch (R) {                                              \
+        case 1: { constexpr int RR = 1; __VA_ARGS__; } break;  \
+        case 2: { constexpr int RR = 2; __VA_ARGS__; } break;  \
+        case 4: { constexpr int RR = 4; __VA_ARGS__; } break;  \
+        case 8: { constexpr int RR = 8; __VA_ARGS__; } break;  \
+        case 16: { constexpr int RR = 16; __VA_ARGS__; } break; \
+        case 32: { constexpr int RR = 32; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;                 \
+    }
+
+bool batch_restarts_supported(int R) {
+    return R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32;
+}
+
+hipError_t launch_batch_solve(const BatchView& B, int R, int64_t max_iters, const double* alpha,
+                              const double* beta, double eps, int x_dtype, const double* x0,
+                              void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
+                              uint64_t* clock_start, uint64_t* clock_end, double* x_out,
+                              int8_t* s_out, hipStream_t s) {
+    DOCH_BATCH_R(R, {
+        const int ig = static_cast<int>(std::min<int64_t>(1024, (static_cast<int64_t>(B.count) * RR + 255) / 256));
+        hipLaunchKernelGGL(batch_init_kernel<RR>, dim3(ig), dim3(256), 0, s, stats, B.count, queue,
+                           clock_start);
+        if (B.vt == ISING_F64) {
+            if (x_dtype == ISING_F64) {
+                auto kern = batch_solve_kernel<double, double, RR>;
+                const int grid = std::min(resident_grid(kern, BT), B.count);
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                                   static_cast<const double*>(B.val), B.inst, B.order, B.count, alpha,
+                                   beta, eps, max_iters, x0, static_cast<double*>(xa),
+                                   static_cast<double*>(xb), queue, stats, clock_start, clock_end,
+                                   x_out, s_out);
+            } else {
+                auto kern = batch_solve_kernel<float, double, RR>;
+                const int grid = std::min(resident_grid(kern, BT), B.count);
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                                   static_cast<const double*>(B.val), B.inst, B.order, B.count, alpha,
+                                   beta, eps, max_iters, x0, static_cast<float*>(xa),
+                                   static_cast<float*>(xb), queue, stats, clock_start, clock_end,
+                                   x_out, s_out);
+            }
+        } else {
+            if (x_dtype == ISING_F64) {
+                auto kern = batch_solve_kernel<double, float, RR>;
+                const int grid = std::min(resident_grid(kern, BT), B.count);
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                                   static_cast<const float*>(B.val), B.inst, B.order, B.count, alpha,
+                                   beta, eps, max_iters, x0, static_cast<double*>(xa),
+                                   static_cast<double*>(xb), queue, stats, clock_start, clock_end,
+                                   x_out, s_out);
+            } else {
+                auto kern = batch_solve_kernel<float, float, RR>;
+                const int grid = std::min(resident_grid(kern, BT), B.count);
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                                   static_cast<const float*>(B.val), B.inst, B.order, B.count, alpha,
+                                   beta, eps, max_iters, x0, static_cast<float*>(xa),
+                                   static_cast<float*>(xb), queue, stats, clock_start, clock_end,
+                                   x_out, s_out);
+            }
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_validate(const BatchView& B, int64_t n, int32_t* bad, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(batch_validate_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, B.rp,
+                       B.col, B.inst, B.count, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_energy(const BatchView& B, const int8_t* s_spins, int R, double* E,
+                               int64_t* E_int, hipStream_t s) {
+    const int grid = std::min(B.count, 2048);
+    DOCH_BATCH_R(R, {
+        if (B.vt == ISING_F64)
+            hipLaunchKernelGGL((batch_energy_kernel<double, RR>), dim3(grid), dim3(BT), 0, s, B.rp,
+                               B.col, static_cast<const double*>(B.val), B.inst, B.count, s_spins,
+                               E_int != nullptr, E, E_int);
+        else
+            hipLaunchKernelGGL((batch_energy_kernel<float, RR>), dim3(grid), dim3(BT), 0, s, B.rp,
+                               B.col, static_cast<const float*>(B.val), B.inst, B.count, s_spins,
+                               E_int != nullptr, E, E_int);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stats(const BatchView& B, double* out, hipStream_t s) {
+    const int grid = std::min(B.count, 2048);
+    if (B.vt == ISING_F64)
+        hipLaunchKernelGGL(batch_stats_kernel<double>, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                           static_cast<const double*>(B.val), B.inst, B.count, out);
+    else
+        hipLaunchKernelGGL(batch_stats_kernel<float>, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                           static_cast<const float*>(B.val), B.inst, B.count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_power(const BatchView& B, const int32_t* jobs, int njobs,
+                              const double* cshift, double tol, int64_t maxit, double* v, double* w,
+                              double* lam, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    const int grid = std::min(njobs, 2048);
+    if (B.vt == ISING_F64)
+        hipLaunchKernelGGL(batch_power_kernel<double>, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                           static_cast<const double*>(B.val), B.inst, jobs, njobs, cshift, tol,
+                           maxit, v, w, lam);
+    else
+        hipLaunchKernelGGL(batch_power_kernel<float>, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
+                           static_cast<const float*>(B.val), B.inst, jobs, njobs, cshift, tol,
+                           maxit, v, w, lam);
+    return hipGetLastError();
+}
+
+}  // namespace doch
