@@ -30,6 +30,10 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="torus",
+                    choices=["torus", "er20000", "sk1024", "dense4096", "batch512"],
+                    help="torus = the 10^8-spin lattice (default line); the others print "
+                         "their own JSON line")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, default=10000, help="lattice side (n = L*L spins)")
@@ -41,6 +45,9 @@ def parse():
     ap.add_argument("--geometry", type=int, default=-2,
                     help="step-kernel geometry (default: autotune)")
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--plain-restarts", type=int, default=16,
+                    help="dense4096: FP64 restarts run one at a time for the comparison")
+    ap.add_argument("--oracle-restarts", type=int, default=1)
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
     return ap.parse_args()
@@ -115,6 +122,277 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# ------------------------------------------------------------------ secondary workloads
+def _timed(fn, warmup, steps):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1)
+
+
+def bench_er20000(args):
+    """Sparse ER n = 20000, mean degree 6, +-1, FP64 iterate, 5000 iterations."""
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import paper_2509_01928_amd as L
+    seed, xseed = gen.SEEDS["er20000"]
+    A = gen.er_csr(20000, 6.0, seed)
+    x0 = gen.uniform_x0(A.n, 1, xseed)[:, 0]
+    d = "cuda:0"
+    keep = [torch.from_numpy(a).to(d) for a in (A.row_ptr, A.col, A.val)]
+    ctx = L.ising_create_csr(A.n, A.nnz, *keep, L.ISING_F32)
+    xd = torch.from_numpy(x0).to(d)
+    so = torch.empty(A.n, dtype=torch.int8, device=d)
+    E = torch.empty(1, dtype=torch.int64, device=d)
+    p, lam = L.ising_default_params(ctx, 1.0, 0)
+    g, w, ms = L.ising_autotune(ctx, xd, 200, p)
+    iters = 5000
+
+    def step():
+        q, _ = L.ising_default_params(ctx, 1.0, 0)
+        L.ising_solve(ctx, xd, 1, iters, q, None, so, want_stats=False)
+        L.ising_energy(ctx, so, 1, None, E)
+
+    dt = _timed(step, args.warmup, args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    it_us = 1e3 * e0.elapsed_time(e1) / iters
+    bytes_iter = 4 * (A.n + 1) + 8 * A.nnz + 16 * A.n
+    print(json.dumps({
+        "metric": "edge-updates/s", "value": A.nnz * iters / dt, "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "Erdos-Renyi n=20000 mean degree 6, +-1, "
+                                        "5000 DOCH iterations (FP64 iterate)",
+                                        "n": A.n, "nnz": A.nnz, "iters": iters,
+                                        "kernel_geometry": g, "workgroups_per_cu": w},
+        "iteration_us": it_us, "energy_int64": int(E.cpu()[0]),
+        "roofline": {"bound": "latency", "achieved": bytes_iter / (it_us * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_iter / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": bytes_iter},
+    }), flush=True)
+    L.ising_destroy(ctx)
+
+
+def bench_sk1024(args):
+    """Dense SK n = 1024, FP64, 1000 iterations."""
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import paper_2509_01928_amd as L
+    seed, xseed = gen.SEEDS["sk1024"]
+    n = 1024
+    J = gen.sk_dense(n, seed)
+    x0 = gen.uniform_x0(n, 1, xseed)[:, 0]
+    d = "cuda:0"
+    Jd = torch.from_numpy(J).to(d)
+    ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
+    xd = torch.from_numpy(x0).to(d)
+    so = torch.empty(n, dtype=torch.int8, device=d)
+    E = torch.empty(1, dtype=torch.float64, device=d)
+    p, lam = L.ising_default_params(ctx, 1.0, 0)
+    iters = 1000
+
+    def step():
+        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+        L.ising_energy(ctx, so, 1, E)
+
+    dt = _timed(step, args.warmup, args.steps)
+    it_us = 1e6 * dt / iters
+    print(json.dumps({
+        "metric": "edge-updates/s", "value": n * (n - 1) * iters / dt, "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "dense SK n=1024, J~N(0,1), 1000 DOCH "
+                                        "iterations, FP64", "n": n, "iters": iters},
+        "iteration_us": it_us, "energy": float(E.cpu()[0]), "lambda_hat": lam,
+        "roofline": {"bound": "latency", "achieved": 8 * n * n / (it_us * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": 8 * n * n / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": 8 * n * n},
+    }), flush=True)
+    L.ising_destroy(ctx)
+
+
+def bench_dense4096(args):
+    """Dense n = 4096, 256 restarts: BF16 and FP8 matrix-core iterations vs
+    the plain FP64 path run one restart at a time, compared at equal energy."""
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import oracle as orc
+    import paper_2509_01928_amd as L
+    seed, xseed = gen.SEEDS["sk4096"]
+    n, R, iters = 4096, 256, 1000
+    J = gen.sk_dense(n, seed)
+    d = "cuda:0"
+    Jd = torch.from_numpy(J).to(d)
+    ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
+    p, lam = L.ising_default_params(ctx, 1.0, 0)
+    log(f"lambda = {lam:.4f}, alpha = {p.alpha:.4f}, beta = {p.beta:.4e}")
+    out = {"metric": "restarts/s at equal best energy", "unit": "restarts/s", "n_gpus": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic", "config": {"workload": "dense SK n=4096, J~N(0,1), 256 restarts "
+                                           "x0~U(-1,1), 1000 DOCH iterations", "n": n, "R": R,
+                                           "iters": iters}}
+    # plain FP64 path: restarts one at a time
+    nplain = args.plain_restarts
+    X0 = gen.uniform_x0(n, R, xseed)
+    so = torch.empty(n, dtype=torch.int8, device=d)
+    E = torch.empty(1, dtype=torch.float64, device=d)
+    Eplain = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(nplain):
+        xd = torch.from_numpy(np.ascontiguousarray(X0[:, r])).to(d)
+        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+        L.ising_energy(ctx, so, 1, E)
+        Eplain.append(float(E.cpu()[0]))
+    t_plain = (time.perf_counter() - t0) / nplain
+    best64 = min(Eplain)
+    out["fp64_plain"] = {"restarts_per_s": 1.0 / t_plain, "best_energy": best64,
+                         "restarts": nplain, "ms_per_restart": 1e3 * t_plain}
+    log(f"FP64 plain: {1e3 * t_plain:.1f} ms/restart, best E {best64:.1f}")
+    # one oracle restart for the energy gap (FP64 CPU)
+    tr = orc.doch_dense(J, X0[:, 0], p.alpha, p.beta, iters) if args.oracle_restarts > 0 else None
+    E_or = orc.energy_dense(J, orc.sign(tr.x)) if tr is not None else None
+    for name, prec, peak in (("bf16", L.ISING_BF16, 2500.0), ("fp8", L.ISING_FP8_E4M3, 5000.0)):
+        xd = torch.from_numpy(np.ascontiguousarray(X0)).to(d)
+        so = torch.empty((n, R), dtype=torch.int8, device=d)
+        Hf = torch.empty(R, dtype=torch.float64, device=d)
+        Eb = torch.empty(R, dtype=torch.float64, device=d)
+        L.ising_solve_lowp(ctx, xd, R, 20, p, prec, None, so, Hf)      # warm-up
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.ising_solve_lowp(ctx, xd, R, iters, p, prec, None, so, Hf, want_stats=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        L.ising_energy(ctx, so, R, Eb)
+        Eh = Eb.cpu().numpy()
+        # equal-energy protocol: batches of R starts until the best energy
+        # reaches the FP64 best (at most 16 batches)
+        best = float(Eh.min())
+        batches = 1
+        t_total = ms * 1e-3
+        while best > best64 and batches < 16:
+            Xb = gen.uniform_x0(n, R, xseed * 1000 + batches)
+            xb = torch.from_numpy(Xb).to(d)
+            e0.record()
+            L.ising_solve_lowp(ctx, xb, R, iters, p, prec, None, so, Hf, want_stats=False)
+            e1.record()
+            torch.cuda.synchronize()
+            t_total += 1e-3 * e0.elapsed_time(e1)
+            L.ising_energy(ctx, so, R, Eb)
+            best = min(best, float(Eb.cpu().numpy().min()))
+            batches += 1
+        flops = 2.0 * n * n * R * iters
+        res = {"restarts_per_s": R * batches / t_total, "ms_per_batch_of_256": ms,
+               "iteration_us": 1e3 * ms / iters, "best_energy": best,
+               "reached_fp64_best": bool(best <= best64), "batches": batches,
+               "energy_gap_same_starts_mean": float(np.mean((Eh[:nplain] - np.array(Eplain)) / np.abs(Eplain))),
+               "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak,
+                            "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / peak}}
+        if E_or is not None:
+            res["energy_gap_vs_fp64_oracle_restart0"] = (float(Eh[0]) - E_or) / abs(E_or)
+        out[name] = res
+        log(f"{name}: {1e3 * ms / iters:.1f} us/iteration, {res['roofline']['achieved']:.1f} TFLOP/s, "
+            f"best {best:.1f} after {batches} batch(es)")
+    out["value"] = out["bf16"]["restarts_per_s"]
+    out["dtype"] = "bf16"
+    out["vs_fp64_plain"] = out["bf16"]["restarts_per_s"] / out["fp64_plain"]["restarts_per_s"]
+    print(json.dumps(out), flush=True)
+    L.ising_destroy(ctx)
+
+
+def bench_batch512(args):
+    """512 Erdos-Renyi instances, n ~ U{800..20000}, degree ~ U[3,20], 8
+    restarts each, eps = 1e-3, at most 5000 iterations, one launch."""
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import paper_2509_01928_amd as L
+    seed, xseed = gen.SEEDS["batch512"]
+    R = 8
+    t0 = time.time()
+    inst = gen.uneven_batch(count=512, seed=seed)
+    rps, cols, vals = [np.zeros(1, np.int64)], [], []
+    row0 = nnz0 = 0
+    for A in inst:
+        rps.append(A.row_ptr[1:].astype(np.int64) + nnz0)
+        cols.append(A.col.astype(np.int64) + row0)
+        vals.append(A.val)
+        row0 += A.n
+        nnz0 += A.nnz
+    rp = np.concatenate(rps).astype(np.int32)
+    col = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate(vals).astype(np.float32)
+    total = row0
+    X0 = np.concatenate([gen.uniform_x0(A.n, R, xseed * (1 << 20) + k) for k, A in enumerate(inst)])
+    log(f"generated 512 instances: {total} spins, {nnz0} couplings in {time.time() - t0:.1f}s")
+    d = "cuda:0"
+    keep = [torch.from_numpy(a).to(d) for a in (rp, col, val)]
+    ctx = L.ising_create_batch([A.n for A in inst], *keep, L.ISING_F32)
+    alpha, beta, lam = L.ising_default_params_batch(ctx, len(inst), 1.0, 0)
+    xd = torch.from_numpy(X0).to(d)
+    so = torch.empty(X0.shape, dtype=torch.int8, device=d)
+    Ei = torch.empty(len(inst) * R, dtype=torch.int64, device=d)
+    xdt = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
+
+    def step():
+        L.ising_solve_batch(ctx, xd, R, 5000, alpha, beta, 1e-3, xdt, None, so, want_stats=False)
+        L.ising_energy_batch(ctx, so, R, None, Ei)
+
+    dt = _timed(step, args.warmup, args.steps)
+    st, tts = L.ising_solve_batch(ctx, xd, R, 5000, alpha, beta, 1e-3, xdt, None, so)
+    iters = np.array([s.iters_done for s in st]).reshape(len(inst), R)
+    nnz = np.array([A.nnz for A in inst])
+    ns = np.array([A.n for A in inst])
+    edge_updates = float((iters * nnz[:, None]).sum())
+    xb = 4 if args.x_dtype == "f32" else 8
+    # per instance: the couplings are streamed once per iteration for all its
+    # restarts (until the slowest stops); each live restart reads and writes
+    # its iterate column
+    bytes_moved = float(((4 * (ns + 1) + 8 * nnz) * iters.max(axis=1)).sum()
+                        + (2 * xb * ns[:, None] * iters).sum())
+    print(json.dumps({
+        "metric": "edge-updates/s", "value": edge_updates / dt, "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "512 Erdos-Renyi instances n~U{800..20000}, "
+                                        "degree~U[3,20], +-1, 8 restarts, eps=1e-3, <=5000 "
+                                        "iterations, one persistent graph-captured launch",
+                                        "spins": int(total), "couplings": int(nnz0), "restarts": R,
+                                        "x_storage": args.x_dtype},
+        "tts_ms_p50": float(np.percentile(tts, 50)), "tts_ms_p99": float(np.percentile(tts, 99)),
+        "tts_ms_max": float(tts.max()),
+        "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
+        "converged_fraction": float(np.mean([s.converged for s in st])),
+        "energy_int64_sum": int(Ei.cpu().numpy().sum()),
+        "roofline": {"bound": "hbm", "achieved": bytes_moved / dt / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes": bytes_moved},
+    }), flush=True)
+    L.ising_destroy(ctx)
+
+
 def main():
     args = parse()
     if args.ingest_pmc:
@@ -124,6 +402,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
                                    "design note, not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload != "torus":
+        {"er20000": bench_er20000, "sk1024": bench_sk1024, "dense4096": bench_dense4096,
+         "batch512": bench_batch512}[args.workload](args)
+        return
     import numpy as np
     import torch
 

@@ -167,6 +167,15 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R,
                          double* x_out_dev, int8_t* s_out_dev,
                          ising_stats* stats_host, void* stream);
 
+/* ADOCH (params->algo = 1, Alg. 2 with the window of eq:BBscheme) runs on
+ * single CSR contexts with R = 1 and FP64 iterates (ISING_E_UNSUPPORTED
+ * otherwise); params->q >= 1 is the look-back window.  It still costs one
+ * matvec per iteration: J y is formed from J x^(k) and J x^(k-1).
+ * ising_get_accept_log copies, for the last ADOCH solve, whether iteration
+ * first + i took the extrapolated point (1) or x^(k) (0).  Synchronous. */
+ising_status ising_get_accept_log(ising_ctx* ctx, int64_t first, int64_t count,
+                                  int8_t* accept_host, void* stream);
+
 /* Copy the per-iteration log of the last solve of restart `restart`:
  * H_host[k] = H(x^(first+k)), r_host[k] = r^(first+k) for k < count.
  * Either output may be NULL.  Synchronous on `stream`.  Entries past the
@@ -185,6 +194,30 @@ ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first,
  * Asynchronous on `stream`. */
 ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
                           double* E_dev, int64_t* E_int_dev, void* stream);
+
+/* ------------------------------------------------- dense low precision
+ * DOCH on a dense context for R restarts at once with J x computed on the
+ * matrix cores: J is held in BF16 (jx_dtype = ISING_BF16) or in FP8 e4m3 with
+ * one FP32 scale per row (ISING_FP8_E4M3), the restarts in FP32 plus a copy
+ * in the same low precision, products accumulate in FP32.  The iteration
+ * runs on u = sqrt(beta) x, where eq:FPE reads u <- cbrt(J u + alpha u)
+ * exactly, so u stays representable in either format; the update itself is
+ * FP64.  H and r of each iteration (ising_get_log) are FP64 sums of the
+ * low-precision products.  This solves a quantised problem: compare its
+ * energies, not its iterates, with the FP64 path.
+ *   x0_dev       double[n * R] (restart-interleaved, as ising_solve)
+ *   params       alpha, beta, eps (per-restart freezing at r < eps); the
+ *                iterate's storage fields are ignored
+ *   x_out_dev    NULL or double[n * R]: final iterates x = u / sqrt(beta)
+ *   s_out_dev    NULL or int8[n * R]: their signs (sign(0) = +1)
+ *   H_final_dev  NULL or double[R]: H of the final iterates evaluated in FP64
+ *                with the FP64 J (eq:Hamilton)
+ *   stats_host   NULL or ising_stats[R]; makes the call synchronous.
+ * Dense contexts without a field, n <= 65536, 1 <= R <= 1024. */
+ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t iters,
+                              const ising_params* params, int32_t jx_dtype, double* x_out_dev,
+                              int8_t* s_out_dev, double* H_final_dev, ising_stats* stats_host,
+                              void* stream);
 
 /* ---------------------------------------------------------------- batches
  * Many independent instances solved together (the benchmark setting of the

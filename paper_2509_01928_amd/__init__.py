@@ -18,7 +18,7 @@ __all__ = [
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
     "ising_energy", "ising_set_geometry", "ising_autotune", "ising_create_batch",
-    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch",
+    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_solve_lowp", "ising_get_accept_log",
     "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
 ]
@@ -99,6 +99,8 @@ _SIGS = {
     "ising_default_params_batch": (_st, [_p, _d, _i32, _p, _p, _p, _p]),
     "ising_solve_batch": (_st, [_p, _p, _i32, _i64, _p, _p, _d, _i32, _p, _p, _p, _p, _p]),
     "ising_energy_batch": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "ising_solve_lowp": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _i32, _p, _p, _p, _p, _p]),
+    "ising_get_accept_log": (_st, [_p, _i64, _i64, _p, _p]),
     "ising_status_string": (ctypes.c_char_p, [_st]),
     "ising_last_error": (ctypes.c_char_p, []),
     "ising_version": (ctypes.c_char_p, []),
@@ -280,3 +282,26 @@ def ising_energy_batch(ctx, s, R, E=None, E_int=None, stream=None):
     _check(lib.ising_energy_batch(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
                                   stream if stream is not None else current_stream()),
            "ising_energy_batch")
+
+
+def ising_solve_lowp(ctx, x0, R, iters, params, jx_dtype, x_out=None, s_out=None, H_final=None,
+                     want_stats=True, stream=None, check=True):
+    """Dense restarts on the matrix cores in BF16 / FP8; returns the stats list."""
+    stats = (ising_stats * int(R))() if want_stats else None
+    st = lib.ising_solve_lowp(ctx, ptr(x0), int(R), int(iters), ctypes.byref(params), int(jx_dtype),
+                              ptr(x_out), ptr(s_out), ptr(H_final),
+                              ctypes.cast(stats, _p) if stats is not None else None,
+                              stream if stream is not None else current_stream())
+    if check:
+        _check(st, "ising_solve_lowp")
+    return list(stats) if stats is not None else []
+
+
+def ising_get_accept_log(ctx, first, count, stream=None):
+    """ADOCH decisions of the last solve (numpy int8: 1 = extrapolated point taken)."""
+    import numpy as np
+    out = np.empty(int(count), dtype=np.int8)
+    _check(lib.ising_get_accept_log(ctx, int(first), int(count), out.ctypes.data,
+                                    stream if stream is not None else current_stream()),
+           "ising_get_accept_log")
+    return out

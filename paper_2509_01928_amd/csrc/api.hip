@@ -184,6 +184,19 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->bstats);
     dev_free(c->bclock);
     dev_free(c->bqueue);
+    dev_free(c->jq[0]);
+    dev_free(c->jq[1]);
+    dev_free(c->rscale);
+    dev_free(c->lp_u[0]);
+    dev_free(c->lp_u[1]);
+    dev_free(c->lp_ub[0]);
+    dev_free(c->lp_ub[1]);
+    dev_free(c->lp_partials);
+    for (auto& b : c->ad_x) dev_free(b);
+    for (auto& b : c->ad_z) dev_free(b);
+    dev_free(c->ad_ring);
+    dev_free(c->ad_accept);
+    dev_free(c->ad_acclog);
     if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
     if (c->bgraph_src) (void)hipGraphDestroy(c->bgraph_src);
     delete c;
@@ -241,9 +254,104 @@ ising_status ensure_scratch(ising_ctx* c, size_t partial_doubles, Scratch* out) 
 
 }  // namespace
 
+// ADOCH (Alg. 2) on a CSR context, one restart, FP64 iterates.
+static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t iters, const ising_params& p,
+                         double* x_out_dev, int8_t* s_out_dev, ising_stats* stats_host, hipStream_t s) {
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t bytes = static_cast<size_t>(ctx->np) * sizeof(double);
+    if (!ctx->ad_x[0] || ctx->ad_bytes < bytes) {
+        for (auto& b : ctx->ad_x) dev_free(b);
+        for (auto& b : ctx->ad_z) dev_free(b);
+        ctx->ad_bytes = 0;
+        for (auto& b : ctx->ad_x) HIP_OK(dev_alloc(&b, bytes), "hipMalloc(x)");
+        for (auto& b : ctx->ad_z) HIP_OK(dev_alloc(&b, bytes), "hipMalloc(z)");
+        ctx->ad_bytes = bytes;
+    }
+    if (!ctx->ad_ring || ctx->ad_ring_cap < p.q + 1) {
+        dev_free(ctx->ad_ring);
+        HIP_OK(dev_alloc(&ctx->ad_ring, (p.q + 1) * sizeof(double)), "hipMalloc(ring)");
+        ctx->ad_ring_cap = p.q + 1;
+    }
+    if (!ctx->ad_accept) HIP_OK(dev_alloc(&ctx->ad_accept, 256), "hipMalloc(accept)");
+    HIP_OK(ensure(&ctx->ad_acclog, &ctx->ad_acclog_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1))),
+           "hipMalloc(accept log)");
+    const int grid = doch::adoch_grid(ctx->np);
+    HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes, static_cast<size_t>(grid) * 7 * sizeof(double)),
+           "hipMalloc(partials)");
+    if (!ctx->ticket) {
+        HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
+        HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
+        ctx->state_cap = kMaxR;
+    }
+    HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * 2 * sizeof(double)),
+           "hipMalloc(log)");
+    HIP_OK(doch::launch_init_state(ctx->state, 1, ctx->ticket, nullptr, s), "init");
+    HIP_OK(hipMemcpyAsync(ctx->ad_x[0], x0_dev, bytes, hipMemcpyDeviceToDevice, s), "load x0");
+    // z^(-1) enters with weight c_0 = 0; it must be finite
+    HIP_OK(hipMemsetAsync(ctx->ad_z[1], 0, bytes, s), "clear z");
+    doch::AdochArgs a;
+    a.alpha = p.alpha;
+    a.beta = p.beta;
+    a.eps = p.eps;
+    a.q = p.q;
+    a.partials = ctx->partials;
+    a.ticket = ctx->ticket;
+    a.log = ctx->log;
+    a.accept = ctx->ad_accept;
+    a.accept_log = ctx->ad_acclog;
+    a.ring = ctx->ad_ring;
+    a.state = ctx->state;
+    const CsrView cv = csr_view(ctx);
+    double t = 1.0;                                   // t_0 (Alg. 2 line 1)
+    for (int64_t k = 0; k < iters; ++k) {
+        const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;   // Alg. 2 line 3
+        a.c = (t - 1.0) / t_next;                                           // 0 at k = 0: y = x
+        a.k = k;
+        const double* x = ctx->ad_x[k % 3];
+        const double* xp = k == 0 ? ctx->ad_x[0] : ctx->ad_x[(k + 2) % 3];
+        double* xn = ctx->ad_x[(k + 1) % 3];
+        double* z = ctx->ad_z[k % 2];
+        const double* zp = ctx->ad_z[(k + 1) % 2];
+        HIP_OK(doch::launch_adoch_mv(cv, x, xp, zp, z, a, s), "ADOCH matvec");
+        HIP_OK(doch::launch_adoch_update(ctx->np, x, xp, z, zp, xn, a, s), "ADOCH update");
+        t = t_next;
+    }
+    ctx->last_R = 1;
+    ctx->last_iters = iters;
+    ctx->last_adoch = true;
+    if (x_out_dev || s_out_dev)
+        HIP_OK(doch::launch_adoch_finish(ctx->ad_x[0], ctx->ad_x[1], ctx->ad_x[2], ctx->state, ctx->n, ctx->np,
+                                         ctx->has_field, x_out_dev, s_out_dev, s), "finish");
+    if (stats_host) {
+        RestartState hs;
+        HIP_OK(hipMemcpyAsync(&hs, ctx->state, sizeof(hs), hipMemcpyDeviceToHost, s), "copy state");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+        stats_host[0].iters_done = hs.iters_done;
+        stats_host[0].converged = hs.converged;
+        stats_host[0].nonfinite = hs.nonfinite;
+        stats_host[0].H_last = hs.H_last;
+        stats_host[0].r_last = hs.r_last;
+        if (hs.nonfinite) return fail(ISING_E_NONFINITE, "H or r became non-finite");
+    }
+    return ISING_OK;
+}
+
 extern "C" {
 
 const char* ising_version(void) { return "0.1.0"; }
+
+ising_status ising_get_accept_log(ising_ctx* ctx, int64_t first, int64_t count, int8_t* accept_host,
+                                  void* stream) {
+    if (!ctx || !accept_host) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (!ctx->last_adoch) return fail(ISING_E_INVALID_ARG, "the last solve was not ADOCH");
+    if (first < 0 || count < 0 || first + count > ctx->last_iters) return fail(ISING_E_INVALID_ARG, "bad range");
+    if (count == 0) return ISING_OK;
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_OK(hipMemcpyAsync(accept_host, ctx->ad_acclog + first, count, hipMemcpyDeviceToHost, s), "copy");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    return ISING_OK;
+}
 
 const char* ising_last_error(void) { return g_last_error.c_str(); }
 
@@ -514,8 +622,16 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     if (p.x_dtype != ISING_F64 && p.x_dtype != ISING_F32) return fail(ISING_E_INVALID_ARG, "x_dtype must be F64 or F32");
     if (p.reserved != 0) return fail(ISING_E_INVALID_ARG, "reserved must be 0");
     if (p.algo != 0 && p.algo != 1) return fail(ISING_E_INVALID_ARG, "algo must be 0 or 1");
-    if (p.algo == 1) return fail(ISING_E_UNSUPPORTED, "ADOCH is not available in this build");
-    if (R != 1) return fail(ISING_E_UNSUPPORTED, "R > 1 is not available in this build");
+    if (p.algo == 1) {
+        if (ctx->dense || ctx->batch) return fail(ISING_E_UNSUPPORTED, "ADOCH runs on single CSR contexts");
+        if (R != 1) return fail(ISING_E_UNSUPPORTED, "ADOCH runs one restart at a time");
+        if (p.x_dtype != ISING_F64) return fail(ISING_E_UNSUPPORTED, "ADOCH stores its iterates in FP64");
+        if (p.q < 1) return fail(ISING_E_INVALID_ARG, "ADOCH needs q >= 1");
+        return solve_adoch(ctx, x0_dev, iters, p, x_out_dev, s_out_dev, stats_host,
+                           static_cast<hipStream_t>(stream));
+    }
+    if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "use ising_solve_batch on a batch context");
+    if (R != 1) return fail(ISING_E_UNSUPPORTED, "R > 1: use ising_solve_batch or ising_solve_lowp");
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t elt = p.x_dtype == ISING_F64 ? 8 : 4;
@@ -575,6 +691,7 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     }
     ctx->last_R = R;
     ctx->last_iters = iters;
+    ctx->last_adoch = false;
     if (x_out_dev || s_out_dev)
         HIP_OK(doch::launch_finish(ctx->xbuf[0], ctx->xbuf[1], p.x_dtype, ctx->state, ctx->n, ctx->np, R,
                                    ctx->has_field, x_out_dev, s_out_dev, s), "finish");
@@ -900,6 +1017,115 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_OK(doch::launch_batch_energy(batch_view(ctx), s_dev, R, E_dev, E_int_dev, static_cast<hipStream_t>(stream)),
            "batch energy");
+    return ISING_OK;
+}
+
+ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t iters,
+                              const ising_params* params, int32_t jx_dtype, double* x_out_dev,
+                              int8_t* s_out_dev, double* H_final_dev, ising_stats* stats_host,
+                              void* stream) {
+    if (!ctx || !params || !x0_dev) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (!ctx->dense) return fail(ISING_E_UNSUPPORTED, "the low-precision path needs a dense context");
+    if (ctx->has_field) return fail(ISING_E_UNSUPPORTED, "the low-precision path takes no field");
+    if (jx_dtype != ISING_BF16 && jx_dtype != ISING_FP8_E4M3)
+        return fail(ISING_E_INVALID_ARG, "jx_dtype must be ISING_BF16 or ISING_FP8_E4M3");
+    if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
+    if (iters < 0) return fail(ISING_E_INVALID_ARG, "iters < 0");
+    const ising_params& p = *params;
+    if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return fail(ISING_E_INVALID_ARG, "alpha must be finite and > 0");
+    if (!(p.beta > 0.0) || !std::isfinite(p.beta)) return fail(ISING_E_INVALID_ARG, "beta must be finite and > 0");
+    if (!(p.eps >= 0.0)) return fail(ISING_E_INVALID_ARG, "eps must be >= 0");
+    if (ctx->n > 65536) return fail(ISING_E_UNSUPPORTED, "the low-precision path is limited to n <= 65536");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int prec = jx_dtype == ISING_BF16 ? 0 : 1;
+    const int n = static_cast<int>(ctx->n);
+    const int np = (n + 127) / 128 * 128;
+    const int Rp = (R + 63) / 64 * 64;
+    const size_t esz = prec == 0 ? 2 : 1;
+    if (!ctx->jq[prec]) {
+        HIP_OK(dev_alloc(&ctx->jq[prec], static_cast<size_t>(np) * np * esz), "hipMalloc(Jq)");
+        if (prec == 1) HIP_OK(dev_alloc(&ctx->rscale, static_cast<size_t>(np) * sizeof(float)), "hipMalloc(scale)");
+        HIP_OK(doch::launch_lowp_convert(prec, ctx->J, n, np, ctx->jq[prec], ctx->rscale, s), "convert J");
+        ctx->lp_np = np;
+    }
+    const size_t ubytes = static_cast<size_t>(np) * Rp * sizeof(float);
+    const size_t ubbytes = static_cast<size_t>(np) * Rp * esz;
+    if (!ctx->lp_u[0] || ctx->lp_ubytes < ubytes) {
+        dev_free(ctx->lp_u[0]);
+        dev_free(ctx->lp_u[1]);
+        ctx->lp_ubytes = 0;
+        HIP_OK(dev_alloc(&ctx->lp_u[0], ubytes), "hipMalloc(U)");
+        HIP_OK(dev_alloc(&ctx->lp_u[1], ubytes), "hipMalloc(U)");
+        ctx->lp_ubytes = ubytes;
+    }
+    if (!ctx->lp_ub[0] || ctx->lp_ubbytes < ubbytes) {
+        dev_free(ctx->lp_ub[0]);
+        dev_free(ctx->lp_ub[1]);
+        ctx->lp_ubbytes = 0;
+        HIP_OK(dev_alloc(&ctx->lp_ub[0], ubbytes), "hipMalloc(Ub)");
+        HIP_OK(dev_alloc(&ctx->lp_ub[1], ubbytes), "hipMalloc(Ub)");
+        ctx->lp_ubbytes = ubbytes;
+    }
+    HIP_OK(ensure(&ctx->lp_partials, &ctx->lp_pbytes, static_cast<size_t>(np / 64) * Rp * 4 * sizeof(double)),
+           "hipMalloc(partials)");
+    if (!ctx->ticket) {
+        HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
+        HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
+        ctx->state_cap = kMaxR;
+    }
+    HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)),
+           "hipMalloc(log)");
+    HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, nullptr, s), "init");
+    const double sb = std::sqrt(p.beta);
+    HIP_OK(doch::launch_lowp_load(prec, x0_dev, n, R, np, Rp, sb, ctx->lp_u[0], ctx->lp_ub[0], s), "load");
+    for (int64_t k = 0; k < iters; ++k) {
+        const int a = static_cast<int>(k & 1), b = 1 - a;
+        HIP_OK(doch::launch_lowp_step(prec, np, Rp, ctx->jq[prec], ctx->rscale, ctx->lp_u[a], ctx->lp_u[b],
+                                      ctx->lp_ub[a], ctx->lp_ub[b], p.alpha, p.beta, p.eps, R, k,
+                                      ctx->lp_partials, ctx->ticket, ctx->log, ctx->state, s),
+               "low-precision step");
+    }
+    ctx->last_R = R;
+    ctx->last_iters = iters;
+    const float* Ufin = ctx->lp_u[iters & 1];
+    double* xtmp = nullptr;
+    if (x_out_dev || s_out_dev || H_final_dev) {
+        double* xo = x_out_dev;
+        if (!xo && H_final_dev) {
+            HIP_OK(dev_alloc(&xtmp, static_cast<size_t>(n) * R * sizeof(double)), "hipMalloc(x)");
+            xo = xtmp;
+        }
+        hipError_t e = doch::launch_lowp_finish(Ufin, n, R, Rp, sb, xo, s_out_dev, s);
+        if (e == hipSuccess && H_final_dev) {
+            const int grid = std::min(1024, (n + 3) / 4);
+            Scratch sc;
+            ising_status st = ensure_scratch(ctx, static_cast<size_t>(grid) * R * 3, &sc);
+            if (st != ISING_OK) { dev_free(xtmp); return st; }
+            e = doch::launch_dense_objective(ctx->J, n, R, xo, p.alpha, p.beta, sc.partials, sc.tickets, grid,
+                                             H_final_dev, s);
+        }
+        if (e != hipSuccess) { dev_free(xtmp); return hip_fail(e, "finish"); }
+    }
+    if (xtmp) {
+        (void)hipStreamSynchronize(s);
+        dev_free(xtmp);
+    }
+    if (stats_host) {
+        std::vector<RestartState> hs(static_cast<size_t>(R));
+        HIP_OK(hipMemcpyAsync(hs.data(), ctx->state, R * sizeof(RestartState), hipMemcpyDeviceToHost, s), "copy state");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+        bool bad = false;
+        for (int r = 0; r < R; ++r) {
+            stats_host[r].iters_done = hs[r].iters_done;
+            stats_host[r].converged = hs[r].converged;
+            stats_host[r].nonfinite = hs[r].nonfinite;
+            stats_host[r].H_last = hs[r].H_last;
+            stats_host[r].r_last = hs[r].r_last;
+            bad = bad || hs[r].nonfinite;
+        }
+        if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
+    }
     return ISING_OK;
 }
 

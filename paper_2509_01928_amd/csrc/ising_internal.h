@@ -134,6 +134,21 @@ struct BatchView {
     const int32_t* order;     // instances by decreasing size
 };
 
+// Arguments of the two ADOCH launches of iteration k.
+struct AdochArgs {
+    double alpha, beta, eps;
+    double c;                 // (t_k - 1) / t_{k+1}
+    int64_t k;
+    int q;                    // look-back window
+    double* partials;
+    unsigned int* ticket;
+    double* log;              // [iters][2]: (H(x^(k)), r^(k))
+    int* accept;              // decision of iteration k
+    int8_t* accept_log;       // [iters]
+    double* ring;             // last q+1 values of H(x)
+    RestartState* state;
+};
+
 }  // namespace doch
 
 struct ising_ctx {
@@ -186,6 +201,25 @@ struct ising_ctx {
     size_t bstats_bytes = 0;
     uint64_t* bclock = nullptr;          // [0] = start, [1 + k] = end of instance k
     unsigned int* bqueue = nullptr;
+    // dense low-precision path (ising_solve_lowp)
+    void* jq[2] = {nullptr, nullptr};    // BF16 / FP8 copies of J, padded
+    float* rscale = nullptr;             // FP8 per-row scales
+    int lp_np = 0;                       // padded order (multiple of 128)
+    float* lp_u[2] = {nullptr, nullptr};
+    void* lp_ub[2] = {nullptr, nullptr};
+    size_t lp_ubytes = 0, lp_ubbytes = 0;
+    double* lp_partials = nullptr;
+    size_t lp_pbytes = 0;
+    // ADOCH buffers (three iterates, two products, window, decisions)
+    double* ad_x[3] = {nullptr, nullptr, nullptr};
+    double* ad_z[2] = {nullptr, nullptr};
+    size_t ad_bytes = 0;
+    double* ad_ring = nullptr;
+    int ad_ring_cap = 0;
+    int* ad_accept = nullptr;
+    int8_t* ad_acclog = nullptr;
+    size_t ad_acclog_bytes = 0;
+    bool last_adoch = false;
     // cached graph of the batch solve
     hipGraphExec_t bgraph = nullptr;
     hipGraph_t bgraph_src = nullptr;
@@ -240,6 +274,32 @@ hipError_t launch_batch_stats(const BatchView& B, double* out, hipStream_t s);
 hipError_t launch_batch_power(const BatchView& B, const int32_t* jobs, int njobs,
                               const double* cshift, double tol, int64_t maxit, double* v, double* w,
                               double* lam, hipStream_t s);
+
+// ---- launchers (kernels_mfma.hip) ----
+hipError_t launch_lowp_convert(int prec, const double* J, int n, int np, void* Jq, float* rscale,
+                               hipStream_t s);
+hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, int Rp, double sqrt_beta,
+                            float* U, void* Ub, hipStream_t s);
+hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const float* rscale,
+                            const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
+                            double alpha, double beta, double eps, int R, int64_t k,
+                            double* partials, unsigned int* ticket, double* log, RestartState* state,
+                            hipStream_t s);
+hipError_t launch_lowp_finish(const float* U, int n, int R, int Rp, double sqrt_beta, double* x_out,
+                              int8_t* s_out, hipStream_t s);
+hipError_t launch_dense_objective(const double* J, int n, int R, const double* X, double alpha,
+                                  double beta, double* partials, unsigned int* tickets, int grid,
+                                  double* H, hipStream_t s);
+
+// ---- launchers (kernels_adoch.hip) ----
+int adoch_grid(int64_t n);
+hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, const double* zp,
+                           double* z, const AdochArgs& a, hipStream_t s);
+hipError_t launch_adoch_update(int64_t np, const double* x, const double* xp, const double* z,
+                               const double* zp, double* xn, const AdochArgs& a, hipStream_t s);
+hipError_t launch_adoch_finish(const double* b0, const double* b1, const double* b2,
+                               const RestartState* st, int64_t n, int64_t np, bool field,
+                               double* x_out, int8_t* s_out, hipStream_t s);
 
 // ---- launchers (kernels_common.hip) ----
 hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,

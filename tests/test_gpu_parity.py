@@ -352,3 +352,68 @@ def test_autotune_keeps_results():
     finally:
         P.close()
     assert_iterate_parity(x[:, 0], tr.x, "after autotune")
+
+
+# ------------------------------------------------------------------ ADOCH
+@pytest.mark.parametrize("case", ["er", "torus_field"])
+def test_adoch_parity(case):
+    """Alg. 2: same decisions, iterates, H and r as the oracle's ADOCH, whose
+    J y is its own matvec (here it comes from J x^(k) and J x^(k-1))."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    if case == "er":
+        A = gen.er_csr(3000, 8.0, 131)
+        x0 = gen.uniform_x0(3000, 1, 132)[:, 0]
+    else:
+        A = gen.torus_csr(60, 133, h_std=0.1)
+        x0 = gen.uniform_x0(3601, 1, 134)[:, 0]
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B, 1.0)
+    iters, q = 250, 5
+    tr = orc.adoch(B, x0, alpha, beta, iters, q)
+    P = GpuProblem(A=A)
+    try:
+        p = P.params(alpha, beta)
+        p.algo, p.q = 1, q
+        xd = torch.from_numpy(x0).to("cuda:0")
+        xo = torch.empty_like(xd)
+        so = torch.empty(A.n, dtype=torch.int8, device="cuda:0")
+        st = Lb.ising_solve(P.ctx, xd, 1, iters, p, xo, so)
+        H, r = Lb.ising_get_log(P.ctx, 0, 0, iters)
+        acc = Lb.ising_get_accept_log(P.ctx, 0, iters)
+        torch.cuda.synchronize()
+        x = xo.cpu().numpy()
+        s = so.cpu().numpy()
+    finally:
+        P.close()
+    assert st[0].iters_done == iters
+    np.testing.assert_array_equal(acc, tr.accept)
+    assert tr.accept.sum() > 10
+    assert_iterate_parity(x, tr.x, f"ADOCH {case}")
+    s_ref = orc.spins_with_field(tr.x) if A.h is not None else orc.sign(tr.x)
+    assert_spin_parity(s, tr.x, s_ref, f"ADOCH {case}")
+    assert_log_parity(H, r, tr, f"ADOCH {case}")
+
+
+def test_adoch_early_stop():
+    import torch
+    import paper_2509_01928_amd as Lb
+    A = gen.er_csr(2500, 6.0, 141)
+    x0 = gen.uniform_x0(2500, 1, 142)[:, 0]
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B, 1.0)
+    tr = orc.adoch(B, x0, alpha, beta, 3000, 5, eps=1e-3)
+    assert tr.iters < 3000
+    P = GpuProblem(A=A)
+    try:
+        p = P.params(alpha, beta, eps=1e-3)
+        p.algo, p.q = 1, 5
+        xd = torch.from_numpy(x0).to("cuda:0")
+        xo = torch.empty_like(xd)
+        st = Lb.ising_solve(P.ctx, xd, 1, 3000, p, xo, None)
+        torch.cuda.synchronize()
+        x = xo.cpu().numpy()
+    finally:
+        P.close()
+    assert st[0].iters_done == tr.iters and st[0].converged == 1
+    assert_iterate_parity(x, tr.x, "ADOCH eps")
