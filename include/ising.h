@@ -120,6 +120,15 @@ ising_status ising_create_dense(int64_t n, const void* J_dev, int32_t jt, int64_
                                 const void* h_dev, int32_t ht, void* stream,
                                 ising_ctx** out);
 
+/* ising_create_procedural: a dense context whose couplings are generated on
+ * demand instead of stored (Supp. Note 9): kind 1 is J_ij = sin(i*j + seed)
+ * with 0-based indices i, j and J_ii = 0, evaluated in FP64 (i*j < 2^53 is
+ * exact for n <= 9e7); the paper uses seed = 100.  No field.  Every entry
+ * point that takes a dense context accepts it except ising_solve_lowp.  It
+ * allocates nothing until used. */
+ising_status ising_create_procedural(int64_t n, int32_t kind, double seed, void* stream,
+                                     ising_ctx** out);
+
 /* Release a context and all its device memory (NULL is ignored). */
 void ising_destroy(ising_ctx* ctx);
 

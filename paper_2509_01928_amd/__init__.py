@@ -18,7 +18,7 @@ __all__ = [
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
     "ising_energy", "ising_set_geometry", "ising_autotune", "ising_create_batch",
-    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_solve_lowp", "ising_get_accept_log",
+    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_solve_lowp", "ising_get_accept_log", "ising_create_procedural",
     "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
 ]
@@ -101,6 +101,7 @@ _SIGS = {
     "ising_energy_batch": (_st, [_p, _p, _i32, _p, _p, _p]),
     "ising_solve_lowp": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _i32, _p, _p, _p, _p, _p]),
     "ising_get_accept_log": (_st, [_p, _i64, _i64, _p, _p]),
+    "ising_create_procedural": (_st, [_i64, _i32, _d, _p, ctypes.POINTER(_p)]),
     "ising_status_string": (ctypes.c_char_p, [_st]),
     "ising_last_error": (ctypes.c_char_p, []),
     "ising_version": (ctypes.c_char_p, []),
@@ -305,3 +306,12 @@ def ising_get_accept_log(ctx, first, count, stream=None):
                                     stream if stream is not None else current_stream()),
            "ising_get_accept_log")
     return out
+
+
+def ising_create_procedural(n, kind=1, seed=100.0, stream=None):
+    """Dense context with J_ij = sin(i*j + seed) generated on demand (kind 1)."""
+    out = _p()
+    _check(lib.ising_create_procedural(int(n), int(kind), float(seed),
+                                       stream if stream is not None else current_stream(),
+                                       ctypes.byref(out)), "ising_create_procedural")
+    return out.value

@@ -105,6 +105,8 @@ DenseView dense_view(const ising_ctx* c) {
     v.J = c->J;
     v.h = c->h;
     v.ht = c->ht;
+    v.proc_kind = c->proc_kind;
+    v.proc_seed = c->proc_seed;
     return v;
 }
 
@@ -475,6 +477,29 @@ ising_status ising_create_dense(int64_t n, const void* J_dev, int32_t jt, int64_
     return ISING_OK;
 }
 
+ising_status ising_create_procedural(int64_t n, int32_t kind, double seed, void* stream,
+                                     ising_ctx** out) {
+    if (!out) return fail(ISING_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 2 || n > 90000000LL) return fail(ISING_E_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (kind != 1) return fail(ISING_E_INVALID_ARG, "unknown procedural kind %d", kind);
+    if (!std::isfinite(seed)) return fail(ISING_E_INVALID_ARG, "seed must be finite");
+    (void)stream;
+    ising_ctx* c = new ising_ctx();
+    if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(ISING_E_HIP, "no HIP device"); }
+    c->dense = true;
+    c->n = n;
+    c->np = n;
+    c->nnz = n * (n - 1);
+    c->vt = ISING_F64;
+    c->ld = n;
+    c->proc_kind = kind;
+    c->proc_seed = seed;
+    c->integer_J = false;
+    *out = c;
+    return ISING_OK;
+}
+
 void ising_destroy(ising_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
@@ -496,6 +521,7 @@ ising_status ising_get_info(const ising_ctx* ctx, ising_info* out) {
 
 ising_status ising_check_symmetric(ising_ctx* ctx, void* stream) {
     if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
+    if (ctx->proc_kind != 0) return ISING_OK;          // sin(i j + seed) is symmetric by construction
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
     Scratch sc;
@@ -1025,7 +1051,8 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
                               int8_t* s_out_dev, double* H_final_dev, ising_stats* stats_host,
                               void* stream) {
     if (!ctx || !params || !x0_dev) return fail(ISING_E_INVALID_ARG, "NULL argument");
-    if (!ctx->dense) return fail(ISING_E_UNSUPPORTED, "the low-precision path needs a dense context");
+    if (!ctx->dense || ctx->proc_kind != 0)
+        return fail(ISING_E_UNSUPPORTED, "the low-precision path needs a stored dense context");
     if (ctx->has_field) return fail(ISING_E_UNSUPPORTED, "the low-precision path takes no field");
     if (jx_dtype != ISING_BF16 && jx_dtype != ISING_FP8_E4M3)
         return fail(ISING_E_INVALID_ARG, "jx_dtype must be ISING_BF16 or ISING_FP8_E4M3");

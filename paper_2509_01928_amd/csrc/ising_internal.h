@@ -64,6 +64,8 @@ struct DenseView {
     const double* J;
     const void* h;
     int ht;
+    int proc_kind;          // 0 = stored J, 1 = J_ij = sin(i j + seed)
+    double proc_seed;
 };
 
 // A launch plan of the CSR step kernel.  Geometries 0-2 are row-block
@@ -166,9 +168,11 @@ struct ising_ctx {
     int vt = ISING_F32;
     void* h = nullptr;
     int ht = ISING_F32;
-    // dense storage
+    // dense storage (or a procedural rule, proc_kind != 0)
     double* J = nullptr;
     int64_t ld = 0;
+    int proc_kind = 0;
+    double proc_seed = 0.0;
     // launch plans of the CSR step kernel, one per block geometry (built on
     // first use), and the geometry solves use (-1: chosen from the row lengths)
     doch::CsrPlan plans[doch::kNumGeometries];

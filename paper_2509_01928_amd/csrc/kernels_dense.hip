@@ -5,7 +5,11 @@
 // the iterate, and a butterfly reduction gives (J x)_i; lane 0 then applies
 // the cube-root update of eq:FPE.  Four wavefronts (four rows) share a
 // workgroup.  A single-vector FP64 product has no data reuse, so it runs on
-// the vector ALUs, not on the matrix cores.
+// the vector ALUs, not on the matrix cores.  The same kernels also serve the
+// procedural couplings J_ij = sin(i j + seed), generated in registers instead
+// of loaded (compute-bound on FP64 sine).
+#include <type_traits>
+
 #include "device_common.h"
 #include "ising_internal.h"
 #include "step_common.h"
@@ -17,9 +21,23 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
 
-template <typename XT, typename HT, bool FIELD>
-__global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, int64_t ld,
-                                                        const double* __restrict__ J,
+// Where the couplings come from: a stored row-major matrix, or the
+// procedural rule J_ij = sin(i j + seed) (0-based indices, zero diagonal) of
+// Supp. Note 9, evaluated on demand in FP64 (i j < 2^53 is exact).
+struct StoredJ {
+    const double* J;
+    int64_t ld;
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const { return J[i * ld + j]; }
+};
+struct SinJ {
+    double seed;
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const {
+        return i == j ? 0.0 : sin(dadd(dmul(static_cast<double>(i), static_cast<double>(j)), seed));
+    }
+};
+
+template <typename XT, typename HT, bool FIELD, typename JS>
+__global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
                                                         const HT* __restrict__ h, StepArgs a) {
     if (a.state->done) return;
     __shared__ double red[kNumPartials * NW];
@@ -33,9 +51,8 @@ __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, int64_t ld,
     for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
-        const double* __restrict__ row = J + i * ld;
         double p = 0.0;
-        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(row[j], static_cast<double>(x[j])));
+        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(J(i, j), static_cast<double>(x[j])));
         const double z0 = wave_sum(p);
         if (lane == 0) {
             double z = z0;
@@ -50,9 +67,8 @@ __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, int64_t ld,
     step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
 }
 
-template <typename HT, bool FIELD>
-__global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, int64_t ld,
-                                                          const double* __restrict__ J,
+template <typename HT, bool FIELD, typename JS>
+__global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, JS J,
                                                           const HT* __restrict__ h,
                                                           const int8_t* __restrict__ s, int R,
                                                           double* partials, unsigned int* tickets,
@@ -65,10 +81,9 @@ __global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, int64_t ld,
     double v[2] = {0.0, 0.0};
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
-        const double* __restrict__ row = J + i * ld;
         double p = 0.0;
         for (int64_t j = lane; j < n; j += kWave)
-            p = dadd(p, dmul(row[j], static_cast<double>(s[j * R + r])));
+            p = dadd(p, dmul(J(i, j), static_cast<double>(s[j * R + r])));
         const double z = wave_sum(p);
         if (lane == 0) {
             const double si = static_cast<double>(s[i * R + r]);
@@ -125,9 +140,8 @@ __global__ __launch_bounds__(NT) void dense_symcheck_kernel(int64_t n, int64_t l
     }
 }
 
-template <typename HT, bool FIELD>
-__global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, int64_t ld,
-                                                         const double* __restrict__ J,
+template <typename HT, bool FIELD, typename JS>
+__global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, JS J,
                                                          const HT* __restrict__ h, double mean,
                                                          int pass, double* partials,
                                                          unsigned int* ticket, MatrixStats* out) {
@@ -140,11 +154,10 @@ __global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, int64_t ld,
     double pmax = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
-        const double* __restrict__ row = J + i * ld;
         double a0 = 0.0, a1 = 0.0;
         for (int64_t j = lane; j < n; j += kWave) {
             if (j == i) continue;
-            const double x = row[j];
+            const double x = J(i, j);
             if (pass == 0) {
                 a0 = dadd(a0, fabs(x));
                 a1 = dadd(a1, x);
@@ -221,9 +234,8 @@ __global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, int64_t ld,
     }
 }
 
-template <typename HT, bool FIELD>
-__global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, int64_t ld,
-                                                         const double* __restrict__ J,
+template <typename HT, bool FIELD, typename JS>
+__global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, JS J,
                                                          const HT* __restrict__ h, double c,
                                                          const double* __restrict__ v,
                                                          double* __restrict__ w, double* partials,
@@ -237,9 +249,8 @@ __global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, int64_t ld,
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
-        const double* __restrict__ row = J + i * ld;
         double p = 0.0;
-        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(row[j], v[j]));
+        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(J(i, j), v[j]));
         const double z0 = wave_sum(p);
         if (lane == 0) {
             double z = z0;
@@ -298,39 +309,62 @@ int grid_for_elems(int64_t total) {
 
 int dense_step_grid(int64_t n) { return grid_for_rows(n); }
 
+// Call f with the view's coupling source (stored or procedural).
+#define DOCH_WITH_JSRC(A, ...)                                                  \
+    do {                                                                        \
+        if ((A).proc_kind == 1) {                                               \
+            const SinJ js{(A).proc_seed};                                       \
+            __VA_ARGS__;                                                        \
+        } else {                                                                \
+            const StoredJ js{(A).J, (A).ld};                                    \
+            __VA_ARGS__;                                                        \
+        }                                                                       \
+    } while (0)
+
 hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid, hipStream_t s) {
     const bool field = A.h != nullptr;
-#define DOCH_DENSE_STEP(XT, HT, F)                                                         \
-    hipLaunchKernelGGL((dense_step_kernel<XT, HT, F>), dim3(grid), dim3(NT), 0, s, A.n, A.ld, \
-                       A.J, static_cast<const HT*>(A.h), a)
-    if (a.x_dtype == ISING_F64) {
-        if (!field) DOCH_DENSE_STEP(double, double, false);
-        else if (A.ht == ISING_F64) DOCH_DENSE_STEP(double, double, true);
-        else DOCH_DENSE_STEP(double, float, true);
-    } else {
-        if (!field) DOCH_DENSE_STEP(float, double, false);
-        else if (A.ht == ISING_F64) DOCH_DENSE_STEP(float, double, true);
-        else DOCH_DENSE_STEP(float, float, true);
-    }
-#undef DOCH_DENSE_STEP
+    DOCH_WITH_JSRC(A, {
+        using JS = std::decay_t<decltype(js)>;
+        if (a.x_dtype == ISING_F64) {
+            if (!field)
+                hipLaunchKernelGGL((dense_step_kernel<double, double, false, JS>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, js, static_cast<const double*>(nullptr), a);
+            else if (A.ht == ISING_F64)
+                hipLaunchKernelGGL((dense_step_kernel<double, double, true, JS>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, js, static_cast<const double*>(A.h), a);
+            else
+                hipLaunchKernelGGL((dense_step_kernel<double, float, true, JS>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, js, static_cast<const float*>(A.h), a);
+        } else {
+            if (!field)
+                hipLaunchKernelGGL((dense_step_kernel<float, double, false, JS>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, js, static_cast<const double*>(nullptr), a);
+            else if (A.ht == ISING_F64)
+                hipLaunchKernelGGL((dense_step_kernel<float, double, true, JS>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, js, static_cast<const double*>(A.h), a);
+            else
+                hipLaunchKernelGGL((dense_step_kernel<float, float, true, JS>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, js, static_cast<const float*>(A.h), a);
+        }
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
                                double* partials, unsigned int* ticket, int grid, double* E,
                                hipStream_t s) {
-    if (A.h == nullptr)
-        hipLaunchKernelGGL((dense_energy_kernel<double, false>), dim3(grid, R), dim3(NT), 0, s,
-                           A.n, A.ld, A.J, static_cast<const double*>(nullptr), s_spins, R,
-                           partials, ticket, E);
-    else if (A.ht == ISING_F64)
-        hipLaunchKernelGGL((dense_energy_kernel<double, true>), dim3(grid, R), dim3(NT), 0, s,
-                           A.n, A.ld, A.J, static_cast<const double*>(A.h), s_spins, R, partials,
-                           ticket, E);
-    else
-        hipLaunchKernelGGL((dense_energy_kernel<float, true>), dim3(grid, R), dim3(NT), 0, s,
-                           A.n, A.ld, A.J, static_cast<const float*>(A.h), s_spins, R, partials,
-                           ticket, E);
+    DOCH_WITH_JSRC(A, {
+        using JS = std::decay_t<decltype(js)>;
+        if (A.h == nullptr)
+            hipLaunchKernelGGL((dense_energy_kernel<double, false, JS>), dim3(grid, R), dim3(NT), 0, s,
+                               A.n, js, static_cast<const double*>(nullptr), s_spins, R, partials, ticket, E);
+        else if (A.ht == ISING_F64)
+            hipLaunchKernelGGL((dense_energy_kernel<double, true, JS>), dim3(grid, R), dim3(NT), 0, s,
+                               A.n, js, static_cast<const double*>(A.h), s_spins, R, partials, ticket, E);
+        else
+            hipLaunchKernelGGL((dense_energy_kernel<float, true, JS>), dim3(grid, R), dim3(NT), 0, s,
+                               A.n, js, static_cast<const float*>(A.h), s_spins, R, partials, ticket, E);
+    });
     return hipGetLastError();
 }
 
@@ -348,36 +382,36 @@ hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s
 
 hipError_t launch_dense_stats(const DenseView& A, double mean, int pass, double* partials,
                               unsigned int* ticket, int grid, MatrixStats* out, hipStream_t s) {
-    if (A.h == nullptr)
-        hipLaunchKernelGGL((dense_stats_kernel<double, false>), dim3(grid), dim3(NT), 0, s, A.n,
-                           A.ld, A.J, static_cast<const double*>(nullptr), mean, pass, partials,
-                           ticket, out);
-    else if (A.ht == ISING_F64)
-        hipLaunchKernelGGL((dense_stats_kernel<double, true>), dim3(grid), dim3(NT), 0, s, A.n,
-                           A.ld, A.J, static_cast<const double*>(A.h), mean, pass, partials,
-                           ticket, out);
-    else
-        hipLaunchKernelGGL((dense_stats_kernel<float, true>), dim3(grid), dim3(NT), 0, s, A.n,
-                           A.ld, A.J, static_cast<const float*>(A.h), mean, pass, partials,
-                           ticket, out);
+    DOCH_WITH_JSRC(A, {
+        using JS = std::decay_t<decltype(js)>;
+        if (A.h == nullptr)
+            hipLaunchKernelGGL((dense_stats_kernel<double, false, JS>), dim3(grid), dim3(NT), 0, s, A.n, js,
+                               static_cast<const double*>(nullptr), mean, pass, partials, ticket, out);
+        else if (A.ht == ISING_F64)
+            hipLaunchKernelGGL((dense_stats_kernel<double, true, JS>), dim3(grid), dim3(NT), 0, s, A.n, js,
+                               static_cast<const double*>(A.h), mean, pass, partials, ticket, out);
+        else
+            hipLaunchKernelGGL((dense_stats_kernel<float, true, JS>), dim3(grid), dim3(NT), 0, s, A.n, js,
+                               static_cast<const float*>(A.h), mean, pass, partials, ticket, out);
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_dense_power_step(const DenseView& A, double c, const double* v, double* w,
                                    double* partials, unsigned int* ticket, int grid,
                                    double* mu_log, int64_t k, hipStream_t s) {
-    if (A.h == nullptr)
-        hipLaunchKernelGGL((dense_power_kernel<double, false>), dim3(grid), dim3(NT), 0, s, A.n,
-                           A.ld, A.J, static_cast<const double*>(nullptr), c, v, w, partials,
-                           ticket, mu_log, k);
-    else if (A.ht == ISING_F64)
-        hipLaunchKernelGGL((dense_power_kernel<double, true>), dim3(grid), dim3(NT), 0, s, A.n,
-                           A.ld, A.J, static_cast<const double*>(A.h), c, v, w, partials, ticket,
-                           mu_log, k);
-    else
-        hipLaunchKernelGGL((dense_power_kernel<float, true>), dim3(grid), dim3(NT), 0, s, A.n,
-                           A.ld, A.J, static_cast<const float*>(A.h), c, v, w, partials, ticket,
-                           mu_log, k);
+    DOCH_WITH_JSRC(A, {
+        using JS = std::decay_t<decltype(js)>;
+        if (A.h == nullptr)
+            hipLaunchKernelGGL((dense_power_kernel<double, false, JS>), dim3(grid), dim3(NT), 0, s, A.n, js,
+                               static_cast<const double*>(nullptr), c, v, w, partials, ticket, mu_log, k);
+        else if (A.ht == ISING_F64)
+            hipLaunchKernelGGL((dense_power_kernel<double, true, JS>), dim3(grid), dim3(NT), 0, s, A.n, js,
+                               static_cast<const double*>(A.h), c, v, w, partials, ticket, mu_log, k);
+        else
+            hipLaunchKernelGGL((dense_power_kernel<float, true, JS>), dim3(grid), dim3(NT), 0, s, A.n, js,
+                               static_cast<const float*>(A.h), c, v, w, partials, ticket, mu_log, k);
+    });
     return hipGetLastError();
 }
 

@@ -417,3 +417,42 @@ def test_adoch_early_stop():
         P.close()
     assert st[0].iters_done == tr.iters and st[0].converged == 1
     assert_iterate_parity(x, tr.x, "ADOCH eps")
+
+
+# ------------------------------------------------- procedural dense couplings
+def test_procedural_sin_couplings_parity():
+    """Supp. Note 9: J_ij = sin(i j + seed) generated on demand (0-based,
+    zero diagonal) gives the oracle's trajectory on the materialised matrix."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    n, seed, iters = 1500, 100.0, 300
+    i = np.arange(n, dtype=np.float64)
+    J = np.sin(np.outer(i, i) + seed)
+    np.fill_diagonal(J, 0.0)
+    x0 = gen.uniform_x0(n, 1, 151)[:, 0]
+    Bd = orc.csr_of_dense(J)
+    alpha, beta, lam = orc.default_params(Bd, 1.0, method="wigner")
+    tr = orc.doch_dense(J, x0, alpha, beta, iters)
+    ctx = Lb.ising_create_procedural(n, 1, seed)
+    try:
+        p, lam_gpu = Lb.ising_default_params(ctx, 1.0, 2)
+        assert lam_gpu == pytest.approx(lam, rel=1e-9)
+        assert p.beta == pytest.approx(beta, rel=1e-9)
+        q = Lb.ising_params()
+        q.alpha, q.beta, q.eps, q.algo, q.q, q.x_dtype, q.reserved = alpha, beta, 0.0, 0, 5, Lb.ISING_F64, 0
+        xd = torch.from_numpy(x0).to("cuda:0")
+        xo = torch.empty_like(xd)
+        so = torch.empty(n, dtype=torch.int8, device="cuda:0")
+        st = Lb.ising_solve(ctx, xd, 1, iters, q, xo, so)
+        H, r = Lb.ising_get_log(ctx, 0, 0, iters)
+        E = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        Lb.ising_energy(ctx, so, 1, E)
+        assert Lb.ising_check_symmetric(ctx)
+        torch.cuda.synchronize()
+        x, s = xo.cpu().numpy(), so.cpu().numpy()
+    finally:
+        Lb.ising_destroy(ctx)
+    assert_iterate_parity(x, tr.x, "procedural")
+    assert_spin_parity(s, tr.x, orc.sign(tr.x), "procedural")
+    assert_log_parity(H, r, tr, "procedural")
+    assert float(E.cpu()[0]) == pytest.approx(orc.energy_dense(J, s), rel=1e-11)
