@@ -18,6 +18,7 @@ Workloads (the paper's benchmark families, Results "Benchmarking"; Supp. Note 9)
                       bonds in {-1,+1}, optional Gaussian field h.
   * ``uneven_batch``  a list of ER instances with n ~ U{800..20000} and mean
                       degree ~ U[3,20].
+  * ``s5_csr``        sparse 9-bit integer couplings of Supp. Alg. S5.
   * ``uniform_x0``    start vectors x0 ~ U(-1,1).
 """
 from __future__ import annotations
@@ -29,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "CSR", "sk_dense", "er_csr", "torus_csr", "uniform_x0", "uneven_batch",
-    "csr_from_dense", "dense_from_csr", "random_dense_int", "pm1_complete",
+    "csr_from_dense", "dense_from_csr", "random_dense_int", "pm1_complete", "s5_csr",
     "SEEDS",
 ]
 
@@ -163,6 +164,26 @@ def er_csr(n: int, mean_degree: float, seed: int) -> CSR:
     ei, ej = _tri_row_col(k)
     ev = np.where(_rng(seed, 1).integers(0, 2, k.shape[0]) == 1, 1.0, -1.0)
     return _csr_from_lower_edges(n, ei, ej, ev)
+
+
+def s5_csr(n: int, p_percent: float, seed: int) -> CSR:
+    """Sparse 9-bit integer couplings of Supp. Alg. S5.
+
+    Every strict-lower pair (row-major order) draws z ~ U{1..N_p},
+    N_p = floor(102300 / p); the pair is coupled when z < 1023, with
+    J_ij = J_ji = z - 511.  The pairs are visited by geometric skipping with
+    the same per-pair probability 1022 / N_p, and the value is drawn from
+    U{1..1022} - 511 (the law of z given z < 1023).  A draw of z = 511 gives
+    J_ij = 0 and is not stored.
+    """
+    Np = int(np.floor(102300.0 / float(p_percent)))
+    q = min(1.0, 1022.0 / Np)
+    k = _lower_pairs_geometric(n, q, _rng(seed, 0))
+    z = _rng(seed, 1).integers(1, 1023, k.shape[0])
+    v = (z - 511).astype(np.float64)
+    keep = v != 0.0
+    ei, ej = _tri_row_col(k[keep])
+    return _csr_from_lower_edges(n, ei, ej, v[keep])
 
 
 def torus_csr(L: int, seed: int, h_std: float = 0.0) -> CSR:

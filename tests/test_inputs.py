@@ -105,3 +105,22 @@ def test_csr_dense_roundtrip():
     J = gen.random_dense_int(25, 9, density=0.4)
     A = gen.csr_from_dense(J)
     assert np.array_equal(gen.dense_from_csr(A), J)
+
+
+def test_s5_nine_bit_generator():
+    """Supp. Alg. S5: keep probability 1022/floor(102300/p), values z - 511 for
+    z ~ U{1..1022} (never 0 in storage), symmetric CSR."""
+    n, p = 3000, 1.0
+    A = gen.s5_csr(n, p, 17)
+    _check_csr_symmetric(A)
+    Np = int(102300 // p)
+    q = 1022 / Np
+    M = n * (n - 1) // 2
+    edges = A.nnz // 2
+    # zero draws (z = 511) are dropped: expected kept edges M q (1 - 1/1022)
+    mean = M * q * (1 - 1 / 1022)
+    assert abs(edges - mean) < 4 * np.sqrt(M * q)
+    v = A.val.astype(np.int64)
+    assert v.min() >= -510 and v.max() <= 511 and not np.any(v == 0)
+    assert abs(v.mean()) < 10
+    assert np.array_equal(A.col, gen.s5_csr(n, p, 17).col)
