@@ -26,13 +26,31 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every translation unit in parallel, then link libising.so."""
+    import tempfile
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with tempfile.TemporaryDirectory(prefix="ising_build_") as tmpdir:
+        objs, procs = [], []
+        for src in srcs:
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            cmd = ["hipcc", *flags, "-c", src, "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            while len([p for p in procs if p.poll() is None]) >= jobs:
+                procs[[p.poll() is None for p in procs].index(True)].wait()
+            procs.append(subprocess.Popen(cmd))
+            objs.append(obj)
+        for p in procs:
+            if p.wait() != 0:
+                raise subprocess.CalledProcessError(p.returncode, p.args)
+        tmp = LIB + ".tmp"
+        cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
     # bandwidth calibration program (a plain executable)
     flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
     cmd = ["hipcc", *flags, CALIB_SRC, "-o", CALIB_BIN + ".tmp"]
