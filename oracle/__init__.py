@@ -57,7 +57,7 @@ def _load():
             "ref_doch_csr": (_i64, [_i64, _p, _p, _p, _p, _dbl, _dbl, _i64, _dbl, _p, _p, _p]),
             "ref_doch_dense": (_i64, [_i64, _p, _p, _dbl, _dbl, _i64, _dbl, _p, _p, _p]),
             "ref_adoch_csr": (_i64, [_i64, _p, _p, _p, _p, _dbl, _dbl, _i64, _i32, _dbl,
-                                     _p, _p, _p, _p]),
+                                     _p, _p, _p, _p, _p, _p]),
             "ref_sign": (None, [_i64, _p, _p]),
             "ref_energy_csr_f64": (_dbl, [_i64, _p, _p, _p, _p, _p]),
             "ref_energy_dense_f64": (_dbl, [_i64, _p, _p, _p]),
@@ -163,7 +163,9 @@ class Trajectory:
     H: np.ndarray          # H(x^(k)), k < iters_done
     r: np.ndarray          # r^(k),   k < iters_done
     iters: int
-    accept: Optional[np.ndarray] = None   # ADOCH only
+    accept: Optional[np.ndarray] = None   # ADOCH only: y^(k) taken
+    Hy: Optional[np.ndarray] = None       # ADOCH only: H(y^(k))
+    Hmax: Optional[np.ndarray] = None     # ADOCH only: window maximum at k
 
 
 def doch(B: OracleCSR, x0: np.ndarray, alpha: float, beta: float, iters: int,
@@ -205,9 +207,13 @@ def adoch(B: OracleCSR, x0: np.ndarray, alpha: float, beta: float, iters: int, q
     H = np.empty(max(iters, 1), dtype=np.float64)
     r = np.empty(max(iters, 1), dtype=np.float64)
     acc = np.empty(max(iters, 1), dtype=np.int8)
+    Hy = np.empty(max(iters, 1), dtype=np.float64)
+    Hm = np.empty(max(iters, 1), dtype=np.float64)
     k = lib.ref_adoch_csr(B.n, _ptr(B.rp), _ptr(B.col), _ptr(B.val), _ptr(x0), alpha, beta,
-                          iters, int(q), eps, _ptr(x), _ptr(H), _ptr(r), _ptr(acc))
-    return Trajectory(x, H[:k].copy(), r[:k].copy(), int(k), acc[:k].copy())
+                          iters, int(q), eps, _ptr(x), _ptr(H), _ptr(r), _ptr(acc), _ptr(Hy),
+                          _ptr(Hm))
+    return Trajectory(x, H[:k].copy(), r[:k].copy(), int(k), acc[:k].copy(), Hy[:k].copy(),
+                      Hm[:k].copy())
 
 
 def sign(x: np.ndarray) -> np.ndarray:

@@ -195,7 +195,7 @@ int64_t ref_adoch_csr(int64_t n, const int64_t* rp, const int32_t* col,
                       const double* val, const double* x0, double alpha,
                       double beta, int64_t iters, int32_t q, double eps,
                       double* x_out, double* H_log, double* r_log,
-                      int8_t* accept_log) {
+                      int8_t* accept_log, double* Hy_log, double* Hmax_log) {
     double* x = dalloc(n);      /* x^(k)   */
     double* xp = dalloc(n);     /* x^(k-1) */
     double* y = dalloc(n);
@@ -224,6 +224,8 @@ int64_t ref_adoch_csr(int64_t n, const int64_t* rp, const int32_t* col,
         ref_matvec_csr(n, rp, col, val, y, z);
         double Hy = hamiltonian_from_z(n, y, z, alpha, beta);
         int accept = (Hy <= Hmax);
+        if (Hy_log) Hy_log[k] = Hy;
+        if (Hmax_log) Hmax_log[k] = Hmax;
         if (accept) {
             v = y;                                        /* z = J y  */
         } else {

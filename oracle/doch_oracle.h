@@ -60,12 +60,15 @@ int64_t ref_doch_dense(int64_t n, const double* J, const double* x0,
 
 /* ADOCH (Alg. 2, eq:BBscheme): Nesterov extrapolation accepted when
  * H(y^(k)) <= max{H(x^(j)) : max(0,k-q) <= j <= k}.  accept_log[k] = 1 if
- * y^(k) was taken (may be NULL).  Same logs as ref_doch_csr. */
+ * y^(k) was taken (may be NULL).  Hy_log[k] = H(y^(k)) and Hmax_log[k] = the
+ * window maximum it was compared with (either may be NULL), so a caller can
+ * tell a clear decision from a tie within rounding.  Same logs as
+ * ref_doch_csr otherwise. */
 int64_t ref_adoch_csr(int64_t n, const int64_t* rp, const int32_t* col,
                       const double* val, const double* x0, double alpha,
                       double beta, int64_t iters, int32_t q, double eps,
                       double* x_out, double* H_log, double* r_log,
-                      int8_t* accept_log);
+                      int8_t* accept_log, double* Hy_log, double* Hmax_log);
 
 /* Alg. 1 return line: s_i = sign(x_i) with sign(0) = +1. */
 void ref_sign(int64_t n, const double* x, int8_t* s);

@@ -189,6 +189,9 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->jq[0]);
     dev_free(c->jq[1]);
     dev_free(c->rscale);
+    dev_free(c->rowabs);
+    dev_free(c->lp_cs);
+    dev_free(c->lp_colmax);
     dev_free(c->lp_u[0]);
     dev_free(c->lp_u[1]);
     dev_free(c->lp_ub[0]);
@@ -1072,8 +1075,24 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
     const size_t esz = prec == 0 ? 2 : 1;
     if (!ctx->jq[prec]) {
         HIP_OK(dev_alloc(&ctx->jq[prec], static_cast<size_t>(np) * np * esz), "hipMalloc(Jq)");
-        if (prec == 1) HIP_OK(dev_alloc(&ctx->rscale, static_cast<size_t>(np) * sizeof(float)), "hipMalloc(scale)");
-        HIP_OK(doch::launch_lowp_convert(prec, ctx->J, n, np, ctx->jq[prec], ctx->rscale, s), "convert J");
+        if (prec == 1) {
+            HIP_OK(dev_alloc(&ctx->rscale, static_cast<size_t>(np) * sizeof(float)), "hipMalloc(scale)");
+            HIP_OK(dev_alloc(&ctx->rowabs, static_cast<size_t>(np) * sizeof(double)), "hipMalloc(row sums)");
+            HIP_OK(dev_alloc(&ctx->lp_cs, 2 * kMaxR * sizeof(float)), "hipMalloc(restart scales)");
+            HIP_OK(dev_alloc(&ctx->lp_colmax, kMaxR * sizeof(unsigned int)), "hipMalloc(column maxima)");
+        }
+        HIP_OK(doch::launch_lowp_convert(prec, ctx->J, n, np, ctx->jq[prec], ctx->rscale, ctx->rowabs, s),
+               "convert J");
+        if (prec == 1) {
+            // once per context: the bound that carries the restart scales
+            std::vector<double> ra(static_cast<size_t>(np));
+            HIP_OK(hipMemcpyAsync(ra.data(), ctx->rowabs, np * sizeof(double), hipMemcpyDeviceToHost, s),
+                   "copy row sums");
+            HIP_OK(hipStreamSynchronize(s), "sync");
+            double m = 0.0;
+            for (double v : ra) m = std::max(m, v);
+            ctx->lp_rho_q = m;
+        }
         ctx->lp_np = np;
     }
     const size_t ubytes = static_cast<size_t>(np) * Rp * sizeof(float);
@@ -1105,12 +1124,15 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
            "hipMalloc(log)");
     HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, nullptr, s), "init");
     const double sb = std::sqrt(p.beta);
-    HIP_OK(doch::launch_lowp_load(prec, x0_dev, n, R, np, Rp, sb, ctx->lp_u[0], ctx->lp_ub[0], s), "load");
+    float* cs[2] = {ctx->lp_cs, ctx->lp_cs ? ctx->lp_cs + kMaxR : nullptr};
+    HIP_OK(doch::launch_lowp_load(prec, x0_dev, n, R, np, Rp, sb, ctx->lp_colmax, cs[0], ctx->lp_u[0],
+                                  ctx->lp_ub[0], s), "load");
     for (int64_t k = 0; k < iters; ++k) {
         const int a = static_cast<int>(k & 1), b = 1 - a;
         HIP_OK(doch::launch_lowp_step(prec, np, Rp, ctx->jq[prec], ctx->rscale, ctx->lp_u[a], ctx->lp_u[b],
-                                      ctx->lp_ub[a], ctx->lp_ub[b], p.alpha, p.beta, p.eps, R, k,
-                                      ctx->lp_partials, ctx->ticket, ctx->log, ctx->state, s),
+                                      ctx->lp_ub[a], ctx->lp_ub[b], cs[a], cs[b], ctx->lp_rho_q, p.alpha,
+                                      p.beta, p.eps, R, k, ctx->lp_partials, ctx->ticket, ctx->log,
+                                      ctx->state, s),
                "low-precision step");
     }
     ctx->last_R = R;

@@ -208,6 +208,10 @@ struct ising_ctx {
     // dense low-precision path (ising_solve_lowp)
     void* jq[2] = {nullptr, nullptr};    // BF16 / FP8 copies of J, padded
     float* rscale = nullptr;             // FP8 per-row scales
+    double* rowabs = nullptr;            // FP8: s_i sum_j |q_ij| per row
+    double lp_rho_q = 0.0;               // FP8: max_i rowabs[i]
+    float* lp_cs = nullptr;              // FP8: restart scales, two buffers of kMaxR
+    unsigned int* lp_colmax = nullptr;   // FP8: start column maxima (float bits)
     int lp_np = 0;                       // padded order (multiple of 128)
     float* lp_u[2] = {nullptr, nullptr};
     void* lp_ub[2] = {nullptr, nullptr};
@@ -281,11 +285,12 @@ hipError_t launch_batch_power(const BatchView& B, const int32_t* jobs, int njobs
 
 // ---- launchers (kernels_mfma.hip) ----
 hipError_t launch_lowp_convert(int prec, const double* J, int n, int np, void* Jq, float* rscale,
-                               hipStream_t s);
+                               double* rowabs, hipStream_t s);
 hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, int Rp, double sqrt_beta,
-                            float* U, void* Ub, hipStream_t s);
+                            unsigned int* colmax_bits, float* cs, float* U, void* Ub, hipStream_t s);
 hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const float* rscale,
                             const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
+                            const float* cs_old, float* cs_new, double rho_q,
                             double alpha, double beta, double eps, int R, int64_t k,
                             double* partials, unsigned int* ticket, double* log, RestartState* state,
                             hipStream_t s);

@@ -14,7 +14,13 @@
 // multiplied.  J sits in a BF16 copy, or an FP8 copy with one FP32 scale per
 // row (J_ij ~ s_i q_ij, s_i = max_j |J_ij| / 448).  The restart block sits as
 // an FP32 master (n x R) plus a low-precision transposed copy (R x n) that
-// feeds the next product.  The epilogue applies the update in FP64, stores
+// feeds the next product.  In FP8 that copy carries one FP32 scale per
+// restart, c_j, with |u_ij| <= 448 c_j: exact at the start (column maximum)
+// and carried forward by the bound |u'| = |cbrt(z + alpha u)| <=
+// cbrt((rho_q + alpha) M) for |u| <= M, where rho_q is the largest absolute
+// row sum of the quantised J.  The bound tends to sqrt(rho_q + alpha), so
+// large starting points (u = sqrt(beta) x is large when beta is) never reach
+// the format's overflow, and later steps keep its full relative precision.  The epilogue applies the update in FP64, stores
 // both copies and adds the restart's FP64 partial sums; the last workgroup
 // closes the iteration for every restart (H, r, freezing at r < eps).
 #include "device_common.h"
@@ -40,9 +46,30 @@ template <> struct Prec<1> {   // FP8 e4m3 (OCP)
     static constexpr int KT = 128;
 };
 
+constexpr float kFp8Max = 448.0f;
+// margin on the carried bound: FP32 accumulation of the product (relative
+// error below n 2^-24 <= 2^-8 for n <= 65536) and rounding of the update
+constexpr double kBoundSlack = 1.01;
+
 __device__ __forceinline__ uint8_t to_fp8(float f) {
-    // v_cvt_pk_fp8_f32: round to nearest even, saturating
+    // v_cvt_pk_fp8_f32 rounds to nearest even; the operands are scaled into
+    // range, the clamp only guards the boundary
+    f = fminf(fmaxf(f, -kFp8Max), kFp8Max);
     return static_cast<uint8_t>(__builtin_amdgcn_cvt_pk_fp8_f32(f, 0.0f, 0, false) & 0xff);
+}
+
+// OCP e4m3 code -> value: bias 7, 3 mantissa bits, subnormals at exponent 0
+__device__ __forceinline__ double fp8_value(uint8_t q) {
+    const int e = (q >> 3) & 15, m = q & 7;
+    const double mag = e == 0 ? ldexp(static_cast<double>(m), -9) : ldexp(1.0 + m / 8.0, e - 7);
+    return (q & 0x80) ? -mag : mag;
+}
+
+// carried bound of the next iterate's magnitude, as a restart scale
+__device__ __forceinline__ float next_colscale(float c_old, double rho_q, double alpha) {
+    const double m_old = dmul(static_cast<double>(kFp8Max), static_cast<double>(c_old));
+    const double m_new = dmul(kBoundSlack, cbrt(dmul(dadd(dmul(kBoundSlack, rho_q), alpha), m_old)));
+    return static_cast<float>(dmul(ddiv(m_new, static_cast<double>(kFp8Max)), kBoundSlack));
 }
 
 template <int PREC>
@@ -71,6 +98,7 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     int np, int Rp, const typename Prec<PREC>::T* __restrict__ Jq, const float* __restrict__ rscale,
     const float* __restrict__ U_old, float* __restrict__ U_new,
     const typename Prec<PREC>::T* __restrict__ Ub_old, typename Prec<PREC>::T* __restrict__ Ub_new,
+    const float* __restrict__ cs_old, float* __restrict__ cs_new, double rho_q,
     double alpha, double beta, double eps, int R, int64_t k, double* __restrict__ partials,
     unsigned int* ticket, double* __restrict__ log, RestartState* __restrict__ state) {
     using T = typename Prec<PREC>::T;
@@ -127,13 +155,20 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     const int j = col0 + wc * 32 + (lane & 31);
     const bool live = j < R && !state[j < R ? j : 0].done;
     double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
+    // FP8: scale of the copy read by this product and of the one written now
+    float c_in = 1.0f, c_out = 1.0f;
+    if constexpr (PREC == 1) {
+        c_in = cs_old[j];
+        c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
+        if (blockIdx.x == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int i = row0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const size_t ij = static_cast<size_t>(i) * Rp + j;
         const double uo = static_cast<double>(U_old[ij]);
         double z = static_cast<double>(acc[v]);
-        if (PREC == 1) z = dmul(z, static_cast<double>(rscale[i]));
+        if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
         float un = static_cast<float>(uo);
         if (live) {
             un = static_cast<float>(cbrt(dadd(z, dmul(alpha, uo))));
@@ -145,7 +180,7 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
             part[3] = dadd(part[3], dmul(d, d));
         }
         U_new[ij] = un;
-        Ub_new[static_cast<size_t>(j) * np + i] = to_lowp<PREC>(un);
+        Ub_new[static_cast<size_t>(j) * np + i] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
     }
     // rows of a column: lanes l and l + 32, then the two row halves of the tile
 #pragma unroll
@@ -193,21 +228,49 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     if (tid == 0) reset_ticket(ticket);
 }
 
+__device__ __forceinline__ float start_u(const double* x0, int64_t i, int R, int j, double sqrt_beta) {
+    return static_cast<float>(dmul(x0[i * R + j], sqrt_beta));
+}
+
+// FP8: max_i |u_ij| of the starting block, as float bits (order-preserving
+// for non-negative values), combined over row chunks of 64 with atomicMax
+// into colmax_bits (zeroed by the caller).
+__global__ __launch_bounds__(256) void lowp_colmax_kernel(const double* __restrict__ x0, int n, int R,
+                                                          double sqrt_beta,
+                                                          unsigned int* __restrict__ colmax_bits) {
+    const int j = blockIdx.y * 256 + threadIdx.x;
+    if (j >= R) return;
+    const int i0 = blockIdx.x * 64;
+    const int i1 = i0 + 64 < n ? i0 + 64 : n;
+    float m = 0.0f;
+    for (int i = i0; i < i1; ++i) m = fmaxf(m, fabsf(start_u(x0, i, R, j, sqrt_beta)));
+    atomicMax(colmax_bits + j, __float_as_uint(m));
+}
+
 // x0 (n x R, double) -> u = sqrt(beta) x in the padded FP32 master and the
-// transposed low-precision copy; padding rows and restarts are zero.
+// transposed low-precision copy; padding rows and restarts are zero.  FP8
+// divides by the restart scale c_j = max_i |u_ij| / 448 (1 for a zero
+// column) and records it.
 template <int PREC>
 __global__ __launch_bounds__(256) void lowp_load_kernel(const double* __restrict__ x0, int n, int R,
                                                        int np, int Rp, double sqrt_beta,
-                                                       float* __restrict__ U,
+                                                       const unsigned int* __restrict__ colmax_bits,
+                                                       float* __restrict__ cs, float* __restrict__ U,
                                                        typename Prec<PREC>::T* __restrict__ Ub) {
     const int64_t total = static_cast<int64_t>(np) * Rp;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; t < total;
          t += static_cast<int64_t>(gridDim.x) * 256) {
         const int i = static_cast<int>(t / Rp), j = static_cast<int>(t % Rp);
-        const float u = (i < n && j < R) ? static_cast<float>(dmul(x0[static_cast<int64_t>(i) * R + j], sqrt_beta))
-                                         : 0.0f;
+        const float u = (i < n && j < R) ? start_u(x0, i, R, j, sqrt_beta) : 0.0f;
         U[t] = u;
-        Ub[static_cast<int64_t>(j) * np + i] = to_lowp<PREC>(u);
+        if constexpr (PREC == 1) {
+            const float m = j < R ? __uint_as_float(colmax_bits[j]) : 0.0f;
+            const float c = m > 0.0f ? m / kFp8Max : 1.0f;
+            if (i == 0) cs[j] = c;
+            Ub[static_cast<int64_t>(j) * np + i] = to_fp8(u / c);
+        } else {
+            Ub[static_cast<int64_t>(j) * np + i] = to_lowp<PREC>(u);
+        }
     }
 }
 
@@ -226,11 +289,13 @@ __global__ __launch_bounds__(256) void lowp_finish_kernel(const float* __restric
     }
 }
 
-// FP64 J -> padded BF16 copy, or FP8 copy with per-row scales.
+// FP64 J -> padded BF16 copy, or FP8 copy with per-row scales and the
+// absolute row sums s_i sum_j |q_ij| of the quantised rows (rowabs).
 template <int PREC>
 __global__ __launch_bounds__(256) void lowp_convert_kernel(const double* __restrict__ J, int n, int np,
                                                            typename Prec<PREC>::T* __restrict__ Jq,
-                                                           float* __restrict__ rscale) {
+                                                           float* __restrict__ rscale,
+                                                           double* __restrict__ rowabs) {
     __shared__ double red[4];
     for (int i = blockIdx.x; i < np; i += gridDim.x) {
         float s = 1.0f;
@@ -246,10 +311,24 @@ __global__ __launch_bounds__(256) void lowp_convert_kernel(const double* __restr
             s = m > 0.0 ? static_cast<float>(m / 448.0) : 1.0f;
             if (threadIdx.x == 0) rscale[i] = s;
         }
+        double ra = 0.0;
         for (int c = threadIdx.x; c < np; c += 256) {
             const double v = (i < n && c < n) ? J[static_cast<int64_t>(i) * n + c] : 0.0;
-            Jq[static_cast<int64_t>(i) * np + c] =
-                to_lowp<PREC>(PREC == 1 ? static_cast<float>(v / static_cast<double>(s)) : static_cast<float>(v));
+            if constexpr (PREC == 1) {
+                const uint8_t q = to_fp8(static_cast<float>(v / static_cast<double>(s)));
+                Jq[static_cast<int64_t>(i) * np + c] = q;
+                ra = dadd(ra, fabs(fp8_value(q)));
+            } else {
+                Jq[static_cast<int64_t>(i) * np + c] = to_lowp<PREC>(static_cast<float>(v));
+            }
+        }
+        if constexpr (PREC == 1) {
+            ra = wave_sum(ra);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ra;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                rowabs[i] = dmul(dadd(dadd(red[0], red[1]), dadd(red[2], red[3])), static_cast<double>(s));
+            __syncthreads();
         }
     }
 }
@@ -302,32 +381,38 @@ __global__ __launch_bounds__(256) void dense_objective_kernel(const double* __re
 }  // namespace
 
 hipError_t launch_lowp_convert(int prec, const double* J, int n, int np, void* Jq, float* rscale,
-                               hipStream_t s) {
+                               double* rowabs, hipStream_t s) {
     const int grid = np < 4096 ? np : 4096;
     if (prec == 0)
         hipLaunchKernelGGL(lowp_convert_kernel<0>, dim3(grid), dim3(256), 0, s, J, n, np,
-                           static_cast<__bf16*>(Jq), rscale);
+                           static_cast<__bf16*>(Jq), rscale, rowabs);
     else
         hipLaunchKernelGGL(lowp_convert_kernel<1>, dim3(grid), dim3(256), 0, s, J, n, np,
-                           static_cast<uint8_t*>(Jq), rscale);
+                           static_cast<uint8_t*>(Jq), rscale, rowabs);
     return hipGetLastError();
 }
 
 hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, int Rp, double sqrt_beta,
-                            float* U, void* Ub, hipStream_t s) {
+                            unsigned int* colmax_bits, float* cs, float* U, void* Ub, hipStream_t s) {
     int64_t g = (static_cast<int64_t>(np) * Rp + 255) / 256;
     if (g > 8192) g = 8192;
-    if (prec == 0)
+    if (prec == 0) {
         hipLaunchKernelGGL(lowp_load_kernel<0>, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, x0, n, R,
-                           np, Rp, sqrt_beta, U, static_cast<__bf16*>(Ub));
-    else
+                           np, Rp, sqrt_beta, nullptr, nullptr, U, static_cast<__bf16*>(Ub));
+    } else {
+        hipError_t e = hipMemsetAsync(colmax_bits, 0, static_cast<size_t>(R) * sizeof(unsigned int), s);
+        if (e != hipSuccess) return e;
+        const dim3 cg((n + 63) / 64, (R + 255) / 256);
+        hipLaunchKernelGGL(lowp_colmax_kernel, cg, dim3(256), 0, s, x0, n, R, sqrt_beta, colmax_bits);
         hipLaunchKernelGGL(lowp_load_kernel<1>, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, x0, n, R,
-                           np, Rp, sqrt_beta, U, static_cast<uint8_t*>(Ub));
+                           np, Rp, sqrt_beta, colmax_bits, cs, U, static_cast<uint8_t*>(Ub));
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const float* rscale,
                             const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
+                            const float* cs_old, float* cs_new, double rho_q,
                             double alpha, double beta, double eps, int R, int64_t k,
                             double* partials, unsigned int* ticket, double* log, RestartState* state,
                             hipStream_t s) {
@@ -335,13 +420,13 @@ hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const floa
     if (prec == 0)
         hipLaunchKernelGGL(lowp_step_kernel<0>, grid, dim3(MT), 0, s, np, Rp,
                            static_cast<const __bf16*>(Jq), rscale, U_old, U_new,
-                           static_cast<const __bf16*>(Ub_old), static_cast<__bf16*>(Ub_new), alpha,
-                           beta, eps, R, k, partials, ticket, log, state);
+                           static_cast<const __bf16*>(Ub_old), static_cast<__bf16*>(Ub_new), cs_old,
+                           cs_new, rho_q, alpha, beta, eps, R, k, partials, ticket, log, state);
     else
         hipLaunchKernelGGL(lowp_step_kernel<1>, grid, dim3(MT), 0, s, np, Rp,
                            static_cast<const uint8_t*>(Jq), rscale, U_old, U_new,
-                           static_cast<const uint8_t*>(Ub_old), static_cast<uint8_t*>(Ub_new), alpha,
-                           beta, eps, R, k, partials, ticket, log, state);
+                           static_cast<const uint8_t*>(Ub_old), static_cast<uint8_t*>(Ub_new), cs_old,
+                           cs_new, rho_q, alpha, beta, eps, R, k, partials, ticket, log, state);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import ising_inputs as gen
+import oracle as orc
 
 # Parity bar for the FP64 path: the oracle and the GPU agree to 1e-9 in max
 # abs (as an absolute bound and relative to the iterate's scale) after K
@@ -129,3 +130,28 @@ def assert_log_parity(H_gpu, r_gpu, tr, label=""):
 
 def seeded_csr_er(n, d, seed):
     return gen.er_csr(n, d, seed)
+
+
+def oracle_fp32_storage(B, x0, alpha, beta, iters):
+    """The oracle's FP64 step with the iterate rounded to FP32 between steps,
+    as a path that stores x in FP32 does: x <- fl32(T(fl32(x0)))...  Returns
+    the final iterate and the H log (H of each stored iterate)."""
+    x = np.asarray(x0, dtype=np.float32).astype(np.float64)
+    H = []
+    for _ in range(iters):
+        tr = orc.doch(B, x, alpha, beta, 1)
+        H.append(tr.H[0])
+        x = tr.x.astype(np.float32).astype(np.float64)
+    return x, np.array(H)
+
+
+def assert_fp32_storage_parity(x_gpu, x_emu, label=""):
+    """Same FP64 arithmetic and the same FP32 rounding of every stored
+    iterate: the iterates agree exactly except where an FP64 result fell
+    within rounding of an FP32 rounding boundary on one side only."""
+    scale = float(np.abs(x_emu).max())
+    exact = float(np.mean(x_gpu == x_emu))
+    assert exact >= 0.999, f"{label}: only {exact:.5f} of the FP32 iterates agree exactly"
+    d = float(np.abs(x_gpu - x_emu).max())
+    assert d <= 1e-6 * scale, f"{label}: max|dx| = {d:.3e} vs scale {scale:.3e}"
+

@@ -11,7 +11,8 @@ import pytest
 
 import ising_inputs as gen
 import oracle as orc
-from tests._util import assert_iterate_parity, assert_spin_parity
+from tests._util import (assert_fp32_storage_parity, assert_iterate_parity, assert_spin_parity,
+                         oracle_fp32_storage)
 
 pytestmark = pytest.mark.gpu
 
@@ -154,9 +155,8 @@ def test_batch_fp32_storage_and_replay():
         B = orc.to_oracle_csr(A)
         a, b = G.offs[k], G.offs[k + 1]
         for r in range(R):
-            tr = orc.doch(B, X0[a:b, r], alpha[k], beta[k], 80)
-            scale = np.abs(tr.x).max()
-            assert np.abs(X1[a:b, r] - tr.x).max() <= 1e-5 * scale
+            xe, _ = oracle_fp32_storage(B, X0[a:b, r], alpha[k], beta[k], 80)
+            assert_fp32_storage_parity(X1[a:b, r], xe, f"instance {k} restart {r}")
 
 
 def test_batch_default_params_match_oracle():

@@ -67,9 +67,13 @@ def test_lowp_zero_coupling_closed_form(prec_name):
 
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
 def test_lowp_energy_gap_and_final_objective(prec_name):
-    """SK n = 512, 32 restarts: the low-precision runs land within a few
-    percent of the FP64 oracle's energies on the same starts, H_final is
-    eq:Hamilton of the returned iterate, energies are those of its signs."""
+    """SK n = 512, 32 restarts.  H_final is eq:Hamilton of the returned
+    iterate and the energies are those of its signs (exact checks).  A
+    quantised run can settle in another local minimum than the FP64 run from
+    the same start, so energies are compared as distributions over the
+    restarts: the mean and the best energy within 2 % of the FP64 oracle's.
+    sqrt(beta) ~ 2.3e3 here, so u = sqrt(beta) x0 starts far above the FP8
+    range: the restart scales must carry it."""
     import paper_2509_01928_amd as L
     prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
     n, R, iters = 512, 32, 300
@@ -77,25 +81,23 @@ def test_lowp_energy_gap_and_final_objective(prec_name):
     X0 = gen.uniform_x0(n, R, 5004)
     alpha = -np.linalg.eigvalsh(J)[0]
     beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    assert math.sqrt(beta) * np.abs(X0).max() > 448 * 4
     X, S, Hf, E, st, Hlog = run_lowp(J, X0, alpha, beta, iters, prec)
-    assert all(s.iters_done == iters for s in st)
+    assert all(s.iters_done == iters and s.nonfinite == 0 for s in st)
     # final FP64 objective of the returned iterates (eq:Hamilton)
     H_np = beta / 4 * (X ** 4).sum(0) - alpha / 2 * (X ** 2).sum(0) - 0.5 * np.einsum("ir,ir->r", X, J @ X)
     np.testing.assert_allclose(Hf, H_np, rtol=1e-10)
     for r in range(R):
         assert E[r] == pytest.approx(orc.energy_dense(J, S[:, r]), rel=1e-12)
-    # the logged H of the quantised iteration decreases to the FP64 value's
-    # neighbourhood (g convex at the exact lambda)
+    # the logged H of the quantised iteration decreases
     for h in Hlog:
         assert h[-1] <= h[0]
-    gaps = []
-    for r in range(0, R, 4):
-        tr = orc.doch_dense(J, X0[:, r], alpha, beta, iters)
-        E64 = orc.energy_dense(J, orc.sign(tr.x))
-        gaps.append((E[r] - E64) / abs(E64))
-    gaps = np.array(gaps)
-    assert np.abs(gaps).max() < 0.05, gaps
-    assert abs(gaps.mean()) < 0.02, gaps
+    E64 = np.array([orc.energy_dense(J, orc.sign(orc.doch_dense(J, X0[:, r], alpha, beta, iters).x))
+                    for r in range(R)])
+    scale = abs(E64.mean())
+    assert abs(E.mean() - E64.mean()) < 0.02 * scale, (E.mean(), E64.mean())
+    assert E.min() - E64.min() < 0.02 * scale, (E.min(), E64.min())
+    assert np.abs(E - E64).max() < 0.15 * scale
 
 
 def test_lowp_freezes_converged_restarts():

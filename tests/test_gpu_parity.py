@@ -11,8 +11,9 @@ import pytest
 
 import ising_inputs as gen
 import oracle as orc
-from tests._util import (GpuProblem, assert_iterate_parity, assert_log_parity,
-                         assert_spin_parity)
+from tests._util import (H_RTOL, GpuProblem, assert_fp32_storage_parity,
+                         assert_iterate_parity, assert_log_parity, assert_spin_parity,
+                         oracle_fp32_storage)
 
 pytestmark = pytest.mark.gpu
 
@@ -184,14 +185,16 @@ def test_zero_iterations_and_zero_start():
 
 
 def test_fp32_iterate_storage():
-    """Iterate stored in FP32 (arithmetic FP64): a precision path, compared
-    with a bound derived from FP32 rounding of every stored iterate."""
+    """Iterate stored in FP32 (arithmetic FP64): compared with the oracle's
+    step applied to FP32-rounded iterates, and with the plain FP64 oracle by
+    a loose bound."""
     L = 128
     A = gen.torus_csr(L, 81, h_std=0.1)
     x0 = gen.uniform_x0(L * L + 1, 1, 82)[:, 0]
     B = orc.problem_matrix(A)
     alpha, beta, _ = orc.default_params(B)
     tr = orc.doch(B, x0, alpha, beta, 100)
+    xe, He = oracle_fp32_storage(B, x0, alpha, beta, 100)
     P = GpuProblem(A=A)
     try:
         import paper_2509_01928_amd as Lb
@@ -199,9 +202,10 @@ def test_fp32_iterate_storage():
         H, r = P.log(100)
     finally:
         P.close()
+    assert_fp32_storage_parity(x[:, 0], xe, "torus FP32 storage")
+    assert np.abs(H - He).max() <= 1e-9 * np.abs(He).max()
     scale = np.abs(tr.x).max()
-    assert np.abs(x[:, 0] - tr.x).max() <= 1e-5 * scale
-    assert np.abs(H - tr.H).max() <= 1e-5 * np.abs(tr.H).max()
+    assert np.abs(x[:, 0] - tr.x).max() <= 1e-3 * scale
     s_ref = orc.spins_with_field(tr.x)
     diff = np.nonzero(s[:, 0] != s_ref)[0]
     assert all(abs(tr.x[i]) < 1e-4 * scale for i in diff)
@@ -355,6 +359,10 @@ def test_autotune_keeps_results():
 
 
 # ------------------------------------------------------------------ ADOCH
+# relative margin below which H(y) and the window maximum tie within rounding
+ADOCH_TIE_RTOL = 1e-11
+
+
 @pytest.mark.parametrize("case", ["er", "torus_field"])
 def test_adoch_parity(case):
     """Alg. 2: same decisions, iterates, H and r as the oracle's ADOCH, whose
@@ -387,12 +395,29 @@ def test_adoch_parity(case):
     finally:
         P.close()
     assert st[0].iters_done == iters
-    np.testing.assert_array_equal(acc, tr.accept)
+    # H(y^(k)) is formed from J x^(k) and J x^(k-1) here and by its own
+    # matvec in the oracle, in another summation order: where it ties the
+    # window maximum to within rounding, either decision is a valid run of
+    # Alg. 2.  Everywhere else the decisions must be the same.
+    # k = 0 ties exactly (y^(0) = x^(0)) and is accepted on both sides.
+    clear = np.abs(tr.Hy - tr.Hmax) > ADOCH_TIE_RTOL * (np.abs(tr.Hy) + np.abs(tr.Hmax))
+    assert clear[1:40].all(), "seeded case must not tie before H settles"
+    assert acc[0] == tr.accept[0] == 1
+    np.testing.assert_array_equal(acc[clear], tr.accept[clear])
     assert tr.accept.sum() > 10
+    # logs agree exactly up to the first decision taken the other way; after
+    # it both runs sit at the same fixed point
+    diff = np.nonzero(acc != tr.accept)[0]
+    m = int(diff[0]) if diff.size else iters
+    Hs = float(np.abs(tr.H).max())
+    assert np.abs(H[:m + 1] - tr.H[:m + 1]).max() <= H_RTOL * Hs
+    dr = np.abs(r[:m] - tr.r[:m])
+    assert np.all(dr <= 1e-12 + 1e-9 * np.abs(tr.r[:m]))
+    assert abs(H[-1] - tr.H[-1]) <= H_RTOL * Hs
+    assert r[-1] < 1e-9 and tr.r[-1] < 1e-9
     assert_iterate_parity(x, tr.x, f"ADOCH {case}")
     s_ref = orc.spins_with_field(tr.x) if A.h is not None else orc.sign(tr.x)
     assert_spin_parity(s, tr.x, s_ref, f"ADOCH {case}")
-    assert_log_parity(H, r, tr, f"ADOCH {case}")
 
 
 def test_adoch_early_stop():
