@@ -1147,11 +1147,11 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         }
         hipError_t e = doch::launch_lowp_finish(Ufin, n, R, Rp, sb, xo, s_out_dev, s);
         if (e == hipSuccess && H_final_dev) {
-            const int grid = std::min(1024, (n + 3) / 4);
+            // per (row tile of 64, padded restart) three FP64 partial sums
             Scratch sc;
-            ising_status st = ensure_scratch(ctx, static_cast<size_t>(grid) * R * 3, &sc);
+            ising_status st = ensure_scratch(ctx, static_cast<size_t>((n + 63) / 64) * Rp * 3, &sc);
             if (st != ISING_OK) { dev_free(xtmp); return st; }
-            e = doch::launch_dense_objective(ctx->J, n, R, xo, p.alpha, p.beta, sc.partials, sc.tickets, grid,
+            e = doch::launch_dense_objective(ctx->J, n, R, xo, p.alpha, p.beta, sc.partials, sc.tickets,
                                              H_final_dev, s);
         }
         if (e != hipSuccess) { dev_free(xtmp); return hip_fail(e, "finish"); }

@@ -100,16 +100,41 @@ __device__ __forceinline__ double load_agent(const double* p) {
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Called by thread 0 after it stored its workgroup's partials: returns true
-// in the one workgroup that arrives last.  Release/acquire at agent scope
-// orders every workgroup's partial stores before the last one's loads.
+// Handing partial results to the last workgroup of a launch.  The arriving
+// wave has stored its workgroup's partials with store_agent, which writes
+// through to the device's point of coherence; it waits until those stores
+// have completed, then counts itself in with a relaxed atomic.  The arrival
+// that completes the count reads every partial with load_agent, which reads
+// at the point of coherence.  No L2 write-back or invalidate is involved, so
+// a workgroup pays one store round trip and one atomic.
+__device__ __forceinline__ void wait_stores_complete() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 __device__ __forceinline__ bool arrive_last(unsigned int* ticket, unsigned int count) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    unsigned int prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    bool last = (prev == count - 1);
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return last;
+    wait_stores_complete();
+    const unsigned int prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return prev == count - 1;
+}
+
+// The same for a 1-D grid of any size, counted in two levels so that no
+// single counter takes more than about grid/8 arrivals: workgroup w counts in
+// group w mod 8 (one group per XCD under round-robin dispatch), the last of
+// each group counts at the top.  tickets[0] is the top, group g's counter is
+// tickets[kTicketStride * (1 + g)]; all nine start at zero and are zero again
+// when the launch is over.
+constexpr int kTicketStride = 32;                 // one counter per 128-byte line
+constexpr int kGridTickets = 9 * kTicketStride;   // counters a grouped ticket spans
+
+__device__ __forceinline__ bool arrive_last_grid(unsigned int* tickets, unsigned int grid) {
+    const unsigned int g = blockIdx.x & 7u;
+    const unsigned int per = (grid - g + 7u) / 8u;   // workgroups in group g (g < grid here)
+    const unsigned int groups = grid < 8u ? grid : 8u;
+    wait_stores_complete();
+    unsigned int* gt = tickets + kTicketStride * (1 + g);
+    if (__hip_atomic_fetch_add(gt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != per - 1) return false;
+    __hip_atomic_store(gt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(tickets, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == groups - 1;
 }
 
 __device__ __forceinline__ void reset_ticket(unsigned int* ticket) {

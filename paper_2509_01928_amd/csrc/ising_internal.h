@@ -297,8 +297,8 @@ hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const floa
 hipError_t launch_lowp_finish(const float* U, int n, int R, int Rp, double sqrt_beta, double* x_out,
                               int8_t* s_out, hipStream_t s);
 hipError_t launch_dense_objective(const double* J, int n, int R, const double* X, double alpha,
-                                  double beta, double* partials, unsigned int* tickets, int grid,
-                                  double* H, hipStream_t s);
+                                  double beta, double* partials, unsigned int* tickets, double* H,
+                                  hipStream_t s);
 
 // ---- launchers (kernels_adoch.hip) ----
 int adoch_grid(int64_t n);

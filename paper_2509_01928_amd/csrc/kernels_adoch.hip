@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT) void adoch_mv_kernel(
     if (threadIdx.x == 0) {
         double* p = a.partials + static_cast<size_t>(blockIdx.x) * 7;
         for (int q = 0; q < 7; ++q) store_agent(p + q, acc[q]);
-        last_flag = arrive_last(a.ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(a.ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NT) void adoch_update_kernel(
         double* p = a.partials + static_cast<size_t>(blockIdx.x) * 2;
         store_agent(p, acc[0]);
         store_agent(p + 1, acc[1]);
-        last_flag = arrive_last(a.ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(a.ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;

@@ -29,6 +29,9 @@ __global__ __launch_bounds__(NT) void load_x0_kernel(const double* __restrict__ 
 __global__ void init_state_kernel(RestartState* st, int R, unsigned int* ticket,
                                   unsigned int* sched) {
     if (sched && threadIdx.x < 8) sched[threadIdx.x * kSchedStride] = 0u;
+    // per-restart counters and the counters of a grouped grid ticket
+    const int nt = R > kGridTickets ? R : kGridTickets;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) ticket[t] = 0u;
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
         st[r].iters_done = 0;
         st[r].done = 0;
@@ -37,7 +40,6 @@ __global__ void init_state_kernel(RestartState* st, int R, unsigned int* ticket,
         st[r].pad = 0;
         st[r].H_last = 0.0;
         st[r].r_last = 0.0;
-        ticket[r] = 0u;
     }
 }
 

@@ -527,7 +527,7 @@ __global__ __launch_bounds__(NT) void csr_stats_kernel(
         store_agent(p + 1, v[1]);
         store_agent(p + 2, v[2]);
         store_agent(p + 3, m);
-        last_flag = arrive_last(ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(NT) void csr_power_kernel(
     if (threadIdx.x == 0) {
         double* p = partials + static_cast<size_t>(blockIdx.x) * 3;
         for (int q = 0; q < 3; ++q) store_agent(p + q, acc[q]);
-        last_flag = arrive_last(ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;

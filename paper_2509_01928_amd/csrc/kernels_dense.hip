@@ -36,6 +36,29 @@ struct SinJ {
     }
 };
 
+// Lane's share of row i of J times a vector: sum over j = lane, lane + 64, ...
+// in that order (the wavefront then adds the 64 lane sums).  Loads are issued
+// eight columns at a time before they are added, so a row costs a few memory
+// round trips instead of one per column.
+template <typename JS, typename V>
+__device__ __forceinline__ double lane_row_dot(const JS& J, int64_t i, V vec, int64_t n, int lane) {
+    constexpr int U = 8;
+    double p = 0.0;
+    int64_t j = lane;
+    for (; j + (U - 1) * kWave < n; j += U * kWave) {
+        double jv[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            jv[u] = J(i, j + u * kWave);
+            xv[u] = vec(j + u * kWave);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) p = dadd(p, dmul(jv[u], xv[u]));
+    }
+    for (; j < n; j += kWave) p = dadd(p, dmul(J(i, j), vec(j)));
+    return p;
+}
+
 template <typename XT, typename HT, bool FIELD, typename JS>
 __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
                                                         const HT* __restrict__ h, StepArgs a) {
@@ -52,7 +75,7 @@ __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
         double p = 0.0;
-        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(J(i, j), static_cast<double>(x[j])));
+        p = lane_row_dot(J, i, [&](int64_t j) { return static_cast<double>(x[j]); }, n, lane);
         const double z0 = wave_sum(p);
         if (lane == 0) {
             double z = z0;
@@ -82,8 +105,7 @@ __global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, JS J,
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
         double p = 0.0;
-        for (int64_t j = lane; j < n; j += kWave)
-            p = dadd(p, dmul(J(i, j), static_cast<double>(s[j * R + r])));
+        p = lane_row_dot(J, i, [&](int64_t j) { return static_cast<double>(s[j * R + r]); }, n, lane);
         const double z = wave_sum(p);
         if (lane == 0) {
             const double si = static_cast<double>(s[i * R + r]);
@@ -202,7 +224,7 @@ __global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, JS J,
         store_agent(p + 1, v[1]);
         store_agent(p + 2, v[2]);
         store_agent(p + 3, m);
-        last_flag = arrive_last(ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;
@@ -250,7 +272,7 @@ __global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, JS J,
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
         double p = 0.0;
-        for (int64_t j = lane; j < n; j += kWave) p = dadd(p, dmul(J(i, j), v[j]));
+        p = lane_row_dot(J, i, [&](int64_t j) { return v[j]; }, n, lane);
         const double z0 = wave_sum(p);
         if (lane == 0) {
             double z = z0;
@@ -269,7 +291,7 @@ __global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, JS J,
     if (threadIdx.x == 0) {
         double* p = partials + static_cast<size_t>(blockIdx.x) * 3;
         for (int q = 0; q < 3; ++q) store_agent(p + q, acc[q]);
-        last_flag = arrive_last(ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;

@@ -93,6 +93,36 @@ __device__ __forceinline__ f32x16 mfma_step(const char* a_row, const char* b_row
     }
 }
 
+// Last workgroup of a column block (64 restarts): reduce the K per-row-tile
+// partials of each restart in row-tile order.  Thread (q, c) owns quantity q
+// of restart c; its loads are issued in batches so the latency is paid once
+// per batch, not once per row tile.
+template <int K>
+__device__ __forceinline__ double column_partial_sum(const double* __restrict__ partials, int Rp,
+                                                     int c, int q, int tiles) {
+    constexpr int B = 16;
+    double s = 0.0;
+    for (int t0 = 0; t0 < tiles; t0 += B) {
+        double v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            v[b] = t0 + b < tiles ? load_agent(partials + (static_cast<size_t>(t0 + b) * Rp + c) * K + q) : 0.0;
+#pragma unroll
+        for (int b = 0; b < B; ++b) s = dadd(s, v[b]);
+    }
+    return s;
+}
+
+// One DOCH iteration for 64 rows x 64 restarts per workgroup.
+//   main loop   the full k range in 128-byte stages (64 BF16 or 128 FP8 per
+//               row): PF stages in flight in registers, two LDS buffers, one
+//               barrier per stage; a column block whose restarts have all
+//               stopped skips it
+//   epilogue    FP64 update of the 16 entries each lane holds, FP32 master
+//               store, the low-precision copy transposed through LDS and
+//               written in whole rows, per-restart partial sums
+//   finish      the last workgroup of each column block closes the
+//               iteration of its 64 restarts (H, r, stopping)
 template <int PREC>
 __global__ __launch_bounds__(MT) void lowp_step_kernel(
     int np, int Rp, const typename Prec<PREC>::T* __restrict__ Jq, const float* __restrict__ rscale,
@@ -103,8 +133,10 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     unsigned int* ticket, double* __restrict__ log, RestartState* __restrict__ state) {
     using T = typename Prec<PREC>::T;
     constexpr int KT = Prec<PREC>::KT;
-    __shared__ __attribute__((aligned(16))) char sA[64 * ROWB];
-    __shared__ __attribute__((aligned(16))) char sB[64 * ROWB];
+    constexpr int PF = 4;                       // stages in flight
+    static_assert(PF % 2 == 0, "LDS buffer of a stage is its ring slot's parity");
+    __shared__ __attribute__((aligned(16))) char sA[2][64 * ROWB];
+    __shared__ __attribute__((aligned(16))) char sB[2][64 * ROWB];
     __shared__ double red[2][64][4];
     __shared__ int last_flag;
     const int tid = threadIdx.x;
@@ -113,46 +145,69 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     const int wr = wave >> 1, wc = wave & 1;
     const int row0 = blockIdx.x * 64;
     const int col0 = blockIdx.y * 64;
-    // global -> register staging: thread loads 16-byte chunks c = tid, tid+256
-    // of the 64 x 128-byte tile (row = c / 8, chunk = c % 8)
-    const char* gA = reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * np * sizeof(T);
-    const char* gB = reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * np * sizeof(T);
-    const size_t gstride = static_cast<size_t>(np) * sizeof(T);
-    i32x4 ra[2], rb[2];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int c = tid + MT * u;
-            const int r = c >> 3, ch = c & 7;
-            const size_t off = r * gstride + static_cast<size_t>(k0) * sizeof(T) + ch * 16;
-            ra[u] = *reinterpret_cast<const i32x4*>(gA + off);
-            rb[u] = *reinterpret_cast<const i32x4*>(gB + off);
-        }
-    };
-    auto stash = [&]() {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int c = tid + MT * u;
-            const int r = c >> 3, ch = c & 7;
-            *reinterpret_cast<i32x4*>(sA + r * ROWB + ch * 16) = ra[u];
-            *reinterpret_cast<i32x4*>(sB + r * ROWB + ch * 16) = rb[u];
-        }
-    };
+    const int mycol = col0 + (tid & 63);
+    const bool block_live =
+        __syncthreads_or(tid < 64 && mycol < R && !state[mycol < R ? mycol : 0].done) != 0;
+
     f32x16 acc = {};
-    const char* a_row = sA + (wr * 32 + (lane & 31)) * ROWB;
-    const char* b_row = sB + (wc * 32 + (lane & 31)) * ROWB;
-    const int khalf = (lane >> 5) * 8;          // this lane's 8 consecutive k of a 16-deep step
-    fetch(0);
-    for (int k0 = 0; k0 < np; k0 += KT) {
-        stash();
-        __syncthreads();
-        if (k0 + KT < np) fetch(k0 + KT);
+    if (block_live) {
+        // thread loads 16-byte chunks c = tid, tid + 256 of each 64 x 128-byte
+        // stage (row c / 8, chunk c % 8) of J and of the restart copy
+        const char* gA = reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * np * sizeof(T);
+        const char* gB = reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * np * sizeof(T);
+        const size_t gstride = static_cast<size_t>(np) * sizeof(T);
+        size_t goff[2];
+        int soff[2];
 #pragma unroll
-        for (int kk = 0; kk < KT; kk += 16) acc = mfma_step<PREC>(a_row, b_row, kk + khalf, acc);
-        __syncthreads();
+        for (int u = 0; u < 2; ++u) {
+            const int c = tid + MT * u;
+            goff[u] = (c >> 3) * gstride + (c & 7) * 16;
+            soff[u] = (c >> 3) * ROWB + (c & 7) * 16;
+        }
+        i32x4 ring[PF][4];
+        auto fetch = [&](i32x4 (&r)[4], int st) {
+            const size_t kb = static_cast<size_t>(st) * 128;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                r[u] = *reinterpret_cast<const i32x4*>(gA + goff[u] + kb);
+                r[2 + u] = *reinterpret_cast<const i32x4*>(gB + goff[u] + kb);
+            }
+        };
+        const int nst = np / KT;
+        const char* a_base = &sA[0][0] + (wr * 32 + (lane & 31)) * ROWB;
+        const char* b_base = &sB[0][0] + (wc * 32 + (lane & 31)) * ROWB;
+        const int khalf = (lane >> 5) * 8;      // this lane's 8 consecutive k of a 16-deep step
+#pragma unroll
+        for (int p = 0; p < PF; ++p)
+            if (p < nst) fetch(ring[p], p);
+        for (int s0 = 0; s0 < nst; s0 += PF) {
+#pragma unroll
+            for (int p = 0; p < PF; ++p) {
+                const int st = s0 + p;
+                if (st < nst) {
+                    constexpr int kBuf = 64 * ROWB;
+                    char* A = &sA[p & 1][0];
+                    char* B = &sB[p & 1][0];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        *reinterpret_cast<i32x4*>(A + soff[u]) = ring[p][u];
+                        *reinterpret_cast<i32x4*>(B + soff[u]) = ring[p][2 + u];
+                    }
+                    if (st + PF < nst) fetch(ring[p], st + PF);
+                    __syncthreads();
+                    const char* a_row = a_base + (p & 1) * kBuf;
+                    const char* b_row = b_base + (p & 1) * kBuf;
+#pragma unroll
+                    for (int kk = 0; kk < KT; kk += 16) acc = mfma_step<PREC>(a_row, b_row, kk + khalf, acc);
+                }
+            }
+        }
     }
+    __syncthreads();                            // the stage buffers are reused below
+
     // ---- epilogue: lane holds column j, rows 8*(v/4) + 4*(lane/32) + v%4
-    const int j = col0 + wc * 32 + (lane & 31);
+    const int jl = wc * 32 + (lane & 31);
+    const int j = col0 + jl;
     const bool live = j < R && !state[j < R ? j : 0].done;
     double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
     // FP8: scale of the copy read by this product and of the one written now
@@ -162,9 +217,13 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
         if (blockIdx.x == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
     }
+    // transposed low-precision tile: row jl holds rows row0 .. row0+63 of restart j
+    T* tileT = reinterpret_cast<T*>(&sA[0][0]);
+    constexpr int TROW = 64 + 16 / static_cast<int>(sizeof(T));   // padded row, in elements
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int i = row0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int il = wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int i = row0 + il;
         const size_t ij = static_cast<size_t>(i) * Rp + j;
         const double uo = static_cast<double>(U_old[ij]);
         double z = static_cast<double>(acc[v]);
@@ -180,52 +239,65 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
             part[3] = dadd(part[3], dmul(d, d));
         }
         U_new[ij] = un;
-        Ub_new[static_cast<size_t>(j) * np + i] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
+        tileT[jl * TROW + il] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
     }
     // rows of a column: lanes l and l + 32, then the two row halves of the tile
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[q] = dadd(part[q], __shfl_xor(part[q], 32, 64));
     if (lane < 32) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[wr][wc * 32 + lane][q] = part[q];
+        for (int q = 0; q < 4; ++q) red[wr][jl][q] = part[q];
     }
     __syncthreads();
-    if (tid < 64) {
+    {
+        // 64 restart rows of 64 * sizeof(T) bytes, in 16-byte chunks
+        constexpr int CPR = 64 * static_cast<int>(sizeof(T)) / 16;
+        for (int c = tid; c < 64 * CPR; c += MT) {
+            const int r = c / CPR, ch = c % CPR;
+            const i32x4 v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(tileT + r * TROW) + ch * 16);
+            *reinterpret_cast<i32x4*>(reinterpret_cast<char*>(Ub_new + static_cast<size_t>(col0 + r) * np + row0) +
+                                      ch * 16) = v;
+        }
+    }
+    if (tid < 64) {                             // wave 0: the wave that releases below
         double* p = partials + (static_cast<size_t>(blockIdx.x) * Rp + col0 + tid) * 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) store_agent(p + q, dadd(red[0][tid][q], red[1][tid][q]));
     }
     __syncthreads();
-    if (tid == 0) last_flag = arrive_last(ticket, gridDim.x * gridDim.y) ? 1 : 0;
+    if (tid == 0) last_flag = arrive_last(ticket + blockIdx.y, gridDim.x) ? 1 : 0;
     __syncthreads();
     if (!last_flag) return;
-    // ---- last workgroup: close the iteration of every live restart
-    for (int c = tid; c < R; c += MT) {
-        if (state[c].done) continue;
-        double S[4] = {0.0, 0.0, 0.0, 0.0};
-        for (unsigned t = 0; t < gridDim.x; ++t)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                S[q] = dadd(S[q], load_agent(partials + (static_cast<size_t>(t) * Rp + c) * 4 + q));
-        // H(x) = H_u / beta with x = u / sqrt(beta); r is scale free
-        const double Hu = dsub(dsub(dmul(0.25, S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
-        const double H = ddiv(Hu, beta);
-        const double r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
-        log[(static_cast<size_t>(k) * R + c) * 2] = H;
-        log[(static_cast<size_t>(k) * R + c) * 2 + 1] = r;
-        RestartState& st = state[c];
-        st.iters_done = k + 1;
-        st.H_last = H;
-        st.r_last = r;
-        if (!isfinite(H) || !isfinite(r)) {
-            st.nonfinite = 1;
-            st.done = 1;
-        } else if (eps > 0.0 && r < eps) {
-            st.converged = 1;
-            st.done = 1;
+    // ---- last workgroup of this column block: close the iteration of its restarts
+    {
+        const int cl = tid & 63, q = tid >> 6;
+        red[0][cl][q] = column_partial_sum<4>(partials, Rp, col0 + cl, q, gridDim.x);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int c = col0 + tid;
+        if (c < R && !state[c].done) {
+            const double* S = red[0][tid];
+            // H(x) = H_u / beta with x = u / sqrt(beta); r is scale free
+            const double Hu = dsub(dsub(dmul(0.25, S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
+            const double H = ddiv(Hu, beta);
+            const double r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
+            log[(static_cast<size_t>(k) * R + c) * 2] = H;
+            log[(static_cast<size_t>(k) * R + c) * 2 + 1] = r;
+            RestartState& st = state[c];
+            st.iters_done = k + 1;
+            st.H_last = H;
+            st.r_last = r;
+            if (!isfinite(H) || !isfinite(r)) {
+                st.nonfinite = 1;
+                st.done = 1;
+            } else if (eps > 0.0 && r < eps) {
+                st.converged = 1;
+                st.done = 1;
+            }
         }
     }
-    if (tid == 0) reset_ticket(ticket);
+    if (tid == 0) reset_ticket(ticket + blockIdx.y);
 }
 
 __device__ __forceinline__ float start_u(const double* x0, int64_t i, int R, int j, double sqrt_beta) {
@@ -333,49 +405,101 @@ __global__ __launch_bounds__(256) void lowp_convert_kernel(const double* __restr
     }
 }
 
-// FP64 objective of R final iterates with the FP64 J (eq:Hamilton):
-// workgroup per (row block, restart); one wavefront per row.
+// FP64 objective of R final iterates with the FP64 J (eq:Hamilton).  Z = J X
+// is a dense (n x n) by (n x R) FP64 product: 64 x 64 output tiles per
+// workgroup, each thread a 4 x 4 block, J and X staged through LDS in k
+// slices of 32, so J is read once per 64 restarts instead of once per
+// restart.  The epilogue reduces x^4, x^2 and x z per restart over the tile's
+// rows; the last workgroup of each column block adds the row tiles in order
+// and writes H.
 __global__ __launch_bounds__(256) void dense_objective_kernel(const double* __restrict__ J, int n,
-                                                              int R, const double* __restrict__ X,
+                                                              int R, int Rp,
+                                                              const double* __restrict__ X,
                                                               double alpha, double beta,
                                                               double* __restrict__ partials,
                                                               unsigned int* tickets,
                                                               double* __restrict__ H) {
-    __shared__ double red[3 * 4];
+    constexpr int KS = 32;
+    __shared__ double Js[64][KS + 1];
+    __shared__ double Xs[KS][64];
+    __shared__ double cred[16][64][3];
     __shared__ int last_flag;
-    const int r = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double v[3] = {0.0, 0.0, 0.0};                 // x^4, x^2, x (J x)
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + wave; i < n;
-         i += static_cast<int64_t>(gridDim.x) * 4) {
-        double p = 0.0;
-        for (int c = lane; c < n; c += 64) p = dadd(p, dmul(J[i * n + c], X[static_cast<int64_t>(c) * R + r]));
-        const double z = wave_sum(p);
-        if (lane == 0) {
-            const double xi = X[i * R + r];
-            const double x2 = dmul(xi, xi);
-            v[0] = dadd(v[0], dmul(x2, x2));
-            v[1] = dadd(v[1], x2);
-            v[2] = dadd(v[2], dmul(xi, z));
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < n; k0 += KS) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / KS, kk = e % KS;
+            const int gi = row0 + r, gk = k0 + kk;
+            Js[r][kk] = (gi < n && gk < n) ? J[static_cast<int64_t>(gi) * n + gk] : 0.0;
+            const int xk = e / 64, xc = e % 64;
+            const int hk = k0 + xk, hc = col0 + xc;
+            Xs[xk][xc] = (hk < n && hc < R) ? X[static_cast<int64_t>(hk) * R + hc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KS; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = Js[ty * 4 + q][kk];
+                b[q] = Xs[kk][tx * 4 + q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+        }
+        __syncthreads();
+    }
+    // per-column sums over this thread's 4 rows
+    double v[4][3] = {};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int i = row0 + ty * 4 + p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = col0 + tx * 4 + q;
+            if (i < n && c < R) {
+                const double x = X[static_cast<int64_t>(i) * R + c];
+                const double x2 = dmul(x, x);
+                v[q][0] = dadd(v[q][0], dmul(x2, x2));
+                v[q][1] = dadd(v[q][1], x2);
+                v[q][2] = dadd(v[q][2], dmul(x, acc[p][q]));
+            }
         }
     }
-    block_sum<3, 256>(v, red);
-    double* p = partials + (static_cast<size_t>(r) * gridDim.x + blockIdx.x) * 3;
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 3; ++q) store_agent(p + q, v[q]);
-        last_flag = arrive_last(tickets + r, gridDim.x) ? 1 : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) cred[ty][tx * 4 + q][m] = v[q][m];
+    __syncthreads();
+    if (tid < 64) {                             // wave 0: the wave that releases below
+        double* p = partials + (static_cast<size_t>(blockIdx.x) * Rp + col0 + tid) * 3;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            double sm = 0.0;
+            for (int t = 0; t < 16; ++t) sm = dadd(sm, cred[t][tid][m]);
+            store_agent(p + m, sm);
+        }
     }
     __syncthreads();
+    if (tid == 0) last_flag = arrive_last(tickets + blockIdx.y, gridDim.x) ? 1 : 0;
+    __syncthreads();
     if (!last_flag) return;
-    double u[3] = {0.0, 0.0, 0.0};
-    const double* pr = partials + static_cast<size_t>(r) * gridDim.x * 3;
-    for (unsigned g = threadIdx.x; g < gridDim.x; g += 256)
-        for (int q = 0; q < 3; ++q) u[q] = dadd(u[q], load_agent(pr + g * 3 + q));
-    block_sum<3, 256>(u, red);
-    if (threadIdx.x == 0) {
-        H[r] = dsub(dsub(dmul(ddiv(beta, 4.0), u[0]), dmul(ddiv(alpha, 2.0), u[1])), dmul(0.5, u[2]));
-        reset_ticket(tickets + r);
+    if (tid < 3 * 64) {
+        const int cl = tid & 63, m = tid >> 6;
+        cred[0][cl][m] = column_partial_sum<3>(partials, Rp, col0 + cl, m, gridDim.x);
     }
+    __syncthreads();
+    if (tid < 64 && col0 + tid < R) {
+        const double* S = cred[0][tid];
+        H[col0 + tid] = dsub(dsub(dmul(ddiv(beta, 4.0), S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
+    }
+    if (tid == 0) reset_ticket(tickets + blockIdx.y);
 }
 
 }  // namespace
@@ -440,10 +564,11 @@ hipError_t launch_lowp_finish(const float* U, int n, int R, int Rp, double sqrt_
 }
 
 hipError_t launch_dense_objective(const double* J, int n, int R, const double* X, double alpha,
-                                  double beta, double* partials, unsigned int* tickets, int grid,
-                                  double* H, hipStream_t s) {
-    hipLaunchKernelGGL(dense_objective_kernel, dim3(grid, R), dim3(256), 0, s, J, n, R, X, alpha, beta,
-                       partials, tickets, H);
+                                  double beta, double* partials, unsigned int* tickets, double* H,
+                                  hipStream_t s) {
+    const int Rp = (R + 63) / 64 * 64;
+    hipLaunchKernelGGL(dense_objective_kernel, dim3((n + 63) / 64, Rp / 64), dim3(256), 0, s, J, n, R, Rp, X,
+                       alpha, beta, partials, tickets, H);
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ __device__ void step_epilogue(const StepArgs& a, double (&acc)[kNumPartials],
         double* p = a.partials + static_cast<size_t>(blockIdx.x) * kNumPartials;
 #pragma unroll
         for (int q = 0; q < kNumPartials; ++q) store_agent(p + q, acc[q]);
-        last_flag = arrive_last(a.ticket, gridDim.x) ? 1 : 0;
+        last_flag = arrive_last_grid(a.ticket, gridDim.x) ? 1 : 0;
     }
     __syncthreads();
     if (!last_flag) return;
