@@ -61,15 +61,29 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# the step kernel each launch geometry runs (ising_set_geometry)
+_GEOMETRY_KERNEL = {0: ("csr_step_kernel", "1, 1, false"), 1: ("csr_step_kernel", "2, 2, false"),
+                    2: ("csr_step_kernel", "4, 2, false"), 3: ("csr_rowlane_kernel", "1, 1"),
+                    4: ("csr_rowlane_kernel", "1, 2"), 5: ("csr_step_kernel", "1, 1, true"),
+                    6: ("csr_step_kernel", "2, 2, true"), 7: ("csr_step_kernel", "4, 2, true")}
+
+
+def step_kernel_name(geometry: int, x_dtype: str) -> str:
+    """Kernel instance timed on the lattice (FP32 couplings and field)."""
+    xt = "float" if x_dtype == "f32" else "double"
+    name, tail = _GEOMETRY_KERNEL[geometry]
+    return f"{name}<{xt}, float, float, true, {tail}>"
+
+
 def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch measured by rocprofv3 counters, if they were taken
-    on the current kernel source (else None)."""
+    on this kernel instance and on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f).get(f"{kernel}/{workload}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+        rec = json.load(f).get(workload)
+    if not rec or rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernel", ""):
         return None
     return rec
 
@@ -112,7 +126,7 @@ def ingest_pmc(paths, workload):
     }
     path = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
-    data[f"csr_step_kernel/{workload}"] = rec
+    data[workload] = rec
     with open(path, "w") as f:
         json.dump(data, f, indent=1)
     print(json.dumps(rec, indent=1))
@@ -436,6 +450,9 @@ def main():
     if args.geometry >= -1:
         L.ising_set_geometry(ctx, args.geometry, args.wg_per_cu)
         geometry, wg_per_cu = args.geometry, args.wg_per_cu
+        if geometry == -1:        # the library's choice from the mean row length
+            d = A.nnz / A.n
+            geometry, wg_per_cu = (4 if d <= 5 else 6 if d <= 8 else 7), 0
     else:
         p0, _ = L.ising_default_params(ctx, 1.0, 0)
         p0.x_dtype = x_dtype
@@ -480,7 +497,8 @@ def main():
     bytes_iter = 4 * (n + 1) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
     achieved = bytes_iter / (per_iter_ms * 1e-3) / 1e9
     workload = f"torus{args.L}"
-    traffic = load_traffic("csr_step_kernel", f"{workload}_{args.x_dtype}")
+    kernel = step_kernel_name(geometry, args.x_dtype)
+    traffic = load_traffic(kernel, f"{workload}_{args.x_dtype}")
     edge_updates = float(nnz) * args.iters * args.steps
     out = {
         "metric": "edge-updates/s",
@@ -509,7 +527,7 @@ def main():
         "energy": energy,
         "lambda_hat": lam,
         "roofline": {
-            "kernel": "csr_step_kernel",
+            "kernel": kernel,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -280,10 +280,10 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
  *
  * ising_set_geometry: 0 = 256-row blocks, 1024-entry spans; 1 = 512-row
  * blocks, 2048-entry spans; 2 = 512-row blocks, 4096-entry spans; 3 and 4 =
- * one row per lane, two rows in flight, rows of up to one (3) or two (4)
- * aligned 4-entry chunks loaded at once (longer rows take a slower path);
- * 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in order from a
- * per-XCD counter; -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
+ * one row per lane with the whole grid sweeping the rows together, rows of
+ * up to one (3) or two (4) aligned 4-entry chunks loaded at once (longer rows
+ * take a slower path); 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in
+ * order from a per-XCD counter; -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
  * workgroups launched per compute unit, 0 = as many as fit.  CSR contexts
  * only.
  *

@@ -136,15 +136,16 @@ std::vector<int2> make_blocks(const std::vector<int32_t>& rp, int64_t n, int row
 // Geometry from the mean row length: in-order scheduled row blocks of 512
 // rows, 2048-entry spans for short rows and 4096-entry spans for long ones
 // (the fastest on the lattice and random-graph workloads measured).
+// Short rows (lattices, mean length up to 5): one row per lane; longer rows:
+// row blocks from per-XCD counters.
 int default_geometry(int64_t n, int64_t nnz) {
     const double d = static_cast<double>(nnz) / static_cast<double>(n);
-    return d <= 8.0 ? 6 : 7;
+    return d <= 5.0 ? 4 : (d <= 8.0 ? 6 : 7);
 }
 
-// Two resident workgroups per CU stream the read-mostly mix of the
-// lane-per-row kernels faster than a full device (measured on gfx950); the
-// row-block kernels need every workgroup that fits to hide their barriers.
-int default_wg_per_cu(int geometry) { return (geometry == 3 || geometry == 4) ? 2 : 0; }
+// Every kernel hides its load chains with as many resident workgroups as
+// fit (measured on gfx950 for all geometries on the 10^8-spin lattice).
+int default_wg_per_cu(int) { return 0; }
 
 ising_status ensure_plan(ising_ctx* c, int geometry, doch::CsrPlan** out) {
     doch::CsrPlan& p = c->plans[geometry];

@@ -246,10 +246,15 @@ __global__ __launch_bounds__(NT) void csr_step_kernel(
 }
 
 // Lane-per-row variant for short rows.  Each lane owns U rows at a time
-// (rows i, i + S, ..., S = threads per XCD share) and loads a row's entries
-// as up to MAXC aligned 16-byte chunks straight into registers -- no LDS, no
+// (rows i, i + S, ..., S = threads in the grid) and loads a row's entries as
+// up to MAXC aligned 16-byte chunks straight into registers -- no LDS, no
 // barriers, no block table.  Rows that need more chunks fall back to an
-// element loop.  Sums still run in ascending column order.
+// element loop.  Sums still run in ascending column order.  The whole grid
+// sweeps the rows together, so at any moment every stream is read within one
+// narrow window of addresses: measured on MI355X this streams the lattice
+// faster than giving each XCD its own eighth of the rows, and a row's
+// neighbours one lattice row away are still inside the window when it is
+// gathered.
 template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC>
 __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
     int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -263,21 +268,9 @@ __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
 #pragma unroll
     for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
 
-    // XCD c (workgroups w with w mod 8 = c) owns the c-th eighth of the rows
-    const unsigned G = gridDim.x;
-    int64_t lo, hi, first, stride;
-    if ((G & 7u) == 0) {
-        const unsigned xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
-        lo = n * xcd / 8;
-        hi = n * (xcd + 1) / 8;
-        first = lo + static_cast<int64_t>(slot) * NT + threadIdx.x;
-        stride = static_cast<int64_t>(G >> 3) * NT;
-    } else {
-        lo = 0;
-        hi = n;
-        first = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
-        stride = static_cast<int64_t>(G) * NT;
-    }
+    const int64_t hi = n;
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * NT;
     for (int64_t base = first; base < hi; base += stride * U) {
         int s[U], e[U], a0[U];
         XT xi[U];
@@ -698,8 +691,8 @@ hipError_t launch_step_geo(const CsrView& A, const CsrPlan& plan, const StepArgs
         case 0: return launch_step_t<XT, VT, HT, FIELD, 1, 1, false>(A, plan, a, s);
         case 1: return launch_step_t<XT, VT, HT, FIELD, 2, 2, false>(A, plan, a, s);
         case 2: return launch_step_t<XT, VT, HT, FIELD, 4, 2, false>(A, plan, a, s);
-        case 3: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 1>(A, plan, a, s);
-        case 4: return launch_rowlane_t<XT, VT, HT, FIELD, 2, 2>(A, plan, a, s);
+        case 3: return launch_rowlane_t<XT, VT, HT, FIELD, 1, 1>(A, plan, a, s);
+        case 4: return launch_rowlane_t<XT, VT, HT, FIELD, 1, 2>(A, plan, a, s);
         case 5: return launch_step_t<XT, VT, HT, FIELD, 1, 1, true>(A, plan, a, s);
         case 6: return launch_step_t<XT, VT, HT, FIELD, 2, 2, true>(A, plan, a, s);
         default: return launch_step_t<XT, VT, HT, FIELD, 4, 2, true>(A, plan, a, s);
