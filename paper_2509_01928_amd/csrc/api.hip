@@ -940,6 +940,20 @@ ising_status ising_default_params_batch(ising_ctx* ctx, double eta, int32_t meth
     return ISING_OK;
 }
 
+// Launch shape of the batch kernel for R <= 8 restarts (see
+// launch_batch_solve): the least splitting of the restarts into jobs that
+// still gives every CU a job.  Measured on 512 uneven instances x 8 restarts:
+// no split 159 ms, groups of 4 292 ms, 2 304 ms, 1 547 ms -- a row's R
+// iterate entries share one cache line, so splitting multiplies the lines
+// the random gathers fetch; it pays only when jobs would leave CUs idle.
+static int batch_shape(int R, int count, int cus) {
+    if (R > 8) return 0;
+    const int rj[4] = {R, R < 4 ? R : 4, R < 2 ? R : 2, 1};
+    for (int sh = 0; sh < 4; ++sh)
+        if (static_cast<int64_t>(count) * (R / rj[sh]) >= cus) return sh;
+    return 3;
+}
+
 ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t max_iters,
                                const double* alpha_host, const double* beta_host, double eps,
                                int32_t x_dtype, double* x_out_dev, int8_t* s_out_dev,
@@ -974,9 +988,13 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
     std::copy(beta_host, beta_host + count, ab.begin() + count);
     HIP_OK(hipMemcpyAsync(ctx->bparams, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, s),
            "copy alpha/beta");
+    int cus = 256;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
+    const int shape = batch_shape(R, count, cus);
     // the whole solve is one persistent kernel (after a small init kernel),
     // captured once into a graph and replayed while the arguments repeat
-    const std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(max_iters),
+    const std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(shape),
+                                       static_cast<uint64_t>(max_iters),
                                        static_cast<uint64_t>(x_dtype), reinterpret_cast<uint64_t>(x0_dev),
                                        reinterpret_cast<uint64_t>(x_out_dev), reinterpret_cast<uint64_t>(s_out_dev),
                                        reinterpret_cast<uint64_t>(ctx->xbuf[0]), reinterpret_cast<uint64_t>(ctx->bstats),
@@ -988,7 +1006,7 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
         HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            e = doch::launch_batch_solve(batch_view(ctx), R, max_iters, ctx->bparams, ctx->bparams + count, eps,
+            e = doch::launch_batch_solve(batch_view(ctx), R, shape, max_iters, ctx->bparams, ctx->bparams + count, eps,
                                          x_dtype, x0_dev, ctx->xbuf[0], ctx->xbuf[1], ctx->bqueue, ctx->bstats,
                                          ctx->bclock, ctx->bclock + 1, x_out_dev, s_out_dev, cs);
             hipGraph_t g = nullptr;

@@ -271,7 +271,9 @@ hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s
 // ---- launchers (kernels_batch.hip) ----
 bool batch_restarts_supported(int R);
 hipError_t launch_batch_validate(const BatchView& B, int64_t n, int32_t* bad, hipStream_t s);
-hipError_t launch_batch_solve(const BatchView& B, int R, int64_t max_iters, const double* alpha,
+// shape (up to 8 restarts): 0 = all restarts per job, 256 threads; 1 = groups
+// of 4, 512 threads; 2 = groups of 2, 1024 threads; 3 = one restart, 1024
+hipError_t launch_batch_solve(const BatchView& B, int R, int shape, int64_t max_iters, const double* alpha,
                               const double* beta, double eps, int x_dtype, const double* x0,
                               void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
                               uint64_t* clock_start, uint64_t* clock_end, double* x_out,

@@ -15,6 +15,7 @@
 // ends when all its restarts have stopped or after max_iters iterations,
 // and stamps the device clock for its time to solution.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "ising_internal.h"
@@ -173,10 +174,216 @@ __global__ __launch_bounds__(BT) void batch_solve_kernel(
     }
 }
 
+// R contiguous iterate entries (one row, all restarts) as one vector access.
+template <typename XT, int R>
+struct RowVec {
+    typedef XT type __attribute__((ext_vector_type(R)));
+};
+template <typename XT>
+struct RowVec<XT, 1> {
+    typedef XT type;
+};
+
+template <typename XT, int R>
+__device__ __forceinline__ void load_row(const XT* p, XT (&out)[R]) {
+    const typename RowVec<XT, R>::type w = *reinterpret_cast<const typename RowVec<XT, R>::type*>(p);
+    if constexpr (R == 1) {
+        out[0] = w;
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[r] = w[r];
+    }
+}
+
+template <typename XT, int R>
+__device__ __forceinline__ void store_row(XT* p, const XT (&in)[R]) {
+    typename RowVec<XT, R>::type w;
+    if constexpr (R == 1) {
+        w = in[0];
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[r] = in[r];
+    }
+    *reinterpret_cast<typename RowVec<XT, R>::type*>(p) = w;
+}
+
+// The same batch loop with one row per thread and a group of RJ (<= 8) of
+// an instance's R restarts in the thread's registers.  A job is (instance,
+// restart group): restarts never interact, so the groups of one instance run
+// as independent jobs, and the fewer restarts a job carries the fewer
+// registers it needs and the more threads (rows in flight) a workgroup can
+// have -- the length of an iteration of a large instance is set by how many
+// rows are in flight against the memory latency, not by the arithmetic.  A
+// coupling costs one index and one value (loaded in aligned 16-byte chunks,
+// the next chunk requested before this one's gathers are waited for) and one
+// contiguous RJ-wide read of the iterate.  Sums run in the rows' stored
+// (ascending column) order; the workgroup reductions are in a fixed order.
+// Jobs are taken largest instance first; an instance's time to solution is
+// the end of its last job.
+template <typename XT, typename VT, int RJ, int WG>
+__global__ __launch_bounds__(WG) void batch_rows_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const VT* __restrict__ val,
+    const BatchInstance* __restrict__ inst, const int32_t* __restrict__ order, int count, int R,
+    const double* __restrict__ alpha, const double* __restrict__ beta, double eps,
+    int64_t max_iters, const double* __restrict__ x0, XT* __restrict__ xa, XT* __restrict__ xb,
+    unsigned int* queue, BatchRestartStat* __restrict__ stats, uint64_t* __restrict__ clock_start,
+    uint64_t* __restrict__ clock_end, double* __restrict__ x_out, int8_t* __restrict__ s_out) {
+    constexpr int K = 4 * RJ;                 // x^4, x^2, x z, (dx)^2 per restart
+    __shared__ double red[K * (WG / kWave)];
+    __shared__ int conv[RJ];
+    __shared__ int s_job;
+    __shared__ int s_all;
+    const int groups = R / RJ;
+    const int njobs = count * groups;
+    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned long long*>(clock_start),
+                                    static_cast<unsigned long long>(device_clock()));
+    for (;;) {
+        if (threadIdx.x == 0) s_job = static_cast<int>(atomicAdd(queue, 1u));
+        if (threadIdx.x < RJ) conv[threadIdx.x] = 0;
+        __syncthreads();
+        const int job = s_job;
+        if (job >= njobs) break;
+        const int k = order[job / groups];
+        const int r0 = (job % groups) * RJ;
+        const BatchInstance I = inst[k];
+        const double a = alpha[k], b = beta[k];
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(I.n) * RJ; t += WG) {
+            const int64_t e = (I.row0 + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
+            xa[e] = static_cast<XT>(x0[e]);
+        }
+        __syncthreads();
+        const XT* xo = xa;
+        XT* xw = xb;
+        int64_t it = 0;
+        for (; it < max_iters; ++it) {
+            bool frozen[RJ];
+#pragma unroll
+            for (int r = 0; r < RJ; ++r) frozen[r] = conv[r] != 0;
+            double acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = 0.0;
+            const int iend = I.row0 + I.n;
+            int sn = 0, en = 0;                 // the next row's offsets, requested early
+            if (I.row0 + static_cast<int>(threadIdx.x) < iend) {
+                sn = rp[I.row0 + threadIdx.x];
+                en = rp[I.row0 + threadIdx.x + 1];
+            }
+            for (int i = I.row0 + static_cast<int>(threadIdx.x); i < iend; i += WG) {
+                const int s = sn, e = en;
+                if (i + WG < iend) {
+                    sn = rp[i + WG];
+                    en = rp[i + WG + 1];
+                }
+                double z[RJ];
+#pragma unroll
+                for (int r = 0; r < RJ; ++r) z[r] = 0.0;
+                // the next chunk's indices and values are requested before this
+                // chunk's gathers are waited for
+                using CV = typename Vec4<int>::type;
+                using VV = typename Vec4<VT>::type;
+                int c0 = s & ~3;
+                CV cn{};
+                VV vn{};
+                if (c0 < e) {
+                    cn = *reinterpret_cast<const CV*>(col + c0);
+                    vn = *reinterpret_cast<const VV*>(val + c0);
+                }
+                for (; c0 < e; c0 += 4) {
+                    const CV cv = cn;
+                    const VV vv = vn;
+                    if (c0 + 4 < e) {
+                        cn = *reinterpret_cast<const CV*>(col + c0 + 4);
+                        vn = *reinterpret_cast<const VV*>(val + c0 + 4);
+                    }
+                    const int cc[4] = {cv.x, cv.y, cv.z, cv.w};
+                    const double vd[4] = {static_cast<double>(vv.x), static_cast<double>(vv.y),
+                                          static_cast<double>(vv.z), static_cast<double>(vv.w)};
+                    XT g[4][RJ];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (c0 + u >= s && c0 + u < e)
+                            load_row<XT, RJ>(xo + static_cast<int64_t>(cc[u]) * R + r0, g[u]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (c0 + u >= s && c0 + u < e) {
+#pragma unroll
+                            for (int r = 0; r < RJ; ++r) z[r] = dadd(z[r], dmul(vd[u], static_cast<double>(g[u][r])));
+                        }
+                }
+                XT xi[RJ], xn[RJ];
+                load_row<XT, RJ>(xo + static_cast<int64_t>(i) * R + r0, xi);
+#pragma unroll
+                for (int r = 0; r < RJ; ++r) {
+                    const double xv = static_cast<double>(xi[r]);
+                    if (frozen[r]) {
+                        xn[r] = xi[r];
+                    } else {
+                        xn[r] = static_cast<XT>(cbrt(ddiv(dadd(z[r], dmul(a, xv)), b)));
+                        const double d = dsub(static_cast<double>(xn[r]), xv);
+                        const double x2 = dmul(xv, xv);
+                        acc[4 * r + 0] = dadd(acc[4 * r + 0], dmul(x2, x2));
+                        acc[4 * r + 1] = dadd(acc[4 * r + 1], x2);
+                        acc[4 * r + 2] = dadd(acc[4 * r + 2], dmul(xv, z[r]));
+                        acc[4 * r + 3] = dadd(acc[4 * r + 3], dmul(d, d));
+                    }
+                }
+                store_row<XT, RJ>(xw + static_cast<int64_t>(i) * R + r0, xn);
+            }
+            block_sum<K, WG>(acc, red);       // totals in thread 0
+            if (threadIdx.x == 0) {
+                int all = 1;
+                for (int r = 0; r < RJ; ++r) {
+                    if (!conv[r]) {
+                        const double* S = acc + 4 * r;
+                        const double H = dsub(dsub(dmul(ddiv(b, 4.0), S[0]), dmul(ddiv(a, 2.0), S[1])),
+                                              dmul(0.5, S[2]));
+                        const double rr = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
+                        BatchRestartStat& st = stats[static_cast<int64_t>(k) * R + r0 + r];
+                        st.iters_done = it + 1;
+                        st.H_last = H;
+                        st.r_last = rr;
+                        if (!isfinite(H) || !isfinite(rr)) {
+                            st.nonfinite = 1;
+                            conv[r] = 1;
+                        } else if (eps > 0.0 && rr < eps) {
+                            st.converged = 1;
+                            conv[r] = 1;
+                        }
+                    }
+                    all &= conv[r];
+                }
+                s_all = all;
+            }
+            const XT* t = xo;
+            xo = xw;
+            xw = const_cast<XT*>(t);
+            __syncthreads();
+            if (s_all) {
+                ++it;
+                break;
+            }
+        }
+        // outputs from the buffer that holds x^(it)
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(I.n) * RJ; t += WG) {
+            const int64_t e = (I.row0 + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
+            const double v = static_cast<double>(xo[e]);
+            if (x_out) x_out[e] = v;
+            if (s_out) s_out[e] = v >= 0.0 ? 1 : -1;
+        }
+        if (threadIdx.x == 0)
+            atomicMax(reinterpret_cast<unsigned long long*>(clock_end + k),
+                      static_cast<unsigned long long>(device_clock()));
+        __syncthreads();
+    }
+}
+
 template <int R>
 __global__ void batch_init_kernel(BatchRestartStat* stats, int count, unsigned int* queue,
-                                  uint64_t* clock_start) {
+                                  uint64_t* clock_start, uint64_t* clock_end) {
     const int64_t total = static_cast<int64_t>(count) * R;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        clock_end[t] = 0;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
          t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         stats[t].iters_done = 0;
@@ -395,7 +602,7 @@ bool batch_restarts_supported(int R) {
     return R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32;
 }
 
-hipError_t launch_batch_solve(const BatchView& B, int R, int64_t max_iters, const double* alpha,
+hipError_t launch_batch_solve(const BatchView& B, int R, int shape, int64_t max_iters, const double* alpha,
                               const double* beta, double eps, int x_dtype, const double* x0,
                               void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
                               uint64_t* clock_start, uint64_t* clock_end, double* x_out,
@@ -403,43 +610,45 @@ hipError_t launch_batch_solve(const BatchView& B, int R, int64_t max_iters, cons
     DOCH_BATCH_R(R, {
         const int ig = static_cast<int>(std::min<int64_t>(1024, (static_cast<int64_t>(B.count) * RR + 255) / 256));
         hipLaunchKernelGGL(batch_init_kernel<RR>, dim3(ig), dim3(256), 0, s, stats, B.count, queue,
-                           clock_start);
+                           clock_start, clock_end);
+        // up to 8 restarts: a row per thread, restart groups of RJ as jobs of
+        // WG-thread workgroups (shape); more: a restart per lane
+        auto go = [&](auto xtag, auto vtag) {
+            using XT = decltype(xtag);
+            using VT = decltype(vtag);
+            if constexpr (RR <= 8) {
+                auto rows = [&](auto rjtag, auto wgtag) {
+                    constexpr int RJ = decltype(rjtag)::value < RR ? decltype(rjtag)::value : RR;
+                    constexpr int WG = decltype(wgtag)::value;
+                    auto kern = batch_rows_kernel<XT, VT, RJ, WG>;
+                    const int grid = std::min(resident_grid(kern, WG), B.count * (RR / RJ));
+                    hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, B.rp, B.col,
+                                       static_cast<const VT*>(B.val), B.inst, B.order, B.count, RR, alpha,
+                                       beta, eps, max_iters, x0, static_cast<XT*>(xa), static_cast<XT*>(xb),
+                                       queue, stats, clock_start, clock_end, x_out, s_out);
+                };
+                using std::integral_constant;
+                switch (shape) {
+                    case 1: rows(integral_constant<int, 4>(), integral_constant<int, 512>()); break;
+                    case 2: rows(integral_constant<int, 2>(), integral_constant<int, 1024>()); break;
+                    case 3: rows(integral_constant<int, 1>(), integral_constant<int, 1024>()); break;
+                    default: rows(integral_constant<int, 8>(), integral_constant<int, 256>()); break;
+                }
+            } else {
+                auto kern = batch_solve_kernel<XT, VT, RR>;
+                const int grid = std::min(resident_grid(kern, BT), B.count);
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col, static_cast<const VT*>(B.val),
+                                   B.inst, B.order, B.count, alpha, beta, eps, max_iters, x0,
+                                   static_cast<XT*>(xa), static_cast<XT*>(xb), queue, stats, clock_start,
+                                   clock_end, x_out, s_out);
+            }
+        };
         if (B.vt == ISING_F64) {
-            if (x_dtype == ISING_F64) {
-                auto kern = batch_solve_kernel<double, double, RR>;
-                const int grid = std::min(resident_grid(kern, BT), B.count);
-                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
-                                   static_cast<const double*>(B.val), B.inst, B.order, B.count, alpha,
-                                   beta, eps, max_iters, x0, static_cast<double*>(xa),
-                                   static_cast<double*>(xb), queue, stats, clock_start, clock_end,
-                                   x_out, s_out);
-            } else {
-                auto kern = batch_solve_kernel<float, double, RR>;
-                const int grid = std::min(resident_grid(kern, BT), B.count);
-                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
-                                   static_cast<const double*>(B.val), B.inst, B.order, B.count, alpha,
-                                   beta, eps, max_iters, x0, static_cast<float*>(xa),
-                                   static_cast<float*>(xb), queue, stats, clock_start, clock_end,
-                                   x_out, s_out);
-            }
+            if (x_dtype == ISING_F64) go(double(), double());
+            else go(float(), double());
         } else {
-            if (x_dtype == ISING_F64) {
-                auto kern = batch_solve_kernel<double, float, RR>;
-                const int grid = std::min(resident_grid(kern, BT), B.count);
-                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
-                                   static_cast<const float*>(B.val), B.inst, B.order, B.count, alpha,
-                                   beta, eps, max_iters, x0, static_cast<double*>(xa),
-                                   static_cast<double*>(xb), queue, stats, clock_start, clock_end,
-                                   x_out, s_out);
-            } else {
-                auto kern = batch_solve_kernel<float, float, RR>;
-                const int grid = std::min(resident_grid(kern, BT), B.count);
-                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col,
-                                   static_cast<const float*>(B.val), B.inst, B.order, B.count, alpha,
-                                   beta, eps, max_iters, x0, static_cast<float*>(xa),
-                                   static_cast<float*>(xb), queue, stats, clock_start, clock_end,
-                                   x_out, s_out);
-            }
+            if (x_dtype == ISING_F64) go(double(), float());
+            else go(float(), float());
         }
     });
     return hipGetLastError();

@@ -110,6 +110,34 @@ def test_batch_fixed_iterations_parity(R):
     assert np.all(tts > 0)
 
 
+@pytest.mark.parametrize("count", [300, 150, 64, 9])
+def test_batch_restart_groups_parity(count):
+    """8 restarts per instance, split into jobs of 8, 4, 2 or 1 restarts
+    depending on how many instances there are (one job per CU at least):
+    every sampled (instance, restart) follows its own oracle run."""
+    R = 8
+    inst = gen.uneven_batch(count=count, seed=500 + count, n_lo=40, n_hi=160, d_lo=3.0, d_hi=9.0)
+    alpha, beta = oracle_params(inst)
+    total = sum(A.n for A in inst)
+    X0 = gen.uniform_x0(total, R, 600 + count)
+    G = GpuBatch(inst, R)
+    try:
+        X, S, st, tts = G.solve(X0, alpha, beta, 60, 0.0)
+    finally:
+        G.close()
+    for k in sorted({0, count // 3, count // 2, count - 1}):
+        A = inst[k]
+        B = orc.to_oracle_csr(A)
+        a, b = G.offs[k], G.offs[k + 1]
+        for r in range(R):
+            tr = orc.doch(B, X0[a:b, r], alpha[k], beta[k], 60)
+            lab = f"{count} instances: instance {k} restart {r}"
+            assert_iterate_parity(X[a:b, r], tr.x, lab)
+            assert st[k * R + r].iters_done == 60
+            assert st[k * R + r].H_last == pytest.approx(tr.H[-1], rel=1e-12)
+    assert np.all(tts > 0)
+
+
 def test_batch_early_stop_per_restart():
     """Remark S2 per restart: every (instance, restart) stops exactly where
     the oracle run of that restart alone stops."""
