@@ -1089,7 +1089,7 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int prec = jx_dtype == ISING_BF16 ? 0 : 1;
     const int n = static_cast<int>(ctx->n);
-    const int np = (n + 127) / 128 * 128;
+    const int np = (n + 255) / 256 * 256;          // whole 256-byte stages in both formats
     const int Rp = (R + 63) / 64 * 64;
     const size_t esz = prec == 0 ? 2 : 1;
     if (!ctx->jq[prec]) {
@@ -1230,8 +1230,13 @@ ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int grid = ctx->dense ? std::min<int64_t>(1024, (ctx->n + 3) / 4)
                                 : std::min<int64_t>(1024, (ctx->n + 255) / 256);
+    // partials: per (workgroup, restart) 3 doubles, or for the tiled dense
+    // kernel per (64-row tile, padded restart) 2
+    size_t need = static_cast<size_t>(grid) * R * 3;
+    if (ctx->dense && R >= doch::kTiledEnergyMinR)
+        need = std::max(need, static_cast<size_t>((ctx->n + 63) / 64) * ((R + 63) / 64 * 64) * 2);
     Scratch sc;
-    ising_status st = ensure_scratch(ctx, static_cast<size_t>(grid) * R * 3, &sc);
+    ising_status st = ensure_scratch(ctx, need, &sc);
     if (st != ISING_OK) return st;
     if (ctx->dense) {
         if (!E_dev) return fail(ISING_E_INVALID_ARG, "E is NULL");

@@ -141,4 +141,24 @@ __device__ __forceinline__ void reset_ticket(unsigned int* ticket) {
     __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Last workgroup of a column block (64 restarts): reduce the K per-row-tile
+// partials of each restart in row-tile order.  Thread (q, c) owns quantity q
+// of restart c; its loads are issued B at a time so the latency (these loads
+// read at the device's point of coherence) is paid once per batch of B row
+// tiles.
+template <int K, int B = 32>
+__device__ __forceinline__ double column_partial_sum(const double* __restrict__ partials, int Rp,
+                                                     int c, int q, int tiles) {
+    double s = 0.0;
+    for (int t0 = 0; t0 < tiles; t0 += B) {
+        double v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            v[b] = t0 + b < tiles ? load_agent(partials + (static_cast<size_t>(t0 + b) * Rp + c) * K + q) : 0.0;
+#pragma unroll
+        for (int b = 0; b < B; ++b) s = dadd(s, v[b]);
+    }
+    return s;
+}
+
 }  // namespace doch

@@ -212,7 +212,7 @@ struct ising_ctx {
     double lp_rho_q = 0.0;               // FP8: max_i rowabs[i]
     float* lp_cs = nullptr;              // FP8: restart scales, two buffers of kMaxR
     unsigned int* lp_colmax = nullptr;   // FP8: start column maxima (float bits)
-    int lp_np = 0;                       // padded order (multiple of 128)
+    int lp_np = 0;                       // padded order (multiple of 256)
     float* lp_u[2] = {nullptr, nullptr};
     void* lp_ub[2] = {nullptr, nullptr};
     size_t lp_ubytes = 0, lp_ubbytes = 0;
@@ -257,6 +257,8 @@ hipError_t launch_dense_validate(const DenseView& A, int32_t* flags, hipStream_t
 hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid,
                              hipStream_t s);
 int dense_step_grid(int64_t n);
+// restarts from which ising_energy on a dense context uses the tiled J S kernel
+constexpr int kTiledEnergyMinR = 8;
 hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
                                double* partials, unsigned int* ticket, int grid,
                                double* E, hipStream_t s);

@@ -90,6 +90,97 @@ __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
     step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
 }
 
+// eq:IsingModel for many restarts at once: Z = J S for the n x R spin block,
+// 64 x 64 output tiles per workgroup, each thread a 4 x 4 block, J and S
+// staged through LDS in k slices of 32, so each coupling is read (or
+// generated) once per 64 restarts.  Per restart the tile adds s_i z_i and
+// h_i s_i over its rows; the last workgroup of each column block adds the row
+// tiles in order and writes E = -1/2 s^T J s - h^T s.
+template <typename HT, bool FIELD, typename JS>
+__global__ __launch_bounds__(NT) void dense_energy_tiled_kernel(int64_t n, JS J, const HT* __restrict__ h,
+                                                                const int8_t* __restrict__ S, int R, int Rp,
+                                                                double* __restrict__ partials,
+                                                                unsigned int* tickets, double* __restrict__ E) {
+    constexpr int KS = 32;
+    __shared__ double Js[64][KS + 1];
+    __shared__ double Ss[KS][64];
+    __shared__ double cred[16][64][2];
+    __shared__ int last_flag;
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 64;
+    const int col0 = blockIdx.y * 64;
+    double acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < n; k0 += KS) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + NT * u;
+            const int r = e / KS, kk = e % KS;
+            const int64_t gi = row0 + r, gk = k0 + kk;
+            Js[r][kk] = (gi < n && gk < n) ? J(gi, gk) : 0.0;
+            const int sk = e / 64, sc = e % 64;
+            const int64_t hk = k0 + sk;
+            const int hc = col0 + sc;
+            Ss[sk][sc] = (hk < n && hc < R) ? static_cast<double>(S[hk * R + hc]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KS; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = Js[ty * 4 + q][kk];
+                b[q] = Ss[kk][tx * 4 + q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+        }
+        __syncthreads();
+    }
+    double v[4][2] = {};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int64_t i = row0 + ty * 4 + p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = col0 + tx * 4 + q;
+            if (i < n && c < R) {
+                const double si = static_cast<double>(S[i * R + c]);
+                v[q][0] = dadd(v[q][0], dmul(si, acc[p][q]));
+                if (FIELD) v[q][1] = dadd(v[q][1], dmul(static_cast<double>(h[i]), si));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        cred[ty][tx * 4 + q][0] = v[q][0];
+        cred[ty][tx * 4 + q][1] = v[q][1];
+    }
+    __syncthreads();
+    if (tid < 64) {                             // wave 0: the wave that releases below
+        double* pp = partials + (static_cast<size_t>(blockIdx.x) * Rp + col0 + tid) * 2;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            double sm = 0.0;
+            for (int t = 0; t < 16; ++t) sm = dadd(sm, cred[t][tid][m]);
+            store_agent(pp + m, sm);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) last_flag = arrive_last(tickets + blockIdx.y, gridDim.x) ? 1 : 0;
+    __syncthreads();
+    if (!last_flag) return;
+    if (tid < 2 * 64) {
+        const int cl = tid & 63, m = tid >> 6;
+        cred[0][cl][m] = column_partial_sum<2>(partials, Rp, col0 + cl, m, gridDim.x);
+    }
+    __syncthreads();
+    if (tid < 64 && col0 + tid < R) E[col0 + tid] = dsub(dmul(-0.5, cred[0][tid][0]), cred[0][tid][1]);
+    if (tid == 0) reset_ticket(tickets + blockIdx.y);
+}
+
 template <typename HT, bool FIELD, typename JS>
 __global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, JS J,
                                                           const HT* __restrict__ h,
@@ -375,6 +466,24 @@ hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid, hi
 hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
                                double* partials, unsigned int* ticket, int grid, double* E,
                                hipStream_t s) {
+    if (R >= kTiledEnergyMinR) {
+        // partials: (row tiles) x (R rounded up to 64) x 2 doubles
+        const int Rp = (R + 63) / 64 * 64;
+        const dim3 tg(static_cast<unsigned>((A.n + 63) / 64), static_cast<unsigned>(Rp / 64));
+        DOCH_WITH_JSRC(A, {
+            using JS = std::decay_t<decltype(js)>;
+            if (A.h == nullptr)
+                hipLaunchKernelGGL((dense_energy_tiled_kernel<double, false, JS>), tg, dim3(NT), 0, s, A.n, js,
+                                   static_cast<const double*>(nullptr), s_spins, R, Rp, partials, ticket, E);
+            else if (A.ht == ISING_F64)
+                hipLaunchKernelGGL((dense_energy_tiled_kernel<double, true, JS>), tg, dim3(NT), 0, s, A.n, js,
+                                   static_cast<const double*>(A.h), s_spins, R, Rp, partials, ticket, E);
+            else
+                hipLaunchKernelGGL((dense_energy_tiled_kernel<float, true, JS>), tg, dim3(NT), 0, s, A.n, js,
+                                   static_cast<const float*>(A.h), s_spins, R, Rp, partials, ticket, E);
+        });
+        return hipGetLastError();
+    }
     DOCH_WITH_JSRC(A, {
         using JS = std::decay_t<decltype(js)>;
         if (A.h == nullptr)

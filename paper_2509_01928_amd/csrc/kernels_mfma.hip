@@ -7,12 +7,13 @@
 // representable in BF16 and in FP8 (e4m3, largest finite 448).
 //
 // One launch per iteration: a workgroup owns a 64 x 64 tile of Z (64 rows,
-// 64 restarts), four wavefronts each a 32 x 32 MFMA accumulator.  The
-// operands are staged through LDS in 128-byte rows (64 BF16 or 128 FP8 along
-// k) padded to 144 bytes so the MFMA fragment reads of 32 rows hit distinct
-// banks; the next stage is fetched into registers while the current one is
-// multiplied.  J sits in a BF16 copy, or an FP8 copy with one FP32 scale per
-// row (J_ij ~ s_i q_ij, s_i = max_j |J_ij| / 448).  The restart block sits as
+// 64 restarts); each of its four wavefronts computes the whole tile over a
+// quarter of the k range as 2 x 2 independent 32 x 32 MFMA accumulators,
+// fed straight from global memory (a lane's operand fragment is 8
+// consecutive k of one row, so each load is whole and the rows' cache lines
+// are reused over the following k-steps).  J sits in a BF16 copy, or an FP8
+// copy with one FP32 scale per row (J_ij ~ s_i q_ij, s_i = max_j |J_ij| /
+// 448).  The restart block sits as
 // an FP32 master (n x R) plus a low-precision transposed copy (R x n) that
 // feeds the next product.  In FP8 that copy carries one FP32 scale per
 // restart, c_j, with |u_ij| <= 448 c_j: exact at the start (column maximum)
@@ -20,9 +21,10 @@
 // cbrt((rho_q + alpha) M) for |u| <= M, where rho_q is the largest absolute
 // row sum of the quantised J.  The bound tends to sqrt(rho_q + alpha), so
 // large starting points (u = sqrt(beta) x is large when beta is) never reach
-// the format's overflow, and later steps keep its full relative precision.  The epilogue applies the update in FP64, stores
-// both copies and adds the restart's FP64 partial sums; the last workgroup
-// closes the iteration for every restart (H, r, freezing at r < eps).
+// the format's overflow, and later steps keep its full relative precision.
+// The epilogue applies the update in FP64, stores both copies and adds the
+// restart's FP64 partial sums; the last workgroup of each column block closes
+// the iteration for its restarts (H, r, freezing at r < eps).
 #include "device_common.h"
 #include "ising_internal.h"
 
@@ -34,16 +36,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int MT = 256;        // threads per workgroup
-constexpr int ROWB = 144;      // staged row: 128 bytes of k plus 16 bytes of pad
 
 template <int PREC> struct Prec;
 template <> struct Prec<0> {   // BF16
     using T = __bf16;
-    static constexpr int KT = 64;
 };
 template <> struct Prec<1> {   // FP8 e4m3 (OCP)
     using T = uint8_t;
-    static constexpr int KT = 128;
 };
 
 constexpr float kFp8Max = 448.0f;
@@ -78,49 +77,32 @@ __device__ __forceinline__ typename Prec<PREC>::T to_lowp(float f) {
     else return to_fp8(f);
 }
 
-// One MFMA step on fragments read from the staged tiles.  a_row / b_row
-// point at this lane's staged row; koff is the element offset along k.
+// A lane's operand fragment of one 32 x 32 x 16 MFMA: 8 consecutive k of one
+// row (16 bytes of BF16, 8 bytes of FP8).
+template <int PREC> struct Frag;
+template <> struct Frag<0> { typedef bf16x8 type; };
+template <> struct Frag<1> { typedef long type; };
+
 template <int PREC>
-__device__ __forceinline__ f32x16 mfma_step(const char* a_row, const char* b_row, int koff, f32x16 c) {
-    if constexpr (PREC == 0) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(a_row + 2 * koff);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(b_row + 2 * koff);
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    } else {
-        const long a = *reinterpret_cast<const long*>(a_row + koff);
-        const long b = *reinterpret_cast<const long*>(b_row + koff);
-        return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
-    }
+__device__ __forceinline__ f32x16 mfma_frag(typename Frag<PREC>::type a, typename Frag<PREC>::type b, f32x16 c) {
+    if constexpr (PREC == 0) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
 }
 
-// Last workgroup of a column block (64 restarts): reduce the K per-row-tile
-// partials of each restart in row-tile order.  Thread (q, c) owns quantity q
-// of restart c; its loads are issued in batches so the latency is paid once
-// per batch, not once per row tile.
-template <int K>
-__device__ __forceinline__ double column_partial_sum(const double* __restrict__ partials, int Rp,
-                                                     int c, int q, int tiles) {
-    constexpr int B = 16;
-    double s = 0.0;
-    for (int t0 = 0; t0 < tiles; t0 += B) {
-        double v[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b)
-            v[b] = t0 + b < tiles ? load_agent(partials + (static_cast<size_t>(t0 + b) * Rp + c) * K + q) : 0.0;
-#pragma unroll
-        for (int b = 0; b < B; ++b) s = dadd(s, v[b]);
-    }
-    return s;
-}
 
 // One DOCH iteration for 64 rows x 64 restarts per workgroup.
-//   main loop   the full k range in 128-byte stages (64 BF16 or 128 FP8 per
-//               row): PF stages in flight in registers, two LDS buffers, one
-//               barrier per stage; a column block whose restarts have all
-//               stopped skips it
-//   epilogue    FP64 update of the 16 entries each lane holds, FP32 master
-//               store, the low-precision copy transposed through LDS and
-//               written in whole rows, per-restart partial sums
+//   main loop   the k range in stages of 256 bytes per row (128 BF16 or 256
+//               FP8 k), loaded as whole cache lines into registers two
+//               stages ahead and staged through two LDS buffers, one barrier
+//               per stage; each wavefront computes the whole 64 x 64 tile as
+//               2 x 2 independent 32 x 32 accumulators over every fourth
+//               16-deep k-step of a stage.  A column block whose restarts
+//               have all stopped skips it.
+//   reduction   the four partial tiles meet in LDS; wavefront w adds the
+//               four copies of sub-tile w in wavefront order
+//   epilogue    FP64 update of the 16 entries each lane then holds, FP32
+//               master store, the low-precision copy transposed through LDS
+//               and written in whole rows, per-restart partial sums
 //   finish      the last workgroup of each column block closes the
 //               iteration of its 64 restarts (H, r, stopping)
 template <int PREC>
@@ -132,13 +114,16 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     double alpha, double beta, double eps, int R, int64_t k, double* __restrict__ partials,
     unsigned int* ticket, double* __restrict__ log, RestartState* __restrict__ state) {
     using T = typename Prec<PREC>::T;
-    constexpr int KT = Prec<PREC>::KT;
-    constexpr int PF = 4;                       // stages in flight
-    static_assert(PF % 2 == 0, "LDS buffer of a stage is its ring slot's parity");
-    __shared__ __attribute__((aligned(16))) char sA[2][64 * ROWB];
-    __shared__ __attribute__((aligned(16))) char sB[2][64 * ROWB];
+    // two stage buffers (J rows, then restart rows; 64 rows of SROW bytes
+    // each), reused for the four wavefronts' partial tiles ([wave][sub-tile]
+    // [v][lane] floats) and then for the transposed low-precision copy
+    constexpr int SROW = 272;                   // 256 bytes of k plus 16 of pad
+    constexpr int SBYTES = 2 * 2 * 64 * SROW > 4 * 4 * 16 * 64 * 4 ? 2 * 2 * 64 * SROW : 4 * 4 * 16 * 64 * 4;
+    __shared__ __attribute__((aligned(16))) char sstage[SBYTES];
     __shared__ double red[2][64][4];
     __shared__ int last_flag;
+    float* const sred = reinterpret_cast<float*>(sstage);
+    char* const sA0 = sstage;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -149,61 +134,93 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     const bool block_live =
         __syncthreads_or(tid < 64 && mycol < R && !state[mycol < R ? mycol : 0].done) != 0;
 
-    f32x16 acc = {};
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
     if (block_live) {
-        // thread loads 16-byte chunks c = tid, tid + 256 of each 64 x 128-byte
-        // stage (row c / 8, chunk c % 8) of J and of the restart copy
+        // stage st: bytes [256 st, 256 st + 256) of each of the 64 rows of J
+        // and of the restart copy; thread loads 16-byte chunks c = tid + 256 u
+        // (row c / 16, chunk c % 16), so 16 consecutive lanes read a row's
+        // two whole cache lines
+        constexpr int SPR = 256;                // bytes per row per stage
+        constexpr int KPS = SPR / static_cast<int>(sizeof(T));   // k per stage
         const char* gA = reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * np * sizeof(T);
         const char* gB = reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * np * sizeof(T);
         const size_t gstride = static_cast<size_t>(np) * sizeof(T);
-        size_t goff[2];
-        int soff[2];
+        size_t goff[4];
+        int soff[4];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int c = tid + MT * u;
-            goff[u] = (c >> 3) * gstride + (c & 7) * 16;
-            soff[u] = (c >> 3) * ROWB + (c & 7) * 16;
+            goff[u] = (c >> 4) * gstride + (c & 15) * 16;
+            soff[u] = (c >> 4) * SROW + (c & 15) * 16;
         }
-        i32x4 ring[PF][4];
-        auto fetch = [&](i32x4 (&r)[4], int st) {
-            const size_t kb = static_cast<size_t>(st) * 128;
+        i32x4 ring[2][8];
+        auto fetch = [&](i32x4 (&r)[8], int st) {
+            const size_t kb = static_cast<size_t>(st) * SPR;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 r[u] = *reinterpret_cast<const i32x4*>(gA + goff[u] + kb);
-                r[2 + u] = *reinterpret_cast<const i32x4*>(gB + goff[u] + kb);
+                r[4 + u] = *reinterpret_cast<const i32x4*>(gB + goff[u] + kb);
             }
         };
-        const int nst = np / KT;
-        const char* a_base = &sA[0][0] + (wr * 32 + (lane & 31)) * ROWB;
-        const char* b_base = &sB[0][0] + (wc * 32 + (lane & 31)) * ROWB;
-        const int khalf = (lane >> 5) * 8;      // this lane's 8 consecutive k of a 16-deep step
+        const int nst = np / KPS;
+        // this wavefront's k-steps of a stage: wave, wave + 4, ... (16 k each)
+        const int khalf = (lane >> 5) * 8;
+        fetch(ring[0], 0);
+        if (nst > 1) fetch(ring[1], 1);
+        for (int s0 = 0; s0 < nst; s0 += 2) {
 #pragma unroll
-        for (int p = 0; p < PF; ++p)
-            if (p < nst) fetch(ring[p], p);
-        for (int s0 = 0; s0 < nst; s0 += PF) {
-#pragma unroll
-            for (int p = 0; p < PF; ++p) {
+            for (int p = 0; p < 2; ++p) {
                 const int st = s0 + p;
                 if (st < nst) {
-                    constexpr int kBuf = 64 * ROWB;
-                    char* A = &sA[p & 1][0];
-                    char* B = &sB[p & 1][0];
+                    char* A = sstage + p * 2 * 64 * SROW;
+                    char* B = A + 64 * SROW;
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
+                    for (int u = 0; u < 4; ++u) {
                         *reinterpret_cast<i32x4*>(A + soff[u]) = ring[p][u];
-                        *reinterpret_cast<i32x4*>(B + soff[u]) = ring[p][2 + u];
+                        *reinterpret_cast<i32x4*>(B + soff[u]) = ring[p][4 + u];
                     }
-                    if (st + PF < nst) fetch(ring[p], st + PF);
+                    if (st + 2 < nst) fetch(ring[p], st + 2);
                     __syncthreads();
-                    const char* a_row = a_base + (p & 1) * kBuf;
-                    const char* b_row = b_base + (p & 1) * kBuf;
 #pragma unroll
-                    for (int kk = 0; kk < KT; kk += 16) acc = mfma_step<PREC>(a_row, b_row, kk + khalf, acc);
+                    for (int ks = wave; ks < KPS / 16; ks += 4) {
+                        const int kb = (ks * 16 + khalf) * static_cast<int>(sizeof(T));
+                        using F = typename Frag<PREC>::type;
+                        const F a0 = *reinterpret_cast<const F*>(A + (lane & 31) * SROW + kb);
+                        const F a1 = *reinterpret_cast<const F*>(A + (32 + (lane & 31)) * SROW + kb);
+                        const F b0 = *reinterpret_cast<const F*>(B + (lane & 31) * SROW + kb);
+                        const F b1 = *reinterpret_cast<const F*>(B + (32 + (lane & 31)) * SROW + kb);
+                        acc[0][0] = mfma_frag<PREC>(a0, b0, acc[0][0]);
+                        acc[0][1] = mfma_frag<PREC>(a0, b1, acc[0][1]);
+                        acc[1][0] = mfma_frag<PREC>(a1, b0, acc[1][0]);
+                        acc[1][1] = mfma_frag<PREC>(a1, b1, acc[1][1]);
+                    }
                 }
             }
         }
     }
     __syncthreads();                            // the stage buffers are reused below
+    // ---- reduction of the four partial tiles: wavefront w keeps sub-tile
+    // (wr, wc) = (w / 2, w % 2), summed over wavefronts 0..3 in order
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) sred[((wave * 4 + a * 2 + b) * 16 + v) * 64 + lane] = acc[a][b][v];
+    __syncthreads();
+    f32x16 tile;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        float t = sred[((0 * 4 + wave) * 16 + v) * 64 + lane];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) t += sred[((w * 4 + wave) * 16 + v) * 64 + lane];
+        tile[v] = t;
+    }
+    __syncthreads();                            // sred is reused below
 
     // ---- epilogue: lane holds column j, rows 8*(v/4) + 4*(lane/32) + v%4
     const int jl = wc * 32 + (lane & 31);
@@ -218,7 +235,7 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         if (blockIdx.x == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
     }
     // transposed low-precision tile: row jl holds rows row0 .. row0+63 of restart j
-    T* tileT = reinterpret_cast<T*>(&sA[0][0]);
+    T* tileT = reinterpret_cast<T*>(sA0);
     constexpr int TROW = 64 + 16 / static_cast<int>(sizeof(T));   // padded row, in elements
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         const int i = row0 + il;
         const size_t ij = static_cast<size_t>(i) * Rp + j;
         const double uo = static_cast<double>(U_old[ij]);
-        double z = static_cast<double>(acc[v]);
+        double z = static_cast<double>(tile[v]);
         if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
         float un = static_cast<float>(uo);
         if (live) {

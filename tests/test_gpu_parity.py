@@ -248,6 +248,42 @@ def test_energy_field_and_dense_gaussian():
         assert E[r] == pytest.approx(orc.energy_dense(J, S[:, r]), rel=1e-12)
 
 
+def test_energy_dense_many_restarts_tiled():
+    """eq:IsingModel for 70 restarts at once (the tiled J S path: two column
+    blocks, the second ragged; 333 rows, the last tile ragged), with and
+    without a field, and on procedural couplings."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    n, R = 333, 70
+    J = gen.sk_dense(n, 96)
+    rng = np.random.default_rng(97)
+    h = rng.normal(0.0, 0.3, n)
+    S = np.where(rng.random((n, R)) < 0.5, 1, -1).astype(np.int8)
+    for hh in (None, h):
+        P = GpuProblem(J=J, h=hh)
+        try:
+            E, _ = P.energy(S)
+        finally:
+            P.close()
+        for r in range(R):
+            assert E[r] == pytest.approx(orc.energy_dense(J, S[:, r], hh), rel=1e-12, abs=1e-9), r
+    seed = 7.0
+    i = np.arange(n, dtype=np.float64)
+    Jp = np.sin(np.outer(i, i) + seed)
+    np.fill_diagonal(Jp, 0.0)
+    ctx = Lb.ising_create_procedural(n, 1, seed)
+    try:
+        sd = torch.from_numpy(S).to("cuda:0")
+        Ed = torch.empty(R, dtype=torch.float64, device="cuda:0")
+        Lb.ising_energy(ctx, sd, R, Ed)
+        torch.cuda.synchronize()
+        E = Ed.cpu().numpy()
+    finally:
+        Lb.ising_destroy(ctx)
+    for r in range(R):
+        assert E[r] == pytest.approx(orc.energy_dense(Jp, S[:, r]), rel=1e-11, abs=1e-9), r
+
+
 # ------------------------------------------------------ setup (eq:alphabeta)
 def test_default_params_wigner_matches_oracle():
     import paper_2509_01928_amd as Lb
