@@ -54,7 +54,8 @@ typedef enum {
     ISING_F32 = 1,
     ISING_BF16 = 2,
     ISING_FP8_E4M3 = 3,
-    ISING_I32 = 4
+    ISING_I32 = 4,
+    ISING_I16 = 5      /* 16-bit signed integer CSR values (the 9-bit workload) */
 } ising_dtype;
 
 /* Solver parameters.  alpha and beta are the attractor parameters of
@@ -102,7 +103,9 @@ typedef struct {
  *   nnz          stored entries, 0 <= nnz < 2^31
  *   row_ptr_dev  int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_dev      int32[nnz], 0 <= col < n, ascending within each row
- *   val_dev      nnz values of type vt (ISING_F32 or ISING_F64)
+ *   val_dev      nnz values of type vt: ISING_F32, ISING_F64, or ISING_I16
+ *                for integer couplings (6 bytes per stored entry with the
+ *                index; the 9-bit workload of Supp. Alg. S5)
  *   h_dev        NULL (no field) or n values of type ht (ISING_F32 / F64)
  * Errors: ISING_E_INVALID_ARG for a malformed CSR (checked on the device),
  * ISING_E_NONZERO_DIAG if a stored diagonal entry is nonzero.
@@ -155,6 +158,25 @@ ising_status ising_default_params(ising_ctx* ctx, double eta, int32_t method,
                                   void* stream, ising_params* out,
                                   double* lambda_out);
 
+/* Supp. Note 6: choose eta by short probe runs.  lambda_hat and the row-sum
+ * bound are estimated once as by ising_default_params (`method`); for each
+ * eta_k, alpha = eta_k lambda_hat and beta follow eq:alphabeta, DOCH runs
+ * `probe_iters` iterations from x0_dev (as for ising_solve with R = 1), the
+ * iterate is rounded and its Ising energy (eq:IsingModel) taken.  The eta
+ * with the lowest energy wins (the first one on a tie).
+ *   count          1..64 candidates, etas_host[k] in (0, 2]
+ *   probe_iters    1..1000 (the paper uses 5-10, 1-3 for ultra-large graphs)
+ *   best_out       the winner's ising_params (eps 0, algo 0, q 5, FP64 iterate)
+ *   best_eta_out   NULL or the winning eta
+ *   energies_host  NULL or count doubles: every probe's energy
+ * Synchronous.  Overwrites the log of the last solve.  Errors: as
+ * ising_default_params and ising_solve; ISING_E_UNSUPPORTED on a batch
+ * context. */
+ising_status ising_tune_eta(ising_ctx* ctx, const double* x0_dev, int32_t count,
+                            const double* etas_host, int64_t probe_iters, int32_t method,
+                            void* stream, ising_params* best_out, double* best_eta_out,
+                            double* energies_host);
+
 /* ------------------------------------------------------------------ solve
  * Run `iters` iterations of DOCH (Alg. 1) -- or ADOCH (Alg. 2) when
  * params->algo == 1 -- from R start vectors at once, then round.
@@ -203,6 +225,26 @@ ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first,
  * Asynchronous on `stream`. */
 ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
                           double* E_dev, int64_t* E_int_dev, void* stream);
+
+/* MAX-CUT value of each spin vector (Supp. Note 5), for the graph whose edge
+ * weights are the negated stored couplings, w_ij = -J_ij:
+ *     cut(s) = sum over i < j with s_i != s_j of w_ij
+ *            = -S_J / 4 - E(s) / 2,     S_J = sum of all stored J_ij,
+ * with E(s) of eq:IsingModel.  The paper builds J = -W/2 from the weighted
+ * adjacency matrix W; any positive multiple of -W gives the same DOCH
+ * iterates under ising_default_params (alpha and beta scale with J), so a
+ * graph with integer weights can be stored as J = -W (ISING_I16 fits the
+ * 9-bit workload) and its cut read here in the weights' units.
+ *   s_dev        int8[n x R] spins (+-1), restart-interleaved as for ising_energy
+ *   cut_dev      NULL or R doubles
+ *   cut_int_dev  NULL or R int64, exact; needs integer couplings (CSR)
+ * Errors: ISING_E_UNSUPPORTED for a context with a field (the cut is defined
+ * for h = 0), a batch context, or cut_int_dev on non-integer or dense
+ * couplings; ISING_E_INVALID_ARG for NULL s_dev, R out of 1..1024 or no
+ * output.  Asynchronous on `stream` except for a statistics pass that
+ * synchronises it. */
+ising_status ising_cut(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* cut_dev,
+                       int64_t* cut_int_dev, void* stream);
 
 /* ------------------------------------------------- dense low precision
  * DOCH on a dense context for R restarts at once with J x computed on the

@@ -13,11 +13,11 @@ import os
 from typing import Optional
 
 __all__ = [
-    "ISING_OK", "ISING_F64", "ISING_F32", "ISING_BF16", "ISING_FP8_E4M3", "ISING_I32",
+    "ISING_OK", "ISING_F64", "ISING_F32", "ISING_BF16", "ISING_FP8_E4M3", "ISING_I32", "ISING_I16",
     "IsingError", "ising_params", "ising_stats", "ising_info", "lib", "LIB_PATH",
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
-    "ising_energy", "ising_set_geometry", "ising_autotune", "ising_create_batch",
+    "ising_energy", "ising_cut", "ising_tune_eta", "ising_set_geometry", "ising_autotune", "ising_create_batch",
     "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_solve_lowp", "ising_get_accept_log", "ising_create_procedural",
     "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
@@ -40,6 +40,7 @@ ISING_F32 = 1
 ISING_BF16 = 2
 ISING_FP8_E4M3 = 3
 ISING_I32 = 4
+ISING_I16 = 5
 
 
 class ising_params(ctypes.Structure):
@@ -93,6 +94,8 @@ _SIGS = {
     "ising_solve": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
     "ising_get_log": (_st, [_p, _i32, _i64, _i64, _p, _p, _p]),
     "ising_energy": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "ising_cut": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "ising_tune_eta": (_st, [_p, _p, _i32, _p, _i64, _i32, _p, ctypes.POINTER(ising_params), _p, _p]),
     "ising_set_geometry": (_st, [_p, _i32, _i32]),
     "ising_autotune": (_st, [_p, _p, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
     "ising_create_batch": (_st, [_i32, _p, _p, _p, _p, _i32, _p, ctypes.POINTER(_p)]),
@@ -217,6 +220,27 @@ def ising_get_log(ctx, restart, first, count, stream=None):
 def ising_energy(ctx, s, R, E=None, E_int=None, stream=None):
     _check(lib.ising_energy(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
                             stream if stream is not None else current_stream()), "ising_energy")
+
+
+def ising_tune_eta(ctx, x0, etas, probe_iters, method=0, stream=None):
+    """Returns (params of the best eta, best eta, numpy array of probe energies)."""
+    import numpy as np
+    etas = np.ascontiguousarray(etas, dtype=np.float64)
+    energies = np.empty(etas.shape[0], dtype=np.float64)
+    best = ising_params()
+    best_eta = ctypes.c_double()
+    _check(lib.ising_tune_eta(ctx, ptr(x0), int(etas.shape[0]), etas.ctypes.data, int(probe_iters),
+                              int(method), stream if stream is not None else current_stream(),
+                              ctypes.byref(best), ctypes.byref(best_eta), energies.ctypes.data),
+           "ising_tune_eta")
+    return best, best_eta.value, energies
+
+
+def ising_cut(ctx, s, R, cut=None, cut_int=None, stream=None):
+    """MAX-CUT value of each spin vector for weights w_ij = -J_ij."""
+    _check(lib.ising_cut(ctx, ptr(s), int(R), ptr(cut), ptr(cut_int),
+                         stream if stream is not None else current_stream()),
+           "ising_cut")
 
 
 def ising_set_geometry(ctx, geometry, wg_per_cu=0) -> None:

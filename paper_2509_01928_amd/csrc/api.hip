@@ -55,6 +55,7 @@ size_t dtype_size(int t) {
         case ISING_BF16: return 2;
         case ISING_FP8_E4M3: return 1;
         case ISING_I32: return 4;
+        case ISING_I16: return 2;
         default: return 0;
     }
 }
@@ -191,6 +192,8 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->jq[1]);
     dev_free(c->rscale);
     dev_free(c->rowabs);
+    dev_free(c->cut_tmp);
+    dev_free(c->tune_s);
     dev_free(c->lp_cs);
     dev_free(c->lp_colmax);
     dev_free(c->lp_u[0]);
@@ -384,7 +387,8 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
     if (nnz < 0 || nnz >= 2147483647LL) return fail(ISING_E_INVALID_ARG, "nnz=%lld out of range", (long long)nnz);
     if (!row_ptr_dev) return fail(ISING_E_INVALID_ARG, "row_ptr is NULL");
     if (nnz > 0 && (!col_dev || !val_dev)) return fail(ISING_E_INVALID_ARG, "col/val NULL with nnz > 0");
-    if (!float_dtype(vt)) return fail(ISING_E_INVALID_ARG, "CSR values must be ISING_F32 or ISING_F64");
+    if (!float_dtype(vt) && vt != ISING_I16)
+        return fail(ISING_E_INVALID_ARG, "CSR values must be ISING_F32, ISING_F64 or ISING_I16");
     hipStream_t s = static_cast<hipStream_t>(stream);
     ising_ctx* c = new ising_ctx();
     ising_status st = ISING_OK;
@@ -625,6 +629,8 @@ ising_status ising_default_params(ising_ctx* ctx, double eta, int32_t method, vo
         }
         lambda = mu - c;
     }
+    ctx->last_lambda = lambda;
+    ctx->last_rowsum = ms.rowsum_max;
     ising_params p;
     p.alpha = eta * lambda;
     p.beta = std::pow(np, 1.5) * (p.alpha + ms.rowsum_max);
@@ -834,6 +840,7 @@ ising_status ising_create_batch(int32_t count, const int64_t* n_host, const int3
     }
     if (total >= 2147483647LL) return fail(ISING_E_INVALID_ARG, "total rows out of range");
     if (!row_ptr_dev) return fail(ISING_E_INVALID_ARG, "row_ptr is NULL");
+    if (!float_dtype(vt)) return fail(ISING_E_INVALID_ARG, "batch values must be ISING_F32 or ISING_F64");
     hipStream_t s = static_cast<hipStream_t>(stream);
     int32_t nnz32 = 0;
     HIP_OK(hipMemcpyAsync(&nnz32, row_ptr_dev + total, sizeof(int32_t), hipMemcpyDeviceToHost, s), "read nnz");
@@ -1245,6 +1252,85 @@ ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double
         HIP_OK(doch::launch_csr_energy(csr_view(ctx), s_dev, R, sc.partials, sc.tickets, grid, E_dev, E_int_dev, s),
                "energy");
     }
+    return ISING_OK;
+}
+
+
+ising_status ising_cut(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* cut_dev, int64_t* cut_int_dev,
+                       void* stream) {
+    if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
+    if (!s_dev) return fail(ISING_E_INVALID_ARG, "s is NULL");
+    if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
+    if (!cut_dev && !cut_int_dev) return fail(ISING_E_INVALID_ARG, "no output requested");
+    if (ctx->has_field) return fail(ISING_E_UNSUPPORTED, "the cut is defined for h = 0");
+    if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "cuts of batch contexts are not provided");
+    if (cut_int_dev && (!ctx->integer_J || ctx->dense))
+        return fail(ISING_E_UNSUPPORTED, "the exact cut needs integer CSR couplings");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->cut_tmp) HIP_OK(dev_alloc(&ctx->cut_tmp, 2 * kMaxR * sizeof(double)), "hipMalloc(cut)");
+    double* E = ctx->cut_tmp;
+    int64_t* Ei = reinterpret_cast<int64_t*>(ctx->cut_tmp + kMaxR);
+    ising_status st = ising_energy(ctx, s_dev, R, E, cut_int_dev ? Ei : nullptr, stream);
+    if (st != ISING_OK) return st;
+    // S_J: pass 0 of the statistics kernels (sum of the stored off-diagonal couplings)
+    const int grid = 1024;
+    Scratch sc;
+    st = ensure_scratch(ctx, static_cast<size_t>(2048) * 4, &sc);
+    if (st != ISING_OK) return st;
+    if (ctx->dense)
+        HIP_OK(doch::launch_dense_stats(dense_view(ctx), 0.0, 0, sc.partials, sc.tickets, grid, sc.stats, s), "stats");
+    else
+        HIP_OK(doch::launch_csr_stats(csr_view(ctx), 0.0, 0, sc.partials, sc.tickets, grid, sc.stats, s), "stats");
+    HIP_OK(doch::launch_cut(E, cut_int_dev ? Ei : nullptr, sc.stats, R, cut_dev, cut_int_dev, s), "cut");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    return ISING_OK;
+}
+
+
+ising_status ising_tune_eta(ising_ctx* ctx, const double* x0_dev, int32_t count, const double* etas_host,
+                            int64_t probe_iters, int32_t method, void* stream, ising_params* best_out,
+                            double* best_eta_out, double* energies_host) {
+    if (!ctx || !x0_dev || !etas_host || !best_out) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "use ising_default_params_batch on a batch context");
+    if (count < 1 || count > 64) return fail(ISING_E_INVALID_ARG, "count must be 1..64");
+    if (probe_iters < 1 || probe_iters > 1000) return fail(ISING_E_INVALID_ARG, "probe_iters must be 1..1000");
+    for (int k = 0; k < count; ++k)
+        if (!(etas_host[k] > 0.0) || !(etas_host[k] <= 2.0))
+            return fail(ISING_E_INVALID_ARG, "eta[%d] must be in (0, 2]", k);
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // lambda_hat and the row-sum bound once (eq:alphabeta), then each eta
+    ising_params p1;
+    ising_status st = ising_default_params(ctx, 1.0, method, stream, &p1, nullptr);
+    if (st != ISING_OK) return st;
+    const double lambda = ctx->last_lambda, rowsum = ctx->last_rowsum;
+    const double np = static_cast<double>(ctx->np);
+    if (!ctx->tune_s) HIP_OK(dev_alloc(&ctx->tune_s, static_cast<size_t>(ctx->n)), "hipMalloc(spins)");
+    if (!ctx->cut_tmp) HIP_OK(dev_alloc(&ctx->cut_tmp, 2 * kMaxR * sizeof(double)), "hipMalloc(energies)");
+    int best = -1;
+    double best_E = 0.0;
+    ising_params best_p = p1;
+    for (int k = 0; k < count; ++k) {
+        ising_params p = p1;
+        p.alpha = etas_host[k] * lambda;
+        p.beta = std::pow(np, 1.5) * (p.alpha + rowsum);
+        st = ising_solve(ctx, x0_dev, 1, probe_iters, &p, nullptr, ctx->tune_s, nullptr, stream);
+        if (st != ISING_OK) return st;
+        st = ising_energy(ctx, ctx->tune_s, 1, ctx->cut_tmp, nullptr, stream);
+        if (st != ISING_OK) return st;
+        double E = 0.0;
+        HIP_OK(hipMemcpyAsync(&E, ctx->cut_tmp, sizeof(double), hipMemcpyDeviceToHost, s), "copy energy");
+        HIP_OK(hipStreamSynchronize(s), "sync");
+        if (energies_host) energies_host[k] = E;
+        if (best < 0 || E < best_E) {
+            best = k;
+            best_E = E;
+            best_p = p;
+        }
+    }
+    *best_out = best_p;
+    if (best_eta_out) *best_eta_out = etas_host[best];
     return ISING_OK;
 }
 

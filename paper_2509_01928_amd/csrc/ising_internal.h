@@ -210,6 +210,10 @@ struct ising_ctx {
     float* rscale = nullptr;             // FP8 per-row scales
     double* rowabs = nullptr;            // FP8: s_i sum_j |q_ij| per row
     double lp_rho_q = 0.0;               // FP8: max_i rowabs[i]
+    double* cut_tmp = nullptr;           // ising_cut: R energies, then R int64 energies
+    double last_lambda = 0.0;            // lambda_hat and max row sum of the last
+    double last_rowsum = 0.0;            // ising_default_params call
+    int8_t* tune_s = nullptr;            // ising_tune_eta: rounded probe spins
     float* lp_cs = nullptr;              // FP8: restart scales, two buffers of kMaxR
     unsigned int* lp_colmax = nullptr;   // FP8: start column maxima (float bits)
     int lp_np = 0;                       // padded order (multiple of 256)
@@ -315,6 +319,8 @@ hipError_t launch_adoch_finish(const double* b0, const double* b1, const double*
                                double* x_out, int8_t* s_out, hipStream_t s);
 
 // ---- launchers (kernels_common.hip) ----
+hipError_t launch_cut(const double* E, const int64_t* E_int, const MatrixStats* ms, int R, double* cut,
+                      int64_t* cut_int, hipStream_t s);
 hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,
                           hipStream_t s);
 hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket,

@@ -200,7 +200,11 @@ hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, 
 #define DOCH_ADOCH_MV(VT, HT, F)                                                                  \
     hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F>), dim3(grid), dim3(NT), 0, s, A.n, A.rp, A.col, \
                        static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), x, xp, zp, z, a)
-    if (A.vt == ISING_F64) {
+    if (A.vt == ISING_I16) {
+        if (!field) DOCH_ADOCH_MV(int16_t, float, false);
+        else if (A.ht == ISING_F64) DOCH_ADOCH_MV(int16_t, double, true);
+        else DOCH_ADOCH_MV(int16_t, float, true);
+    } else if (A.vt == ISING_F64) {
         if (!field) DOCH_ADOCH_MV(double, double, false);
         else if (A.ht == ISING_F64) DOCH_ADOCH_MV(double, double, true);
         else DOCH_ADOCH_MV(double, float, true);

@@ -82,7 +82,25 @@ __global__ __launch_bounds__(NT) void normalize_kernel(const double* __restrict_
         v[t] = ddiv(w[t], nrm);
 }
 
+// Supp. Note 5 with w = -J: cut = -S_J / 4 - E / 2 (exact in int64 for
+// integer couplings, where S_J + 2 E is a multiple of 4).
+__global__ void cut_kernel(const double* __restrict__ E, const int64_t* __restrict__ E_int,
+                           const MatrixStats* __restrict__ ms, int R, double* __restrict__ cut,
+                           int64_t* __restrict__ cut_int) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double s1 = ms->s1;
+    if (cut) cut[r] = dsub(dmul(-0.25, s1), dmul(0.5, E[r]));
+    if (cut_int) cut_int[r] = -(llround(s1) + 2 * E_int[r]) / 4;
+}
+
 }  // namespace
+
+hipError_t launch_cut(const double* E, const int64_t* E_int, const MatrixStats* ms, int R, double* cut,
+                      int64_t* cut_int, hipStream_t s) {
+    hipLaunchKernelGGL(cut_kernel, dim3((R + 255) / 256), dim3(256), 0, s, E, E_int, ms, R, cut, cut_int);
+    return hipGetLastError();
+}
 
 hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;

@@ -616,7 +616,11 @@ int grid_for_rows(int64_t n) {
 
 #define DOCH_DISPATCH_VT_HT(A, ...)                                               \
     do {                                                                          \
-        if ((A).vt == ISING_F64 && (A).ht == ISING_F64) {                         \
+        if ((A).vt == ISING_I16 && (A).ht == ISING_F64) {                         \
+            using VT = int16_t; using HT = double; __VA_ARGS__;                   \
+        } else if ((A).vt == ISING_I16) {                                         \
+            using VT = int16_t; using HT = float; __VA_ARGS__;                    \
+        } else if ((A).vt == ISING_F64 && (A).ht == ISING_F64) {                  \
             using VT = double; using HT = double; __VA_ARGS__;                    \
         } else if ((A).vt == ISING_F64) {                                         \
             using VT = double; using HT = float; __VA_ARGS__;                     \
@@ -747,6 +751,9 @@ hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s) 
     if (A.vt == ISING_F64)
         hipLaunchKernelGGL(csr_validate_kernel<double>, dim3(grid), dim3(NT), 0, s, A.n, A.nnz,
                            A.rp, A.col, static_cast<const double*>(A.val), flags);
+    else if (A.vt == ISING_I16)
+        hipLaunchKernelGGL(csr_validate_kernel<int16_t>, dim3(grid), dim3(NT), 0, s, A.n, A.nnz,
+                           A.rp, A.col, static_cast<const int16_t*>(A.val), flags);
     else
         hipLaunchKernelGGL(csr_validate_kernel<float>, dim3(grid), dim3(NT), 0, s, A.n, A.nnz,
                            A.rp, A.col, static_cast<const float*>(A.val), flags);
@@ -758,6 +765,9 @@ hipError_t launch_csr_symcheck(const CsrView& A, int32_t* bad, hipStream_t s) {
     if (A.vt == ISING_F64)
         hipLaunchKernelGGL(csr_symcheck_kernel<double>, dim3(grid), dim3(NT), 0, s, A.n, A.rp,
                            A.col, static_cast<const double*>(A.val), bad);
+    else if (A.vt == ISING_I16)
+        hipLaunchKernelGGL(csr_symcheck_kernel<int16_t>, dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, static_cast<const int16_t*>(A.val), bad);
     else
         hipLaunchKernelGGL(csr_symcheck_kernel<float>, dim3(grid), dim3(NT), 0, s, A.n, A.rp,
                            A.col, static_cast<const float*>(A.val), bad);

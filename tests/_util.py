@@ -37,6 +37,9 @@ class GpuProblem:
             if val_dtype == "f32":
                 val = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float32)).to(dev)
                 vt = L.ISING_F32
+            elif val_dtype == "i16":
+                val = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.int16)).to(dev)
+                vt = L.ISING_I16
             else:
                 val = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(dev)
                 vt = L.ISING_F64

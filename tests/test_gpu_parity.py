@@ -517,3 +517,37 @@ def test_procedural_sin_couplings_parity():
     assert_spin_parity(s, tr.x, orc.sign(tr.x), "procedural")
     assert_log_parity(H, r, tr, "procedural")
     assert float(E.cpu()[0]) == pytest.approx(orc.energy_dense(J, s), rel=1e-11)
+
+
+# ------------------------------------------------------ eta tuning (Supp. Note 6)
+@pytest.mark.parametrize("case", ["er", "torus_field"])
+def test_tune_eta_matches_oracle_probes(case):
+    """Short probe runs per eta: every probe energy and the chosen eta agree
+    with the oracle's own probe runs (parameters by eq:alphabeta)."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    if case == "er":
+        A = gen.er_csr(2000, 8.0, 201)
+        x0 = gen.uniform_x0(A.n, 1, 202)[:, 0]
+    else:
+        A = gen.torus_csr(40, 203, h_std=1.0)
+        x0 = gen.uniform_x0(A.n + 1, 1, 204)[:, 0]
+    etas = [0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0]
+    probe = 8
+    B = orc.problem_matrix(A)
+    E_ref = []
+    for eta in etas:
+        a, b, _ = orc.default_params(B, eta)
+        tr = orc.doch(B, x0, a, b, probe)
+        s = orc.spins_with_field(tr.x) if A.h is not None else orc.sign(tr.x)
+        E_ref.append(orc.energy(A, s))
+    P = GpuProblem(A=A)
+    try:
+        xd = torch.from_numpy(x0).to("cuda:0")
+        best, eta, E = Lb.ising_tune_eta(P.ctx, xd, etas, probe, 0)
+    finally:
+        P.close()
+    np.testing.assert_allclose(E, E_ref, rtol=1e-12, atol=1e-9)
+    assert eta == etas[int(np.argmin(E_ref))]
+    a, b, lam = orc.default_params(B, eta)
+    assert best.alpha == pytest.approx(a, rel=1e-9) and best.beta == pytest.approx(b, rel=1e-9)
