@@ -70,10 +70,12 @@ _GEOMETRY_KERNEL = {0: ("csr_step_kernel", "1, 1, false"), 1: ("csr_step_kernel"
                     6: ("csr_step_kernel", "2, 2, true"), 7: ("csr_step_kernel", "4, 2, true")}
 
 
-def step_kernel_name(geometry: int, x_dtype: str) -> str:
+def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False) -> str:
     """Kernel instance timed on the lattice (FP32 couplings and field)."""
     xt = "float" if x_dtype == "f32" else "double"
     name, tail = _GEOMETRY_KERNEL[geometry]
+    if name == "csr_rowlane_kernel":
+        tail += ", 4" if implicit_offsets else ", 0"      # the lattice's rows hold 4 entries
     return f"{name}<{xt}, float, float, true, {tail}>"
 
 
@@ -517,7 +519,8 @@ def main():
     s_out = torch.empty(A.n, dtype=torch.int8, device=dev)
     E = torch.empty(1, dtype=torch.float64, device=dev)
     x_dtype = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
-    log("context created")
+    row_len = L.ising_get_info(ctx).row_len
+    log(f"context created (constant row length {row_len})" if row_len else "context created")
     # launch-shape tuning is setup, outside the timed region
     if args.geometry >= -1:
         L.ising_set_geometry(ctx, args.geometry, args.wg_per_cu)
@@ -528,7 +531,7 @@ def main():
     else:
         p0, _ = L.ising_default_params(ctx, 1.0, 0)
         p0.x_dtype = x_dtype
-        geometry, wg_per_cu, tune_ms = L.ising_autotune(ctx, xd, 10, p0)
+        geometry, wg_per_cu, tune_ms = L.ising_autotune(ctx, xd, 30, p0)
         log(f"autotune: geometry {geometry}, {wg_per_cu} workgroups/CU "
             f"({', '.join(f'{m * 1e3:.0f}' for m in tune_ms)} us/iteration per geometry)")
 
@@ -564,12 +567,16 @@ def main():
 
     n, nnz, np1 = A.n, A.nnz, A.n + 1
     xb = 4 if args.x_dtype == "f32" else 8
-    # algorithmic bytes of one fused iteration: row offsets, column indices and
-    # values once, iterate read once and written once, field once
-    bytes_iter = 4 * (n + 1) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
+    # a constant row length makes the row offsets implicit for the lane-per-row
+    # kernels: they are then not read and not counted
+    implicit = row_len > 0 and geometry in (3, 4)
+    # algorithmic bytes of one fused iteration: row offsets (unless implicit),
+    # column indices and values once, iterate read once and written once,
+    # field once
+    bytes_iter = (0 if implicit else 4 * (n + 1)) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
     achieved = bytes_iter / (per_iter_ms * 1e-3) / 1e9
     workload = f"torus{args.L}"
-    kernel = step_kernel_name(geometry, args.x_dtype)
+    kernel = step_kernel_name(geometry, args.x_dtype, implicit)
     traffic = load_traffic(kernel, f"{workload}_{args.x_dtype}")
     edge_updates = float(nnz) * args.iters * args.steps
     out = {
@@ -594,6 +601,7 @@ def main():
             "x_storage": args.x_dtype, "couplings": "f32 CSR, int32 indices",
             "arithmetic": "f64", "parallelism": "single GPU",
             "kernel_geometry": geometry, "workgroups_per_cu": wg_per_cu,
+            "row_offsets": (f"implicit (every row holds {row_len} entries)" if implicit else "read"),
         },
         "iteration_us": per_iter_ms * 1e3,
         "energy": energy,

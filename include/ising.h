@@ -90,6 +90,10 @@ typedef struct {
     int32_t has_field;
     int32_t integer_J;     /* all couplings are integers (exact int64 energy) */
     int32_t val_dtype;     /* ising_dtype the couplings are stored in        */
+    int32_t row_len;       /* CSR: d if every row holds d entries (row i
+                              starts at d*i; the lane-per-row kernels then
+                              do not read the offsets), else 0             */
+    int32_t reserved;
 } ising_info;
 
 /* ---------------------------------------------------------------- create
@@ -324,14 +328,16 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
  * blocks, 2048-entry spans; 2 = 512-row blocks, 4096-entry spans; 3 and 4 =
  * one row per lane with the whole grid sweeping the rows together, rows of
  * up to one (3) or two (4) aligned 4-entry chunks loaded at once (longer rows
- * take a slower path); 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in
+ * take a slower path; with a constant row length, see ising_info.row_len,
+ * the row offsets are implicit and not read); 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in
  * order from a per-XCD counter; -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
  * workgroups launched per compute unit, 0 = as many as fit.  CSR contexts
  * only.
  *
  * ising_autotune: time `iters` DOCH iterations (params as for ising_solve,
- * from x0_dev with R = 1) for every geometry and workgroups-per-CU setting
- * in {1, 2, 3, 4, all}, and keep the fastest pair for later solves.
+ * from x0_dev with R = 1; best of two timings) for every geometry and
+ * workgroups-per-CU setting in {1, 2, 3, 4, all}, and keep the fastest pair
+ * for later solves.
  * *geometry_out and *wg_per_cu_out (nullable) receive it, ms_per_iter_out
  * (nullable, 8 entries) the best time of each geometry.  Synchronous.
  * Overwrites the log of the last solve. */

@@ -56,6 +56,7 @@ struct CsrView {
     int vt;                 // ISING_F32 or ISING_F64
     const void* h;          // nullptr: no field
     int ht;
+    int row_len;            // d > 0: every row holds d entries, row i starts at d i
 };
 
 struct DenseView {
@@ -211,6 +212,7 @@ struct ising_ctx {
     double* rowabs = nullptr;            // FP8: s_i sum_j |q_ij| per row
     double lp_rho_q = 0.0;               // FP8: max_i rowabs[i]
     double* cut_tmp = nullptr;           // ising_cut: R energies, then R int64 energies
+    int32_t row_len = 0;                 // CSR: constant row length d (rp[i] = d i), else 0
     double last_lambda = 0.0;            // lambda_hat and max row sum of the last
     double last_rowsum = 0.0;            // ising_default_params call
     int8_t* tune_s = nullptr;            // ising_tune_eta: rounded probe spins

@@ -255,10 +255,13 @@ __global__ __launch_bounds__(NT) void csr_step_kernel(
 // faster than giving each XCD its own eighth of the rows, and a row's
 // neighbours one lattice row away are still inside the window when it is
 // gathered.
-template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC>
+// RL: 0 = row offsets read from rp; -1 = every row holds row_len entries
+// (row i starts at row_len i, rp not read); d > 0 = the same with row_len = d
+// known at compile time (d = 4: the 4-neighbour lattice).
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC, int RL>
 __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
     int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-    const VT* __restrict__ val, const HT* __restrict__ h, StepArgs a) {
+    const VT* __restrict__ val, const HT* __restrict__ h, int row_len, StepArgs a) {
     if (a.state->done) return;
     __shared__ double red[kNumPartials * NW];
     const XT* __restrict__ x = static_cast<const XT*>(a.x_old);
@@ -281,8 +284,14 @@ __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
         for (int u = 0; u < U; ++u) {
             const int64_t i = base + u * stride;
             if (i < hi) {
-                s[u] = rp[i];
-                e[u] = rp[i + 1];
+                if (RL != 0) {                  // constant row length: offsets implicit
+                    const int d = RL > 0 ? RL : row_len;
+                    s[u] = static_cast<int>(i * d);
+                    e[u] = s[u] + d;
+                } else {
+                    s[u] = rp[i];
+                    e[u] = rp[i + 1];
+                }
                 xi[u] = x[i];
                 if (FIELD) hv[u] = ld_stream(h + i);
             }
@@ -661,9 +670,9 @@ hipError_t launch_step_t(const CsrView& A, const CsrPlan& plan, const StepArgs& 
     return hipGetLastError();
 }
 
-template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC>
-hipError_t launch_rowlane_t(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
-    auto kern = csr_rowlane_kernel<XT, VT, HT, FIELD, U, MAXC>;
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC, int RL>
+hipError_t launch_rowlane_r(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    auto kern = csr_rowlane_kernel<XT, VT, HT, FIELD, U, MAXC, RL>;
     static int per_cu = 0;
     static int cus = 0;
     if (per_cu == 0) {
@@ -685,8 +694,15 @@ hipError_t launch_rowlane_t(const CsrView& A, const CsrPlan& plan, const StepArg
     if (grid >= 8) grid &= ~static_cast<int64_t>(7);
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NT), 0, s, A.n, A.rp, A.col,
-                       static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), a);
+                       static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), A.row_len, a);
     return hipGetLastError();
+}
+
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC>
+hipError_t launch_rowlane_t(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    if (A.row_len == 4) return launch_rowlane_r<XT, VT, HT, FIELD, U, MAXC, 4>(A, plan, a, s);
+    if (A.row_len > 0) return launch_rowlane_r<XT, VT, HT, FIELD, U, MAXC, -1>(A, plan, a, s);
+    return launch_rowlane_r<XT, VT, HT, FIELD, U, MAXC, 0>(A, plan, a, s);
 }
 
 template <typename XT, typename VT, typename HT, bool FIELD>

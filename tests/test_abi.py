@@ -45,8 +45,29 @@ def test_host_only_calls():
     L.ising_destroy(None)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's structures have the sizes and field offsets the C
+    header gives them (compiled with the host C compiler)."""
+    import subprocess
     import paper_2509_01928_amd as L
-    assert ctypes.sizeof(L.ising_params) == 40
-    assert ctypes.sizeof(L.ising_stats) == 32
-    assert ctypes.sizeof(L.ising_info) == 40
+    fields = {"ising_params": ["alpha", "beta", "eps", "algo", "q", "x_dtype", "reserved"],
+              "ising_stats": ["iters_done", "converged", "nonfinite", "H_last", "r_last"],
+              "ising_info": ["n", "n_iter", "nnz", "is_dense", "has_field", "integer_J", "val_dtype",
+                             "row_len", "reserved"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ising.h"', "int main(void) {"]
+    for t, fs in fields.items():
+        lines.append(f'  printf("{t} %zu\\n", sizeof({t}));')
+        for f in fs:
+            lines.append(f'  printf("{t}.{f} %zu\\n", offsetof({t}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c11", "-I", include, str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for t, fs in fields.items():
+        cls = getattr(L, t)
+        assert ctypes.sizeof(cls) == int(got[t]), t
+        for f in fs:
+            assert getattr(cls, f).offset == int(got[f"{t}.{f}"]), (t, f)

@@ -519,6 +519,17 @@ def test_procedural_sin_couplings_parity():
     assert float(E.cpu()[0]) == pytest.approx(orc.energy_dense(J, s), rel=1e-11)
 
 
+def test_constant_row_length_detected():
+    """A CSR whose rows all hold d entries is recognised (row i starts at d i)."""
+    import paper_2509_01928_amd as Lb
+    for A, d in ((gen.torus_csr(30, 5, h_std=0.1), 4), (gen.er_csr(500, 6.0, 6), 0)):
+        P = GpuProblem(A=A)
+        try:
+            assert Lb.ising_get_info(P.ctx).row_len == d
+        finally:
+            P.close()
+
+
 # ------------------------------------------------------ eta tuning (Supp. Note 6)
 @pytest.mark.parametrize("case", ["er", "torus_field"])
 def test_tune_eta_matches_oracle_probes(case):
