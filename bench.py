@@ -73,6 +73,8 @@ _GEOMETRY_KERNEL = {0: ("csr_step_kernel", "1, 1, false"), 1: ("csr_step_kernel"
 def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False) -> str:
     """Kernel instance timed on the lattice (FP32 couplings and field)."""
     xt = "float" if x_dtype == "f32" else "double"
+    if geometry == 8:                                      # the single-launch solve
+        return f"resident_csr_kernel<{xt}, float, float, true>"
     name, tail = _GEOMETRY_KERNEL[geometry]
     if name == "csr_rowlane_kernel":
         tail += ", 4" if implicit_offsets else ", 0"      # the lattice's rows hold 4 entries
@@ -196,7 +198,9 @@ def bench_er20000(args):
                                         "n": A.n, "nnz": A.nnz, "iters": iters,
                                         "kernel_geometry": g, "workgroups_per_cu": w},
         "iteration_us": it_us, "energy_int64": int(E.cpu()[0]),
-        "roofline": {"bound": "latency", "achieved": bytes_iter / (it_us * 1e-6) / 1e9,
+        "autotune_us_per_iteration": {str(k): round(m * 1e3, 2) for k, m in enumerate(ms) if m > 0},
+        "roofline": {"kernel": "resident_csr_kernel" if g == 8 else step_kernel_name(g, "f64"),
+                     "bound": "latency", "achieved": bytes_iter / (it_us * 1e-6) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bytes_iter / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": bytes_iter},
@@ -230,14 +234,32 @@ def bench_sk1024(args):
 
     dt = _timed(step, args.warmup, args.steps)
     it_us = 1e6 * dt / iters
+    geometry = L.ising_get_info(ctx).geometry
+
+    def solve_us(g):
+        L.ising_set_geometry(ctx, g, 0)
+        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / iters
+
+    solve_it_us = {"resident": solve_us(8), "launch_per_iteration": solve_us(0)}
+    L.ising_set_geometry(ctx, geometry, 0)
     print(json.dumps({
         "metric": "edge-updates/s", "value": n * (n - 1) * iters / dt, "unit": "edge-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic", "config": {"workload": "dense SK n=1024, J~N(0,1), 1000 DOCH "
-                                        "iterations, FP64", "n": n, "iters": iters},
-        "iteration_us": it_us, "energy": float(E.cpu()[0]), "lambda_hat": lam,
-        "roofline": {"bound": "latency", "achieved": 8 * n * n / (it_us * 1e-6) / 1e9,
+                                        "iterations, FP64", "n": n, "iters": iters,
+                                        "kernel_geometry": geometry},
+        "iteration_us": it_us, "solve_iteration_us": solve_it_us,
+        "energy": float(E.cpu()[0]), "lambda_hat": lam,
+        "roofline": {"kernel": "resident_dense_kernel" if geometry in (-1, 8) else "dense_step_kernel",
+                     "bound": "latency", "achieved": 8 * n * n / (it_us * 1e-6) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": 8 * n * n / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": 8 * n * n},
@@ -525,9 +547,8 @@ def main():
     if args.geometry >= -1:
         L.ising_set_geometry(ctx, args.geometry, args.wg_per_cu)
         geometry, wg_per_cu = args.geometry, args.wg_per_cu
-        if geometry == -1:        # the library's choice from the mean row length
-            d = A.nnz / A.n
-            geometry, wg_per_cu = (4 if d <= 5 else 6 if d <= 8 else 7), 0
+        if geometry == -1:        # the library's choice from the size and mean row length
+            geometry, wg_per_cu = L.ising_get_info(ctx).geometry, 0
     else:
         p0, _ = L.ising_default_params(ctx, 1.0, 0)
         p0.x_dtype = x_dtype
@@ -567,14 +588,16 @@ def main():
 
     n, nnz, np1 = A.n, A.nnz, A.n + 1
     xb = 4 if args.x_dtype == "f32" else 8
-    # a constant row length makes the row offsets implicit for the lane-per-row
-    # kernels: they are then not read and not counted
-    implicit = row_len > 0 and geometry in (3, 4)
-    # algorithmic bytes of one fused iteration: row offsets (unless implicit),
-    # column indices and values once, iterate read once and written once,
-    # field once
-    bytes_iter = (0 if implicit else 4 * (n + 1)) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
+    # algorithmic bytes of one fused iteration in the stated CSR format: row
+    # offsets, column indices and values once, iterate read once and written
+    # once, field once (12 B per edge-update with an FP32 iterate)
+    bytes_iter = 4 * (n + 1) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
     achieved = bytes_iter / (per_iter_ms * 1e-3) / 1e9
+    # with a constant row length the lane-per-row kernels compute the row
+    # offsets instead of reading them: what the kernel itself moves
+    implicit = row_len > 0 and geometry in (3, 4)
+    kernel_bytes = bytes_iter - (4 * (n + 1) if implicit else 0)
+    kernel_gbs = kernel_bytes / (per_iter_ms * 1e-3) / 1e9
     workload = f"torus{args.L}"
     kernel = step_kernel_name(geometry, args.x_dtype, implicit)
     traffic = load_traffic(kernel, f"{workload}_{args.x_dtype}")
@@ -615,6 +638,9 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic["hbm_bytes_per_launch"] if traffic else None),
             "algorithmic_bytes_per_launch": bytes_iter,
+            "kernel_bytes_per_launch": kernel_bytes,
+            "kernel_gbs": kernel_gbs,
+            "kernel_frac": kernel_gbs / HBM_PEAK_GBS,
         },
     }
     L.ising_destroy(ctx)

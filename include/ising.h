@@ -93,7 +93,9 @@ typedef struct {
     int32_t row_len;       /* CSR: d if every row holds d entries (row i
                               starts at d*i; the lane-per-row kernels then
                               do not read the offsets), else 0             */
-    int32_t reserved;
+    int32_t geometry;      /* geometry single-restart solves use (see
+                              ising_set_geometry): 0..8 for CSR; -1
+                              (automatic), 0 or 8 for dense; -1 for batches */
 } ising_info;
 
 /* ---------------------------------------------------------------- create
@@ -330,17 +332,26 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
  * up to one (3) or two (4) aligned 4-entry chunks loaded at once (longer rows
  * take a slower path; with a constant row length, see ising_info.row_len,
  * the row offsets are implicit and not read); 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in
- * order from a per-XCD counter; -1 = choose from the mean row length.  wg_per_cu (0..32) caps the
- * workgroups launched per compute unit, 0 = as many as fit.  CSR contexts
- * only.
+ * order from a per-XCD counter; 8 = resident: the whole single-restart DOCH
+ * solve runs in one cooperative launch, with a grid-wide barrier between
+ * iterations instead of a launch per iteration (for problems whose
+ * iteration is shorter than a launch; it needs every workgroup of the launch
+ * resident at once and fails with ISING_E_HIP if the device cannot hold
+ * them); -1 = choose from the size and the mean row length (resident up to
+ * 65536 rows and 2^20 stored entries).  wg_per_cu (0..32) caps the
+ * workgroups launched per compute unit, 0 = as many as fit (ignored by
+ * geometry 8).  Dense contexts take -1 (resident for stored matrices of order
+ * up to 2048, else a launch per iteration), 0 (a launch per iteration) or 8
+ * (resident; order up to 2048, stored matrices only).  Batch contexts take
+ * none.  Every geometry gives the same iterates bit for bit.
  *
  * ising_autotune: time `iters` DOCH iterations (params as for ising_solve,
  * from x0_dev with R = 1; best of two timings) for every geometry and
- * workgroups-per-CU setting in {1, 2, 3, 4, all}, and keep the fastest pair
- * for later solves.
+ * workgroups-per-CU setting in {1, 2, 3, 4, all} (the resident geometry once,
+ * up to 2^22 rows), and keep the fastest pair for later solves.
  * *geometry_out and *wg_per_cu_out (nullable) receive it, ms_per_iter_out
- * (nullable, 8 entries) the best time of each geometry.  Synchronous.
- * Overwrites the log of the last solve. */
+ * (nullable, 9 entries, 0 = not tried) the best time of each geometry.
+ * Synchronous.  Overwrites the log of the last solve.  CSR contexts only. */
 ising_status ising_set_geometry(ising_ctx* ctx, int32_t geometry, int32_t wg_per_cu);
 ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,
                             const ising_params* params, void* stream,

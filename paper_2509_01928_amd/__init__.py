@@ -59,7 +59,7 @@ class ising_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_iter", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("is_dense", ctypes.c_int32), ("has_field", ctypes.c_int32),
                 ("integer_J", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
-                ("row_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("row_len", ctypes.c_int32), ("geometry", ctypes.c_int32)]
 
 
 class IsingError(RuntimeError):
@@ -244,6 +244,10 @@ def ising_cut(ctx, s, R, cut=None, cut_int=None, stream=None):
            "ising_cut")
 
 
+# geometry id of the single-launch (resident) solve
+GEOMETRY_RESIDENT = 8
+
+
 def ising_set_geometry(ctx, geometry, wg_per_cu=0) -> None:
     _check(lib.ising_set_geometry(ctx, int(geometry), int(wg_per_cu)), "ising_set_geometry")
 
@@ -252,7 +256,7 @@ def ising_autotune(ctx, x0, iters, params, stream=None):
     """Returns (best geometry, best workgroups per CU, [best ms/iteration per geometry])."""
     g = ctypes.c_int32(-1)
     w = ctypes.c_int32(-1)
-    ms = (ctypes.c_double * 8)()
+    ms = (ctypes.c_double * (GEOMETRY_RESIDENT + 1))()
     _check(lib.ising_autotune(ctx, ptr(x0), int(iters), ctypes.byref(params),
                               stream if stream is not None else current_stream(),
                               ctypes.byref(g), ctypes.byref(w), ctypes.cast(ms, _p)),

@@ -140,7 +140,11 @@ std::vector<int2> make_blocks(const std::vector<int32_t>& rp, int64_t n, int row
 // (the fastest on the lattice and random-graph workloads measured).
 // Short rows (lattices, mean length up to 5): one row per lane; longer rows:
 // row blocks from per-XCD counters.
+// Small problems (up to 65536 rows and 2^20 entries) run resident: the whole
+// solve in one cooperative launch, since a launch per iteration would cost
+// more than the iteration.
 int default_geometry(int64_t n, int64_t nnz) {
+    if (n <= doch::kResidentAutoRows && nnz <= doch::kResidentAutoNnz) return doch::kGeometryResident;
     const double d = static_cast<double>(nnz) / static_cast<double>(n);
     return d <= 5.0 ? 4 : (d <= 8.0 ? 6 : 7);
 }
@@ -206,6 +210,8 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->lp_ub[0]);
     dev_free(c->lp_ub[1]);
     dev_free(c->lp_partials);
+    dev_free(c->rx);
+    dev_free(c->rsync);
     for (auto& b : c->ad_x) dev_free(b);
     for (auto& b : c->ad_z) dev_free(b);
     dev_free(c->ad_ring);
@@ -240,6 +246,9 @@ struct Scratch {
 };
 
 constexpr int kPowerChunk = 64;
+// The autotuner tries the resident solve up to this many rows (beyond, each
+// lane walks thousands of rows per iteration and the streaming kernels win).
+constexpr int64_t kResidentTuneMaxRows = 1 << 22;
 constexpr int kMaxR = 1024;
 
 ising_status ensure_scratch(ising_ctx* c, size_t partial_doubles, Scratch* out) {
@@ -267,6 +276,99 @@ ising_status ensure_scratch(ising_ctx* c, size_t partial_doubles, Scratch* out) 
 }
 
 }  // namespace
+
+// Per-restart state, tickets and the (H, r) log of a solve of `iters`
+// iterations and R restarts.
+static ising_status ensure_solve_state(ising_ctx* ctx, int64_t iters, int R) {
+    if (!ctx->ticket) {
+        HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)),
+               "hipMalloc(ticket)");
+        HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
+        ctx->state_cap = kMaxR;
+    }
+    HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)),
+           "hipMalloc(log)");
+    return ISING_OK;
+}
+
+// Copy the restarts' state into stats_host (if given; synchronises).
+static ising_status read_stats(ising_ctx* ctx, int R, ising_stats* stats_host, hipStream_t s) {
+    if (!stats_host) return ISING_OK;
+    std::vector<RestartState> hs(static_cast<size_t>(R));
+    HIP_OK(hipMemcpyAsync(hs.data(), ctx->state, R * sizeof(RestartState), hipMemcpyDeviceToHost, s),
+           "copy state");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    bool bad = false, aborted = false;
+    for (int r = 0; r < R; ++r) {
+        stats_host[r].iters_done = hs[r].iters_done;
+        stats_host[r].converged = hs[r].converged;
+        stats_host[r].nonfinite = hs[r].nonfinite;
+        stats_host[r].H_last = hs[r].H_last;
+        stats_host[r].r_last = hs[r].r_last;
+        bad = bad || hs[r].nonfinite;
+        aborted = aborted || hs[r].aborted;
+    }
+    if (aborted) return fail(ISING_E_HIP, "a grid barrier wait of the resident solve timed out");
+    if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
+    return ISING_OK;
+}
+
+// Whether a single-restart DOCH solve of this context runs resident (one
+// cooperative launch for all iterations): a CSR context set to the resident
+// geometry, or a stored dense matrix of order up to 2048 unless another
+// geometry was set.
+static bool resident_selected(const ising_ctx* ctx) {
+    if (ctx->dense)
+        return ctx->proc_kind == 0 && ctx->n <= doch::kResidentMaxDense &&
+               (ctx->geometry == doch::kGeometryResident || ctx->geometry < 0);
+    return ctx->geometry == doch::kGeometryResident;
+}
+
+// The whole solve in one cooperative launch (kernels_resident.hip).
+static ising_status solve_resident(ising_ctx* ctx, const double* x0_dev, int64_t iters, const ising_params& p,
+                                   double* x_out_dev, int8_t* s_out_dev, ising_stats* stats_host, hipStream_t s) {
+    // three iterate buffers in one allocation, each rounded up to 256 bytes
+    const int64_t elt = p.x_dtype == ISING_F64 ? 8 : 4;
+    const int64_t xstride = (ctx->np * elt + 255) / 256 * 256 / elt;
+    const size_t xbytes = 3 * static_cast<size_t>(xstride) * elt;
+    HIP_OK(ensure(&ctx->rx, &ctx->rx_bytes, xbytes), "hipMalloc(x)");
+    char* rx = static_cast<char*>(ctx->rx);
+    void* xb[3] = {rx, rx + xstride * elt, rx + 2 * xstride * elt};
+    const int G = doch::resident_row_groups(ctx->dense, ctx->n);
+    HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes, 2 * static_cast<size_t>(G) * doch::kNumPartials * sizeof(double)),
+           "hipMalloc(partials)");
+    ising_status sst = ensure_solve_state(ctx, iters, 1);
+    if (sst != ISING_OK) return sst;
+    if (!ctx->rsync) HIP_OK(dev_alloc(&ctx->rsync, sizeof(doch::ResidentSync)), "hipMalloc(sync)");
+    HIP_OK(doch::launch_init_state(ctx->state, 1, ctx->ticket, ctx->ticket + kMaxR, s), "init");
+    HIP_OK(doch::launch_resident_reset(ctx->rsync, s), "reset");
+    HIP_OK(doch::launch_load_x0(x0_dev, xb[0], p.x_dtype, ctx->np, s), "load x0");
+    doch::ResidentArgs a;
+    a.x = ctx->rx;
+    a.xstride = xstride;
+    a.x_dtype = p.x_dtype;
+    a.row_groups = G;
+    a.alpha = p.alpha;
+    a.beta = p.beta;
+    a.eps = p.eps;
+    a.iters = iters;
+    a.partials = ctx->partials;
+    a.log = ctx->log;
+    a.state = ctx->state;
+    a.sync = ctx->rsync;
+    if (iters > 0) {
+        const hipError_t e = ctx->dense ? doch::launch_resident_dense(dense_view(ctx), a, s)
+                                        : doch::launch_resident_csr(csr_view(ctx), a, s);
+        if (e != hipSuccess) return hip_fail(e, "resident solve launch");
+    }
+    ctx->last_R = 1;
+    ctx->last_iters = iters;
+    ctx->last_adoch = false;
+    if (x_out_dev || s_out_dev)
+        HIP_OK(doch::launch_finish(xb[0], xb[1], xb[2], p.x_dtype, ctx->state, ctx->n, ctx->np, 1,
+                                   ctx->has_field, x_out_dev, s_out_dev, s), "finish");
+    return read_stats(ctx, 1, stats_host, s);
+}
 
 // ADOCH (Alg. 2) on a CSR context, one restart, FP64 iterates.
 static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t iters, const ising_params& p,
@@ -452,7 +554,8 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
     c->geometry = default_geometry(n, nnz);
     c->wg_per_cu = default_wg_per_cu(c->geometry, c->row_len);
     doch::CsrPlan* plan = nullptr;
-    if ((st = ensure_plan(c, c->geometry, &plan)) != ISING_OK) return bail(st);
+    if (c->geometry != doch::kGeometryResident && (st = ensure_plan(c, c->geometry, &plan)) != ISING_OK)
+        return bail(st);
     *out = c;
     return ISING_OK;
 }
@@ -538,7 +641,7 @@ ising_status ising_get_info(const ising_ctx* ctx, ising_info* out) {
     out->integer_J = ctx->integer_J ? 1 : 0;
     out->val_dtype = ctx->vt;
     out->row_len = ctx->row_len;
-    out->reserved = 0;
+    out->geometry = ctx->batch ? -1 : ctx->geometry;
     return ISING_OK;
 }
 
@@ -685,6 +788,8 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     if (R != 1) return fail(ISING_E_UNSUPPORTED, "R > 1: use ising_solve_batch or ising_solve_lowp");
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (resident_selected(ctx))
+        return solve_resident(ctx, x0_dev, iters, p, x_out_dev, s_out_dev, stats_host, s);
     const size_t elt = p.x_dtype == ISING_F64 ? 8 : 4;
     const size_t xbytes = static_cast<size_t>(ctx->np) * R * elt;
     if (!ctx->xbuf[0] || ctx->xbuf_bytes < xbytes) {
@@ -707,14 +812,8 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     const size_t max_grid = ctx->dense ? static_cast<size_t>(grid) : static_cast<size_t>(doch::kMaxStepGrid);
     HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
                   max_grid * R * doch::kNumPartials * sizeof(double)), "hipMalloc(partials)");
-    if (!ctx->ticket) {
-        HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)),
-               "hipMalloc(ticket)");
-        HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
-        ctx->state_cap = kMaxR;
-    }
-    HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)),
-           "hipMalloc(log)");
+    ising_status sst = ensure_solve_state(ctx, iters, R);
+    if (sst != ISING_OK) return sst;
     unsigned int* sched = ctx->ticket + kMaxR;
     HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, sched, s), "init");
     HIP_OK(doch::launch_load_x0(x0_dev, ctx->xbuf[0], p.x_dtype, ctx->np * R, s), "load x0");
@@ -744,37 +843,32 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     ctx->last_iters = iters;
     ctx->last_adoch = false;
     if (x_out_dev || s_out_dev)
-        HIP_OK(doch::launch_finish(ctx->xbuf[0], ctx->xbuf[1], p.x_dtype, ctx->state, ctx->n, ctx->np, R,
+        HIP_OK(doch::launch_finish(ctx->xbuf[0], ctx->xbuf[1], nullptr, p.x_dtype, ctx->state, ctx->n, ctx->np, R,
                                    ctx->has_field, x_out_dev, s_out_dev, s), "finish");
-    if (stats_host) {
-        std::vector<RestartState> hs(static_cast<size_t>(R));
-        HIP_OK(hipMemcpyAsync(hs.data(), ctx->state, R * sizeof(RestartState), hipMemcpyDeviceToHost, s),
-               "copy state");
-        HIP_OK(hipStreamSynchronize(s), "sync");
-        bool bad = false;
-        for (int r = 0; r < R; ++r) {
-            stats_host[r].iters_done = hs[r].iters_done;
-            stats_host[r].converged = hs[r].converged;
-            stats_host[r].nonfinite = hs[r].nonfinite;
-            stats_host[r].H_last = hs[r].H_last;
-            stats_host[r].r_last = hs[r].r_last;
-            bad = bad || hs[r].nonfinite;
-        }
-        if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
-    }
-    return ISING_OK;
+    return read_stats(ctx, R, stats_host, s);
 }
 
 ising_status ising_set_geometry(ising_ctx* ctx, int32_t geometry, int32_t wg_per_cu) {
     if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
-    if (ctx->dense) return fail(ISING_E_UNSUPPORTED, "geometries apply to CSR contexts");
-    if (geometry < -1 || geometry >= doch::kNumGeometries) return fail(ISING_E_INVALID_ARG, "bad geometry");
+    if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "geometries apply to single CSR or dense contexts");
     if (wg_per_cu < 0 || wg_per_cu > 32) return fail(ISING_E_INVALID_ARG, "wg_per_cu out of range");
+    if (ctx->dense) {
+        if (geometry != -1 && geometry != 0 && geometry != doch::kGeometryResident)
+            return fail(ISING_E_INVALID_ARG, "dense contexts take geometry -1, 0 or %d", doch::kGeometryResident);
+        if (geometry == doch::kGeometryResident && (ctx->proc_kind != 0 || ctx->n > doch::kResidentMaxDense))
+            return fail(ISING_E_UNSUPPORTED, "the resident solve holds stored dense matrices of order <= %lld",
+                        (long long)doch::kResidentMaxDense);
+        ctx->geometry = geometry;
+        return ISING_OK;
+    }
+    if (geometry < -1 || geometry > doch::kGeometryResident) return fail(ISING_E_INVALID_ARG, "bad geometry");
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     const int g = geometry < 0 ? default_geometry(ctx->n, ctx->nnz) : geometry;
-    doch::CsrPlan* plan = nullptr;
-    ising_status st = ensure_plan(ctx, g, &plan);
-    if (st != ISING_OK) return st;
+    if (g != doch::kGeometryResident) {
+        doch::CsrPlan* plan = nullptr;
+        ising_status st = ensure_plan(ctx, g, &plan);
+        if (st != ISING_OK) return st;
+    }
     ctx->geometry = g;
     ctx->wg_per_cu = geometry < 0 ? default_wg_per_cu(g, ctx->row_len) : wg_per_cu;
     return ISING_OK;
@@ -784,7 +878,7 @@ ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,
                             const ising_params* params, void* stream, int32_t* geometry_out,
                             int32_t* wg_per_cu_out, double* ms_per_iter_out) {
     if (!ctx || !params || !x0_dev) return fail(ISING_E_INVALID_ARG, "NULL argument");
-    if (ctx->dense) return fail(ISING_E_UNSUPPORTED, "geometries apply to CSR contexts");
+    if (ctx->dense || ctx->batch) return fail(ISING_E_UNSUPPORTED, "geometries are tuned on single CSR contexts");
     if (iters < 1) return fail(ISING_E_INVALID_ARG, "iters < 1");
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -796,11 +890,13 @@ ising_status ising_autotune(ising_ctx* ctx, const double* x0_dev, int64_t iters,
     ising_params p = *params;
     p.eps = 0.0;                     // time exactly `iters` iterations
     ising_status st = ISING_OK;
-    // workgroups per CU to try (0 = as many as fit)
+    // workgroups per CU to try (0 = as many as fit); the resident solve has
+    // a single launch shape
     const int wpcs[] = {1, 2, 3, 4, 0};
-    for (int g = 0; g < doch::kNumGeometries && st == ISING_OK; ++g) {
+    for (int g = 0; g <= doch::kGeometryResident && st == ISING_OK; ++g) {
         float g_best = 0.0f;
         for (int w : wpcs) {
+            if (g == doch::kGeometryResident && (w != 0 || ctx->n > kResidentTuneMaxRows)) continue;
             if ((st = ising_set_geometry(ctx, g, w)) != ISING_OK) break;
             if ((st = ising_solve(ctx, x0_dev, 1, 1, &p, nullptr, nullptr, nullptr, stream)) != ISING_OK) break;
             // best of two timings of `iters` iterations

@@ -32,7 +32,7 @@ struct RestartState {
     int32_t done;        // converged or failed: later iterations are skipped
     int32_t converged;
     int32_t nonfinite;
-    int32_t pad;
+    int32_t aborted;     // a bounded wait of the resident solve ran out
     double H_last;
     double r_last;
 };
@@ -105,6 +105,41 @@ struct StepArgs {
     double* log;            // [iters][R][2]: (H, r)
     RestartState* state;    // [R]
     int all_done_flag;      // unused placeholder
+};
+
+// ---- single-launch (resident) solves of small problems (kernels_resident.hip) ----
+// Geometry id that selects the resident solve (CSR and dense contexts).
+constexpr int kGeometryResident = 8;
+// Largest dense order the resident solve holds in registers.
+constexpr int64_t kResidentMaxDense = 2048;
+// Row workgroups of a sparse resident solve (rows beyond 256 per workgroup
+// take further passes).
+constexpr int kResidentMaxCsrGroups = 255;
+// Below these sizes a solve with the default geometry is resident.
+constexpr int64_t kResidentAutoRows = 65536;
+constexpr int64_t kResidentAutoNnz = 1 << 20;
+
+// Barrier words of a resident solve; counters are 32 uints (one 128-byte
+// line) apart.  grp[32 g]: arrivals of XCD group g; top[0]: groups complete;
+// flag[32 g]: last barrier released to group g, flag[32 g + 1]: nonzero once
+// the run stops (1 = finished early, 2 = a wait timed out).
+struct ResidentSync {
+    unsigned int grp[8 * 32];
+    unsigned int top[32];
+    unsigned int flag[8 * 32];
+};
+
+struct ResidentArgs {
+    void* x;                // three iterate buffers, xstride elements apart;
+    int64_t xstride;        // x^(k) is buffer k mod 3
+    int x_dtype;
+    int row_groups;         // workgroups owning rows; one more reduces
+    double alpha, beta, eps;
+    int64_t iters;
+    double* partials;       // [2][row_groups][kNumPartials]
+    double* log;            // [iters][2]: (H, r)
+    RestartState* state;
+    ResidentSync* sync;
 };
 
 // ---- batches of independent instances (kernels_batch.hip) ----
@@ -234,6 +269,10 @@ struct ising_ctx {
     int8_t* ad_acclog = nullptr;
     size_t ad_acclog_bytes = 0;
     bool last_adoch = false;
+    // resident solve: three iterate buffers and the barrier words
+    void* rx = nullptr;
+    size_t rx_bytes = 0;
+    doch::ResidentSync* rsync = nullptr;
     // cached graph of the batch solve
     hipGraphExec_t bgraph = nullptr;
     hipGraph_t bgraph_src = nullptr;
@@ -320,6 +359,12 @@ hipError_t launch_adoch_finish(const double* b0, const double* b1, const double*
                                const RestartState* st, int64_t n, int64_t np, bool field,
                                double* x_out, int8_t* s_out, hipStream_t s);
 
+// ---- launchers (kernels_resident.hip) ----
+int resident_row_groups(bool dense, int64_t n);
+hipError_t launch_resident_reset(ResidentSync* sy, hipStream_t s);
+hipError_t launch_resident_dense(const DenseView& A, const ResidentArgs& a, hipStream_t s);
+hipError_t launch_resident_csr(const CsrView& A, const ResidentArgs& a, hipStream_t s);
+
 // ---- launchers (kernels_common.hip) ----
 hipError_t launch_cut(const double* E, const int64_t* E_int, const MatrixStats* ms, int R, double* cut,
                       int64_t* cut_int, hipStream_t s);
@@ -327,7 +372,9 @@ hipError_t launch_load_x0(const double* x0, void* x, int x_dtype, int64_t count,
                           hipStream_t s);
 hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket,
                              unsigned int* sched, hipStream_t s);
-hipError_t launch_finish(const void* xb0, const void* xb1, int x_dtype,
+// xb2 == nullptr: the iterate alternates between xb0 and xb1; otherwise it
+// rotates through all three.
+hipError_t launch_finish(const void* xb0, const void* xb1, const void* xb2, int x_dtype,
                          const RestartState* st, int64_t n, int64_t np, int R,
                          bool field, double* x_out, int8_t* s_out, hipStream_t s);
 hipError_t launch_normalize(const double* w, double* v, const double* mu_log,

@@ -37,7 +37,7 @@ __global__ void init_state_kernel(RestartState* st, int R, unsigned int* ticket,
         st[r].done = 0;
         st[r].converged = 0;
         st[r].nonfinite = 0;
-        st[r].pad = 0;
+        st[r].aborted = 0;
         st[r].H_last = 0.0;
         st[r].r_last = 0.0;
     }
@@ -45,10 +45,11 @@ __global__ void init_state_kernel(RestartState* st, int R, unsigned int* ticket,
 
 // The iterate of restart r after iters_done steps sits in buffer
 // iters_done mod 2 (buffers alternate every iteration, and a stopped
-// restart is never written again).
+// restart is never written again), or mod 3 when three buffers rotate.
 template <typename XT>
 __global__ __launch_bounds__(NT) void finish_kernel(const XT* __restrict__ xb0,
                                                     const XT* __restrict__ xb1,
+                                                    const XT* __restrict__ xb2,
                                                     const RestartState* __restrict__ st,
                                                     int64_t n, int64_t np, int R, int field,
                                                     double* __restrict__ x_out,
@@ -58,7 +59,8 @@ __global__ __launch_bounds__(NT) void finish_kernel(const XT* __restrict__ xb0,
          t += static_cast<int64_t>(gridDim.x) * NT) {
         const int64_t i = t / R;
         const int r = static_cast<int>(t - i * R);
-        const XT* xb = (st[r].iters_done & 1) ? xb1 : xb0;
+        const int64_t m = xb2 ? st[r].iters_done % 3 : (st[r].iters_done & 1);
+        const XT* xb = m == 0 ? xb0 : (m == 1 ? xb1 : xb2);
         const double x = static_cast<double>(xb[t]);
         if (x_out) x_out[t] = x;
         if (s_out && i < n) {
@@ -119,17 +121,19 @@ hipError_t launch_init_state(RestartState* st, int R, unsigned int* ticket, unsi
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const void* xb0, const void* xb1, int x_dtype, const RestartState* st,
+hipError_t launch_finish(const void* xb0, const void* xb1, const void* xb2, int x_dtype, const RestartState* st,
                          int64_t n, int64_t np, int R, bool field, double* x_out, int8_t* s_out,
                          hipStream_t s) {
     const int grid = grid_for(np * R);
     if (x_dtype == ISING_F64)
         hipLaunchKernelGGL(finish_kernel<double>, dim3(grid), dim3(NT), 0, s,
-                           static_cast<const double*>(xb0), static_cast<const double*>(xb1), st, n,
+                           static_cast<const double*>(xb0), static_cast<const double*>(xb1),
+                           static_cast<const double*>(xb2), st, n,
                            np, R, field ? 1 : 0, x_out, s_out);
     else
         hipLaunchKernelGGL(finish_kernel<float>, dim3(grid), dim3(NT), 0, s,
-                           static_cast<const float*>(xb0), static_cast<const float*>(xb1), st, n,
+                           static_cast<const float*>(xb0), static_cast<const float*>(xb1),
+                           static_cast<const float*>(xb2), st, n,
                            np, R, field ? 1 : 0, x_out, s_out);
     return hipGetLastError();
 }

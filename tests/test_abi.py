@@ -53,7 +53,7 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {"ising_params": ["alpha", "beta", "eps", "algo", "q", "x_dtype", "reserved"],
               "ising_stats": ["iters_done", "converged", "nonfinite", "H_last", "r_last"],
               "ising_info": ["n", "n_iter", "nnz", "is_dense", "has_field", "integer_J", "val_dtype",
-                             "row_len", "reserved"]}
+                             "row_len", "geometry"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ising.h"', "int main(void) {"]
     for t, fs in fields.items():
         lines.append(f'  printf("{t} %zu\\n", sizeof({t}));')

@@ -41,7 +41,7 @@ def check_all(A, tr, x, s, st, H, r, label):
     assert_log_parity(H, r, tr, label)
 
 
-@pytest.mark.parametrize("geometry", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("geometry", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("n,d,seed,iters", [(3000, 6.0, 11, 300), (777, 3.0, 12, 200),
                                             (5000, 20.0, 13, 150)])
 def test_er_fp64_parity(n, d, seed, iters, geometry):
@@ -68,7 +68,7 @@ def test_er_c2_full_config():
     assert E[0] == orc.energy(A, s)
 
 
-@pytest.mark.parametrize("geometry", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("geometry", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("L,iters", [(64, 300), (97, 120)])
 def test_torus_with_field_fp64_parity(L, iters, geometry):
     """Lattice with h ~ N(0, 0.1^2): the extra spin of Supp. Note 1."""
@@ -106,14 +106,16 @@ def test_long_rows_and_empty_rows():
     A = gen.csr_from_dense(J.astype(np.float64))
     assert np.diff(A.row_ptr).max() > 4096 and np.sum(np.diff(A.row_ptr) == 0) >= 100
     x0 = gen.uniform_x0(n, 1, 33)[:, 0]
-    for geometry in range(8):
+    for geometry in range(9):
         B, tr, x, s, st, H, r = run_both(A, x0, 150, geometry=geometry)
         check_all(A, tr, x, s, st, H, r, f"long rows geometry {geometry}")
 
 
+@pytest.mark.parametrize("geometry", [-1, 0])
 @pytest.mark.parametrize("n,iters", [(300, 400), (1024, 1000)])
-def test_dense_sk_parity(n, iters):
-    """Dense SK (n=1024 with 1000 iterations is the dense FP64 workload)."""
+def test_dense_sk_parity(n, iters, geometry):
+    """Dense SK (n=1024 with 1000 iterations is the dense FP64 workload), on
+    the default (resident) solve and with a launch per iteration."""
     seed, xseed = gen.SEEDS["sk1024"] if n == 1024 else (41, 42)
     J = gen.sk_dense(n, seed)
     x0 = gen.uniform_x0(n, 1, xseed)[:, 0]
@@ -122,6 +124,7 @@ def test_dense_sk_parity(n, iters):
     tr = orc.doch_dense(J, x0, alpha, beta, iters)
     P = GpuProblem(J=J)
     try:
+        P.L.ising_set_geometry(P.ctx, geometry, 0)
         x, s, st = P.solve(x0, alpha, beta, iters)
         H, r = P.log(iters)
         E, _ = P.energy(s[:, 0])
@@ -134,7 +137,8 @@ def test_dense_sk_parity(n, iters):
     assert E[0] == pytest.approx(orc.energy_dense(J, s[:, 0]), rel=1e-12)
 
 
-def test_dense_with_field():
+@pytest.mark.parametrize("geometry", [-1, 0])
+def test_dense_with_field(geometry):
     n = 200
     J = gen.sk_dense(n, 51)
     h = np.random.default_rng(52).standard_normal(n) * 0.5
@@ -145,6 +149,7 @@ def test_dense_with_field():
     tr = orc.doch(B, x0, alpha, beta, 300)
     P = GpuProblem(J=J, h=h)
     try:
+        P.L.ising_set_geometry(P.ctx, geometry, 0)
         x, s, st = P.solve(x0, alpha, beta, 300)
         H, r = P.log(300)
         E, _ = P.energy(s[:, 0])
@@ -387,7 +392,7 @@ def test_autotune_keeps_results():
     try:
         xd = torch.from_numpy(x0).to("cuda:0")
         g, w, ms = Lb.ising_autotune(P.ctx, xd, 5, P.params(alpha, beta))
-        assert 0 <= g < 8 and w in (0, 1, 2, 3, 4) and all(m > 0 for m in ms)
+        assert 0 <= g <= 8 and w in (0, 1, 2, 3, 4) and len(ms) == 9 and all(m > 0 for m in ms)
         x, s, st = P.solve(x0, alpha, beta, 60)
     finally:
         P.close()
