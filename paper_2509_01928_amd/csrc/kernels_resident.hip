@@ -299,45 +299,83 @@ __global__ __launch_bounds__(NT) void resident_dense_kernel(int64_t n, const dou
 
 // Sparse rows: one lane per row (rows i = w NT + lane, w NT + lane + G NT,
 // ...), entries in ascending order, gathers of x^(k) at the point of
-// coherence issued eight at a time.
-template <typename XT, typename VT, typename HT, bool FIELD>
+// coherence issued eight at a time.  With one row per lane (CACHE > 0) the
+// row's first CACHE column indices and values stay in registers for the
+// whole run, so an iteration starts with its gathers.
+template <typename XT, typename VT>
+__device__ __forceinline__ double row_tail(const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                           const XT* xo, int e, int e1, double z) {
+    for (; e < e1; e += 8) {
+        int c[8];
+        XT g[8];
+        double vv[8];
+        // indices past the row's end repeat its last entry, so every load is
+        // in bounds and none waits on a branch
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = e + u < e1 ? e + u : e1 - 1;
+            c[u] = col[q];
+            vv[u] = static_cast<double>(val[q]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g[u] = ld_coh(xo + c[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e + u < e1) z = dadd(z, dmul(vv[u], static_cast<double>(g[u])));
+    }
+    return z;
+}
+
+template <typename XT, typename VT, typename HT, bool FIELD, int CACHE>
 __global__ __launch_bounds__(NT) void resident_csr_kernel(int64_t n, const int32_t* __restrict__ rp,
                                                           const int32_t* __restrict__ col,
                                                           const VT* __restrict__ val,
                                                           const HT* __restrict__ h, ResidentArgs a) {
     const int64_t first = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(a.row_groups) * NT;
-    resident_loop<XT, FIELD>(a, n, [&](const XT* xo, XT* xn, double t, double (&acc)[kNumPartials]) {
-        for (int64_t i = first; i < n; i += stride) {
-            const int e0 = rp[i], e1 = rp[i + 1];
-            const double xi = static_cast<double>(ld_coh(xo + i));
-            double z = 0.0;
-            for (int e = e0; e < e1; e += 8) {
-                int c[8];
-                XT g[8];
-                double vv[8];
-                // indices past the row's end repeat its last entry, so every
-                // load is in bounds and none waits on a branch
+    if constexpr (CACHE > 0) {
+        // this lane's only row, cached
+        const bool own = static_cast<int>(blockIdx.x) < a.row_groups && first < n;
+        const int e0 = own ? rp[first] : 0, e1 = own ? rp[first + 1] : 0;
+        const int len = e1 - e0;
+        int cc[CACHE];
+        double cv[CACHE];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int q = e + u < e1 ? e + u : e1 - 1;
-                    c[u] = col[q];
-                    vv[u] = static_cast<double>(val[q]);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) g[u] = ld_coh(xo + c[u]);
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (e + u < e1) z = dadd(z, dmul(vv[u], static_cast<double>(g[u])));
-            }
-            double hq = 0.0;
-            if (FIELD) {
-                hq = static_cast<double>(h[i]);
-                z = dadd(z, dmul(hq, t));
-            }
-            resident_update<XT>(z, xi, hq, FIELD, a, xn, i, acc);
+        for (int u = 0; u < CACHE; ++u) {
+            const int q = u < len ? e0 + u : e0;
+            cc[u] = u < len ? col[q] : 0;
+            cv[u] = u < len ? static_cast<double>(val[q]) : 0.0;
         }
-    });
+        const double hq = (FIELD && own) ? static_cast<double>(h[first]) : 0.0;
+        resident_loop<XT, FIELD>(a, n, [&](const XT* xo, XT* xn, double t, double (&acc)[kNumPartials]) {
+            if (!own) return;
+            XT g[CACHE];
+            const double xi = static_cast<double>(ld_coh(xo + first));
+#pragma unroll
+            for (int u = 0; u < CACHE; ++u) g[u] = ld_coh(xo + cc[u]);
+            double z = 0.0;
+#pragma unroll
+            for (int u = 0; u < CACHE; ++u)
+                if (u < len) z = dadd(z, dmul(cv[u], static_cast<double>(g[u])));
+            if (len > CACHE) z = row_tail(col, val, xo, e0 + CACHE, e1, z);
+            if (FIELD) z = dadd(z, dmul(hq, t));
+            resident_update<XT>(z, xi, hq, FIELD, a, xn, first, acc);
+        });
+    } else {
+        resident_loop<XT, FIELD>(a, n, [&](const XT* xo, XT* xn, double t, double (&acc)[kNumPartials]) {
+            for (int64_t i = first; i < n; i += stride) {
+                const int e0 = rp[i], e1 = rp[i + 1];
+                const double xi = static_cast<double>(ld_coh(xo + i));
+                double z = row_tail(col, val, xo, e0, e1, 0.0);
+                double hq = 0.0;
+                if (FIELD) {
+                    hq = static_cast<double>(h[i]);
+                    z = dadd(z, dmul(hq, t));
+                }
+                resident_update<XT>(z, xi, hq, FIELD, a, xn, i, acc);
+            }
+        });
+    }
 }
 
 __global__ void resident_reset_kernel(ResidentSync* sy) {
@@ -384,7 +422,7 @@ hipError_t launch_dense_x(const DenseView& A, const ResidentArgs& a, hipStream_t
     return launch_dense_f<XT, HT, false>(A, a, s);
 }
 
-template <typename XT, typename VT, typename HT, bool FIELD>
+template <typename XT, typename VT, typename HT, bool FIELD, int CACHE>
 hipError_t launch_csr_t(const CsrView& A, ResidentArgs a, hipStream_t s) {
     static int cap = 0;
     int64_t n = A.n;
@@ -393,14 +431,21 @@ hipError_t launch_csr_t(const CsrView& A, ResidentArgs a, hipStream_t s) {
     const VT* val = static_cast<const VT*>(A.val);
     const HT* h = static_cast<const HT*>(A.h);
     void* args[] = {&n, &rp, &col, &val, &h, &a};
-    return launch_coop(resident_csr_kernel<XT, VT, HT, FIELD>, &cap, a.row_groups, args, s);
+    return launch_coop(resident_csr_kernel<XT, VT, HT, FIELD, CACHE>, &cap, a.row_groups, args, s);
+}
+
+template <typename VT, typename HT, int CACHE>
+hipError_t launch_csr_c(const CsrView& A, const ResidentArgs& a, hipStream_t s) {
+    if (a.x_dtype == ISING_F64)
+        return A.h ? launch_csr_t<double, VT, HT, true, CACHE>(A, a, s) : launch_csr_t<double, VT, HT, false, CACHE>(A, a, s);
+    return A.h ? launch_csr_t<float, VT, HT, true, CACHE>(A, a, s) : launch_csr_t<float, VT, HT, false, CACHE>(A, a, s);
 }
 
 template <typename VT, typename HT>
 hipError_t launch_csr_x(const CsrView& A, const ResidentArgs& a, hipStream_t s) {
-    if (a.x_dtype == ISING_F64)
-        return A.h ? launch_csr_t<double, VT, HT, true>(A, a, s) : launch_csr_t<double, VT, HT, false>(A, a, s);
-    return A.h ? launch_csr_t<float, VT, HT, true>(A, a, s) : launch_csr_t<float, VT, HT, false>(A, a, s);
+    // one row per lane: keep the first 16 entries of each row in registers
+    if (A.n <= static_cast<int64_t>(a.row_groups) * NT) return launch_csr_c<VT, HT, 16>(A, a, s);
+    return launch_csr_c<VT, HT, 0>(A, a, s);
 }
 
 }  // namespace
