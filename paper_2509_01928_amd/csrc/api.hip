@@ -205,10 +205,8 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->tune_s);
     dev_free(c->lp_cs);
     dev_free(c->lp_colmax);
-    dev_free(c->lp_u[0]);
-    dev_free(c->lp_u[1]);
-    dev_free(c->lp_ub[0]);
-    dev_free(c->lp_ub[1]);
+    for (auto& b : c->lp_u) dev_free(b);
+    for (auto& b : c->lp_ub) dev_free(b);
     dev_free(c->lp_partials);
     dev_free(c->rx);
     dev_free(c->rsync);
@@ -1221,7 +1219,7 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         if (prec == 1) {
             HIP_OK(dev_alloc(&ctx->rscale, static_cast<size_t>(np) * sizeof(float)), "hipMalloc(scale)");
             HIP_OK(dev_alloc(&ctx->rowabs, static_cast<size_t>(np) * sizeof(double)), "hipMalloc(row sums)");
-            HIP_OK(dev_alloc(&ctx->lp_cs, 2 * kMaxR * sizeof(float)), "hipMalloc(restart scales)");
+            HIP_OK(dev_alloc(&ctx->lp_cs, 3 * kMaxR * sizeof(float)), "hipMalloc(restart scales)");
             HIP_OK(dev_alloc(&ctx->lp_colmax, kMaxR * sizeof(unsigned int)), "hipMalloc(column maxima)");
         }
         HIP_OK(doch::launch_lowp_convert(prec, ctx->J, n, np, ctx->jq[prec], ctx->rscale, ctx->rowabs, s),
@@ -1238,26 +1236,26 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         }
         ctx->lp_np = np;
     }
+    // three rotating iterate buffers (FP32 master and low-precision copy): a
+    // restart that stops keeps its last iterate in buffer iters_done mod 3
     const size_t ubytes = static_cast<size_t>(np) * Rp * sizeof(float);
     const size_t ubbytes = static_cast<size_t>(np) * Rp * esz;
     if (!ctx->lp_u[0] || ctx->lp_ubytes < ubytes) {
-        dev_free(ctx->lp_u[0]);
-        dev_free(ctx->lp_u[1]);
+        for (auto& b : ctx->lp_u) dev_free(b);
         ctx->lp_ubytes = 0;
-        HIP_OK(dev_alloc(&ctx->lp_u[0], ubytes), "hipMalloc(U)");
-        HIP_OK(dev_alloc(&ctx->lp_u[1], ubytes), "hipMalloc(U)");
+        for (auto& b : ctx->lp_u) HIP_OK(dev_alloc(&b, ubytes), "hipMalloc(U)");
         ctx->lp_ubytes = ubytes;
     }
     if (!ctx->lp_ub[0] || ctx->lp_ubbytes < ubbytes) {
-        dev_free(ctx->lp_ub[0]);
-        dev_free(ctx->lp_ub[1]);
+        for (auto& b : ctx->lp_ub) dev_free(b);
         ctx->lp_ubbytes = 0;
-        HIP_OK(dev_alloc(&ctx->lp_ub[0], ubbytes), "hipMalloc(Ub)");
-        HIP_OK(dev_alloc(&ctx->lp_ub[1], ubbytes), "hipMalloc(Ub)");
+        for (auto& b : ctx->lp_ub) HIP_OK(dev_alloc(&b, ubbytes), "hipMalloc(Ub)");
         ctx->lp_ubbytes = ubbytes;
     }
-    HIP_OK(ensure(&ctx->lp_partials, &ctx->lp_pbytes, static_cast<size_t>(np / 64) * Rp * 4 * sizeof(double)),
-           "hipMalloc(partials)");
+    // two partial-sum buffers: iteration k writes one while its launch closes
+    // iteration k - 1 from the other
+    const size_t pstride = static_cast<size_t>(np / 64) * Rp * 4;
+    HIP_OK(ensure(&ctx->lp_partials, &ctx->lp_pbytes, 2 * pstride * sizeof(double)), "hipMalloc(partials)");
     if (!ctx->ticket) {
         HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
         HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
@@ -1267,20 +1265,32 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
            "hipMalloc(log)");
     HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, nullptr, s), "init");
     const double sb = std::sqrt(p.beta);
-    float* cs[2] = {ctx->lp_cs, ctx->lp_cs ? ctx->lp_cs + kMaxR : nullptr};
+    float* cs[3] = {ctx->lp_cs, ctx->lp_cs ? ctx->lp_cs + kMaxR : nullptr, ctx->lp_cs ? ctx->lp_cs + 2 * kMaxR : nullptr};
     HIP_OK(doch::launch_lowp_load(prec, x0_dev, n, R, np, Rp, sb, ctx->lp_colmax, cs[0], ctx->lp_u[0],
                                   ctx->lp_ub[0], s), "load");
+    // the other buffers start as copies, so padding rows and restarts hold
+    // finite values in every buffer
+    for (int b = 1; b < 3; ++b) {
+        HIP_OK(hipMemcpyAsync(ctx->lp_u[b], ctx->lp_u[0], ubytes, hipMemcpyDeviceToDevice, s), "copy U");
+        HIP_OK(hipMemcpyAsync(ctx->lp_ub[b], ctx->lp_ub[0], ubbytes, hipMemcpyDeviceToDevice, s), "copy Ub");
+        if (prec == 1)
+            HIP_OK(hipMemcpyAsync(cs[b], cs[0], kMaxR * sizeof(float), hipMemcpyDeviceToDevice, s), "copy scales");
+    }
     for (int64_t k = 0; k < iters; ++k) {
-        const int a = static_cast<int>(k & 1), b = 1 - a;
+        const int a = static_cast<int>(k % 3), b = static_cast<int>((k + 1) % 3);
+        double* pk = ctx->lp_partials + (k & 1) * pstride;
+        const double* pprev = ctx->lp_partials + ((k + 1) & 1) * pstride;
         HIP_OK(doch::launch_lowp_step(prec, np, Rp, ctx->jq[prec], ctx->rscale, ctx->lp_u[a], ctx->lp_u[b],
                                       ctx->lp_ub[a], ctx->lp_ub[b], cs[a], cs[b], ctx->lp_rho_q, p.alpha,
-                                      p.beta, p.eps, R, k, ctx->lp_partials, ctx->ticket, ctx->log,
-                                      ctx->state, s),
+                                      p.beta, p.eps, R, k, pprev, pk, ctx->log, ctx->state, s),
                "low-precision step");
     }
+    if (iters > 0)
+        HIP_OK(doch::launch_lowp_close(np, Rp, R, iters - 1, ctx->lp_partials + ((iters - 1) & 1) * pstride,
+                                       p.alpha, p.beta, p.eps, ctx->log, ctx->state, s),
+               "close last iteration");
     ctx->last_R = R;
     ctx->last_iters = iters;
-    const float* Ufin = ctx->lp_u[iters & 1];
     double* xtmp = nullptr;
     if (x_out_dev || s_out_dev || H_final_dev) {
         double* xo = x_out_dev;
@@ -1288,7 +1298,7 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
             HIP_OK(dev_alloc(&xtmp, static_cast<size_t>(n) * R * sizeof(double)), "hipMalloc(x)");
             xo = xtmp;
         }
-        hipError_t e = doch::launch_lowp_finish(Ufin, n, R, Rp, sb, xo, s_out_dev, s);
+        hipError_t e = doch::launch_lowp_finish(ctx->lp_u, ctx->state, n, R, Rp, sb, xo, s_out_dev, s);
         if (e == hipSuccess && H_final_dev) {
             // per (row tile of 64, padded restart) three FP64 partial sums
             Scratch sc;

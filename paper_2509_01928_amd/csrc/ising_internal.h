@@ -251,11 +251,11 @@ struct ising_ctx {
     double last_lambda = 0.0;            // lambda_hat and max row sum of the last
     double last_rowsum = 0.0;            // ising_default_params call
     int8_t* tune_s = nullptr;            // ising_tune_eta: rounded probe spins
-    float* lp_cs = nullptr;              // FP8: restart scales, two buffers of kMaxR
+    float* lp_cs = nullptr;              // FP8: restart scales, three buffers of kMaxR
     unsigned int* lp_colmax = nullptr;   // FP8: start column maxima (float bits)
     int lp_np = 0;                       // padded order (multiple of 256)
-    float* lp_u[2] = {nullptr, nullptr};
-    void* lp_ub[2] = {nullptr, nullptr};
+    float* lp_u[3] = {nullptr, nullptr, nullptr};   // FP32 master iterates (rotating)
+    void* lp_ub[3] = {nullptr, nullptr, nullptr};   // their low-precision copies
     size_t lp_ubytes = 0, lp_ubbytes = 0;
     double* lp_partials = nullptr;
     size_t lp_pbytes = 0;
@@ -337,14 +337,20 @@ hipError_t launch_lowp_convert(int prec, const double* J, int n, int np, void* J
                                double* rowabs, hipStream_t s);
 hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, int Rp, double sqrt_beta,
                             unsigned int* colmax_bits, float* cs, float* U, void* Ub, hipStream_t s);
+// One iteration of the restart block; its extra workgroups close iteration
+// k - 1 from partials_prev (k > 0).  A stopped restart is never written, so
+// its last iterate stays in buffer iters_done mod 3 (three buffers rotate).
 hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const float* rscale,
                             const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
                             const float* cs_old, float* cs_new, double rho_q,
                             double alpha, double beta, double eps, int R, int64_t k,
-                            double* partials, unsigned int* ticket, double* log, RestartState* state,
+                            const double* partials_prev, double* partials, double* log, RestartState* state,
                             hipStream_t s);
-hipError_t launch_lowp_finish(const float* U, int n, int R, int Rp, double sqrt_beta, double* x_out,
-                              int8_t* s_out, hipStream_t s);
+// Close iteration kk (the last one, after the final step).
+hipError_t launch_lowp_close(int np, int Rp, int R, int64_t kk, const double* partials, double alpha,
+                             double beta, double eps, double* log, RestartState* state, hipStream_t s);
+hipError_t launch_lowp_finish(const float* const* U, const RestartState* state, int n, int R, int Rp,
+                              double sqrt_beta, double* x_out, int8_t* s_out, hipStream_t s);
 hipError_t launch_dense_objective(const double* J, int n, int R, const double* X, double alpha,
                                   double beta, double* partials, unsigned int* tickets, double* H,
                                   hipStream_t s);

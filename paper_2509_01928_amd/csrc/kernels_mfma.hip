@@ -36,6 +36,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int MT = 256;        // threads per workgroup
+#ifndef DOCH_LOWP_DEPTH
+#define DOCH_LOWP_DEPTH 2
+#endif
+// stages of J and restart rows a thread keeps in flight (256 bytes of each of
+// 64 rows per stage, 32 KB per workgroup)
+constexpr int kLowpDepth = DOCH_LOWP_DEPTH;
 
 template <int PREC> struct Prec;
 template <> struct Prec<0> {   // BF16
@@ -105,14 +111,52 @@ __device__ __forceinline__ f32x16 mfma_frag(typename Frag<PREC>::type a, typenam
 //               and written in whole rows, per-restart partial sums
 //   finish      the last workgroup of each column block closes the
 //               iteration of its 64 restarts (H, r, stopping)
-template <int PREC>
+// Close iteration kk of the 64 restarts of column block cb: add the row
+// tiles' partial sums in tile order and write H, r, the log and the state
+// (eq:Hamilton in u = sqrt(beta) x, Remark S2).  red: 64 x 4 doubles of LDS.
+__device__ void lowp_close(const double* __restrict__ P, int tiles, int Rp, int cb, int R, int64_t kk,
+                           double alpha, double beta, double eps, double* __restrict__ log,
+                           RestartState* __restrict__ state, double (*red)[4]) {
+    const int tid = threadIdx.x;
+    const int col0 = cb * 64;
+    {
+        const int cl = tid & 63, q = tid >> 6;
+        red[cl][q] = column_partial_sum<4>(P, Rp, col0 + cl, q, tiles);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int c = col0 + tid;
+        if (c < R && !state[c].done) {
+            const double* S = red[tid];
+            // H(x) = H_u / beta with x = u / sqrt(beta); r is scale free
+            const double Hu = dsub(dsub(dmul(0.25, S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
+            const double H = ddiv(Hu, beta);
+            const double r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
+            log[(static_cast<size_t>(kk) * R + c) * 2] = H;
+            log[(static_cast<size_t>(kk) * R + c) * 2 + 1] = r;
+            RestartState& st = state[c];
+            st.iters_done = kk + 1;
+            st.H_last = H;
+            st.r_last = r;
+            if (!isfinite(H) || !isfinite(r)) {
+                st.nonfinite = 1;
+                st.done = 1;
+            } else if (eps > 0.0 && r < eps) {
+                st.converged = 1;
+                st.done = 1;
+            }
+        }
+    }
+}
+
+template <int PREC, int DEPTH>
 __global__ __launch_bounds__(MT) void lowp_step_kernel(
     int np, int Rp, const typename Prec<PREC>::T* __restrict__ Jq, const float* __restrict__ rscale,
     const float* __restrict__ U_old, float* __restrict__ U_new,
     const typename Prec<PREC>::T* __restrict__ Ub_old, typename Prec<PREC>::T* __restrict__ Ub_new,
     const float* __restrict__ cs_old, float* __restrict__ cs_new, double rho_q,
-    double alpha, double beta, double eps, int R, int64_t k, double* __restrict__ partials,
-    unsigned int* ticket, double* __restrict__ log, RestartState* __restrict__ state) {
+    double alpha, double beta, double eps, int R, int64_t k, const double* __restrict__ partials_prev,
+    double* __restrict__ partials, double* __restrict__ log, RestartState* __restrict__ state) {
     using T = typename Prec<PREC>::T;
     // two stage buffers (J rows, then restart rows; 64 rows of SROW bytes
     // each), reused for the four wavefronts' partial tiles ([wave][sub-tile]
@@ -121,7 +165,17 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     constexpr int SBYTES = 2 * 2 * 64 * SROW > 4 * 4 * 16 * 64 * 4 ? 2 * 2 * 64 * SROW : 4 * 4 * 16 * 64 * 4;
     __shared__ __attribute__((aligned(16))) char sstage[SBYTES];
     __shared__ double red[2][64][4];
-    __shared__ int last_flag;
+    __shared__ int sdead[64];
+    // the extra row of workgroups (dispatched after every row tile, so each
+    // lands beside a row tile on a CU of its own) closes the previous
+    // iteration: workgroup x of it for column block x
+    const int tiles = np / 64;
+    if (static_cast<int>(blockIdx.y) == Rp / 64) {
+        if (k > 0 && static_cast<int>(blockIdx.x) < Rp / 64)
+            lowp_close(partials_prev, tiles, Rp, blockIdx.x, R, k - 1, alpha, beta, eps, log, state, red[0]);
+        return;
+    }
+    if (static_cast<int>(blockIdx.x) >= tiles) return;     // grid padded to the closing row's width
     float* const sred = reinterpret_cast<float*>(sstage);
     char* const sA0 = sstage;
     const int tid = threadIdx.x;
@@ -131,8 +185,55 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     const int row0 = blockIdx.x * 64;
     const int col0 = blockIdx.y * 64;
     const int mycol = col0 + (tid & 63);
-    const bool block_live =
-        __syncthreads_or(tid < 64 && mycol < R && !state[mycol < R ? mycol : 0].done) != 0;
+    // The inputs of the epilogue and of the liveness test are requested
+    // first, the first DEPTH stages right after them, so the latency of all
+    // of it overlaps: lane column j, rows 8*(v/4) + 4*(lane/32) + v%4 of
+    // sub-tile row wr.
+    const int jl = wc * 32 + (lane & 31);
+    const int j = col0 + jl;
+    const int done_m = (tid < 64 && mycol < R) ? state[mycol].done : 1;
+    const int done_j = j < R ? state[j].done : 1;
+    // stage st: bytes [256 st, 256 st + 256) of each of the 64 rows of J and
+    // of the restart copy; thread loads 16-byte chunks c = tid + 256 u (row
+    // c / 16, chunk c % 16), so 16 consecutive lanes read a row's two whole
+    // cache lines
+    constexpr int SPR = 256;                // bytes per row per stage
+    constexpr int KPS = SPR / static_cast<int>(sizeof(T));   // k per stage
+    const char* gA = reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * np * sizeof(T);
+    const char* gB = reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * np * sizeof(T);
+    const size_t gstride = static_cast<size_t>(np) * sizeof(T);
+    size_t goff[4];
+    int soff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = tid + MT * u;
+        goff[u] = (c >> 4) * gstride + (c & 15) * 16;
+        soff[u] = (c >> 4) * SROW + (c & 15) * 16;
+    }
+    // DEPTH stages in flight per thread (registers), two LDS buffers
+    i32x4 ring[DEPTH][8];
+    auto fetch = [&](i32x4 (&r)[8], int st) {
+        const size_t kb = static_cast<size_t>(st) * SPR;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r[u] = *reinterpret_cast<const i32x4*>(gA + goff[u] + kb);
+            r[4 + u] = *reinterpret_cast<const i32x4*>(gB + goff[u] + kb);
+        }
+    };
+    const int nst = np / KPS;
+#pragma unroll
+    for (int p = 0; p < DEPTH; ++p)
+        if (p < nst) fetch(ring[p], p);
+    float uo_pre[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int il = wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        uo_pre[v] = U_old[static_cast<size_t>(row0 + il) * Rp + j];
+    }
+    float c_in = 1.0f;
+    if constexpr (PREC == 1) c_in = cs_old[j];
+    if (tid < 64) sdead[tid] = done_m;
+    const bool block_live = __syncthreads_or(!done_m) != 0;
 
     f32x16 acc[2][2];
 #pragma unroll
@@ -140,50 +241,21 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
     if (block_live) {
-        // stage st: bytes [256 st, 256 st + 256) of each of the 64 rows of J
-        // and of the restart copy; thread loads 16-byte chunks c = tid + 256 u
-        // (row c / 16, chunk c % 16), so 16 consecutive lanes read a row's
-        // two whole cache lines
-        constexpr int SPR = 256;                // bytes per row per stage
-        constexpr int KPS = SPR / static_cast<int>(sizeof(T));   // k per stage
-        const char* gA = reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * np * sizeof(T);
-        const char* gB = reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * np * sizeof(T);
-        const size_t gstride = static_cast<size_t>(np) * sizeof(T);
-        size_t goff[4];
-        int soff[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = tid + MT * u;
-            goff[u] = (c >> 4) * gstride + (c & 15) * 16;
-            soff[u] = (c >> 4) * SROW + (c & 15) * 16;
-        }
-        i32x4 ring[2][8];
-        auto fetch = [&](i32x4 (&r)[8], int st) {
-            const size_t kb = static_cast<size_t>(st) * SPR;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                r[u] = *reinterpret_cast<const i32x4*>(gA + goff[u] + kb);
-                r[4 + u] = *reinterpret_cast<const i32x4*>(gB + goff[u] + kb);
-            }
-        };
-        const int nst = np / KPS;
         // this wavefront's k-steps of a stage: wave, wave + 4, ... (16 k each)
         const int khalf = (lane >> 5) * 8;
-        fetch(ring[0], 0);
-        if (nst > 1) fetch(ring[1], 1);
-        for (int s0 = 0; s0 < nst; s0 += 2) {
+        for (int s0 = 0; s0 < nst; s0 += DEPTH) {
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < DEPTH; ++p) {
                 const int st = s0 + p;
                 if (st < nst) {
-                    char* A = sstage + p * 2 * 64 * SROW;
+                    char* A = sstage + (st & 1) * 2 * 64 * SROW;
                     char* B = A + 64 * SROW;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         *reinterpret_cast<i32x4*>(A + soff[u]) = ring[p][u];
                         *reinterpret_cast<i32x4*>(B + soff[u]) = ring[p][4 + u];
                     }
-                    if (st + 2 < nst) fetch(ring[p], st + 2);
+                    if (st + DEPTH < nst) fetch(ring[p], st + DEPTH);
                     __syncthreads();
 #pragma unroll
                     for (int ks = wave; ks < KPS / 16; ks += 4) {
@@ -223,14 +295,11 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     __syncthreads();                            // sred is reused below
 
     // ---- epilogue: lane holds column j, rows 8*(v/4) + 4*(lane/32) + v%4
-    const int jl = wc * 32 + (lane & 31);
-    const int j = col0 + jl;
-    const bool live = j < R && !state[j < R ? j : 0].done;
+    const bool live = j < R && !done_j;
     double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
     // FP8: scale of the copy read by this product and of the one written now
-    float c_in = 1.0f, c_out = 1.0f;
+    float c_out = 1.0f;
     if constexpr (PREC == 1) {
-        c_in = cs_old[j];
         c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
         if (blockIdx.x == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
     }
@@ -242,7 +311,7 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         const int il = wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int i = row0 + il;
         const size_t ij = static_cast<size_t>(i) * Rp + j;
-        const double uo = static_cast<double>(U_old[ij]);
+        const double uo = static_cast<double>(uo_pre[v]);
         double z = static_cast<double>(tile[v]);
         if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
         float un = static_cast<float>(uo);
@@ -255,7 +324,9 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
             part[2] = dadd(part[2], dmul(uo, z));
             part[3] = dadd(part[3], dmul(d, d));
         }
-        U_new[ij] = un;
+        // a stopped restart is never written again: its last iterate stays
+        // in the buffer the next iteration would otherwise overwrite
+        if (live) U_new[ij] = un;
         tileT[jl * TROW + il] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
     }
     // rows of a column: lanes l and l + 32, then the two row halves of the tile
@@ -271,50 +342,27 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         constexpr int CPR = 64 * static_cast<int>(sizeof(T)) / 16;
         for (int c = tid; c < 64 * CPR; c += MT) {
             const int r = c / CPR, ch = c % CPR;
+            if (sdead[r]) continue;
             const i32x4 v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(tileT + r * TROW) + ch * 16);
             *reinterpret_cast<i32x4*>(reinterpret_cast<char*>(Ub_new + static_cast<size_t>(col0 + r) * np + row0) +
                                       ch * 16) = v;
         }
     }
-    if (tid < 64) {                             // wave 0: the wave that releases below
+    // partial sums of this row tile, closed by the next launch's extra
+    // workgroups
+    if (tid < 64) {
         double* p = partials + (static_cast<size_t>(blockIdx.x) * Rp + col0 + tid) * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) store_agent(p + q, dadd(red[0][tid][q], red[1][tid][q]));
+        for (int q = 0; q < 4; ++q) p[q] = dadd(red[0][tid][q], red[1][tid][q]);
     }
-    __syncthreads();
-    if (tid == 0) last_flag = arrive_last(ticket + blockIdx.y, gridDim.x) ? 1 : 0;
-    __syncthreads();
-    if (!last_flag) return;
-    // ---- last workgroup of this column block: close the iteration of its restarts
-    {
-        const int cl = tid & 63, q = tid >> 6;
-        red[0][cl][q] = column_partial_sum<4>(partials, Rp, col0 + cl, q, gridDim.x);
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const int c = col0 + tid;
-        if (c < R && !state[c].done) {
-            const double* S = red[0][tid];
-            // H(x) = H_u / beta with x = u / sqrt(beta); r is scale free
-            const double Hu = dsub(dsub(dmul(0.25, S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
-            const double H = ddiv(Hu, beta);
-            const double r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
-            log[(static_cast<size_t>(k) * R + c) * 2] = H;
-            log[(static_cast<size_t>(k) * R + c) * 2 + 1] = r;
-            RestartState& st = state[c];
-            st.iters_done = k + 1;
-            st.H_last = H;
-            st.r_last = r;
-            if (!isfinite(H) || !isfinite(r)) {
-                st.nonfinite = 1;
-                st.done = 1;
-            } else if (eps > 0.0 && r < eps) {
-                st.converged = 1;
-                st.done = 1;
-            }
-        }
-    }
-    if (tid == 0) reset_ticket(ticket + blockIdx.y);
+}
+
+// The last iteration's closing, after the final step launch.
+__global__ __launch_bounds__(MT) void lowp_close_kernel(const double* __restrict__ P, int tiles, int Rp, int R,
+                                                        int64_t kk, double alpha, double beta, double eps,
+                                                        double* __restrict__ log, RestartState* __restrict__ state) {
+    __shared__ double red[64][4];
+    lowp_close(P, tiles, Rp, blockIdx.x, R, kk, alpha, beta, eps, log, state, red);
 }
 
 __device__ __forceinline__ float start_u(const double* x0, int64_t i, int R, int j, double sqrt_beta) {
@@ -364,7 +412,9 @@ __global__ __launch_bounds__(256) void lowp_load_kernel(const double* __restrict
 }
 
 // u -> x = u / sqrt(beta) (double) and sign(x).
-__global__ __launch_bounds__(256) void lowp_finish_kernel(const float* __restrict__ U, int n, int R,
+__global__ __launch_bounds__(256) void lowp_finish_kernel(const float* __restrict__ U0, const float* __restrict__ U1,
+                                                          const float* __restrict__ U2,
+                                                          const RestartState* __restrict__ state, int n, int R,
                                                           int Rp, double sqrt_beta,
                                                           double* __restrict__ x_out,
                                                           int8_t* __restrict__ s_out) {
@@ -372,6 +422,9 @@ __global__ __launch_bounds__(256) void lowp_finish_kernel(const float* __restric
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; t < total;
          t += static_cast<int64_t>(gridDim.x) * 256) {
         const int i = static_cast<int>(t / R), j = static_cast<int>(t % R);
+        // restart j's last iterate: buffer iters_done mod 3
+        const int64_t m = state[j].iters_done % 3;
+        const float* U = m == 0 ? U0 : (m == 1 ? U1 : U2);
         const double x = ddiv(static_cast<double>(U[static_cast<int64_t>(i) * Rp + j]), sqrt_beta);
         if (x_out) x_out[t] = x;
         if (s_out) s_out[t] = x >= 0.0 ? 1 : -1;
@@ -555,28 +608,38 @@ hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const floa
                             const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
                             const float* cs_old, float* cs_new, double rho_q,
                             double alpha, double beta, double eps, int R, int64_t k,
-                            double* partials, unsigned int* ticket, double* log, RestartState* state,
+                            const double* partials_prev, double* partials, double* log, RestartState* state,
                             hipStream_t s) {
-    const dim3 grid(np / 64, Rp / 64);
+    // np / 64 row tiles per column block, and one more row of workgroups
+    // whose first Rp / 64 close the previous iteration
+    const int tiles = np / 64, cblocks = Rp / 64;
+    const dim3 grid(tiles > cblocks ? tiles : cblocks, cblocks + 1);
     if (prec == 0)
-        hipLaunchKernelGGL(lowp_step_kernel<0>, grid, dim3(MT), 0, s, np, Rp,
+        hipLaunchKernelGGL((lowp_step_kernel<0, kLowpDepth>), grid, dim3(MT), 0, s, np, Rp,
                            static_cast<const __bf16*>(Jq), rscale, U_old, U_new,
                            static_cast<const __bf16*>(Ub_old), static_cast<__bf16*>(Ub_new), cs_old,
-                           cs_new, rho_q, alpha, beta, eps, R, k, partials, ticket, log, state);
+                           cs_new, rho_q, alpha, beta, eps, R, k, partials_prev, partials, log, state);
     else
-        hipLaunchKernelGGL(lowp_step_kernel<1>, grid, dim3(MT), 0, s, np, Rp,
+        hipLaunchKernelGGL((lowp_step_kernel<1, kLowpDepth>), grid, dim3(MT), 0, s, np, Rp,
                            static_cast<const uint8_t*>(Jq), rscale, U_old, U_new,
                            static_cast<const uint8_t*>(Ub_old), static_cast<uint8_t*>(Ub_new), cs_old,
-                           cs_new, rho_q, alpha, beta, eps, R, k, partials, ticket, log, state);
+                           cs_new, rho_q, alpha, beta, eps, R, k, partials_prev, partials, log, state);
     return hipGetLastError();
 }
 
-hipError_t launch_lowp_finish(const float* U, int n, int R, int Rp, double sqrt_beta, double* x_out,
-                              int8_t* s_out, hipStream_t s) {
+hipError_t launch_lowp_close(int np, int Rp, int R, int64_t kk, const double* partials, double alpha,
+                             double beta, double eps, double* log, RestartState* state, hipStream_t s) {
+    hipLaunchKernelGGL(lowp_close_kernel, dim3(Rp / 64), dim3(MT), 0, s, partials, np / 64, Rp, R, kk, alpha,
+                       beta, eps, log, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowp_finish(const float* const* U, const RestartState* state, int n, int R, int Rp,
+                              double sqrt_beta, double* x_out, int8_t* s_out, hipStream_t s) {
     int64_t g = (static_cast<int64_t>(n) * R + 255) / 256;
     if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(lowp_finish_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, U, n, R, Rp,
-                       sqrt_beta, x_out, s_out);
+    hipLaunchKernelGGL(lowp_finish_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, U[0], U[1], U[2],
+                       state, n, R, Rp, sqrt_beta, x_out, s_out);
     return hipGetLastError();
 }
 

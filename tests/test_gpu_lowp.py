@@ -48,13 +48,15 @@ def run_lowp(J, X0, alpha, beta, iters, prec, eps=0.0):
         L.ising_destroy(ctx)
 
 
+@pytest.mark.parametrize("n,R", [(200, 64), (100, 300)])
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
-def test_lowp_zero_coupling_closed_form(prec_name):
+def test_lowp_zero_coupling_closed_form(prec_name, n, R):
     """J = 0: u-space iteration u <- cbrt(alpha u); x = u / sqrt(beta) follows
-    x^(k) = sign(x0)(a/b)^((1-3^-k)/2)|x0|^(3^-k) (FP32 storage of u)."""
+    x^(k) = sign(x0)(a/b)^((1-3^-k)/2)|x0|^(3^-k) (FP32 storage of u).  The
+    second shape has more restart blocks (5) than row tiles (4) and ragged
+    edges in both."""
     import paper_2509_01928_amd as L
     prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
-    n, R = 200, 64
     J = np.zeros((n, n))
     X0 = gen.uniform_x0(n, R, 3)
     a, b = 2.5, 7.0e4
@@ -100,14 +102,29 @@ def test_lowp_energy_gap_and_final_objective(prec_name):
     assert np.abs(E - E64).max() < 0.15 * scale
 
 
-def test_lowp_freezes_converged_restarts():
+@pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
+def test_lowp_freezes_converged_restarts(prec_name):
+    """Restarts stop on their own; each returns the iterate of the iteration
+    it stopped at: a restart's column of the product depends on that
+    restart alone, so a run of exactly iters_done iterations without a
+    tolerance gives the same column bit for bit."""
     import paper_2509_01928_amd as L
+    prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
     n, R = 256, 64
     J = gen.sk_dense(n, 4005)
     X0 = gen.uniform_x0(n, R, 5005)
     alpha = -np.linalg.eigvalsh(J)[0]
     beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
-    X, S, Hf, E, st, _ = run_lowp(J, X0, alpha, beta, 2000, L.ISING_BF16, eps=1e-3)
+    X, S, Hf, E, st, Hlog = run_lowp(J, X0, alpha, beta, 2000, prec, eps=1e-3)
     assert all(s.converged == 1 for s in st)
     assert all(s.iters_done < 2000 for s in st)
-    assert len({s.iters_done for s in st}) > 1       # restarts stop on their own
+    done = np.array([s.iters_done for s in st])
+    assert len(set(done.tolist())) > 1       # restarts stop on their own
+    for r in (int(np.argmin(done)), int(np.argmax(done))):
+        m = int(done[r])
+        Xm, Sm, _, _, stm, Hm = run_lowp(J, X0, alpha, beta, m, prec)
+        assert stm[r].iters_done == m
+        assert np.array_equal(X[:, r], Xm[:, r]), f"restart {r}: final iterate is not iteration {m}'s"
+        assert np.array_equal(S[:, r], Sm[:, r])
+        if r < 3:
+            assert np.array_equal(Hlog[r], Hm[r])
