@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6          # FP64 vector peak (FMA = 2 flops)
+DENSE_SOURCES = ("kernels_dense.hip", "step_common.h", "device_common.h")
 
 
 def parse():
@@ -33,7 +35,8 @@ def parse():
     ap.add_argument("--s5-n", type=int, default=100_000_000,
                     help="spins of the 9-bit integer instance (mean degree 10)")
     ap.add_argument("--workload", default="torus",
-                    choices=["torus", "er20000", "sk1024", "dense4096", "batch512", "s5"],
+                    choices=["torus", "er20000", "sk1024", "dense4096", "batch512", "s5", "adoch",
+                             "procedural", "tune_eta"],
                     help="torus = the 10^8-spin lattice (default line); the others print "
                          "their own JSON line")
     ap.add_argument("--steps", type=int, default=3)
@@ -52,12 +55,17 @@ def parse():
     ap.add_argument("--oracle-restarts", type=int, default=1)
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
+    ap.add_argument("--proc-n", type=int, default=65536,
+                    help="spins of the procedural sin(ij+100) instance")
+    ap.add_argument("--ingest-flops", metavar="CSV",
+                    help="record the FP64 flops per coupling of the procedural step kernel from a "
+                         "rocprofv3 counter file (SQ_INSTS_VALU_FLOPS_FP64[_TRANS]) and exit")
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(names=("kernels_csr.hip", "step_common.h", "device_common.h")) -> str:
     h = hashlib.sha256()
-    for name in ("kernels_csr.hip", "step_common.h", "device_common.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2509_01928_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -92,6 +100,46 @@ def load_traffic(kernel: str, workload: str):
     if not rec or rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernel", ""):
         return None
     return rec
+
+
+def load_flops(kernel: str, workload: str):
+    """FP64 flops per coupling of the procedural step kernel, measured by
+    rocprofv3 counters on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "flops.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(workload)
+    if not rec or rec.get("source_hash") != kernel_source_hash(DENSE_SOURCES) or kernel not in rec.get("kernel", ""):
+        return None
+    return rec
+
+
+def ingest_flops(path, n):
+    """FP64 flops per dispatch of the procedural step kernel over the n(n-1)
+    couplings it generates, stored in profiles/flops.json.  The counters add,
+    over the whole device, each executed wavefront instruction's flops per
+    lane (a fused multiply-add is two); a wavefront has 64 lanes, all active
+    in the row loop, so flops = 64 x (FLOPS_FP64 + FLOPS_FP64_TRANS)."""
+    import csv
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    step = next(k for k in vals if "dense_step_kernel" in k and "SinJ" in k)
+    c = vals[step]
+    avg = {k: sum(v) / len(v) for k, v in c.items()}
+    flops = 64.0 * (avg.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) + avg.get("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0))
+    rec = {"kernel": step, "source_hash": kernel_source_hash(DENSE_SOURCES), "n": n,
+           "dispatches": len(next(iter(c.values()))), "counters_per_dispatch": avg,
+           "fp64_flops_per_dispatch": flops, "fp64_flops_per_coupling": flops / (n * (n - 1))}
+    out = os.path.join(ROOT, "profiles", "flops.json")
+    data = json.load(open(out)) if os.path.exists(out) else {}
+    data[f"procedural{n}"] = rec
+    with open(out, "w") as f:
+        json.dump(data, f, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def ingest_pmc(paths, workload):
@@ -503,10 +551,200 @@ def bench_s5(args):
     L.ising_destroy(ctx)
 
 
+def _torus_ctx(L_side, x_extra=1):
+    """The 10^8-spin lattice context of the main bench (FP32 CSR, FP32 field)."""
+    import torch
+
+    import ising_inputs as gen
+    import paper_2509_01928_amd as L
+    seed, xseed = gen.SEEDS["torus1e4"]
+    t0 = time.time()
+    A = gen.torus_csr(L_side, seed, h_std=0.1)
+    x0 = gen.uniform_x0(A.n + x_extra, 1, xseed)[:, 0]
+    log(f"generated torus L={L_side}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    d = "cuda:0"
+    rp = torch.from_numpy(A.row_ptr).to(d)
+    col = torch.from_numpy(A.col).to(d)
+    val = torch.from_numpy(A.val).to(d)
+    h = torch.from_numpy(A.h).to(d)
+    ctx = L.ising_create_csr(A.n, A.nnz, rp, col, val, L.ISING_F32, h, L.ISING_F32)
+    del rp, col, val, h
+    torch.cuda.empty_cache()
+    return A, x0, ctx
+
+
+def bench_adoch(args):
+    """ADOCH (Alg. 2, NEXT-1) on the 10^8-spin lattice with its field: FP64
+    iterates, window q = 5, 100 iterations per step.  Each iteration is two
+    launches: the product with H(x) and H(y) and the acceptance test, then
+    the update of the accepted point."""
+    import numpy as np
+    import torch
+
+    import paper_2509_01928_amd as L
+    A, x0, ctx = _torus_ctx(args.L)
+    d = "cuda:0"
+    xd = torch.from_numpy(x0).to(d)
+    so = torch.empty(A.n, dtype=torch.int8, device=d)
+    E = torch.empty(1, dtype=torch.float64, device=d)
+    iters = 100
+    solve_ms = []
+
+    def step():
+        p, _ = L.ising_default_params(ctx, 1.0, 0)
+        p.algo, p.q = 1, 5
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+        e1.record()
+        L.ising_energy(ctx, so, 1, E)
+        solve_ms.append((e0, e1))
+
+    dt = _timed(step, args.warmup, args.steps)
+    torch.cuda.synchronize()
+    it_us = 1e3 * float(np.mean([a.elapsed_time(b) for a, b in solve_ms[args.warmup:]])) / iters
+    acc = L.ising_get_accept_log(ctx, 0, iters)
+    n, nnz, np1 = A.n, A.nnz, A.n + 1
+    # two passes over the vectors, forced by the acceptance test (a global
+    # reduction) between the product and the update:
+    #   product: offsets, indices, values, field, x^(k) (read with its
+    #            gathers), x^(k-1), z_(k-1) read, z_k written
+    #   update : x^(k), x^(k-1), z_k, z_(k-1) read, x^(k+1) written
+    prod = 4 * (n + 1) + 8 * nnz + 4 * n + 4 * 8 * np1
+    upd = 5 * 8 * np1
+    bytes_iter = prod + upd
+    achieved = bytes_iter / (it_us * 1e-6) / 1e9
+    print(json.dumps({
+        "metric": "edge-updates/s", "value": nnz * iters / dt, "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded torus lattice generator)",
+        "config": {"workload": f"ADOCH (Alg. 2, q=5) on the 2D periodic lattice {args.L}x{args.L} "
+                               f"({n} spins, {nnz} stored couplings +-1, field h~N(0,0.1^2)), "
+                               f"{iters} iterations per step + parameters + energy",
+                   "n": n, "nnz": nnz, "iters": iters, "x_storage": "f64", "q": 5},
+        "iteration_us": it_us, "energy": float(E.cpu()[0]),
+        "accepted_fraction": float(np.mean(acc)),
+        "roofline": {"kernel": "adoch_mv_kernel<float, float, true> + adoch_update_kernel",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_iteration": bytes_iter,
+                     "bytes_product": prod, "bytes_update": upd},
+    }), flush=True)
+    L.ising_destroy(ctx)
+
+
+def bench_procedural(args):
+    """Procedural dense couplings J_ij = sin(i j + 100) (Supp. Note 9,
+    NEXT-3), generated in FP64 on the fly: n = 65536, 10 DOCH iterations per
+    step, Wigner parameters, FP64 energy.  Bound by the FP64 arithmetic of
+    the sine."""
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import paper_2509_01928_amd as L
+    n = args.proc_n
+    ctx = L.ising_create_procedural(n, 1, 100.0)
+    x0 = gen.uniform_x0(n, 1, 2007)[:, 0]
+    d = "cuda:0"
+    xd = torch.from_numpy(x0).to(d)
+    so = torch.empty(n, dtype=torch.int8, device=d)
+    E = torch.empty(1, dtype=torch.float64, device=d)
+    p, lam = L.ising_default_params(ctx, 1.0, 0)
+    iters = 10
+    solve_ms = []
+
+    def step():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
+        e1.record()
+        L.ising_energy(ctx, so, 1, E)
+        solve_ms.append((e0, e1))
+
+    dt = _timed(step, args.warmup, args.steps)
+    torch.cuda.synchronize()
+    it_us = 1e3 * float(np.mean([a.elapsed_time(b) for a, b in solve_ms[args.warmup:]])) / iters
+    couplings = n * (n - 1)
+    flops = load_flops("dense_step_kernel", f"procedural{n}")
+    roof = {"kernel": "dense_step_kernel<double, double, false, SinJ>", "bound": "alu",
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "couplings_per_s": couplings / (it_us * 1e-6)}
+    if flops:
+        achieved = flops["fp64_flops_per_coupling"] * couplings / (it_us * 1e-6) / 1e12
+        roof.update({"achieved": achieved, "frac": achieved / FP64_PEAK_TFLOPS,
+                     "fp64_flops_per_coupling": flops["fp64_flops_per_coupling"]})
+    else:
+        roof.update({"achieved": None, "frac": None})
+    print(json.dumps({
+        "metric": "edge-updates/s", "value": couplings * iters / dt, "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "procedural (J_ij = sin(i j + 100), generated on the fly)",
+        "config": {"workload": f"procedural dense couplings sin(ij+100), n={n}, {iters} DOCH "
+                               f"iterations per step + energy (FP64)", "n": n, "iters": iters},
+        "iteration_us": it_us, "energy": float(E.cpu()[0]), "lambda_hat": lam,
+        "roofline": roof,
+    }), flush=True)
+    L.ising_destroy(ctx)
+
+
+def bench_tune_eta(args):
+    """eta tuning by short probe runs (Supp. Note 6, NEXT-4) on the
+    10^8-spin lattice: 8 values of eta in (0, 2], 10 DOCH iterations and the
+    energy of the rounded spins each; the best eta's parameters are kept."""
+    import numpy as np
+    import torch
+
+    import paper_2509_01928_amd as L
+    A, x0, ctx = _torus_ctx(args.L)
+    d = "cuda:0"
+    xd = torch.from_numpy(x0).to(d)
+    etas = np.array([0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0])
+    probe = 10
+    p0, _ = L.ising_default_params(ctx, 1.0, 0)
+    g, w, _ = L.ising_autotune(ctx, xd, 10, p0)
+    out = {}
+
+    def step():
+        out["r"] = L.ising_tune_eta(ctx, xd, etas, probe)
+
+    dt = _timed(step, args.warmup, args.steps)
+    best, best_eta, energies = out["r"]
+    n, nnz = A.n, A.nnz
+    bytes_iter = 4 * (n + 1) + 8 * nnz + 2 * 8 * (n + 1) + 4 * n
+    sweep_bytes = bytes_iter * probe * len(etas)
+    print(json.dumps({
+        "metric": "eta candidates/s", "value": len(etas) / dt, "unit": "candidates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded torus lattice generator)",
+        "config": {"workload": f"eta sweep of {len(etas)} values x {probe} probe iterations on the "
+                               f"2D periodic lattice {args.L}x{args.L} with field (FP64 iterate)",
+                   "n": A.n, "nnz": A.nnz, "etas": etas.tolist(), "probe_iters": probe,
+                   "kernel_geometry": g, "workgroups_per_cu": w},
+        "probe_edge_updates_per_s": A.nnz * probe * len(etas) / dt,
+        "best_eta": best_eta, "probe_energies": energies.tolist(),
+        # whole sweep: the probes' algorithmic bytes (FP64 iterate, row
+        # offsets counted) over the wall time, energies and setup included
+        "roofline": {"kernel": step_kernel_name(g, "f64", True), "bound": "hbm",
+                     "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_iteration": bytes_iter},
+    }), flush=True)
+    L.ising_destroy(ctx)
+
+
 def main():
     args = parse()
     if args.ingest_pmc:
         ingest_pmc(args.ingest_pmc, f"torus{args.L}_{args.x_dtype}")
+        return
+    if args.ingest_flops:
+        ingest_flops(args.ingest_flops, args.proc_n)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
@@ -514,7 +752,8 @@ def main():
         sys.exit(2)
     if args.workload != "torus":
         {"er20000": bench_er20000, "sk1024": bench_sk1024, "dense4096": bench_dense4096,
-         "batch512": bench_batch512, "s5": bench_s5}[args.workload](args)
+         "batch512": bench_batch512, "s5": bench_s5, "adoch": bench_adoch,
+         "procedural": bench_procedural, "tune_eta": bench_tune_eta}[args.workload](args)
         return
     import numpy as np
     import torch

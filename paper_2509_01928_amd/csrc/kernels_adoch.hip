@@ -23,7 +23,10 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
 
-template <typename VT, typename HT, bool FIELD>
+// RL = 4: every row holds 4 entries starting at 4 i (the lattice), read as
+// one 16-byte chunk of indices and one of values without the row offsets;
+// RL = 0: offsets read, entries one at a time.  Same order either way.
+template <typename VT, typename HT, bool FIELD, int RL>
 __global__ __launch_bounds__(NT) void adoch_mv_kernel(
     int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const VT* __restrict__ val, const HT* __restrict__ h, const double* __restrict__ x,
@@ -39,7 +42,17 @@ __global__ __launch_bounds__(NT) void adoch_mv_kernel(
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * NT) {
         double zi = 0.0;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) zi = dadd(zi, dmul(static_cast<double>(val[e]), x[col[e]]));
+        if constexpr (RL == 4) {
+            const auto cv = ld_stream4(col + 4 * i);
+            const auto vv = ld_stream4(val + 4 * i);
+            const double g[4] = {x[cv.x], x[cv.y], x[cv.z], x[cv.w]};
+            const double v[4] = {static_cast<double>(vv.x), static_cast<double>(vv.y),
+                                 static_cast<double>(vv.z), static_cast<double>(vv.w)};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zi = dadd(zi, dmul(v[q], g[q]));
+        } else {
+            for (int e = rp[i]; e < rp[i + 1]; ++e) zi = dadd(zi, dmul(static_cast<double>(val[e]), x[col[e]]));
+        }
         const double xi = x[i];
         if (FIELD) {
             const double hi = static_cast<double>(h[i]);
@@ -197,9 +210,17 @@ hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, 
                            double* z, const AdochArgs& a, hipStream_t s) {
     const int grid = grid_rows(A.n);
     const bool field = A.h != nullptr;
-#define DOCH_ADOCH_MV(VT, HT, F)                                                                  \
-    hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F>), dim3(grid), dim3(NT), 0, s, A.n, A.rp, A.col, \
-                       static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), x, xp, zp, z, a)
+#define DOCH_ADOCH_MV(VT, HT, F)                                                                   \
+    do {                                                                                           \
+        if (A.row_len == 4)                                                                        \
+            hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4>), dim3(grid), dim3(NT), 0, s, A.n, A.rp, \
+                               A.col, static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), x, xp, \
+                               zp, z, a);                                                          \
+        else                                                                                       \
+            hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 0>), dim3(grid), dim3(NT), 0, s, A.n, A.rp, \
+                               A.col, static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), x, xp, \
+                               zp, z, a);                                                          \
+    } while (0)
     if (A.vt == ISING_I16) {
         if (!field) DOCH_ADOCH_MV(int16_t, float, false);
         else if (A.ht == ISING_F64) DOCH_ADOCH_MV(int16_t, double, true);

@@ -59,6 +59,48 @@ __device__ __forceinline__ double lane_row_dot(const JS& J, int64_t i, V vec, in
     return p;
 }
 
+// Lane's share of row i of J_ij = sin(i j + seed) times a vector, in the
+// same order as lane_row_dot.  The lane's arguments i j + seed, j = lane,
+// lane + 64, ..., form an arithmetic progression with step d = 64 i, so
+// (sin, cos) advance by the rotation (cos d, sin d) -- four products per
+// coupling instead of a range-reduced sine -- and restart from an exact
+// sin/cos every kSinRestart steps, which bounds the accumulated rounding to
+// a few dozen ulp.  All angles are integers (plus the seed) below 2^53, so
+// each restart is exact to the sine's own accuracy.
+constexpr int kSinRestart = 32;
+template <typename V>
+__device__ __forceinline__ double lane_row_dot_sin(const SinJ& J, int64_t i, V vec, int64_t n, int lane) {
+    constexpr int U = 8;
+    const double di = static_cast<double>(i);
+    double sd, cd;
+    sincos(dmul(64.0, di), &sd, &cd);
+    double p = 0.0;
+    int64_t j = lane;
+    int since = kSinRestart;
+    double sv = 0.0, cv = 0.0;
+    for (; j < n; j += U * kWave) {
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = j + u * kWave < n ? vec(j + u * kWave) : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t jj = j + u * kWave;
+            if (jj < n) {
+                if (since == kSinRestart) {
+                    sincos(dadd(dmul(di, static_cast<double>(jj)), J.seed), &sv, &cv);
+                    since = 0;
+                }
+                p = dadd(p, dmul(jj == i ? 0.0 : sv, xv[u]));
+                const double sn = fma(sv, cd, cv * sd);
+                cv = fma(cv, cd, -(sv * sd));
+                sv = sn;
+                ++since;
+            }
+        }
+    }
+    return p;
+}
+
 template <typename XT, typename HT, bool FIELD, typename JS>
 __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
                                                         const HT* __restrict__ h, StepArgs a) {
@@ -75,7 +117,9 @@ __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
         double p = 0.0;
-        p = lane_row_dot(J, i, [&](int64_t j) { return static_cast<double>(x[j]); }, n, lane);
+        auto xv = [&](int64_t j) { return static_cast<double>(x[j]); };
+        if constexpr (std::is_same<JS, SinJ>::value) p = lane_row_dot_sin(J, i, xv, n, lane);
+        else p = lane_row_dot(J, i, xv, n, lane);
         const double z0 = wave_sum(p);
         if (lane == 0) {
             double z = z0;

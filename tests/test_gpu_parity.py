@@ -524,6 +524,38 @@ def test_procedural_sin_couplings_parity():
     assert float(E.cpu()[0]) == pytest.approx(orc.energy_dense(J, s), rel=1e-11)
 
 
+def test_procedural_large_arguments():
+    """n = 8192: arguments i j + seed up to 6.7e7 and rows long enough for many
+    restarts of the step kernel's sine recurrence; 20 iterations against the
+    oracle on the materialised matrix."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    n, seed, iters = 8192, 100.0, 20
+    i = np.arange(n, dtype=np.float64)
+    J = np.sin(np.outer(i, i) + seed)
+    np.fill_diagonal(J, 0.0)
+    x0 = gen.uniform_x0(n, 1, 152)[:, 0]
+    alpha = 2.0 * np.sqrt(n) * float(np.sqrt((J ** 2).sum() / (n * (n - 1))))
+    beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    tr = orc.doch_dense(J, x0, alpha, beta, iters)
+    ctx = Lb.ising_create_procedural(n, 1, seed)
+    try:
+        q = Lb.ising_params()
+        q.alpha, q.beta, q.eps, q.algo, q.q, q.x_dtype, q.reserved = alpha, beta, 0.0, 0, 5, Lb.ISING_F64, 0
+        xd = torch.from_numpy(x0).to("cuda:0")
+        xo = torch.empty_like(xd)
+        so = torch.empty(n, dtype=torch.int8, device="cuda:0")
+        Lb.ising_solve(ctx, xd, 1, iters, q, xo, so)
+        H, r = Lb.ising_get_log(ctx, 0, 0, iters)
+        torch.cuda.synchronize()
+        x, s = xo.cpu().numpy(), so.cpu().numpy()
+    finally:
+        Lb.ising_destroy(ctx)
+    assert_iterate_parity(x, tr.x, "procedural n=8192")
+    assert_spin_parity(s, tr.x, orc.sign(tr.x), "procedural n=8192")
+    assert_log_parity(H, r, tr, "procedural n=8192")
+
+
 def test_constant_row_length_detected():
     """A CSR whose rows all hold d entries is recognised (row i starts at d i)."""
     import paper_2509_01928_amd as Lb
