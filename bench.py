@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--oracle-restarts", type=int, default=1)
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
+    ap.add_argument("--tune-instance", choices=["torus", "s5"], default="torus",
+                    help="tune_eta: the lattice or the Supp. Alg. S5 instance")
     ap.add_argument("--proc-n", type=int, default=65536,
                     help="spins of the procedural sin(ij+100) instance")
     ap.add_argument("--ingest-flops", metavar="CSV",
@@ -693,20 +695,36 @@ def bench_procedural(args):
 
 
 def bench_tune_eta(args):
-    """eta tuning by short probe runs (Supp. Note 6, NEXT-4) on the
-    10^8-spin lattice: 8 values of eta in (0, 2], 10 DOCH iterations and the
-    energy of the rounded spins each; the best eta's parameters are kept."""
+    """eta tuning by short probe runs (Supp. Note 6, NEXT-4): 8 values of eta
+    in (0, 2], 10 probe iterations each (FP64 iterates) and the energy of the
+    rounded spins; the best eta's parameters are kept.  On a CSR context the
+    probes run as restarts of one pass over the couplings; the same probes
+    one eta per call give the sequential reference.  --tune-instance picks
+    the 10^8-spin lattice (streaming-bound) or the Supp. Alg. S5 instance of
+    10^8 spins and ~10^9 couplings (random-gather-bound)."""
     import numpy as np
     import torch
 
+    import ising_inputs as gen
     import paper_2509_01928_amd as L
-    A, x0, ctx = _torus_ctx(args.L)
     d = "cuda:0"
+    if args.tune_instance == "s5":
+        n = args.s5_n
+        A = gen.s5_csr(n, 100.0 * 10.0 / (n - 1), 1006)
+        x0 = gen.uniform_x0(n, 1, 2006)[:, 0]
+        rp = torch.from_numpy(A.row_ptr).to(d)
+        col = torch.from_numpy(A.col).to(d)
+        val = torch.from_numpy(A.val.astype(np.int16)).to(d)
+        ctx = L.ising_create_csr(A.n, A.nnz, rp, col, val, L.ISING_I16)
+        del rp, col, val
+        torch.cuda.empty_cache()
+        label = f"Supp. Alg. S5 instance n={A.n}, mean degree 10, int16 values, h=0"
+    else:
+        A, x0, ctx = _torus_ctx(args.L)
+        label = f"2D periodic lattice {args.L}x{args.L} with field"
     xd = torch.from_numpy(x0).to(d)
     etas = np.array([0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0])
     probe = 10
-    p0, _ = L.ising_default_params(ctx, 1.0, 0)
-    g, w, _ = L.ising_autotune(ctx, xd, 10, p0)
     out = {}
 
     def step():
@@ -714,23 +732,33 @@ def bench_tune_eta(args):
 
     dt = _timed(step, args.warmup, args.steps)
     best, best_eta, energies = out["r"]
+
+    def sequential():
+        out["e"] = [L.ising_tune_eta(ctx, xd, etas[k:k + 1], probe)[2][0] for k in range(len(etas))]
+
+    dt_seq = _timed(sequential, 0, 1)
+    assert np.array_equal(np.array(out["e"]), energies), "batched and sequential probes differ"
     n, nnz = A.n, A.nnz
-    bytes_iter = 4 * (n + 1) + 8 * nnz + 2 * 8 * (n + 1) + 4 * n
-    sweep_bytes = bytes_iter * probe * len(etas)
+    vb = 2 if args.tune_instance == "s5" else 4
+    field = args.tune_instance != "s5"
+    # one pass per probe iteration for all 8 probes: offsets, indices and
+    # values, the field, and 8 FP64 iterates read and written
+    bytes_iter = 4 * (n + 1) + (4 + vb) * nnz + (4 * n if field else 0) + 2 * 8 * len(etas) * (n + 1)
+    sweep_bytes = bytes_iter * probe
     print(json.dumps({
         "metric": "eta candidates/s", "value": len(etas) / dt, "unit": "candidates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded torus lattice generator)",
+        "data": "synthetic",
         "config": {"workload": f"eta sweep of {len(etas)} values x {probe} probe iterations on the "
-                               f"2D periodic lattice {args.L}x{args.L} with field (FP64 iterate)",
-                   "n": A.n, "nnz": A.nnz, "etas": etas.tolist(), "probe_iters": probe,
-                   "kernel_geometry": g, "workgroups_per_cu": w},
-        "probe_edge_updates_per_s": A.nnz * probe * len(etas) / dt,
+                               f"{label} (FP64 iterates), probes as restarts of one pass",
+                   "n": n, "nnz": nnz, "etas": etas.tolist(), "probe_iters": probe},
+        "sequential_ms_per_sweep": 1e3 * dt_seq, "speedup_vs_sequential": dt_seq / dt,
+        "probe_edge_updates_per_s": nnz * probe * len(etas) / dt,
         "best_eta": best_eta, "probe_energies": energies.tolist(),
-        # whole sweep: the probes' algorithmic bytes (FP64 iterate, row
-        # offsets counted) over the wall time, energies and setup included
-        "roofline": {"kernel": step_kernel_name(g, "f64", True), "bound": "hbm",
+        # the batched pass's algorithmic bytes over the wall time of whole
+        # sweeps (energies and parameter setting included)
+        "roofline": {"kernel": "csr_sweep_kernel", "bound": "hbm",
                      "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_iteration": bytes_iter},

@@ -203,6 +203,7 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->rowabs);
     dev_free(c->cut_tmp);
     dev_free(c->tune_s);
+    dev_free(c->sweep_x);
     dev_free(c->lp_cs);
     dev_free(c->lp_colmax);
     for (auto& b : c->lp_u) dev_free(b);
@@ -1433,29 +1434,82 @@ ising_status ising_tune_eta(ising_ctx* ctx, const double* x0_dev, int32_t count,
     if (st != ISING_OK) return st;
     const double lambda = ctx->last_lambda, rowsum = ctx->last_rowsum;
     const double np = static_cast<double>(ctx->np);
-    if (!ctx->tune_s) HIP_OK(dev_alloc(&ctx->tune_s, static_cast<size_t>(ctx->n)), "hipMalloc(spins)");
     if (!ctx->cut_tmp) HIP_OK(dev_alloc(&ctx->cut_tmp, 2 * kMaxR * sizeof(double)), "hipMalloc(energies)");
-    int best = -1;
-    double best_E = 0.0;
-    ising_params best_p = p1;
+    std::vector<ising_params> ps(static_cast<size_t>(count), p1);
+    std::vector<double> Es(static_cast<size_t>(count), 0.0);
     for (int k = 0; k < count; ++k) {
-        ising_params p = p1;
-        p.alpha = etas_host[k] * lambda;
-        p.beta = std::pow(np, 1.5) * (p.alpha + rowsum);
-        st = ising_solve(ctx, x0_dev, 1, probe_iters, &p, nullptr, ctx->tune_s, nullptr, stream);
-        if (st != ISING_OK) return st;
-        st = ising_energy(ctx, ctx->tune_s, 1, ctx->cut_tmp, nullptr, stream);
-        if (st != ISING_OK) return st;
-        double E = 0.0;
-        HIP_OK(hipMemcpyAsync(&E, ctx->cut_tmp, sizeof(double), hipMemcpyDeviceToHost, s), "copy energy");
-        HIP_OK(hipStreamSynchronize(s), "sync");
-        if (energies_host) energies_host[k] = E;
-        if (best < 0 || E < best_E) {
-            best = k;
-            best_E = E;
-            best_p = p;
-        }
+        ps[k].alpha = etas_host[k] * lambda;
+        ps[k].beta = std::pow(np, 1.5) * (ps[k].alpha + rowsum);
     }
+    if (!ctx->dense) {
+        // CSR: up to 8 probes at a time as restarts of one pass over the
+        // couplings (each probe's iterates are those ising_solve computes)
+        const int rmax = std::min<int>(count, doch::kSweepMaxR);
+        HIP_OK(ensure(&ctx->sweep_x, &ctx->sweep_x_bytes, 2 * static_cast<size_t>(ctx->np) * rmax * sizeof(double)),
+               "hipMalloc(sweep iterates)");
+        HIP_OK(ensure(&ctx->tune_s, &ctx->tune_s_bytes, static_cast<size_t>(ctx->n) * rmax), "hipMalloc(spins)");
+        const int grid = doch::sweep_grid(ctx->n);
+        HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
+                      static_cast<size_t>(grid) * rmax * doch::kNumPartials * sizeof(double)),
+               "hipMalloc(partials)");
+        st = ensure_solve_state(ctx, 1, rmax);
+        if (st != ISING_OK) return st;
+        const CsrView cv = csr_view(ctx);
+        for (int c0 = 0; c0 < count; c0 += doch::kSweepMaxR) {
+            const int R = std::min(doch::kSweepMaxR, count - c0);
+            if (R == 1) {
+                // a lone probe runs on the single-restart path
+                st = ising_solve(ctx, x0_dev, 1, probe_iters, &ps[c0], nullptr, ctx->tune_s, nullptr, stream);
+                if (st != ISING_OK) return st;
+                st = ising_energy(ctx, ctx->tune_s, 1, ctx->cut_tmp, nullptr, stream);
+                if (st != ISING_OK) return st;
+                HIP_OK(hipMemcpyAsync(Es.data() + c0, ctx->cut_tmp, sizeof(double), hipMemcpyDeviceToHost, s),
+                       "copy energy");
+                continue;
+            }
+            double* X[2] = {ctx->sweep_x, ctx->sweep_x + static_cast<size_t>(ctx->np) * R};
+            HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, nullptr, s), "init");
+            HIP_OK(doch::launch_sweep_load(x0_dev, ctx->np, R, X[0], s), "load sweep");
+            doch::SweepArgs a{};
+            a.R = R;
+            for (int r = 0; r < R; ++r) {
+                a.alpha[r] = ps[c0 + r].alpha;
+                a.beta[r] = ps[c0 + r].beta;
+            }
+            a.partials = ctx->partials;
+            a.tickets = ctx->ticket;
+            a.state = ctx->state;
+            for (int64_t k = 0; k < probe_iters; ++k) {
+                a.x_old = X[k & 1];
+                a.x_new = X[(k + 1) & 1];
+                a.k = k;
+                HIP_OK(doch::launch_sweep_step(cv, a, s), "sweep step");
+            }
+            HIP_OK(doch::launch_sweep_round(X[probe_iters & 1], ctx->n, R, ctx->has_field, ctx->tune_s, s), "round");
+            st = ising_energy(ctx, ctx->tune_s, R, ctx->cut_tmp, nullptr, stream);
+            if (st != ISING_OK) return st;
+            HIP_OK(hipMemcpyAsync(Es.data() + c0, ctx->cut_tmp, R * sizeof(double), hipMemcpyDeviceToHost, s),
+                   "copy energies");
+        }
+        HIP_OK(hipStreamSynchronize(s), "sync");
+    } else {
+        HIP_OK(ensure(&ctx->tune_s, &ctx->tune_s_bytes, static_cast<size_t>(ctx->n)), "hipMalloc(spins)");
+        for (int k = 0; k < count; ++k) {
+            st = ising_solve(ctx, x0_dev, 1, probe_iters, &ps[k], nullptr, ctx->tune_s, nullptr, stream);
+            if (st != ISING_OK) return st;
+            st = ising_energy(ctx, ctx->tune_s, 1, ctx->cut_tmp, nullptr, stream);
+            if (st != ISING_OK) return st;
+            HIP_OK(hipMemcpyAsync(Es.data() + k, ctx->cut_tmp, sizeof(double), hipMemcpyDeviceToHost, s),
+                   "copy energy");
+        }
+        HIP_OK(hipStreamSynchronize(s), "sync");
+    }
+    int best = 0;
+    for (int k = 0; k < count; ++k) {
+        if (energies_host) energies_host[k] = Es[k];
+        if (Es[k] < Es[best]) best = k;
+    }
+    const ising_params best_p = ps[best];
     *best_out = best_p;
     if (best_eta_out) *best_eta_out = etas_host[best];
     return ISING_OK;

@@ -142,6 +142,19 @@ struct ResidentArgs {
     ResidentSync* sync;
 };
 
+// ---- eta sweeps as restarts of one pass (kernels_sweep.hip) ----
+constexpr int kSweepMaxR = 8;
+struct SweepArgs {
+    const double* x_old;    // (n' x R) restart-interleaved FP64 iterates
+    double* x_new;
+    int R;                  // 1..kSweepMaxR
+    int64_t k;
+    double alpha[kSweepMaxR], beta[kSweepMaxR];
+    double* partials;       // [grid][R][kNumPartials]
+    unsigned int* tickets;  // a grouped grid ticket (zero between launches)
+    RestartState* state;    // [R]
+};
+
 // ---- batches of independent instances (kernels_batch.hip) ----
 constexpr int kBatchThreads = 512;
 
@@ -251,6 +264,9 @@ struct ising_ctx {
     double last_lambda = 0.0;            // lambda_hat and max row sum of the last
     double last_rowsum = 0.0;            // ising_default_params call
     int8_t* tune_s = nullptr;            // ising_tune_eta: rounded probe spins
+    size_t tune_s_bytes = 0;
+    double* sweep_x = nullptr;           // ising_tune_eta: two interleaved iterate blocks
+    size_t sweep_x_bytes = 0;
     float* lp_cs = nullptr;              // FP8: restart scales, three buffers of kMaxR
     unsigned int* lp_colmax = nullptr;   // FP8: start column maxima (float bits)
     int lp_np = 0;                       // padded order (multiple of 256)
@@ -370,6 +386,12 @@ int resident_row_groups(bool dense, int64_t n);
 hipError_t launch_resident_reset(ResidentSync* sy, hipStream_t s);
 hipError_t launch_resident_dense(const DenseView& A, const ResidentArgs& a, hipStream_t s);
 hipError_t launch_resident_csr(const CsrView& A, const ResidentArgs& a, hipStream_t s);
+
+// ---- launchers (kernels_sweep.hip) ----
+int sweep_grid(int64_t n);
+hipError_t launch_sweep_step(const CsrView& A, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_load(const double* x0, int64_t np, int R, double* X, hipStream_t s);
+hipError_t launch_sweep_round(const double* X, int64_t n, int R, bool field, int8_t* S, hipStream_t s);
 
 // ---- launchers (kernels_common.hip) ----
 hipError_t launch_cut(const double* E, const int64_t* E_int, const MatrixStats* ms, int R, double* cut,

@@ -568,20 +568,34 @@ def test_constant_row_length_detected():
 
 
 # ------------------------------------------------------ eta tuning (Supp. Note 6)
-@pytest.mark.parametrize("case", ["er", "torus_field"])
+@pytest.mark.parametrize("case", ["er", "torus_field", "er_two_groups", "er_lone", "single"])
 def test_tune_eta_matches_oracle_probes(case):
     """Short probe runs per eta: every probe energy and the chosen eta agree
-    with the oracle's own probe runs (parameters by eq:alphabeta)."""
+    with the oracle's own probe runs (parameters by eq:alphabeta).  On CSR
+    contexts the probes run as restarts of one pass, eight at a time: the
+    cases cover one partial group (7 values), two groups (11: 8 + 3), a full
+    group and a lone probe (9: 8 + 1, the lone one on the single-restart
+    path) and a single one-iteration probe."""
     import torch
     import paper_2509_01928_amd as Lb
+    etas = [0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0]
+    probe = 8
     if case == "er":
         A = gen.er_csr(2000, 8.0, 201)
         x0 = gen.uniform_x0(A.n, 1, 202)[:, 0]
+    elif case in ("er_two_groups", "er_lone"):
+        A = gen.er_csr(3000, 5.0, 205)
+        x0 = gen.uniform_x0(A.n, 1, 206)[:, 0]
+        # 11 = 8 + 3 restarts; 9 = 8 + a lone probe
+        etas = [0.1 + 0.18 * k for k in range(11 if case == "er_two_groups" else 9)]
+        probe = 5
+    elif case == "single":
+        A = gen.er_csr(500, 4.0, 207)
+        x0 = gen.uniform_x0(A.n, 1, 208)[:, 0]
+        etas, probe = [1.3], 1
     else:
         A = gen.torus_csr(40, 203, h_std=1.0)
         x0 = gen.uniform_x0(A.n + 1, 1, 204)[:, 0]
-    etas = [0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0]
-    probe = 8
     B = orc.problem_matrix(A)
     E_ref = []
     for eta in etas:
