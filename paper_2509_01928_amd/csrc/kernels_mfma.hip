@@ -36,12 +36,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int MT = 256;        // threads per workgroup
-#ifndef DOCH_LOWP_DEPTH
-#define DOCH_LOWP_DEPTH 2
-#endif
 // stages of J and restart rows a thread keeps in flight (256 bytes of each of
-// 64 rows per stage, 32 KB per workgroup)
-constexpr int kLowpDepth = DOCH_LOWP_DEPTH;
+// 64 rows per stage, 32 KB per workgroup); 2 to 12 measured the same
+constexpr int kLowpDepth = 2;
 
 template <int PREC> struct Prec;
 template <> struct Prec<0> {   // BF16
