@@ -59,47 +59,76 @@ __device__ __forceinline__ double lane_row_dot(const JS& J, int64_t i, V vec, in
     return p;
 }
 
-// Lane's share of row i of J_ij = sin(i j + seed) times a vector, in the
-// same order as lane_row_dot.  The lane's arguments i j + seed, j = lane,
-// lane + 64, ..., form an arithmetic progression with step d = 64 i, so
-// (sin, cos) advance by the rotation (cos d, sin d) -- four products per
-// coupling instead of a range-reduced sine -- and restart from an exact
+// Lane's share of RW consecutive rows i0 .. i0 + RW - 1 of J_ij = sin(i j +
+// seed) times a vector, in the order of lane_row_dot (j = lane, lane + 64,
+// ...), each loaded x_j serving all RW rows.  A row's arguments i j + seed
+// along the lane form an arithmetic progression with step d = 64 i, so its
+// (sin, cos) pair advances by the rotation (cos d, sin d) -- four products
+// per coupling instead of a range-reduced sine -- and restarts from an exact
 // sin/cos every kSinRestart steps, which bounds the accumulated rounding to
 // a few dozen ulp.  All angles are integers (plus the seed) below 2^53, so
 // each restart is exact to the sine's own accuracy.
 constexpr int kSinRestart = 32;
-template <typename V>
-__device__ __forceinline__ double lane_row_dot_sin(const SinJ& J, int64_t i, V vec, int64_t n, int lane) {
-    constexpr int U = 8;
-    const double di = static_cast<double>(i);
-    double sd, cd;
-    sincos(dmul(64.0, di), &sd, &cd);
-    double p = 0.0;
+template <int RW, typename V>
+__device__ __forceinline__ void lane_rows_dot_sin(const SinJ& J, int64_t i0, V vec, int64_t n, int lane,
+                                                  double (&p)[RW]) {
+    constexpr int U = 8;                         // steps per batch; kSinRestart is 4 batches
+    static_assert(kSinRestart % U == 0, "restarts fall on batch boundaries");
+    double di[RW], sd[RW], cd[RW], sv[RW], cv[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        di[r] = static_cast<double>(i0 + r);
+        sincos(dmul(64.0, di[r]), &sd[r], &cd[r]);
+        p[r] = 0.0;
+        sv[r] = cv[r] = 0.0;
+    }
+    auto restart = [&](int64_t jj) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) sincos(dadd(dmul(di[r], static_cast<double>(jj)), J.seed), &sv[r], &cv[r]);
+    };
+    auto rotate = [&]() {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const double sn = fma(sv[r], cd[r], cv[r] * sd[r]);
+            cv[r] = fma(cv[r], cd[r], -(sv[r] * sd[r]));
+            sv[r] = sn;
+        }
+    };
+    // one coupling step of every row; the diagonal (J_ii = 0) is tested only
+    // in batches that can hold it
+    auto step = [&](int64_t jj, double x, bool maybe_diag) {
+        if (maybe_diag) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) p[r] = dadd(p[r], dmul(jj == i0 + r ? 0.0 : sv[r], x));
+        } else {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) p[r] = dadd(p[r], dmul(sv[r], x));
+        }
+        rotate();
+    };
     int64_t j = lane;
-    int since = kSinRestart;
-    double sv = 0.0, cv = 0.0;
-    for (; j < n; j += U * kWave) {
+    int batch = 0;
+    // full batches: all U steps in range
+    for (; j + (U - 1) * kWave < n; j += U * kWave, ++batch) {
+        if ((batch & (kSinRestart / U - 1)) == 0) restart(j);
         double xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = j + u * kWave < n ? vec(j + u * kWave) : 0.0;
+        for (int u = 0; u < U; ++u) xv[u] = vec(j + u * kWave);
+        // the batch's steps j, j + 64, ..., j + 448 meet rows i0 .. i0 + RW - 1
+        // only if those rows lie within [j, j + 448]
+        const bool maybe_diag = i0 + RW - 1 >= j && i0 <= j + (U - 1) * kWave;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t jj = j + u * kWave;
-            if (jj < n) {
-                if (since == kSinRestart) {
-                    sincos(dadd(dmul(di, static_cast<double>(jj)), J.seed), &sv, &cv);
-                    since = 0;
-                }
-                p = dadd(p, dmul(jj == i ? 0.0 : sv, xv[u]));
-                const double sn = fma(sv, cd, cv * sd);
-                cv = fma(cv, cd, -(sv * sd));
-                sv = sn;
-                ++since;
-            }
-        }
+        for (int u = 0; u < U; ++u) step(j + u * kWave, xv[u], maybe_diag);
     }
-    return p;
+    // the last, partial batch
+    for (int u = 0; j < n; j += kWave, ++u) {
+        if (u == 0 && (batch & (kSinRestart / U - 1)) == 0) restart(j);
+        step(j, vec(j), true);
+    }
 }
+
+// rows of the procedural couplings a wavefront forms together
+constexpr int kSinRows = 4;
 
 template <typename XT, typename HT, bool FIELD, typename JS>
 __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
@@ -114,12 +143,36 @@ __global__ __launch_bounds__(NT) void dense_step_kernel(int64_t n, JS J,
     double acc[kNumPartials];
 #pragma unroll
     for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+    auto xv = [&](int64_t j) { return static_cast<double>(x[j]); };
+    if constexpr (std::is_same<JS, SinJ>::value) {
+        // kSinRows rows per wavefront; lane r updates row i0 + r with the
+        // row total as lane 0 forms it
+        constexpr int RW = kSinRows;
+        for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
+             i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
+            double p[RW];
+            lane_rows_dot_sin<RW>(J, i0, xv, n, lane, p);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const double z0 = __shfl(wave_sum(p[r]), 0, kWave);
+                const int64_t i = i0 + r;
+                if (lane == r && i < n) {
+                    double z = z0;
+                    double hv = 0.0;
+                    if (FIELD) {
+                        hv = static_cast<double>(h[i]);
+                        z = dadd(z, dmul(hv, t_old));
+                    }
+                    update_row<XT>(z, static_cast<double>(x[i]), hv, FIELD, a, xn, i, acc);
+                }
+            }
+        }
+        step_epilogue<XT, NT>(a, acc, red, n, FIELD, t_old);
+        return;
+    }
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
          i += static_cast<int64_t>(gridDim.x) * NW) {
-        double p = 0.0;
-        auto xv = [&](int64_t j) { return static_cast<double>(x[j]); };
-        if constexpr (std::is_same<JS, SinJ>::value) p = lane_row_dot_sin(J, i, xv, n, lane);
-        else p = lane_row_dot(J, i, xv, n, lane);
+        double p = lane_row_dot(J, i, xv, n, lane);
         const double z0 = wave_sum(p);
         if (lane == 0) {
             double z = z0;
