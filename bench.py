@@ -737,7 +737,9 @@ def bench_tune_eta(args):
         out["e"] = [L.ising_tune_eta(ctx, xd, etas[k:k + 1], probe)[2][0] for k in range(len(etas))]
 
     dt_seq = _timed(sequential, 0, 1)
-    assert np.array_equal(np.array(out["e"]), energies), "batched and sequential probes differ"
+    # the same spins; the energies' field sums may differ in the last bits
+    # (the 8-restart energy adds its workgroups' sums in another order)
+    assert np.allclose(np.array(out["e"]), energies, rtol=1e-12, atol=1e-6), "batched and sequential probes differ"
     n, nnz = A.n, A.nnz
     vb = 2 if args.tune_instance == "s5" else 4
     field = args.tune_instance != "s5"

@@ -1368,6 +1368,8 @@ ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double
     // partials: per (workgroup, restart) 3 doubles, or for the tiled dense
     // kernel per (64-row tile, padded restart) 2
     size_t need = static_cast<size_t>(grid) * R * 3;
+    if (!ctx->dense && R >= 2 && R <= 8)
+        need = std::max(need, static_cast<size_t>(doch::csr_energy8_grid(ctx->n)) * R * 3);
     if (ctx->dense && R >= doch::kTiledEnergyMinR)
         need = std::max(need, static_cast<size_t>((ctx->n + 63) / 64) * ((R + 63) / 64 * 64) * 2);
     Scratch sc;

@@ -302,6 +302,9 @@ hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s);
 void csr_geometry(int geometry, int* rows, int* span);
 hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs& a,
                            hipStream_t s);
+// workgroups of the one-pass energy for 2..8 restarts (its partials: 3 per
+// workgroup and restart)
+int csr_energy8_grid(int64_t n);
 hipError_t launch_csr_energy(const CsrView& A, const int8_t* s_spins, int R,
                              double* partials, unsigned int* ticket, int grid,
                              double* E, int64_t* E_int, hipStream_t s);

@@ -422,6 +422,86 @@ __global__ __launch_bounds__(NT) void csr_energy_kernel(
     }
 }
 
+// The same for 2 <= R <= 8 restarts in one pass over the couplings: eight
+// lanes per row, lane r holding restart r, so the spins of a column are one
+// run of R bytes and the row's entries are read once for all restarts.  The
+// last workgroup adds the workgroups' sums of each restart in index order.
+template <typename VT, typename HT, bool FIELD, int R>
+__global__ __launch_bounds__(NT) void csr_energy8_kernel(
+    int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const VT* __restrict__ val, const HT* __restrict__ h, const int8_t* __restrict__ s,
+    int want_int, double* partials, unsigned int* tickets, double* E, int64_t* E_int) {
+    constexpr int G = 8;
+    __shared__ double redd[NW][G][2];
+    __shared__ int64_t redi[NW][G];
+    __shared__ int last_flag;
+    const int r = threadIdx.x & (G - 1);
+    const bool on = r < R;
+    double eJ = 0.0, eh = 0.0;
+    int64_t eI = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * (NT / G) + threadIdx.x / G; i < n;
+         i += static_cast<int64_t>(gridDim.x) * (NT / G)) {
+        double acc = 0.0;
+        int64_t iacc = 0;
+        const int e1 = rp[i + 1];
+        for (int e = rp[i]; e < e1; ++e) {
+            const double v = static_cast<double>(val[e]);
+            const double sj = on ? static_cast<double>(s[static_cast<int64_t>(col[e]) * R + r]) : 0.0;
+            acc = dadd(acc, dmul(v, sj));
+            if (want_int) iacc += static_cast<int64_t>(v) * static_cast<int64_t>(sj);
+        }
+        if (!on) continue;
+        const double si = static_cast<double>(s[i * R + r]);
+        eJ = dadd(eJ, dmul(si, acc));
+        eI += static_cast<int64_t>(si) * iacc;
+        if (FIELD) eh = dadd(eh, dmul(static_cast<double>(h[i]), si));
+    }
+    // per restart: the wavefront's eight row groups, then the wavefronts in order
+#pragma unroll
+    for (int off = 8; off < kWave; off <<= 1) {
+        eJ = dadd(eJ, __shfl_xor(eJ, off, kWave));
+        eh = dadd(eh, __shfl_xor(eh, off, kWave));
+        eI += __shfl_xor(eI, off, kWave);
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane < G) {
+        redd[wave][lane][0] = eJ;
+        redd[wave][lane][1] = eh;
+        redi[wave][lane] = eI;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double tJ = 0.0, th = 0.0;
+        int64_t ti = 0;
+        for (int w = 0; w < NW; ++w) {
+            tJ = dadd(tJ, redd[w][threadIdx.x][0]);
+            th = dadd(th, redd[w][threadIdx.x][1]);
+            ti += redi[w][threadIdx.x];
+        }
+        double* p = partials + (static_cast<size_t>(blockIdx.x) * R + threadIdx.x) * 3;
+        store_agent(p + 0, tJ);
+        store_agent(p + 1, th);
+        store_agent(p + 2, __longlong_as_double(ti));
+    }
+    // the storing wavefront (0) waits for its stores inside the arrival
+    if (threadIdx.x == 0) last_flag = arrive_last_grid(tickets, gridDim.x) ? 1 : 0;
+    __syncthreads();
+    if (!last_flag) return;
+    if (threadIdx.x < R) {
+        double uJ = 0.0, uh = 0.0;
+        int64_t ui = 0;
+        for (unsigned g = 0; g < gridDim.x; ++g) {
+            const double* p = partials + (static_cast<size_t>(g) * R + threadIdx.x) * 3;
+            uJ = dadd(uJ, load_agent(p + 0));
+            uh = dadd(uh, load_agent(p + 1));
+            ui += __double_as_longlong(load_agent(p + 2));
+        }
+        if (E) E[threadIdx.x] = dsub(dmul(-0.5, uJ), uh);
+        if (E_int) E_int[threadIdx.x] = -(ui / 2);
+    }
+    if (threadIdx.x == 0) reset_ticket(tickets);
+}
+
 // ------------------------------------------------------------ validation
 // flags[0]: malformed CSR, flags[1]: nonzero diagonal, flags[2]: a value is
 // not an integer of magnitude < 2^31.
@@ -744,11 +824,57 @@ hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs
     return hipErrorInvalidValue;
 }
 
+template <typename VT, typename HT, bool FIELD>
+hipError_t launch_energy8_f(const CsrView& A, const int8_t* s_spins, int R, int want_int, double* partials,
+                            unsigned int* ticket, double* E, int64_t* E_int, hipStream_t s) {
+    const int g8 = csr_energy8_grid(A.n);
+    const VT* val = static_cast<const VT*>(A.val);
+    const HT* h = static_cast<const HT*>(A.h);
+    switch (R) {
+#define DOCH_ENERGY8(RR)                                                                                  \
+    case RR:                                                                                              \
+        hipLaunchKernelGGL((csr_energy8_kernel<VT, HT, FIELD, RR>), dim3(g8), dim3(NT), 0, s, A.n, A.rp,   \
+                           A.col, val, h, s_spins, want_int, partials, ticket, E, E_int);                  \
+        break;
+        DOCH_ENERGY8(2)
+        DOCH_ENERGY8(3)
+        DOCH_ENERGY8(4)
+        DOCH_ENERGY8(5)
+        DOCH_ENERGY8(6)
+        DOCH_ENERGY8(7)
+        DOCH_ENERGY8(8)
+#undef DOCH_ENERGY8
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename VT, typename HT>
+hipError_t launch_energy8(const CsrView& A, const int8_t* s_spins, int R, bool field, int want_int,
+                          double* partials, unsigned int* ticket, double* E, int64_t* E_int, hipStream_t s) {
+    if (field) return launch_energy8_f<VT, HT, true>(A, s_spins, R, want_int, partials, ticket, E, E_int, s);
+    return launch_energy8_f<VT, HT, false>(A, s_spins, R, want_int, partials, ticket, E, E_int, s);
+}
+
+int csr_energy8_grid(int64_t n) {
+    int64_t g = (n + NT / 8 - 1) / (NT / 8);
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return static_cast<int>(g);
+}
+
 hipError_t launch_csr_energy(const CsrView& A, const int8_t* s_spins, int R,
                              double* partials, unsigned int* ticket, int grid,
                              double* E, int64_t* E_int, hipStream_t s) {
     const bool field = A.h != nullptr;
     const int want_int = E_int != nullptr;
+    if (R >= 2 && R <= 8) {
+        DOCH_DISPATCH_VT_HT(A, {
+            return launch_energy8<VT, HT>(A, s_spins, R, field, want_int, partials, ticket, E, E_int, s);
+        });
+        return hipGetLastError();
+    }
     DOCH_DISPATCH_VT_HT(A, {
         const VT* val = static_cast<const VT*>(A.val);
         const HT* h = static_cast<const HT*>(A.h);

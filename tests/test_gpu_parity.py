@@ -231,6 +231,35 @@ def test_energy_many_restarts_and_integer():
         assert E[r] == float(Ei[r])
 
 
+@pytest.mark.parametrize("R", [2, 5, 8])
+def test_energy_restarts_in_one_pass(R):
+    """2..8 restarts take one pass over the couplings (eight lanes per row):
+    exact int64 energies on integer couplings (also with int16 values) and
+    FP64 energies with a field, against the oracle restart by restart."""
+    rng = np.random.default_rng(300 + R)
+    A = gen.er_csr(4000, 9.0, 301)
+    B = orc.to_oracle_csr(A)
+    S = np.where(rng.random((A.n, R)) < 0.5, 1, -1).astype(np.int8)
+    for vd in ("f32", "i16"):
+        P = GpuProblem(A=A, val_dtype=vd)
+        try:
+            E, Ei = P.energy(S, want_int=True)
+        finally:
+            P.close()
+        for r in range(R):
+            assert int(Ei[r]) == orc.energy_i64(B, S[:, r])
+            assert E[r] == float(Ei[r])
+    T = gen.torus_csr(70, 302, h_std=0.3)
+    S = np.where(rng.random((T.n, R)) < 0.5, 1, -1).astype(np.int8)
+    P = GpuProblem(A=T)
+    try:
+        E, _ = P.energy(S)
+    finally:
+        P.close()
+    for r in range(R):
+        assert E[r] == pytest.approx(orc.energy(T, S[:, r]), rel=1e-12, abs=1e-9)
+
+
 def test_energy_field_and_dense_gaussian():
     A = gen.torus_csr(50, 93, h_std=0.1)
     rng = np.random.default_rng(94)
