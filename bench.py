@@ -55,8 +55,9 @@ def parse():
     ap.add_argument("--oracle-restarts", type=int, default=1)
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
-    ap.add_argument("--tune-instance", choices=["torus", "s5"], default="torus",
-                    help="tune_eta: the lattice or the Supp. Alg. S5 instance")
+    ap.add_argument("--tune-instance", choices=["torus", "s5", "procedural"], default="torus",
+                    help="tune_eta: the lattice, the Supp. Alg. S5 instance or the procedural "
+                         "sin(ij+100) couplings (--proc-n spins)")
     ap.add_argument("--proc-n", type=int, default=65536,
                     help="spins of the procedural sin(ij+100) instance")
     ap.add_argument("--ingest-flops", metavar="CSV",
@@ -708,7 +709,18 @@ def bench_tune_eta(args):
     import ising_inputs as gen
     import paper_2509_01928_amd as L
     d = "cuda:0"
-    if args.tune_instance == "s5":
+    field = args.tune_instance == "torus"
+    if args.tune_instance == "procedural":
+        n = args.proc_n
+
+        class _P:                         # shape of the instance for the accounting below
+            pass
+        A = _P()
+        A.n, A.nnz = n, n * (n - 1)
+        x0 = gen.uniform_x0(n, 1, 2007)[:, 0]
+        ctx = L.ising_create_procedural(n, 1, 100.0)
+        label = f"procedural couplings sin(ij+100), n={n}"
+    elif args.tune_instance == "s5":
         n = args.s5_n
         A = gen.s5_csr(n, 100.0 * 10.0 / (n - 1), 1006)
         x0 = gen.uniform_x0(n, 1, 2006)[:, 0]
@@ -742,10 +754,13 @@ def bench_tune_eta(args):
     assert np.allclose(np.array(out["e"]), energies, rtol=1e-12, atol=1e-6), "batched and sequential probes differ"
     n, nnz = A.n, A.nnz
     vb = 2 if args.tune_instance == "s5" else 4
-    field = args.tune_instance != "s5"
     # one pass per probe iteration for all 8 probes: offsets, indices and
-    # values, the field, and 8 FP64 iterates read and written
-    bytes_iter = 4 * (n + 1) + (4 + vb) * nnz + (4 * n if field else 0) + 2 * 8 * len(etas) * (n + 1)
+    # values, the field, and 8 FP64 iterates read and written (the
+    # procedural couplings are generated, not read)
+    if args.tune_instance == "procedural":
+        bytes_iter = 2 * 8 * len(etas) * n
+    else:
+        bytes_iter = 4 * (n + 1) + (4 + vb) * nnz + (4 * n if field else 0) + 2 * 8 * len(etas) * (n + 1)
     sweep_bytes = bytes_iter * probe
     print(json.dumps({
         "metric": "eta candidates/s", "value": len(etas) / dt, "unit": "candidates/s",
@@ -760,10 +775,14 @@ def bench_tune_eta(args):
         "best_eta": best_eta, "probe_energies": energies.tolist(),
         # the batched pass's algorithmic bytes over the wall time of whole
         # sweeps (energies and parameter setting included)
-        "roofline": {"kernel": "csr_sweep_kernel", "bound": "hbm",
-                     "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_iteration": bytes_iter},
+        "roofline": ({"kernel": "dense_sin_sweep_kernel", "bound": "alu", "peak": FP64_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "achieved": None, "frac": None,
+                      "coupling_probes_per_s": nnz * len(etas) * probe / dt}
+                     if args.tune_instance == "procedural" else
+                     {"kernel": "csr_sweep_kernel", "bound": "hbm",
+                      "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,
+                      "algorithmic_bytes_per_iteration": bytes_iter}),
     }), flush=True)
     L.ising_destroy(ctx)
 

@@ -1443,20 +1443,22 @@ ising_status ising_tune_eta(ising_ctx* ctx, const double* x0_dev, int32_t count,
         ps[k].alpha = etas_host[k] * lambda;
         ps[k].beta = std::pow(np, 1.5) * (ps[k].alpha + rowsum);
     }
-    if (!ctx->dense) {
-        // CSR: up to 8 probes at a time as restarts of one pass over the
-        // couplings (each probe's iterates are those ising_solve computes)
+    // CSR, and procedural dense couplings: up to 8 probes at a time as
+    // restarts of one pass over the couplings (each probe's iterates are
+    // those ising_solve computes)
+    const bool proc_sweep = ctx->dense && ctx->proc_kind == 1 && !ctx->has_field;
+    if (!ctx->dense || proc_sweep) {
         const int rmax = std::min<int>(count, doch::kSweepMaxR);
         HIP_OK(ensure(&ctx->sweep_x, &ctx->sweep_x_bytes, 2 * static_cast<size_t>(ctx->np) * rmax * sizeof(double)),
                "hipMalloc(sweep iterates)");
         HIP_OK(ensure(&ctx->tune_s, &ctx->tune_s_bytes, static_cast<size_t>(ctx->n) * rmax), "hipMalloc(spins)");
-        const int grid = doch::sweep_grid(ctx->n);
+        const int grid = proc_sweep ? doch::dense_sweep_grid(ctx->n) : doch::sweep_grid(ctx->n);
         HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
                       static_cast<size_t>(grid) * rmax * doch::kNumPartials * sizeof(double)),
                "hipMalloc(partials)");
         st = ensure_solve_state(ctx, 1, rmax);
         if (st != ISING_OK) return st;
-        const CsrView cv = csr_view(ctx);
+        const CsrView cv = proc_sweep ? CsrView{} : csr_view(ctx);
         for (int c0 = 0; c0 < count; c0 += doch::kSweepMaxR) {
             const int R = std::min(doch::kSweepMaxR, count - c0);
             if (R == 1) {
@@ -1485,7 +1487,8 @@ ising_status ising_tune_eta(ising_ctx* ctx, const double* x0_dev, int32_t count,
                 a.x_old = X[k & 1];
                 a.x_new = X[(k + 1) & 1];
                 a.k = k;
-                HIP_OK(doch::launch_sweep_step(cv, a, s), "sweep step");
+                if (proc_sweep) HIP_OK(doch::launch_dense_sin_sweep(ctx->n, ctx->proc_seed, a, s), "sweep step");
+                else HIP_OK(doch::launch_sweep_step(cv, a, s), "sweep step");
             }
             HIP_OK(doch::launch_sweep_round(X[probe_iters & 1], ctx->n, R, ctx->has_field, ctx->tune_s, s), "round");
             st = ising_energy(ctx, ctx->tune_s, R, ctx->cut_tmp, nullptr, stream);

@@ -395,6 +395,9 @@ int sweep_grid(int64_t n);
 hipError_t launch_sweep_step(const CsrView& A, const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_load(const double* x0, int64_t np, int R, double* X, hipStream_t s);
 hipError_t launch_sweep_round(const double* X, int64_t n, int R, bool field, int8_t* S, hipStream_t s);
+// the sweep on procedural couplings sin(i j + seed), 2 <= R <= 8, no field
+int dense_sweep_grid(int64_t n);
+hipError_t launch_dense_sin_sweep(int64_t n, double seed, const SweepArgs& a, hipStream_t s);
 
 // ---- launchers (kernels_common.hip) ----
 hipError_t launch_cut(const double* E, const int64_t* E_int, const MatrixStats* ms, int R, double* cut,

@@ -22,6 +22,80 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / kWave;
 
+// End of a sweep launch: add each restart's partial sums over the lanes that
+// hold it (lanes r, r + 8, ... of a wavefront), the wavefronts and then the
+// workgroups in fixed order; the last workgroup finishes H, r and, with a
+// field, the extra spin t of every restart (eq:Hamilton, Remark S2, Supp.
+// Note 1).
+template <int R, bool FIELD>
+__device__ void sweep_close(double (&acc)[kNumPartials], const SweepArgs& a, const double* __restrict__ x,
+                            double* __restrict__ xn, int64_t n) {
+    constexpr int G = 8;
+    __shared__ double red[NW][G][kNumPartials];
+    __shared__ int last_flag;
+    // per restart: the wavefront's eight row groups, then the four
+    // wavefronts
+#pragma unroll
+    for (int q = 0; q < kNumPartials; ++q) {
+        double v = acc[q];
+        v = dadd(v, __shfl_xor(v, 8, kWave));
+        v = dadd(v, __shfl_xor(v, 16, kWave));
+        v = dadd(v, __shfl_xor(v, 32, kWave));
+        acc[q] = v;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane < G)
+#pragma unroll
+        for (int q = 0; q < kNumPartials; ++q) red[wave][lane][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < R * kNumPartials) {
+        const int rr = threadIdx.x / kNumPartials, q = threadIdx.x % kNumPartials;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s = dadd(s, red[w][rr][q]);
+        store_agent(a.partials + static_cast<size_t>(blockIdx.x) * kNumPartials * R + threadIdx.x, s);
+    }
+    // the storing wavefront (0) waits for its stores inside the arrival
+    if (threadIdx.x == 0) last_flag = arrive_last_grid(a.tickets, gridDim.x) ? 1 : 0;
+    __syncthreads();
+    if (!last_flag) return;
+    // last workgroup: thread (r, q) of the first kNumPartials * R threads adds
+    // quantity q of restart r over the workgroups in index order
+    const int slot = threadIdx.x;
+    double s = 0.0;
+    if (slot < kNumPartials * R)
+        for (unsigned g = 0; g < gridDim.x; ++g)
+            s = dadd(s, load_agent(a.partials + static_cast<size_t>(g) * kNumPartials * R + slot));
+    __shared__ double tot[kNumPartials * R];
+    if (slot < kNumPartials * R) tot[slot] = s;
+    __syncthreads();
+    if (threadIdx.x >= R) return;
+    const int rr = threadIdx.x;
+    const double* S = tot + kNumPartials * rr;
+    double S4 = S[P_X4], S2 = S[P_X2], Sxz = S[P_XZ], Sd = S[P_DX2];
+    if (FIELD) {
+        const double t = x[n * R + rr];
+        const double zn = S[P_HX];
+        const double t2 = dmul(t, t);
+        S4 = dadd(S4, dmul(t2, t2));
+        S2 = dadd(S2, t2);
+        Sxz = dadd(Sxz, dmul(t, zn));
+        const double tn = cbrt(ddiv(dadd(zn, dmul(a.alpha[rr], t)), a.beta[rr]));
+        xn[n * R + rr] = tn;
+        const double d = dsub(tn, t);
+        Sd = dadd(Sd, dmul(d, d));
+    }
+    const double H = dsub(dsub(dmul(ddiv(a.beta[rr], 4.0), S4), dmul(ddiv(a.alpha[rr], 2.0), S2)), dmul(0.5, Sxz));
+    const double rv = (S2 == 0.0) ? 0.0 : ddiv(sqrt(Sd), sqrt(S2));
+    RestartState* st = a.state + rr;
+    st->iters_done = a.k + 1;
+    st->H_last = H;
+    st->r_last = rv;
+    if (!isfinite(H) || !isfinite(rv)) st->nonfinite = 1;
+    if (rr == 0) reset_ticket(a.tickets);
+}
+
+
 // Eight lanes per row, lane r of the group holding restart r (lanes r >= R
 // idle), so a row's R iterate values are one contiguous run of 8R bytes for
 // every gather and store; the group reads the row's entries together (one
@@ -32,8 +106,6 @@ __global__ __launch_bounds__(NT) void csr_sweep_kernel(int64_t n, const int32_t*
                                                        const VT* __restrict__ val, const HT* __restrict__ h,
                                                        SweepArgs a) {
     constexpr int G = 8;                        // lanes per row
-    __shared__ double red[NW][G][kNumPartials];
-    __shared__ int last_flag;
     const double* __restrict__ x = a.x_old;
     double* __restrict__ xn = a.x_new;
     const int r = threadIdx.x & (G - 1);
@@ -113,66 +185,94 @@ __global__ __launch_bounds__(NT) void csr_sweep_kernel(int64_t n, const int32_t*
             update(i, z, x[i * R + r], FIELD ? static_cast<double>(h[i]) : 0.0);
         }
     }
-    // per restart: the wavefront's eight row groups, then the four
-    // wavefronts, in fixed order
+    sweep_close<R, FIELD>(acc, a, x, xn, n);
+}
+
+// The sweep on procedural couplings J_ij = sin(i j + seed) (0-based, zero
+// diagonal, no field): each wavefront forms four rows at a time, each lane
+// advancing the rows' sines along j = lane, lane + 64, ... by a rotation
+// (the arguments form an arithmetic progression with step 64 i) with an
+// exact sin/cos restart every 32 steps -- the step kernel's generator -- and
+// every generated coupling serves all R probes: the lane loads the R
+// interleaved iterate values of column j once.  Lane 8 r + q then updates
+// row i0 + r of probe q.  Each probe's row sum runs in the step kernel's
+// order with its couplings, so its iterates are those of a single-restart
+// solve.
+template <int R>
+__global__ __launch_bounds__(NT) void dense_sin_sweep_kernel(int64_t n, double seed, SweepArgs a) {
+    constexpr int RW = 4, U = 8, RESTART = 32;
+    const double* __restrict__ x = a.x_old;
+    double* __restrict__ xn = a.x_new;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double acc[kNumPartials];
 #pragma unroll
-    for (int q = 0; q < kNumPartials; ++q) {
-        double v = acc[q];
-        v = dadd(v, __shfl_xor(v, 8, kWave));
-        v = dadd(v, __shfl_xor(v, 16, kWave));
-        v = dadd(v, __shfl_xor(v, 32, kWave));
-        acc[q] = v;
-    }
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    if (lane < G)
+    for (int q = 0; q < kNumPartials; ++q) acc[q] = 0.0;
+    for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
+         i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
+        double di[RW], sd[RW], cd[RW], sv[RW], cv[RW], p[RW][R];
 #pragma unroll
-        for (int q = 0; q < kNumPartials; ++q) red[wave][lane][q] = acc[q];
-    __syncthreads();
-    if (threadIdx.x < R * kNumPartials) {
-        const int rr = threadIdx.x / kNumPartials, q = threadIdx.x % kNumPartials;
-        double s = 0.0;
+        for (int r = 0; r < RW; ++r) {
+            di[r] = static_cast<double>(i0 + r);
+            sincos(dmul(64.0, di[r]), &sd[r], &cd[r]);
+            sv[r] = cv[r] = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) s = dadd(s, red[w][rr][q]);
-        store_agent(a.partials + static_cast<size_t>(blockIdx.x) * kNumPartials * R + threadIdx.x, s);
+            for (int q = 0; q < R; ++q) p[r][q] = 0.0;
+        }
+        auto restart = [&](int64_t jj) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) sincos(dadd(dmul(di[r], static_cast<double>(jj)), seed), &sv[r], &cv[r]);
+        };
+        auto step = [&](int64_t jj, bool maybe_diag) {
+            double xr[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) xr[q] = x[jj * R + q];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const double jv = (maybe_diag && jj == i0 + r) ? 0.0 : sv[r];
+#pragma unroll
+                for (int q = 0; q < R; ++q) p[r][q] = dadd(p[r][q], dmul(jv, xr[q]));
+            }
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const double sn = fma(sv[r], cd[r], cv[r] * sd[r]);
+                cv[r] = fma(cv[r], cd[r], -(sv[r] * sd[r]));
+                sv[r] = sn;
+            }
+        };
+        int64_t j = lane;
+        int batch = 0;
+        for (; j + (U - 1) * kWave < n; j += U * kWave, ++batch) {
+            if ((batch & (RESTART / U - 1)) == 0) restart(j);
+            const bool maybe_diag = i0 + RW - 1 >= j && i0 <= j + (U - 1) * kWave;
+#pragma unroll
+            for (int u = 0; u < U; ++u) step(j + u * kWave, maybe_diag);
+        }
+        for (int u = 0; j < n; j += kWave, ++u) {
+            if (u == 0 && (batch & (RESTART / U - 1)) == 0) restart(j);
+            step(j, true);
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const double z = __shfl(wave_sum(p[r][q]), 0, kWave);
+                const int64_t i = i0 + r;
+                if (lane == 8 * r + q && i < n) {
+                    const double xi = x[i * R + q];
+                    const double xnew = cbrt(ddiv(dadd(z, dmul(a.alpha[q], xi)), a.beta[q]));
+                    xn[i * R + q] = xnew;
+                    const double d = dsub(xnew, xi);
+                    const double x2 = dmul(xi, xi);
+                    acc[P_X4] = dadd(acc[P_X4], dmul(x2, x2));
+                    acc[P_X2] = dadd(acc[P_X2], x2);
+                    acc[P_XZ] = dadd(acc[P_XZ], dmul(xi, z));
+                    acc[P_DX2] = dadd(acc[P_DX2], dmul(d, d));
+                }
+            }
+        }
     }
-    // the storing wavefront (0) waits for its stores inside the arrival
-    if (threadIdx.x == 0) last_flag = arrive_last_grid(a.tickets, gridDim.x) ? 1 : 0;
-    __syncthreads();
-    if (!last_flag) return;
-    // last workgroup: thread (r, q) of the first kNumPartials * R threads adds
-    // quantity q of restart r over the workgroups in index order
-    const int slot = threadIdx.x;
-    double s = 0.0;
-    if (slot < kNumPartials * R)
-        for (unsigned g = 0; g < gridDim.x; ++g)
-            s = dadd(s, load_agent(a.partials + static_cast<size_t>(g) * kNumPartials * R + slot));
-    __shared__ double tot[kNumPartials * R];
-    if (slot < kNumPartials * R) tot[slot] = s;
-    __syncthreads();
-    if (threadIdx.x >= R) return;
-    const int rr = threadIdx.x;
-    const double* S = tot + kNumPartials * rr;
-    double S4 = S[P_X4], S2 = S[P_X2], Sxz = S[P_XZ], Sd = S[P_DX2];
-    if (FIELD) {
-        const double t = x[n * R + rr];
-        const double zn = S[P_HX];
-        const double t2 = dmul(t, t);
-        S4 = dadd(S4, dmul(t2, t2));
-        S2 = dadd(S2, t2);
-        Sxz = dadd(Sxz, dmul(t, zn));
-        const double tn = cbrt(ddiv(dadd(zn, dmul(a.alpha[rr], t)), a.beta[rr]));
-        xn[n * R + rr] = tn;
-        const double d = dsub(tn, t);
-        Sd = dadd(Sd, dmul(d, d));
-    }
-    const double H = dsub(dsub(dmul(ddiv(a.beta[rr], 4.0), S4), dmul(ddiv(a.alpha[rr], 2.0), S2)), dmul(0.5, Sxz));
-    const double rv = (S2 == 0.0) ? 0.0 : ddiv(sqrt(Sd), sqrt(S2));
-    RestartState* st = a.state + rr;
-    st->iters_done = a.k + 1;
-    st->H_last = H;
-    st->r_last = rv;
-    if (!isfinite(H) || !isfinite(rv)) st->nonfinite = 1;
-    if (rr == 0) reset_ticket(a.tickets);
+    sweep_close<R, false>(acc, a, x, xn, n);
 }
 
 // x0 (n' values) -> R interleaved copies
@@ -247,6 +347,35 @@ hipError_t launch_sweep_v(const CsrView& A, const SweepArgs& a, hipStream_t s) {
 }  // namespace
 
 int sweep_grid(int64_t n) { return grid_rows8(n); }
+
+// four rows per wavefront, 16 per workgroup
+int dense_sweep_grid(int64_t n) {
+    int64_t g = (n + 15) / 16;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return static_cast<int>(g);
+}
+
+hipError_t launch_dense_sin_sweep(int64_t n, double seed, const SweepArgs& a, hipStream_t s) {
+    const int grid = dense_sweep_grid(n);
+    switch (a.R) {
+#define DOCH_DSWEEP_R(RR)                                                                             \
+    case RR:                                                                                          \
+        hipLaunchKernelGGL((dense_sin_sweep_kernel<RR>), dim3(grid), dim3(NT), 0, s, n, seed, a);    \
+        break;
+        DOCH_DSWEEP_R(2)
+        DOCH_DSWEEP_R(3)
+        DOCH_DSWEEP_R(4)
+        DOCH_DSWEEP_R(5)
+        DOCH_DSWEEP_R(6)
+        DOCH_DSWEEP_R(7)
+        DOCH_DSWEEP_R(8)
+#undef DOCH_DSWEEP_R
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_sweep_step(const CsrView& A, const SweepArgs& a, hipStream_t s) {
     const bool h64 = A.h && A.ht == ISING_F64;

@@ -585,6 +585,41 @@ def test_procedural_large_arguments():
     assert_log_parity(H, r, tr, "procedural n=8192")
 
 
+@pytest.mark.parametrize("count", [8, 5, 9])
+def test_tune_eta_procedural_matches_oracle_probes(count):
+    """eta sweep on procedural couplings sin(i j + 100): the probes run as
+    restarts of one pass that generates every coupling once for all of them
+    (a lone ninth probe on the single-restart path); each probe energy and
+    the choice agree with the oracle's probes on the materialised matrix."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    n, seed, probe = 700, 100.0, 6
+    i = np.arange(n, dtype=np.float64)
+    J = np.sin(np.outer(i, i) + seed)
+    np.fill_diagonal(J, 0.0)
+    B = orc.csr_of_dense(J)
+    x0 = gen.uniform_x0(n, 1, 153)[:, 0]
+    etas = [0.2 + 0.2 * k for k in range(count)]
+    # lambda_hat once (Wigner's estimate, as the device is asked to use);
+    # alpha and beta per eta by eq:alphabeta
+    _, _, lam = orc.default_params(B, 1.0, method="wigner")
+    rho = np.abs(J).sum(axis=1).max()
+    E_ref = []
+    for eta in etas:
+        a = eta * lam
+        b = n ** 1.5 * (a + rho)
+        tr = orc.doch_dense(J, x0, a, b, probe)
+        E_ref.append(orc.energy_dense(J, orc.sign(tr.x)))
+    ctx = Lb.ising_create_procedural(n, 1, seed)
+    try:
+        xd = torch.from_numpy(x0).to("cuda:0")
+        best, eta, E = Lb.ising_tune_eta(ctx, xd, etas, probe, 2)
+    finally:
+        Lb.ising_destroy(ctx)
+    np.testing.assert_allclose(E, E_ref, rtol=1e-11, atol=1e-9)
+    assert eta == etas[int(np.argmin(E_ref))]
+
+
 def test_constant_row_length_detected():
     """A CSR whose rows all hold d entries is recognised (row i starts at d i)."""
     import paper_2509_01928_amd as Lb
