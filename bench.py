@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6          # FP64 vector peak (FMA = 2 flops)
 DENSE_SOURCES = ("kernels_dense.hip", "step_common.h", "device_common.h")
+SWEEP_SOURCES = ("kernels_sweep.hip", "step_common.h", "device_common.h")
 
 
 def parse():
@@ -105,44 +106,54 @@ def load_traffic(kernel: str, workload: str):
     return rec
 
 
-def load_flops(kernel: str, workload: str):
-    """FP64 flops per coupling of the procedural step kernel, measured by
-    rocprofv3 counters on the current kernel source (else None)."""
+def load_flops(kernel: str, workload: str, sources=DENSE_SOURCES):
+    """FP64 flops per coupling (per coupling and probe for the sweep) of a
+    procedural kernel, measured by rocprofv3 counters on the current kernel
+    source (else None)."""
     path = os.path.join(ROOT, "profiles", "flops.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f).get(workload)
-    if not rec or rec.get("source_hash") != kernel_source_hash(DENSE_SOURCES) or kernel not in rec.get("kernel", ""):
+    if not rec or rec.get("source_hash") != kernel_source_hash(sources) or kernel not in rec.get("kernel", ""):
         return None
     return rec
 
 
 def ingest_flops(path, n):
-    """FP64 flops per dispatch of the procedural step kernel over the n(n-1)
-    couplings it generates, stored in profiles/flops.json.  The counters add,
-    over the whole device, each executed wavefront instruction's flops per
-    lane (a fused multiply-add is two); a wavefront has 64 lanes, all active
-    in the row loop, so flops = 64 x (FLOPS_FP64 + FLOPS_FP64_TRANS)."""
+    """FP64 flops per dispatch of the procedural kernels found in a counter
+    file, stored in profiles/flops.json: the step kernel per coupling of the
+    n(n-1) it generates, the eta sweep kernel per coupling and probe (it
+    generates each coupling once for its R probes).  The counters add, over
+    the whole device, each executed wavefront instruction's flops per lane
+    (a fused multiply-add is two); a wavefront has 64 lanes, all active in
+    the row loop, so flops = 64 x (FLOPS_FP64 + FLOPS_FP64_TRANS)."""
     import csv
+    import re
     from collections import defaultdict
     vals = defaultdict(lambda: defaultdict(list))
     with open(path) as f:
         for r in csv.DictReader(f):
             vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    step = next(k for k in vals if "dense_step_kernel" in k and "SinJ" in k)
-    c = vals[step]
-    avg = {k: sum(v) / len(v) for k, v in c.items()}
-    flops = 64.0 * (avg.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) + avg.get("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0))
-    rec = {"kernel": step, "source_hash": kernel_source_hash(DENSE_SOURCES), "n": n,
-           "dispatches": len(next(iter(c.values()))), "counters_per_dispatch": avg,
-           "fp64_flops_per_dispatch": flops, "fp64_flops_per_coupling": flops / (n * (n - 1))}
     out = os.path.join(ROOT, "profiles", "flops.json")
     data = json.load(open(out)) if os.path.exists(out) else {}
-    data[f"procedural{n}"] = rec
+    found = [(k, f"procedural{n}", DENSE_SOURCES, 1) for k in vals
+             if "dense_step_kernel" in k and "SinJ" in k]
+    for k in vals:
+        m = re.search(r"dense_sin_sweep_kernel<(\d+)>", k)
+        if m:
+            found.append((k, f"sweep_procedural{n}_R{m.group(1)}", SWEEP_SOURCES, int(m.group(1))))
+    for name, key, sources, R in found:
+        c = vals[name]
+        avg = {k: sum(v) / len(v) for k, v in c.items()}
+        flops = 64.0 * (avg.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) + avg.get("SQ_INSTS_VALU_FLOPS_FP64_TRANS", 0.0))
+        rec = {"kernel": name, "source_hash": kernel_source_hash(sources), "n": n, "probes": R,
+               "dispatches": len(next(iter(c.values()))), "counters_per_dispatch": avg,
+               "fp64_flops_per_dispatch": flops, "fp64_flops_per_coupling": flops / (n * (n - 1) * R)}
+        data[key] = rec
+        print(json.dumps({key: rec}, indent=1))
     with open(out, "w") as f:
         json.dump(data, f, indent=1)
-    print(json.dumps(rec, indent=1))
 
 
 def ingest_pmc(paths, workload):
@@ -762,6 +773,18 @@ def bench_tune_eta(args):
     else:
         bytes_iter = 4 * (n + 1) + (4 + vb) * nnz + (4 * n if field else 0) + 2 * 8 * len(etas) * (n + 1)
     sweep_bytes = bytes_iter * probe
+    if args.tune_instance == "procedural":
+        # FP64 flops per coupling and probe, counted on the sweep kernel, over
+        # the wall time of whole sweeps (energies and setup included)
+        fl = load_flops("dense_sin_sweep_kernel", f"sweep_procedural{n}_R{len(etas)}", SWEEP_SOURCES)
+        cps = nnz * len(etas) * probe / dt
+        sweep_roof = {"kernel": f"dense_sin_sweep_kernel<{len(etas)}>", "bound": "alu",
+                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "coupling_probes_per_s": cps,
+                      "achieved": None, "frac": None}
+        if fl:
+            ach = fl["fp64_flops_per_coupling"] * cps / 1e12
+            sweep_roof.update({"achieved": ach, "frac": ach / FP64_PEAK_TFLOPS,
+                               "fp64_flops_per_coupling_probe": fl["fp64_flops_per_coupling"]})
     print(json.dumps({
         "metric": "eta candidates/s", "value": len(etas) / dt, "unit": "candidates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
@@ -775,10 +798,7 @@ def bench_tune_eta(args):
         "best_eta": best_eta, "probe_energies": energies.tolist(),
         # the batched pass's algorithmic bytes over the wall time of whole
         # sweeps (energies and parameter setting included)
-        "roofline": ({"kernel": "dense_sin_sweep_kernel", "bound": "alu", "peak": FP64_PEAK_TFLOPS,
-                      "unit": "TFLOP/s", "achieved": None, "frac": None,
-                      "coupling_probes_per_s": nnz * len(etas) * probe / dt}
-                     if args.tune_instance == "procedural" else
+        "roofline": (sweep_roof if args.tune_instance == "procedural" else
                      {"kernel": "csr_sweep_kernel", "bound": "hbm",
                       "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,

@@ -127,6 +127,52 @@ __device__ __forceinline__ void lane_rows_dot_sin(const SinJ& J, int64_t i0, V v
     }
 }
 
+// The same generator as lane_rows_dot_sin, handing each step to a visitor:
+// f(j, sv, dr) sees column j, the current sines sv[r] = sin((i0 + r) j +
+// seed) of the RW rows and dr = j - i0 when column j is one of the rows'
+// diagonals (J_ii = 0: the visitor skips row dr there), else -1.
+template <int RW, typename F>
+__device__ __forceinline__ void lane_rows_sin_walk(const SinJ& J, int64_t i0, int64_t n, int lane, F&& f) {
+    constexpr int U = 8;
+    double di[RW], sd[RW], cd[RW], sv[RW], cv[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        di[r] = static_cast<double>(i0 + r);
+        sincos(dmul(64.0, di[r]), &sd[r], &cd[r]);
+        sv[r] = cv[r] = 0.0;
+    }
+    auto restart = [&](int64_t jj) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) sincos(dadd(dmul(di[r], static_cast<double>(jj)), J.seed), &sv[r], &cv[r]);
+    };
+    auto rotate = [&]() {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const double sn = fma(sv[r], cd[r], cv[r] * sd[r]);
+            cv[r] = fma(cv[r], cd[r], -(sv[r] * sd[r]));
+            sv[r] = sn;
+        }
+    };
+    auto diag = [&](int64_t jj) { return (jj >= i0 && jj < i0 + RW) ? static_cast<int>(jj - i0) : -1; };
+    int64_t j = lane;
+    int batch = 0;
+    for (; j + (U - 1) * kWave < n; j += U * kWave, ++batch) {
+        if ((batch & (kSinRestart / U - 1)) == 0) restart(j);
+        const bool maybe_diag = i0 + RW - 1 >= j && i0 <= j + (U - 1) * kWave;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t jj = j + u * kWave;
+            f(jj, sv, maybe_diag ? diag(jj) : -1);
+            rotate();
+        }
+    }
+    for (int u = 0; j < n; j += kWave, ++u) {
+        if (u == 0 && (batch & (kSinRestart / U - 1)) == 0) restart(j);
+        f(j, sv, diag(j));
+        rotate();
+    }
+}
+
 // rows of the procedural couplings a wavefront forms together
 constexpr int kSinRows = 4;
 
@@ -323,6 +369,94 @@ __global__ __launch_bounds__(NT) void dense_energy_kernel(int64_t n, JS J,
     }
 }
 
+// eq:IsingModel on the procedural couplings for RB restarts at once: each
+// wavefront forms four rows with the step kernel's sine generator, and every
+// generated coupling serves the RB restarts c0 .. c0 + RB - 1 of its column
+// block (restarts beyond R are left out).  Per restart the workgroup adds
+// s_i z_i over its rows; the last workgroup of a column block adds the
+// workgroups' sums in index order and writes E = -1/2 s^T J s.  PACKED: a
+// full block of 8 at an 8-byte aligned address, its spins of column j read
+// as one 8-byte word.
+template <int RB, bool PACKED>
+__global__ __launch_bounds__(NT) void dense_sin_energy_kernel(int64_t n, SinJ J, const int8_t* __restrict__ S,
+                                                              int R, double* partials, unsigned int* tickets,
+                                                              double* E) {
+    constexpr int RW = kSinRows;
+    __shared__ double red[RB * NW];
+    __shared__ int last_flag;
+    const int c0 = blockIdx.y * RB;
+    const int nc = min(RB, R - c0);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    double v[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) v[q] = 0.0;
+    for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
+         i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
+        double p[RW][RB];
+        if constexpr (RB == 1) {
+            double p1[RW];
+            lane_rows_dot_sin<RW>(J, i0, [&](int64_t j) { return static_cast<double>(S[j * R + c0]); }, n,
+                                  lane, p1);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) p[r][0] = p1[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int q = 0; q < RB; ++q) p[r][q] = 0.0;
+            lane_rows_sin_walk<RW>(J, i0, n, lane, [&](int64_t j, const double (&sv)[RW], int dr) {
+                double sj[RB];
+                if constexpr (PACKED) {
+                    const uint64_t w = *reinterpret_cast<const uint64_t*>(S + j * R + c0);
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) sj[q] = static_cast<double>(static_cast<int8_t>(w >> (8 * q)));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) sj[q] = q < nc ? static_cast<double>(S[j * R + c0 + q]) : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const double jv = r == dr ? 0.0 : sv[r];
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) p[r][q] = dadd(p[r][q], dmul(jv, sj[q]));
+                }
+            });
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int64_t i = i0 + r;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const double z = wave_sum(p[r][q]);
+                if (lane == 0 && i < n && q < nc) v[q] = dadd(v[q], dmul(static_cast<double>(S[i * R + c0 + q]), z));
+            }
+        }
+    }
+    block_sum<RB, NT>(v, red);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < nc; ++q)
+            store_agent(partials + static_cast<size_t>(c0 + q) * gridDim.x + blockIdx.x, v[q]);
+        last_flag = arrive_last(tickets + blockIdx.y, gridDim.x) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last_flag) return;
+    double u[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        u[q] = 0.0;
+        if (q < nc) {
+            const double* pr = partials + static_cast<size_t>(c0 + q) * gridDim.x;
+            for (unsigned g = threadIdx.x; g < gridDim.x; g += NT) u[q] = dadd(u[q], load_agent(pr + g));
+        }
+    }
+    block_sum<RB, NT>(u, red);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < nc; ++q) E[c0 + q] = dmul(-0.5, u[q]);
+        reset_ticket(tickets + blockIdx.y);
+    }
+}
+
 // flags[0]: non-finite entry, flags[1]: nonzero diagonal, flags[2]: an entry
 // is not an integer of magnitude < 2^31.
 __global__ __launch_bounds__(NT) void dense_validate_kernel(int64_t n, int64_t ld,
@@ -362,22 +496,9 @@ __global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, JS J,
     const int wave = threadIdx.x / kWave;
     double v[3] = {0.0, 0.0, 0.0};
     double pmax = 0.0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
-         i += static_cast<int64_t>(gridDim.x) * NW) {
-        double a0 = 0.0, a1 = 0.0;
-        for (int64_t j = lane; j < n; j += kWave) {
-            if (j == i) continue;
-            const double x = J(i, j);
-            if (pass == 0) {
-                a0 = dadd(a0, fabs(x));
-                a1 = dadd(a1, x);
-            } else {
-                const double d = dsub(x, mean);
-                a0 = dadd(a0, dmul(d, d));
-            }
-        }
-        const double rs = wave_sum(a0);
-        const double sm = wave_sum(a1);
+    // row i's sums over j != i: rs of |J_ij| (pass 0) or (J_ij - mean)^2
+    // (pass 1), sm of J_ij, complete in lane 0
+    auto row_done = [&](int64_t i, double rs, double sm) {
         if (lane == 0) {
             if (pass == 0) {
                 double rsum = rs;
@@ -398,6 +519,48 @@ __global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, JS J,
                     v[0] = dadd(v[0], dmul(2.0, dmul(d, d)));
                 }
             }
+        }
+    };
+    auto add = [&](double& a0, double& a1, double x) {
+        if (pass == 0) {
+            a0 = dadd(a0, fabs(x));
+            a1 = dadd(a1, x);
+        } else {
+            const double d = dsub(x, mean);
+            a0 = dadd(a0, dmul(d, d));
+        }
+    };
+    if constexpr (std::is_same<JS, SinJ>::value) {
+        // kSinRows rows per wavefront from the sine generator
+        constexpr int RW = kSinRows;
+        for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
+             i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
+            double a0[RW], a1[RW];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) a0[r] = a1[r] = 0.0;
+            lane_rows_sin_walk<RW>(J, i0, n, lane, [&](int64_t, const double (&sv)[RW], int dr) {
+#pragma unroll
+                for (int r = 0; r < RW; ++r)
+                    if (r != dr) add(a0[r], a1[r], sv[r]);
+            });
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const double rs = wave_sum(a0[r]);
+                const double sm = wave_sum(a1[r]);
+                if (i0 + r < n) row_done(i0 + r, rs, sm);
+            }
+        }
+    } else {
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+             i += static_cast<int64_t>(gridDim.x) * NW) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int64_t j = lane; j < n; j += kWave) {
+                if (j == i) continue;
+                add(a0, a1, J(i, j));
+            }
+            const double rs = wave_sum(a0);
+            const double sm = wave_sum(a1);
+            row_done(i, rs, sm);
         }
     }
     block_sum<3, NT>(v, red);
@@ -563,6 +726,25 @@ hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid, hi
 hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
                                double* partials, unsigned int* ticket, int grid, double* E,
                                hipStream_t s) {
+    if (A.proc_kind == 1 && A.h == nullptr && R <= kSinEnergyMaxR) {
+        // partials: R x grid doubles; one ticket per column block
+        const SinJ js{A.proc_seed};
+        const int RB = R == 1 ? 1 : R == 2 ? 2 : R <= 4 ? 4 : 8;
+        const dim3 g(static_cast<unsigned>(grid), static_cast<unsigned>((R + RB - 1) / RB));
+        const bool packed = R % 8 == 0 && (reinterpret_cast<uintptr_t>(s_spins) & 7) == 0;
+        switch (RB) {
+        case 1: hipLaunchKernelGGL((dense_sin_energy_kernel<1, false>), g, dim3(NT), 0, s, A.n, js, s_spins, R, partials, ticket, E); break;
+        case 2: hipLaunchKernelGGL((dense_sin_energy_kernel<2, false>), g, dim3(NT), 0, s, A.n, js, s_spins, R, partials, ticket, E); break;
+        case 4: hipLaunchKernelGGL((dense_sin_energy_kernel<4, false>), g, dim3(NT), 0, s, A.n, js, s_spins, R, partials, ticket, E); break;
+        default:
+            if (packed)
+                hipLaunchKernelGGL((dense_sin_energy_kernel<8, true>), g, dim3(NT), 0, s, A.n, js, s_spins, R, partials, ticket, E);
+            else
+                hipLaunchKernelGGL((dense_sin_energy_kernel<8, false>), g, dim3(NT), 0, s, A.n, js, s_spins, R, partials, ticket, E);
+            break;
+        }
+        return hipGetLastError();
+    }
     if (R >= kTiledEnergyMinR) {
         // partials: (row tiles) x (R rounded up to 64) x 2 doubles
         const int Rp = (R + 63) / 64 * 64;

@@ -318,6 +318,33 @@ def test_energy_dense_many_restarts_tiled():
         assert E[r] == pytest.approx(orc.energy_dense(Jp, S[:, r]), rel=1e-11, abs=1e-9), r
 
 
+@pytest.mark.parametrize("R", [1, 2, 3, 8, 13, 16])
+def test_energy_procedural_restart_blocks(R):
+    """eq:IsingModel on procedural couplings sin(i j + 7) for up to 16
+    restarts: the couplings come from the sine generator once per block of
+    up to 8 restarts (R = 3: one block of 4 with one left out; R = 13: a
+    block of 8 and a ragged one of 5), 333 rows (ragged row groups)."""
+    import torch
+    import paper_2509_01928_amd as Lb
+    n, seed = 333, 7.0
+    i = np.arange(n, dtype=np.float64)
+    Jp = np.sin(np.outer(i, i) + seed)
+    np.fill_diagonal(Jp, 0.0)
+    S = np.where(np.random.default_rng(98 + R).random((n, R)) < 0.5, 1, -1).astype(np.int8)
+    ctx = Lb.ising_create_procedural(n, 1, seed)
+    try:
+        sd = torch.from_numpy(S).to("cuda:0")
+        Ed = torch.empty(R, dtype=torch.float64, device="cuda:0")
+        for _ in range(2):                      # the tickets are clean again after a call
+            Lb.ising_energy(ctx, sd, R, Ed)
+            torch.cuda.synchronize()
+            E = Ed.cpu().numpy()
+            for r in range(R):
+                assert E[r] == pytest.approx(orc.energy_dense(Jp, S[:, r]), rel=1e-11, abs=1e-9), r
+    finally:
+        Lb.ising_destroy(ctx)
+
+
 # ------------------------------------------------------ setup (eq:alphabeta)
 def test_default_params_wigner_matches_oracle():
     import paper_2509_01928_amd as Lb
