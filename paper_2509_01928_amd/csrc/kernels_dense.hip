@@ -158,12 +158,20 @@ __device__ __forceinline__ void lane_rows_sin_walk(const SinJ& J, int64_t i0, in
     int batch = 0;
     for (; j + (U - 1) * kWave < n; j += U * kWave, ++batch) {
         if ((batch & (kSinRestart / U - 1)) == 0) restart(j);
-        const bool maybe_diag = i0 + RW - 1 >= j && i0 <= j + (U - 1) * kWave;
+        // batches that cannot hold a diagonal pass a constant -1, so the
+        // visitor's test folds away there
+        if (i0 + RW - 1 >= j && i0 <= j + (U - 1) * kWave) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t jj = j + u * kWave;
-            f(jj, sv, maybe_diag ? diag(jj) : -1);
-            rotate();
+            for (int u = 0; u < U; ++u) {
+                f(j + u * kWave, sv, diag(j + u * kWave));
+                rotate();
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                f(j + u * kWave, sv, -1);
+                rotate();
+            }
         }
     }
     for (int u = 0; j < n; j += kWave, ++u) {
@@ -531,18 +539,33 @@ __global__ __launch_bounds__(NT) void dense_stats_kernel(int64_t n, JS J,
         }
     };
     if constexpr (std::is_same<JS, SinJ>::value) {
-        // kSinRows rows per wavefront from the sine generator
+        // kSinRows rows per wavefront from the sine generator, one walk per
+        // pass so that the loop holds only that pass's arithmetic
         constexpr int RW = kSinRows;
         for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
              i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
             double a0[RW], a1[RW];
 #pragma unroll
             for (int r = 0; r < RW; ++r) a0[r] = a1[r] = 0.0;
-            lane_rows_sin_walk<RW>(J, i0, n, lane, [&](int64_t, const double (&sv)[RW], int dr) {
+            if (pass == 0) {
+                lane_rows_sin_walk<RW>(J, i0, n, lane, [&](int64_t, const double (&sv)[RW], int dr) {
 #pragma unroll
-                for (int r = 0; r < RW; ++r)
-                    if (r != dr) add(a0[r], a1[r], sv[r]);
-            });
+                    for (int r = 0; r < RW; ++r)
+                        if (r != dr) {
+                            a0[r] = dadd(a0[r], fabs(sv[r]));
+                            a1[r] = dadd(a1[r], sv[r]);
+                        }
+                });
+            } else {
+                lane_rows_sin_walk<RW>(J, i0, n, lane, [&](int64_t, const double (&sv)[RW], int dr) {
+#pragma unroll
+                    for (int r = 0; r < RW; ++r)
+                        if (r != dr) {
+                            const double d = dsub(sv[r], mean);
+                            a0[r] = dadd(a0[r], dmul(d, d));
+                        }
+                });
+            }
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 const double rs = wave_sum(a0[r]);
