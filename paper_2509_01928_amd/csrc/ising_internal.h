@@ -323,9 +323,6 @@ hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid,
 int dense_step_grid(int64_t n);
 // restarts from which ising_energy on a dense context uses the tiled J S kernel
 constexpr int kTiledEnergyMinR = 8;
-// procedural couplings without a field: up to this many restarts take the
-// energy kernel that generates each coupling once per 8 restarts
-constexpr int kSinEnergyMaxR = 16;
 hipError_t launch_dense_energy(const DenseView& A, const int8_t* s_spins, int R,
                                double* partials, unsigned int* ticket, int grid,
                                double* E, hipStream_t s);

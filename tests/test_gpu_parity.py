@@ -285,7 +285,8 @@ def test_energy_field_and_dense_gaussian():
 def test_energy_dense_many_restarts_tiled():
     """eq:IsingModel for 70 restarts at once (the tiled J S path: two column
     blocks, the second ragged; 333 rows, the last tile ragged), with and
-    without a field, and on procedural couplings."""
+    without a field; and on procedural couplings, whose energy kernel takes
+    the 70 restarts in nine blocks of up to 8."""
     import torch
     import paper_2509_01928_amd as Lb
     n, R = 333, 70
@@ -318,12 +319,12 @@ def test_energy_dense_many_restarts_tiled():
         assert E[r] == pytest.approx(orc.energy_dense(Jp, S[:, r]), rel=1e-11, abs=1e-9), r
 
 
-@pytest.mark.parametrize("R", [1, 2, 3, 8, 13, 16])
+@pytest.mark.parametrize("R", [1, 2, 3, 8, 13, 16, 130])
 def test_energy_procedural_restart_blocks(R):
-    """eq:IsingModel on procedural couplings sin(i j + 7) for up to 16
-    restarts: the couplings come from the sine generator once per block of
-    up to 8 restarts (R = 3: one block of 4 with one left out; R = 13: a
-    block of 8 and a ragged one of 5), 333 rows (ragged row groups)."""
+    """eq:IsingModel on procedural couplings sin(i j + 7): the couplings come
+    from the sine generator once per block of up to 8 restarts (R = 3: one
+    block of 4 with one left out; R = 13: a block of 8 and a ragged one of
+    5; R = 130: 17 blocks, the last of 2), 333 rows (ragged row groups)."""
     import torch
     import paper_2509_01928_amd as Lb
     n, seed = 333, 7.0
