@@ -417,9 +417,9 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t it
     a.ring = ctx->ad_ring;
     a.state = ctx->state;
     const CsrView cv = csr_view(ctx);
-    double t = 1.0;                                   // t_0 (Alg. 2 line 1)
+    double t = 1.0;                                   // momentum sequence of Alg. 2: t_0 = 1
     for (int64_t k = 0; k < iters; ++k) {
-        const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;   // Alg. 2 line 3
+        const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;   // t_{k+1} of Alg. 2
         a.c = (t - 1.0) / t_next;                                           // 0 at k = 0: y = x
         a.k = k;
         const double* x = ctx->ad_x[k % 3];

@@ -483,7 +483,7 @@ def test_adoch_first_step_and_nonmonotone_bound():
 
 
 def test_adoch_momentum_coefficients():
-    """Alg. 2 line 3: t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2, t_0 = 1, so the
+    """Alg. 2's momentum sequence t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2, t_0 = 1, so the
     extrapolation weights (t_k - 1)/t_{k+1} are 0, 0.2818, 0.4340, ...
     On the scalar problem J = [0] with beta = alpha the map is T(v) = cbrt(v),
     and when every y is accepted x^(2) = cbrt(x1 + c1 (x1 - x0))."""
