@@ -643,11 +643,8 @@ __global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, JS J,
     const int wave = threadIdx.x / kWave;
     const double vn = FIELD ? v[n] : 0.0;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
-         i += static_cast<int64_t>(gridDim.x) * NW) {
-        double p = 0.0;
-        p = lane_row_dot(J, i, [&](int64_t j) { return v[j]; }, n, lane);
-        const double z0 = wave_sum(p);
+    // w_i = c v_i - (J v)_i from row i's total z0, in lane 0
+    auto row_done = [&](int64_t i, double z0) {
         if (lane == 0) {
             double z = z0;
             if (FIELD) {
@@ -660,6 +657,25 @@ __global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, JS J,
             acc[0] = dadd(acc[0], dmul(v[i], wi));
             acc[1] = dadd(acc[1], dmul(wi, wi));
         }
+    };
+    auto vv = [&](int64_t j) { return v[j]; };
+    if constexpr (std::is_same<JS, SinJ>::value) {
+        // kSinRows rows per wavefront from the sine generator
+        constexpr int RW = kSinRows;
+        for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
+             i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
+            double p[RW];
+            lane_rows_dot_sin<RW>(J, i0, vv, n, lane, p);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const double z0 = wave_sum(p[r]);
+                if (i0 + r < n) row_done(i0 + r, z0);
+            }
+        }
+    } else {
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+             i += static_cast<int64_t>(gridDim.x) * NW)
+            row_done(i, wave_sum(lane_row_dot(J, i, vv, n, lane)));
     }
     block_sum<3, NT>(acc, red);
     if (threadIdx.x == 0) {

@@ -388,6 +388,26 @@ def test_default_params_power_matches_eigvalsh():
     assert lam_o == pytest.approx(lam_true, rel=1e-7)
 
 
+def test_default_params_power_procedural():
+    """The power method (eq:estimate_eig_J's lambda_max(-J), Supp. Note 6)
+    on procedural couplings sin(i j + 100), n = 400: the rows come from the
+    sine generator; lambda_hat against the dense eigensolver of the
+    materialised matrix, beta by eq:alphabeta with its row sums."""
+    import paper_2509_01928_amd as Lb
+    n, seed = 400, 100.0
+    i = np.arange(n, dtype=np.float64)
+    J = np.sin(np.outer(i, i) + seed)
+    np.fill_diagonal(J, 0.0)
+    lam_true = -np.linalg.eigvalsh(J)[0]
+    ctx = Lb.ising_create_procedural(n, 1, seed)
+    try:
+        p, lam = Lb.ising_default_params(ctx, 1.0, 1)
+    finally:
+        Lb.ising_destroy(ctx)
+    assert lam == pytest.approx(lam_true, rel=1e-7)
+    assert p.beta == pytest.approx(n ** 1.5 * (p.alpha + np.abs(J).sum(axis=1).max()), rel=1e-12)
+
+
 # --------------------------------------------------------------- errors
 def test_error_paths():
     import torch
