@@ -169,11 +169,12 @@ ising_status ising_default_params(ising_ctx* ctx, double eta, int32_t method,
  * eta_k, alpha = eta_k lambda_hat and beta follow eq:alphabeta, DOCH runs
  * `probe_iters` iterations from x0_dev (as for ising_solve with R = 1), the
  * iterate is rounded and its Ising energy (eq:IsingModel) taken.  The eta
- * with the lowest energy wins (the first one on a tie).  On a CSR context
- * the probes run eight at a time as restarts of one pass over the couplings
- * (a lone remaining probe on the single-restart path); every probe's
- * iterates, and so its energy, are those of a single-restart solve with its
- * parameters.  A dense context runs them one after another.
+ * with the lowest energy wins (the first one on a tie).  On a CSR or a
+ * procedural context the probes run eight at a time as restarts of one pass
+ * over the couplings (a lone remaining probe on the single-restart path);
+ * every probe's iterates, and so its energy, are those of a single-restart
+ * solve with its parameters.  A stored dense context runs them one after
+ * another.
  *   count          1..64 candidates, etas_host[k] in (0, 2]
  *   probe_iters    1..1000 (the paper uses 5-10, 1-3 for ultra-large graphs)
  *   best_out       the winner's ising_params (eps 0, algo 0, q 5, FP64 iterate)
