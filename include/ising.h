@@ -131,8 +131,11 @@ ising_status ising_create_dense(int64_t n, const void* J_dev, int32_t jt, int64_
 
 /* ising_create_procedural: a dense context whose couplings are generated on
  * demand instead of stored (Supp. Note 9): kind 1 is J_ij = sin(i*j + seed)
- * with 0-based indices i, j and J_ii = 0, evaluated in FP64 (i*j < 2^53 is
- * exact for n <= 9e7); the paper uses seed = 100.  No field.  Every entry
+ * with 0-based indices i, j and J_ii = 0, evaluated in FP64; the paper uses
+ * seed = 100.  The seed must be an integer with |seed| + (n-1)^2 < 2^53, so
+ * that every argument i*j + seed is an exact FP64 integer (the kernels step
+ * the angle exactly and restart from exact arguments); other seeds give
+ * ISING_E_INVALID_ARG, as do n < 2 or n > 9e7.  No field.  Every entry
  * point that takes a dense context accepts it except ising_solve_lowp.  It
  * allocates nothing until used. */
 ising_status ising_create_procedural(int64_t n, int32_t kind, double seed, void* stream,

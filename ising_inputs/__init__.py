@@ -31,6 +31,7 @@ import numpy as np
 __all__ = [
     "CSR", "sk_dense", "er_csr", "torus_csr", "uniform_x0", "uneven_batch",
     "csr_from_dense", "dense_from_csr", "random_dense_int", "pm1_complete", "s5_csr",
+    "circulant_csr",
     "SEEDS",
 ]
 
@@ -272,3 +273,22 @@ def dense_from_csr(A: CSR) -> np.ndarray:
     rows = np.repeat(np.arange(A.n), np.diff(rp))
     J[rows, A.col.astype(np.int64)] = A.val.astype(np.float64)
     return J
+
+
+def circulant_csr(n: int, offsets, seed: int, h_std: float = 0.0) -> CSR:
+    """Circulant graph: spin i coupled to i +- o (mod n) for every o in
+    ``offsets`` (distinct, 0 < o < n/2), so every row holds exactly
+    2 len(offsets) entries.  Bonds are +-1 (p = 1/2), drawn per (i, o) in
+    site-major order; h ~ N(0, h_std^2) rounded to FP32 when h_std > 0."""
+    offs = np.asarray(sorted(int(o) for o in offsets), dtype=np.int64)
+    if offs.size == 0 or offs[0] <= 0 or 2 * offs[-1] >= n or np.unique(offs).size != offs.size:
+        raise ValueError("offsets must be distinct and in (0, n/2)")
+    g = _rng(seed)
+    bonds = np.where(g.random((n, offs.size)) < 0.5, -1.0, 1.0)
+    i = np.repeat(np.arange(n, dtype=np.int64), offs.size)
+    j = (i + np.tile(offs, n)) % n
+    ei, ej = np.maximum(i, j), np.minimum(i, j)
+    h = None
+    if h_std > 0:
+        h = (_rng(seed, 2).standard_normal(n) * h_std).astype(np.float32)
+    return _csr_from_lower_edges(n, ei, ej, bonds.reshape(-1), h)

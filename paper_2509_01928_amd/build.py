@@ -9,8 +9,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libising.so")
-# bandwidth calibration programs (plain executables)
-CALIB = [os.path.join(HERE, "calib", name) for name in ("stream_bw", "lattice_mix_bw")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -51,13 +49,6 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         os.replace(tmp, LIB)
-    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
-    for exe in CALIB:
-        cmd = ["hipcc", *flags, exe + ".hip", "-o", exe + ".tmp"]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        os.replace(exe + ".tmp", exe)
     return LIB
 
 

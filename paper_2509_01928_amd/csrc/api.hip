@@ -607,6 +607,14 @@ ising_status ising_create_procedural(int64_t n, int32_t kind, double seed, void*
     if (n < 2 || n > 90000000LL) return fail(ISING_E_INVALID_ARG, "n=%lld out of range", (long long)n);
     if (kind != 1) return fail(ISING_E_INVALID_ARG, "unknown procedural kind %d", kind);
     if (!std::isfinite(seed)) return fail(ISING_E_INVALID_ARG, "seed must be finite");
+    // The kernels advance the angle i*j + seed by exact steps and restart from
+    // exact integer arguments; both are exact only when every argument is an
+    // integer below 2^53 in magnitude.
+    if (seed != std::floor(seed))
+        return fail(ISING_E_INVALID_ARG, "seed %.17g is not an integer", seed);
+    const double nm1 = static_cast<double>(n - 1);
+    if (std::fabs(seed) + nm1 * nm1 >= 9007199254740992.0)
+        return fail(ISING_E_INVALID_ARG, "|seed| + (n-1)^2 must stay below 2^53");
     (void)stream;
     ising_ctx* c = new ising_ctx();
     if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(ISING_E_HIP, "no HIP device"); }

@@ -1,0 +1,107 @@
+"""Parity of the lattice step kernel at the launch shape the throughput
+measurement uses: one row per lane, the whole grid sweeping the rows
+together, more rows than lanes (every lane takes several trips through the
+grid-stride loop), implicit row offsets on constant-degree rows, with the
+field's extra spin (Supp. Note 1).
+
+FP64 iterates are compared with the oracle (eq:FPE, Alg. 1) at 1e-9; FP32
+iterate storage with the oracle's FP64 step applied to FP32-rounded iterates
+(at least 99.9% bit-equal, all within 1e-6 |x|_inf), and its H log within
+1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+import ising_inputs as gen
+import oracle as orc
+from tests._util import (GpuProblem, assert_fp32_storage_parity, assert_iterate_parity,
+                         assert_log_parity, assert_spin_parity, oracle_fp32_storage)
+
+pytestmark = pytest.mark.gpu
+
+ITERS = 50
+
+
+def _case(A, xseed):
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B, 1.0, method="wigner")
+    x0 = gen.uniform_x0(B.n, 1, xseed)[:, 0]
+    tr = orc.doch(B, x0, alpha, beta, ITERS)
+    xe, He = oracle_fp32_storage(B, x0, alpha, beta, ITERS)
+    return dict(A=A, B=B, alpha=alpha, beta=beta, x0=x0, tr=tr, xe=xe, He=He)
+
+
+@pytest.fixture(scope="module")
+def torus1024():
+    # 1024 x 1024 lattice with field: 1 048 577 rows, 4 per row; at 4
+    # workgroups per CU (262 144 lanes) each lane takes four trips
+    return _case(gen.torus_csr(1024, 1103, h_std=0.1), 2103)
+
+
+@pytest.fixture(scope="module")
+def circulant6():
+    # constant degree 6 (row length known only at run time), no field
+    return _case(gen.circulant_csr(600_000, [1, 5, 777], 1104), 2104)
+
+
+def _run(case, geometry, wg_per_cu, x_dtype):
+    P = GpuProblem(A=case["A"])
+    try:
+        info = P.L.ising_get_info(P.ctx)
+        P.L.ising_set_geometry(P.ctx, geometry, wg_per_cu)
+        assert P.L.ising_get_info(P.ctx).geometry == geometry
+        xt = P.L.ISING_F64 if x_dtype == "f64" else P.L.ISING_F32
+        x, s, st = P.solve(case["x0"], case["alpha"], case["beta"], ITERS, x_dtype=xt)
+        H, r = P.log(st[0].iters_done)
+    finally:
+        P.close()
+    return info, x[:, 0], s[:, 0], st[0], H, r
+
+
+def _check(case, label, info, x, s, st, H, r, x_dtype):
+    A, tr = case["A"], case["tr"]
+    assert st.iters_done == ITERS, label
+    if x_dtype == "f64":
+        assert_iterate_parity(x, tr.x, label)
+        s_ref = orc.spins_with_field(tr.x) if A.h is not None else orc.sign(tr.x)
+        assert_spin_parity(s, tr.x, s_ref, label)
+        assert_log_parity(H, r, tr, label)
+    else:
+        assert_fp32_storage_parity(x, case["xe"], label)
+        He = case["He"]
+        assert np.abs(H - He).max() <= 1e-9 * np.abs(He).max(), label
+        s_ref = orc.spins_with_field(case["xe"]) if A.h is not None else orc.sign(case["xe"])
+        assert_spin_parity(s, case["xe"], s_ref, label)
+
+
+@pytest.mark.parametrize("x_dtype", ["f32", "f64"])
+@pytest.mark.parametrize("wg_per_cu", [4, 0, 1])
+@pytest.mark.parametrize("geometry", [3, 4])
+def test_lattice_rowlane_multi_trip(torus1024, geometry, wg_per_cu, x_dtype):
+    """geometry 3, FP32 iterate, 4 workgroups per CU is the measured
+    configuration of the 10^8-spin lattice."""
+    info, x, s, st, H, r = _run(torus1024, geometry, wg_per_cu, x_dtype)
+    assert info.row_len == 4          # implicit offsets, compile-time length
+    _check(torus1024, f"torus L=1024 geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
+           info, x, s, st, H, r, x_dtype)
+
+
+@pytest.mark.parametrize("x_dtype", ["f32", "f64"])
+@pytest.mark.parametrize("geometry,wg_per_cu", [(3, 1), (4, 4), (4, 0)])
+def test_runtime_row_length_multi_trip(circulant6, geometry, wg_per_cu, x_dtype):
+    """Rows of 6 entries starting at 6i (half of them not 16-byte aligned):
+    geometry 4 loads them as two chunks, geometry 3 takes the element loop."""
+    info, x, s, st, H, r = _run(circulant6, geometry, wg_per_cu, x_dtype)
+    assert info.row_len == 6
+    _check(circulant6, f"circulant geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
+           info, x, s, st, H, r, x_dtype)
+
+
+def test_read_offsets_multi_trip():
+    """Rows of varying length (offsets read) with more rows than lanes."""
+    A = gen.er_csr(300_000, 6.0, 1105)
+    case = _case(A, 2105)
+    for geometry, wpc in ((3, 1), (4, 2)):
+        info, x, s, st, H, r = _run(case, geometry, wpc, "f64")
+        assert info.row_len == 0
+        _check(case, f"ER n=300000 geometry {geometry} wg/CU {wpc}", info, x, s, st, H, r, "f64")

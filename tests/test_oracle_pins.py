@@ -494,3 +494,30 @@ def test_adoch_momentum_coefficients():
     c1 = 0.28175
     assert tr2.accept.tolist() == [1, 1]
     assert tr2.x[0] == pytest.approx(np.cbrt(x1 + c1 * (x1 - x0)), rel=2e-5)
+
+
+def test_adoch_window_holds_q_plus_one_values():
+    """Alg. 2's look-back window is x^(max(0,k-q)) .. x^(k): q + 1 values of H.
+    Scalar J = [0], alpha = beta = 1: T(v) = cbrt(v) and H(v) = v^4/4 - v^2/2
+    in closed form.  From x^(0) = 27: x^(1) = 3, H(x^(0)) = 132495.75,
+    H(x^(1)) = 15.75, and the momentum point y^(1) = 3 + c_1 (3 - 27) with
+    c_1 = (t_1 - 1)/t_2 = 0.2818 lands at -3.762, H(y^(1)) = 43.00 -- above
+    H(x^(1)) and below H(x^(0)).  So y^(1) is accepted exactly when the window
+    at k = 1 reaches back to x^(0): with q = 1 (two values) it is, giving
+    x^(2) = cbrt(y^(1)); with q = 0 (one value) it is not, giving
+    x^(2) = cbrt(3).  A window one value short fails the q = 1 case."""
+    t1 = (1.0 + math.sqrt(5.0)) / 2.0
+    t2 = (1.0 + math.sqrt(1.0 + 4.0 * t1 * t1)) / 2.0
+    y1 = 3.0 + (t1 - 1.0) / t2 * (3.0 - 27.0)
+    H = lambda v: v ** 4 / 4.0 - v * v / 2.0  # noqa: E731
+    assert H(3.0) < H(y1) < H(27.0)
+    Z = orc.OracleCSR(1, np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    tr1 = orc.adoch(Z, np.array([27.0]), 1.0, 1.0, 2, 1)
+    assert tr1.accept.tolist() == [1, 1]
+    assert tr1.x[0] == pytest.approx(np.cbrt(y1), rel=1e-14)
+    assert tr1.Hy[1] == pytest.approx(H(y1), rel=1e-13)
+    assert tr1.Hmax[1] == pytest.approx(H(27.0), rel=1e-15)
+    tr0 = orc.adoch(Z, np.array([27.0]), 1.0, 1.0, 2, 0)
+    assert tr0.accept.tolist() == [1, 0]
+    assert tr0.x[0] == pytest.approx(np.cbrt(3.0), rel=1e-15)
+    assert tr0.Hmax[1] == pytest.approx(H(3.0), rel=1e-15)
