@@ -240,6 +240,26 @@ ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first,
 ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
                           double* E_dev, int64_t* E_int_dev, void* stream);
 
+/* ising_energy for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as ising_energy, but the partial sums
+ * and arrival tickets live in a static device array of 4 MiB (one copy per
+ * GPU, held until the process ends) instead of context memory that
+ * ising_energy allocates on first use.  The call allocates and frees
+ * nothing; the context itself is created beforehand as usual.  Every call
+ * on one GPU shares that GPU's array, so calls that overlap in time on one
+ * GPU (on different streams, or from different threads) race: serialise
+ * them.  Tickets are cleared by a small kernel on `stream` at each call.
+ * Errors: those of ising_energy; ISING_E_UNSUPPORTED for a batch context;
+ * ISING_E_INVALID_ARG when the launch needs more partial sums than the
+ * array holds (523 776 doubles: a CSR context takes any R <= 8, and
+ * R <= 170 at any n; a stored dense context R < 8 at any n, and for
+ * R >= 8 ceil(n/64) * ceil(R/64) * 128 partial sums; a generated dense
+ * context 1024 * ceil(R/8) * 8 at n >= 4096, i.e. R <= 504).
+ * Asynchronous on `stream`. */
+ising_status ising_energy_noalloc(ising_ctx* ctx, const int8_t* s_dev, int32_t R,
+                                  double* E_dev, int64_t* E_int_dev, void* stream);
+
 /* MAX-CUT value of each spin vector (Supp. Note 5), for the graph whose edge
  * weights are the negated stored couplings, w_ij = -J_ij:
  *     cut(s) = sum over i < j with s_i != s_j of w_ij

@@ -17,7 +17,7 @@ __all__ = [
     "IsingError", "ising_params", "ising_stats", "ising_info", "lib", "LIB_PATH",
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
-    "ising_energy", "ising_cut", "ising_tune_eta", "ising_set_geometry", "ising_autotune", "ising_create_batch",
+    "ising_energy", "ising_energy_noalloc", "ising_cut", "ising_tune_eta", "ising_set_geometry", "ising_autotune", "ising_create_batch",
     "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_solve_lowp", "ising_get_accept_log", "ising_create_procedural",
     "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
@@ -95,6 +95,7 @@ _SIGS = {
     "ising_solve": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _p, _p, _p, _p]),
     "ising_get_log": (_st, [_p, _i32, _i64, _i64, _p, _p, _p]),
     "ising_energy": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "ising_energy_noalloc": (_st, [_p, _p, _i32, _p, _p, _p]),
     "ising_cut": (_st, [_p, _p, _i32, _p, _p, _p]),
     "ising_tune_eta": (_st, [_p, _p, _i32, _p, _i64, _i32, _p, ctypes.POINTER(ising_params), _p, _p]),
     "ising_set_geometry": (_st, [_p, _i32, _i32]),
@@ -221,6 +222,12 @@ def ising_get_log(ctx, restart, first, count, stream=None):
 def ising_energy(ctx, s, R, E=None, E_int=None, stream=None):
     _check(lib.ising_energy(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
                             stream if stream is not None else current_stream()), "ising_energy")
+
+
+def ising_energy_noalloc(ctx, s, R, E=None, E_int=None, stream=None):
+    _check(lib.ising_energy_noalloc(ctx, ptr(s), int(R), ptr(E), ptr(E_int),
+                                    stream if stream is not None else current_stream()),
+           "ising_energy_noalloc")
 
 
 def ising_tune_eta(ctx, x0, etas, probe_iters, method=0, stream=None):

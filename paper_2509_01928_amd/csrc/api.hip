@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1361,36 +1362,128 @@ ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first, int64
     return ISING_OK;
 }
 
-ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
-                          int64_t* E_int_dev, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks of ising_energy and the size of its launch: the grid and
+// the partial sums the kernel that launch_*_energy picks needs.
+ising_status energy_plan(const ising_ctx* ctx, const int8_t* s_dev, int32_t R, const double* E_dev,
+                         const int64_t* E_int_dev, int* grid_out, size_t* need_out) {
     if (!ctx) return fail(ISING_E_INVALID_ARG, "ctx is NULL");
     if (!s_dev) return fail(ISING_E_INVALID_ARG, "s is NULL");
     if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
     if (!E_dev && !E_int_dev) return fail(ISING_E_INVALID_ARG, "no output requested");
     if (E_int_dev && !ctx->integer_J) return fail(ISING_E_UNSUPPORTED, "integer energy needs integer couplings");
     if (E_int_dev && ctx->dense) return fail(ISING_E_UNSUPPORTED, "integer energy is CSR-only in this build");
-    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->dense && !E_dev) return fail(ISING_E_INVALID_ARG, "E is NULL");
     const int grid = ctx->dense ? std::min<int64_t>(1024, (ctx->n + 3) / 4)
                                 : std::min<int64_t>(1024, (ctx->n + 255) / 256);
-    // partials: per (workgroup, restart) 3 doubles, or for the tiled dense
-    // kernel per (64-row tile, padded restart) 2
-    size_t need = static_cast<size_t>(grid) * R * 3;
-    if (!ctx->dense && R >= 2 && R <= 8)
-        need = std::max(need, static_cast<size_t>(doch::csr_energy8_grid(ctx->n)) * R * 3);
-    if (ctx->dense && R >= doch::kTiledEnergyMinR)
-        need = std::max(need, static_cast<size_t>((ctx->n + 63) / 64) * ((R + 63) / 64 * 64) * 2);
-    Scratch sc;
-    ising_status st = ensure_scratch(ctx, need, &sc);
-    if (st != ISING_OK) return st;
-    if (ctx->dense) {
-        if (!E_dev) return fail(ISING_E_INVALID_ARG, "E is NULL");
-        HIP_OK(doch::launch_dense_energy(dense_view(ctx), s_dev, R, sc.partials, sc.tickets, grid, E_dev, s), "energy");
+    size_t need;
+    if (!ctx->dense) {
+        // per (workgroup, restart): J part, field part, integer J part
+        need = (R >= 2 && R <= 8) ? static_cast<size_t>(doch::csr_energy8_grid(ctx->n)) * R * 3
+                                  : static_cast<size_t>(grid) * R * 3;
+    } else if (ctx->proc_kind == 1 && !ctx->h) {
+        // generated couplings: per (restart rounded up to its block of 8, workgroup)
+        need = static_cast<size_t>(grid) * ((R + 7) / 8 * 8);
+    } else if (R >= doch::kTiledEnergyMinR) {
+        // per (64-row tile, restart padded to 64): J part, field part
+        need = static_cast<size_t>((ctx->n + 63) / 64) * ((R + 63) / 64 * 64) * 2;
     } else {
-        HIP_OK(doch::launch_csr_energy(csr_view(ctx), s_dev, R, sc.partials, sc.tickets, grid, E_dev, E_int_dev, s),
-               "energy");
+        need = static_cast<size_t>(grid) * R * 2;
     }
+    *grid_out = grid;
+    *need_out = need;
     return ISING_OK;
+}
+
+ising_status energy_launch(const ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
+                           int64_t* E_int_dev, double* partials, unsigned int* tickets, int grid,
+                           hipStream_t s) {
+    if (ctx->dense)
+        HIP_OK(doch::launch_dense_energy(dense_view(ctx), s_dev, R, partials, tickets, grid, E_dev, s), "energy");
+    else
+        HIP_OK(doch::launch_csr_energy(csr_view(ctx), s_dev, R, partials, tickets, grid, E_dev, E_int_dev, s),
+               "energy");
+    return ISING_OK;
+}
+
+// ---------------------------------------------------- allocation-free energy
+// The partial sums and tickets of ising_energy_noalloc live in this array,
+// one copy per device, held until the process ends.  Host code never uses
+// the array's name as an address: the device address of each device's copy
+// is looked up once, with that device current, and kept in g_scratch_addr.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr size_t kScratchTicketBytes = kMaxR * sizeof(unsigned int);
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kScratchMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+ising_status scratch_address(int device, unsigned char** out) {
+    if (device < 0 || device >= kScratchMaxDevices)
+        return fail(ISING_E_UNSUPPORTED, "device %d beyond the %d the library tracks", device, kScratchMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(ISING_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_addr[device] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_addr[device]);
+    return ISING_OK;
+}
+
+// Zero the tickets: every energy kernel counts arrivals from 0.  A kernel
+// rather than a memset node keeps the call safe to capture in a graph.
+__global__ void zero_tickets_kernel(unsigned int* t, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) t[i] = 0u;
+}
+
+}  // namespace
+
+extern "C" {
+
+ising_status ising_energy(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
+                          int64_t* E_int_dev, void* stream) {
+    int grid = 0;
+    size_t need = 0;
+    ising_status st = energy_plan(ctx, s_dev, R, E_dev, E_int_dev, &grid, &need);
+    if (st != ISING_OK) return st;
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    Scratch sc;
+    st = ensure_scratch(ctx, need, &sc);
+    if (st != ISING_OK) return st;
+    return energy_launch(ctx, s_dev, R, E_dev, E_int_dev, sc.partials, sc.tickets, grid,
+                         static_cast<hipStream_t>(stream));
+}
+
+ising_status ising_energy_noalloc(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* E_dev,
+                                  int64_t* E_int_dev, void* stream) {
+    int grid = 0;
+    size_t need = 0;
+    ising_status st = energy_plan(ctx, s_dev, R, E_dev, E_int_dev, &grid, &need);
+    if (st != ISING_OK) return st;
+    if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "use ising_energy_batch on a batch context");
+    const size_t cap = (kScratchBytes - kScratchTicketBytes) / sizeof(double);
+    if (need > cap)
+        return fail(ISING_E_INVALID_ARG,
+                    "n=%lld with R=%d needs %zu partial sums; the static scratch of ising_energy_noalloc "
+                    "holds %zu (%zu bytes)",
+                    static_cast<long long>(ctx->n), R, need, cap, kScratchBytes);
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    unsigned char* base = nullptr;
+    st = scratch_address(ctx->device, &base);
+    if (st != ISING_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned int* tickets = reinterpret_cast<unsigned int*>(base);
+    double* partials = reinterpret_cast<double*>(base + kScratchTicketBytes);
+    hipLaunchKernelGGL(zero_tickets_kernel, dim3(4), dim3(256), 0, s, tickets, kMaxR);
+    HIP_OK(hipGetLastError(), "zero tickets");
+    return energy_launch(ctx, s_dev, R, E_dev, E_int_dev, partials, tickets, grid, s);
 }
 
 
