@@ -51,9 +51,10 @@ def parse():
     ap.add_argument("--geometry", type=int, default=-2,
                     help="step-kernel geometry (default: autotune)")
     ap.add_argument("--wg-per-cu", type=int, default=0)
-    ap.add_argument("--plain-restarts", type=int, default=16,
+    ap.add_argument("--plain-restarts", type=int, default=256,
                     help="dense4096: FP64 restarts run one at a time for the comparison")
-    ap.add_argument("--oracle-restarts", type=int, default=1)
+    ap.add_argument("--oracle-restarts", type=int, default=0,
+                    help="oracle restarts of the dense 4096 workload (0: one per host thread, at most 16)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
     ap.add_argument("--tune-instance", choices=["torus", "s5", "procedural"], default="torus",
@@ -204,6 +205,64 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# ------------------------------------------------------------------ CPU baselines
+def host_info():
+    """The host the oracle is timed on: logical CPUs and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cpus": os.cpu_count(), "cpu_model": model}
+
+
+def host_threads():
+    """Threads for the concurrent oracle runs: the CPUs this process may use,
+    at most 16 (a GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_concurrent(fn, items, threads):
+    """fn(item) for every item on `threads` host threads; each call runs the
+    single-threaded C oracle (ctypes releases the interpreter lock during the
+    call), so `threads` independent oracle runs proceed at once.  Returns the
+    results, the wall time and the sum of the calls' own durations."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def timed(item):
+        t0 = time.perf_counter()
+        r = fn(item)
+        return r, time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(timed, items))
+    wall = time.perf_counter() - t0
+    return [r for r, _ in res], wall, sum(d for _, d in res)
+
+
+def iterate_parity(x_gpu, x_ref, s_gpu, s_ref):
+    """max |dx| (absolute and over |x|_inf) and sign mismatches, with the
+    scale-aware exemption |x_i| < 1e-6 |x|_inf."""
+    import numpy as np
+    x_gpu = np.asarray(x_gpu, dtype=np.float64).reshape(-1)
+    x_ref = np.asarray(x_ref, dtype=np.float64).reshape(-1)
+    scale = float(np.abs(x_ref).max())
+    dx = float(np.abs(x_gpu - x_ref).max())
+    mism = np.nonzero(np.asarray(s_gpu).reshape(-1) != np.asarray(s_ref).reshape(-1))[0]
+    return {"max_abs_dx": dx, "max_dx_over_xinf": dx / scale if scale > 0 else dx, "x_inf": scale,
+            "spin_mismatches": int(mism.size),
+            "spin_mismatches_scale_aware": int(np.sum(np.abs(x_ref[mism]) >= 1e-6 * scale))}
+
+
 # ------------------------------------------------------------------ secondary workloads
 def _timed(fn, warmup, steps):
     import torch
@@ -251,6 +310,27 @@ def bench_er20000(args):
     torch.cuda.synchronize()
     it_us = 1e3 * e0.elapsed_time(e1) / iters
     bytes_iter = 4 * (A.n + 1) + 8 * A.nnz + 16 * A.n
+    extra = {}
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        xo = torch.empty_like(xd)
+        L.ising_solve(ctx, xd, 1, iters, p, xo, so)
+        torch.cuda.synchronize()
+        xg, sg, Eg = xo.cpu().numpy(), so.cpu().numpy(), int(E.cpu()[0])
+        B = orc.problem_matrix(A)
+        t0 = time.perf_counter()
+        tr = orc.doch(B, x0, p.alpha, p.beta, iters)
+        dt_cpu = time.perf_counter() - t0
+        s_ref = orc.sign(tr.x)
+        extra["parity"] = iterate_parity(xg, tr.x, sg, s_ref)
+        extra["parity"]["energy_int64_gpu"] = Eg
+        extra["parity"]["energy_int64_oracle"] = orc.energy_i64(B, s_ref)
+        extra["cpu_baseline"] = {"value": A.nnz * iters / dt_cpu, "unit": "edge-updates/s", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": f"the whole workload: {iters} DOCH iterations of the "
+                                           f"single-threaded FP64 oracle from the same x0 ({dt_cpu:.1f} s)",
+                                 **host_info()}
+        log(f"parity {extra['parity']}; CPU baseline {extra['cpu_baseline']['value']:.3e} edge-updates/s")
     print(json.dumps({
         "metric": "edge-updates/s", "value": A.nnz * iters / dt, "unit": "edge-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
@@ -266,6 +346,7 @@ def bench_er20000(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bytes_iter / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": bytes_iter},
+        **extra,
     }), flush=True)
     L.ising_destroy(ctx)
 
@@ -311,6 +392,27 @@ def bench_sk1024(args):
 
     solve_it_us = {"resident": solve_us(8), "launch_per_iteration": solve_us(0)}
     L.ising_set_geometry(ctx, geometry, 0)
+    extra = {}
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        xo = torch.empty_like(xd)
+        L.ising_solve(ctx, xd, 1, iters, p, xo, so)
+        L.ising_energy(ctx, so, 1, E)
+        torch.cuda.synchronize()
+        xg, sg, Eg = xo.cpu().numpy(), so.cpu().numpy(), float(E.cpu()[0])
+        t0 = time.perf_counter()
+        tr = orc.doch_dense(J, x0, p.alpha, p.beta, iters)
+        dt_cpu = time.perf_counter() - t0
+        s_ref = orc.sign(tr.x)
+        extra["parity"] = iterate_parity(xg, tr.x, sg, s_ref)
+        extra["parity"]["energy_gpu"] = Eg
+        extra["parity"]["energy_oracle"] = orc.energy_dense(J, s_ref)
+        extra["cpu_baseline"] = {"value": n * (n - 1) * iters / dt_cpu, "unit": "edge-updates/s",
+                                 "cores": 1, "kind": "oracle",
+                                 "sample": f"the whole workload: {iters} DOCH iterations of the "
+                                           f"single-threaded FP64 oracle from the same x0 ({dt_cpu:.2f} s)",
+                                 **host_info()}
+        log(f"parity {extra['parity']}; CPU baseline {extra['cpu_baseline']['value']:.3e} edge-updates/s")
     print(json.dumps({
         "metric": "edge-updates/s", "value": n * (n - 1) * iters / dt, "unit": "edge-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
@@ -325,13 +427,16 @@ def bench_sk1024(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": 8 * n * n / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": 8 * n * n},
+        **extra,
     }), flush=True)
     L.ising_destroy(ctx)
 
 
 def bench_dense4096(args):
     """Dense n = 4096, 256 restarts: BF16 and FP8 matrix-core iterations vs
-    the plain FP64 path run one restart at a time, compared at equal energy."""
+    the plain FP64 path on the same 256 starts run one restart at a time,
+    compared at equal best energy; energy gaps per restart against the GPU's
+    FP64 path (all starts) and the FP64 oracle (one start per host thread)."""
     import numpy as np
     import torch
 
@@ -351,27 +456,49 @@ def bench_dense4096(args):
            "data": "synthetic", "config": {"workload": "dense SK n=4096, J~N(0,1), 256 restarts "
                                            "x0~U(-1,1), 1000 DOCH iterations", "n": n, "R": R,
                                            "iters": iters}}
-    # plain FP64 path: restarts one at a time
-    nplain = args.plain_restarts
-    X0 = gen.uniform_x0(n, R, xseed)
-    so = torch.empty(n, dtype=torch.int8, device=d)
-    E = torch.empty(1, dtype=torch.float64, device=d)
-    Eplain = []
+    X0 = gen.uniform_x0(n, R, xseed)                     # n x R, restart-interleaved
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    # plain FP64 path on the same R starts, one restart at a time (matrix-
+    # vector products), timed with device events and no host round trips
+    nplain = min(args.plain_restarts, R)
+    X0T = torch.from_numpy(np.ascontiguousarray(X0.T)).to(d)      # row r: start r
+    S64 = torch.empty((R, n), dtype=torch.int8, device=d)
+    E64 = torch.empty(R, dtype=torch.float64, device=d)
+    L.ising_solve(ctx, X0T[0], 1, 20, p, None, S64[0], want_stats=False)   # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    e0.record()
     for r in range(nplain):
-        xd = torch.from_numpy(np.ascontiguousarray(X0[:, r])).to(d)
-        L.ising_solve(ctx, xd, 1, iters, p, None, so, want_stats=False)
-        L.ising_energy(ctx, so, 1, E)
-        Eplain.append(float(E.cpu()[0]))
-    t_plain = (time.perf_counter() - t0) / nplain
-    best64 = min(Eplain)
+        L.ising_solve(ctx, X0T[r], 1, iters, p, None, S64[r], want_stats=False)
+        L.ising_energy(ctx, S64[r], 1, E64[r:r + 1])
+    e1.record()
+    torch.cuda.synchronize()
+    t_plain = 1e-3 * e0.elapsed_time(e1) / nplain
+    E_plain = E64.cpu().numpy()[:nplain]
+    best64 = float(E_plain.min())
     out["fp64_plain"] = {"restarts_per_s": 1.0 / t_plain, "best_energy": best64,
                          "restarts": nplain, "ms_per_restart": 1e3 * t_plain}
-    log(f"FP64 plain: {1e3 * t_plain:.1f} ms/restart, best E {best64:.1f}")
-    # one oracle restart for the energy gap (FP64 CPU)
-    tr = orc.doch_dense(J, X0[:, 0], p.alpha, p.beta, iters) if args.oracle_restarts > 0 else None
-    E_or = orc.energy_dense(J, orc.sign(tr.x)) if tr is not None else None
+    log(f"FP64 plain: {1e3 * t_plain:.1f} ms/restart over {nplain} starts, best E {best64:.1f}")
+
+    # the FP64 oracle on the first starts, one single-threaded run per host thread
+    n_or = args.oracle_restarts if args.oracle_restarts > 0 else host_threads()
+    n_or = min(n_or, nplain)
+    E_or = None
+    if not args.no_cpu_baseline and n_or > 0:
+        trs, wall, busy = oracle_concurrent(
+            lambda r: orc.doch_dense(J, X0[:, r], p.alpha, p.beta, iters), range(n_or), n_or)
+        E_or = np.array([orc.energy_dense(J, orc.sign(t.x)) for t in trs])
+        out["cpu_baseline"] = {"value": n_or / wall, "unit": "restarts/s", "cores": n_or, "kind": "oracle",
+                               "sample": f"starts 0..{n_or - 1} of the same 256, {iters} DOCH iterations "
+                                         f"each, one single-threaded FP64 oracle run per host thread, "
+                                         f"concurrently ({wall:.1f} s wall)",
+                               "value_1core": n_or / busy, **host_info()}
+        gap = (E_plain[:n_or] - E_or) / np.abs(E_or)
+        out["fp64_plain"]["energy_gap_vs_fp64_oracle"] = {"restarts": n_or, "max_abs": float(np.abs(gap).max()),
+                                                         "equal": int(np.sum(E_plain[:n_or] == E_or))}
+        log(f"oracle: {n_or} restarts in {wall:.1f} s; GPU FP64 vs oracle max |gap| {np.abs(gap).max():.2e}")
+
     for name, prec, peak in (("bf16", L.ISING_BF16, 2500.0), ("fp8", L.ISING_FP8_E4M3, 5000.0)):
         xd = torch.from_numpy(np.ascontiguousarray(X0)).to(d)
         so = torch.empty((n, R), dtype=torch.int8, device=d)
@@ -379,8 +506,6 @@ def bench_dense4096(args):
         Eb = torch.empty(R, dtype=torch.float64, device=d)
         L.ising_solve_lowp(ctx, xd, R, 20, p, prec, None, so, Hf)      # warm-up
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         L.ising_solve_lowp(ctx, xd, R, iters, p, prec, None, so, Hf, want_stats=False)
         e1.record()
@@ -388,8 +513,9 @@ def bench_dense4096(args):
         ms = e0.elapsed_time(e1)
         L.ising_energy(ctx, so, R, Eb)
         Eh = Eb.cpu().numpy()
-        # equal-energy protocol: batches of R starts until the best energy
-        # reaches the FP64 best (at most 16 batches)
+        # equal-energy protocol: the first batch is the same R starts as the
+        # FP64 path; further batches of R new starts until the best energy
+        # reaches the FP64 path's best (at most 16 batches)
         best = float(Eh.min())
         batches = 1
         t_total = ms * 1e-3
@@ -405,14 +531,20 @@ def bench_dense4096(args):
             best = min(best, float(Eb.cpu().numpy().min()))
             batches += 1
         flops = 2.0 * n * n * R * iters
+        g64 = (Eh[:nplain] - E_plain) / np.abs(E_plain)
         res = {"restarts_per_s": R * batches / t_total, "ms_per_batch_of_256": ms,
                "iteration_us": 1e3 * ms / iters, "best_energy": best,
+               "best_energy_first_batch": float(Eh.min()),
                "reached_fp64_best": bool(best <= best64), "batches": batches,
-               "energy_gap_same_starts_mean": float(np.mean((Eh[:nplain] - np.array(Eplain)) / np.abs(Eplain))),
+               "energy_gap_vs_gpu_fp64_same_starts": {
+                   "restarts": nplain, "mean": float(g64.mean()), "min": float(g64.min()),
+                   "max": float(g64.max()), "lower_or_equal_fraction": float(np.mean(g64 <= 0))},
                "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak,
                             "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / peak}}
         if E_or is not None:
-            res["energy_gap_vs_fp64_oracle_restart0"] = (float(Eh[0]) - E_or) / abs(E_or)
+            go = (Eh[:n_or] - E_or) / np.abs(E_or)
+            res["energy_gap_vs_fp64_oracle"] = {"restarts": n_or, "per_restart": [float(v) for v in go],
+                                                "mean": float(go.mean())}
         out[name] = res
         log(f"{name}: {1e3 * ms / iters:.1f} us/iteration, {res['roofline']['achieved']:.1f} TFLOP/s, "
             f"best {best:.1f} after {batches} batch(es)")
@@ -474,6 +606,9 @@ def bench_batch512(args):
     # its iterate column
     bytes_moved = float(((4 * (ns + 1) + 8 * nnz) * iters.max(axis=1)).sum()
                         + (2 * xb * ns[:, None] * iters).sum())
+    extra = {}
+    if not args.no_cpu_baseline:
+        extra = batch_oracle_sample(args, L, torch, ctx, inst, X0, alpha, beta, R, xd, so, Ei)
     print(json.dumps({
         "metric": "edge-updates/s", "value": edge_updates / dt, "unit": "edge-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
@@ -491,8 +626,53 @@ def bench_batch512(args):
         "roofline": {"bound": "hbm", "achieved": bytes_moved / dt / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes": bytes_moved},
+        **extra,
     }), flush=True)
     L.ising_destroy(ctx)
+
+
+def batch_oracle_sample(args, L, torch, ctx, inst, X0, alpha, beta, R, xd, so, Ei):
+    """The oracle on the instances with index = 0 mod 8, every restart, to
+    the same stopping rule: its rate on the host's threads, and parity of the
+    GPU's FP64-iterate solve (iterations to stop and exact energies) on that
+    sample."""
+    import numpy as np
+
+    import oracle as orc
+    ids = list(range(0, len(inst), 8))
+    row0 = np.concatenate([[0], np.cumsum([A.n for A in inst])])
+    # the GPU with FP64 iterates, outside the timed region
+    st64, _ = L.ising_solve_batch(ctx, xd, R, 5000, alpha, beta, 1e-3, L.ISING_F64, None, so)
+    L.ising_energy_batch(ctx, so, R, None, Ei)
+    torch.cuda.synchronize()
+    it64 = np.array([s.iters_done for s in st64]).reshape(len(inst), R)
+    E64 = Ei.cpu().numpy().reshape(len(inst), R)
+    mats = {k: orc.problem_matrix(inst[k]) for k in ids}
+    tasks = [(k, r) for k in ids for r in range(R)]
+
+    def run(task):
+        k, r = task
+        x0 = X0[row0[k]:row0[k + 1], r]
+        tr = orc.doch(mats[k], x0, alpha[k], beta[k], 5000, eps=1e-3)
+        return tr.iters, orc.energy_i64(mats[k], orc.sign(tr.x))
+
+    threads = host_threads()
+    res, wall, busy = oracle_concurrent(run, tasks, threads)
+    edge_updates = float(sum(inst[k].nnz * it for (k, _), (it, _) in zip(tasks, res)))
+    same_iters = sum(int(it64[k, r] == it) for (k, r), (it, _) in zip(tasks, res))
+    same_energy = sum(int(E64[k, r] == e) for (k, r), (_, e) in zip(tasks, res))
+    log(f"oracle sample: {len(tasks)} restarts in {wall:.1f} s on {threads} threads; "
+        f"iterations equal {same_iters}, energies equal {same_energy}")
+    return {
+        "parity": {"sample": f"{len(ids)} instances (index = 0 mod 8) x {R} restarts, FP64 iterates",
+                   "restarts": len(tasks), "iterations_equal": same_iters, "energy_int64_equal": same_energy},
+        "cpu_baseline": {"value": edge_updates / wall, "unit": "edge-updates/s", "cores": threads,
+                         "kind": "oracle",
+                         "sample": f"{len(ids)} of the 512 instances (index = 0 mod 8) x {R} restarts, "
+                                   f"eps = 1e-3, at most 5000 iterations; one single-threaded FP64 oracle "
+                                   f"run per (instance, restart), {threads} at a time ({wall:.1f} s wall)",
+                         "value_1core": edge_updates / busy, **host_info()},
+    }
 
 
 def bench_s5(args):
