@@ -55,6 +55,12 @@ def parse():
                     help="dense4096: FP64 restarts run one at a time for the comparison")
     ap.add_argument("--oracle-restarts", type=int, default=0,
                     help="oracle restarts of the dense 4096 workload (0: one per host thread, at most 16)")
+    ap.add_argument("--batch-shape", default="",
+                    help="batch512: launch shape 'rj,wg,rows_per_member' instead of the autotuner's")
+    ap.add_argument("--tune-cache",
+                    default=os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
+                                         "paper_2509_01928_amd", "batch_shapes.json"),
+                    help="JSON cache of the batch autotuner")
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
     ap.add_argument("--tune-instance", choices=["torus", "s5", "procedural"], default="torus",
@@ -589,6 +595,20 @@ def bench_batch512(args):
     so = torch.empty(X0.shape, dtype=torch.int8, device=d)
     Ei = torch.empty(len(inst) * R, dtype=torch.int64, device=d)
     xdt = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
+    # launch shape: the project's autotuner (setup, outside the timed region),
+    # its choice kept in a JSON cache
+    tune = {}
+    if args.batch_shape:
+        rj, wg, rpm = (int(v) for v in args.batch_shape.split(","))
+        L.ising_set_batch_shape(ctx, rj, wg, rpm)
+        tune = {"shape": [rj, wg, rpm], "source": "command line"}
+    else:
+        os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+        t0 = time.perf_counter()
+        shape, ms, cached = L.ising_autotune_batch(ctx, xd, R, 5000, alpha, beta, 1e-3, xdt, args.tune_cache)
+        tune = {"shape": list(shape), "ms": ms, "source": "cache" if cached else "autotuner",
+                "tuning_s": time.perf_counter() - t0}
+        log(f"batch shape {shape} ({tune['source']}, {ms:.1f} ms)")
 
     def step():
         L.ising_solve_batch(ctx, xd, R, 5000, alpha, beta, 1e-3, xdt, None, so, want_stats=False)
@@ -617,7 +637,12 @@ def bench_batch512(args):
                                         "degree~U[3,20], +-1, 8 restarts, eps=1e-3, <=5000 "
                                         "iterations, one persistent graph-captured launch",
                                         "spins": int(total), "couplings": int(nnz0), "restarts": R,
-                                        "x_storage": args.x_dtype},
+                                        "x_storage": args.x_dtype,
+                                        "launch_shape": {"restarts_per_job": tune["shape"][0],
+                                                         "threads": tune["shape"][1],
+                                                         "rows_per_member": tune["shape"][2],
+                                                         "chosen_by": tune["source"]}},
+        "autotune": tune,
         "tts_ms_p50": float(np.percentile(tts, 50)), "tts_ms_p99": float(np.percentile(tts, 99)),
         "tts_ms_max": float(tts.max()),
         "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),

@@ -198,6 +198,7 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->bstats);
     dev_free(c->bclock);
     dev_free(c->bqueue);
+    dev_free(c->bplan_mem);
     dev_free(c->jq[0]);
     dev_free(c->jq[1]);
     dev_free(c->rscale);
@@ -1072,18 +1073,139 @@ ising_status ising_default_params_batch(ising_ctx* ctx, double eta, int32_t meth
     return ISING_OK;
 }
 
-// Launch shape of the batch kernel for R <= 8 restarts (see
-// launch_batch_solve): the least splitting of the restarts into jobs that
-// still gives every CU a job.  Measured on 512 uneven instances x 8 restarts:
-// no split 159 ms, groups of 4 292 ms, 2 304 ms, 1 547 ms -- a row's R
-// iterate entries share one cache line, so splitting multiplies the lines
-// the random gathers fetch; it pays only when jobs would leave CUs idle.
-static int batch_shape(int R, int count, int cus) {
-    if (R > 8) return 0;
-    const int rj[4] = {R, R < 4 ? R : 4, R < 2 ? R : 2, 1};
-    for (int sh = 0; sh < 4; ++sh)
-        if (static_cast<int64_t>(count) * (R / rj[sh]) >= cus) return sh;
-    return 3;
+// Default launch shape of the batch solve for R <= 8 restarts: every
+// restart of an instance in one job (a row's R iterate entries share one
+// cache line, so splitting the restarts multiplies the lines the gathers
+// fetch), teams of workgroups for instances of more than 2048 rows.
+static doch::BatchShape default_batch_shape(int R) {
+    doch::BatchShape sh;
+    sh.rj = std::min(8, R);
+    sh.wg = sh.rj >= 4 ? 256 : 512;
+    sh.rows_per_member = 2048;
+    return sh;
+}
+
+static doch::BatchShape batch_shape_for(const ising_ctx* ctx, int R) {
+    if (ctx->bshape_set && doch::batch_shape_supported(ctx->bshape, R)) return ctx->bshape;
+    return default_batch_shape(R);
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// The job plan of the batch solve for R <= 8 restarts and shape `sh`:
+// jobs in decreasing instance size; an instance of n rows gets a team of
+// P = ceil(n / rows_per_member) workgroups (at most pmax, at most half of
+// an XCD's resident workgroups); team jobs are dealt to the XCD queues
+// largest first, each to the queue with the least work so far among those
+// with room for its P members, where an XCD's room is its resident
+// workgroups: every team ticket is taken in the launch's first round, so a
+// team's members meet at once.  A job that finds no room, and every job of
+// one workgroup, is a single job of the common queue.
+static ising_status ensure_batch_plan(ising_ctx* ctx, int R, const doch::BatchShape& sh, int x_dtype,
+                                      hipStream_t s) {
+    const std::vector<int64_t> key = {R, sh.rj, sh.wg, sh.rows_per_member, x_dtype};
+    if (ctx->bplan_mem && ctx->bplan_key == key) return ISING_OK;
+    if (R > 8) {
+        ctx->bplan_key = key;
+        return ISING_OK;
+    }
+    const int RJ = std::min(sh.rj, R);
+    const int groups = R / RJ;
+    int cus = 256;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
+    const int n_xcd = std::max(1, std::min(doch::kBatchMaxXcd, cus / 32));
+    doch::BatchShape eff = sh;
+    eff.rj = RJ;
+    const int grid = doch::batch_shape_grid(eff, x_dtype, ctx->vt);
+    if (grid < 1) return fail(ISING_E_HIP, "no resident workgroups for the batch shape");
+    const int pmax = std::max(1, std::min(doch::kBatchMaxTeam, grid / n_xcd / 2));
+    std::vector<int32_t> order(static_cast<size_t>(ctx->count));
+    for (int k = 0; k < ctx->count; ++k) order[k] = k;
+    auto work = [&](int k) { return static_cast<int64_t>(ctx->inst_host[k].nnz) + ctx->inst_host[k].n; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work(a) > work(b); });
+    std::vector<doch::BatchJob> jobs;
+    std::vector<int32_t> singles;
+    std::vector<std::vector<int32_t>> bins(static_cast<size_t>(n_xcd));
+    std::vector<int64_t> load(static_cast<size_t>(n_xcd), 0);
+    std::vector<int> room(static_cast<size_t>(n_xcd), grid / n_xcd);
+    int n_teams = 0;
+    for (int32_t k : order) {
+        const int n = ctx->inst_host[k].n;
+        int P = 1;
+        if (sh.rows_per_member > 0)
+            P = static_cast<int>(std::min<int64_t>(pmax, (n + sh.rows_per_member - 1) / sh.rows_per_member));
+        P = std::max(1, std::min(P, n));
+        for (int g = 0; g < groups; ++g) {
+            int x = -1;
+            if (P > 1)
+                for (int q = 0; q < n_xcd; ++q)
+                    if (room[q] >= P && (x < 0 || load[q] < load[x])) x = q;
+            doch::BatchJob J;
+            J.inst = k;
+            J.r0 = g * RJ;
+            J.P = x >= 0 ? P : 1;
+            J.team = x >= 0 ? n_teams++ : -1;
+            const int id = static_cast<int>(jobs.size());
+            jobs.push_back(J);
+            if (x >= 0) {
+                bins[x].push_back(id);
+                load[x] += work(k);
+                room[x] -= P;
+            } else {
+                singles.push_back(id);
+            }
+        }
+    }
+    std::vector<doch::BatchTicket> tickets;
+    std::vector<int32_t> off(doch::kBatchMaxXcd + 1, 0);
+    for (int x = 0; x < doch::kBatchMaxXcd; ++x) {
+        off[x] = static_cast<int32_t>(tickets.size());
+        if (x < n_xcd)
+            for (int id : bins[x])
+                for (int m = 0; m < jobs[id].P; ++m) tickets.push_back({id, m});
+    }
+    off[doch::kBatchMaxXcd] = static_cast<int32_t>(tickets.size());
+    const size_t K = 4 * static_cast<size_t>(RJ);
+    const size_t b_args = align256(sizeof(doch::BatchTeamArgs));
+    const size_t b_jobs = align256(jobs.size() * sizeof(doch::BatchJob));
+    const size_t b_tickets = align256(std::max<size_t>(1, tickets.size()) * sizeof(doch::BatchTicket));
+    const size_t b_off = align256(off.size() * sizeof(int32_t));
+    const size_t b_singles = align256(std::max<size_t>(1, singles.size()) * sizeof(int32_t));
+    const size_t b_counters = align256(doch::kBatchCounterWords * sizeof(unsigned int));
+    const size_t b_bar = align256(std::max(1, n_teams) * 32 * sizeof(unsigned int));
+    const size_t b_partials = align256(std::max(1, n_teams) * 2 * static_cast<size_t>(pmax) * K * sizeof(double));
+    const size_t total = b_args + b_jobs + b_tickets + b_off + b_singles + b_counters + b_bar + b_partials;
+    HIP_OK(ensure(&ctx->bplan_mem, &ctx->bplan_bytes, total), "hipMalloc(batch plan)");
+    ctx->bargs_dev = static_cast<doch::BatchTeamArgs*>(ctx->bplan_mem);
+    char* base = static_cast<char*>(ctx->bplan_mem) + b_args;
+    doch::BatchPlan& pl = ctx->bplan;
+    auto* d_jobs = reinterpret_cast<doch::BatchJob*>(base);
+    auto* d_tickets = reinterpret_cast<doch::BatchTicket*>(base + b_jobs);
+    auto* d_off = reinterpret_cast<int32_t*>(base + b_jobs + b_tickets);
+    auto* d_singles = reinterpret_cast<int32_t*>(base + b_jobs + b_tickets + b_off);
+    pl.jobs = d_jobs;
+    pl.tickets = d_tickets;
+    pl.off = d_off;
+    pl.singles = d_singles;
+    pl.counters = reinterpret_cast<unsigned int*>(base + b_jobs + b_tickets + b_off + b_singles);
+    pl.bar = reinterpret_cast<unsigned int*>(base + b_jobs + b_tickets + b_off + b_singles + b_counters);
+    pl.partials = reinterpret_cast<double*>(base + b_jobs + b_tickets + b_off + b_singles + b_counters + b_bar);
+    pl.n_singles = static_cast<int32_t>(singles.size());
+    pl.n_teams = n_teams;
+    pl.n_xcd = n_xcd;
+    pl.pmax = pmax;
+    HIP_OK(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(doch::BatchJob), hipMemcpyHostToDevice, s),
+           "copy jobs");
+    if (!tickets.empty())
+        HIP_OK(hipMemcpyAsync(d_tickets, tickets.data(), tickets.size() * sizeof(doch::BatchTicket),
+                              hipMemcpyHostToDevice, s), "copy tickets");
+    HIP_OK(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy offsets");
+    if (!singles.empty())
+        HIP_OK(hipMemcpyAsync(d_singles, singles.data(), singles.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+               "copy single jobs");
+    HIP_OK(hipStreamSynchronize(s), "sync");
+    ctx->bplan_key = key;
+    return ISING_OK;
 }
 
 ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t max_iters,
@@ -1120,12 +1242,14 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
     std::copy(beta_host, beta_host + count, ab.begin() + count);
     HIP_OK(hipMemcpyAsync(ctx->bparams, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice, s),
            "copy alpha/beta");
-    int cus = 256;
-    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
-    const int shape = batch_shape(R, count, cus);
+    const doch::BatchShape shape = batch_shape_for(ctx, R);
+    ising_status pst = ensure_batch_plan(ctx, R, shape, x_dtype, s);
+    if (pst != ISING_OK) return pst;
     // the whole solve is one persistent kernel (after a small init kernel),
     // captured once into a graph and replayed while the arguments repeat
-    const std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(shape),
+    const std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(shape.rj),
+                                       static_cast<uint64_t>(shape.wg), static_cast<uint64_t>(shape.rows_per_member),
+                                       reinterpret_cast<uint64_t>(ctx->bplan_mem),
                                        static_cast<uint64_t>(max_iters),
                                        static_cast<uint64_t>(x_dtype), reinterpret_cast<uint64_t>(x0_dev),
                                        reinterpret_cast<uint64_t>(x_out_dev), reinterpret_cast<uint64_t>(s_out_dev),
@@ -1134,11 +1258,36 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
     if (!ctx->bgraph || ctx->bgraph_key != key) {
         if (ctx->bgraph) { (void)hipGraphExecDestroy(ctx->bgraph); ctx->bgraph = nullptr; }
         if (ctx->bgraph_src) { (void)hipGraphDestroy(ctx->bgraph_src); ctx->bgraph_src = nullptr; }
+        if (R <= 8) {
+            // the kernel's arguments, in stream order after earlier solves
+            doch::BatchTeamArgs& ta = ctx->bargs_host;
+            ta.rp = ctx->rp;
+            ta.col = ctx->col;
+            ta.val = ctx->val;
+            ta.inst = ctx->inst;
+            ta.R = R;
+            ta.alpha = ctx->bparams;
+            ta.beta = ctx->bparams + count;
+            ta.eps = eps;
+            ta.max_iters = max_iters;
+            ta.x0 = x0_dev;
+            ta.xa = ctx->xbuf[0];
+            ta.xb = ctx->xbuf[1];
+            ta.plan = ctx->bplan;
+            ta.stats = ctx->bstats;
+            ta.clock_start = ctx->bclock;
+            ta.clock_end = ctx->bclock + 1;
+            ta.x_out = x_out_dev;
+            ta.s_out = s_out_dev;
+            HIP_OK(hipMemcpyAsync(ctx->bargs_dev, &ta, sizeof(ta), hipMemcpyHostToDevice, s), "copy batch arguments");
+        }
         hipStream_t cs;
         HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            e = doch::launch_batch_solve(batch_view(ctx), R, shape, max_iters, ctx->bparams, ctx->bparams + count, eps,
+            e = doch::launch_batch_solve(batch_view(ctx), R, shape, ctx->bplan, ctx->bargs_dev, max_iters,
+                                         ctx->bparams,
+                                         ctx->bparams + count, eps,
                                          x_dtype, x0_dev, ctx->xbuf[0], ctx->xbuf[1], ctx->bqueue, ctx->bstats,
                                          ctx->bclock, ctx->bclock + 1, x_out_dev, s_out_dev, cs);
             hipGraph_t g = nullptr;
@@ -1163,7 +1312,16 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
                "copy stats");
         HIP_OK(hipMemcpyAsync(clk.data(), ctx->bclock, clk.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s),
                "copy clocks");
+        unsigned int aborted = 0;
+        if (R <= 8)
+            HIP_OK(hipMemcpyAsync(&aborted, ctx->bplan.counters + 32 * 9, sizeof(aborted), hipMemcpyDeviceToHost, s),
+                   "copy abort word");
         HIP_OK(hipStreamSynchronize(s), "sync");
+        if (aborted) return fail(ISING_E_HIP, "a team of workgroups timed out waiting at its barrier");
+        if (max_iters > 0)
+            for (size_t q = 0; q < hs.size(); ++q)
+                if (hs[q].iters_done < 1)
+                    return fail(ISING_E_HIP, "restart %zu of the batch was never run", q);
         bool bad = false;
         if (stats_host) {
             for (size_t q = 0; q < hs.size(); ++q) {
@@ -1197,6 +1355,196 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     HIP_OK(doch::launch_batch_energy(batch_view(ctx), s_dev, R, E_dev, E_int_dev, static_cast<hipStream_t>(stream)),
            "batch energy");
+    return ISING_OK;
+}
+
+ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32_t rows_per_member) {
+    if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
+    if (rj == 0 && wg == 0 && rows_per_member == 0) {      // back to the default
+        ctx->bshape_set = false;
+        return ISING_OK;
+    }
+    doch::BatchShape sh;
+    sh.rj = rj;
+    sh.wg = wg;
+    sh.rows_per_member = rows_per_member;
+    if (!doch::batch_shape_supported(sh, rj))
+        return fail(ISING_E_INVALID_ARG, "no batch kernel for %d restarts per job on %d threads (rows per member %d)",
+                    rj, wg, rows_per_member);
+    ctx->bshape = sh;
+    ctx->bshape_set = true;
+    return ISING_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The tuning cache is a JSON object with one entry per line,
+//   "key": {"rj": 8, "wg": 256, "rows_per_member": 2048, "ms": 12.5},
+// written and read only by the two functions below.
+bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh, double* ms) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    const std::string head = "\"" + key + "\": {";
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        const char* p = std::strstr(line, head.c_str());
+        if (!p) continue;
+        int rj = 0, wg = 0, rpm = 0;
+        double t = 0.0;
+        if (std::sscanf(p + head.size(), " \"rj\": %d, \"wg\": %d, \"rows_per_member\": %d, \"ms\": %lf", &rj, &wg,
+                        &rpm, &t) == 4) {
+            sh->rj = rj;
+            sh->wg = wg;
+            sh->rows_per_member = rpm;
+            *ms = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+bool cache_store(const char* path, const std::string& key, const doch::BatchShape& sh, double ms) {
+    if (!path) return false;
+    std::vector<std::string> entries;
+    const std::string head = "\"" + key + "\": {";
+    if (FILE* f = std::fopen(path, "r")) {
+        char line[1024];
+        while (std::fgets(line, sizeof(line), f)) {
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == '\r' || l.back() == ',' || l.back() == ' '))
+                l.pop_back();
+            if (l.size() < 2 || l[0] != '"' || l.find(head) == 0) continue;
+            entries.push_back(l);
+        }
+        std::fclose(f);
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s\"rj\": %d, \"wg\": %d, \"rows_per_member\": %d, \"ms\": %.4f}", head.c_str(),
+                  sh.rj, sh.wg, sh.rows_per_member, ms);
+    entries.emplace_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fputs("{\n", f);
+    for (size_t i = 0; i < entries.size(); ++i)
+        std::fprintf(f, "%s%s\n", entries[i].c_str(), i + 1 < entries.size() ? "," : "");
+    std::fputs("}\n", f);
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+ising_status ising_autotune_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t max_iters,
+                                  const double* alpha_host, const double* beta_host, double eps, int32_t x_dtype,
+                                  const char* cache_path, void* stream, int32_t* shape_out, double* ms_out,
+                                  int32_t* from_cache_out) {
+    if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
+    if (!doch::batch_restarts_supported(R)) return fail(ISING_E_INVALID_ARG, "R must be 1, 2, 4, 8, 16 or 32");
+    if (R > 8) return fail(ISING_E_UNSUPPORTED, "more than 8 restarts run one workgroup per instance: nothing to tune");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, ctx->device), "device properties");
+    int64_t rows = 0, nnz = 0;
+    for (const auto& I : ctx->inst_host) {
+        rows += I.n;
+        nnz += I.nnz;
+    }
+    char kb[512];
+    std::snprintf(kb, sizeof(kb), "batch-v1|%s|cus=%d|count=%d|rows=%lld|nnz=%lld|R=%d|x=%s|v=%s|iters=%lld|eps=%.6g",
+                  prop.gcnArchName, prop.multiProcessorCount, ctx->count, static_cast<long long>(rows),
+                  static_cast<long long>(nnz), R, x_dtype == ISING_F64 ? "f64" : "f32",
+                  ctx->vt == ISING_F64 ? "f64" : "f32", static_cast<long long>(max_iters), eps);
+    const std::string key(kb);
+    doch::BatchShape best;
+    double best_ms = 0.0;
+    if (cache_lookup(cache_path, key, &best, &best_ms) && doch::batch_shape_supported(best, R)) {
+        ctx->bshape = best;
+        ctx->bshape_set = true;
+        if (shape_out) {
+            shape_out[0] = best.rj;
+            shape_out[1] = best.wg;
+            shape_out[2] = best.rows_per_member;
+        }
+        if (ms_out) *ms_out = best_ms;
+        if (from_cache_out) *from_cache_out = 1;
+        return ISING_OK;
+    }
+    // candidates: restart groups and threads the kernel is built for, team
+    // sizes from none to 512 rows per member
+    std::vector<doch::BatchShape> cand;
+    const int rjs[4] = {8, 4, 2, 1};
+    const int wgs[3] = {256, 512, 1024};
+    const int rpms[5] = {0, 4096, 2048, 1024, 512};
+    for (int rj : rjs) {
+        if (rj > R) continue;
+        for (int wg : wgs)
+            for (int rpm : rpms) {
+                doch::BatchShape sh;
+                sh.rj = rj;
+                sh.wg = wg;
+                sh.rows_per_member = rpm;
+                if (doch::batch_shape_supported(sh, R)) cand.push_back(sh);
+            }
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0), "event");
+    HIP_OK(hipEventCreate(&e1), "event");
+    const doch::BatchShape saved = ctx->bshape;
+    const bool saved_set = ctx->bshape_set;
+    best_ms = -1.0;
+    ising_status st = ISING_OK;
+    for (const auto& sh : cand) {
+        ctx->bshape = sh;
+        ctx->bshape_set = true;
+        // one run to capture and load, one timed
+        st = ising_solve_batch(ctx, x0_dev, R, max_iters, alpha_host, beta_host, eps, x_dtype, nullptr, nullptr,
+                               nullptr, nullptr, stream);
+        if (st != ISING_OK) break;
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) {
+            st = ising_solve_batch(ctx, x0_dev, R, max_iters, alpha_host, beta_host, eps, x_dtype, nullptr, nullptr,
+                                   nullptr, nullptr, stream);
+            if (st != ISING_OK) break;
+            e = hipEventRecord(e1, s);
+        }
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "autotune timing");
+            break;
+        }
+        if (best_ms < 0.0 || ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ISING_OK || best_ms < 0.0) {
+        ctx->bshape = saved;
+        ctx->bshape_set = saved_set;
+        return st != ISING_OK ? st : fail(ISING_E_UNSUPPORTED, "no batch shape to try");
+    }
+    ctx->bshape = best;
+    ctx->bshape_set = true;
+    if (shape_out) {
+        shape_out[0] = best.rj;
+        shape_out[1] = best.wg;
+        shape_out[2] = best.rows_per_member;
+    }
+    if (ms_out) *ms_out = best_ms;
+    if (from_cache_out) *from_cache_out = 0;
+    (void)cache_store(cache_path, key, best, best_ms);
     return ISING_OK;
 }
 

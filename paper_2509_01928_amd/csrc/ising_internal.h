@@ -175,6 +175,68 @@ struct BatchRestartStat {
     double r_last;
 };
 
+// Launch shape of the batch solve for up to 8 restarts: restarts per job
+// (rj), threads per workgroup (wg) and the rows each member of a team of
+// workgroups takes (rows_per_member; 0 = every job on one workgroup).
+struct BatchShape {
+    int rj = 8;
+    int wg = 256;
+    int rows_per_member = 0;
+};
+
+// One job of the batch solve: restart group [r0, r0 + rj) of instance
+// `inst`, run by a team of P workgroups of one XCD (P = 1: one workgroup of
+// any XCD); `team` numbers the team jobs (their barrier and partial sums).
+struct BatchJob {
+    int32_t inst, r0, P, team;
+};
+struct BatchTicket {
+    int32_t job, member;
+};
+
+constexpr int kBatchMaxXcd = 8;
+constexpr int kBatchMaxTeam = 16;
+constexpr int kBatchCounterWords = 10 * 32;   // queue words, 128 bytes apart
+
+// Device side of a job plan (library-owned arrays built by the host).
+struct BatchPlan {
+    const BatchJob* jobs = nullptr;
+    const BatchTicket* tickets = nullptr;   // team tickets; XCD x's are [off[x], off[x+1])
+    const int32_t* off = nullptr;           // kBatchMaxXcd + 1 entries
+    const int32_t* singles = nullptr;       // jobs with P = 1, largest first
+    int32_t n_singles = 0;
+    int32_t n_teams = 0;
+    int32_t n_xcd = 1;
+    int32_t pmax = 1;
+    unsigned int* counters = nullptr;       // [32 x] team queue of XCD x, [32*8] singles, [32*9] abort
+    unsigned int* bar = nullptr;            // team barrier counters, 32 words apart
+    double* partials = nullptr;             // [team][2][pmax][4 * rj]
+};
+
+// Arguments of the batch kernel for up to 8 restarts.  They live in device
+// memory and the kernel reads them through one pointer (as kernel
+// arguments they would be held in scalar registers for the whole launch).
+struct BatchTeamArgs {
+    const int32_t* rp;
+    const int32_t* col;
+    const void* val;
+    const BatchInstance* inst;
+    int R;
+    const double* alpha;
+    const double* beta;
+    double eps;
+    int64_t max_iters;
+    const double* x0;
+    void* xa;
+    void* xb;
+    BatchPlan plan;
+    BatchRestartStat* stats;
+    uint64_t* clock_start;
+    uint64_t* clock_end;
+    double* x_out;
+    int8_t* s_out;
+};
+
 struct BatchView {
     int count;
     const int32_t* rp;
@@ -254,6 +316,15 @@ struct ising_ctx {
     size_t bstats_bytes = 0;
     uint64_t* bclock = nullptr;          // [0] = start, [1 + k] = end of instance k
     unsigned int* bqueue = nullptr;
+    // launch shape and job plan of the batch solve (R <= 8)
+    doch::BatchShape bshape;
+    bool bshape_set = false;
+    std::vector<int64_t> bplan_key;
+    doch::BatchPlan bplan;
+    doch::BatchTeamArgs bargs_host{};
+    doch::BatchTeamArgs* bargs_dev = nullptr;   // in bplan_mem
+    void* bplan_mem = nullptr;
+    size_t bplan_bytes = 0;
     // dense low-precision path (ising_solve_lowp)
     void* jq[2] = {nullptr, nullptr};    // BF16 / FP8 copies of J, padded
     float* rscale = nullptr;             // FP8 per-row scales
@@ -337,9 +408,16 @@ hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s
 // ---- launchers (kernels_batch.hip) ----
 bool batch_restarts_supported(int R);
 hipError_t launch_batch_validate(const BatchView& B, int64_t n, int32_t* bad, hipStream_t s);
-// shape (up to 8 restarts): 0 = all restarts per job, 256 threads; 1 = groups
-// of 4, 512 threads; 2 = groups of 2, 1024 threads; 3 = one restart, 1024
-hipError_t launch_batch_solve(const BatchView& B, int R, int shape, int64_t max_iters, const double* alpha,
+// Up to 8 restarts: the job plan's teams and single jobs on a persistent
+// grid of `wg`-thread workgroups (shape.rj restarts per job); 16 or 32: one
+// workgroup per instance with a restart per lane (shape and plan unused).
+bool batch_shape_supported(const BatchShape& sh, int R);
+// Resident workgroups of the shape's kernel on the current device.
+int batch_shape_grid(const BatchShape& sh, int x_dtype, int vt);
+// args_dev: the device copy of the kernel's arguments (R <= 8), written by
+// the caller in stream order before the launch.
+hipError_t launch_batch_solve(const BatchView& B, int R, const BatchShape& shape, const BatchPlan& plan,
+                              const BatchTeamArgs* args_dev, int64_t max_iters, const double* alpha,
                               const double* beta, double eps, int x_dtype, const double* x0,
                               void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
                               uint64_t* clock_start, uint64_t* clock_end, double* x_out,

@@ -207,129 +207,265 @@ __device__ __forceinline__ void store_row(XT* p, const XT (&in)[R]) {
     *reinterpret_cast<typename RowVec<XT, R>::type*>(p) = w;
 }
 
-// The same batch loop with one row per thread and a group of RJ (<= 8) of
-// an instance's R restarts in the thread's registers.  A job is (instance,
-// restart group): restarts never interact, so the groups of one instance run
-// as independent jobs, and the fewer restarts a job carries the fewer
-// registers it needs and the more threads (rows in flight) a workgroup can
-// have -- the length of an iteration of a large instance is set by how many
-// rows are in flight against the memory latency, not by the arithmetic.  A
-// coupling costs one index and one value (loaded in aligned 16-byte chunks,
-// the next chunk requested before this one's gathers are waited for) and one
-// contiguous RJ-wide read of the iterate.  Sums run in the rows' stored
-// (ascending column) order; the workgroup reductions are in a fixed order.
-// Jobs are taken largest instance first; an instance's time to solution is
-// the end of its last job.
+// R contiguous iterate entries read from the XCD's L2, past this CU's L1
+// (sc0 buffer loads): the workgroups of a team run on different CUs of one
+// XCD, whose L1 caches are not kept coherent with each other, while the
+// XCD's L2 is shared by them.  `rs` covers the instance's iterate block;
+// out-of-range offsets would read zeros (the couplings are checked to stay
+// in their block when the batch is created).
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufferWord3 = 0x00020000;        // raw buffer, gfx9 family
+constexpr int kSc0 = 1;                         // cache policy: L1 miss always
+
+template <typename XT, int R>
+__device__ __forceinline__ void load_row_l2(__amdgpu_buffer_rsrc_t rs, uint32_t off, XT (&out)[R]) {
+    constexpr int kBytes = static_cast<int>(sizeof(XT)) * R;
+    if constexpr (kBytes % 16 == 0) {
+        constexpr int W = kBytes / 16;
+        i32x4 w[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16 * i, 0, kSc0);
+        __builtin_memcpy(out, w, kBytes);
+    } else if constexpr (kBytes == 8) {
+        const i32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kSc0);
+        __builtin_memcpy(out, &w, 8);
+    } else {
+        static_assert(kBytes == 4, "one FP32 entry");
+        const int w = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kSc0);
+        __builtin_memcpy(out, &w, 4);
+    }
+}
+
+__device__ __forceinline__ double ld_l2(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Which XCD this workgroup runs on (the hardware XCC id register).
+__device__ __forceinline__ unsigned int xcd_id() {
+    unsigned int v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 0xfu;
+}
+
+constexpr unsigned int kTeamSpinLimit = 1u << 24;
+
+// Rows [lo, hi) of one instance, restarts [r0, r0 + RJ): z = J x, the
+// update of eq:FPE and the sums of eq:Hamilton and Remark S2 (x^4, x^2,
+// x z, (dx)^2 per restart).  One row per thread; a coupling costs one index
+// and one value (aligned 16-byte chunks, the next chunk requested before
+// this one's gathers are waited for) and one contiguous RJ-wide read of the
+// iterate, from L2 for a team (COH: other workgroups wrote it), through
+// this CU's L1 for a single job (this workgroup wrote all of it); row sums
+// in ascending column order.
+template <typename XT, typename VT, int RJ, int WG, bool COH>
+__device__ __forceinline__ void team_sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, int R, int r0, const BatchInstance& I,
+                                           int lo, int hi, const XT* xo, XT* xw, const bool (&frozen)[RJ],
+                                           double a, double b, double (&acc)[4 * RJ]) {
+    const XT* xblk = xo + static_cast<int64_t>(I.row0) * R;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<XT*>(xblk), static_cast<short>(0), static_cast<int>(static_cast<int64_t>(I.n) * R * sizeof(XT)),
+        kBufferWord3);
+    int sn = 0, en = 0;                 // the next row's offsets, requested early
+    if (lo + static_cast<int>(threadIdx.x) < hi) {
+        sn = rp[lo + threadIdx.x];
+        en = rp[lo + threadIdx.x + 1];
+    }
+    for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += WG) {
+        const int s = sn, e = en;
+        if (i + WG < hi) {
+            sn = rp[i + WG];
+            en = rp[i + WG + 1];
+        }
+        double z[RJ];
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) z[r] = 0.0;
+        using CV = typename Vec4<int>::type;
+        using VV = typename Vec4<VT>::type;
+        int c0 = s & ~3;
+        CV cn{};
+        VV vn{};
+        if (c0 < e) {
+            cn = *reinterpret_cast<const CV*>(col + c0);
+            vn = *reinterpret_cast<const VV*>(val + c0);
+        }
+        for (; c0 < e; c0 += 4) {
+            const CV cv = cn;
+            const VV vv = vn;
+            if (c0 + 4 < e) {
+                cn = *reinterpret_cast<const CV*>(col + c0 + 4);
+                vn = *reinterpret_cast<const VV*>(val + c0 + 4);
+            }
+            const int cc[4] = {cv.x, cv.y, cv.z, cv.w};
+            const double vd[4] = {static_cast<double>(vv.x), static_cast<double>(vv.y),
+                                  static_cast<double>(vv.z), static_cast<double>(vv.w)};
+            XT g[4][RJ];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u >= s && c0 + u < e) {
+                    if constexpr (COH) load_row_l2<XT, RJ>(rs, static_cast<uint32_t>(((cc[u] - I.row0) * R + r0) * sizeof(XT)), g[u]);
+                    else load_row<XT, RJ>(xo + static_cast<int64_t>(cc[u]) * R + r0, g[u]);
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u >= s && c0 + u < e) {
+#pragma unroll
+                    for (int r = 0; r < RJ; ++r) z[r] = dadd(z[r], dmul(vd[u], static_cast<double>(g[u][r])));
+                }
+        }
+        XT xi[RJ], xn[RJ];
+        // a row's own entries were written by this workgroup
+        load_row<XT, RJ>(xo + static_cast<int64_t>(i) * R + r0, xi);
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+            const double xv = static_cast<double>(xi[r]);
+            if (frozen[r]) {
+                xn[r] = xi[r];
+            } else {
+                xn[r] = static_cast<XT>(cbrt(ddiv(dadd(z[r], dmul(a, xv)), b)));
+                const double d = dsub(static_cast<double>(xn[r]), xv);
+                const double x2 = dmul(xv, xv);
+                acc[4 * r + 0] = dadd(acc[4 * r + 0], dmul(x2, x2));
+                acc[4 * r + 1] = dadd(acc[4 * r + 1], x2);
+                acc[4 * r + 2] = dadd(acc[4 * r + 2], dmul(xv, z[r]));
+                acc[4 * r + 3] = dadd(acc[4 * r + 3], dmul(d, d));
+            }
+        }
+        store_row<XT, RJ>(xw + static_cast<int64_t>(i) * R + r0, xn);
+    }
+}
+
+// Barrier number `gen` of a team of P workgroups: every wave waits for its
+// stores (iterate rows, partial sums) to reach L2, thread 0 counts the
+// workgroup in and polls the counter.  Returns false if the wait exceeded
+// its bound or another workgroup gave up (the abort word is then set and
+// the caller leaves the kernel).
+__device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int target, unsigned int* abort_word,
+                                             int* s_flag) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned int spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kTeamSpinLimit ||
+                __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_flag = ok;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
+// The batch loop for up to 8 restarts on a persistent grid.  A job is a
+// group of RJ of an instance's R restarts (restarts never interact, so the
+// groups run as independent jobs); a large instance's job is split by rows
+// over a team of P workgroups.  A workgroup first takes tickets of its own
+// XCD's team queue, then single jobs from the common queue (largest
+// first).  Team members exchange their iterate rows and partial sums
+// through the XCD's L2 and meet at a barrier once per iteration; every
+// member adds the members' partial sums in member order, so all of them
+// take the same stopping decisions.  The host plans no more team tickets
+// for an XCD than it has resident workgroups, so every team ticket is
+// taken in the launch's first round and a team's members all run from the
+// start; a wait that still exceeds its bound sets the abort word, which the
+// host reports.  An instance's time to solution is the end of its last job.
 template <typename XT, typename VT, int RJ, int WG>
-__global__ __launch_bounds__(WG) void batch_rows_kernel(
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const VT* __restrict__ val,
-    const BatchInstance* __restrict__ inst, const int32_t* __restrict__ order, int count, int R,
-    const double* __restrict__ alpha, const double* __restrict__ beta, double eps,
-    int64_t max_iters, const double* __restrict__ x0, XT* __restrict__ xa, XT* __restrict__ xb,
-    unsigned int* queue, BatchRestartStat* __restrict__ stats, uint64_t* __restrict__ clock_start,
-    uint64_t* __restrict__ clock_end, double* __restrict__ x_out, int8_t* __restrict__ s_out) {
+__global__ __launch_bounds__(WG) void batch_team_kernel(const BatchTeamArgs* __restrict__ args) {
+    const BatchTeamArgs& A = *args;
     constexpr int K = 4 * RJ;                 // x^4, x^2, x z, (dx)^2 per restart
     __shared__ double red[K * (WG / kWave)];
     __shared__ int conv[RJ];
-    __shared__ int s_job;
-    __shared__ int s_all;
-    const int groups = R / RJ;
-    const int njobs = count * groups;
-    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned long long*>(clock_start),
+    __shared__ int s_job, s_member, s_all, s_flag;
+    const BatchPlan& pl = A.plan;
+    const VT* val = static_cast<const VT*>(A.val);
+    const int R = A.R;
+    unsigned int* abort_word = pl.counters + 32 * 9;
+    const unsigned int xcd = xcd_id() % static_cast<unsigned int>(pl.n_xcd);
+    bool team_open = true;                    // thread 0: this XCD's team queue may hold tickets
+    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned long long*>(A.clock_start),
                                     static_cast<unsigned long long>(device_clock()));
     for (;;) {
-        if (threadIdx.x == 0) s_job = static_cast<int>(atomicAdd(queue, 1u));
+        if (threadIdx.x == 0) {
+            int job = -1, member = 0;
+            if (team_open) {
+                const int t = static_cast<int>(atomicAdd(pl.counters + 32 * xcd, 1u)) + pl.off[xcd];
+                if (t < pl.off[xcd + 1]) {
+                    job = pl.tickets[t].job;
+                    member = pl.tickets[t].member;
+                } else {
+                    team_open = false;
+                }
+            }
+            if (job < 0) {
+                const int t = static_cast<int>(atomicAdd(pl.counters + 32 * 8, 1u));
+                if (t < pl.n_singles) job = pl.singles[t];
+            }
+            s_job = job;
+            s_member = member;
+        }
         if (threadIdx.x < RJ) conv[threadIdx.x] = 0;
         __syncthreads();
-        const int job = s_job;
-        if (job >= njobs) break;
-        const int k = order[job / groups];
-        const int r0 = (job % groups) * RJ;
-        const BatchInstance I = inst[k];
-        const double a = alpha[k], b = beta[k];
-        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(I.n) * RJ; t += WG) {
-            const int64_t e = (I.row0 + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
-            xa[e] = static_cast<XT>(x0[e]);
+        const int jid = s_job;
+        const int member = s_member;
+        if (jid < 0) break;
+        const BatchJob J = pl.jobs[jid];
+        const int k = J.inst;
+        const int r0 = J.r0;
+        const int P = J.P;
+        const BatchInstance I = A.inst[k];
+        const double a = A.alpha[k], b = A.beta[k];
+        const int lo = I.row0 + static_cast<int>(static_cast<int64_t>(I.n) * member / P);
+        const int hi = I.row0 + static_cast<int>(static_cast<int64_t>(I.n) * (member + 1) / P);
+        unsigned int* bar = pl.bar + 32 * static_cast<size_t>(J.team >= 0 ? J.team : 0);
+        XT* xa = static_cast<XT*>(A.xa);
+        XT* xb = static_cast<XT*>(A.xb);
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(hi - lo) * RJ; t += WG) {
+            const int64_t e = (lo + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
+            xa[e] = static_cast<XT>(A.x0[e]);
         }
-        __syncthreads();
+        if (P > 1) {
+            if (!team_barrier(bar, static_cast<unsigned int>(P), abort_word, &s_flag)) return;
+        } else {
+            __syncthreads();
+        }
         const XT* xo = xa;
         XT* xw = xb;
         int64_t it = 0;
-        for (; it < max_iters; ++it) {
+        for (; it < A.max_iters; ++it) {
             bool frozen[RJ];
 #pragma unroll
             for (int r = 0; r < RJ; ++r) frozen[r] = conv[r] != 0;
             double acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = 0.0;
-            const int iend = I.row0 + I.n;
-            int sn = 0, en = 0;                 // the next row's offsets, requested early
-            if (I.row0 + static_cast<int>(threadIdx.x) < iend) {
-                sn = rp[I.row0 + threadIdx.x];
-                en = rp[I.row0 + threadIdx.x + 1];
-            }
-            for (int i = I.row0 + static_cast<int>(threadIdx.x); i < iend; i += WG) {
-                const int s = sn, e = en;
-                if (i + WG < iend) {
-                    sn = rp[i + WG];
-                    en = rp[i + WG + 1];
+            if (P > 1) team_sweep<XT, VT, RJ, WG, true>(A.rp, A.col, val, R, r0, I, lo, hi, xo, xw, frozen, a, b, acc);
+            else team_sweep<XT, VT, RJ, WG, false>(A.rp, A.col, val, R, r0, I, lo, hi, xo, xw, frozen, a, b, acc);
+            block_sum<K, WG>(acc, red);       // this workgroup's totals in thread 0
+            if (P > 1) {
+                double* pp = pl.partials + ((static_cast<size_t>(J.team) * 2 + (it & 1)) * pl.pmax) * K;
+                if (threadIdx.x == 0) {
+#pragma unroll
+                    for (int q = 0; q < K; ++q) pp[static_cast<size_t>(member) * K + q] = acc[q];
                 }
-                double z[RJ];
+                if (!team_barrier(bar, static_cast<unsigned int>(P) * static_cast<unsigned int>(it + 2), abort_word,
+                                  &s_flag))
+                    return;
+                if (threadIdx.x == 0) {
 #pragma unroll
-                for (int r = 0; r < RJ; ++r) z[r] = 0.0;
-                // the next chunk's indices and values are requested before this
-                // chunk's gathers are waited for
-                using CV = typename Vec4<int>::type;
-                using VV = typename Vec4<VT>::type;
-                int c0 = s & ~3;
-                CV cn{};
-                VV vn{};
-                if (c0 < e) {
-                    cn = *reinterpret_cast<const CV*>(col + c0);
-                    vn = *reinterpret_cast<const VV*>(val + c0);
-                }
-                for (; c0 < e; c0 += 4) {
-                    const CV cv = cn;
-                    const VV vv = vn;
-                    if (c0 + 4 < e) {
-                        cn = *reinterpret_cast<const CV*>(col + c0 + 4);
-                        vn = *reinterpret_cast<const VV*>(val + c0 + 4);
-                    }
-                    const int cc[4] = {cv.x, cv.y, cv.z, cv.w};
-                    const double vd[4] = {static_cast<double>(vv.x), static_cast<double>(vv.y),
-                                          static_cast<double>(vv.z), static_cast<double>(vv.w)};
-                    XT g[4][RJ];
+                    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+                    for (int m = 0; m < P; ++m) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (c0 + u >= s && c0 + u < e)
-                            load_row<XT, RJ>(xo + static_cast<int64_t>(cc[u]) * R + r0, g[u]);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (c0 + u >= s && c0 + u < e) {
-#pragma unroll
-                            for (int r = 0; r < RJ; ++r) z[r] = dadd(z[r], dmul(vd[u], static_cast<double>(g[u][r])));
-                        }
-                }
-                XT xi[RJ], xn[RJ];
-                load_row<XT, RJ>(xo + static_cast<int64_t>(i) * R + r0, xi);
-#pragma unroll
-                for (int r = 0; r < RJ; ++r) {
-                    const double xv = static_cast<double>(xi[r]);
-                    if (frozen[r]) {
-                        xn[r] = xi[r];
-                    } else {
-                        xn[r] = static_cast<XT>(cbrt(ddiv(dadd(z[r], dmul(a, xv)), b)));
-                        const double d = dsub(static_cast<double>(xn[r]), xv);
-                        const double x2 = dmul(xv, xv);
-                        acc[4 * r + 0] = dadd(acc[4 * r + 0], dmul(x2, x2));
-                        acc[4 * r + 1] = dadd(acc[4 * r + 1], x2);
-                        acc[4 * r + 2] = dadd(acc[4 * r + 2], dmul(xv, z[r]));
-                        acc[4 * r + 3] = dadd(acc[4 * r + 3], dmul(d, d));
+                        for (int q = 0; q < K; ++q) acc[q] = dadd(acc[q], ld_l2(pp + static_cast<size_t>(m) * K + q));
                     }
                 }
-                store_row<XT, RJ>(xw + static_cast<int64_t>(i) * R + r0, xn);
             }
-            block_sum<K, WG>(acc, red);       // totals in thread 0
             if (threadIdx.x == 0) {
                 int all = 1;
                 for (int r = 0; r < RJ; ++r) {
@@ -338,17 +474,23 @@ __global__ __launch_bounds__(WG) void batch_rows_kernel(
                         const double H = dsub(dsub(dmul(ddiv(b, 4.0), S[0]), dmul(ddiv(a, 2.0), S[1])),
                                               dmul(0.5, S[2]));
                         const double rr = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
-                        BatchRestartStat& st = stats[static_cast<int64_t>(k) * R + r0 + r];
-                        st.iters_done = it + 1;
-                        st.H_last = H;
-                        st.r_last = rr;
+                        int stop = 0, nonfinite = 0, converged = 0;
                         if (!isfinite(H) || !isfinite(rr)) {
-                            st.nonfinite = 1;
-                            conv[r] = 1;
-                        } else if (eps > 0.0 && rr < eps) {
-                            st.converged = 1;
-                            conv[r] = 1;
+                            nonfinite = 1;
+                            stop = 1;
+                        } else if (A.eps > 0.0 && rr < A.eps) {
+                            converged = 1;
+                            stop = 1;
                         }
+                        if (member == 0) {
+                            BatchRestartStat& st = A.stats[static_cast<int64_t>(k) * R + r0 + r];
+                            st.iters_done = it + 1;
+                            st.H_last = H;
+                            st.r_last = rr;
+                            st.nonfinite = nonfinite;
+                            st.converged = converged;
+                        }
+                        conv[r] = stop;
                     }
                     all &= conv[r];
                 }
@@ -363,15 +505,15 @@ __global__ __launch_bounds__(WG) void batch_rows_kernel(
                 break;
             }
         }
-        // outputs from the buffer that holds x^(it)
-        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(I.n) * RJ; t += WG) {
-            const int64_t e = (I.row0 + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
+        // outputs of this member's rows from the buffer that holds x^(it)
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(hi - lo) * RJ; t += WG) {
+            const int64_t e = (lo + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
             const double v = static_cast<double>(xo[e]);
-            if (x_out) x_out[e] = v;
-            if (s_out) s_out[e] = v >= 0.0 ? 1 : -1;
+            if (A.x_out) A.x_out[e] = v;
+            if (A.s_out) A.s_out[e] = v >= 0.0 ? 1 : -1;
         }
         if (threadIdx.x == 0)
-            atomicMax(reinterpret_cast<unsigned long long*>(clock_end + k),
+            atomicMax(reinterpret_cast<unsigned long long*>(A.clock_end + k),
                       static_cast<unsigned long long>(device_clock()));
         __syncthreads();
     }
@@ -379,19 +521,23 @@ __global__ __launch_bounds__(WG) void batch_rows_kernel(
 
 template <int R>
 __global__ void batch_init_kernel(BatchRestartStat* stats, int count, unsigned int* queue,
-                                  uint64_t* clock_start, uint64_t* clock_end) {
+                                  uint64_t* clock_start, uint64_t* clock_end, unsigned int* counters,
+                                  unsigned int* bar, int n_bar_words) {
     const int64_t total = static_cast<int64_t>(count) * R;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count;
-         t += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        clock_end[t] = 0;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
-         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t t = t0; t < count; t += stride) clock_end[t] = 0;
+    for (int64_t t = t0; t < total; t += stride) {
         stats[t].iters_done = 0;
         stats[t].converged = 0;
         stats[t].nonfinite = 0;
         stats[t].H_last = 0.0;
         stats[t].r_last = 0.0;
     }
+    if (counters)
+        for (int64_t t = t0; t < kBatchCounterWords; t += stride) counters[t] = 0u;
+    if (bar)
+        for (int64_t t = t0; t < n_bar_words; t += stride) bar[t] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *queue = 0u;
         *clock_start = ~0ull;
@@ -602,53 +748,104 @@ bool batch_restarts_supported(int R) {
     return R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32;
 }
 
-hipError_t launch_batch_solve(const BatchView& B, int R, int shape, int64_t max_iters, const double* alpha,
+// The (restarts per job, threads) pairs the team kernel is built for.
+static bool team_shape_built(int rj, int wg) {
+    switch (rj) {
+        case 8:
+        case 4: return wg == 256 || wg == 512;
+        case 2:
+        case 1: return wg == 512 || wg == 1024;
+        default: return false;
+    }
+}
+
+bool batch_shape_supported(const BatchShape& sh, int R) {
+    if (R > 8) return true;                   // restart-per-lane kernel, no shape
+    if (sh.rows_per_member < 0) return false;
+    if (sh.rj != 1 && sh.rj != 2 && sh.rj != 4 && sh.rj != 8) return false;
+    return team_shape_built(std::min(sh.rj, R), sh.wg);
+}
+
+// Calls f(kernel pointer, RJ, WG tags) for the team kernel of the shape.
+template <typename XT, typename VT, typename F>
+static hipError_t with_team_kernel(int RJ, int WG, F&& f) {
+    using std::integral_constant;
+#define DOCH_TEAM(RJV, WGV)                                                                          \
+    if (RJ == RJV && WG == WGV)                                                                      \
+        return f(batch_team_kernel<XT, VT, RJV, WGV>, integral_constant<int, WGV>());
+    DOCH_TEAM(8, 256)
+    DOCH_TEAM(8, 512)
+    DOCH_TEAM(4, 256)
+    DOCH_TEAM(4, 512)
+    DOCH_TEAM(2, 512)
+    DOCH_TEAM(2, 1024)
+    DOCH_TEAM(1, 512)
+    DOCH_TEAM(1, 1024)
+#undef DOCH_TEAM
+    return hipErrorInvalidValue;
+}
+
+template <typename F>
+static hipError_t with_types(int x_dtype, int vt, F&& f) {
+    if (vt == ISING_F64) return x_dtype == ISING_F64 ? f(double(), double()) : f(float(), double());
+    return x_dtype == ISING_F64 ? f(double(), float()) : f(float(), float());
+}
+
+int batch_shape_grid(const BatchShape& sh, int x_dtype, int vt) {
+    int grid = 0;
+    (void)with_types(x_dtype, vt, [&](auto xtag, auto vtag) {
+        using XT = decltype(xtag);
+        using VT = decltype(vtag);
+        return with_team_kernel<XT, VT>(sh.rj, sh.wg, [&](auto kern, auto wgtag) {
+            grid = resident_grid(kern, decltype(wgtag)::value);
+            return hipSuccess;
+        });
+    });
+    return grid;
+}
+
+hipError_t launch_batch_solve(const BatchView& B, int R, const BatchShape& shape, const BatchPlan& plan,
+                              const BatchTeamArgs* args_dev, int64_t max_iters, const double* alpha,
                               const double* beta, double eps, int x_dtype, const double* x0,
                               void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
                               uint64_t* clock_start, uint64_t* clock_end, double* x_out,
                               int8_t* s_out, hipStream_t s) {
+    if (!batch_restarts_supported(R)) return hipErrorInvalidValue;
+    const int ig = static_cast<int>(std::min<int64_t>(1024, (static_cast<int64_t>(B.count) * R + 255) / 256));
+    const bool team = R <= 8;
     DOCH_BATCH_R(R, {
-        const int ig = static_cast<int>(std::min<int64_t>(1024, (static_cast<int64_t>(B.count) * RR + 255) / 256));
         hipLaunchKernelGGL(batch_init_kernel<RR>, dim3(ig), dim3(256), 0, s, stats, B.count, queue,
-                           clock_start, clock_end);
-        // up to 8 restarts: a row per thread, restart groups of RJ as jobs of
-        // WG-thread workgroups (shape); more: a restart per lane
-        auto go = [&](auto xtag, auto vtag) {
+                           clock_start, clock_end, team ? plan.counters : nullptr, team ? plan.bar : nullptr,
+                           team ? 32 * plan.n_teams : 0);
+    });
+    if (team) {
+        if (!batch_shape_supported(shape, R)) return hipErrorInvalidValue;
+        hipError_t e = with_types(x_dtype, B.vt, [&](auto xtag, auto vtag) {
             using XT = decltype(xtag);
             using VT = decltype(vtag);
-            if constexpr (RR <= 8) {
-                auto rows = [&](auto rjtag, auto wgtag) {
-                    constexpr int RJ = decltype(rjtag)::value < RR ? decltype(rjtag)::value : RR;
-                    constexpr int WG = decltype(wgtag)::value;
-                    auto kern = batch_rows_kernel<XT, VT, RJ, WG>;
-                    const int grid = std::min(resident_grid(kern, WG), B.count * (RR / RJ));
-                    hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, B.rp, B.col,
-                                       static_cast<const VT*>(B.val), B.inst, B.order, B.count, RR, alpha,
-                                       beta, eps, max_iters, x0, static_cast<XT*>(xa), static_cast<XT*>(xb),
-                                       queue, stats, clock_start, clock_end, x_out, s_out);
-                };
-                using std::integral_constant;
-                switch (shape) {
-                    case 1: rows(integral_constant<int, 4>(), integral_constant<int, 512>()); break;
-                    case 2: rows(integral_constant<int, 2>(), integral_constant<int, 1024>()); break;
-                    case 3: rows(integral_constant<int, 1>(), integral_constant<int, 1024>()); break;
-                    default: rows(integral_constant<int, 8>(), integral_constant<int, 256>()); break;
-                }
-            } else {
+            return with_team_kernel<XT, VT>(std::min(shape.rj, R), shape.wg, [&](auto kern, auto wgtag) {
+                constexpr int WG = decltype(wgtag)::value;
+                hipLaunchKernelGGL(kern, dim3(resident_grid(kern, WG)), dim3(WG), 0, s, args_dev);
+                return hipSuccess;
+            });
+        });
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    }
+    DOCH_BATCH_R(R, {
+        if constexpr (RR > 8) {
+            auto go = [&](auto xtag, auto vtag) {
+                using XT = decltype(xtag);
+                using VT = decltype(vtag);
                 auto kern = batch_solve_kernel<XT, VT, RR>;
                 const int grid = std::min(resident_grid(kern, BT), B.count);
                 hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, B.rp, B.col, static_cast<const VT*>(B.val),
                                    B.inst, B.order, B.count, alpha, beta, eps, max_iters, x0,
                                    static_cast<XT*>(xa), static_cast<XT*>(xb), queue, stats, clock_start,
                                    clock_end, x_out, s_out);
-            }
-        };
-        if (B.vt == ISING_F64) {
-            if (x_dtype == ISING_F64) go(double(), double());
-            else go(float(), double());
-        } else {
-            if (x_dtype == ISING_F64) go(double(), float());
-            else go(float(), float());
+                return hipSuccess;
+            };
+            (void)with_types(x_dtype, B.vt, go);
         }
     });
     return hipGetLastError();

@@ -112,9 +112,9 @@ def test_batch_fixed_iterations_parity(R):
 
 @pytest.mark.parametrize("count", [300, 150, 64, 9])
 def test_batch_restart_groups_parity(count):
-    """8 restarts per instance, split into jobs of 8, 4, 2 or 1 restarts
-    depending on how many instances there are (one job per CU at least):
-    every sampled (instance, restart) follows its own oracle run."""
+    """8 restarts per instance, many small instances (single-workgroup jobs
+    of the default shape): every sampled (instance, restart) follows its own
+    oracle run."""
     R = 8
     inst = gen.uneven_batch(count=count, seed=500 + count, n_lo=40, n_hi=160, d_lo=3.0, d_hi=9.0)
     alpha, beta = oracle_params(inst)
@@ -219,3 +219,125 @@ def test_batch_rejects_cross_block_coupling():
         L.ising_create_batch([A.n for A in inst], torch.from_numpy(rp).to(d),
                              torch.from_numpy(col).to(d), torch.from_numpy(val).to(d), L.ISING_F32)
     assert e.value.status == L.ISING_E_INVALID_ARG
+
+
+# ------------------------------------------------------ teams of workgroups
+@pytest.fixture(scope="module")
+def team_case():
+    """Instances of 20000, 9000, 2600 and 700 rows (mean degrees 20, 12, 8,
+    5) x 8 restarts, with the oracle's trajectories of 60 fixed iterations
+    and of the eps = 1e-3 stopping rule for every (instance, restart)."""
+    sizes = [(20000, 20.0), (9000, 12.0), (2600, 8.0), (700, 5.0)]
+    inst = [gen.er_csr(n, d, 7100 + i) for i, (n, d) in enumerate(sizes)]
+    alpha, beta = oracle_params(inst)
+    R = 8
+    total = sum(A.n for A in inst)
+    X0 = gen.uniform_x0(total, R, 7200)
+    offs = np.concatenate([[0], np.cumsum([A.n for A in inst])])
+    fixed, stop = {}, {}
+    for k, A in enumerate(inst):
+        B = orc.to_oracle_csr(A)
+        for r in range(R):
+            x0 = X0[offs[k]:offs[k + 1], r]
+            fixed[k, r] = orc.doch(B, x0, alpha[k], beta[k], 60)
+            stop[k, r] = orc.doch(B, x0, alpha[k], beta[k], 5000, eps=1e-3)
+    return dict(inst=inst, alpha=alpha, beta=beta, R=R, X0=X0, fixed=fixed, stop=stop)
+
+
+@pytest.mark.parametrize("rj,wg,rpm", [(8, 256, 1024), (8, 512, 4096), (4, 256, 500), (2, 1024, 2048),
+                                       (1, 512, 3000), (8, 256, 0)])
+def test_batch_team_shapes_parity(team_case, rj, wg, rpm):
+    """Every launch shape: jobs of rj restarts; instances split over teams of
+    ceil(n / rpm) workgroups (the 20000-row instance over 16 at rpm 1024 and
+    500) that exchange iterate rows through L2 each iteration.  Iterates,
+    spins, H and r after 60 iterations follow the oracle per (instance,
+    restart); under eps = 1e-3 every restart stops at the oracle's
+    iteration; exact energies."""
+    import paper_2509_01928_amd as L
+    c = team_case
+    inst, R = c["inst"], c["R"]
+    G = GpuBatch(inst, R)
+    try:
+        L.ising_set_batch_shape(G.ctx, rj, wg, rpm)
+        X, S, st, tts = G.solve(c["X0"], c["alpha"], c["beta"], 60, 0.0)
+        E, Ei = G.energy(S)
+        X2, S2, st2, tts2 = G.solve(c["X0"], c["alpha"], c["beta"], 5000, 1e-3)
+    finally:
+        G.close()
+    for k, A in enumerate(inst):
+        B = orc.to_oracle_csr(A)
+        a, b = G.offs[k], G.offs[k + 1]
+        for r in range(R):
+            lab = f"shape ({rj}, {wg}, {rpm}) instance {k} (n={A.n}) restart {r}"
+            tr = c["fixed"][k, r]
+            assert_iterate_parity(X[a:b, r], tr.x, lab)
+            assert_spin_parity(S[a:b, r], tr.x, orc.sign(tr.x), lab)
+            s_ = st[k * R + r]
+            assert s_.iters_done == 60 and not s_.converged, lab
+            assert s_.H_last == pytest.approx(tr.H[-1], rel=1e-12), lab
+            assert s_.r_last == pytest.approx(tr.r[-1], rel=1e-9, abs=1e-12), lab
+            assert int(Ei[k * R + r]) == orc.energy_i64(B, S[a:b, r]), lab
+            ts = c["stop"][k, r]
+            s2 = st2[k * R + r]
+            assert s2.iters_done == ts.iters and s2.converged == 1, lab
+            assert_iterate_parity(X2[a:b, r], ts.x, lab + " (eps)")
+    assert np.all(tts > 0) and np.all(tts2 > 0)
+
+
+def test_batch_set_shape_rejects_unbuilt():
+    import paper_2509_01928_amd as L
+    inst = small_batch(count=2, seed=5)
+    G = GpuBatch(inst, 8)
+    try:
+        for rj, wg, rpm in ((8, 1024, 0), (3, 256, 0), (4, 128, 0), (8, 256, -1)):
+            with pytest.raises(L.IsingError) as e:
+                L.ising_set_batch_shape(G.ctx, rj, wg, rpm)
+            assert e.value.status == L.ISING_E_INVALID_ARG
+        L.ising_set_batch_shape(G.ctx, 0, 0, 0)      # the default again
+    finally:
+        G.close()
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    """The autotuner times every built shape, keeps the fastest, and writes
+    it to the JSON cache; a second context over the same batch reads it back
+    without timing; the tuned shape's solve follows the oracle."""
+    import json
+    import torch
+    import paper_2509_01928_amd as L
+    R = 4
+    inst = gen.uneven_batch(count=24, seed=77, n_lo=200, n_hi=6000)
+    alpha, beta = oracle_params(inst)
+    total = sum(A.n for A in inst)
+    X0 = gen.uniform_x0(total, R, 78)
+    cache = str(tmp_path / "shapes.json")
+    G = GpuBatch(inst, R)
+    try:
+        xd = torch.from_numpy(X0).to("cuda:0")
+        shape, ms, cached = L.ising_autotune_batch(G.ctx, xd, R, 5000, alpha, beta, 1e-3, L.ISING_F64, cache)
+        assert not cached and ms > 0
+        assert shape[0] in (1, 2, 4) and shape[1] in (256, 512, 1024) and shape[2] >= 0
+        X, S, st, _ = G.solve(X0, alpha, beta, 5000, 1e-3)
+    finally:
+        G.close()
+    with open(cache) as f:
+        data = json.load(f)
+    assert len(data) == 1
+    (entry,) = data.values()
+    assert (entry["rj"], entry["wg"], entry["rows_per_member"]) == tuple(shape)
+    G2 = GpuBatch(inst, R)
+    try:
+        xd = torch.from_numpy(X0).to("cuda:0")
+        shape2, ms2, cached2 = L.ising_autotune_batch(G2.ctx, xd, R, 5000, alpha, beta, 1e-3, L.ISING_F64,
+                                                      cache)
+    finally:
+        G2.close()
+    assert cached2 and tuple(shape2) == tuple(shape) and ms2 == pytest.approx(ms, rel=1e-3)
+    for k in (0, 7, 23):
+        A = inst[k]
+        B = orc.to_oracle_csr(A)
+        a, b = G.offs[k], G.offs[k + 1]
+        for r in range(R):
+            tr = orc.doch(B, X0[a:b, r], alpha[k], beta[k], 5000, eps=1e-3)
+            assert st[k * R + r].iters_done == tr.iters, (k, r)
+            assert_iterate_parity(X[a:b, r], tr.x, f"tuned shape {shape}: instance {k} restart {r}")
