@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--oracle-restarts", type=int, default=0,
                     help="oracle restarts of the dense 4096 workload (0: one per host thread, at most 16)")
     ap.add_argument("--batch-shape", default="",
-                    help="batch512: launch shape 'rj,wg,rows_per_member' instead of the autotuner's")
+                    help="batch512: launch shape 'rj,wg,chunk_rows' instead of the autotuner's")
     ap.add_argument("--tune-cache",
                     default=os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
                                          "paper_2509_01928_amd", "batch_shapes.json"),
@@ -640,7 +640,7 @@ def bench_batch512(args):
                                         "x_storage": args.x_dtype,
                                         "launch_shape": {"restarts_per_job": tune["shape"][0],
                                                          "threads": tune["shape"][1],
-                                                         "rows_per_member": tune["shape"][2],
+                                                         "chunk_rows": tune["shape"][2],
                                                          "chosen_by": tune["source"]}},
         "autotune": tune,
         "tts_ms_p50": float(np.percentile(tts, 50)), "tts_ms_p99": float(np.percentile(tts, 99)),

@@ -333,14 +333,15 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
  * device clock) make the call synchronous; a synchronous call also returns
  * ISING_E_HIP if a team of workgroups gave up waiting at its barrier (after
  * about a second) or a restart was never run.  No per-iteration log.
- * With R <= 8 the launch shape set by ising_set_batch_shape or
- * ising_autotune_batch applies: jobs of rj restarts of one instance, run
- * on wg-thread workgroups; an instance of n rows is split over a team of
- * ceil(n / rows_per_member) workgroups of one XCD (at most 16; 0 = never
- * split), which meet at a barrier once per iteration.  Default: rj = 8 (or
- * R), wg = 256 (512 below 4 restarts per job), rows_per_member = 2048.
- * The iterates do not depend on the shape; H and r are summed in a
- * shape-dependent order.
+ * With R <= 8 the instances' restart groups of rj restarts (units) are
+ * dealt to the GPU's XCDs and each XCD iterates its units in lockstep: the
+ * units' rows are cut into chunks of chunk_rows rows spread over all the
+ * XCD's workgroups of wg threads, which meet at a barrier once per
+ * iteration; a unit drops out when all its restarts stopped.  The shape
+ * (rj, wg, chunk_rows) is set by ising_set_batch_shape or
+ * ising_autotune_batch; default rj = 8 (or R), wg = 256 (512 below 4
+ * restarts per unit), chunk_rows = 512.  The iterates do not depend on the
+ * shape; H and r are summed in a shape-dependent order.
  *
  * ising_energy_batch: eq:IsingModel of each instance and restart,
  * E_dev[k*R + r] in FP64 and E_int_dev[k*R + r] exactly (integer couplings
@@ -361,19 +362,19 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
 
 /* Launch shape of ising_solve_batch for R <= 8 (see above).  Built pairs
  * (rj, wg): (8, 256), (8, 512), (4, 256), (4, 512), (2, 512), (2, 1024),
- * (1, 512), (1, 1024); rows_per_member >= 0.  rj larger than the solve's R
- * runs R restarts per job.  All three 0 restores the default.
+ * (1, 512), (1, 1024); chunk_rows >= 1.  rj larger than the solve's R
+ * runs R restarts per unit.  All three 0 restores the default.
  * ISING_E_INVALID_ARG for other values or a non-batch context. */
-ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32_t rows_per_member);
+ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32_t chunk_rows);
 
 /* Choose the launch shape of ising_solve_batch for these arguments by
  * timing the solve (one warm-up and one timed run, device events) for every
- * built (rj <= R, wg) pair and rows_per_member in {0, 4096, 2048, 1024,
- * 512}; the fastest becomes the context's shape.  With cache_path, a JSON
+ * built (rj <= R, wg) pair and chunk_rows in {256, 512, 1024, 2048}; the
+ * fastest becomes the context's shape.  With cache_path, a JSON
  * file of earlier choices is consulted first, keyed by the device (gfx
  * name, CU count), the batch (instances, rows, couplings, value type) and
  * the solve (R, iterate type, max_iters, eps); a fresh choice is added to
- * it.  shape_out (3 ints: rj, wg, rows_per_member), ms_out (the chosen
+ * it.  shape_out (3 ints: rj, wg, chunk_rows), ms_out (the chosen
  * shape's time in ms) and from_cache_out (1 when read from the file) may be
  * NULL.  The trial solves overwrite the context's iterate buffers and
  * statistics.  Arguments as for ising_solve_batch; R <= 8

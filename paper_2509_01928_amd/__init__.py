@@ -323,13 +323,13 @@ def ising_energy_batch(ctx, s, R, E=None, E_int=None, stream=None):
            "ising_energy_batch")
 
 
-def ising_set_batch_shape(ctx, rj, wg, rows_per_member):
-    _check(lib.ising_set_batch_shape(ctx, int(rj), int(wg), int(rows_per_member)), "ising_set_batch_shape")
+def ising_set_batch_shape(ctx, rj, wg, chunk_rows):
+    _check(lib.ising_set_batch_shape(ctx, int(rj), int(wg), int(chunk_rows)), "ising_set_batch_shape")
 
 
 def ising_autotune_batch(ctx, x0, R, max_iters, alpha, beta, eps=0.0, x_dtype=ISING_F64, cache_path=None,
                          stream=None):
-    """Returns ((rj, wg, rows_per_member), milliseconds, from_cache)."""
+    """Returns ((rj, wg, chunk_rows), milliseconds, from_cache)."""
     import numpy as np
     alpha = np.ascontiguousarray(alpha, dtype=np.float64)
     beta = np.ascontiguousarray(beta, dtype=np.float64)

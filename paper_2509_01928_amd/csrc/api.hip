@@ -1074,14 +1074,14 @@ ising_status ising_default_params_batch(ising_ctx* ctx, double eta, int32_t meth
 }
 
 // Default launch shape of the batch solve for R <= 8 restarts: every
-// restart of an instance in one job (a row's R iterate entries share one
+// restart of an instance in one unit (a row's R iterate entries share one
 // cache line, so splitting the restarts multiplies the lines the gathers
-// fetch), teams of workgroups for instances of more than 2048 rows.
+// fetch), 256 threads (512 below 4 restarts per unit), chunks of 512 rows.
 static doch::BatchShape default_batch_shape(int R) {
     doch::BatchShape sh;
     sh.rj = std::min(8, R);
     sh.wg = sh.rj >= 4 ? 256 : 512;
-    sh.rows_per_member = 2048;
+    sh.chunk_rows = 512;
     return sh;
 }
 
@@ -1092,18 +1092,13 @@ static doch::BatchShape batch_shape_for(const ising_ctx* ctx, int R) {
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// The job plan of the batch solve for R <= 8 restarts and shape `sh`:
-// jobs in decreasing instance size; an instance of n rows gets a team of
-// P = ceil(n / rows_per_member) workgroups (at most pmax, at most half of
-// an XCD's resident workgroups); team jobs are dealt to the XCD queues
-// largest first, each to the queue with the least work so far among those
-// with room for its P members, where an XCD's room is its resident
-// workgroups: every team ticket is taken in the launch's first round, so a
-// team's members meet at once.  A job that finds no room, and every job of
-// one workgroup, is a single job of the common queue.
+// The plan of the lockstep batch solve for R <= 8 restarts and shape `sh`:
+// units (restart groups of instances) dealt to the XCDs largest first, each
+// to the XCD with the least work so far; each unit's rows cut into chunks
+// of sh.chunk_rows rows (the last one shorter).
 static ising_status ensure_batch_plan(ising_ctx* ctx, int R, const doch::BatchShape& sh, int x_dtype,
                                       hipStream_t s) {
-    const std::vector<int64_t> key = {R, sh.rj, sh.wg, sh.rows_per_member, x_dtype};
+    const std::vector<int64_t> key = {R, sh.rj, sh.wg, sh.chunk_rows, x_dtype};
     if (ctx->bplan_mem && ctx->bplan_key == key) return ISING_OK;
     if (R > 8) {
         ctx->bplan_key = key;
@@ -1114,95 +1109,92 @@ static ising_status ensure_batch_plan(ising_ctx* ctx, int R, const doch::BatchSh
     int cus = 256;
     HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
     const int n_xcd = std::max(1, std::min(doch::kBatchMaxXcd, cus / 32));
-    doch::BatchShape eff = sh;
-    eff.rj = RJ;
-    const int grid = doch::batch_shape_grid(eff, x_dtype, ctx->vt);
-    if (grid < 1) return fail(ISING_E_HIP, "no resident workgroups for the batch shape");
-    const int pmax = std::max(1, std::min(doch::kBatchMaxTeam, grid / n_xcd / 2));
     std::vector<int32_t> order(static_cast<size_t>(ctx->count));
     for (int k = 0; k < ctx->count; ++k) order[k] = k;
     auto work = [&](int k) { return static_cast<int64_t>(ctx->inst_host[k].nnz) + ctx->inst_host[k].n; };
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work(a) > work(b); });
-    std::vector<doch::BatchJob> jobs;
-    std::vector<int32_t> singles;
-    std::vector<std::vector<int32_t>> bins(static_cast<size_t>(n_xcd));
+    std::vector<std::vector<int32_t>> bins(static_cast<size_t>(n_xcd));   // units per XCD
     std::vector<int64_t> load(static_cast<size_t>(n_xcd), 0);
-    std::vector<int> room(static_cast<size_t>(n_xcd), grid / n_xcd);
-    int n_teams = 0;
-    for (int32_t k : order) {
-        const int n = ctx->inst_host[k].n;
-        int P = 1;
-        if (sh.rows_per_member > 0)
-            P = static_cast<int>(std::min<int64_t>(pmax, (n + sh.rows_per_member - 1) / sh.rows_per_member));
-        P = std::max(1, std::min(P, n));
+    std::vector<doch::BatchUnit> units;
+    for (int32_t k : order)
         for (int g = 0; g < groups; ++g) {
-            int x = -1;
-            if (P > 1)
-                for (int q = 0; q < n_xcd; ++q)
-                    if (room[q] >= P && (x < 0 || load[q] < load[x])) x = q;
-            doch::BatchJob J;
-            J.inst = k;
-            J.r0 = g * RJ;
-            J.P = x >= 0 ? P : 1;
-            J.team = x >= 0 ? n_teams++ : -1;
-            const int id = static_cast<int>(jobs.size());
-            jobs.push_back(J);
-            if (x >= 0) {
-                bins[x].push_back(id);
-                load[x] += work(k);
-                room[x] -= P;
-            } else {
-                singles.push_back(id);
+            const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+            doch::BatchUnit U;
+            U.inst = k;
+            U.r0 = g * RJ;
+            U.first_slot = 0;
+            U.nchunks = 0;
+            bins[x].push_back(static_cast<int32_t>(units.size()));
+            units.push_back(U);
+            load[x] += work(k);
+        }
+    std::vector<doch::BatchChunk> chunks;
+    std::vector<int32_t> off(doch::kBatchMaxXcd + 1, 0), units_on(doch::kBatchMaxXcd, 0);
+    for (int x = 0; x < doch::kBatchMaxXcd; ++x) {
+        off[x] = static_cast<int32_t>(chunks.size());
+        if (x >= n_xcd) continue;
+        units_on[x] = static_cast<int32_t>(bins[x].size());
+        for (int32_t u : bins[x]) {
+            const doch::BatchInstance& I = ctx->inst_host[units[u].inst];
+            units[u].first_slot = static_cast<int32_t>(chunks.size());
+            for (int lo = 0; lo < I.n; lo += sh.chunk_rows) {
+                doch::BatchChunk c;
+                c.unit = u;
+                c.lo = I.row0 + lo;
+                c.hi = I.row0 + std::min(I.n, lo + sh.chunk_rows);
+                c.slot = static_cast<int32_t>(chunks.size());
+                chunks.push_back(c);
+                ++units[u].nchunks;
             }
         }
     }
-    std::vector<doch::BatchTicket> tickets;
-    std::vector<int32_t> off(doch::kBatchMaxXcd + 1, 0);
-    for (int x = 0; x < doch::kBatchMaxXcd; ++x) {
-        off[x] = static_cast<int32_t>(tickets.size());
-        if (x < n_xcd)
-            for (int id : bins[x])
-                for (int m = 0; m < jobs[id].P; ++m) tickets.push_back({id, m});
-    }
-    off[doch::kBatchMaxXcd] = static_cast<int32_t>(tickets.size());
+    off[doch::kBatchMaxXcd] = static_cast<int32_t>(chunks.size());
     const size_t K = 4 * static_cast<size_t>(RJ);
-    const size_t b_args = align256(sizeof(doch::BatchTeamArgs));
-    const size_t b_jobs = align256(jobs.size() * sizeof(doch::BatchJob));
-    const size_t b_tickets = align256(std::max<size_t>(1, tickets.size()) * sizeof(doch::BatchTicket));
+    const size_t nu = units.size();
+    const size_t b_args = align256(sizeof(doch::BatchStepArgs));
+    const size_t b_units = align256(nu * sizeof(doch::BatchUnit));
+    const size_t b_chunks = align256(chunks.size() * sizeof(doch::BatchChunk));
     const size_t b_off = align256(off.size() * sizeof(int32_t));
-    const size_t b_singles = align256(std::max<size_t>(1, singles.size()) * sizeof(int32_t));
+    const size_t b_on = align256(units_on.size() * sizeof(int32_t));
     const size_t b_counters = align256(doch::kBatchCounterWords * sizeof(unsigned int));
-    const size_t b_bar = align256(std::max(1, n_teams) * 32 * sizeof(unsigned int));
-    const size_t b_partials = align256(std::max(1, n_teams) * 2 * static_cast<size_t>(pmax) * K * sizeof(double));
-    const size_t total = b_args + b_jobs + b_tickets + b_off + b_singles + b_counters + b_bar + b_partials;
+    const size_t b_tickets = align256(nu * 32 * sizeof(unsigned int));
+    const size_t b_done = align256(nu * sizeof(int32_t));
+    const size_t b_conv = align256(nu * RJ * sizeof(int32_t));
+    const size_t b_partials = align256(chunks.size() * K * sizeof(double));
+    const size_t total =
+        b_args + b_units + b_chunks + b_off + b_on + b_counters + b_tickets + b_done + b_conv + b_partials;
     HIP_OK(ensure(&ctx->bplan_mem, &ctx->bplan_bytes, total), "hipMalloc(batch plan)");
-    ctx->bargs_dev = static_cast<doch::BatchTeamArgs*>(ctx->bplan_mem);
-    char* base = static_cast<char*>(ctx->bplan_mem) + b_args;
+    char* p = static_cast<char*>(ctx->bplan_mem);
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += bytes;
+        return q;
+    };
+    ctx->bargs_dev = reinterpret_cast<doch::BatchStepArgs*>(take(b_args));
+    auto* d_units = reinterpret_cast<doch::BatchUnit*>(take(b_units));
+    auto* d_chunks = reinterpret_cast<doch::BatchChunk*>(take(b_chunks));
+    auto* d_off = reinterpret_cast<int32_t*>(take(b_off));
+    auto* d_on = reinterpret_cast<int32_t*>(take(b_on));
     doch::BatchPlan& pl = ctx->bplan;
-    auto* d_jobs = reinterpret_cast<doch::BatchJob*>(base);
-    auto* d_tickets = reinterpret_cast<doch::BatchTicket*>(base + b_jobs);
-    auto* d_off = reinterpret_cast<int32_t*>(base + b_jobs + b_tickets);
-    auto* d_singles = reinterpret_cast<int32_t*>(base + b_jobs + b_tickets + b_off);
-    pl.jobs = d_jobs;
-    pl.tickets = d_tickets;
+    pl.units = d_units;
+    pl.chunks = d_chunks;
     pl.off = d_off;
-    pl.singles = d_singles;
-    pl.counters = reinterpret_cast<unsigned int*>(base + b_jobs + b_tickets + b_off + b_singles);
-    pl.bar = reinterpret_cast<unsigned int*>(base + b_jobs + b_tickets + b_off + b_singles + b_counters);
-    pl.partials = reinterpret_cast<double*>(base + b_jobs + b_tickets + b_off + b_singles + b_counters + b_bar);
-    pl.n_singles = static_cast<int32_t>(singles.size());
-    pl.n_teams = n_teams;
+    pl.units_on = d_on;
+    pl.counters = reinterpret_cast<unsigned int*>(take(b_counters));
+    pl.tickets = reinterpret_cast<unsigned int*>(take(b_tickets));
+    pl.done = reinterpret_cast<int32_t*>(take(b_done));
+    pl.conv = reinterpret_cast<int32_t*>(take(b_conv));
+    pl.partials = reinterpret_cast<double*>(take(b_partials));
+    pl.n_units = static_cast<int32_t>(nu);
+    pl.n_slots = static_cast<int32_t>(chunks.size());
     pl.n_xcd = n_xcd;
-    pl.pmax = pmax;
-    HIP_OK(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(doch::BatchJob), hipMemcpyHostToDevice, s),
-           "copy jobs");
-    if (!tickets.empty())
-        HIP_OK(hipMemcpyAsync(d_tickets, tickets.data(), tickets.size() * sizeof(doch::BatchTicket),
-                              hipMemcpyHostToDevice, s), "copy tickets");
+    pl.rj = RJ;
+    HIP_OK(hipMemcpyAsync(d_units, units.data(), nu * sizeof(doch::BatchUnit), hipMemcpyHostToDevice, s), "copy units");
+    HIP_OK(hipMemcpyAsync(d_chunks, chunks.data(), chunks.size() * sizeof(doch::BatchChunk), hipMemcpyHostToDevice, s),
+           "copy chunks");
     HIP_OK(hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy offsets");
-    if (!singles.empty())
-        HIP_OK(hipMemcpyAsync(d_singles, singles.data(), singles.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
-               "copy single jobs");
+    HIP_OK(hipMemcpyAsync(d_on, units_on.data(), units_on.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+           "copy unit counts");
     HIP_OK(hipStreamSynchronize(s), "sync");
     ctx->bplan_key = key;
     return ISING_OK;
@@ -1248,7 +1240,7 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
     // the whole solve is one persistent kernel (after a small init kernel),
     // captured once into a graph and replayed while the arguments repeat
     const std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(shape.rj),
-                                       static_cast<uint64_t>(shape.wg), static_cast<uint64_t>(shape.rows_per_member),
+                                       static_cast<uint64_t>(shape.wg), static_cast<uint64_t>(shape.chunk_rows),
                                        reinterpret_cast<uint64_t>(ctx->bplan_mem),
                                        static_cast<uint64_t>(max_iters),
                                        static_cast<uint64_t>(x_dtype), reinterpret_cast<uint64_t>(x0_dev),
@@ -1260,10 +1252,7 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
         if (ctx->bgraph_src) { (void)hipGraphDestroy(ctx->bgraph_src); ctx->bgraph_src = nullptr; }
         if (R <= 8) {
             // the kernel's arguments, in stream order after earlier solves
-            doch::BatchTeamArgs& ta = ctx->bargs_host;
-            ta.rp = ctx->rp;
-            ta.col = ctx->col;
-            ta.val = ctx->val;
+            doch::BatchStepArgs& ta = ctx->bargs_host;
             ta.inst = ctx->inst;
             ta.R = R;
             ta.alpha = ctx->bparams;
@@ -1271,8 +1260,6 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
             ta.eps = eps;
             ta.max_iters = max_iters;
             ta.x0 = x0_dev;
-            ta.xa = ctx->xbuf[0];
-            ta.xb = ctx->xbuf[1];
             ta.plan = ctx->bplan;
             ta.stats = ctx->bstats;
             ta.clock_start = ctx->bclock;
@@ -1314,10 +1301,10 @@ ising_status ising_solve_batch(ising_ctx* ctx, const double* x0_dev, int32_t R, 
                "copy clocks");
         unsigned int aborted = 0;
         if (R <= 8)
-            HIP_OK(hipMemcpyAsync(&aborted, ctx->bplan.counters + 32 * 9, sizeof(aborted), hipMemcpyDeviceToHost, s),
+            HIP_OK(hipMemcpyAsync(&aborted, ctx->bplan.counters + 32 * 25, sizeof(aborted), hipMemcpyDeviceToHost, s),
                    "copy abort word");
         HIP_OK(hipStreamSynchronize(s), "sync");
-        if (aborted) return fail(ISING_E_HIP, "a team of workgroups timed out waiting at its barrier");
+        if (aborted) return fail(ISING_E_HIP, "the batch kernel's workgroups timed out waiting at a barrier");
         if (max_iters > 0)
             for (size_t q = 0; q < hs.size(); ++q)
                 if (hs[q].iters_done < 1)
@@ -1358,19 +1345,19 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
     return ISING_OK;
 }
 
-ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32_t rows_per_member) {
+ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32_t chunk_rows) {
     if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
-    if (rj == 0 && wg == 0 && rows_per_member == 0) {      // back to the default
+    if (rj == 0 && wg == 0 && chunk_rows == 0) {      // back to the default
         ctx->bshape_set = false;
         return ISING_OK;
     }
     doch::BatchShape sh;
     sh.rj = rj;
     sh.wg = wg;
-    sh.rows_per_member = rows_per_member;
+    sh.chunk_rows = chunk_rows;
     if (!doch::batch_shape_supported(sh, rj))
-        return fail(ISING_E_INVALID_ARG, "no batch kernel for %d restarts per job on %d threads (rows per member %d)",
-                    rj, wg, rows_per_member);
+        return fail(ISING_E_INVALID_ARG, "no batch kernel for %d restarts per unit on %d threads (chunks of %d rows)",
+                    rj, wg, chunk_rows);
     ctx->bshape = sh;
     ctx->bshape_set = true;
     return ISING_OK;
@@ -1381,7 +1368,7 @@ ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32
 namespace {
 
 // The tuning cache is a JSON object with one entry per line,
-//   "key": {"rj": 8, "wg": 256, "rows_per_member": 2048, "ms": 12.5},
+//   "key": {"rj": 8, "wg": 256, "chunk_rows": 512, "ms": 12.5},
 // written and read only by the two functions below.
 bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh, double* ms) {
     if (!path) return false;
@@ -1395,11 +1382,11 @@ bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh
         if (!p) continue;
         int rj = 0, wg = 0, rpm = 0;
         double t = 0.0;
-        if (std::sscanf(p + head.size(), " \"rj\": %d, \"wg\": %d, \"rows_per_member\": %d, \"ms\": %lf", &rj, &wg,
+        if (std::sscanf(p + head.size(), " \"rj\": %d, \"wg\": %d, \"chunk_rows\": %d, \"ms\": %lf", &rj, &wg,
                         &rpm, &t) == 4) {
             sh->rj = rj;
             sh->wg = wg;
-            sh->rows_per_member = rpm;
+            sh->chunk_rows = rpm;
             *ms = t;
             found = true;
         }
@@ -1424,8 +1411,8 @@ bool cache_store(const char* path, const std::string& key, const doch::BatchShap
         std::fclose(f);
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "%s\"rj\": %d, \"wg\": %d, \"rows_per_member\": %d, \"ms\": %.4f}", head.c_str(),
-                  sh.rj, sh.wg, sh.rows_per_member, ms);
+    std::snprintf(buf, sizeof(buf), "%s\"rj\": %d, \"wg\": %d, \"chunk_rows\": %d, \"ms\": %.4f}", head.c_str(),
+                  sh.rj, sh.wg, sh.chunk_rows, ms);
     entries.emplace_back(buf);
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
@@ -1459,7 +1446,7 @@ ising_status ising_autotune_batch(ising_ctx* ctx, const double* x0_dev, int32_t 
         nnz += I.nnz;
     }
     char kb[512];
-    std::snprintf(kb, sizeof(kb), "batch-v1|%s|cus=%d|count=%d|rows=%lld|nnz=%lld|R=%d|x=%s|v=%s|iters=%lld|eps=%.6g",
+    std::snprintf(kb, sizeof(kb), "batch-v2|%s|cus=%d|count=%d|rows=%lld|nnz=%lld|R=%d|x=%s|v=%s|iters=%lld|eps=%.6g",
                   prop.gcnArchName, prop.multiProcessorCount, ctx->count, static_cast<long long>(rows),
                   static_cast<long long>(nnz), R, x_dtype == ISING_F64 ? "f64" : "f32",
                   ctx->vt == ISING_F64 ? "f64" : "f32", static_cast<long long>(max_iters), eps);
@@ -1472,18 +1459,18 @@ ising_status ising_autotune_batch(ising_ctx* ctx, const double* x0_dev, int32_t 
         if (shape_out) {
             shape_out[0] = best.rj;
             shape_out[1] = best.wg;
-            shape_out[2] = best.rows_per_member;
+            shape_out[2] = best.chunk_rows;
         }
         if (ms_out) *ms_out = best_ms;
         if (from_cache_out) *from_cache_out = 1;
         return ISING_OK;
     }
-    // candidates: restart groups and threads the kernel is built for, team
-    // sizes from none to 512 rows per member
+    // candidates: restart groups and threads the kernel is built for,
+    // chunks of 256 to 2048 rows
     std::vector<doch::BatchShape> cand;
     const int rjs[4] = {8, 4, 2, 1};
     const int wgs[3] = {256, 512, 1024};
-    const int rpms[5] = {0, 4096, 2048, 1024, 512};
+    const int rpms[4] = {256, 512, 1024, 2048};
     for (int rj : rjs) {
         if (rj > R) continue;
         for (int wg : wgs)
@@ -1491,7 +1478,7 @@ ising_status ising_autotune_batch(ising_ctx* ctx, const double* x0_dev, int32_t 
                 doch::BatchShape sh;
                 sh.rj = rj;
                 sh.wg = wg;
-                sh.rows_per_member = rpm;
+                sh.chunk_rows = rpm;
                 if (doch::batch_shape_supported(sh, R)) cand.push_back(sh);
             }
     }
@@ -1540,7 +1527,7 @@ ising_status ising_autotune_batch(ising_ctx* ctx, const double* x0_dev, int32_t 
     if (shape_out) {
         shape_out[0] = best.rj;
         shape_out[1] = best.wg;
-        shape_out[2] = best.rows_per_member;
+        shape_out[2] = best.chunk_rows;
     }
     if (ms_out) *ms_out = best_ms;
     if (from_cache_out) *from_cache_out = 0;

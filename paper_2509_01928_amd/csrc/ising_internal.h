@@ -175,51 +175,53 @@ struct BatchRestartStat {
     double r_last;
 };
 
-// Launch shape of the batch solve for up to 8 restarts: restarts per job
-// (rj), threads per workgroup (wg) and the rows each member of a team of
-// workgroups takes (rows_per_member; 0 = every job on one workgroup).
+// Launch shape of the batch solve for up to 8 restarts: restarts per unit
+// of work (rj), threads per workgroup (wg) and rows per chunk (chunk_rows).
 struct BatchShape {
     int rj = 8;
     int wg = 256;
-    int rows_per_member = 0;
+    int chunk_rows = 512;
 };
 
-// One job of the batch solve: restart group [r0, r0 + rj) of instance
-// `inst`, run by a team of P workgroups of one XCD (P = 1: one workgroup of
-// any XCD); `team` numbers the team jobs (their barrier and partial sums).
-struct BatchJob {
-    int32_t inst, r0, P, team;
+// A unit is restart group [r0, r0 + rj) of one instance; its rows are cut
+// into nchunks chunks whose partial sums sit in slots first_slot.. of the
+// plan's partial-sum array.
+struct BatchUnit {
+    int32_t inst, r0, first_slot, nchunks;
 };
-struct BatchTicket {
-    int32_t job, member;
+// Rows [lo, hi) of a unit; its partial sums go to slot `slot`.
+struct BatchChunk {
+    int32_t unit, lo, hi, slot;
 };
 
 constexpr int kBatchMaxXcd = 8;
-constexpr int kBatchMaxTeam = 16;
-constexpr int kBatchCounterWords = 10 * 32;   // queue words, 128 bytes apart
+// Counter words of the batch solve, each on its own 128-byte line:
+// [32 x] workgroups registered on XCD x, [32 (8 + x)] its barrier,
+// [32 (16 + x)] its finished units, [32 * 24] grid registration, [32 * 25] abort.
+constexpr int kBatchCounterWords = 26 * 32;
 
-// Device side of a job plan (library-owned arrays built by the host).
+// Device side of a batch plan (library-owned arrays built by the host).
 struct BatchPlan {
-    const BatchJob* jobs = nullptr;
-    const BatchTicket* tickets = nullptr;   // team tickets; XCD x's are [off[x], off[x+1])
+    const BatchUnit* units = nullptr;
+    const BatchChunk* chunks = nullptr;     // XCD x's chunks are [off[x], off[x + 1])
     const int32_t* off = nullptr;           // kBatchMaxXcd + 1 entries
-    const int32_t* singles = nullptr;       // jobs with P = 1, largest first
-    int32_t n_singles = 0;
-    int32_t n_teams = 0;
+    const int32_t* units_on = nullptr;      // kBatchMaxXcd entries: units per XCD
+    int32_t n_units = 0;
+    int32_t n_slots = 0;
     int32_t n_xcd = 1;
-    int32_t pmax = 1;
-    unsigned int* counters = nullptr;       // [32 x] team queue of XCD x, [32*8] singles, [32*9] abort
-    unsigned int* bar = nullptr;            // team barrier counters, 32 words apart
-    double* partials = nullptr;             // [team][2][pmax][4 * rj]
+    int32_t rj = 1;
+    unsigned int* counters = nullptr;       // kBatchCounterWords
+    unsigned int* tickets = nullptr;        // per unit, 32 words apart
+    int32_t* done = nullptr;                // per unit: iterations when it stopped, 0 while running
+    int32_t* conv = nullptr;                // per unit and restart: stopped
+    double* partials = nullptr;             // [slot][4 * rj]
 };
 
-// Arguments of the batch kernel for up to 8 restarts.  They live in device
-// memory and the kernel reads them through one pointer (as kernel
-// arguments they would be held in scalar registers for the whole launch).
-struct BatchTeamArgs {
-    const int32_t* rp;
-    const int32_t* col;
-    const void* val;
+// Arguments of the batch kernel for up to 8 restarts other than the row
+// loop's pointers.  They live in device memory and the kernel reads them
+// through one pointer (as kernel arguments they would hold scalar
+// registers for the whole launch).
+struct BatchStepArgs {
     const BatchInstance* inst;
     int R;
     const double* alpha;
@@ -227,8 +229,6 @@ struct BatchTeamArgs {
     double eps;
     int64_t max_iters;
     const double* x0;
-    void* xa;
-    void* xb;
     BatchPlan plan;
     BatchRestartStat* stats;
     uint64_t* clock_start;
@@ -321,8 +321,8 @@ struct ising_ctx {
     bool bshape_set = false;
     std::vector<int64_t> bplan_key;
     doch::BatchPlan bplan;
-    doch::BatchTeamArgs bargs_host{};
-    doch::BatchTeamArgs* bargs_dev = nullptr;   // in bplan_mem
+    doch::BatchStepArgs bargs_host{};
+    doch::BatchStepArgs* bargs_dev = nullptr;   // in bplan_mem
     void* bplan_mem = nullptr;
     size_t bplan_bytes = 0;
     // dense low-precision path (ising_solve_lowp)
@@ -408,8 +408,8 @@ hipError_t launch_dense_symcheck(const DenseView& A, int32_t* bad, hipStream_t s
 // ---- launchers (kernels_batch.hip) ----
 bool batch_restarts_supported(int R);
 hipError_t launch_batch_validate(const BatchView& B, int64_t n, int32_t* bad, hipStream_t s);
-// Up to 8 restarts: the job plan's teams and single jobs on a persistent
-// grid of `wg`-thread workgroups (shape.rj restarts per job); 16 or 32: one
+// Up to 8 restarts: every XCD iterates the units of its share of the plan
+// in lockstep on a persistent grid of `wg`-thread workgroups; 16 or 32: one
 // workgroup per instance with a restart per lane (shape and plan unused).
 bool batch_shape_supported(const BatchShape& sh, int R);
 // Resident workgroups of the shape's kernel on the current device.
@@ -417,7 +417,7 @@ int batch_shape_grid(const BatchShape& sh, int x_dtype, int vt);
 // args_dev: the device copy of the kernel's arguments (R <= 8), written by
 // the caller in stream order before the launch.
 hipError_t launch_batch_solve(const BatchView& B, int R, const BatchShape& shape, const BatchPlan& plan,
-                              const BatchTeamArgs* args_dev, int64_t max_iters, const double* alpha,
+                              const BatchStepArgs* args_dev, int64_t max_iters, const double* alpha,
                               const double* beta, double eps, int x_dtype, const double* x0,
                               void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
                               uint64_t* clock_start, uint64_t* clock_end, double* x_out,

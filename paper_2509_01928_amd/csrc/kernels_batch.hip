@@ -207,37 +207,18 @@ __device__ __forceinline__ void store_row(XT* p, const XT (&in)[R]) {
     *reinterpret_cast<typename RowVec<XT, R>::type*>(p) = w;
 }
 
-// R contiguous iterate entries read from the XCD's L2, past this CU's L1
-// (sc0 buffer loads): the workgroups of a team run on different CUs of one
-// XCD, whose L1 caches are not kept coherent with each other, while the
-// XCD's L2 is shared by them.  `rs` covers the instance's iterate block;
-// out-of-range offsets would read zeros (the couplings are checked to stay
-// in their block when the batch is created).
-typedef int i32x2 __attribute__((ext_vector_type(2)));
-constexpr int kBufferWord3 = 0x00020000;        // raw buffer, gfx9 family
-constexpr int kSc0 = 1;                         // cache policy: L1 miss always
-
-template <typename XT, int R>
-__device__ __forceinline__ void load_row_l2(__amdgpu_buffer_rsrc_t rs, uint32_t off, XT (&out)[R]) {
-    constexpr int kBytes = static_cast<int>(sizeof(XT)) * R;
-    if constexpr (kBytes % 16 == 0) {
-        constexpr int W = kBytes / 16;
-        i32x4 w[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16 * i, 0, kSc0);
-        __builtin_memcpy(out, w, kBytes);
-    } else if constexpr (kBytes == 8) {
-        const i32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kSc0);
-        __builtin_memcpy(out, &w, 8);
-    } else {
-        static_assert(kBytes == 4, "one FP32 entry");
-        const int w = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kSc0);
-        __builtin_memcpy(out, &w, 4);
-    }
+// Values other workgroups wrote in the current iteration (partial sums,
+// unit flags): agent-scope loads, which miss in this CU's L1.  (A
+// workgroup-scope atomic load carries only sc0, which outside
+// threadgroup-split dispatches may still hit a stale L1 line.)
+__device__ __forceinline__ double ld_coh(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-__device__ __forceinline__ double ld_l2(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ int ld_coh(const int32_t* p) {
+    return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned int ld_agent(const unsigned int* p) {
+    return __hip_atomic_load(const_cast<unsigned int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Which XCD this workgroup runs on (the hardware XCC id register).
@@ -247,25 +228,21 @@ __device__ __forceinline__ unsigned int xcd_id() {
     return v & 0xfu;
 }
 
-constexpr unsigned int kTeamSpinLimit = 1u << 24;
+constexpr unsigned int kStepSpinLimit = 1u << 24;
 
 // Rows [lo, hi) of one instance, restarts [r0, r0 + RJ): z = J x, the
 // update of eq:FPE and the sums of eq:Hamilton and Remark S2 (x^4, x^2,
 // x z, (dx)^2 per restart).  One row per thread; a coupling costs one index
 // and one value (aligned 16-byte chunks, the next chunk requested before
 // this one's gathers are waited for) and one contiguous RJ-wide read of the
-// iterate, from L2 for a team (COH: other workgroups wrote it), through
-// this CU's L1 for a single job (this workgroup wrote all of it); row sums
-// in ascending column order.
-template <typename XT, typename VT, int RJ, int WG, bool COH>
-__device__ __forceinline__ void team_sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                           const VT* __restrict__ val, int R, int r0, const BatchInstance& I,
-                                           int lo, int hi, const XT* xo, XT* xw, const bool (&frozen)[RJ],
-                                           double a, double b, double (&acc)[4 * RJ]) {
-    const XT* xblk = xo + static_cast<int64_t>(I.row0) * R;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<XT*>(xblk), static_cast<short>(0), static_cast<int>(static_cast<int64_t>(I.n) * R * sizeof(XT)),
-        kBufferWord3);
+// iterate (written by the XCD's workgroups in the previous iteration; the
+// barrier that ended it invalidated this CU's L1); row sums in ascending
+// column order.
+template <typename XT, typename VT, int RJ, int WG>
+__device__ __forceinline__ void chunk_sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                            const VT* __restrict__ val, int R, int r0, int lo, int hi,
+                                            const XT* xo, XT* xw, const bool (&frozen)[RJ], double a, double b,
+                                            double (&acc)[4 * RJ]) {
     int sn = 0, en = 0;                 // the next row's offsets, requested early
     if (lo + static_cast<int>(threadIdx.x) < hi) {
         sn = rp[lo + threadIdx.x];
@@ -302,10 +279,7 @@ __device__ __forceinline__ void team_sweep(const int32_t* __restrict__ rp, const
             XT g[4][RJ];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (c0 + u >= s && c0 + u < e) {
-                    if constexpr (COH) load_row_l2<XT, RJ>(rs, static_cast<uint32_t>(((cc[u] - I.row0) * R + r0) * sizeof(XT)), g[u]);
-                    else load_row<XT, RJ>(xo + static_cast<int64_t>(cc[u]) * R + r0, g[u]);
-                }
+                if (c0 + u >= s && c0 + u < e) load_row<XT, RJ>(xo + static_cast<int64_t>(cc[u]) * R + r0, g[u]);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (c0 + u >= s && c0 + u < e) {
@@ -314,7 +288,6 @@ __device__ __forceinline__ void team_sweep(const int32_t* __restrict__ rp, const
                 }
         }
         XT xi[RJ], xn[RJ];
-        // a row's own entries were written by this workgroup
         load_row<XT, RJ>(xo + static_cast<int64_t>(i) * R + r0, xi);
 #pragma unroll
         for (int r = 0; r < RJ; ++r) {
@@ -335,22 +308,23 @@ __device__ __forceinline__ void team_sweep(const int32_t* __restrict__ rp, const
     }
 }
 
-// Barrier number `gen` of a team of P workgroups: every wave waits for its
-// stores (iterate rows, partial sums) to reach L2, thread 0 counts the
-// workgroup in and polls the counter.  Returns false if the wait exceeded
-// its bound or another workgroup gave up (the abort word is then set and
-// the caller leaves the kernel).
-__device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int target, unsigned int* abort_word,
-                                             int* s_flag) {
+// Barrier `target` of the workgroups counted on *bar (all on one XCD, or
+// the whole grid at launch): every wave waits for its stores to reach the
+// XCD's L2, thread 0 counts the workgroup in and polls, and afterwards an
+// agent-scope acquire invalidates this CU's L1, so that plain loads see
+// what the XCD's workgroups wrote before the barrier.  Returns false if the
+// wait exceeded its bound or another workgroup gave up (the abort word is
+// then set and the caller leaves the kernel).
+__device__ __forceinline__ bool counter_barrier(unsigned int* bar, unsigned int target, unsigned int* abort_word,
+                                                int* s_flag) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned int spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > kTeamSpinLimit ||
-                __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        while (ld_agent(bar) < target) {
+            if (++spins > kStepSpinLimit || ld_agent(abort_word) != 0u) {
                 __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
@@ -360,169 +334,177 @@ __device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int tar
         *s_flag = ok;
     }
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *s_flag != 0;
 }
 
-// The batch loop for up to 8 restarts on a persistent grid.  A job is a
-// group of RJ of an instance's R restarts (restarts never interact, so the
-// groups run as independent jobs); a large instance's job is split by rows
-// over a team of P workgroups.  A workgroup first takes tickets of its own
-// XCD's team queue, then single jobs from the common queue (largest
-// first).  Team members exchange their iterate rows and partial sums
-// through the XCD's L2 and meet at a barrier once per iteration; every
-// member adds the members' partial sums in member order, so all of them
-// take the same stopping decisions.  The host plans no more team tickets
-// for an XCD than it has resident workgroups, so every team ticket is
-// taken in the launch's first round and a team's members all run from the
-// start; a wait that still exceeds its bound sets the abort word, which the
-// host reports.  An instance's time to solution is the end of its last job.
+// The batch loop for up to 8 restarts: every XCD iterates its share of the
+// units (restart groups of instances) in lockstep.  The host deals the
+// units to the XCDs by work and cuts each unit's rows into chunks; the
+// chunks of an XCD go round-robin to the workgroups running on it (ranks
+// taken at launch from the hardware XCD id), so every instance is spread
+// over all of them and a unit that stops takes the same share of work from
+// each.  Iteration k: every workgroup sweeps its chunks of running units
+// (reading x^(k) from L2, where the XCD's workgroups wrote it) and stores
+// the chunk's partial sums; the workgroup that completes a unit's count of
+// chunks adds the unit's partials in chunk order, takes the stopping
+// decisions of Remark S2 for its restarts (a stopped restart is copied
+// forward from then on) and marks the unit done when all stopped or after
+// max_iters iterations; then the XCD's workgroups meet at a barrier.  An
+// XCD leaves the loop once all its units are done.  No XCD waits for
+// another.  A unit's time to solution is the clock when it was marked done.
 template <typename XT, typename VT, int RJ, int WG>
-__global__ __launch_bounds__(WG) void batch_team_kernel(const BatchTeamArgs* __restrict__ args) {
-    const BatchTeamArgs& A = *args;
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(RJ >= 8 ? 2 : RJ >= 4 ? 3 : 4))) void batch_step_kernel(const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const VT* __restrict__ val, XT* xa, XT* xb,
+                                                        const BatchStepArgs* __restrict__ args) {
     constexpr int K = 4 * RJ;                 // x^4, x^2, x z, (dx)^2 per restart
-    __shared__ double red[K * (WG / kWave)];
-    __shared__ int conv[RJ];
-    __shared__ int s_job, s_member, s_all, s_flag;
+    constexpr int NW = WG / kWave;
+    constexpr int SPLIT = WG / K;             // threads per quantity in a unit's reduction
+    __shared__ double red[K * NW];
+    __shared__ double tot[K * SPLIT];
+    __shared__ int s_rank, s_w, s_flag, s_last, s_done;
+    const BatchStepArgs& A = *args;
     const BatchPlan& pl = A.plan;
-    const VT* val = static_cast<const VT*>(A.val);
     const int R = A.R;
-    unsigned int* abort_word = pl.counters + 32 * 9;
-    const unsigned int xcd = xcd_id() % static_cast<unsigned int>(pl.n_xcd);
-    bool team_open = true;                    // thread 0: this XCD's team queue may hold tickets
-    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned long long*>(A.clock_start),
-                                    static_cast<unsigned long long>(device_clock()));
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int job = -1, member = 0;
-            if (team_open) {
-                const int t = static_cast<int>(atomicAdd(pl.counters + 32 * xcd, 1u)) + pl.off[xcd];
-                if (t < pl.off[xcd + 1]) {
-                    job = pl.tickets[t].job;
-                    member = pl.tickets[t].member;
-                } else {
-                    team_open = false;
-                }
-            }
-            if (job < 0) {
-                const int t = static_cast<int>(atomicAdd(pl.counters + 32 * 8, 1u));
-                if (t < pl.n_singles) job = pl.singles[t];
-            }
-            s_job = job;
-            s_member = member;
-        }
-        if (threadIdx.x < RJ) conv[threadIdx.x] = 0;
-        __syncthreads();
-        const int jid = s_job;
-        const int member = s_member;
-        if (jid < 0) break;
-        const BatchJob J = pl.jobs[jid];
-        const int k = J.inst;
-        const int r0 = J.r0;
-        const int P = J.P;
-        const BatchInstance I = A.inst[k];
-        const double a = A.alpha[k], b = A.beta[k];
-        const int lo = I.row0 + static_cast<int>(static_cast<int64_t>(I.n) * member / P);
-        const int hi = I.row0 + static_cast<int>(static_cast<int64_t>(I.n) * (member + 1) / P);
-        unsigned int* bar = pl.bar + 32 * static_cast<size_t>(J.team >= 0 ? J.team : 0);
-        XT* xa = static_cast<XT*>(A.xa);
-        XT* xb = static_cast<XT*>(A.xb);
-        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(hi - lo) * RJ; t += WG) {
-            const int64_t e = (lo + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
+    unsigned int* ctr = pl.counters;
+    unsigned int* abort_word = ctr + 32 * 25;
+    const unsigned int x = xcd_id() % static_cast<unsigned int>(pl.n_xcd);
+    if (threadIdx.x == 0) {
+        atomicMin(reinterpret_cast<unsigned long long*>(A.clock_start),
+                  static_cast<unsigned long long>(device_clock()));
+        s_rank = static_cast<int>(__hip_atomic_fetch_add(ctr + 32 * x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    // every workgroup registered once: the ranks are final after this
+    if (!counter_barrier(ctr + 32 * 24, gridDim.x, abort_word, &s_flag)) return;
+    if (threadIdx.x == 0) {
+        s_w = static_cast<int>(ld_agent(ctr + 32 * x));
+        // an XCD without workgroups would leave its units unrun
+        if (blockIdx.x == 0)
+            for (int q = 0; q < pl.n_xcd; ++q)
+                if (ld_agent(ctr + 32 * q) == 0u) __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int rank = s_rank, W = s_w;
+    const int c_lo = pl.off[x], c_hi = pl.off[x + 1];
+    const int my_units = pl.units_on[x];
+    unsigned int* bar = ctr + 32 * (8 + x);
+    unsigned int* ndone = ctr + 32 * (16 + x);
+    // x^(0) into buffer a for this workgroup's chunks
+    for (int c = c_lo + rank; c < c_hi; c += W) {
+        const BatchChunk ch = pl.chunks[c];
+        const int r0 = pl.units[ch.unit].r0;
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(ch.hi - ch.lo) * RJ; t += WG) {
+            const int64_t e = (ch.lo + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
             xa[e] = static_cast<XT>(A.x0[e]);
         }
-        if (P > 1) {
-            if (!team_barrier(bar, static_cast<unsigned int>(P), abort_word, &s_flag)) return;
-        } else {
-            __syncthreads();
-        }
-        const XT* xo = xa;
-        XT* xw = xb;
-        int64_t it = 0;
-        for (; it < A.max_iters; ++it) {
+    }
+    unsigned int gen = 1;
+    if (!counter_barrier(bar, W * gen, abort_word, &s_flag)) return;
+    for (int64_t it = 0; it < A.max_iters; ++it) {
+        const XT* xo = (it & 1) ? xb : xa;
+        XT* xw = (it & 1) ? xa : xb;
+        for (int c = c_lo + rank; c < c_hi; c += W) {
+            const BatchChunk ch = pl.chunks[c];
+            const int u = ch.unit;
+            // a unit's flags change only after all its chunks of the
+            // iteration are done, and were last written before the barrier
+            // that began it (which invalidated L1): plain loads see them
+            if (pl.done[u] != 0) continue;
+            const BatchUnit U = pl.units[u];
+            const int k = U.inst;
+            const double a = A.alpha[k], b = A.beta[k];
             bool frozen[RJ];
 #pragma unroll
-            for (int r = 0; r < RJ; ++r) frozen[r] = conv[r] != 0;
+            for (int r = 0; r < RJ; ++r) frozen[r] = pl.conv[static_cast<int64_t>(u) * RJ + r] != 0;
             double acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = 0.0;
-            if (P > 1) team_sweep<XT, VT, RJ, WG, true>(A.rp, A.col, val, R, r0, I, lo, hi, xo, xw, frozen, a, b, acc);
-            else team_sweep<XT, VT, RJ, WG, false>(A.rp, A.col, val, R, r0, I, lo, hi, xo, xw, frozen, a, b, acc);
-            block_sum<K, WG>(acc, red);       // this workgroup's totals in thread 0
-            if (P > 1) {
-                double* pp = pl.partials + ((static_cast<size_t>(J.team) * 2 + (it & 1)) * pl.pmax) * K;
-                if (threadIdx.x == 0) {
+            chunk_sweep<XT, VT, RJ, WG>(rp, col, val, R, U.r0, ch.lo, ch.hi, xo, xw, frozen, a, b, acc);
+            block_sum<K, WG>(acc, red);       // the chunk's totals in thread 0
+            if (threadIdx.x == 0) {
+                double* p = pl.partials + static_cast<size_t>(ch.slot) * K;
 #pragma unroll
-                    for (int q = 0; q < K; ++q) pp[static_cast<size_t>(member) * K + q] = acc[q];
+                for (int q = 0; q < K; ++q) p[q] = acc[q];
+                s_last = arrive_last(pl.tickets + 32 * static_cast<size_t>(u), static_cast<unsigned int>(U.nchunks));
+            }
+            __syncthreads();
+            if (!s_last) continue;
+            // the unit's last chunk: its partials in chunk order (thread
+            // (q, j) adds chunks j, j + SPLIT, ... of quantity q; then the
+            // SPLIT sums in order)
+            {
+                const int q = threadIdx.x % K, j0 = threadIdx.x / K;
+                double v = 0.0;
+                if (j0 < SPLIT)
+                    for (int j = j0; j < U.nchunks; j += SPLIT)
+                        v = dadd(v, ld_coh(pl.partials + (static_cast<size_t>(U.first_slot) + j) * K + q));
+                if (j0 < SPLIT) tot[j0 * K + q] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < RJ) {
+                const int r = threadIdx.x;
+                double S[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    double v = 0.0;
+                    for (int j = 0; j < SPLIT; ++j) v = dadd(v, tot[j * K + 4 * r + m]);
+                    S[m] = v;
                 }
-                if (!team_barrier(bar, static_cast<unsigned int>(P) * static_cast<unsigned int>(it + 2), abort_word,
-                                  &s_flag))
-                    return;
-                if (threadIdx.x == 0) {
-#pragma unroll
-                    for (int q = 0; q < K; ++q) acc[q] = 0.0;
-                    for (int m = 0; m < P; ++m) {
-#pragma unroll
-                        for (int q = 0; q < K; ++q) acc[q] = dadd(acc[q], ld_l2(pp + static_cast<size_t>(m) * K + q));
+                int32_t* cv = pl.conv + static_cast<int64_t>(u) * RJ + r;
+                if (!frozen[r]) {
+                    const double H = dsub(dsub(dmul(ddiv(b, 4.0), S[0]), dmul(ddiv(a, 2.0), S[1])), dmul(0.5, S[2]));
+                    const double rr = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
+                    BatchRestartStat& st = A.stats[static_cast<int64_t>(k) * R + U.r0 + r];
+                    st.iters_done = it + 1;
+                    st.H_last = H;
+                    st.r_last = rr;
+                    if (!isfinite(H) || !isfinite(rr)) {
+                        st.nonfinite = 1;
+                        *cv = 1;
+                    } else if (A.eps > 0.0 && rr < A.eps) {
+                        st.converged = 1;
+                        *cv = 1;
                     }
                 }
             }
+            __syncthreads();
             if (threadIdx.x == 0) {
                 int all = 1;
-                for (int r = 0; r < RJ; ++r) {
-                    if (!conv[r]) {
-                        const double* S = acc + 4 * r;
-                        const double H = dsub(dsub(dmul(ddiv(b, 4.0), S[0]), dmul(ddiv(a, 2.0), S[1])),
-                                              dmul(0.5, S[2]));
-                        const double rr = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
-                        int stop = 0, nonfinite = 0, converged = 0;
-                        if (!isfinite(H) || !isfinite(rr)) {
-                            nonfinite = 1;
-                            stop = 1;
-                        } else if (A.eps > 0.0 && rr < A.eps) {
-                            converged = 1;
-                            stop = 1;
-                        }
-                        if (member == 0) {
-                            BatchRestartStat& st = A.stats[static_cast<int64_t>(k) * R + r0 + r];
-                            st.iters_done = it + 1;
-                            st.H_last = H;
-                            st.r_last = rr;
-                            st.nonfinite = nonfinite;
-                            st.converged = converged;
-                        }
-                        conv[r] = stop;
-                    }
-                    all &= conv[r];
+                for (int r = 0; r < RJ; ++r) all &= ld_coh(pl.conv + static_cast<int64_t>(u) * RJ + r) != 0;
+                if (all || it + 1 == A.max_iters) {
+                    pl.done[u] = static_cast<int32_t>(it + 1);
+                    atomicMax(reinterpret_cast<unsigned long long*>(A.clock_end + k),
+                              static_cast<unsigned long long>(device_clock()));
+                    __hip_atomic_fetch_add(ndone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                s_all = all;
-            }
-            const XT* t = xo;
-            xo = xw;
-            xw = const_cast<XT*>(t);
-            __syncthreads();
-            if (s_all) {
-                ++it;
-                break;
+                reset_ticket(pl.tickets + 32 * static_cast<size_t>(u));
             }
         }
-        // outputs of this member's rows from the buffer that holds x^(it)
-        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(hi - lo) * RJ; t += WG) {
-            const int64_t e = (lo + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
-            const double v = static_cast<double>(xo[e]);
+        ++gen;
+        if (!counter_barrier(bar, W * gen, abort_word, &s_flag)) return;
+        if (threadIdx.x == 0) s_done = static_cast<int>(ld_agent(ndone)) >= my_units;
+        __syncthreads();
+        if (s_done) break;
+    }
+    // outputs of this workgroup's chunks, from the buffer of each unit's last iterate
+    for (int c = c_lo + rank; c < c_hi; c += W) {
+        const BatchChunk ch = pl.chunks[c];
+        const int r0 = pl.units[ch.unit].r0;
+        const XT* xf = (ld_coh(pl.done + ch.unit) & 1) ? xb : xa;
+        for (int64_t t = threadIdx.x; t < static_cast<int64_t>(ch.hi - ch.lo) * RJ; t += WG) {
+            const int64_t e = (ch.lo + t / RJ) * static_cast<int64_t>(R) + r0 + t % RJ;
+            const double v = static_cast<double>(xf[e]);
             if (A.x_out) A.x_out[e] = v;
             if (A.s_out) A.s_out[e] = v >= 0.0 ? 1 : -1;
         }
-        if (threadIdx.x == 0)
-            atomicMax(reinterpret_cast<unsigned long long*>(A.clock_end + k),
-                      static_cast<unsigned long long>(device_clock()));
-        __syncthreads();
     }
 }
 
 template <int R>
 __global__ void batch_init_kernel(BatchRestartStat* stats, int count, unsigned int* queue,
                                   uint64_t* clock_start, uint64_t* clock_end, unsigned int* counters,
-                                  unsigned int* bar, int n_bar_words) {
+                                  unsigned int* tickets, int32_t* done, int32_t* conv, int n_units, int rj) {
     const int64_t total = static_cast<int64_t>(count) * R;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -534,10 +516,12 @@ __global__ void batch_init_kernel(BatchRestartStat* stats, int count, unsigned i
         stats[t].H_last = 0.0;
         stats[t].r_last = 0.0;
     }
-    if (counters)
+    if (counters) {
         for (int64_t t = t0; t < kBatchCounterWords; t += stride) counters[t] = 0u;
-    if (bar)
-        for (int64_t t = t0; t < n_bar_words; t += stride) bar[t] = 0u;
+        for (int64_t t = t0; t < static_cast<int64_t>(n_units) * 32; t += stride) tickets[t] = 0u;
+        for (int64_t t = t0; t < n_units; t += stride) done[t] = 0;
+        for (int64_t t = t0; t < static_cast<int64_t>(n_units) * rj; t += stride) conv[t] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *queue = 0u;
         *clock_start = ~0ull;
@@ -748,8 +732,8 @@ bool batch_restarts_supported(int R) {
     return R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32;
 }
 
-// The (restarts per job, threads) pairs the team kernel is built for.
-static bool team_shape_built(int rj, int wg) {
+// The (restarts per unit, threads) pairs the lockstep kernel is built for.
+static bool step_shape_built(int rj, int wg) {
     switch (rj) {
         case 8:
         case 4: return wg == 256 || wg == 512;
@@ -761,27 +745,27 @@ static bool team_shape_built(int rj, int wg) {
 
 bool batch_shape_supported(const BatchShape& sh, int R) {
     if (R > 8) return true;                   // restart-per-lane kernel, no shape
-    if (sh.rows_per_member < 0) return false;
+    if (sh.chunk_rows < 1) return false;
     if (sh.rj != 1 && sh.rj != 2 && sh.rj != 4 && sh.rj != 8) return false;
-    return team_shape_built(std::min(sh.rj, R), sh.wg);
+    return step_shape_built(std::min(sh.rj, R), sh.wg);
 }
 
-// Calls f(kernel pointer, RJ, WG tags) for the team kernel of the shape.
+// Calls f(kernel pointer, WG tag) for the lockstep kernel of the shape.
 template <typename XT, typename VT, typename F>
-static hipError_t with_team_kernel(int RJ, int WG, F&& f) {
+static hipError_t with_step_kernel(int RJ, int WG, F&& f) {
     using std::integral_constant;
-#define DOCH_TEAM(RJV, WGV)                                                                          \
+#define DOCH_STEP(RJV, WGV)                                                                          \
     if (RJ == RJV && WG == WGV)                                                                      \
-        return f(batch_team_kernel<XT, VT, RJV, WGV>, integral_constant<int, WGV>());
-    DOCH_TEAM(8, 256)
-    DOCH_TEAM(8, 512)
-    DOCH_TEAM(4, 256)
-    DOCH_TEAM(4, 512)
-    DOCH_TEAM(2, 512)
-    DOCH_TEAM(2, 1024)
-    DOCH_TEAM(1, 512)
-    DOCH_TEAM(1, 1024)
-#undef DOCH_TEAM
+        return f(batch_step_kernel<XT, VT, RJV, WGV>, integral_constant<int, WGV>());
+    DOCH_STEP(8, 256)
+    DOCH_STEP(8, 512)
+    DOCH_STEP(4, 256)
+    DOCH_STEP(4, 512)
+    DOCH_STEP(2, 512)
+    DOCH_STEP(2, 1024)
+    DOCH_STEP(1, 512)
+    DOCH_STEP(1, 1024)
+#undef DOCH_STEP
     return hipErrorInvalidValue;
 }
 
@@ -796,7 +780,7 @@ int batch_shape_grid(const BatchShape& sh, int x_dtype, int vt) {
     (void)with_types(x_dtype, vt, [&](auto xtag, auto vtag) {
         using XT = decltype(xtag);
         using VT = decltype(vtag);
-        return with_team_kernel<XT, VT>(sh.rj, sh.wg, [&](auto kern, auto wgtag) {
+        return with_step_kernel<XT, VT>(sh.rj, sh.wg, [&](auto kern, auto wgtag) {
             grid = resident_grid(kern, decltype(wgtag)::value);
             return hipSuccess;
         });
@@ -805,27 +789,28 @@ int batch_shape_grid(const BatchShape& sh, int x_dtype, int vt) {
 }
 
 hipError_t launch_batch_solve(const BatchView& B, int R, const BatchShape& shape, const BatchPlan& plan,
-                              const BatchTeamArgs* args_dev, int64_t max_iters, const double* alpha,
+                              const BatchStepArgs* args_dev, int64_t max_iters, const double* alpha,
                               const double* beta, double eps, int x_dtype, const double* x0,
                               void* xa, void* xb, unsigned int* queue, BatchRestartStat* stats,
                               uint64_t* clock_start, uint64_t* clock_end, double* x_out,
                               int8_t* s_out, hipStream_t s) {
     if (!batch_restarts_supported(R)) return hipErrorInvalidValue;
     const int ig = static_cast<int>(std::min<int64_t>(1024, (static_cast<int64_t>(B.count) * R + 255) / 256));
-    const bool team = R <= 8;
+    const bool lockstep = R <= 8;
     DOCH_BATCH_R(R, {
         hipLaunchKernelGGL(batch_init_kernel<RR>, dim3(ig), dim3(256), 0, s, stats, B.count, queue,
-                           clock_start, clock_end, team ? plan.counters : nullptr, team ? plan.bar : nullptr,
-                           team ? 32 * plan.n_teams : 0);
+                           clock_start, clock_end, lockstep ? plan.counters : nullptr, plan.tickets, plan.done,
+                           plan.conv, lockstep ? plan.n_units : 0, plan.rj);
     });
-    if (team) {
+    if (lockstep) {
         if (!batch_shape_supported(shape, R)) return hipErrorInvalidValue;
         hipError_t e = with_types(x_dtype, B.vt, [&](auto xtag, auto vtag) {
             using XT = decltype(xtag);
             using VT = decltype(vtag);
-            return with_team_kernel<XT, VT>(std::min(shape.rj, R), shape.wg, [&](auto kern, auto wgtag) {
+            return with_step_kernel<XT, VT>(std::min(shape.rj, R), shape.wg, [&](auto kern, auto wgtag) {
                 constexpr int WG = decltype(wgtag)::value;
-                hipLaunchKernelGGL(kern, dim3(resident_grid(kern, WG)), dim3(WG), 0, s, args_dev);
+                hipLaunchKernelGGL(kern, dim3(resident_grid(kern, WG)), dim3(WG), 0, s, B.rp, B.col,
+                                   static_cast<const VT*>(B.val), static_cast<XT*>(xa), static_cast<XT*>(xb), args_dev);
                 return hipSuccess;
             });
         });

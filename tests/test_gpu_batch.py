@@ -221,7 +221,7 @@ def test_batch_rejects_cross_block_coupling():
     assert e.value.status == L.ISING_E_INVALID_ARG
 
 
-# ------------------------------------------------------ teams of workgroups
+# --------------------------------------------------- lockstep launch shapes
 @pytest.fixture(scope="module")
 def team_case():
     """Instances of 20000, 9000, 2600 and 700 rows (mean degrees 20, 12, 8,
@@ -244,12 +244,13 @@ def team_case():
     return dict(inst=inst, alpha=alpha, beta=beta, R=R, X0=X0, fixed=fixed, stop=stop)
 
 
-@pytest.mark.parametrize("rj,wg,rpm", [(8, 256, 1024), (8, 512, 4096), (4, 256, 500), (2, 1024, 2048),
-                                       (1, 512, 3000), (8, 256, 0)])
+@pytest.mark.parametrize("rj,wg,rpm", [(8, 256, 512), (8, 512, 4096), (4, 256, 500), (2, 1024, 2048),
+                                       (1, 512, 3000), (8, 256, 100)])
 def test_batch_team_shapes_parity(team_case, rj, wg, rpm):
-    """Every launch shape: jobs of rj restarts; instances split over teams of
-    ceil(n / rpm) workgroups (the 20000-row instance over 16 at rpm 1024 and
-    500) that exchange iterate rows through L2 each iteration.  Iterates,
+    """Every launch shape: units of rj restarts, rows in chunks of rpm (the
+    20000-row instance in 200 chunks at rpm 100, one chunk of 4096 rows
+    covering the 700-row instance), spread over the workgroups of an XCD
+    that exchange iterate rows through L2 each iteration.  Iterates,
     spins, H and r after 60 iterations follow the oracle per (instance,
     restart); under eps = 1e-3 every restart stops at the oracle's
     iteration; exact energies."""
@@ -289,7 +290,7 @@ def test_batch_set_shape_rejects_unbuilt():
     inst = small_batch(count=2, seed=5)
     G = GpuBatch(inst, 8)
     try:
-        for rj, wg, rpm in ((8, 1024, 0), (3, 256, 0), (4, 128, 0), (8, 256, -1)):
+        for rj, wg, rpm in ((8, 1024, 512), (3, 256, 512), (4, 128, 512), (8, 256, 0)):
             with pytest.raises(L.IsingError) as e:
                 L.ising_set_batch_shape(G.ctx, rj, wg, rpm)
             assert e.value.status == L.ISING_E_INVALID_ARG
@@ -316,7 +317,7 @@ def test_batch_autotune_and_cache(tmp_path):
         xd = torch.from_numpy(X0).to("cuda:0")
         shape, ms, cached = L.ising_autotune_batch(G.ctx, xd, R, 5000, alpha, beta, 1e-3, L.ISING_F64, cache)
         assert not cached and ms > 0
-        assert shape[0] in (1, 2, 4) and shape[1] in (256, 512, 1024) and shape[2] >= 0
+        assert shape[0] in (1, 2, 4) and shape[1] in (256, 512, 1024) and shape[2] in (256, 512, 1024, 2048)
         X, S, st, _ = G.solve(X0, alpha, beta, 5000, 1e-3)
     finally:
         G.close()
@@ -324,7 +325,7 @@ def test_batch_autotune_and_cache(tmp_path):
         data = json.load(f)
     assert len(data) == 1
     (entry,) = data.values()
-    assert (entry["rj"], entry["wg"], entry["rows_per_member"]) == tuple(shape)
+    assert (entry["rj"], entry["wg"], entry["chunk_rows"]) == tuple(shape)
     G2 = GpuBatch(inst, R)
     try:
         xd = torch.from_numpy(X0).to("cuda:0")
