@@ -213,11 +213,15 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R,
                          ising_stats* stats_host, void* stream);
 
 /* ADOCH (params->algo = 1, Alg. 2 with the window of eq:BBscheme) runs on
- * single CSR contexts with R = 1 and FP64 iterates (ISING_E_UNSUPPORTED
- * otherwise); params->q >= 1 is the look-back window.  It still costs one
- * matvec per iteration: J y is formed from J x^(k) and J x^(k-1).
+ * single CSR and dense contexts (stored or generated couplings) with R in
+ * {1, 2, 4, 8} restarts together and FP64 iterates (ISING_E_UNSUPPORTED
+ * otherwise); params->q >= 1 is the look-back window.  Every restart keeps
+ * its own window, decisions and stopping (Remark S2 with params->eps), and
+ * ising_get_log(restart) reads its H and r.  It still costs one matvec per
+ * iteration: J y is formed from J x^(k) and J x^(k-1).
  * ising_get_accept_log copies, for the last ADOCH solve, whether iteration
- * first + i took the extrapolated point (1) or x^(k) (0).  Synchronous. */
+ * first + i of restart r took the extrapolated point (1) or x^(k) (0), at
+ * accept_host[i * R + r] (count * R entries).  Synchronous. */
 ising_status ising_get_accept_log(ising_ctx* ctx, int64_t first, int64_t count,
                                   int8_t* accept_host, void* stream);
 

@@ -358,14 +358,15 @@ def ising_solve_lowp(ctx, x0, R, iters, params, jx_dtype, x_out=None, s_out=None
     return list(stats) if stats is not None else []
 
 
-def ising_get_accept_log(ctx, first, count, stream=None):
-    """ADOCH decisions of the last solve (numpy int8: 1 = extrapolated point taken)."""
+def ising_get_accept_log(ctx, first, count, R=1, stream=None):
+    """ADOCH decisions of the last solve (numpy int8: 1 = extrapolated point
+    taken); shape (count,) for one restart, (count, R) for R restarts."""
     import numpy as np
-    out = np.empty(int(count), dtype=np.int8)
+    out = np.empty(int(count) * int(R), dtype=np.int8)
     _check(lib.ising_get_accept_log(ctx, int(first), int(count), out.ctypes.data,
                                     stream if stream is not None else current_stream()),
            "ising_get_accept_log")
-    return out
+    return out if R == 1 else out.reshape(int(count), int(R))
 
 
 def ising_create_procedural(n, kind=1, seed=100.0, stream=None):

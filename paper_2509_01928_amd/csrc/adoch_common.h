@@ -1,0 +1,88 @@
+// adoch_common.h -- the closing step of an ADOCH (Alg. 2) matvec launch,
+// shared by the CSR and dense kernels.
+//
+// Iteration k of R interleaved restarts: every workgroup has added, per
+// restart, x^4, x^2, x.z, y^4, y^2, y.(J y) and h.x over its rows, with
+// y = x^(k) + c_k (x^(k) - x^(k-1)) and J y = (1 + c_k) z_k - c_k z_{k-1}
+// (one matvec per iteration, by linearity).  The last workgroup adds the
+// workgroups' sums in workgroup order, closes the field spin's row, forms
+// H(x^(k)) and H(y^(k)) (eq:Hamilton), keeps the window of the last q + 1
+// values of H(x) and decides per restart whether y is taken (H(y) at most
+// the window's maximum, eq:BBscheme).
+#pragma once
+
+#include "device_common.h"
+#include "ising_internal.h"
+
+namespace doch {
+
+// Store this workgroup's 7 R sums and, in the last workgroup to arrive,
+// close the iteration.  acc: thread 0's workgroup totals (restart r at 7 r).
+template <int R, int NT, bool FIELD>
+__device__ __forceinline__ void adoch_mv_close(double (&acc)[7 * R], double* red, int* last_flag, int64_t n,
+                                               const double* __restrict__ x, const double* __restrict__ xp,
+                                               const double* __restrict__ zp, double* __restrict__ z,
+                                               const AdochArgs& a) {
+    constexpr int K = 7 * R;
+    if (threadIdx.x == 0) {
+        double* p = a.partials + static_cast<size_t>(blockIdx.x) * K;
+#pragma unroll
+        for (int q = 0; q < K; ++q) store_agent(p + q, acc[q]);
+        *last_flag = arrive_last_grid(a.ticket, gridDim.x) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*last_flag) return;
+    double u[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) u[q] = 0.0;
+    for (unsigned g = threadIdx.x; g < gridDim.x; g += NT)
+#pragma unroll
+        for (int q = 0; q < K; ++q) u[q] = dadd(u[q], load_agent(a.partials + static_cast<size_t>(g) * K + q));
+    block_sum<K, NT>(u, red);
+    if (threadIdx.x != 0) return;
+    const double c = a.c;
+    const double b4 = ddiv(a.beta, 4.0), a2 = ddiv(a.alpha, 2.0);
+    const int W = a.q + 1;
+    for (int r = 0; r < R; ++r) {
+        RestartState& st = a.state[r];
+        if (st.done) continue;
+        double* ur = u + 7 * r;
+        if (FIELD) {
+            // the extra spin's row: z_n = sum_i h_i x_i, and its share of every sum
+            const int64_t tn = n * R + r;
+            const double tx = x[tn];
+            const double zn = ur[6];
+            z[tn] = zn;
+            const double yn = dadd(tx, dmul(c, dsub(tx, xp[tn])));
+            const double jyn = dsub(dmul(dadd(1.0, c), zn), dmul(c, zp[tn]));
+            const double t2 = dmul(tx, tx), y2 = dmul(yn, yn);
+            ur[0] = dadd(ur[0], dmul(t2, t2));
+            ur[1] = dadd(ur[1], t2);
+            ur[2] = dadd(ur[2], dmul(tx, zn));
+            ur[3] = dadd(ur[3], dmul(y2, y2));
+            ur[4] = dadd(ur[4], y2);
+            ur[5] = dadd(ur[5], dmul(yn, jyn));
+        }
+        const double Hx = dsub(dsub(dmul(b4, ur[0]), dmul(a2, ur[1])), dmul(0.5, ur[2]));
+        const double Hy = dsub(dsub(dmul(b4, ur[3]), dmul(a2, ur[4])), dmul(0.5, ur[5]));
+        // window of H(x^(j)), max(0, k - q) <= j <= k
+        double* ring = a.ring + static_cast<size_t>(r) * W;
+        ring[a.k % W] = Hx;
+        const int64_t j0 = a.k - a.q > 0 ? a.k - a.q : 0;
+        double hmax = Hx;
+        for (int64_t j = j0; j <= a.k; ++j) hmax = fmax(hmax, ring[j % W]);
+        const int accept = Hy <= hmax ? 1 : 0;
+        a.accept[r] = accept;
+        a.log[(static_cast<size_t>(a.k) * R + r) * 2] = Hx;
+        a.accept_log[static_cast<size_t>(a.k) * R + r] = static_cast<int8_t>(accept);
+        st.H_last = Hx;
+        if (!isfinite(Hx)) {
+            st.nonfinite = 1;
+            st.done = 1;
+            st.iters_done = a.k + 1;
+        }
+    }
+    reset_ticket(a.ticket);
+}
+
+}  // namespace doch

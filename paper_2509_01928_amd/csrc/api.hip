@@ -371,11 +371,12 @@ static ising_status solve_resident(ising_ctx* ctx, const double* x0_dev, int64_t
     return read_stats(ctx, 1, stats_host, s);
 }
 
-// ADOCH (Alg. 2) on a CSR context, one restart, FP64 iterates.
-static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t iters, const ising_params& p,
+// ADOCH (Alg. 2) on a single CSR or dense (stored or generated) context,
+// R in {1, 2, 4, 8} interleaved restarts, FP64 iterates.
+static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int64_t iters, const ising_params& p,
                          double* x_out_dev, int8_t* s_out_dev, ising_stats* stats_host, hipStream_t s) {
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
-    const size_t bytes = static_cast<size_t>(ctx->np) * sizeof(double);
+    const size_t bytes = static_cast<size_t>(ctx->np) * R * sizeof(double);
     if (!ctx->ad_x[0] || ctx->ad_bytes < bytes) {
         for (auto& b : ctx->ad_x) dev_free(b);
         for (auto& b : ctx->ad_z) dev_free(b);
@@ -384,25 +385,28 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t it
         for (auto& b : ctx->ad_z) HIP_OK(dev_alloc(&b, bytes), "hipMalloc(z)");
         ctx->ad_bytes = bytes;
     }
-    if (!ctx->ad_ring || ctx->ad_ring_cap < p.q + 1) {
+    if (!ctx->ad_ring || ctx->ad_ring_cap < R * (p.q + 1)) {
         dev_free(ctx->ad_ring);
-        HIP_OK(dev_alloc(&ctx->ad_ring, (p.q + 1) * sizeof(double)), "hipMalloc(ring)");
-        ctx->ad_ring_cap = p.q + 1;
+        HIP_OK(dev_alloc(&ctx->ad_ring, static_cast<size_t>(R) * (p.q + 1) * sizeof(double)), "hipMalloc(ring)");
+        ctx->ad_ring_cap = R * (p.q + 1);
     }
-    if (!ctx->ad_accept) HIP_OK(dev_alloc(&ctx->ad_accept, 256), "hipMalloc(accept)");
-    HIP_OK(ensure(&ctx->ad_acclog, &ctx->ad_acclog_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1))),
+    // decisions [R] and the all-done flag (word 64)
+    if (!ctx->ad_accept) HIP_OK(dev_alloc(&ctx->ad_accept, 512), "hipMalloc(accept)");
+    HIP_OK(ensure(&ctx->ad_acclog, &ctx->ad_acclog_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R),
            "hipMalloc(accept log)");
-    const int grid = doch::adoch_grid(ctx->np);
-    HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes, static_cast<size_t>(grid) * 7 * sizeof(double)),
-           "hipMalloc(partials)");
+    const int mv_grid = ctx->dense ? doch::adoch_dense_grid(dense_view(ctx)) : doch::adoch_grid(ctx->n);
+    const int up_grid = doch::adoch_grid(ctx->np * R);
+    const size_t pd = std::max(static_cast<size_t>(mv_grid) * 7 * R, static_cast<size_t>(up_grid) * 2 * R);
+    HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes, pd * sizeof(double)), "hipMalloc(partials)");
     if (!ctx->ticket) {
         HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
         HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
         ctx->state_cap = kMaxR;
     }
-    HIP_OK(ensure(&ctx->log, &ctx->log_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * 2 * sizeof(double)),
-           "hipMalloc(log)");
-    HIP_OK(doch::launch_init_state(ctx->state, 1, ctx->ticket, nullptr, s), "init");
+    HIP_OK(ensure(&ctx->log, &ctx->log_bytes,
+                  static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)), "hipMalloc(log)");
+    HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, nullptr, s), "init");
+    HIP_OK(hipMemsetAsync(ctx->ad_accept, 0, 512, s), "clear flags");
     HIP_OK(hipMemcpyAsync(ctx->ad_x[0], x0_dev, bytes, hipMemcpyDeviceToDevice, s), "load x0");
     // z^(-1) enters with weight c_0 = 0; it must be finite
     HIP_OK(hipMemsetAsync(ctx->ad_z[1], 0, bytes, s), "clear z");
@@ -411,14 +415,17 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t it
     a.beta = p.beta;
     a.eps = p.eps;
     a.q = p.q;
+    a.R = R;
     a.partials = ctx->partials;
     a.ticket = ctx->ticket;
     a.log = ctx->log;
     a.accept = ctx->ad_accept;
+    a.all_done = ctx->ad_accept + 64;
     a.accept_log = ctx->ad_acclog;
     a.ring = ctx->ad_ring;
     a.state = ctx->state;
     const CsrView cv = csr_view(ctx);
+    const DenseView dv = dense_view(ctx);
     double t = 1.0;                                   // momentum sequence of Alg. 2: t_0 = 1
     for (int64_t k = 0; k < iters; ++k) {
         const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;   // t_{k+1} of Alg. 2
@@ -429,28 +436,20 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int64_t it
         double* xn = ctx->ad_x[(k + 1) % 3];
         double* z = ctx->ad_z[k % 2];
         const double* zp = ctx->ad_z[(k + 1) % 2];
-        HIP_OK(doch::launch_adoch_mv(cv, x, xp, zp, z, a, s), "ADOCH matvec");
+        if (ctx->dense)
+            HIP_OK(doch::launch_adoch_dense_mv(dv, x, xp, zp, z, a, s), "ADOCH matvec");
+        else
+            HIP_OK(doch::launch_adoch_mv(cv, x, xp, zp, z, a, s), "ADOCH matvec");
         HIP_OK(doch::launch_adoch_update(ctx->np, x, xp, z, zp, xn, a, s), "ADOCH update");
         t = t_next;
     }
-    ctx->last_R = 1;
+    ctx->last_R = R;
     ctx->last_iters = iters;
     ctx->last_adoch = true;
     if (x_out_dev || s_out_dev)
-        HIP_OK(doch::launch_adoch_finish(ctx->ad_x[0], ctx->ad_x[1], ctx->ad_x[2], ctx->state, ctx->n, ctx->np,
+        HIP_OK(doch::launch_adoch_finish(ctx->ad_x[0], ctx->ad_x[1], ctx->ad_x[2], ctx->state, ctx->n, ctx->np, R,
                                          ctx->has_field, x_out_dev, s_out_dev, s), "finish");
-    if (stats_host) {
-        RestartState hs;
-        HIP_OK(hipMemcpyAsync(&hs, ctx->state, sizeof(hs), hipMemcpyDeviceToHost, s), "copy state");
-        HIP_OK(hipStreamSynchronize(s), "sync");
-        stats_host[0].iters_done = hs.iters_done;
-        stats_host[0].converged = hs.converged;
-        stats_host[0].nonfinite = hs.nonfinite;
-        stats_host[0].H_last = hs.H_last;
-        stats_host[0].r_last = hs.r_last;
-        if (hs.nonfinite) return fail(ISING_E_NONFINITE, "H or r became non-finite");
-    }
-    return ISING_OK;
+    return read_stats(ctx, R, stats_host, s);
 }
 
 extern "C" {
@@ -465,7 +464,9 @@ ising_status ising_get_accept_log(ising_ctx* ctx, int64_t first, int64_t count, 
     if (count == 0) return ISING_OK;
     HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_OK(hipMemcpyAsync(accept_host, ctx->ad_acclog + first, count, hipMemcpyDeviceToHost, s), "copy");
+    const int R = ctx->last_R;
+    HIP_OK(hipMemcpyAsync(accept_host, ctx->ad_acclog + first * R, static_cast<size_t>(count) * R,
+                          hipMemcpyDeviceToHost, s), "copy");
     HIP_OK(hipStreamSynchronize(s), "sync");
     return ISING_OK;
 }
@@ -786,11 +787,12 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_
     if (p.reserved != 0) return fail(ISING_E_INVALID_ARG, "reserved must be 0");
     if (p.algo != 0 && p.algo != 1) return fail(ISING_E_INVALID_ARG, "algo must be 0 or 1");
     if (p.algo == 1) {
-        if (ctx->dense || ctx->batch) return fail(ISING_E_UNSUPPORTED, "ADOCH runs on single CSR contexts");
-        if (R != 1) return fail(ISING_E_UNSUPPORTED, "ADOCH runs one restart at a time");
+        if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "ADOCH runs on single CSR or dense contexts");
+        if (R != 1 && R != 2 && R != 4 && R != 8)
+            return fail(ISING_E_UNSUPPORTED, "ADOCH runs 1, 2, 4 or 8 restarts together");
         if (p.x_dtype != ISING_F64) return fail(ISING_E_UNSUPPORTED, "ADOCH stores its iterates in FP64");
         if (p.q < 1) return fail(ISING_E_INVALID_ARG, "ADOCH needs q >= 1");
-        return solve_adoch(ctx, x0_dev, iters, p, x_out_dev, s_out_dev, stats_host,
+        return solve_adoch(ctx, x0_dev, R, iters, p, x_out_dev, s_out_dev, stats_host,
                            static_cast<hipStream_t>(stream));
     }
     if (ctx->batch) return fail(ISING_E_UNSUPPORTED, "use ising_solve_batch on a batch context");

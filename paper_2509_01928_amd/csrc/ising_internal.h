@@ -248,19 +248,23 @@ struct BatchView {
 };
 
 // Arguments of the two ADOCH launches of iteration k.
+// Iterates of R restarts are interleaved: entry (i, r) at i R + r.
 struct AdochArgs {
     double alpha, beta, eps;
     double c;                 // (t_k - 1) / t_{k+1}
     int64_t k;
     int q;                    // look-back window
+    int R;                    // restarts: 1, 2, 4 or 8
     double* partials;
     unsigned int* ticket;
-    double* log;              // [iters][2]: (H(x^(k)), r^(k))
-    int* accept;              // decision of iteration k
-    int8_t* accept_log;       // [iters]
-    double* ring;             // last q+1 values of H(x)
-    RestartState* state;
+    double* log;              // [iters][R][2]: (H(x^(k)), r^(k))
+    int* accept;              // [R]: decision of iteration k
+    int* all_done;            // every restart stopped: later launches return at once
+    int8_t* accept_log;       // [iters][R]
+    double* ring;             // [R][q + 1]: last q+1 values of H(x)
+    RestartState* state;      // [R]
 };
+constexpr int kAdochMaxR = 8;
 
 }  // namespace doch
 
@@ -452,14 +456,18 @@ hipError_t launch_dense_objective(const double* J, int n, int R, const double* X
                                   double beta, double* partials, unsigned int* tickets, double* H,
                                   hipStream_t s);
 
-// ---- launchers (kernels_adoch.hip) ----
+// ---- launchers (kernels_adoch.hip, kernels_dense.hip) ----
+// Workgroups of the ADOCH launches (partial sums: 7 R doubles per workgroup).
 int adoch_grid(int64_t n);
+int adoch_dense_grid(const DenseView& A);
 hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, const double* zp,
                            double* z, const AdochArgs& a, hipStream_t s);
+hipError_t launch_adoch_dense_mv(const DenseView& A, const double* x, const double* xp, const double* zp,
+                                 double* z, const AdochArgs& a, hipStream_t s);
 hipError_t launch_adoch_update(int64_t np, const double* x, const double* xp, const double* z,
                                const double* zp, double* xn, const AdochArgs& a, hipStream_t s);
 hipError_t launch_adoch_finish(const double* b0, const double* b1, const double* b2,
-                               const RestartState* st, int64_t n, int64_t np, bool field,
+                               const RestartState* st, int64_t n, int64_t np, int R, bool field,
                                double* x_out, int8_t* s_out, hipStream_t s);
 
 // ---- launchers (kernels_resident.hip) ----

@@ -10,6 +10,7 @@
 // of loaded (compute-bound on FP64 sine).
 #include <type_traits>
 
+#include "adoch_common.h"
 #include "device_common.h"
 #include "ising_internal.h"
 #include "step_common.h"
@@ -703,6 +704,116 @@ __global__ __launch_bounds__(NT) void dense_power_kernel(int64_t n, JS J,
     }
 }
 
+// ADOCH (Alg. 2) matvec of R interleaved restarts on dense couplings: z =
+// Jhat x^(k) with the sums of H(x^(k)) and H(y^(k)) (see adoch_common.h).
+// Stored J: a wavefront per row, each loaded J_ij serving the R restarts;
+// generated J: kSinRows rows per wavefront, each generated sine serving the
+// R restarts of its row.  Rows are summed in the column order of the DOCH
+// step kernels.
+template <typename HT, bool FIELD, typename JS, int R>
+__global__ __launch_bounds__(NT) void adoch_dense_mv_kernel(int64_t n, JS J, const HT* __restrict__ h,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ xp,
+                                                            const double* __restrict__ zp, double* __restrict__ z,
+                                                            AdochArgs a) {
+    if (*a.all_done) return;
+    __shared__ double red[7 * R * NW];
+    __shared__ int last_flag;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const double c = a.c;
+    double acc[7 * R];
+#pragma unroll
+    for (int q = 0; q < 7 * R; ++q) acc[q] = 0.0;
+    // row i's products for every restart are complete in zr: the row's
+    // update of the sums (lane `owner` only)
+    auto row_done = [&](int64_t i, const double (&zr)[R]) {
+        const double hi = FIELD ? static_cast<double>(h[i]) : 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t t = i * R + r;
+            const double xi = x[t];
+            double zi = zr[r];
+            if (FIELD) {
+                zi = dadd(zi, dmul(hi, x[n * R + r]));
+                acc[7 * r + 6] = dadd(acc[7 * r + 6], dmul(hi, xi));
+            }
+            z[t] = zi;
+            const double yi = dadd(xi, dmul(c, dsub(xi, xp[t])));
+            const double jy = dsub(dmul(dadd(1.0, c), zi), dmul(c, zp[t]));
+            const double x2 = dmul(xi, xi), y2 = dmul(yi, yi);
+            acc[7 * r + 0] = dadd(acc[7 * r + 0], dmul(x2, x2));
+            acc[7 * r + 1] = dadd(acc[7 * r + 1], x2);
+            acc[7 * r + 2] = dadd(acc[7 * r + 2], dmul(xi, zi));
+            acc[7 * r + 3] = dadd(acc[7 * r + 3], dmul(y2, y2));
+            acc[7 * r + 4] = dadd(acc[7 * r + 4], y2);
+            acc[7 * r + 5] = dadd(acc[7 * r + 5], dmul(yi, jy));
+        }
+    };
+    if constexpr (std::is_same<JS, SinJ>::value) {
+        constexpr int RW = kSinRows;
+        for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * NW + wave) * RW; i0 < n;
+             i0 += static_cast<int64_t>(gridDim.x) * NW * RW) {
+            double p[RW][R];
+#pragma unroll
+            for (int w = 0; w < RW; ++w)
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[w][r] = 0.0;
+            lane_rows_sin_walk<RW>(J, i0, n, lane, [&](int64_t j, const double (&sv)[RW], int dr) {
+                double xv[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) xv[r] = x[j * R + r];
+#pragma unroll
+                for (int w = 0; w < RW; ++w)
+                    if (w != dr) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) p[w][r] = dadd(p[w][r], dmul(sv[w], xv[r]));
+                    }
+            });
+#pragma unroll
+            for (int w = 0; w < RW; ++w) {
+                double zr[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) zr[r] = __shfl(wave_sum(p[w][r]), 0, kWave);
+                if (lane == w && i0 + w < n) row_done(i0 + w, zr);
+            }
+        }
+    } else {
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave; i < n;
+             i += static_cast<int64_t>(gridDim.x) * NW) {
+            constexpr int U = 8;
+            double p[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r] = 0.0;
+            int64_t j = lane;
+            for (; j + (U - 1) * kWave < n; j += U * kWave) {
+                double jv[U], xv[U][R];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    jv[u] = J(i, j + u * kWave);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) xv[u][r] = x[(j + u * kWave) * R + r];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) p[r] = dadd(p[r], dmul(jv[u], xv[u][r]));
+            }
+            for (; j < n; j += kWave) {
+                const double jv = J(i, j);
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[r] = dadd(p[r], dmul(jv, x[j * R + r]));
+            }
+            double zr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) zr[r] = wave_sum(p[r]);
+            if (lane == 0) row_done(i, zr);
+        }
+    }
+    block_sum<7 * R, NT>(acc, red);
+    adoch_mv_close<R, NT, FIELD>(acc, red, &last_flag, n, x, xp, zp, z, a);
+}
+
 int grid_for_rows(int64_t n) {
     int64_t g = (n + NW - 1) / NW;
     if (g > 2048) g = 2048;
@@ -732,6 +843,43 @@ int dense_step_grid(int64_t n) { return grid_for_rows(n); }
             __VA_ARGS__;                                                        \
         }                                                                       \
     } while (0)
+
+int adoch_dense_grid(const DenseView& A) {
+    const int64_t rows_per_wave = A.proc_kind == 1 ? kSinRows : 1;
+    int64_t g = (A.n + NW * rows_per_wave - 1) / (NW * rows_per_wave);
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return static_cast<int>(g);
+}
+
+hipError_t launch_adoch_dense_mv(const DenseView& A, const double* x, const double* xp, const double* zp,
+                                 double* z, const AdochArgs& a, hipStream_t s) {
+    const int grid = adoch_dense_grid(A);
+    auto go = [&](auto rtag) {
+        constexpr int RR = decltype(rtag)::value;
+        DOCH_WITH_JSRC(A, {
+            using JS = std::decay_t<decltype(js)>;
+            if (!A.h)
+                hipLaunchKernelGGL((adoch_dense_mv_kernel<double, false, JS, RR>), dim3(grid), dim3(NT), 0, s, A.n,
+                                   js, static_cast<const double*>(nullptr), x, xp, zp, z, a);
+            else if (A.ht == ISING_F64)
+                hipLaunchKernelGGL((adoch_dense_mv_kernel<double, true, JS, RR>), dim3(grid), dim3(NT), 0, s, A.n,
+                                   js, static_cast<const double*>(A.h), x, xp, zp, z, a);
+            else
+                hipLaunchKernelGGL((adoch_dense_mv_kernel<float, true, JS, RR>), dim3(grid), dim3(NT), 0, s, A.n,
+                                   js, static_cast<const float*>(A.h), x, xp, zp, z, a);
+        });
+        return hipGetLastError();
+    };
+    using std::integral_constant;
+    switch (a.R) {
+        case 1: return go(integral_constant<int, 1>());
+        case 2: return go(integral_constant<int, 2>());
+        case 4: return go(integral_constant<int, 4>());
+        case 8: return go(integral_constant<int, 8>());
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_dense_step(const DenseView& A, const StepArgs& a, int grid, hipStream_t s) {
     const bool field = A.h != nullptr;
