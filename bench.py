@@ -37,7 +37,7 @@ def parse():
                     help="spins of the 9-bit integer instance (mean degree 10)")
     ap.add_argument("--workload", default="torus",
                     choices=["torus", "er20000", "sk1024", "dense4096", "batch512", "s5", "adoch",
-                             "procedural", "tune_eta", "copy_calib"],
+                             "procedural", "tune_eta", "adoch_dense", "copy_calib"],
                     help="torus = the 10^8-spin lattice (default line); the others print "
                          "their own JSON line")
     ap.add_argument("--steps", type=int, default=3)
@@ -55,6 +55,8 @@ def parse():
                     help="dense4096: FP64 restarts run one at a time for the comparison")
     ap.add_argument("--oracle-restarts", type=int, default=0,
                     help="oracle restarts of the dense 4096 workload (0: one per host thread, at most 16)")
+    ap.add_argument("--adoch-instance", choices=["sk1024", "procedural"], default="sk1024",
+                    help="adoch_dense: the dense instance")
     ap.add_argument("--batch-shape", default="",
                     help="batch512: launch shape 'rj,wg,chunk_rows' instead of the autotuner's")
     ap.add_argument("--tune-cache",
@@ -854,6 +856,104 @@ def bench_adoch(args):
     L.ising_destroy(ctx)
 
 
+def bench_adoch_dense(args):
+    """ADOCH (Alg. 2, q = 5) on dense couplings against DOCH on the same
+    starts: the stored SK instance n = 1024 (1000 iterations) or the
+    generated couplings sin(i j + 100), n = 65536 (10 iterations), for one
+    restart and for 8 restarts at once (each generated coupling or loaded
+    J_ij then serves all 8).  Iterations per second, edge-updates/s and the
+    energies reached; the oracle's ADOCH as the host baseline with parity of
+    the GPU run (SK: the same run; generated: the same rule at n = 4096,
+    since the oracle holds J in memory)."""
+    import numpy as np
+    import torch
+
+    import ising_inputs as gen
+    import oracle as orc
+    import paper_2509_01928_amd as L
+    d = "cuda:0"
+    if args.adoch_instance == "sk1024":
+        seed, xseed = gen.SEEDS["sk1024"]
+        n, iters = 1024, 1000
+        J = gen.sk_dense(n, seed)
+        Jd = torch.from_numpy(J).to(d)
+        ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
+        label = "dense SK n=1024, J~N(0,1)"
+    else:
+        n, iters = args.proc_n, 10
+        ctx = L.ising_create_procedural(n, 1, 100.0)
+        xseed = 2007
+        label = f"generated couplings sin(ij+100), n={n}"
+    p, lam = L.ising_default_params(ctx, 1.0, 0)
+    out = {"metric": "edge-updates/s", "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic" if args.adoch_instance == "sk1024" else "procedural",
+           "config": {"workload": f"ADOCH (Alg. 2, q=5) vs DOCH on {label}, {iters} iterations, "
+                                  f"1 and 8 restarts", "n": n, "iters": iters, "q": 5}}
+    runs = {}
+    for R in (1, 8):
+        X0 = gen.uniform_x0(n, R, xseed)
+        xd = torch.from_numpy(np.ascontiguousarray(X0)).to(d)
+        so = torch.empty((n, R), dtype=torch.int8, device=d)
+        E = torch.empty(R, dtype=torch.float64, device=d)
+        for algo in (0, 1):
+            if algo == 0 and R > 1:
+                continue                     # DOCH on one context runs one restart at a time
+            q = L.ising_params()
+            q.alpha, q.beta, q.eps, q.algo, q.q, q.x_dtype, q.reserved = p.alpha, p.beta, 0.0, algo, 5, L.ISING_F64, 0
+
+            def step():
+                L.ising_solve(ctx, xd, R, iters, q, None, so, want_stats=False)
+                L.ising_energy(ctx, so, R, E)
+
+            dt = _timed(step, args.warmup, args.steps)
+            key = f"{'adoch' if algo else 'doch'}_R{R}"
+            runs[key] = {"ms_per_solve": 1e3 * dt, "iteration_us": 1e6 * dt / iters,
+                         "edge_updates_per_s": float(n) * (n - 1) * R * iters / dt,
+                         "energies": [float(v) for v in E.cpu().numpy()]}
+            log(f"{key}: {1e6 * dt / iters:.1f} us/iteration, best E {min(runs[key]['energies']):.2f}")
+    out["runs"] = runs
+    out["value"] = runs["adoch_R8"]["edge_updates_per_s"]
+    out["ms_per_step"] = runs["adoch_R8"]["ms_per_solve"]
+    if not args.no_cpu_baseline:
+        # the oracle's ADOCH, and the GPU's on the same start, compared
+        if args.adoch_instance == "sk1024":
+            Jo, no, it_o, lab = J, n, iters, "the same instance and start"
+        else:
+            no, it_o = 4096, 10
+            i = np.arange(no, dtype=np.float64)
+            Jo = np.sin(np.outer(i, i) + 100.0)
+            np.fill_diagonal(Jo, 0.0)
+            lab = "the same rule at n=4096 (the oracle holds J in memory)"
+        log(f"oracle ADOCH on {lab}")
+        B = orc.csr_of_dense(Jo)
+        x0 = gen.uniform_x0(no, 1, xseed)[:, 0]
+        # the sample's parameters by the O(nnz) estimate, on both sides
+        a2, b2 = (p.alpha, p.beta) if no == n else orc.default_params(B, 1.0, method="wigner")[:2]
+        t0 = time.perf_counter()
+        tr = orc.adoch(B, x0, a2, b2, it_o, 5)
+        dt_cpu = time.perf_counter() - t0
+        ctx2 = ctx if no == n else L.ising_create_procedural(no, 1, 100.0)
+        q = L.ising_params()
+        q.alpha, q.beta, q.eps, q.algo, q.q, q.x_dtype, q.reserved = a2, b2, 0.0, 1, 5, L.ISING_F64, 0
+        xd = torch.from_numpy(x0).to(d)
+        xo = torch.empty_like(xd)
+        so = torch.empty(no, dtype=torch.int8, device=d)
+        L.ising_solve(ctx2, xd, 1, it_o, q, xo, so)
+        torch.cuda.synchronize()
+        out["parity"] = iterate_parity(xo.cpu().numpy(), tr.x, so.cpu().numpy(), orc.sign(tr.x))
+        out["parity"]["sample"] = lab
+        if ctx2 is not ctx:
+            L.ising_destroy(ctx2)
+        out["cpu_baseline"] = {"value": float(no) * (no - 1) * it_o / dt_cpu, "unit": "edge-updates/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{it_o} ADOCH iterations of the single-threaded FP64 oracle on "
+                                         f"{lab} ({dt_cpu:.2f} s)", **host_info()}
+        log(f"parity {out['parity']}")
+    print(json.dumps(out), flush=True)
+    L.ising_destroy(ctx)
+
+
 def bench_procedural(args):
     """Procedural dense couplings J_ij = sin(i j + 100) (Supp. Note 9,
     NEXT-3), generated in FP64 on the fly: n = 65536, 10 DOCH iterations per
@@ -1080,7 +1180,7 @@ def main():
     if args.workload != "torus":
         {"er20000": bench_er20000, "sk1024": bench_sk1024, "dense4096": bench_dense4096,
          "batch512": bench_batch512, "s5": bench_s5, "adoch": bench_adoch,
-         "procedural": bench_procedural, "tune_eta": bench_tune_eta,
+         "procedural": bench_procedural, "tune_eta": bench_tune_eta, "adoch_dense": bench_adoch_dense,
          "copy_calib": bench_copy_calib}[args.workload](args)
         return
     import numpy as np
