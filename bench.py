@@ -186,8 +186,10 @@ def ingest_pmc(paths, workload):
     write = per_kernel(paths[1], "WRITE_SIZE")
     cf = per_kernel(paths[2], "FETCH_SIZE")
     cw = per_kernel(paths[3], "WRITE_SIZE")
-    copy_name = next(k for k in cf if k.startswith("copy_kernel"))
-    copy_bytes = float(os.environ.get("COPY_BYTES", 1024 * 1024 * 1024))   # stream_bw 1024 MiB
+    # the copy of known size: the dispatch reading the most in the copy run
+    # (`bench.py --workload copy_calib`: 1 GiB read, 1 GiB written)
+    copy_name = max(cf, key=lambda k: sum(cf[k]) / len(cf[k]))
+    copy_bytes = float(1024 * 1024 * 1024)
     fetch_scale = copy_bytes / (1024.0 * sum(cf[copy_name]) / len(cf[copy_name]))
     write_scale = copy_bytes / (1024.0 * sum(cw[copy_name]) / len(cw[copy_name]))
     # the timed kernel is the step-kernel variant dispatched most often
