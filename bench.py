@@ -59,10 +59,13 @@ def parse():
                     help="adoch_dense: the dense instance")
     ap.add_argument("--batch-shape", default="",
                     help="batch512: launch shape 'rj,wg,chunk_rows' instead of the autotuner's")
+    ap.add_argument("--lowp-shape", default="",
+                    help="dense4096: bn,splits,stage_bytes,depth of the matrix-core product instead of the "
+                         "tuned one (splits 0: the fused iteration)")
     ap.add_argument("--tune-cache",
                     default=os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
-                                         "paper_2509_01928_amd", "batch_shapes.json"),
-                    help="JSON cache of the batch autotuner")
+                                         "paper_2509_01928_amd", "launch_shapes.json"),
+                    help="JSON cache of the launch-shape autotuners (batch512, dense4096)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
     ap.add_argument("--tune-instance", choices=["torus", "s5", "procedural"], default="torus",
@@ -514,6 +517,17 @@ def bench_dense4096(args):
         so = torch.empty((n, R), dtype=torch.int8, device=d)
         Hf = torch.empty(R, dtype=torch.float64, device=d)
         Eb = torch.empty(R, dtype=torch.float64, device=d)
+        if args.lowp_shape:
+            shape = tuple(int(v) for v in args.lowp_shape.split(","))
+            L.ising_set_lowp_shape(ctx, *shape)
+            tune = {"source": "flag"}
+        else:
+            t0 = time.time()
+            os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+            shape, tms, cached = L.ising_autotune_lowp(ctx, xd, R, 50, p, prec, args.tune_cache)
+            tune = {"source": "cache" if cached else "autotuner", "us_per_iteration": 1e3 * tms / 50,
+                    "tuning_s": time.time() - t0}
+        log(f"{name} shape {shape} ({tune['source']})")
         L.ising_solve_lowp(ctx, xd, R, 20, p, prec, None, so, Hf)      # warm-up
         torch.cuda.synchronize()
         e0.record()
@@ -549,7 +563,13 @@ def bench_dense4096(args):
                "energy_gap_vs_gpu_fp64_same_starts": {
                    "restarts": nplain, "mean": float(g64.mean()), "min": float(g64.min()),
                    "max": float(g64.max()), "lower_or_equal_fraction": float(np.mean(g64 <= 0))},
-               "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak,
+               "launch_shape": {"bn": shape[0], "splits": shape[1], "stage_bytes": shape[2], "depth": shape[3],
+                                "kind": "fused" if shape[1] == 0 else "split product + update"},
+               "autotune": tune,
+               "roofline": {"bound": "mfma",
+                            "kernel": ("lowp_fused_kernel" if shape[1] == 0 else
+                                       "lowp_gemm_kernel + lowp_update_kernel"),
+                            "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak,
                             "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / peak}}
         if E_or is not None:
             go = (Eh[:n_or] - E_or) / np.abs(E_or)

@@ -308,6 +308,43 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
                               int8_t* s_out_dev, double* H_final_dev, ising_stats* stats_host,
                               void* stream);
 
+/* Shape of the matrix-core product of ising_solve_lowp on this context: each
+ * iteration computes J U as tiles of 128 rows x bn restarts (bn = 64 or 128)
+ * over `splits` equal parts of the k range (1, 2, 4 or 8), whose FP32
+ * partial tiles the update adds in split order; the k range streams through
+ * LDS in stages of stage_bytes per row (128 or 256) with `depth` stages in
+ * flight (2 or 3).  splits = 0 selects the fused iteration instead: one
+ * launch whose 64 x 64 tiles (bn 64, 256-byte stages) cover the whole k
+ * range and update in place, with no partial tiles in memory.  bn = 0
+ * restores the default, the fused iteration (depth 3 in BF16 where the
+ * padded order holds three stages, else 2).  A shape that does not fit a later call (bn not
+ * dividing the padded restart count, or a split holding fewer than `depth`
+ * whole stages) falls back to the default for that call.  The shape changes
+ * the order of the FP32 additions, nothing else.
+ * Errors: ISING_E_INVALID_ARG for a value outside those sets, or for
+ * splits = 0 with bn != 64 or stage_bytes != 256. */
+ising_status ising_set_lowp_shape(ising_ctx* ctx, int32_t bn, int32_t splits, int32_t stage_bytes,
+                                  int32_t depth);
+
+/* Choose the shape of ising_solve_lowp for this context, restart count and
+ * format by timing: every shape the library is built for that fits (the
+ * fused iteration with 64 x 64 tiles, which needs no partial tiles, and the
+ * split product of ising_set_lowp_shape over tile widths, splits, stage
+ * widths and depths) runs `iters` iterations from x0_dev twice, the second
+ * timed on `stream`; the fastest becomes this context's shape.  With
+ * cache_path non-NULL the choice is looked up first and stored after tuning
+ * in a JSON file of one entry per line, keyed by device name, compute-unit
+ * count, format, padded order, padded restart count and iters.
+ *   shape_out       NULL or int32[4]: bn, splits (0: fused), stage_bytes, depth
+ *   ms_out          NULL or the chosen shape's time for `iters` iterations
+ *   from_cache_out  NULL or 1 when the shape came from the cache
+ * The context's last-solve state (logs, statistics) is overwritten.
+ * Synchronises `stream`.  Errors: as ising_solve_lowp; ISING_E_INVALID_ARG
+ * for iters < 1. */
+ising_status ising_autotune_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t iters,
+                                 const ising_params* params, int32_t jx_dtype, const char* cache_path, void* stream,
+                                 int32_t* shape_out, double* ms_out, int32_t* from_cache_out);
+
 /* ---------------------------------------------------------------- batches
  * Many independent instances solved together (the benchmark setting of the
  * paper's small and medium models: many instances and many random

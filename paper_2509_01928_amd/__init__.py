@@ -18,7 +18,7 @@ __all__ = [
     "ising_create_csr", "ising_create_dense", "ising_destroy", "ising_get_info",
     "ising_check_symmetric", "ising_default_params", "ising_solve", "ising_get_log",
     "ising_energy", "ising_energy_noalloc", "ising_cut", "ising_tune_eta", "ising_set_geometry", "ising_autotune", "ising_create_batch",
-    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_set_batch_shape", "ising_autotune_batch", "ising_solve_lowp", "ising_get_accept_log", "ising_create_procedural",
+    "ising_default_params_batch", "ising_solve_batch", "ising_energy_batch", "ising_set_batch_shape", "ising_autotune_batch", "ising_set_lowp_shape", "ising_autotune_lowp", "ising_solve_lowp", "ising_get_accept_log", "ising_create_procedural",
     "ising_status_string", "ising_last_error", "ising_version",
     "ptr", "current_stream",
 ]
@@ -105,7 +105,9 @@ _SIGS = {
     "ising_solve_batch": (_st, [_p, _p, _i32, _i64, _p, _p, _d, _i32, _p, _p, _p, _p, _p]),
     "ising_energy_batch": (_st, [_p, _p, _i32, _p, _p, _p]),
     "ising_set_batch_shape": (_st, [_p, _i32, _i32, _i32]),
+    "ising_set_lowp_shape": (_st, [_p, _i32, _i32, _i32, _i32]),
     "ising_autotune_batch": (_st, [_p, _p, _i32, _i64, _p, _p, _d, _i32, ctypes.c_char_p, _p, _p, _p, _p]),
+    "ising_autotune_lowp": (_st, [_p, _p, _i32, _i64, _p, _i32, ctypes.c_char_p, _p, _p, _p, _p]),
     "ising_solve_lowp": (_st, [_p, _p, _i32, _i64, ctypes.POINTER(ising_params), _i32, _p, _p, _p, _p, _p]),
     "ising_get_accept_log": (_st, [_p, _i64, _i64, _p, _p]),
     "ising_create_procedural": (_st, [_i64, _i32, _d, _p, ctypes.POINTER(_p)]),
@@ -323,6 +325,11 @@ def ising_energy_batch(ctx, s, R, E=None, E_int=None, stream=None):
            "ising_energy_batch")
 
 
+def ising_set_lowp_shape(ctx, bn, splits=1, stage_bytes=256, depth=2):
+    _check(lib.ising_set_lowp_shape(ctx, int(bn), int(splits), int(stage_bytes), int(depth)),
+           "ising_set_lowp_shape")
+
+
 def ising_set_batch_shape(ctx, rj, wg, chunk_rows):
     _check(lib.ising_set_batch_shape(ctx, int(rj), int(wg), int(chunk_rows)), "ising_set_batch_shape")
 
@@ -343,6 +350,19 @@ def ising_autotune_batch(ctx, x0, R, max_iters, alpha, beta, eps=0.0, x_dtype=IS
                                     ctypes.cast(shape, _p), ctypes.byref(ms), ctypes.byref(cached)),
            "ising_autotune_batch")
     return (shape[0], shape[1], shape[2]), ms.value, bool(cached.value)
+
+
+def ising_autotune_lowp(ctx, x0, R, iters, params, jx_dtype, cache_path=None, stream=None):
+    """Returns ((bn, splits, stage_bytes, depth), milliseconds, from_cache)."""
+    shape = (ctypes.c_int32 * 4)()
+    ms = ctypes.c_double()
+    cached = ctypes.c_int32()
+    _check(lib.ising_autotune_lowp(ctx, ptr(x0), int(R), int(iters), ctypes.byref(params), int(jx_dtype),
+                                   os.fsencode(cache_path) if cache_path is not None else None,
+                                   stream if stream is not None else current_stream(),
+                                   ctypes.cast(shape, _p), ctypes.byref(ms), ctypes.byref(cached)),
+           "ising_autotune_lowp")
+    return (shape[0], shape[1], shape[2], shape[3]), ms.value, bool(cached.value)
 
 
 def ising_solve_lowp(ctx, x0, R, iters, params, jx_dtype, x_out=None, s_out=None, H_final=None,

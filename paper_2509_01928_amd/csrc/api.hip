@@ -211,6 +211,7 @@ void free_ctx(ising_ctx* c) {
     for (auto& b : c->lp_u) dev_free(b);
     for (auto& b : c->lp_ub) dev_free(b);
     dev_free(c->lp_partials);
+    dev_free(c->lp_P);
     dev_free(c->rx);
     dev_free(c->rsync);
     for (auto& b : c->ad_x) dev_free(b);
@@ -451,6 +452,14 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
                                          ctx->has_field, x_out_dev, s_out_dev, s), "finish");
     return read_stats(ctx, R, stats_host, s);
 }
+
+namespace {
+bool cache_lookup_ints(const char* path, const std::string& key, const char* const* names, int n, int* vals,
+                       double* ms);
+bool cache_store_ints(const char* path, const std::string& key, const char* const* names, int n, const int* vals,
+                      double ms);
+extern const char* const kLowpFields[4];
+}  // namespace
 
 extern "C" {
 
@@ -1347,6 +1356,145 @@ ising_status ising_energy_batch(ising_ctx* ctx, const int8_t* s_dev, int32_t R, 
     return ISING_OK;
 }
 
+ising_status ising_autotune_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, int64_t iters,
+                                 const ising_params* params, int32_t jx_dtype, const char* cache_path, void* stream,
+                                 int32_t* shape_out, double* ms_out, int32_t* from_cache_out) {
+    if (!ctx || !params || !x0_dev) return fail(ISING_E_INVALID_ARG, "NULL argument");
+    if (!ctx->dense || ctx->proc_kind != 0)
+        return fail(ISING_E_UNSUPPORTED, "the low-precision path needs a stored dense context");
+    if (jx_dtype != ISING_BF16 && jx_dtype != ISING_FP8_E4M3)
+        return fail(ISING_E_INVALID_ARG, "jx_dtype must be ISING_BF16 or ISING_FP8_E4M3");
+    if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
+    if (iters < 1) return fail(ISING_E_INVALID_ARG, "iters < 1");
+    HIP_OK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, ctx->device), "device properties");
+    const int prec = jx_dtype == ISING_BF16 ? 0 : 1;
+    const int n = static_cast<int>(ctx->n);
+    const int npg = prec == 0 ? 256 : 512;      // as ising_solve_lowp pads
+    const int np = (n + npg - 1) / npg * npg;
+    const int Rp = (R + 63) / 64 * 64;
+    char kb[256];
+    std::snprintf(kb, sizeof(kb), "lowp-v1|%s|cus=%d|%s|np=%d|Rp=%d|iters=%lld", prop.gcnArchName,
+                  prop.multiProcessorCount, prec == 0 ? "bf16" : "fp8", np, Rp, static_cast<long long>(iters));
+    const std::string key(kb);
+    auto report = [&](const doch::LowpShape& sh, double ms, int cached) {
+        if (shape_out) {
+            shape_out[0] = sh.bn;
+            shape_out[1] = sh.splits;
+            shape_out[2] = sh.sb;
+            shape_out[3] = sh.depth;
+        }
+        if (ms_out) *ms_out = ms;
+        if (from_cache_out) *from_cache_out = cached;
+    };
+    int v[4];
+    double cms = 0.0;
+    if (cache_lookup_ints(cache_path, key, kLowpFields, 4, v, &cms)) {
+        doch::LowpShape sh;
+        sh.bn = v[0];
+        sh.splits = v[1];
+        sh.sb = v[2];
+        sh.depth = v[3];
+        if (doch::lowp_shape_valid(prec, np, Rp, sh)) {
+            ctx->lp_shape = sh;
+            report(sh, cms, 1);
+            return ISING_OK;
+        }
+    }
+    // candidates: the fused iteration, and the split product over tile
+    // widths, splits, stage widths and depths, as far as they fit
+    std::vector<doch::LowpShape> cand;
+    for (int d : {2, 3}) {
+        doch::LowpShape sh;
+        sh.bn = 64;
+        sh.splits = 0;
+        sh.sb = 256;
+        sh.depth = d;
+        if (doch::lowp_shape_valid(prec, np, Rp, sh)) cand.push_back(sh);
+    }
+    for (int bn : {128, 64})
+        for (int S : {1, 2, 4, 8})
+            for (int sb : {128, 256})
+                for (int d : {2, 3}) {
+                    doch::LowpShape sh;
+                    sh.bn = bn;
+                    sh.splits = S;
+                    sh.sb = sb;
+                    sh.depth = d;
+                    if (doch::lowp_shape_valid(prec, np, Rp, sh)) cand.push_back(sh);
+                }
+    if (cand.empty()) return fail(ISING_E_UNSUPPORTED, "no low-precision shape fits n=%d, R=%d", n, R);
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0), "event");
+    HIP_OK(hipEventCreate(&e1), "event");
+    const doch::LowpShape saved = ctx->lp_shape;
+    doch::LowpShape best;
+    double best_ms = -1.0;
+    ising_status st = ISING_OK;
+    for (const auto& sh : cand) {
+        ctx->lp_shape = sh;
+        // one run to allocate and warm up, one timed
+        st = ising_solve_lowp(ctx, x0_dev, R, iters, params, jx_dtype, nullptr, nullptr, nullptr, nullptr, stream);
+        if (st != ISING_OK) break;
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess) {
+            st = ising_solve_lowp(ctx, x0_dev, R, iters, params, jx_dtype, nullptr, nullptr, nullptr, nullptr,
+                                  stream);
+            if (st != ISING_OK) break;
+            e = hipEventRecord(e1, s);
+        }
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "autotune timing");
+            break;
+        }
+        if (best_ms < 0.0 || ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ISING_OK) {
+        ctx->lp_shape = saved;
+        return st;
+    }
+    ctx->lp_shape = best;
+    report(best, best_ms, 0);
+    const int bv[4] = {best.bn, best.splits, best.sb, best.depth};
+    (void)cache_store_ints(cache_path, key, kLowpFields, 4, bv, best_ms);
+    return ISING_OK;
+}
+
+ising_status ising_set_lowp_shape(ising_ctx* ctx, int32_t bn, int32_t splits, int32_t stage_bytes,
+                                  int32_t depth) {
+    if (!ctx) return fail(ISING_E_INVALID_ARG, "NULL context");
+    if (bn == 0) {
+        ctx->lp_shape = doch::LowpShape{};
+        return ISING_OK;
+    }
+    doch::LowpShape sh;
+    sh.bn = bn;
+    sh.splits = splits;
+    sh.sb = stage_bytes;
+    sh.depth = depth;
+    // the values the library is built for; whether they fit a problem is
+    // checked per call
+    if (bn != 64 && bn != 128) return fail(ISING_E_INVALID_ARG, "bn must be 0, 64 or 128");
+    if (splits != 0 && splits != 1 && splits != 2 && splits != 4 && splits != 8)
+        return fail(ISING_E_INVALID_ARG, "splits must be 0, 1, 2, 4 or 8");
+    if (stage_bytes != 128 && stage_bytes != 256) return fail(ISING_E_INVALID_ARG, "stage_bytes must be 128 or 256");
+    if (depth != 2 && depth != 3) return fail(ISING_E_INVALID_ARG, "depth must be 2 or 3");
+    if (splits == 0 && (bn != 64 || stage_bytes != 256))
+        return fail(ISING_E_INVALID_ARG, "the fused iteration (splits 0) takes bn 64 and 256-byte stages");
+    ctx->lp_shape = sh;
+    return ISING_OK;
+}
+
 ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32_t chunk_rows) {
     if (!ctx || !ctx->batch) return fail(ISING_E_INVALID_ARG, "not a batch context");
     if (rj == 0 && wg == 0 && chunk_rows == 0) {      // back to the default
@@ -1369,10 +1517,12 @@ ising_status ising_set_batch_shape(ising_ctx* ctx, int32_t rj, int32_t wg, int32
 
 namespace {
 
-// The tuning cache is a JSON object with one entry per line,
+// The tuning cache is a JSON object with one entry per line, the key then
+// named integer fields and the time of the chosen shape,
 //   "key": {"rj": 8, "wg": 256, "chunk_rows": 512, "ms": 12.5},
-// written and read only by the two functions below.
-bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh, double* ms) {
+// written and read only by the functions below.
+bool cache_lookup_ints(const char* path, const std::string& key, const char* const* names, int n, int* vals,
+                       double* ms) {
     if (!path) return false;
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
@@ -1382,13 +1532,18 @@ bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh
     while (std::fgets(line, sizeof(line), f)) {
         const char* p = std::strstr(line, head.c_str());
         if (!p) continue;
-        int rj = 0, wg = 0, rpm = 0;
+        p += head.size();
+        bool ok = true;
+        std::vector<int> v(static_cast<size_t>(n));
+        for (int i = 0; i < n && ok; ++i) {
+            const std::string field = "\"" + std::string(names[i]) + "\": ";
+            const char* q = std::strstr(p, field.c_str());
+            ok = q && std::sscanf(q + field.size(), "%d", &v[static_cast<size_t>(i)]) == 1;
+        }
+        const char* q = ok ? std::strstr(p, "\"ms\": ") : nullptr;
         double t = 0.0;
-        if (std::sscanf(p + head.size(), " \"rj\": %d, \"wg\": %d, \"chunk_rows\": %d, \"ms\": %lf", &rj, &wg,
-                        &rpm, &t) == 4) {
-            sh->rj = rj;
-            sh->wg = wg;
-            sh->chunk_rows = rpm;
+        if (q && std::sscanf(q + 6, "%lf", &t) == 1) {
+            for (int i = 0; i < n; ++i) vals[i] = v[static_cast<size_t>(i)];
             *ms = t;
             found = true;
         }
@@ -1397,7 +1552,8 @@ bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh
     return found;
 }
 
-bool cache_store(const char* path, const std::string& key, const doch::BatchShape& sh, double ms) {
+bool cache_store_ints(const char* path, const std::string& key, const char* const* names, int n, const int* vals,
+                      double ms) {
     if (!path) return false;
     std::vector<std::string> entries;
     const std::string head = "\"" + key + "\": {";
@@ -1412,10 +1568,15 @@ bool cache_store(const char* path, const std::string& key, const doch::BatchShap
         }
         std::fclose(f);
     }
-    char buf[512];
-    std::snprintf(buf, sizeof(buf), "%s\"rj\": %d, \"wg\": %d, \"chunk_rows\": %d, \"ms\": %.4f}", head.c_str(),
-                  sh.rj, sh.wg, sh.chunk_rows, ms);
-    entries.emplace_back(buf);
+    std::string e = head;
+    char buf[96];
+    for (int i = 0; i < n; ++i) {
+        std::snprintf(buf, sizeof(buf), "\"%s\": %d, ", names[i], vals[i]);
+        e += buf;
+    }
+    std::snprintf(buf, sizeof(buf), "\"ms\": %.4f}", ms);
+    e += buf;
+    entries.push_back(e);
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return false;
@@ -1425,6 +1586,23 @@ bool cache_store(const char* path, const std::string& key, const doch::BatchShap
     std::fputs("}\n", f);
     const bool ok = std::fclose(f) == 0;
     return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+const char* const kBatchFields[3] = {"rj", "wg", "chunk_rows"};
+extern const char* const kLowpFields[4] = {"bn", "splits", "stage_bytes", "depth"};
+
+bool cache_lookup(const char* path, const std::string& key, doch::BatchShape* sh, double* ms) {
+    int v[3];
+    if (!cache_lookup_ints(path, key, kBatchFields, 3, v, ms)) return false;
+    sh->rj = v[0];
+    sh->wg = v[1];
+    sh->chunk_rows = v[2];
+    return true;
+}
+
+bool cache_store(const char* path, const std::string& key, const doch::BatchShape& sh, double ms) {
+    const int v[3] = {sh.rj, sh.wg, sh.chunk_rows};
+    return cache_store_ints(path, key, kBatchFields, 3, v, ms);
 }
 
 }  // namespace
@@ -1558,7 +1736,9 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int prec = jx_dtype == ISING_BF16 ? 0 : 1;
     const int n = static_cast<int>(ctx->n);
-    const int np = (n + 255) / 256 * 256;          // whole 256-byte stages in both formats
+    // padded order: at least two whole 256-byte stages per row (512 k in FP8)
+    const int npg = prec == 0 ? 256 : 512;
+    const int np = (n + npg - 1) / npg * npg;
     const int Rp = (R + 63) / 64 * 64;
     const size_t esz = prec == 0 ? 2 : 1;
     if (!ctx->jq[prec]) {
@@ -1581,7 +1761,6 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
             for (double v : ra) m = std::max(m, v);
             ctx->lp_rho_q = m;
         }
-        ctx->lp_np = np;
     }
     // three rotating iterate buffers (FP32 master and low-precision copy): a
     // restart that stops keeps its last iterate in buffer iters_done mod 3
@@ -1603,6 +1782,13 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
     // iteration k - 1 from the other
     const size_t pstride = static_cast<size_t>(np / 64) * Rp * 4;
     HIP_OK(ensure(&ctx->lp_partials, &ctx->lp_pbytes, 2 * pstride * sizeof(double)), "hipMalloc(partials)");
+    doch::LowpShape shape = ctx->lp_shape;
+    if (shape.bn == 0 || !doch::lowp_shape_valid(prec, np, Rp, shape)) {
+        int cus = 256;
+        HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
+        shape = doch::lowp_default_shape(prec, np, Rp, cus);
+    }
+    HIP_OK(ensure(&ctx->lp_P, &ctx->lp_Pbytes, doch::lowp_product_bytes(np, Rp, shape)), "hipMalloc(products)");
     if (!ctx->ticket) {
         HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
         HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
@@ -1627,9 +1813,9 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         const int a = static_cast<int>(k % 3), b = static_cast<int>((k + 1) % 3);
         double* pk = ctx->lp_partials + (k & 1) * pstride;
         const double* pprev = ctx->lp_partials + ((k + 1) & 1) * pstride;
-        HIP_OK(doch::launch_lowp_step(prec, np, Rp, ctx->jq[prec], ctx->rscale, ctx->lp_u[a], ctx->lp_u[b],
-                                      ctx->lp_ub[a], ctx->lp_ub[b], cs[a], cs[b], ctx->lp_rho_q, p.alpha,
-                                      p.beta, p.eps, R, k, pprev, pk, ctx->log, ctx->state, s),
+        HIP_OK(doch::launch_lowp_step(prec, np, Rp, shape, ctx->jq[prec], ctx->rscale, ctx->lp_u[a], ctx->lp_u[b],
+                                      ctx->lp_ub[a], ctx->lp_ub[b], cs[a], cs[b], ctx->lp_rho_q, p.alpha, p.beta,
+                                      p.eps, R, k, ctx->lp_P, pprev, pk, ctx->log, ctx->state, s),
                "low-precision step");
     }
     if (iters > 0)

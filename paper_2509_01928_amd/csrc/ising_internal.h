@@ -175,6 +175,11 @@ struct BatchRestartStat {
     double r_last;
 };
 
+// Launch shape of the dense low-precision product (launch_lowp_step).
+struct LowpShape {
+    int bn = 0, splits = 0, sb = 0, depth = 0;
+};
+
 // Launch shape of the batch solve for up to 8 restarts: restarts per unit
 // of work (rj), threads per workgroup (wg) and rows per chunk (chunk_rows).
 struct BatchShape {
@@ -344,12 +349,14 @@ struct ising_ctx {
     size_t sweep_x_bytes = 0;
     float* lp_cs = nullptr;              // FP8: restart scales, three buffers of kMaxR
     unsigned int* lp_colmax = nullptr;   // FP8: start column maxima (float bits)
-    int lp_np = 0;                       // padded order (multiple of 256)
     float* lp_u[3] = {nullptr, nullptr, nullptr};   // FP32 master iterates (rotating)
     void* lp_ub[3] = {nullptr, nullptr, nullptr};   // their low-precision copies
     size_t lp_ubytes = 0, lp_ubbytes = 0;
     double* lp_partials = nullptr;
     size_t lp_pbytes = 0;
+    float* lp_P = nullptr;               // split partial products of one iteration
+    size_t lp_Pbytes = 0;
+    doch::LowpShape lp_shape;            // product shape set by the caller (bn 0: default)
     // ADOCH buffers (three iterates, two products, window, decisions)
     double* ad_x[3] = {nullptr, nullptr, nullptr};
     double* ad_z[2] = {nullptr, nullptr};
@@ -438,15 +445,23 @@ hipError_t launch_lowp_convert(int prec, const double* J, int n, int np, void* J
                                double* rowabs, hipStream_t s);
 hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, int Rp, double sqrt_beta,
                             unsigned int* colmax_bits, float* cs, float* U, void* Ub, hipStream_t s);
-// One iteration of the restart block; its extra workgroups close iteration
-// k - 1 from partials_prev (k > 0).  A stopped restart is never written, so
-// its last iterate stays in buffer iters_done mod 3 (three buffers rotate).
-hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const float* rscale,
+// Shape of the product of one iteration: tiles of 128 rows x bn restarts
+// (64 or 128), `splits` equal parts of the k range (1, 2, 4 or 8), stages of
+// sb bytes per row (128 or 256) with `depth` stages in flight (2 or 3).
+// Valid when the tiles divide the padded problem and every split holds at
+// least `depth` whole stages.
+bool lowp_shape_valid(int prec, int np, int Rp, const LowpShape& sh);
+LowpShape lowp_default_shape(int prec, int np, int Rp, int cus);
+size_t lowp_product_bytes(int np, int Rp, const LowpShape& sh);   // the split partial tiles P
+// One iteration of the restart block: the split product into P, whose
+// extra workgroups close iteration k - 1 from partials_prev (k > 0), then the
+// update.  A stopped restart is never written, so its last iterate stays
+// in buffer iters_done mod 3 (three buffers rotate).
+hipError_t launch_lowp_step(int prec, int np, int Rp, const LowpShape& sh, const void* Jq, const float* rscale,
                             const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
-                            const float* cs_old, float* cs_new, double rho_q,
-                            double alpha, double beta, double eps, int R, int64_t k,
-                            const double* partials_prev, double* partials, double* log, RestartState* state,
-                            hipStream_t s);
+                            const float* cs_old, float* cs_new, double rho_q, double alpha, double beta,
+                            double eps, int R, int64_t k, float* P, const double* partials_prev,
+                            double* partials, double* log, RestartState* state, hipStream_t s);
 // Close iteration kk (the last one, after the final step).
 hipError_t launch_lowp_close(int np, int Rp, int R, int64_t kk, const double* partials, double alpha,
                              double beta, double eps, double* log, RestartState* state, hipStream_t s);

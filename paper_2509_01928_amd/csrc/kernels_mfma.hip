@@ -36,9 +36,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int MT = 256;        // threads per workgroup
-// stages of J and restart rows a thread keeps in flight (256 bytes of each of
-// 64 rows per stage, 32 KB per workgroup); 2 to 12 measured the same
-constexpr int kLowpDepth = 2;
 
 template <int PREC> struct Prec;
 template <> struct Prec<0> {   // BF16
@@ -80,34 +77,6 @@ __device__ __forceinline__ typename Prec<PREC>::T to_lowp(float f) {
     else return to_fp8(f);
 }
 
-// A lane's operand fragment of one 32 x 32 x 16 MFMA: 8 consecutive k of one
-// row (16 bytes of BF16, 8 bytes of FP8).
-template <int PREC> struct Frag;
-template <> struct Frag<0> { typedef bf16x8 type; };
-template <> struct Frag<1> { typedef long type; };
-
-template <int PREC>
-__device__ __forceinline__ f32x16 mfma_frag(typename Frag<PREC>::type a, typename Frag<PREC>::type b, f32x16 c) {
-    if constexpr (PREC == 0) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    else return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
-}
-
-
-// One DOCH iteration for 64 rows x 64 restarts per workgroup.
-//   main loop   the k range in stages of 256 bytes per row (128 BF16 or 256
-//               FP8 k), loaded as whole cache lines into registers two
-//               stages ahead and staged through two LDS buffers, one barrier
-//               per stage; each wavefront computes the whole 64 x 64 tile as
-//               2 x 2 independent 32 x 32 accumulators over every fourth
-//               16-deep k-step of a stage.  A column block whose restarts
-//               have all stopped skips it.
-//   reduction   the four partial tiles meet in LDS; wavefront w adds the
-//               four copies of sub-tile w in wavefront order
-//   epilogue    FP64 update of the 16 entries each lane then holds, FP32
-//               master store, the low-precision copy transposed through LDS
-//               and written in whole rows, per-restart partial sums
-//   finish      the last workgroup of each column block closes the
-//               iteration of its 64 restarts (H, r, stopping)
 // Close iteration kk of the 64 restarts of column block cb: add the row
 // tiles' partial sums in tile order and write H, r, the log and the state
 // (eq:Hamilton in u = sqrt(beta) x, Remark S2).  red: 64 x 4 doubles of LDS.
@@ -146,8 +115,233 @@ __device__ void lowp_close(const double* __restrict__ P, int tiles, int Rp, int 
     }
 }
 
+
+// ---- the product: split-k partial tiles --------------------------------
+//
+// P[s] = J[:, K_s] U^T[K_s, :] for split s of the k range, as FP32 partial
+// tiles (np x Rp, row-major).  A workgroup owns a 128 x BN tile of one
+// split; its four wavefronts split the tile 2 x 2 and each accumulates its
+// 64 x BN/2 sub-tile as 2 x BN/64 independent 32 x 32 MFMA blocks over the
+// whole k range of the split (no reduction inside the workgroup).  The k
+// range streams in stages of 256 bytes per row: every row of J and of the
+// restart copy that the tile needs is loaded as whole cache lines into
+// registers DEPTH stages ahead, written to one of two LDS buffers, and read
+// back as MFMA fragments -- one barrier per stage.  Stages of SB = 256 bytes
+// per row take about 136 KB of LDS at BN = 128 (one workgroup per compute
+// unit); SB = 128 halves that, so two workgroups can share one.
+//
+// Fragment layout: lane l takes row l % 32 of its 32-row block and half
+// l / 32 of the k-step's bytes (16 bytes of BF16 for the 32 x 32 x 16 MFMA,
+// 32 bytes of FP8 for the 32 x 32 x 64 one).  Both operands are read the
+// same way, so the products pair k with k whatever order the matrix core
+// assigns to the bytes inside a fragment.
+constexpr int kTileM = 128;                    // rows of J per product tile
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// bytes of k per MFMA step, and the step itself on two LDS fragments
+template <int PREC> struct Mfma;
+template <> struct Mfma<0> {
+    static constexpr int kBytes = 32;         // 32 x 32 x 16 BF16
+    typedef bf16x8 frag;
+    static __device__ __forceinline__ frag load(const char* p) { return *reinterpret_cast<const bf16x8*>(p); }
+    static __device__ __forceinline__ f32x16 step(frag a, frag b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<1> {
+    static constexpr int kBytes = 64;         // 32 x 32 x 64 FP8 (e4m3 both operands, no block scales)
+    typedef i32x8 frag;
+    static __device__ __forceinline__ frag load(const char* p) {
+        const i32x4 lo = *reinterpret_cast<const i32x4*>(p);
+        const i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
+        return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+    static __device__ __forceinline__ f32x16 step(frag a, frag b, f32x16 c) {
+        // format codes 0/0: e4m3 x e4m3; zero scale operands select the
+        // unscaled instruction
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+    }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
+                                             static_cast<int>(bytes), 0x00020000);
+}
+
+template <int PREC, int BN, int SB, int DEPTH>
+__device__ __forceinline__ void lowp_gemm_tile(int np, int Rp, int S, int R,
+                                                       const typename Prec<PREC>::T* __restrict__ Jq,
+                                                       const typename Prec<PREC>::T* __restrict__ Ub,
+                                                       float* __restrict__ P, int64_t k, double alpha,
+                                                       double beta, double eps,
+                                                       const double* __restrict__ partials_prev,
+                                                       double* __restrict__ log,
+                                                       RestartState* __restrict__ state) {
+    using T = typename Prec<PREC>::T;
+    using M = Mfma<PREC>;
+    constexpr int ROWS = kTileM + BN;          // staged rows: J, then restarts
+    constexpr int TN = BN / 64;                // 32-column blocks per wavefront
+    constexpr int kSrow = SB + 16;             // LDS row pitch: 16-row groups hit distinct banks
+    constexpr int CPR = SB / 16;               // 16-byte chunks per row per stage
+    constexpr int RPU = MT / CPR;              // rows one load instruction of the workgroup covers
+    constexpr int LJ = kTileM / RPU, LU = BN / RPU;   // 16-byte loads per thread per stage
+    constexpr int FB = M::kBytes / 2;          // fragment bytes per lane
+    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * kSrow];
+
+    // tile of this workgroup: consecutive logical tiles share an XCD (round-
+    // robin dispatch), so the column tiles of one (row tile, split) -- which
+    // read the same slab of J -- meet in one L2
+    const int tn = Rp / BN;
+    const int G = (np / kTileM) * tn * S;
+    const int b = blockIdx.x;
+    // the Rp / 64 workgroups after the product tiles close the previous
+    // iteration, whose partial sums the previous update wrote; with stages
+    // of 128 bytes a workgroup takes little enough LDS for one of them to
+    // share a compute unit with a product tile
+    if (b >= G) {
+        if (k > 0)
+            lowp_close(partials_prev, np / 64, Rp, b - G, R, k - 1, alpha, beta, eps, log, state,
+                       reinterpret_cast<double(*)[4]>(lds));
+        return;
+    }
+    int L = (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
+    const int nt = L % tn;
+    L /= tn;
+    const int s = L % S;
+    const int mt = L / S;
+    const int row0 = mt * kTileM, col0 = nt * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+
+    // a tile whose restarts have all stopped is not needed
+    const int cc = col0 + tid;
+    const bool live = tid < BN && cc < R && !state[cc].done;
+    if (!__syncthreads_or(live)) return;
+
+    const uint32_t rowb = static_cast<uint32_t>(np) * sizeof(T);   // bytes per row of J and of the copy
+    const uint32_t kw = rowb / S;                                    // k bytes of this split
+    const int nst = static_cast<int>(kw / SB);
+    const __amdgpu_buffer_rsrc_t rJ =
+        slab_rsrc(reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * rowb + static_cast<size_t>(s) * kw,
+                  kTileM * rowb);
+    const __amdgpu_buffer_rsrc_t rU =
+        slab_rsrc(reinterpret_cast<const char*>(Ub) + static_cast<size_t>(col0) * rowb + static_cast<size_t>(s) * kw,
+                  BN * rowb);
+    // chunk (row RPU u + tid / CPR, bytes 16 (tid % CPR)) of a stage: CPR
+    // lanes read one row's stage as whole cache lines
+    const uint32_t voff = (tid / CPR) * rowb + (tid % CPR) * 16;
+    const int soff = (tid / CPR) * kSrow + (tid % CPR) * 16;
+    i32x4 ring[DEPTH][LJ + LU];
+    auto fetch = [&](i32x4 (&r)[LJ + LU], int st) {
+        const uint32_t o = voff + static_cast<uint32_t>(st) * SB;
+#pragma unroll
+        for (int u = 0; u < LJ; ++u) r[u] = __builtin_amdgcn_raw_buffer_load_b128(rJ, o, u * RPU * rowb, 0);
+#pragma unroll
+        for (int u = 0; u < LU; ++u) r[LJ + u] = __builtin_amdgcn_raw_buffer_load_b128(rU, o, u * RPU * rowb, 0);
+    };
+    // every split holds at least DEPTH stages (lowp_shape_valid)
+#pragma unroll
+    for (int p = 0; p < DEPTH; ++p) fetch(ring[p], p);
+
+    f32x16 acc[2][TN];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x16{};
+    const int fa = (wr * 64 + (lane & 31)) * kSrow + (lane >> 5) * FB;
+    const int fb = (kTileM + wc * (BN / 2) + (lane & 31)) * kSrow + (lane >> 5) * FB;
+    // stage st: its registers to LDS buffer st % 2, the refetch DEPTH stages
+    // ahead into the same registers, one barrier, the MFMA steps
+    auto stage = [&](i32x4 (&r)[LJ + LU], int st, bool refetch) {
+        char* buf = lds + (st & 1) * ROWS * kSrow;
+#pragma unroll
+        for (int u = 0; u < LJ + LU; ++u) *reinterpret_cast<i32x4*>(buf + soff + u * RPU * kSrow) = r[u];
+        if (refetch) fetch(r, st + DEPTH);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < SB / M::kBytes; ++ks) {
+            typename M::frag a[2], bb[TN];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = M::load(buf + fa + i * 32 * kSrow + ks * M::kBytes);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bb[j] = M::load(buf + fb + j * 32 * kSrow + ks * M::kBytes);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = M::step(a[i], bb[j], acc[i][j]);
+        }
+    };
+    // steady state: every stage refetches, so the loads of the next DEPTH - 1
+    // stages stay in flight across each wait; the last stages (at most
+    // 2 DEPTH - 1) follow with the refetch where one is left
+    int s0 = 0;
+    for (; s0 + 2 * DEPTH <= nst; s0 += DEPTH) {
+#pragma unroll
+        for (int p = 0; p < DEPTH; ++p) stage(ring[p], s0 + p, true);
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * DEPTH - 1; ++q) {
+        const int st = s0 + q;
+        if (st < nst) stage(ring[q % DEPTH], st, st + DEPTH < nst);
+    }
+    // lane holds column l % 32 and rows 8 (v / 4) + 4 (l / 32) + v % 4 of
+    // each 32 x 32 block
+    float* Ps = P + static_cast<size_t>(s) * np * Rp;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = row0 + wr * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int c = col0 + wc * (BN / 2) + j * 32 + (lane & 31);
+                Ps[static_cast<size_t>(r) * Rp + c] = acc[i][j][v];
+            }
+}
+
+
+#define DOCH_LOWP_GEMM_PARAMS                                                                              \
+    int np, int Rp, int S, int R, const typename Prec<PREC>::T *__restrict__ Jq,                          \
+        const typename Prec<PREC>::T *__restrict__ Ub, float *__restrict__ P, int64_t k, double alpha,    \
+        double beta, double eps, const double *__restrict__ partials_prev, double *__restrict__ log,      \
+        RestartState *__restrict__ state
+#define DOCH_LOWP_GEMM_ARGS np, Rp, S, R, Jq, Ub, P, k, alpha, beta, eps, partials_prev, log, state
+
+// 256-byte stages: one workgroup per compute unit, registers unconstrained
+template <int PREC, int BN, int DEPTH>
+__global__ __launch_bounds__(MT) void lowp_gemm_kernel(DOCH_LOWP_GEMM_PARAMS) {
+    lowp_gemm_tile<PREC, BN, 256, DEPTH>(DOCH_LOWP_GEMM_ARGS);
+}
+
+// 128-byte stages: registers kept to two wavefronts per SIMD, so a second
+// workgroup (a closing one, or a product tile when there are more tiles
+// than compute units) fits beside each product tile
+template <int PREC, int BN, int DEPTH>
+__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_gemm2_kernel(
+    DOCH_LOWP_GEMM_PARAMS) {
+    lowp_gemm_tile<PREC, BN, 128, DEPTH>(DOCH_LOWP_GEMM_ARGS);
+}
+#undef DOCH_LOWP_GEMM_PARAMS
+#undef DOCH_LOWP_GEMM_ARGS
+
+// ---- the fused iteration: one 64 x 64 tile per workgroup, whole k range --
+//
+// The product and the update in one launch, with no partial tiles in
+// memory: a workgroup owns 64 rows x 64 restarts; each of its four
+// wavefronts accumulates the whole tile as 2 x 2 independent 32 x 32 MFMA
+// blocks over every fourth MFMA step of each 256-byte stage, the four
+// partial tiles meet in LDS (wavefront w keeps sub-tile w, summed over the
+// wavefronts in order), and the epilogue is the update's.  The extra row of
+// workgroups (dispatched after every row tile) closes the previous
+// iteration: workgroup x of it for column block x.  Registers are capped at
+// two wavefronts per SIMD so that these closing workgroups find room beside
+// the tiles at once instead of waiting for the first tile to finish.  They
+// may run beside the tiles that read the same restart states; a restart
+// they stop is then updated once more into the buffer after its last
+// iterate, which stays where iters_done says.
 template <int PREC, int DEPTH>
-__global__ __launch_bounds__(MT) void lowp_step_kernel(
+__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_fused_kernel(
     int np, int Rp, const typename Prec<PREC>::T* __restrict__ Jq, const float* __restrict__ rscale,
     const float* __restrict__ U_old, float* __restrict__ U_new,
     const typename Prec<PREC>::T* __restrict__ Ub_old, typename Prec<PREC>::T* __restrict__ Ub_new,
@@ -155,17 +349,17 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     double alpha, double beta, double eps, int R, int64_t k, const double* __restrict__ partials_prev,
     double* __restrict__ partials, double* __restrict__ log, RestartState* __restrict__ state) {
     using T = typename Prec<PREC>::T;
+    using M = Mfma<PREC>;
+    constexpr int SB = 256;                     // k bytes per row per stage
+    constexpr int SROW = SB + 16;               // LDS row pitch
+    constexpr int FB = M::kBytes / 2;           // fragment bytes per lane
     // two stage buffers (J rows, then restart rows; 64 rows of SROW bytes
     // each), reused for the four wavefronts' partial tiles ([wave][sub-tile]
     // [v][lane] floats) and then for the transposed low-precision copy
-    constexpr int SROW = 272;                   // 256 bytes of k plus 16 of pad
     constexpr int SBYTES = 2 * 2 * 64 * SROW > 4 * 4 * 16 * 64 * 4 ? 2 * 2 * 64 * SROW : 4 * 4 * 16 * 64 * 4;
     __shared__ __attribute__((aligned(16))) char sstage[SBYTES];
     __shared__ double red[2][64][4];
     __shared__ int sdead[64];
-    // the extra row of workgroups (dispatched after every row tile, so each
-    // lands beside a row tile on a CU of its own) closes the previous
-    // iteration: workgroup x of it for column block x
     const int tiles = np / 64;
     if (static_cast<int>(blockIdx.y) == Rp / 64) {
         if (k > 0 && static_cast<int>(blockIdx.x) < Rp / 64)
@@ -174,7 +368,6 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     }
     if (static_cast<int>(blockIdx.x) >= tiles) return;     // grid padded to the closing row's width
     float* const sred = reinterpret_cast<float*>(sstage);
-    char* const sA0 = sstage;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -190,37 +383,30 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     const int j = col0 + jl;
     const int done_m = (tid < 64 && mycol < R) ? state[mycol].done : 1;
     const int done_j = j < R ? state[j].done : 1;
-    // stage st: bytes [256 st, 256 st + 256) of each of the 64 rows of J and
-    // of the restart copy; thread loads 16-byte chunks c = tid + 256 u (row
-    // c / 16, chunk c % 16), so 16 consecutive lanes read a row's two whole
+    // stage st: bytes [SB st, SB st + SB) of each of the 64 rows of J and of
+    // the restart copy; thread loads 16-byte chunks (row 16 u + tid / 16,
+    // bytes 16 (tid % 16)), so 16 consecutive lanes read a row's two whole
     // cache lines
-    constexpr int SPR = 256;                // bytes per row per stage
-    constexpr int KPS = SPR / static_cast<int>(sizeof(T));   // k per stage
-    const char* gA = reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * np * sizeof(T);
-    const char* gB = reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * np * sizeof(T);
-    const size_t gstride = static_cast<size_t>(np) * sizeof(T);
-    size_t goff[4];
-    int soff[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int c = tid + MT * u;
-        goff[u] = (c >> 4) * gstride + (c & 15) * 16;
-        soff[u] = (c >> 4) * SROW + (c & 15) * 16;
-    }
-    // DEPTH stages in flight per thread (registers), two LDS buffers
+    const uint32_t rowb = static_cast<uint32_t>(np) * sizeof(T);
+    const __amdgpu_buffer_rsrc_t rJ =
+        slab_rsrc(reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * rowb, 64 * rowb);
+    const __amdgpu_buffer_rsrc_t rU =
+        slab_rsrc(reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * rowb, 64 * rowb);
+    const uint32_t voff = (tid >> 4) * rowb + (tid & 15) * 16;
+    const int soff = (tid >> 4) * SROW + (tid & 15) * 16;
     i32x4 ring[DEPTH][8];
     auto fetch = [&](i32x4 (&r)[8], int st) {
-        const size_t kb = static_cast<size_t>(st) * SPR;
+        const uint32_t o = voff + static_cast<uint32_t>(st) * SB;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            r[u] = *reinterpret_cast<const i32x4*>(gA + goff[u] + kb);
-            r[4 + u] = *reinterpret_cast<const i32x4*>(gB + goff[u] + kb);
+            r[u] = __builtin_amdgcn_raw_buffer_load_b128(rJ, o, u * 16 * rowb, 0);
+            r[4 + u] = __builtin_amdgcn_raw_buffer_load_b128(rU, o, u * 16 * rowb, 0);
         }
     };
-    const int nst = np / KPS;
+    const int nst = static_cast<int>(rowb / SB);
+    // every row holds at least DEPTH stages (lowp_shape_valid)
 #pragma unroll
-    for (int p = 0; p < DEPTH; ++p)
-        if (p < nst) fetch(ring[p], p);
+    for (int p = 0; p < DEPTH; ++p) fetch(ring[p], p);
     float uo_pre[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -238,37 +424,41 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
     if (block_live) {
-        // this wavefront's k-steps of a stage: wave, wave + 4, ... (16 k each)
-        const int khalf = (lane >> 5) * 8;
-        for (int s0 = 0; s0 < nst; s0 += DEPTH) {
+        const int fo = (lane & 31) * SROW + (lane >> 5) * FB;
+        // stage st: registers to LDS buffer st % 2, the refetch DEPTH stages
+        // ahead, one barrier, this wavefront's MFMA steps (wave, wave + 4, ...)
+        auto stage = [&](i32x4 (&r)[8], int st, bool refetch) {
+            char* A = sstage + (st & 1) * 2 * 64 * SROW;
+            char* B = A + 64 * SROW;
 #pragma unroll
-            for (int p = 0; p < DEPTH; ++p) {
-                const int st = s0 + p;
-                if (st < nst) {
-                    char* A = sstage + (st & 1) * 2 * 64 * SROW;
-                    char* B = A + 64 * SROW;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        *reinterpret_cast<i32x4*>(A + soff[u]) = ring[p][u];
-                        *reinterpret_cast<i32x4*>(B + soff[u]) = ring[p][4 + u];
-                    }
-                    if (st + DEPTH < nst) fetch(ring[p], st + DEPTH);
-                    __syncthreads();
-#pragma unroll
-                    for (int ks = wave; ks < KPS / 16; ks += 4) {
-                        const int kb = (ks * 16 + khalf) * static_cast<int>(sizeof(T));
-                        using F = typename Frag<PREC>::type;
-                        const F a0 = *reinterpret_cast<const F*>(A + (lane & 31) * SROW + kb);
-                        const F a1 = *reinterpret_cast<const F*>(A + (32 + (lane & 31)) * SROW + kb);
-                        const F b0 = *reinterpret_cast<const F*>(B + (lane & 31) * SROW + kb);
-                        const F b1 = *reinterpret_cast<const F*>(B + (32 + (lane & 31)) * SROW + kb);
-                        acc[0][0] = mfma_frag<PREC>(a0, b0, acc[0][0]);
-                        acc[0][1] = mfma_frag<PREC>(a0, b1, acc[0][1]);
-                        acc[1][0] = mfma_frag<PREC>(a1, b0, acc[1][0]);
-                        acc[1][1] = mfma_frag<PREC>(a1, b1, acc[1][1]);
-                    }
-                }
+            for (int u = 0; u < 4; ++u) {
+                *reinterpret_cast<i32x4*>(A + soff + u * 16 * SROW) = r[u];
+                *reinterpret_cast<i32x4*>(B + soff + u * 16 * SROW) = r[4 + u];
             }
+            if (refetch) fetch(r, st + DEPTH);
+            __syncthreads();
+#pragma unroll
+            for (int ks = wave; ks < SB / M::kBytes; ks += 4) {
+                const int kb = ks * M::kBytes;
+                const auto a0 = M::load(A + fo + kb);
+                const auto a1 = M::load(A + 32 * SROW + fo + kb);
+                const auto b0 = M::load(B + fo + kb);
+                const auto b1 = M::load(B + 32 * SROW + fo + kb);
+                acc[0][0] = M::step(a0, b0, acc[0][0]);
+                acc[0][1] = M::step(a0, b1, acc[0][1]);
+                acc[1][0] = M::step(a1, b0, acc[1][0]);
+                acc[1][1] = M::step(a1, b1, acc[1][1]);
+            }
+        };
+        int s0 = 0;
+        for (; s0 + 2 * DEPTH <= nst; s0 += DEPTH) {
+#pragma unroll
+            for (int p = 0; p < DEPTH; ++p) stage(ring[p], s0 + p, true);
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * DEPTH - 1; ++q) {
+            const int st = s0 + q;
+            if (st < nst) stage(ring[q % DEPTH], st, st + DEPTH < nst);
         }
     }
     __syncthreads();                            // the stage buffers are reused below
@@ -301,7 +491,7 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         if (blockIdx.x == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
     }
     // transposed low-precision tile: row jl holds rows row0 .. row0+63 of restart j
-    T* tileT = reinterpret_cast<T*>(sA0);
+    T* tileT = reinterpret_cast<T*>(sstage);
     constexpr int TROW = 64 + 16 / static_cast<int>(sizeof(T));   // padded row, in elements
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -311,19 +501,21 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
         const double uo = static_cast<double>(uo_pre[v]);
         double z = static_cast<double>(tile[v]);
         if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
-        float un = static_cast<float>(uo);
+        float un = uo_pre[v];
         if (live) {
-            un = static_cast<float>(cbrt(dadd(z, dmul(alpha, uo))));
+            // the argument in FP64, its cube root in FP32: the result is
+            // stored in FP32 either way
+            un = cbrtf(static_cast<float>(dadd(z, dmul(alpha, uo))));
             const double d = dsub(static_cast<double>(un), uo);
             const double u2 = dmul(uo, uo);
             part[0] = dadd(part[0], dmul(u2, u2));
             part[1] = dadd(part[1], u2);
             part[2] = dadd(part[2], dmul(uo, z));
             part[3] = dadd(part[3], dmul(d, d));
+            // a stopped restart is never written again: its last iterate
+            // stays in the buffer the next iteration would otherwise overwrite
+            U_new[ij] = un;
         }
-        // a stopped restart is never written again: its last iterate stays
-        // in the buffer the next iteration would otherwise overwrite
-        if (live) U_new[ij] = un;
         tileT[jl * TROW + il] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
     }
     // rows of a column: lanes l and l + 32, then the two row halves of the tile
@@ -354,7 +546,102 @@ __global__ __launch_bounds__(MT) void lowp_step_kernel(
     }
 }
 
-// The last iteration's closing, after the final step launch.
+// ---- the update: sum of the splits, eq:FPE in u, partial sums ----------
+//
+// 64 rows x 64 restarts per workgroup: lane l of wavefront w holds restart
+// column l and rows 16 w .. 16 w + 15, so every load and store of a row
+// covers 64 consecutive restarts.  The update of each entry (its argument
+// z + alpha u in FP64, the cube root in FP32, the precision it is stored
+// in), the FP32 master store and the low-precision copy (transposed through
+// LDS and written in whole rows), then the restart's FP64 partial sums of
+// the row tile, which the next product launch closes.  Nothing waits on the
+// restart states: the loads of the iterate and of the S partial tiles are
+// issued with them, and a stopped restart only discards what it loaded.
+template <int PREC, int S>
+__global__ __launch_bounds__(MT) void lowp_update_kernel(
+    int np, int Rp, const float* __restrict__ P, const float* __restrict__ rscale,
+    const float* __restrict__ U_old, float* __restrict__ U_new, typename Prec<PREC>::T* __restrict__ Ub_new,
+    const float* __restrict__ cs_old, float* __restrict__ cs_new, double rho_q, double alpha,
+    int R, double* __restrict__ partials, const RestartState* __restrict__ state) {
+    using T = typename Prec<PREC>::T;
+    constexpr int TROW = 64 + 16 / static_cast<int>(sizeof(T));   // padded row of the transposed copy
+    __shared__ __attribute__((aligned(16))) T tileT[64 * TROW];
+    __shared__ double red[4][64][4];
+    __shared__ int sdead[64];
+    const int tid = threadIdx.x;
+    const int jl = tid & 63, rg = tid >> 6;
+    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    const int j = col0 + jl;
+    const int i0 = row0 + rg * 16;
+    float uo[16], zs[S][16];
+    const size_t base = static_cast<size_t>(i0) * Rp + j;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) uo[v] = U_old[base + static_cast<size_t>(v) * Rp];
+#pragma unroll
+    for (int sp = 0; sp < S; ++sp)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) zs[sp][v] = P[static_cast<size_t>(sp) * np * Rp + base + static_cast<size_t>(v) * Rp];
+    const int dead = j < R ? state[j].done : 1;
+    if (tid < 64) sdead[tid] = dead;
+    const bool live = !dead;
+    // FP8: scale of the copy read by this product and of the one written now
+    float c_in = 1.0f, c_out = 1.0f;
+    if constexpr (PREC == 1) {
+        c_in = cs_old[j];
+        c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
+        if (blockIdx.x == 0 && rg == 0) cs_new[j] = c_out;
+    }
+    double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = i0 + v;
+        float z32 = zs[0][v];
+#pragma unroll
+        for (int sp = 1; sp < S; ++sp) z32 += zs[sp][v];
+        const double u = static_cast<double>(uo[v]);
+        double z = static_cast<double>(z32);
+        if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
+        float un = uo[v];
+        if (live) {
+            // the argument in FP64, its cube root in FP32: the result is
+            // stored in FP32 either way
+            un = cbrtf(static_cast<float>(dadd(z, dmul(alpha, u))));
+            const double d = dsub(static_cast<double>(un), u);
+            const double u2 = dmul(u, u);
+            part[0] = dadd(part[0], dmul(u2, u2));
+            part[1] = dadd(part[1], u2);
+            part[2] = dadd(part[2], dmul(u, z));
+            part[3] = dadd(part[3], dmul(d, d));
+            // a stopped restart is never written again: its last iterate
+            // stays in the buffer the next iteration would otherwise overwrite
+            U_new[base + static_cast<size_t>(v) * Rp] = un;
+        }
+        tileT[jl * TROW + rg * 16 + v] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[rg][jl][q] = part[q];
+    __syncthreads();
+    {
+        // 64 restart rows of 64 * sizeof(T) bytes, in 16-byte chunks
+        constexpr int CPR = 64 * static_cast<int>(sizeof(T)) / 16;
+        for (int c = tid; c < 64 * CPR; c += MT) {
+            const int r = c / CPR, ch = c % CPR;
+            if (sdead[r]) continue;
+            const i32x4 v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(tileT + r * TROW) + ch * 16);
+            *reinterpret_cast<i32x4*>(reinterpret_cast<char*>(Ub_new + static_cast<size_t>(col0 + r) * np + row0) +
+                                      ch * 16) = v;
+        }
+    }
+    // this row tile's partial sums (row groups in order)
+    if (tid < 64) {
+        double* p = partials + (static_cast<size_t>(blockIdx.x) * Rp + col0 + tid) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            p[q] = dadd(dadd(dadd(red[0][tid][q], red[1][tid][q]), red[2][tid][q]), red[3][tid][q]);
+    }
+}
+
+// The last iteration's closing, after the final update.
 __global__ __launch_bounds__(MT) void lowp_close_kernel(const double* __restrict__ P, int tiles, int Rp, int R,
                                                         int64_t kk, double alpha, double beta, double eps,
                                                         double* __restrict__ log, RestartState* __restrict__ state) {
@@ -601,26 +888,142 @@ hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, in
     return hipGetLastError();
 }
 
-hipError_t launch_lowp_step(int prec, int np, int Rp, const void* Jq, const float* rscale,
-                            const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
-                            const float* cs_old, float* cs_new, double rho_q,
-                            double alpha, double beta, double eps, int R, int64_t k,
-                            const double* partials_prev, double* partials, double* log, RestartState* state,
-                            hipStream_t s) {
-    // np / 64 row tiles per column block, and one more row of workgroups
-    // whose first Rp / 64 close the previous iteration
-    const int tiles = np / 64, cblocks = Rp / 64;
-    const dim3 grid(tiles > cblocks ? tiles : cblocks, cblocks + 1);
-    if (prec == 0)
-        hipLaunchKernelGGL((lowp_step_kernel<0, kLowpDepth>), grid, dim3(MT), 0, s, np, Rp,
-                           static_cast<const __bf16*>(Jq), rscale, U_old, U_new,
-                           static_cast<const __bf16*>(Ub_old), static_cast<__bf16*>(Ub_new), cs_old,
-                           cs_new, rho_q, alpha, beta, eps, R, k, partials_prev, partials, log, state);
+bool lowp_shape_valid(int prec, int np, int Rp, const LowpShape& sh) {
+    // the fused iteration: 64 x 64 tiles, 256-byte stages, depth 3 in BF16
+    // only (FP8 fragments leave no registers for a third stage under the
+    // two-wavefront cap)
+    if (sh.splits == 0)
+        return sh.bn == 64 && sh.sb == 256 && (sh.depth == 2 || (sh.depth == 3 && prec == 0)) && Rp % 64 == 0 &&
+               np % 64 == 0 && np * (prec == 0 ? 2 : 1) / 256 >= sh.depth;
+    if (sh.bn != 64 && sh.bn != 128) return false;
+    if (sh.sb != 128 && sh.sb != 256) return false;
+    if (sh.depth != 2 && sh.depth != 3) return false;
+    if (sh.splits != 1 && sh.splits != 2 && sh.splits != 4 && sh.splits != 8) return false;
+    const int stages = np * (prec == 0 ? 2 : 1) / sh.sb;   // stages per row
+    return Rp % sh.bn == 0 && np % kTileM == 0 && stages % sh.splits == 0 && stages / sh.splits >= sh.depth;
+}
+
+LowpShape lowp_default_shape(int prec, int np, int Rp, int cus) {
+    // the fused iteration: no partial tiles in memory, one launch per
+    // iteration (depth 3 where the padded order holds three stages in BF16)
+    (void)cus;
+    LowpShape sh;
+    sh.bn = 64;
+    sh.splits = 0;
+    sh.sb = 256;
+    sh.depth = 3;
+    if (!lowp_shape_valid(prec, np, Rp, sh)) sh.depth = 2;
+    return sh;
+}
+
+size_t lowp_product_bytes(int np, int Rp, const LowpShape& sh) {
+    return static_cast<size_t>(sh.splits) * np * Rp * sizeof(float);
+}
+
+namespace {
+
+struct CloseArgs {
+    int64_t k;
+    double alpha, beta, eps;
+    const double* partials_prev;
+    double* log;
+    RestartState* state;
+};
+
+template <int PREC, int BN, int SB, int DEPTH>
+void launch_gemm_one(dim3 g, hipStream_t s, int np, int Rp, int S, int R, const void* Jq, const void* Ub, float* P,
+                     const CloseArgs& c) {
+    using T = typename Prec<PREC>::T;
+    if constexpr (SB == 256)
+        hipLaunchKernelGGL((lowp_gemm_kernel<PREC, BN, DEPTH>), g, dim3(MT), 0, s, np, Rp, S, R,
+                           static_cast<const T*>(Jq), static_cast<const T*>(Ub), P, c.k, c.alpha, c.beta, c.eps,
+                           c.partials_prev, c.log, c.state);
     else
-        hipLaunchKernelGGL((lowp_step_kernel<1, kLowpDepth>), grid, dim3(MT), 0, s, np, Rp,
-                           static_cast<const uint8_t*>(Jq), rscale, U_old, U_new,
-                           static_cast<const uint8_t*>(Ub_old), static_cast<uint8_t*>(Ub_new), cs_old,
-                           cs_new, rho_q, alpha, beta, eps, R, k, partials_prev, partials, log, state);
+        hipLaunchKernelGGL((lowp_gemm2_kernel<PREC, BN, DEPTH>), g, dim3(MT), 0, s, np, Rp, S, R,
+                           static_cast<const T*>(Jq), static_cast<const T*>(Ub), P, c.k, c.alpha, c.beta, c.eps,
+                           c.partials_prev, c.log, c.state);
+}
+
+template <int PREC>
+void launch_gemm(const LowpShape& sh, dim3 g, hipStream_t s, int np, int Rp, int R, const void* Jq,
+                 const void* Ub, float* P, const CloseArgs& c) {
+    const int key = (sh.bn == 128 ? 4 : 0) + (sh.sb == 256 ? 2 : 0) + (sh.depth == 3 ? 1 : 0);
+    switch (key) {
+        case 0: launch_gemm_one<PREC, 64, 128, 2>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        case 1: launch_gemm_one<PREC, 64, 128, 3>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        case 2: launch_gemm_one<PREC, 64, 256, 2>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        case 3: launch_gemm_one<PREC, 64, 256, 3>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        case 4: launch_gemm_one<PREC, 128, 128, 2>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        case 5: launch_gemm_one<PREC, 128, 128, 3>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        case 6: launch_gemm_one<PREC, 128, 256, 2>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+        default: launch_gemm_one<PREC, 128, 256, 3>(g, s, np, Rp, sh.splits, R, Jq, Ub, P, c); break;
+    }
+}
+
+template <int PREC, int S>
+void launch_update_one(dim3 g, hipStream_t s, int np, int Rp, const float* P, const float* rscale,
+                       const float* U_old, float* U_new, void* Ub_new, const float* cs_old, float* cs_new,
+                       double rho_q, double alpha, int R, double* partials, const RestartState* state) {
+    using T = typename Prec<PREC>::T;
+    hipLaunchKernelGGL((lowp_update_kernel<PREC, S>), g, dim3(MT), 0, s, np, Rp, P, rscale, U_old, U_new,
+                       static_cast<T*>(Ub_new), cs_old, cs_new, rho_q, alpha, R, partials, state);
+}
+
+template <int PREC>
+void launch_update(int S, dim3 g, hipStream_t s, int np, int Rp, const float* P, const float* rscale,
+                   const float* U_old, float* U_new, void* Ub_new, const float* cs_old, float* cs_new,
+                   double rho_q, double alpha, int R, double* partials, const RestartState* state) {
+#define DOCH_LOWP_UPDATE(SS)                                                                                 \
+    launch_update_one<PREC, SS>(g, s, np, Rp, P, rscale, U_old, U_new, Ub_new, cs_old, cs_new, rho_q, alpha, \
+                                R, partials, state)
+    switch (S) {
+        case 1: DOCH_LOWP_UPDATE(1); break;
+        case 2: DOCH_LOWP_UPDATE(2); break;
+        case 4: DOCH_LOWP_UPDATE(4); break;
+        default: DOCH_LOWP_UPDATE(8); break;
+    }
+#undef DOCH_LOWP_UPDATE
+}
+
+}  // namespace
+
+hipError_t launch_lowp_step(int prec, int np, int Rp, const LowpShape& sh, const void* Jq, const float* rscale,
+                            const float* U_old, float* U_new, const void* Ub_old, void* Ub_new,
+                            const float* cs_old, float* cs_new, double rho_q, double alpha, double beta,
+                            double eps, int R, int64_t k, float* P, const double* partials_prev,
+                            double* partials, double* log, RestartState* state, hipStream_t s) {
+    if (!lowp_shape_valid(prec, np, Rp, sh)) return hipErrorInvalidValue;
+    if (sh.splits == 0) {
+        // np / 64 row tiles per column block, and one more row of workgroups
+        // whose first Rp / 64 close the previous iteration
+        const int tiles = np / 64, cblocks = Rp / 64;
+        const dim3 grid(tiles > cblocks ? tiles : cblocks, cblocks + 1);
+#define DOCH_LOWP_FUSED(PP, DD)                                                                                 \
+    hipLaunchKernelGGL((lowp_fused_kernel<PP, DD>), grid, dim3(MT), 0, s, np, Rp,                              \
+                       static_cast<const Prec<PP>::T*>(Jq), rscale, U_old, U_new,                              \
+                       static_cast<const Prec<PP>::T*>(Ub_old), static_cast<Prec<PP>::T*>(Ub_new), cs_old,    \
+                       cs_new, rho_q, alpha, beta, eps, R, k, partials_prev, partials, log, state)
+        if (prec == 0) {
+            if (sh.depth == 3) DOCH_LOWP_FUSED(0, 3); else DOCH_LOWP_FUSED(0, 2);
+        } else {
+            DOCH_LOWP_FUSED(1, 2);
+        }
+#undef DOCH_LOWP_FUSED
+        return hipGetLastError();
+    }
+    // the product tiles, then Rp / 64 workgroups closing iteration k - 1
+    const dim3 pg((np / kTileM) * (Rp / sh.bn) * sh.splits + Rp / 64);
+    const dim3 ug(np / 64, Rp / 64);
+    const CloseArgs c{k, alpha, beta, eps, partials_prev, log, state};
+    if (prec == 0) {
+        launch_gemm<0>(sh, pg, s, np, Rp, R, Jq, Ub_old, P, c);
+        launch_update<0>(sh.splits, ug, s, np, Rp, P, rscale, U_old, U_new, Ub_new, cs_old, cs_new, rho_q, alpha, R,
+                         partials, state);
+    } else {
+        launch_gemm<1>(sh, pg, s, np, Rp, R, Jq, Ub_old, P, c);
+        launch_update<1>(sh.splits, ug, s, np, Rp, P, rscale, U_old, U_new, Ub_new, cs_old, cs_new, rho_q, alpha, R,
+                         partials, state);
+    }
     return hipGetLastError();
 }
 

@@ -26,12 +26,14 @@ def dense_ctx(J):
     return L.ising_create_dense(J.shape[0], Jd, L.ISING_F64, J.shape[0]), Jd
 
 
-def run_lowp(J, X0, alpha, beta, iters, prec, eps=0.0):
+def run_lowp(J, X0, alpha, beta, iters, prec, eps=0.0, shape=None):
     import torch
     import paper_2509_01928_amd as L
     n, R = X0.shape
     ctx, keep = dense_ctx(J)
     try:
+        if shape is not None:
+            L.ising_set_lowp_shape(ctx, *shape)
         p = L.ising_params()
         p.alpha, p.beta, p.eps, p.algo, p.q, p.x_dtype, p.reserved = alpha, beta, eps, 0, 5, L.ISING_F64, 0
         xd = torch.from_numpy(np.ascontiguousarray(X0)).to("cuda:0")
@@ -67,8 +69,14 @@ def test_lowp_zero_coupling_closed_form(prec_name, n, R):
         np.testing.assert_array_equal(S, np.where(X >= 0, 1, -1))
 
 
+# (bn, splits, stage_bytes, depth): the fused iteration and a split product
+# that fits n = 512 with 32 restarts in both formats
+SHAPES = {"fused": (64, 0, 256, 2), "split": (64, 2, 128, 2)}
+
+
+@pytest.mark.parametrize("shape_name", ["fused", "split"])
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
-def test_lowp_energy_gap_and_final_objective(prec_name):
+def test_lowp_energy_gap_and_final_objective(prec_name, shape_name):
     """SK n = 512, 32 restarts.  H_final is eq:Hamilton of the returned
     iterate and the energies are those of its signs (exact checks).  A
     quantised run can settle in another local minimum than the FP64 run from
@@ -84,7 +92,7 @@ def test_lowp_energy_gap_and_final_objective(prec_name):
     alpha = -np.linalg.eigvalsh(J)[0]
     beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
     assert math.sqrt(beta) * np.abs(X0).max() > 448 * 4
-    X, S, Hf, E, st, Hlog = run_lowp(J, X0, alpha, beta, iters, prec)
+    X, S, Hf, E, st, Hlog = run_lowp(J, X0, alpha, beta, iters, prec, shape=SHAPES[shape_name])
     assert all(s.iters_done == iters and s.nonfinite == 0 for s in st)
     # final FP64 objective of the returned iterates (eq:Hamilton)
     H_np = beta / 4 * (X ** 4).sum(0) - alpha / 2 * (X ** 2).sum(0) - 0.5 * np.einsum("ir,ir->r", X, J @ X)
@@ -128,3 +136,74 @@ def test_lowp_freezes_converged_restarts(prec_name):
         assert np.array_equal(S[:, r], Sm[:, r])
         if r < 3:
             assert np.array_equal(Hlog[r], Hm[r])
+
+
+def lowp_shapes(prec_name, n, R):
+    """Every shape the library is built for that fits n x R (as ising_solve_lowp pads)."""
+    np_ = -(-n // (256 if prec_name == "bf16" else 512)) * (256 if prec_name == "bf16" else 512)
+    Rp = -(-R // 64) * 64
+    esz = 2 if prec_name == "bf16" else 1
+    out = [(64, 0, 256, 2)] + ([(64, 0, 256, 3)] if prec_name == "bf16" and np_ * esz // 256 >= 3 else [])
+    for bn in (128, 64):
+        for S in (1, 2, 4, 8):
+            for sb in (128, 256):
+                for d in (2, 3):
+                    stages = np_ * esz // sb
+                    if Rp % bn == 0 and stages % S == 0 and stages // S >= d:
+                        out.append((bn, S, sb, d))
+    return out
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
+def test_lowp_every_shape_same_step(prec_name):
+    """One iteration (SK n = 512, 128 restarts) under every shape that fits.
+    The shapes change only the order of the FP32 additions of the product
+    (k split across wavefronts, splits, stages), so w = z + alpha u, which
+    the cube root takes, differs at most by the order-independent bound
+    n 2^-24 sum_k |J_ik q_k| of FP32 summation (written with margin for the
+    quantised magnitudes); w is recovered as u'^3 up to the FP32 rounding of
+    u' and of the cube root.  Comparing u' itself would not do: the cube
+    root amplifies any difference in w where w is near zero."""
+    import paper_2509_01928_amd as L
+    prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
+    n, R = 512, 128
+    J = gen.sk_dense(n, 4006)
+    X0 = gen.uniform_x0(n, R, 5006)
+    alpha = -np.linalg.eigvalsh(J)[0]
+    beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    sb = math.sqrt(beta)
+    bound = 3 * n * 2.0 ** -24 * (np.abs(J) @ np.abs(sb * X0))
+    shapes = lowp_shapes(prec_name, n, R)
+    assert len(shapes) >= 8
+    W_ref = (sb * run_lowp(J, X0, alpha, beta, 1, prec, shape=shapes[0])[0]) ** 3
+    for sh in shapes[1:]:
+        W = (sb * run_lowp(J, X0, alpha, beta, 1, prec, shape=sh)[0]) ** 3
+        excess = np.abs(W - W_ref) - (bound + 8 * 2.0 ** -24 * np.abs(W_ref))
+        assert excess.max() <= 0.0, (sh, excess.max())
+
+
+def test_lowp_autotune_and_cache(tmp_path):
+    """The tuner picks one of the shapes that fit, stores it, and a second
+    call returns it from the cache; the solve then runs under that shape."""
+    import torch
+    import paper_2509_01928_amd as L
+    n, R = 512, 64
+    J = gen.sk_dense(n, 4007)
+    X0 = gen.uniform_x0(n, R, 5007)
+    ctx, keep = dense_ctx(J)
+    cache = str(tmp_path / "lowp_shapes.json")
+    try:
+        p, lam = L.ising_default_params(ctx, 1.0, 0)
+        xd = torch.from_numpy(np.ascontiguousarray(X0)).to("cuda:0")
+        for prec_name, prec in (("bf16", L.ISING_BF16), ("fp8", L.ISING_FP8_E4M3)):
+            shape, ms, cached = L.ising_autotune_lowp(ctx, xd, R, 10, p, prec, cache)
+            assert not cached and ms > 0.0
+            assert tuple(shape) in lowp_shapes(prec_name, n, R), shape
+            shape2, ms2, cached2 = L.ising_autotune_lowp(ctx, xd, R, 10, p, prec, cache)
+            assert cached2 and tuple(shape2) == tuple(shape) and ms2 == pytest.approx(ms, rel=1e-3)
+            st = L.ising_solve_lowp(ctx, xd, R, 20, p, prec)
+            assert all(s.iters_done == 20 and s.nonfinite == 0 for s in st)
+        text = open(cache).read()
+        assert text.count("lowp-v1|") == 2 and '"splits": ' in text
+    finally:
+        L.ising_destroy(ctx)
