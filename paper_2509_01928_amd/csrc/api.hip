@@ -1406,14 +1406,15 @@ ising_status ising_autotune_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R
     // candidates: the fused iteration, and the split product over tile
     // widths, splits, stage widths and depths, as far as they fit
     std::vector<doch::LowpShape> cand;
-    for (int d : {2, 3}) {
-        doch::LowpShape sh;
-        sh.bn = 64;
-        sh.splits = 0;
-        sh.sb = 256;
-        sh.depth = d;
-        if (doch::lowp_shape_valid(prec, np, Rp, sh)) cand.push_back(sh);
-    }
+    for (int mode : {-1, 0})
+        for (int d : {2, 3}) {
+            doch::LowpShape sh;
+            sh.bn = 64;
+            sh.splits = mode;
+            sh.sb = 256;
+            sh.depth = d;
+            if (doch::lowp_shape_valid(prec, np, Rp, sh)) cand.push_back(sh);
+        }
     for (int bn : {128, 64})
         for (int S : {1, 2, 4, 8})
             for (int sb : {128, 256})
@@ -1485,12 +1486,12 @@ ising_status ising_set_lowp_shape(ising_ctx* ctx, int32_t bn, int32_t splits, in
     // the values the library is built for; whether they fit a problem is
     // checked per call
     if (bn != 64 && bn != 128) return fail(ISING_E_INVALID_ARG, "bn must be 0, 64 or 128");
-    if (splits != 0 && splits != 1 && splits != 2 && splits != 4 && splits != 8)
-        return fail(ISING_E_INVALID_ARG, "splits must be 0, 1, 2, 4 or 8");
+    if (splits != -1 && splits != 0 && splits != 1 && splits != 2 && splits != 4 && splits != 8)
+        return fail(ISING_E_INVALID_ARG, "splits must be -1, 0, 1, 2, 4 or 8");
     if (stage_bytes != 128 && stage_bytes != 256) return fail(ISING_E_INVALID_ARG, "stage_bytes must be 128 or 256");
     if (depth != 2 && depth != 3) return fail(ISING_E_INVALID_ARG, "depth must be 2 or 3");
-    if (splits == 0 && (bn != 64 || stage_bytes != 256))
-        return fail(ISING_E_INVALID_ARG, "the fused iteration (splits 0) takes bn 64 and 256-byte stages");
+    if (splits <= 0 && (bn != 64 || stage_bytes != 256))
+        return fail(ISING_E_INVALID_ARG, "the fused iteration (splits 0 or -1) takes bn 64 and 256-byte stages");
     ctx->lp_shape = sh;
     return ISING_OK;
 }
@@ -1809,7 +1810,27 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         if (prec == 1)
             HIP_OK(hipMemcpyAsync(cs[b], cs[0], kMaxR * sizeof(float), hipMemcpyDeviceToDevice, s), "copy scales");
     }
-    for (int64_t k = 0; k < iters; ++k) {
+    bool resident_done = false;
+    if (shape.splits == -1 && iters > 0) {
+        // the whole run in one cooperative launch, or the same iteration a
+        // launch at a time when its grid does not fit on the device at once
+        if (!ctx->rsync) HIP_OK(dev_alloc(&ctx->rsync, sizeof(doch::ResidentSync)), "hipMalloc(sync)");
+        HIP_OK(doch::launch_resident_reset(ctx->rsync, s), "reset");
+        double* parts[2] = {ctx->lp_partials, ctx->lp_partials + pstride};
+        void* ubs[3] = {ctx->lp_ub[0], ctx->lp_ub[1], ctx->lp_ub[2]};
+        const hipError_t e = doch::launch_lowp_resident(prec, np, Rp, shape, iters, ctx->jq[prec], ctx->rscale,
+                                                        ctx->lp_u, ubs, cs, ctx->lp_rho_q, p.alpha, p.beta, p.eps, R,
+                                                        parts, ctx->log, ctx->state, ctx->rsync, s);
+        if (e == hipSuccess) {
+            resident_done = true;
+        } else if (e == hipErrorCooperativeLaunchTooLarge) {
+            (void)hipGetLastError();
+            shape.splits = 0;
+        } else {
+            return hip_fail(e, "resident low-precision run");
+        }
+    }
+    for (int64_t k = 0; !resident_done && k < iters; ++k) {
         const int a = static_cast<int>(k % 3), b = static_cast<int>((k + 1) % 3);
         double* pk = ctx->lp_partials + (k & 1) * pstride;
         const double* pprev = ctx->lp_partials + ((k + 1) & 1) * pstride;
@@ -1818,7 +1839,7 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
                                       p.eps, R, k, ctx->lp_P, pprev, pk, ctx->log, ctx->state, s),
                "low-precision step");
     }
-    if (iters > 0)
+    if (iters > 0 && !resident_done)
         HIP_OK(doch::launch_lowp_close(np, Rp, R, iters - 1, ctx->lp_partials + ((iters - 1) & 1) * pstride,
                                        p.alpha, p.beta, p.eps, ctx->log, ctx->state, s),
                "close last iteration");
@@ -1846,22 +1867,8 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         (void)hipStreamSynchronize(s);
         dev_free(xtmp);
     }
-    if (stats_host) {
-        std::vector<RestartState> hs(static_cast<size_t>(R));
-        HIP_OK(hipMemcpyAsync(hs.data(), ctx->state, R * sizeof(RestartState), hipMemcpyDeviceToHost, s), "copy state");
-        HIP_OK(hipStreamSynchronize(s), "sync");
-        bool bad = false;
-        for (int r = 0; r < R; ++r) {
-            stats_host[r].iters_done = hs[r].iters_done;
-            stats_host[r].converged = hs[r].converged;
-            stats_host[r].nonfinite = hs[r].nonfinite;
-            stats_host[r].H_last = hs[r].H_last;
-            stats_host[r].r_last = hs[r].r_last;
-            bad = bad || hs[r].nonfinite;
-        }
-        if (bad) return fail(ISING_E_NONFINITE, "H or r became non-finite");
-    }
-    return ISING_OK;
+    // a timed-out barrier wait of the resident run is reported here
+    return read_stats(ctx, R, stats_host, s);
 }
 
 ising_status ising_get_log(ising_ctx* ctx, int32_t restart, int64_t first, int64_t count,

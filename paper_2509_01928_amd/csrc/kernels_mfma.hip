@@ -327,53 +327,76 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
 
 // ---- the fused iteration: one 64 x 64 tile per workgroup, whole k range --
 //
-// The product and the update in one launch, with no partial tiles in
-// memory: a workgroup owns 64 rows x 64 restarts; each of its four
-// wavefronts accumulates the whole tile as 2 x 2 independent 32 x 32 MFMA
-// blocks over every fourth MFMA step of each 256-byte stage, the four
-// partial tiles meet in LDS (wavefront w keeps sub-tile w, summed over the
-// wavefronts in order), and the epilogue is the update's.  The extra row of
-// workgroups (dispatched after every row tile) closes the previous
-// iteration: workgroup x of it for column block x.  Registers are capped at
-// two wavefronts per SIMD so that these closing workgroups find room beside
-// the tiles at once instead of waiting for the first tile to finish.  They
-// may run beside the tiles that read the same restart states; a restart
-// they stop is then updated once more into the buffer after its last
-// iterate, which stays where iters_done says.
+// The product and the update with no partial tiles in memory: a workgroup
+// owns 64 rows x 64 restarts; each of its four wavefronts accumulates the
+// whole tile as 2 x 2 independent 32 x 32 MFMA blocks over every fourth MFMA
+// step of each 256-byte stage, the four partial tiles meet in LDS
+// (wavefront w keeps sub-tile w, summed over the wavefronts in order), and
+// the epilogue is the update's.  It runs either as one launch per iteration
+// (lowp_fused_kernel, whose extra row of workgroups closes the previous
+// iteration) or resident for the whole run (lowp_resident_kernel).  Both
+// cap registers at two wavefronts per SIMD, so that the closing workgroups
+// find room beside the tiles at once.
+
+constexpr int kFusedStage = 256;                      // k bytes per row per stage
+constexpr int kFusedSrow = kFusedStage + 16;          // LDS row pitch
+// two stage buffers (J rows, then restart rows; 64 rows each), reused for
+// the four wavefronts' partial tiles ([wave][sub-tile][v][lane] floats) and
+// then for the transposed low-precision copy
+constexpr int kFusedStageLds = 2 * 2 * 64 * kFusedSrow > 4 * 4 * 16 * 64 * 4 ? 2 * 2 * 64 * kFusedSrow
+                                                                               : 4 * 4 * 16 * 64 * 4;
+struct FusedLds {
+    __attribute__((aligned(16))) char stage[kFusedStageLds];
+    double red[2][64][4];
+    int dead[64];
+    int flag;
+};
+
+// The tile's slabs of J and of the restart copy, and the thread's chunk of
+// a stage: row 16 u + tid / 16, bytes 16 (tid % 16), so 16 consecutive
+// lanes read a row's stage as two whole cache lines.
+struct FusedSlab {
+    __amdgpu_buffer_rsrc_t rJ, rU;
+    uint32_t voff, rowb;
+    int soff, nst;
+};
+
+template <int DEPTH>
+__device__ __forceinline__ void fused_fetch_j(i32x4 (&r)[8], const FusedSlab& sl, int st) {
+    const uint32_t o = sl.voff + static_cast<uint32_t>(st) * kFusedStage;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[u] = __builtin_amdgcn_raw_buffer_load_b128(sl.rJ, o, u * 16 * sl.rowb, 0);
+}
+
+template <int DEPTH>
+__device__ __forceinline__ void fused_fetch_u(i32x4 (&r)[8], const FusedSlab& sl, int st) {
+    const uint32_t o = sl.voff + static_cast<uint32_t>(st) * kFusedStage;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[4 + u] = __builtin_amdgcn_raw_buffer_load_b128(sl.rU, o, u * 16 * sl.rowb, 0);
+}
+
+// One iteration of tile (row0, col0).  ring holds DEPTH stages in flight;
+// with j_ready the J halves of the first DEPTH stages are already in it
+// (the resident kernel requests them before its barrier: J does not change).
+// Its partial sums go to row tile `tx` of `partials`.
 template <int PREC, int DEPTH>
-__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_fused_kernel(
-    int np, int Rp, const typename Prec<PREC>::T* __restrict__ Jq, const float* __restrict__ rscale,
-    const float* __restrict__ U_old, float* __restrict__ U_new,
-    const typename Prec<PREC>::T* __restrict__ Ub_old, typename Prec<PREC>::T* __restrict__ Ub_new,
-    const float* __restrict__ cs_old, float* __restrict__ cs_new, double rho_q,
-    double alpha, double beta, double eps, int R, int64_t k, const double* __restrict__ partials_prev,
-    double* __restrict__ partials, double* __restrict__ log, RestartState* __restrict__ state) {
+__device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8], bool j_ready, const FusedSlab& sl,
+                                           int Rp, int row0, int col0, int tx, const float* __restrict__ rscale,
+                                           const float* __restrict__ U_old, float* __restrict__ U_new,
+                                           typename Prec<PREC>::T* __restrict__ Ub_new,
+                                           const float* __restrict__ cs_old, float* __restrict__ cs_new,
+                                           double rho_q, double alpha, int R, double* __restrict__ partials,
+                                           const RestartState* __restrict__ state) {
     using T = typename Prec<PREC>::T;
     using M = Mfma<PREC>;
-    constexpr int SB = 256;                     // k bytes per row per stage
-    constexpr int SROW = SB + 16;               // LDS row pitch
+    constexpr int SROW = kFusedSrow;
     constexpr int FB = M::kBytes / 2;           // fragment bytes per lane
-    // two stage buffers (J rows, then restart rows; 64 rows of SROW bytes
-    // each), reused for the four wavefronts' partial tiles ([wave][sub-tile]
-    // [v][lane] floats) and then for the transposed low-precision copy
-    constexpr int SBYTES = 2 * 2 * 64 * SROW > 4 * 4 * 16 * 64 * 4 ? 2 * 2 * 64 * SROW : 4 * 4 * 16 * 64 * 4;
-    __shared__ __attribute__((aligned(16))) char sstage[SBYTES];
-    __shared__ double red[2][64][4];
-    __shared__ int sdead[64];
-    const int tiles = np / 64;
-    if (static_cast<int>(blockIdx.y) == Rp / 64) {
-        if (k > 0 && static_cast<int>(blockIdx.x) < Rp / 64)
-            lowp_close(partials_prev, tiles, Rp, blockIdx.x, R, k - 1, alpha, beta, eps, log, state, red[0]);
-        return;
-    }
-    if (static_cast<int>(blockIdx.x) >= tiles) return;     // grid padded to the closing row's width
-    float* const sred = reinterpret_cast<float*>(sstage);
+    const int np = static_cast<int>(sl.rowb / sizeof(T));
+    float* const sred = reinterpret_cast<float*>(L.stage);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int row0 = blockIdx.x * 64;
-    const int col0 = blockIdx.y * 64;
     const int mycol = col0 + (tid & 63);
     // The inputs of the epilogue and of the liveness test are requested
     // first, the first DEPTH stages right after them, so the latency of all
@@ -383,30 +406,13 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
     const int j = col0 + jl;
     const int done_m = (tid < 64 && mycol < R) ? state[mycol].done : 1;
     const int done_j = j < R ? state[j].done : 1;
-    // stage st: bytes [SB st, SB st + SB) of each of the 64 rows of J and of
-    // the restart copy; thread loads 16-byte chunks (row 16 u + tid / 16,
-    // bytes 16 (tid % 16)), so 16 consecutive lanes read a row's two whole
-    // cache lines
-    const uint32_t rowb = static_cast<uint32_t>(np) * sizeof(T);
-    const __amdgpu_buffer_rsrc_t rJ =
-        slab_rsrc(reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * rowb, 64 * rowb);
-    const __amdgpu_buffer_rsrc_t rU =
-        slab_rsrc(reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * rowb, 64 * rowb);
-    const uint32_t voff = (tid >> 4) * rowb + (tid & 15) * 16;
-    const int soff = (tid >> 4) * SROW + (tid & 15) * 16;
-    i32x4 ring[DEPTH][8];
-    auto fetch = [&](i32x4 (&r)[8], int st) {
-        const uint32_t o = voff + static_cast<uint32_t>(st) * SB;
+    if (!j_ready) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            r[u] = __builtin_amdgcn_raw_buffer_load_b128(rJ, o, u * 16 * rowb, 0);
-            r[4 + u] = __builtin_amdgcn_raw_buffer_load_b128(rU, o, u * 16 * rowb, 0);
-        }
-    };
-    const int nst = static_cast<int>(rowb / SB);
+        for (int p = 0; p < DEPTH; ++p) fused_fetch_j<DEPTH>(ring[p], sl, p);
+    }
     // every row holds at least DEPTH stages (lowp_shape_valid)
 #pragma unroll
-    for (int p = 0; p < DEPTH; ++p) fetch(ring[p], p);
+    for (int p = 0; p < DEPTH; ++p) fused_fetch_u<DEPTH>(ring[p], sl, p);
     float uo_pre[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -415,7 +421,7 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
     }
     float c_in = 1.0f;
     if constexpr (PREC == 1) c_in = cs_old[j];
-    if (tid < 64) sdead[tid] = done_m;
+    if (tid < 64) L.dead[tid] = done_m;
     const bool block_live = __syncthreads_or(!done_m) != 0;
 
     f32x16 acc[2][2];
@@ -425,20 +431,27 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
     if (block_live) {
         const int fo = (lane & 31) * SROW + (lane >> 5) * FB;
-        // stage st: registers to LDS buffer st % 2, the refetch DEPTH stages
-        // ahead, one barrier, this wavefront's MFMA steps (wave, wave + 4, ...)
-        auto stage = [&](i32x4 (&r)[8], int st, bool refetch) {
-            char* A = sstage + (st & 1) * 2 * 64 * SROW;
+        // registers of stage st to LDS buffer st % 2, then the refetch DEPTH
+        // stages ahead into the same registers
+        auto put = [&](i32x4 (&r)[8], int st, bool refetch) {
+            char* A = L.stage + (st & 1) * 2 * 64 * SROW;
             char* B = A + 64 * SROW;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                *reinterpret_cast<i32x4*>(A + soff + u * 16 * SROW) = r[u];
-                *reinterpret_cast<i32x4*>(B + soff + u * 16 * SROW) = r[4 + u];
+                *reinterpret_cast<i32x4*>(A + sl.soff + u * 16 * SROW) = r[u];
+                *reinterpret_cast<i32x4*>(B + sl.soff + u * 16 * SROW) = r[4 + u];
             }
-            if (refetch) fetch(r, st + DEPTH);
-            __syncthreads();
+            if (refetch) {
+                fused_fetch_j<DEPTH>(r, sl, st + DEPTH);
+                fused_fetch_u<DEPTH>(r, sl, st + DEPTH);
+            }
+        };
+        // this wavefront's MFMA steps of stage st (wave, wave + 4, ...)
+        auto compute = [&](int st) {
+            const char* A = L.stage + (st & 1) * 2 * 64 * SROW;
+            const char* B = A + 64 * SROW;
 #pragma unroll
-            for (int ks = wave; ks < SB / M::kBytes; ks += 4) {
+            for (int ks = wave; ks < kFusedStage / M::kBytes; ks += 4) {
                 const int kb = ks * M::kBytes;
                 const auto a0 = M::load(A + fo + kb);
                 const auto a1 = M::load(A + 32 * SROW + fo + kb);
@@ -450,15 +463,29 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
                 acc[1][1] = M::step(a1, b1, acc[1][1]);
             }
         };
+        // stage st + 1 goes to LDS while stage st is multiplied (the other
+        // buffer, free since the barrier that ended stage st - 1), one
+        // barrier per stage
+        const int nst = sl.nst;
+        put(ring[0], 0, DEPTH < nst);
+        __syncthreads();
         int s0 = 0;
-        for (; s0 + 2 * DEPTH <= nst; s0 += DEPTH) {
+        for (; s0 + 2 * DEPTH < nst; s0 += DEPTH) {
 #pragma unroll
-            for (int p = 0; p < DEPTH; ++p) stage(ring[p], s0 + p, true);
+            for (int p = 0; p < DEPTH; ++p) {
+                put(ring[(p + 1) % DEPTH], s0 + p + 1, true);
+                compute(s0 + p);
+                __syncthreads();
+            }
         }
 #pragma unroll
-        for (int q = 0; q < 2 * DEPTH - 1; ++q) {
+        for (int q = 0; q < 2 * DEPTH; ++q) {
             const int st = s0 + q;
-            if (st < nst) stage(ring[q % DEPTH], st, st + DEPTH < nst);
+            if (st < nst) {
+                if (st + 1 < nst) put(ring[(q + 1) % DEPTH], st + 1, st + 1 + DEPTH < nst);
+                compute(st);
+                __syncthreads();
+            }
         }
     }
     __syncthreads();                            // the stage buffers are reused below
@@ -488,10 +515,10 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
     float c_out = 1.0f;
     if constexpr (PREC == 1) {
         c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
-        if (blockIdx.x == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
+        if (row0 == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
     }
     // transposed low-precision tile: row jl holds rows row0 .. row0+63 of restart j
-    T* tileT = reinterpret_cast<T*>(sstage);
+    T* tileT = reinterpret_cast<T*>(L.stage);
     constexpr int TROW = 64 + 16 / static_cast<int>(sizeof(T));   // padded row, in elements
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -523,7 +550,7 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
     for (int q = 0; q < 4; ++q) part[q] = dadd(part[q], __shfl_xor(part[q], 32, 64));
     if (lane < 32) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[wr][jl][q] = part[q];
+        for (int q = 0; q < 4; ++q) L.red[wr][jl][q] = part[q];
     }
     __syncthreads();
     {
@@ -531,19 +558,183 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
         constexpr int CPR = 64 * static_cast<int>(sizeof(T)) / 16;
         for (int c = tid; c < 64 * CPR; c += MT) {
             const int r = c / CPR, ch = c % CPR;
-            if (sdead[r]) continue;
+            if (L.dead[r]) continue;
             const i32x4 v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(tileT + r * TROW) + ch * 16);
             *reinterpret_cast<i32x4*>(reinterpret_cast<char*>(Ub_new + static_cast<size_t>(col0 + r) * np + row0) +
                                       ch * 16) = v;
         }
     }
-    // partial sums of this row tile, closed by the next launch's extra
-    // workgroups
+    // partial sums of this row tile, closed after the iteration
     if (tid < 64) {
-        double* p = partials + (static_cast<size_t>(blockIdx.x) * Rp + col0 + tid) * 4;
+        double* p = partials + (static_cast<size_t>(tx) * Rp + col0 + tid) * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) p[q] = dadd(red[0][tid][q], red[1][tid][q]);
+        for (int q = 0; q < 4; ++q) p[q] = dadd(L.red[0][tid][q], L.red[1][tid][q]);
     }
+    __syncthreads();                            // LDS is reused by the next iteration
+}
+
+template <int PREC>
+__device__ __forceinline__ FusedSlab fused_slab(int np, int row0, int col0, const typename Prec<PREC>::T* Jq,
+                                                const typename Prec<PREC>::T* Ub_old) {
+    using T = typename Prec<PREC>::T;
+    FusedSlab sl;
+    sl.rowb = static_cast<uint32_t>(np) * sizeof(T);
+    sl.rJ = slab_rsrc(reinterpret_cast<const char*>(Jq) + static_cast<size_t>(row0) * sl.rowb, 64 * sl.rowb);
+    sl.rU = slab_rsrc(reinterpret_cast<const char*>(Ub_old) + static_cast<size_t>(col0) * sl.rowb, 64 * sl.rowb);
+    sl.voff = (threadIdx.x >> 4) * sl.rowb + (threadIdx.x & 15) * 16;
+    sl.soff = (threadIdx.x >> 4) * kFusedSrow + (threadIdx.x & 15) * 16;
+    sl.nst = static_cast<int>(sl.rowb / kFusedStage);
+    return sl;
+}
+
+// One launch per iteration; the extra row of workgroups (dispatched after
+// every row tile) closes the previous iteration: workgroup x of it for
+// column block x.  It may run beside the tiles that read the same restart
+// states; a restart it stops is then updated once more into the buffer
+// after its last iterate, which stays where iters_done says.
+template <int PREC, int DEPTH>
+__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_fused_kernel(
+    int np, int Rp, const typename Prec<PREC>::T* __restrict__ Jq, const float* __restrict__ rscale,
+    const float* __restrict__ U_old, float* __restrict__ U_new,
+    const typename Prec<PREC>::T* __restrict__ Ub_old, typename Prec<PREC>::T* __restrict__ Ub_new,
+    const float* __restrict__ cs_old, float* __restrict__ cs_new, double rho_q,
+    double alpha, double beta, double eps, int R, int64_t k, const double* __restrict__ partials_prev,
+    double* __restrict__ partials, double* __restrict__ log, RestartState* __restrict__ state) {
+    __shared__ FusedLds L;
+    const int tiles = np / 64;
+    if (static_cast<int>(blockIdx.y) == Rp / 64) {
+        if (k > 0 && static_cast<int>(blockIdx.x) < Rp / 64)
+            lowp_close(partials_prev, tiles, Rp, blockIdx.x, R, k - 1, alpha, beta, eps, log, state, L.red[0]);
+        return;
+    }
+    if (static_cast<int>(blockIdx.x) >= tiles) return;     // grid padded to the closing row's width
+    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    const FusedSlab sl = fused_slab<PREC>(np, row0, col0, Jq, Ub_old);
+    i32x4 ring[DEPTH][8];
+    fused_tile<PREC, DEPTH>(L, ring, false, sl, Rp, row0, col0, blockIdx.x, rscale, U_old, U_new, Ub_new, cs_old,
+                            cs_new, rho_q, alpha, R, partials, state);
+}
+
+// ---- the fused iteration resident for the whole run ---------------------
+//
+// One cooperative launch: workgroup t < tiles x cblocks owns a tile for
+// every iteration (the column blocks of a row tile on one XCD, so the J
+// slab they share meets in one L2), the last cblocks workgroups close the
+// iterations.  Between iterations a grid barrier: every wave drains its
+// stores, then one thread per workgroup releases at device scope (the
+// restart copy crosses XCDs, whose L2 caches are not coherent with each
+// other), counts the workgroup in (a counter per group of workgroups, then
+// one for the groups) and polls its group's release word, and acquires at
+// device scope.  The J halves of the next iteration's first stages are
+// requested before the barrier: J does not change.  Closing workgroup c
+// closes iteration k after barrier k + 1 and arrives at barrier k + 2 when
+// done, so a restart it stops is seen by the tiles two iterations later;
+// the three rotating buffers keep its last iterate.  Every wait is bounded:
+// a workgroup that polls too long marks every restart aborted and publishes
+// a stop that every other one sees at its next poll.
+struct LowpResArgs {
+    int np, Rp, R, tiles, cblocks;
+    int64_t iters;
+    const void* Jq;
+    const float* rscale;
+    float* U[3];
+    void* Ub[3];
+    float* cs[3];
+    double rho_q, alpha, beta, eps;
+    double* partials[2];
+    double* log;
+    RestartState* state;
+    ResidentSync* sync;
+};
+
+constexpr unsigned int kLowpSpinLimit = 1u << 22;
+
+__device__ bool lowp_barrier(ResidentSync* sy, unsigned int gen, RestartState* st, int R, FusedLds& L) {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned int G = gridDim.x;
+        const unsigned int g = blockIdx.x & 7u;
+        const unsigned int per = (G - g + 7u) / 8u;
+        const unsigned int groups = G < 8u ? G : 8u;
+        auto add = [](unsigned int* p) {
+            return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        auto put = [](unsigned int* p, unsigned int v) {
+            __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        if (add(&sy->grp[g * kTicketStride]) == gen * per - 1u) {
+            if (add(&sy->top[0]) == gen * groups - 1u)
+                for (unsigned int q = 0; q < groups; ++q) put(&sy->flag[q * kTicketStride], gen);
+        }
+        unsigned long long* f = reinterpret_cast<unsigned long long*>(sy->flag + g * kTicketStride);
+        unsigned int spins = 0;
+        int ok = 1;
+        for (;;) {
+            const unsigned long long v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (static_cast<unsigned int>(v >> 32) != 0u) { ok = 0; break; }
+            if (static_cast<unsigned int>(v) >= gen) break;
+            if (++spins > kLowpSpinLimit) {
+                for (int r = 0; r < R; ++r) {
+                    __hip_atomic_store(&st[r].aborted, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st[r].done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                for (unsigned int q = 0; q < groups; ++q) put(&sy->flag[q * kTicketStride + 1], 2u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        L.flag = ok;
+    }
+    __syncthreads();
+    return L.flag != 0;
+}
+
+template <int PREC, int DEPTH>
+__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_resident_kernel(LowpResArgs a) {
+    using T = typename Prec<PREC>::T;
+    __shared__ FusedLds L;
+    const int ntile = a.tiles * a.cblocks;
+    const int b = blockIdx.x;
+    if (b >= ntile) {
+        const int cb = b - ntile;
+        for (int64_t k = 0; k < a.iters; ++k) {
+            if (!lowp_barrier(a.sync, static_cast<unsigned int>(k + 1), a.state, a.R, L)) return;
+            lowp_close(a.partials[k & 1], a.tiles, a.Rp, cb, a.R, k, a.alpha, a.beta, a.eps, a.log, a.state,
+                       L.red[0]);
+        }
+        return;
+    }
+    // tile: the cblocks column blocks of a row tile on one XCD (workgroup b
+    // runs on XCD b mod 8 under round-robin dispatch)
+    int tx, ty;
+    if ((a.tiles & 7) == 0) {
+        const int x8 = b >> 3;
+        tx = (b & 7) + 8 * (x8 / a.cblocks);
+        ty = x8 % a.cblocks;
+    } else {
+        tx = b % a.tiles;
+        ty = b / a.tiles;
+    }
+    const int row0 = tx * 64, col0 = ty * 64;
+    const T* Jq = static_cast<const T*>(a.Jq);
+    i32x4 ring[DEPTH][8];
+    for (int64_t k = 0; k < a.iters; ++k) {
+        const int o = static_cast<int>(k % 3), n = static_cast<int>((k + 1) % 3);
+        if (k > 0 && !lowp_barrier(a.sync, static_cast<unsigned int>(k), a.state, a.R, L)) return;
+        const FusedSlab sl = fused_slab<PREC>(a.np, row0, col0, Jq, static_cast<const T*>(a.Ub[o]));
+        fused_tile<PREC, DEPTH>(L, ring, k > 0, sl, a.Rp, row0, col0, tx, a.rscale, a.U[o], a.U[n],
+                                static_cast<T*>(a.Ub[n]), a.cs[o], a.cs[n], a.rho_q, a.alpha, a.R,
+                                a.partials[k & 1], a.state);
+        if (k + 1 < a.iters) {
+#pragma unroll
+            for (int p = 0; p < DEPTH; ++p) fused_fetch_j<DEPTH>(ring[p], sl, p);
+        }
+    }
+    (void)lowp_barrier(a.sync, static_cast<unsigned int>(a.iters), a.state, a.R, L);
 }
 
 // ---- the update: sum of the splits, eq:FPE in u, partial sums ----------
@@ -889,12 +1080,13 @@ hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, in
 }
 
 bool lowp_shape_valid(int prec, int np, int Rp, const LowpShape& sh) {
-    // the fused iteration: 64 x 64 tiles, 256-byte stages, depth 3 in BF16
-    // only (FP8 fragments leave no registers for a third stage under the
-    // two-wavefront cap)
-    if (sh.splits == 0)
-        return sh.bn == 64 && sh.sb == 256 && (sh.depth == 2 || (sh.depth == 3 && prec == 0)) && Rp % 64 == 0 &&
-               np % 64 == 0 && np * (prec == 0 ? 2 : 1) / 256 >= sh.depth;
+    // the fused iteration (splits 0: a launch per iteration, -1: resident):
+    // 64 x 64 tiles, 256-byte stages, depth 3 in BF16 only (FP8 fragments
+    // leave no registers for a third stage under the two-wavefront cap)
+    // (the resident kernel, which keeps more registers live, takes depth 2)
+    if (sh.splits == 0 || sh.splits == -1)
+        return sh.bn == 64 && sh.sb == 256 && (sh.depth == 2 || (sh.depth == 3 && prec == 0 && sh.splits == 0)) &&
+               Rp % 64 == 0 && np % 64 == 0 && np * (prec == 0 ? 2 : 1) / 256 >= sh.depth;
     if (sh.bn != 64 && sh.bn != 128) return false;
     if (sh.sb != 128 && sh.sb != 256) return false;
     if (sh.depth != 2 && sh.depth != 3) return false;
@@ -917,7 +1109,8 @@ LowpShape lowp_default_shape(int prec, int np, int Rp, int cus) {
 }
 
 size_t lowp_product_bytes(int np, int Rp, const LowpShape& sh) {
-    return static_cast<size_t>(sh.splits) * np * Rp * sizeof(float);
+    // the fused iteration (splits 0 or -1) keeps no partial tiles
+    return sh.splits > 0 ? static_cast<size_t>(sh.splits) * np * Rp * sizeof(float) : 0;
 }
 
 namespace {
@@ -1025,6 +1218,61 @@ hipError_t launch_lowp_step(int prec, int np, int Rp, const LowpShape& sh, const
                          partials, state);
     }
     return hipGetLastError();
+}
+
+namespace {
+
+template <int PREC, int DEPTH>
+hipError_t launch_resident_one(const LowpResArgs& a, hipStream_t s) {
+    static int cap = 0;           // workgroups of this kernel the device holds at once
+    auto kern = lowp_resident_kernel<PREC, DEPTH>;
+    if (cap == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, MT, 0);
+        if (e != hipSuccess) return e;
+        cap = cus * occ;
+    }
+    const int groups = a.tiles * a.cblocks + a.cblocks;
+    if (groups > cap) return hipErrorCooperativeLaunchTooLarge;
+    LowpResArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(groups), dim3(MT), args, 0, s);
+}
+
+}  // namespace
+
+hipError_t launch_lowp_resident(int prec, int np, int Rp, const LowpShape& sh, int64_t iters, const void* Jq,
+                                const float* rscale, float* const* U, void* const* Ub, float* const* cs,
+                                double rho_q, double alpha, double beta, double eps, int R, double* const* partials,
+                                double* log, RestartState* state, ResidentSync* sync, hipStream_t s) {
+    if (sh.splits != -1 || !lowp_shape_valid(prec, np, Rp, sh)) return hipErrorInvalidValue;
+    LowpResArgs a{};
+    a.np = np;
+    a.Rp = Rp;
+    a.R = R;
+    a.tiles = np / 64;
+    a.cblocks = Rp / 64;
+    a.iters = iters;
+    a.Jq = Jq;
+    a.rscale = rscale;
+    for (int i = 0; i < 3; ++i) {
+        a.U[i] = U[i];
+        a.Ub[i] = Ub[i];
+        a.cs[i] = cs[i];
+    }
+    a.rho_q = rho_q;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.eps = eps;
+    a.partials[0] = partials[0];
+    a.partials[1] = partials[1];
+    a.log = log;
+    a.state = state;
+    a.sync = sync;
+    if (prec == 0) return launch_resident_one<0, 2>(a, s);
+    return launch_resident_one<1, 2>(a, s);
 }
 
 hipError_t launch_lowp_close(int np, int Rp, int R, int64_t kk, const double* partials, double alpha,

@@ -71,10 +71,10 @@ def test_lowp_zero_coupling_closed_form(prec_name, n, R):
 
 # (bn, splits, stage_bytes, depth): the fused iteration and a split product
 # that fits n = 512 with 32 restarts in both formats
-SHAPES = {"fused": (64, 0, 256, 2), "split": (64, 2, 128, 2)}
+SHAPES = {"fused": (64, 0, 256, 2), "split": (64, 2, 128, 2), "resident": (64, -1, 256, 2)}
 
 
-@pytest.mark.parametrize("shape_name", ["fused", "split"])
+@pytest.mark.parametrize("shape_name", ["fused", "split", "resident"])
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
 def test_lowp_energy_gap_and_final_objective(prec_name, shape_name):
     """SK n = 512, 32 restarts.  H_final is eq:Hamilton of the returned
@@ -110,27 +110,31 @@ def test_lowp_energy_gap_and_final_objective(prec_name, shape_name):
     assert np.abs(E - E64).max() < 0.15 * scale
 
 
+@pytest.mark.parametrize("shape_name", ["fused", "resident"])
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
-def test_lowp_freezes_converged_restarts(prec_name):
+def test_lowp_freezes_converged_restarts(prec_name, shape_name):
     """Restarts stop on their own; each returns the iterate of the iteration
     it stopped at: a restart's column of the product depends on that
     restart alone, so a run of exactly iters_done iterations without a
-    tolerance gives the same column bit for bit."""
+    tolerance gives the same column bit for bit.  The resident run sees a
+    stop two iterations late, the launch-per-iteration run one: neither may
+    overwrite the stopped restart's last iterate."""
     import paper_2509_01928_amd as L
     prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
+    shape = SHAPES[shape_name]
     n, R = 256, 64
     J = gen.sk_dense(n, 4005)
     X0 = gen.uniform_x0(n, R, 5005)
     alpha = -np.linalg.eigvalsh(J)[0]
     beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
-    X, S, Hf, E, st, Hlog = run_lowp(J, X0, alpha, beta, 2000, prec, eps=1e-3)
+    X, S, Hf, E, st, Hlog = run_lowp(J, X0, alpha, beta, 2000, prec, eps=1e-3, shape=shape)
     assert all(s.converged == 1 for s in st)
     assert all(s.iters_done < 2000 for s in st)
     done = np.array([s.iters_done for s in st])
     assert len(set(done.tolist())) > 1       # restarts stop on their own
     for r in (int(np.argmin(done)), int(np.argmax(done))):
         m = int(done[r])
-        Xm, Sm, _, _, stm, Hm = run_lowp(J, X0, alpha, beta, m, prec)
+        Xm, Sm, _, _, stm, Hm = run_lowp(J, X0, alpha, beta, m, prec, shape=shape)
         assert stm[r].iters_done == m
         assert np.array_equal(X[:, r], Xm[:, r]), f"restart {r}: final iterate is not iteration {m}'s"
         assert np.array_equal(S[:, r], Sm[:, r])
@@ -143,7 +147,9 @@ def lowp_shapes(prec_name, n, R):
     np_ = -(-n // (256 if prec_name == "bf16" else 512)) * (256 if prec_name == "bf16" else 512)
     Rp = -(-R // 64) * 64
     esz = 2 if prec_name == "bf16" else 1
-    out = [(64, 0, 256, 2)] + ([(64, 0, 256, 3)] if prec_name == "bf16" and np_ * esz // 256 >= 3 else [])
+    out = [(64, -1, 256, 2), (64, 0, 256, 2)]
+    if prec_name == "bf16" and np_ * esz // 256 >= 3:
+        out.append((64, 0, 256, 3))
     for bn in (128, 64):
         for S in (1, 2, 4, 8):
             for sb in (128, 256):
@@ -207,3 +213,29 @@ def test_lowp_autotune_and_cache(tmp_path):
         assert text.count("lowp-v1|") == 2 and '"splits": ' in text
     finally:
         L.ising_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
+def test_lowp_resident_matches_launches_bitwise(prec_name):
+    """The resident run (one cooperative launch, grid barriers) performs the
+    same arithmetic in the same order as one launch per iteration, so 100
+    iterations (SK n = 768: a ragged 12 x 3 tile grid in BF16, 12 row tiles
+    over a padded order of 1024 in FP8) give identical iterates, spins and
+    H / r logs -- which also shows that every barrier published the copy of
+    the restarts to every XCD before it was read."""
+    import paper_2509_01928_amd as L
+    prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
+    n, R, iters = 768, 160, 100
+    J = gen.sk_dense(n, 4008)
+    X0 = gen.uniform_x0(n, R, 5008)
+    alpha = -np.linalg.eigvalsh(J)[0]
+    beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    Xa, Sa, Ha, Ea, sta, La = run_lowp(J, X0, alpha, beta, iters, prec, shape=(64, 0, 256, 2))
+    Xb, Sb, Hb, Eb, stb, Lb = run_lowp(J, X0, alpha, beta, iters, prec, shape=(64, -1, 256, 2))
+    # (a timed-out barrier wait would have raised in the stats read)
+    assert [s.iters_done for s in sta] == [s.iters_done for s in stb]
+    assert np.array_equal(Xa, Xb)
+    assert np.array_equal(Sa, Sb)
+    assert np.array_equal(Ha, Hb)
+    for a_, b_ in zip(La, Lb):
+        assert np.array_equal(a_, b_)
