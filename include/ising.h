@@ -290,8 +290,9 @@ ising_status ising_cut(ising_ctx* ctx, const int8_t* s_dev, int32_t R, double* c
  * one FP32 scale per row (ISING_FP8_E4M3), the restarts in FP32 plus a copy
  * in the same low precision, products accumulate in FP32.  The iteration
  * runs on u = sqrt(beta) x, where eq:FPE reads u <- cbrt(J u + alpha u)
- * exactly, so u stays representable in either format; the update itself is
- * FP64.  H and r of each iteration (ising_get_log) are FP64 sums of the
+ * exactly, so u stays representable in either format; the update forms
+ * z + alpha u in FP64 and takes its cube root in FP32 (the precision u is
+ * stored in).  H and r of each iteration (ising_get_log) are FP64 sums of the
  * low-precision products.  This solves a quantised problem: compare its
  * energies, not its iterates, with the FP64 path.
  *   x0_dev       double[n * R] (restart-interleaved, as ising_solve)
@@ -314,28 +315,34 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
  * partial tiles the update adds in split order; the k range streams through
  * LDS in stages of stage_bytes per row (128 or 256) with `depth` stages in
  * flight (2 or 3).  splits = 0 selects the fused iteration instead: one
- * launch whose 64 x 64 tiles (bn 64, 256-byte stages) cover the whole k
- * range and update in place, with no partial tiles in memory.  bn = 0
- * restores the default, the fused iteration (depth 3 in BF16 where the
- * padded order holds three stages, else 2).  A shape that does not fit a later call (bn not
+ * launch per iteration whose 64 x 64 tiles (bn 64, 256-byte stages) cover
+ * the whole k range and update in place, with no partial tiles in memory;
+ * splits = -1 runs that iteration resident, every iteration in one
+ * cooperative launch with grid barriers between them (depth 2; when its
+ * grid does not fit on the device at once, the call runs the fused
+ * launches instead).  All shapes compute the same products, in a different
+ * order of FP32 additions; the resident run and the fused launches are
+ * identical bit for bit.  bn = 0 restores the default, the fused iteration
+ * (depth 3 in BF16 where the padded order holds three stages, else 2).  A shape that does not fit a later call (bn not
  * dividing the padded restart count, or a split holding fewer than `depth`
  * whole stages) falls back to the default for that call.  The shape changes
  * the order of the FP32 additions, nothing else.
  * Errors: ISING_E_INVALID_ARG for a value outside those sets, or for
- * splits = 0 with bn != 64 or stage_bytes != 256. */
+ * splits 0 or -1 with bn != 64 or stage_bytes != 256. */
 ising_status ising_set_lowp_shape(ising_ctx* ctx, int32_t bn, int32_t splits, int32_t stage_bytes,
                                   int32_t depth);
 
 /* Choose the shape of ising_solve_lowp for this context, restart count and
- * format by timing: every shape the library is built for that fits (the
- * fused iteration with 64 x 64 tiles, which needs no partial tiles, and the
- * split product of ising_set_lowp_shape over tile widths, splits, stage
- * widths and depths) runs `iters` iterations from x0_dev twice, the second
- * timed on `stream`; the fastest becomes this context's shape.  With
+ * format by timing: every shape of ising_set_lowp_shape that fits (the
+ * fused iteration as launches and as a resident run, and the split product
+ * over tile widths, splits, stage widths and depths) runs `iters`
+ * iterations from x0_dev twice, the second timed on `stream`; the fastest
+ * becomes this context's shape.  With
  * cache_path non-NULL the choice is looked up first and stored after tuning
  * in a JSON file of one entry per line, keyed by device name, compute-unit
  * count, format, padded order, padded restart count and iters.
- *   shape_out       NULL or int32[4]: bn, splits (0: fused), stage_bytes, depth
+ *   shape_out       NULL or int32[4]: bn, splits (0 fused, -1 resident),
+ *                   stage_bytes, depth
  *   ms_out          NULL or the chosen shape's time for `iters` iterations
  *   from_cache_out  NULL or 1 when the shape came from the cache
  * The context's last-solve state (logs, statistics) is overwritten.
