@@ -319,8 +319,8 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
  * the whole k range and update in place, with no partial tiles in memory;
  * splits = -1 runs that iteration resident, every iteration in one
  * cooperative launch with grid barriers between them (depth 2; when its
- * grid does not fit on the device at once, the call runs the fused
- * launches instead).  All shapes compute the same products, in a different
+ * grid does not fit on the device at once, or for more than 10^8
+ * iterations, the call runs the fused launches instead).  All shapes compute the same products, in a different
  * order of FP32 additions; the resident run and the fused launches are
  * identical bit for bit.  bn = 0 restores the default, the fused iteration
  * (depth 3 in BF16 where the padded order holds three stages, else 2).  A shape that does not fit a later call (bn not

@@ -1811,6 +1811,9 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
             HIP_OK(hipMemcpyAsync(cs[b], cs[0], kMaxR * sizeof(float), hipMemcpyDeviceToDevice, s), "copy scales");
     }
     bool resident_done = false;
+    // the resident run counts barrier arrivals (iterations x workgroups per
+    // group) in 32-bit words: longer runs take the same iteration as launches
+    if (shape.splits == -1 && iters > 100000000) shape.splits = 0;
     if (shape.splits == -1 && iters > 0) {
         // the whole run in one cooperative launch, or the same iteration a
         // launch at a time when its grid does not fit on the device at once

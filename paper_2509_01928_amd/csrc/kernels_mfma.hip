@@ -6,15 +6,9 @@
 // drops out exactly), so the iterate stays O(sqrt(alpha + lambda)) and is
 // representable in BF16 and in FP8 (e4m3, largest finite 448).
 //
-// One launch per iteration: a workgroup owns a 64 x 64 tile of Z (64 rows,
-// 64 restarts); each of its four wavefronts computes the whole tile over a
-// quarter of the k range as 2 x 2 independent 32 x 32 MFMA accumulators,
-// fed straight from global memory (a lane's operand fragment is 8
-// consecutive k of one row, so each load is whole and the rows' cache lines
-// are reused over the following k-steps).  J sits in a BF16 copy, or an FP8
-// copy with one FP32 scale per row (J_ij ~ s_i q_ij, s_i = max_j |J_ij| /
-// 448).  The restart block sits as
-// an FP32 master (n x R) plus a low-precision transposed copy (R x n) that
+// J sits in a BF16 copy, or an FP8 copy with one FP32 scale per row
+// (J_ij ~ s_i q_ij, s_i = max_j |J_ij| / 448).  The restart block sits as an
+// FP32 master (n x R) plus a low-precision transposed copy (R x n) that
 // feeds the next product.  In FP8 that copy carries one FP32 scale per
 // restart, c_j, with |u_ij| <= 448 c_j: exact at the start (column maximum)
 // and carried forward by the bound |u'| = |cbrt(z + alpha u)| <=
@@ -22,9 +16,21 @@
 // row sum of the quantised J.  The bound tends to sqrt(rho_q + alpha), so
 // large starting points (u = sqrt(beta) x is large when beta is) never reach
 // the format's overflow, and later steps keep its full relative precision.
-// The epilogue applies the update in FP64, stores both copies and adds the
-// restart's FP64 partial sums; the last workgroup of each column block closes
-// the iteration for its restarts (H, r, freezing at r < eps).
+//
+// Three shapes of one iteration (chosen per problem by the caller or by
+// timing them):
+//   fused      one launch per iteration; a workgroup owns a 64 x 64 tile of
+//              Z over the whole k range and updates it in place;
+//   resident   the fused tile body for every iteration in one cooperative
+//              launch, grid barriers between iterations;
+//   split      128 x bn tiles over 1..8 splits of the k range into FP32
+//              partial tiles, then an update kernel that adds them.
+// Every shape stages the k range through LDS in stages of whole cache lines
+// and ends an iteration the same way: the update (z + alpha u in FP64, its
+// cube root in FP32, the precision u is stored in), both copies stored, the
+// restart's FP64 partial sums per row tile, and extra workgroups closing the
+// iteration for their restarts (H, r, freezing at r < eps) while the next
+// one runs.
 #include "device_common.h"
 #include "ising_internal.h"
 
@@ -123,7 +129,7 @@ __device__ void lowp_close(const double* __restrict__ P, int tiles, int Rp, int 
 // split; its four wavefronts split the tile 2 x 2 and each accumulates its
 // 64 x BN/2 sub-tile as 2 x BN/64 independent 32 x 32 MFMA blocks over the
 // whole k range of the split (no reduction inside the workgroup).  The k
-// range streams in stages of 256 bytes per row: every row of J and of the
+// range streams in stages of SB bytes per row: every row of J and of the
 // restart copy that the tile needs is loaded as whole cache lines into
 // registers DEPTH stages ahead, written to one of two LDS buffers, and read
 // back as MFMA fragments -- one barrier per stage.  Stages of SB = 256 bytes
