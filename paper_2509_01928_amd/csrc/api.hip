@@ -1842,7 +1842,7 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
                                       p.eps, R, k, ctx->lp_P, pprev, pk, ctx->log, ctx->state, s),
                "low-precision step");
     }
-    if (iters > 0 && !resident_done)
+    if (iters > 0)
         HIP_OK(doch::launch_lowp_close(np, Rp, R, iters - 1, ctx->lp_partials + ((iters - 1) & 1) * pstride,
                                        p.alpha, p.beta, p.eps, ctx->log, ctx->state, s),
                "close last iteration");

@@ -464,9 +464,10 @@ hipError_t launch_lowp_step(int prec, int np, int Rp, const LowpShape& sh, const
                             double* partials, double* log, RestartState* state, hipStream_t s);
 // The whole run of the fused iteration in one cooperative launch (shape
 // splits -1): tiles resident on their compute units, grid barriers between
-// iterations, the closing done by extra workgroups.  sync must be zeroed
-// (launch_resident_reset).  hipErrorCooperativeLaunchTooLarge when the
-// tiles and closing workgroups do not fit on the device at once.
+// iterations, each iteration closed by the next one's tiles (the last by
+// launch_lowp_close).  sync must be zeroed (launch_resident_reset).
+// hipErrorCooperativeLaunchTooLarge when the tiles do not fit on the device
+// at once.
 hipError_t launch_lowp_resident(int prec, int np, int Rp, const LowpShape& sh, int64_t iters, const void* Jq,
                                 const float* rscale, float* const* U, void* const* Ub, float* const* cs,
                                 double rho_q, double alpha, double beta, double eps, int R, double* const* partials,

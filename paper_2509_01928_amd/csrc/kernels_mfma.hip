@@ -83,9 +83,35 @@ __device__ __forceinline__ typename Prec<PREC>::T to_lowp(float f) {
     else return to_fp8(f);
 }
 
+// Finish iteration kk of restart c from its four FP64 sums over all rows
+// (u^4, u^2, u z, (du)^2): H, r, the log and the state (eq:Hamilton in
+// u = sqrt(beta) x, Remark S2).
+__device__ __forceinline__ void lowp_close_restart(const double (&S)[4], int c, int R, int64_t kk, double alpha,
+                                                   double beta, double eps, double* __restrict__ log,
+                                                   RestartState* __restrict__ state, int done = -1) {
+    if (c >= R || (done < 0 ? state[c].done : done)) return;
+    // H(x) = H_u / beta with x = u / sqrt(beta); r is scale free
+    const double Hu = dsub(dsub(dmul(0.25, S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
+    const double H = ddiv(Hu, beta);
+    const double r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
+    log[(static_cast<size_t>(kk) * R + c) * 2] = H;
+    log[(static_cast<size_t>(kk) * R + c) * 2 + 1] = r;
+    RestartState& st = state[c];
+    st.iters_done = kk + 1;
+    st.H_last = H;
+    st.r_last = r;
+    if (!isfinite(H) || !isfinite(r)) {
+        st.nonfinite = 1;
+        st.done = 1;
+    } else if (eps > 0.0 && r < eps) {
+        st.converged = 1;
+        st.done = 1;
+    }
+}
+
 // Close iteration kk of the 64 restarts of column block cb: add the row
-// tiles' partial sums in tile order and write H, r, the log and the state
-// (eq:Hamilton in u = sqrt(beta) x, Remark S2).  red: 64 x 4 doubles of LDS.
+// tiles' partial sums in tile order (0, 1, ..., tiles - 1), then finish each
+// restart.  red: 64 x 4 doubles of LDS.
 __device__ void lowp_close(const double* __restrict__ P, int tiles, int Rp, int cb, int R, int64_t kk,
                            double alpha, double beta, double eps, double* __restrict__ log,
                            RestartState* __restrict__ state, double (*red)[4]) {
@@ -97,27 +123,8 @@ __device__ void lowp_close(const double* __restrict__ P, int tiles, int Rp, int 
     }
     __syncthreads();
     if (tid < 64) {
-        const int c = col0 + tid;
-        if (c < R && !state[c].done) {
-            const double* S = red[tid];
-            // H(x) = H_u / beta with x = u / sqrt(beta); r is scale free
-            const double Hu = dsub(dsub(dmul(0.25, S[0]), dmul(ddiv(alpha, 2.0), S[1])), dmul(0.5, S[2]));
-            const double H = ddiv(Hu, beta);
-            const double r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[3]), sqrt(S[1]));
-            log[(static_cast<size_t>(kk) * R + c) * 2] = H;
-            log[(static_cast<size_t>(kk) * R + c) * 2 + 1] = r;
-            RestartState& st = state[c];
-            st.iters_done = kk + 1;
-            st.H_last = H;
-            st.r_last = r;
-            if (!isfinite(H) || !isfinite(r)) {
-                st.nonfinite = 1;
-                st.done = 1;
-            } else if (eps > 0.0 && r < eps) {
-                st.converged = 1;
-                st.done = 1;
-            }
-        }
+        const double S[4] = {red[tid][0], red[tid][1], red[tid][2], red[tid][3]};
+        lowp_close_restart(S, col0 + tid, R, kk, alpha, beta, eps, log, state);
     }
 }
 
@@ -338,11 +345,13 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
 // whole tile as 2 x 2 independent 32 x 32 MFMA blocks over every fourth MFMA
 // step of each 256-byte stage, the four partial tiles meet in LDS
 // (wavefront w keeps sub-tile w, summed over the wavefronts in order), and
-// the epilogue is the update's.  It runs either as one launch per iteration
-// (lowp_fused_kernel, whose extra row of workgroups closes the previous
-// iteration) or resident for the whole run (lowp_resident_kernel).  Both
-// cap registers at two wavefronts per SIMD, so that the closing workgroups
-// find room beside the tiles at once.
+// the epilogue is the update's.  The tiles also close the previous
+// iteration (FusedClose): no workgroup of its own does it, because one
+// sharing a compute unit with a tile slowed that tile by 2 us and with it
+// the whole iteration.  It runs either as one launch per iteration
+// (lowp_fused_kernel; registers capped at two wavefronts per SIMD, which
+// measured 24.0 against 24.6 us per BF16 iteration without the cap) or
+// resident for the whole run (lowp_resident_kernel).
 
 constexpr int kFusedStage = 256;                      // k bytes per row per stage
 constexpr int kFusedSrow = kFusedStage + 16;          // LDS row pitch
@@ -354,8 +363,25 @@ constexpr int kFusedStageLds = 2 * 2 * 64 * kFusedSrow > 4 * 4 * 16 * 64 * 4 ? 2
 struct FusedLds {
     __attribute__((aligned(16))) char stage[kFusedStageLds];
     double red[2][64][4];
+    double close_s[64][4];      // sums of the restarts this tile closes
+    double close_v[256];        // their partial sums, when they number at most 256
     int dead[64];
     int flag;
+};
+
+// The previous iteration's closing, spread over the tiles of a launch: tile
+// x of column block y closes restarts 64 y + x, 64 y + x + tiles, ... (one
+// each when there are 64 row tiles).  Its threads load the restarts' partial
+// sums of every row tile at the start, beside the tile's own operands; one
+// thread per (restart, quantity) adds them in tile order 0 .. tiles - 1 --
+// the order of lowp_close, so the sums are the same bit for bit -- and the
+// restarts are finished in the epilogue.
+struct FusedClose {
+    const double* partials;     // nullptr: nothing to close
+    int64_t kk;
+    double beta, eps;
+    double* log;
+    RestartState* state;
 };
 
 // The tile's slabs of J and of the restart copy, and the thread's chunk of
@@ -385,19 +411,40 @@ __device__ __forceinline__ void fused_fetch_u(i32x4 (&r)[8], const FusedSlab& sl
 // with j_ready the J halves of the first DEPTH stages are already in it
 // (the resident kernel requests them before its barrier: J does not change).
 // Its partial sums go to row tile `tx` of `partials`.
-template <int PREC, int DEPTH>
+// RS_PRE: the FP8 row scales are requested with the other epilogue inputs
+// at the start (registers permitting), else read in the epilogue.  CLOSE:
+// the tile also closes restarts of the previous iteration (fc).
+template <int PREC, int DEPTH, bool RS_PRE, bool CLOSE>
 __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8], bool j_ready, const FusedSlab& sl,
                                            int Rp, int row0, int col0, int tx, const float* __restrict__ rscale,
                                            const float* __restrict__ U_old, float* __restrict__ U_new,
                                            typename Prec<PREC>::T* __restrict__ Ub_new,
                                            const float* __restrict__ cs_old, float* __restrict__ cs_new,
                                            double rho_q, double alpha, int R, double* __restrict__ partials,
-                                           const RestartState* __restrict__ state) {
+                                           const RestartState* __restrict__ state, const FusedClose& fc) {
     using T = typename Prec<PREC>::T;
     using M = Mfma<PREC>;
     constexpr int SROW = kFusedSrow;
     constexpr int FB = M::kBytes / 2;           // fragment bytes per lane
     const int np = static_cast<int>(sl.rowb / sizeof(T));
+    const int tiles = np / 64;
+    // restarts this tile closes: col0 + tx + m * tiles, m < nres; their sums
+    // (nres x tiles x 4) are loaded first and parked in the second stage
+    // buffer, which the k loop first writes after its first barrier
+    const int nres = (CLOSE && fc.partials) ? (tx < 64 ? (64 - tx + tiles - 1) / tiles : 0) : 0;
+    const int ncl = nres * tiles * 4;
+    // up to 256 sums (64 row tiles or fewer): one per thread, held in a
+    // register through the k loop and added in the epilogue, so their
+    // latency is off the path; more (np > 4096) are parked and added before
+    // the k loop, in the second stage buffer, which the loop first writes
+    // after its first barrier
+    const bool cl_small = ncl <= MT;
+    double clv = 0.0;
+    if (cl_small && static_cast<int>(threadIdx.x) < ncl) {
+        const int idx = threadIdx.x;
+        const int m = idx / (tiles * 4), t = (idx >> 2) % tiles, q = idx & 3;
+        clv = fc.partials[(static_cast<size_t>(t) * Rp + col0 + tx + m * tiles) * 4 + q];
+    }
     float* const sred = reinterpret_cast<float*>(L.stage);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -426,9 +473,31 @@ __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8],
         uo_pre[v] = U_old[static_cast<size_t>(row0 + il) * Rp + j];
     }
     float c_in = 1.0f;
-    if constexpr (PREC == 1) c_in = cs_old[j];
+    float rs_pre[16];
+    if constexpr (PREC == 1) {
+        c_in = cs_old[j];
+        if constexpr (RS_PRE) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                rs_pre[v] = rscale[row0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
+        }
+    }
     if (tid < 64) L.dead[tid] = done_m;
+    if (!cl_small) {
+        double* const cl = reinterpret_cast<double*>(L.stage + 2 * 64 * SROW);
+        for (int idx = tid; idx < ncl; idx += MT) {
+            const int m = idx / (tiles * 4), t = (idx >> 2) % tiles, q = idx & 3;
+            cl[idx] = fc.partials[(static_cast<size_t>(t) * Rp + col0 + tx + m * tiles) * 4 + q];
+        }
+    }
     const bool block_live = __syncthreads_or(!done_m) != 0;
+    if (!cl_small && tid < nres * 4) {
+        const double* const cl = reinterpret_cast<const double*>(L.stage + 2 * 64 * SROW);
+        const int m = tid >> 2, q = tid & 3;
+        double sum = 0.0;
+        for (int t = 0; t < tiles; ++t) sum = dadd(sum, cl[(m * tiles + t) * 4 + q]);
+        L.close_s[m][q] = sum;
+    }
 
     f32x16 acc[2][2];
 #pragma unroll
@@ -513,14 +582,19 @@ __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8],
         tile[v] = t;
     }
     __syncthreads();                            // sred is reused below
+    if (cl_small && tid < ncl) L.close_v[tid] = clv;
 
     // ---- epilogue: lane holds column j, rows 8*(v/4) + 4*(lane/32) + v%4
     const bool live = j < R && !done_j;
     double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
     // FP8: scale of the copy read by this product and of the one written now
-    float c_out = 1.0f;
+    float c_out = 1.0f, inv_c = 1.0f;
     if constexpr (PREC == 1) {
         c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
+        // the copy is u times a reciprocal of its scale (v_rcp_f32, within an
+        // ulp): the next product multiplies by the scale itself, and the
+        // carried bound has a margin far beyond an ulp
+        inv_c = __builtin_amdgcn_rcpf(c_out);
         if (row0 == 0 && wr == 0 && lane < 32) cs_new[j] = c_out;
     }
     // transposed low-precision tile: row jl holds rows row0 .. row0+63 of restart j
@@ -533,7 +607,8 @@ __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8],
         const size_t ij = static_cast<size_t>(i) * Rp + j;
         const double uo = static_cast<double>(uo_pre[v]);
         double z = static_cast<double>(tile[v]);
-        if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
+        if (PREC == 1)
+            z = dmul(dmul(z, static_cast<double>(RS_PRE ? rs_pre[v] : rscale[i])), static_cast<double>(c_in));
         float un = uo_pre[v];
         if (live) {
             // the argument in FP64, its cube root in FP32: the result is
@@ -549,7 +624,7 @@ __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8],
             // stays in the buffer the next iteration would otherwise overwrite
             U_new[ij] = un;
         }
-        tileT[jl * TROW + il] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
+        tileT[jl * TROW + il] = to_lowp<PREC>(PREC == 1 ? un * inv_c : un);
     }
     // rows of a column: lanes l and l + 32, then the two row halves of the tile
 #pragma unroll
@@ -559,6 +634,14 @@ __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8],
         for (int q = 0; q < 4; ++q) L.red[wr][jl][q] = part[q];
     }
     __syncthreads();
+    if (cl_small && (tid & 63) < nres) {
+        // quantity q = wave, restart m = lane: four chains per restart at once,
+        // each in tile order
+        const int m = tid & 63, q = tid >> 6;
+        double sum = 0.0;
+        for (int t = 0; t < tiles; ++t) sum = dadd(sum, L.close_v[(m * tiles + t) * 4 + q]);
+        L.close_s[m][q] = sum;
+    }
     {
         // 64 restart rows of 64 * sizeof(T) bytes, in 16-byte chunks
         constexpr int CPR = 64 * static_cast<int>(sizeof(T)) / 16;
@@ -577,6 +660,13 @@ __device__ __forceinline__ void fused_tile(FusedLds& L, i32x4 (&ring)[DEPTH][8],
         for (int q = 0; q < 4; ++q) p[q] = dadd(L.red[0][tid][q], L.red[1][tid][q]);
     }
     __syncthreads();                            // LDS is reused by the next iteration
+    if (tid < nres) {
+        // the restart's stop flag as this launch read it (only this tile
+        // writes its state here)
+        const int off = tx + tid * tiles;
+        const double S[4] = {L.close_s[tid][0], L.close_s[tid][1], L.close_s[tid][2], L.close_s[tid][3]};
+        lowp_close_restart(S, col0 + off, R, fc.kk, alpha, fc.beta, fc.eps, fc.log, fc.state, L.dead[off]);
+    }
 }
 
 template <int PREC>
@@ -593,10 +683,9 @@ __device__ __forceinline__ FusedSlab fused_slab(int np, int row0, int col0, cons
     return sl;
 }
 
-// One launch per iteration; the extra row of workgroups (dispatched after
-// every row tile) closes the previous iteration: workgroup x of it for
-// column block x.  It may run beside the tiles that read the same restart
-// states; a restart it stops is then updated once more into the buffer
+// One launch per iteration; its tiles also close the previous iteration
+// (FusedClose).  A tile may read a restart's state while another tile of the
+// launch stops it; the restart is then updated once more into the buffer
 // after its last iterate, which stays where iters_done says.
 template <int PREC, int DEPTH>
 __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_fused_kernel(
@@ -607,37 +696,30 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
     double alpha, double beta, double eps, int R, int64_t k, const double* __restrict__ partials_prev,
     double* __restrict__ partials, double* __restrict__ log, RestartState* __restrict__ state) {
     __shared__ FusedLds L;
-    const int tiles = np / 64;
-    if (static_cast<int>(blockIdx.y) == Rp / 64) {
-        if (k > 0 && static_cast<int>(blockIdx.x) < Rp / 64)
-            lowp_close(partials_prev, tiles, Rp, blockIdx.x, R, k - 1, alpha, beta, eps, log, state, L.red[0]);
-        return;
-    }
-    if (static_cast<int>(blockIdx.x) >= tiles) return;     // grid padded to the closing row's width
     const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
     const FusedSlab sl = fused_slab<PREC>(np, row0, col0, Jq, Ub_old);
+    const FusedClose fc{k > 0 ? partials_prev : nullptr, k - 1, beta, eps, log, state};
     i32x4 ring[DEPTH][8];
-    fused_tile<PREC, DEPTH>(L, ring, false, sl, Rp, row0, col0, blockIdx.x, rscale, U_old, U_new, Ub_new, cs_old,
-                            cs_new, rho_q, alpha, R, partials, state);
+    fused_tile<PREC, DEPTH, true, true>(L, ring, false, sl, Rp, row0, col0, blockIdx.x, rscale, U_old, U_new, Ub_new, cs_old,
+                            cs_new, rho_q, alpha, R, partials, state, fc);
 }
 
 // ---- the fused iteration resident for the whole run ---------------------
 //
-// One cooperative launch: workgroup t < tiles x cblocks owns a tile for
-// every iteration (the column blocks of a row tile on one XCD, so the J
-// slab they share meets in one L2), the last cblocks workgroups close the
-// iterations.  Between iterations a grid barrier: every wave drains its
+// One cooperative launch: workgroup t owns a tile for every iteration (the
+// column blocks of a row tile on one XCD, so the J slab they share meets in
+// one L2), and closes restarts of the previous iteration as the launches'
+// tiles do.  Between iterations a grid barrier: every wave drains its
 // stores, then one thread per workgroup releases at device scope (the
 // restart copy crosses XCDs, whose L2 caches are not coherent with each
 // other), counts the workgroup in (a counter per group of workgroups, then
 // one for the groups) and polls its group's release word, and acquires at
 // device scope.  The J halves of the next iteration's first stages are
-// requested before the barrier: J does not change.  Closing workgroup c
-// closes iteration k after barrier k + 1 and arrives at barrier k + 2 when
-// done, so a restart it stops is seen by the tiles two iterations later;
-// the three rotating buffers keep its last iterate.  Every wait is bounded:
-// a workgroup that polls too long marks every restart aborted and publishes
-// a stop that every other one sees at its next poll.
+// requested before the barrier: J does not change.  A restart stopped by
+// the closing in iteration k is seen from iteration k + 1 on, as with the
+// launches, so both give the same iterates bit for bit.  Every wait is
+// bounded: a workgroup that polls too long marks every restart aborted and
+// publishes a stop that every other one sees at its next poll.
 struct LowpResArgs {
     int np, Rp, R, tiles, cblocks;
     int64_t iters;
@@ -700,20 +782,10 @@ __device__ bool lowp_barrier(ResidentSync* sy, unsigned int gen, RestartState* s
 }
 
 template <int PREC, int DEPTH>
-__global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lowp_resident_kernel(LowpResArgs a) {
+__global__ __launch_bounds__(MT) void lowp_resident_kernel(LowpResArgs a) {
     using T = typename Prec<PREC>::T;
     __shared__ FusedLds L;
-    const int ntile = a.tiles * a.cblocks;
     const int b = blockIdx.x;
-    if (b >= ntile) {
-        const int cb = b - ntile;
-        for (int64_t k = 0; k < a.iters; ++k) {
-            if (!lowp_barrier(a.sync, static_cast<unsigned int>(k + 1), a.state, a.R, L)) return;
-            lowp_close(a.partials[k & 1], a.tiles, a.Rp, cb, a.R, k, a.alpha, a.beta, a.eps, a.log, a.state,
-                       L.red[0]);
-        }
-        return;
-    }
     // tile: the cblocks column blocks of a row tile on one XCD (workgroup b
     // runs on XCD b mod 8 under round-robin dispatch)
     int tx, ty;
@@ -732,15 +804,15 @@ __global__ __launch_bounds__(MT) __attribute__((amdgpu_waves_per_eu(2))) void lo
         const int o = static_cast<int>(k % 3), n = static_cast<int>((k + 1) % 3);
         if (k > 0 && !lowp_barrier(a.sync, static_cast<unsigned int>(k), a.state, a.R, L)) return;
         const FusedSlab sl = fused_slab<PREC>(a.np, row0, col0, Jq, static_cast<const T*>(a.Ub[o]));
-        fused_tile<PREC, DEPTH>(L, ring, k > 0, sl, a.Rp, row0, col0, tx, a.rscale, a.U[o], a.U[n],
-                                static_cast<T*>(a.Ub[n]), a.cs[o], a.cs[n], a.rho_q, a.alpha, a.R,
-                                a.partials[k & 1], a.state);
+        const FusedClose fc{k > 0 ? a.partials[(k - 1) & 1] : nullptr, k - 1, a.beta, a.eps, a.log, a.state};
+        fused_tile<PREC, DEPTH, true, true>(L, ring, k > 0, sl, a.Rp, row0, col0, tx, a.rscale, a.U[o], a.U[n],
+                                            static_cast<T*>(a.Ub[n]), a.cs[o], a.cs[n], a.rho_q, a.alpha, a.R,
+                                            a.partials[k & 1], a.state, fc);
         if (k + 1 < a.iters) {
 #pragma unroll
             for (int p = 0; p < DEPTH; ++p) fused_fetch_j<DEPTH>(ring[p], sl, p);
         }
     }
-    (void)lowp_barrier(a.sync, static_cast<unsigned int>(a.iters), a.state, a.R, L);
 }
 
 // ---- the update: sum of the splits, eq:FPE in u, partial sums ----------
@@ -782,10 +854,14 @@ __global__ __launch_bounds__(MT) void lowp_update_kernel(
     if (tid < 64) sdead[tid] = dead;
     const bool live = !dead;
     // FP8: scale of the copy read by this product and of the one written now
-    float c_in = 1.0f, c_out = 1.0f;
+    float c_in = 1.0f, c_out = 1.0f, inv_c = 1.0f;
     if constexpr (PREC == 1) {
         c_in = cs_old[j];
         c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
+        // the copy is u times a reciprocal of its scale (v_rcp_f32, within an
+        // ulp): the next product multiplies by the scale itself, and the
+        // carried bound has a margin far beyond an ulp
+        inv_c = __builtin_amdgcn_rcpf(c_out);
         if (blockIdx.x == 0 && rg == 0) cs_new[j] = c_out;
     }
     double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
@@ -813,7 +889,7 @@ __global__ __launch_bounds__(MT) void lowp_update_kernel(
             // stays in the buffer the next iteration would otherwise overwrite
             U_new[base + static_cast<size_t>(v) * Rp] = un;
         }
-        tileT[jl * TROW + rg * 16 + v] = to_lowp<PREC>(PREC == 1 ? un / c_out : un);
+        tileT[jl * TROW + rg * 16 + v] = to_lowp<PREC>(PREC == 1 ? un * inv_c : un);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[rg][jl][q] = part[q];
@@ -1193,10 +1269,9 @@ hipError_t launch_lowp_step(int prec, int np, int Rp, const LowpShape& sh, const
                             double* partials, double* log, RestartState* state, hipStream_t s) {
     if (!lowp_shape_valid(prec, np, Rp, sh)) return hipErrorInvalidValue;
     if (sh.splits == 0) {
-        // np / 64 row tiles per column block, and one more row of workgroups
-        // whose first Rp / 64 close the previous iteration
-        const int tiles = np / 64, cblocks = Rp / 64;
-        const dim3 grid(tiles > cblocks ? tiles : cblocks, cblocks + 1);
+        // np / 64 row tiles per column block; the tiles close the previous
+        // iteration themselves
+        const dim3 grid(np / 64, Rp / 64);
 #define DOCH_LOWP_FUSED(PP, DD)                                                                                 \
     hipLaunchKernelGGL((lowp_fused_kernel<PP, DD>), grid, dim3(MT), 0, s, np, Rp,                              \
                        static_cast<const Prec<PP>::T*>(Jq), rscale, U_old, U_new,                              \
@@ -1240,7 +1315,7 @@ hipError_t launch_resident_one(const LowpResArgs& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         cap = cus * occ;
     }
-    const int groups = a.tiles * a.cblocks + a.cblocks;
+    const int groups = a.tiles * a.cblocks;
     if (groups > cap) return hipErrorCooperativeLaunchTooLarge;
     LowpResArgs arg = a;
     void* args[] = {&arg};
