@@ -16,14 +16,25 @@
 
 namespace doch {
 
-// Store this workgroup's 7 R sums and, in the last workgroup to arrive,
-// close the iteration.  acc: thread 0's workgroup totals (restart r at 7 r).
-template <int R, int NT, bool FIELD>
-__device__ __forceinline__ void adoch_mv_close(double (&acc)[7 * R], double* red, int* last_flag, int64_t n,
-                                               const double* __restrict__ x, const double* __restrict__ xp,
-                                               const double* __restrict__ zp, double* __restrict__ z,
-                                               const AdochArgs& a) {
-    constexpr int K = 7 * R;
+// Store this workgroup's S R sums and, in the last workgroup to arrive,
+// close the iteration.  acc: thread 0's workgroup totals (restart r at S r,
+// S = 7, or 8 with OPT).
+//
+// OPT (the CSR product that has already written x^(k+1) = T(y^(k)) for every
+// restart that had not stopped, and copied stopped ones forward): the eighth
+// sum is |T(y) - x^(k)|^2, so an accepted restart is closed here, r^(k)
+// and Remark S2's test included.  A rejected restart is left to the fix-up
+// launch (fix[r] = 1: x^(k+1) = T(x^(k)) recomputed), so is one whose H(x)
+// is not finite (fix[r] = 2: x^(k) copied forward); fix[8] says whether any
+// is pending, and all_done is raised here only when none is.
+template <int R, int NT, bool FIELD, bool OPT = false>
+__device__ __forceinline__ void adoch_mv_close(double (&acc)[(OPT ? 8 : 7) * R], double* red, int* last_flag,
+                                               int64_t n, const double* __restrict__ x,
+                                               const double* __restrict__ xp, const double* __restrict__ zp,
+                                               double* __restrict__ z, const AdochArgs& a,
+                                               double* __restrict__ xn = nullptr) {
+    constexpr int S = OPT ? 8 : 7;
+    constexpr int K = S * R;
     if (threadIdx.x == 0) {
         double* p = a.partials + static_cast<size_t>(blockIdx.x) * K;
 #pragma unroll
@@ -43,10 +54,15 @@ __device__ __forceinline__ void adoch_mv_close(double (&acc)[7 * R], double* red
     const double c = a.c;
     const double b4 = ddiv(a.beta, 4.0), a2 = ddiv(a.alpha, 2.0);
     const int W = a.q + 1;
+    int pending = 0, all = 1;
     for (int r = 0; r < R; ++r) {
         RestartState& st = a.state[r];
-        if (st.done) continue;
-        double* ur = u + 7 * r;
+        if (OPT) a.fix[r] = 0;
+        if (st.done) {
+            if (OPT && FIELD) xn[n * R + r] = x[n * R + r];
+            continue;
+        }
+        double* ur = u + S * r;
         if (FIELD) {
             // the extra spin's row: z_n = sum_i h_i x_i, and its share of every sum
             const int64_t tn = n * R + r;
@@ -62,6 +78,12 @@ __device__ __forceinline__ void adoch_mv_close(double (&acc)[7 * R], double* red
             ur[3] = dadd(ur[3], dmul(y2, y2));
             ur[4] = dadd(ur[4], y2);
             ur[5] = dadd(ur[5], dmul(yn, jyn));
+            if (OPT) {
+                const double nx = cbrt(ddiv(dadd(jyn, dmul(a.alpha, yn)), a.beta));
+                xn[tn] = nx;
+                const double d = dsub(nx, tx);
+                ur[7] = dadd(ur[7], dmul(d, d));
+            }
         }
         const double Hx = dsub(dsub(dmul(b4, ur[0]), dmul(a2, ur[1])), dmul(0.5, ur[2]));
         const double Hy = dsub(dsub(dmul(b4, ur[3]), dmul(a2, ur[4])), dmul(0.5, ur[5]));
@@ -80,7 +102,31 @@ __device__ __forceinline__ void adoch_mv_close(double (&acc)[7 * R], double* red
             st.nonfinite = 1;
             st.done = 1;
             st.iters_done = a.k + 1;
+            if (OPT) {
+                a.fix[r] = 2;
+                pending = 1;
+            }
+        } else if (OPT && !accept) {
+            a.fix[r] = 1;
+            pending = 1;
+        } else if (OPT) {
+            const double rr = ur[1] == 0.0 ? 0.0 : ddiv(sqrt(ur[7]), sqrt(ur[1]));
+            a.log[(static_cast<size_t>(a.k) * R + r) * 2 + 1] = rr;
+            st.iters_done = a.k + 1;
+            st.r_last = rr;
+            if (!isfinite(rr)) {
+                st.nonfinite = 1;
+                st.done = 1;
+            } else if (a.eps > 0.0 && rr < a.eps) {
+                st.converged = 1;
+                st.done = 1;
+            }
         }
+        all &= st.done;
+    }
+    if (OPT) {
+        a.fix[8] = pending;
+        if (!pending && all) *a.all_done = 1;
     }
     reset_ticket(a.ticket);
 }

@@ -391,13 +391,13 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
         HIP_OK(dev_alloc(&ctx->ad_ring, static_cast<size_t>(R) * (p.q + 1) * sizeof(double)), "hipMalloc(ring)");
         ctx->ad_ring_cap = R * (p.q + 1);
     }
-    // decisions [R] and the all-done flag (word 64)
+    // decisions [R], the fix-up marks (words 16 to 24) and the all-done flag (word 64)
     if (!ctx->ad_accept) HIP_OK(dev_alloc(&ctx->ad_accept, 512), "hipMalloc(accept)");
     HIP_OK(ensure(&ctx->ad_acclog, &ctx->ad_acclog_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R),
            "hipMalloc(accept log)");
     const int mv_grid = ctx->dense ? doch::adoch_dense_grid(dense_view(ctx)) : doch::adoch_grid(ctx->n);
     const int up_grid = doch::adoch_grid(ctx->np * R);
-    const size_t pd = std::max(static_cast<size_t>(mv_grid) * 7 * R, static_cast<size_t>(up_grid) * 2 * R);
+    const size_t pd = std::max(static_cast<size_t>(mv_grid) * 8 * R, static_cast<size_t>(up_grid) * 2 * R);
     HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes, pd * sizeof(double)), "hipMalloc(partials)");
     if (!ctx->ticket) {
         HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
@@ -422,6 +422,7 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
     a.log = ctx->log;
     a.accept = ctx->ad_accept;
     a.all_done = ctx->ad_accept + 64;
+    a.fix = ctx->ad_accept + 16;
     a.accept_log = ctx->ad_acclog;
     a.ring = ctx->ad_ring;
     a.state = ctx->state;
@@ -437,11 +438,13 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
         double* xn = ctx->ad_x[(k + 1) % 3];
         double* z = ctx->ad_z[k % 2];
         const double* zp = ctx->ad_z[(k + 1) % 2];
+        // CSR: the product writes x^(k+1) of an accepted y itself; the update
+        // launch only repairs rejected restarts (and returns at once if none)
         if (ctx->dense)
             HIP_OK(doch::launch_adoch_dense_mv(dv, x, xp, zp, z, a, s), "ADOCH matvec");
         else
-            HIP_OK(doch::launch_adoch_mv(cv, x, xp, zp, z, a, s), "ADOCH matvec");
-        HIP_OK(doch::launch_adoch_update(ctx->np, x, xp, z, zp, xn, a, s), "ADOCH update");
+            HIP_OK(doch::launch_adoch_mv(cv, x, xp, zp, z, xn, a, s), "ADOCH matvec");
+        HIP_OK(doch::launch_adoch_update(ctx->np, x, xp, z, zp, xn, a, !ctx->dense, s), "ADOCH update");
         t = t_next;
     }
     ctx->last_R = R;

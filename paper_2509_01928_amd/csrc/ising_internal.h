@@ -265,6 +265,7 @@ struct AdochArgs {
     double* log;              // [iters][R][2]: (H(x^(k)), r^(k))
     int* accept;              // [R]: decision of iteration k
     int* all_done;            // every restart stopped: later launches return at once
+    int* fix;                 // [R] + word 8: fix-ups left by the optimistic CSR product
     int8_t* accept_log;       // [iters][R]
     double* ring;             // [R][q + 1]: last q+1 values of H(x)
     RestartState* state;      // [R]
@@ -482,15 +483,18 @@ hipError_t launch_dense_objective(const double* J, int n, int R, const double* X
                                   hipStream_t s);
 
 // ---- launchers (kernels_adoch.hip, kernels_dense.hip) ----
-// Workgroups of the ADOCH launches (partial sums: 7 R doubles per workgroup).
+// Workgroups of the ADOCH launches (partial sums: 7 R doubles per workgroup,
+// 8 R for the optimistic CSR product).
 int adoch_grid(int64_t n);
 int adoch_dense_grid(const DenseView& A);
+// xn non-null: the optimistic product, which writes x^(k+1) = T(y^(k)) and
+// closes accepted restarts; follow it with launch_adoch_update(fixup = true).
 hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, const double* zp,
-                           double* z, const AdochArgs& a, hipStream_t s);
+                           double* z, double* xn, const AdochArgs& a, hipStream_t s);
 hipError_t launch_adoch_dense_mv(const DenseView& A, const double* x, const double* xp, const double* zp,
                                  double* z, const AdochArgs& a, hipStream_t s);
 hipError_t launch_adoch_update(int64_t np, const double* x, const double* xp, const double* z,
-                               const double* zp, double* xn, const AdochArgs& a, hipStream_t s);
+                               const double* zp, double* xn, const AdochArgs& a, bool fixup, hipStream_t s);
 hipError_t launch_adoch_finish(const double* b0, const double* b1, const double* b2,
                                const RestartState* st, int64_t n, int64_t np, int R, bool field,
                                double* x_out, int8_t* s_out, hipStream_t s);

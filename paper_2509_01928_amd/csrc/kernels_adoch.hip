@@ -10,8 +10,13 @@
 //                       last workgroup finishes both, keeps the window of
 //                       the last q+1 values of H(x) and decides whether y is
 //                       accepted (H(y) <= max of the window), per restart;
+//                       on CSR it also writes x^(k+1) = T(y^(k)) before that
+//                       decision is known, with the sums of r^(k), and
+//                       closes every restart whose y is accepted;
 //   adoch_update_kernel x^(k+1) = cbrt((Jhat v + alpha v) / beta) elementwise
-//                       (the extra field spin included) and r^(k).
+//                       (the extra field spin included) and r^(k): after
+//                       the dense product for every restart, after the CSR
+//                       one only for those whose y was rejected.
 // R restarts (1, 2, 4 or 8) run together, interleaved (entry (i, r) at
 // i R + r), each with its own window, decisions and stopping; a stopped
 // restart is copied forward unchanged.  Iterates rotate through three
@@ -30,23 +35,38 @@ constexpr int NW = NT / kWave;
 // RL = 4: every row holds 4 entries starting at 4 i (the lattice), read as
 // one 16-byte chunk of indices and one of values without the row offsets;
 // RL = 0: offsets read, entries one at a time.  Same order either way.
-template <typename VT, typename HT, bool FIELD, int RL, int R>
+//
+// OPT: the product also writes x^(k+1) = T(y^(k)) = cbrt((Jhat y + alpha y)
+// / beta) of every restart that has not stopped (a stopped one is copied
+// forward), optimistically, before the acceptance test that follows the
+// global sums, and adds |T(y) - x^(k)|^2 as an eighth sum.  y is taken far
+// more often than not, and then x^(k+1) and r^(k) are final when the launch
+// ends: the second pass over x^(k), x^(k-1), z_k, z_(k-1) and x^(k+1) is
+// made only for a rejected restart (adoch_update_kernel's fix-up mode).
+// The value written is the one the update would write, bit for bit.
+template <typename VT, typename HT, bool FIELD, int RL, int R, bool OPT>
 __global__ __launch_bounds__(NT) void adoch_mv_kernel(
     int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const VT* __restrict__ val, const HT* __restrict__ h, const double* __restrict__ x,
     const double* __restrict__ xp, const double* __restrict__ zp, double* __restrict__ z,
-    AdochArgs a) {
+    double* __restrict__ xn, AdochArgs a) {
     if (*a.all_done) return;
-    __shared__ double red[7 * R * NW];
+    constexpr int S = OPT ? 8 : 7;
+    __shared__ double red[S * R * NW];
     __shared__ int last_flag;
     const double c = a.c;
+    const double al = a.alpha, be = a.beta;
     double tx[R];
+    bool live[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) tx[r] = FIELD ? x[n * R + r] : 0.0;
-    // per restart: x^4, x^2, x z, y^4, y^2, y (Jy), h x
-    double acc[7 * R];
+    for (int r = 0; r < R; ++r) {
+        tx[r] = FIELD ? x[n * R + r] : 0.0;
+        live[r] = OPT ? a.state[r].done == 0 : true;
+    }
+    // per restart: x^4, x^2, x z, y^4, y^2, y (Jy), h x [, |T(y) - x|^2]
+    double acc[S * R];
 #pragma unroll
-    for (int q = 0; q < 7 * R; ++q) acc[q] = 0.0;
+    for (int q = 0; q < S * R; ++q) acc[q] = 0.0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * NT) {
         double zi[R];
@@ -83,44 +103,62 @@ __global__ __launch_bounds__(NT) void adoch_mv_kernel(
             double zr = zi[r];
             if (FIELD) {
                 zr = dadd(zr, dmul(hi, tx[r]));
-                acc[7 * r + 6] = dadd(acc[7 * r + 6], dmul(hi, xi));
+                acc[S * r + 6] = dadd(acc[S * r + 6], dmul(hi, xi));
             }
             z[t] = zr;
             const double yi = dadd(xi, dmul(c, dsub(xi, xp[t])));
             const double jy = dsub(dmul(dadd(1.0, c), zr), dmul(c, zp[t]));
             const double x2 = dmul(xi, xi), y2 = dmul(yi, yi);
-            acc[7 * r + 0] = dadd(acc[7 * r + 0], dmul(x2, x2));
-            acc[7 * r + 1] = dadd(acc[7 * r + 1], x2);
-            acc[7 * r + 2] = dadd(acc[7 * r + 2], dmul(xi, zr));
-            acc[7 * r + 3] = dadd(acc[7 * r + 3], dmul(y2, y2));
-            acc[7 * r + 4] = dadd(acc[7 * r + 4], y2);
-            acc[7 * r + 5] = dadd(acc[7 * r + 5], dmul(yi, jy));
+            acc[S * r + 0] = dadd(acc[S * r + 0], dmul(x2, x2));
+            acc[S * r + 1] = dadd(acc[S * r + 1], x2);
+            acc[S * r + 2] = dadd(acc[S * r + 2], dmul(xi, zr));
+            acc[S * r + 3] = dadd(acc[S * r + 3], dmul(y2, y2));
+            acc[S * r + 4] = dadd(acc[S * r + 4], y2);
+            acc[S * r + 5] = dadd(acc[S * r + 5], dmul(yi, jy));
+            if constexpr (OPT) {
+                double nx = xi;
+                if (live[r]) {
+                    nx = cbrt(ddiv(dadd(jy, dmul(al, yi)), be));
+                    const double d = dsub(nx, xi);
+                    acc[S * r + 7] = dadd(acc[S * r + 7], dmul(d, d));
+                }
+                xn[t] = nx;
+            }
         }
     }
-    block_sum<7 * R, NT>(acc, red);
-    adoch_mv_close<R, NT, FIELD>(acc, red, &last_flag, n, x, xp, zp, z, a);
+    block_sum<S * R, NT>(acc, red);
+    adoch_mv_close<R, NT, FIELD, OPT>(acc, red, &last_flag, n, x, xp, zp, z, a, xn);
 }
 
 // x^(k+1) of every restart that has not stopped (a stopped one is copied
 // forward), and r^(k) = |x^(k+1) - x^(k)| / |x^(k)| per restart; the last
 // workgroup applies Remark S2's test and raises all_done when every restart
 // has stopped.
-template <int R>
+//
+// FIXUP (after the optimistic CSR product): only the restarts the product's
+// closing step marked are touched: fix = 1 (y rejected) gets x^(k+1) =
+// T(x^(k)) and its r^(k) and stopping test here, fix = 2 (H(x^(k)) not
+// finite) has x^(k) copied forward; the launch returns at once when nothing
+// is marked, and its last workgroup clears the marks.
+template <int R, bool FIXUP>
 __global__ __launch_bounds__(NT) void adoch_update_kernel(
     int64_t np, const double* __restrict__ x, const double* __restrict__ xp,
     const double* __restrict__ z, const double* __restrict__ zp, double* __restrict__ xn,
     AdochArgs a) {
     if (*a.all_done) return;
+    if (FIXUP && !a.fix[8]) return;
     __shared__ double red[2 * R * NW];
     __shared__ int last_flag;
     const double c = a.c;
     // a thread's entries t = i R + r all have the same restart r (the grid
     // stride is a multiple of R)
     const int myr = static_cast<int>((static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x) % R);
-    const bool stopped = a.state[myr].done != 0;
-    const bool acc_y = a.accept[myr] != 0;
+    const int code = FIXUP ? a.fix[myr] : 0;
+    const bool stopped = FIXUP ? code == 2 : a.state[myr].done != 0;
+    const bool acc_y = FIXUP ? false : a.accept[myr] != 0;
+    const bool idle = FIXUP && code == 0;
     double d2 = 0.0, x2 = 0.0;        // (x^(k+1) - x^(k))^2, x^(k)^2
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; t < np * R;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; t < np * R && !idle;
          t += static_cast<int64_t>(gridDim.x) * NT) {
         const double xi = x[t];
         if (stopped) {
@@ -164,7 +202,9 @@ __global__ __launch_bounds__(NT) void adoch_update_kernel(
     int all = 1;
     for (int r = 0; r < R; ++r) {
         RestartState* st = a.state + r;
-        if (!st->done) {
+        const bool mine = FIXUP ? a.fix[r] == 1 : !st->done;
+        if (FIXUP) a.fix[r] = 0;
+        if (mine) {
             const double rr = u[2 * r + 1] == 0.0 ? 0.0 : ddiv(sqrt(u[2 * r]), sqrt(u[2 * r + 1]));
             a.log[(static_cast<size_t>(a.k) * R + r) * 2 + 1] = rr;
             st->iters_done = a.k + 1;
@@ -179,6 +219,7 @@ __global__ __launch_bounds__(NT) void adoch_update_kernel(
         }
         all &= st->done;
     }
+    if (FIXUP) a.fix[8] = 0;
     if (all) *a.all_done = 1;
     reset_ticket(a.ticket);
 }
@@ -232,39 +273,51 @@ int adoch_grid(int64_t n) { return grid_rows(n); }
 
 template <typename VT, typename HT, bool F, int RR>
 static void adoch_mv_go(const CsrView& A, int grid, const double* x, const double* xp, const double* zp,
-                        double* z, const AdochArgs& a, hipStream_t s) {
-    if (A.row_len == 4)
-        hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4, RR>), dim3(grid), dim3(NT), 0, s, A.n, A.rp, A.col,
-                           static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), x, xp, zp, z, a);
+                        double* z, double* xn, const AdochArgs& a, hipStream_t s) {
+    const VT* v = static_cast<const VT*>(A.val);
+    const HT* h = static_cast<const HT*>(A.h);
+    if (A.row_len == 4 && xn)
+        hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4, RR, true>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, x, xp, zp, z, xn, a);
+    else if (A.row_len == 4)
+        hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4, RR, false>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, x, xp, zp, z, xn, a);
+    else if (xn)
+        hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 0, RR, true>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, x, xp, zp, z, xn, a);
     else
-        hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 0, RR>), dim3(grid), dim3(NT), 0, s, A.n, A.rp, A.col,
-                           static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), x, xp, zp, z, a);
+        hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 0, RR, false>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, x, xp, zp, z, xn, a);
 }
 
 template <typename VT, int RR>
 static void adoch_mv_vt(const CsrView& A, int grid, const double* x, const double* xp, const double* zp,
-                        double* z, const AdochArgs& a, hipStream_t s) {
-    if (!A.h) adoch_mv_go<VT, float, false, RR>(A, grid, x, xp, zp, z, a, s);
-    else if (A.ht == ISING_F64) adoch_mv_go<VT, double, true, RR>(A, grid, x, xp, zp, z, a, s);
-    else adoch_mv_go<VT, float, true, RR>(A, grid, x, xp, zp, z, a, s);
+                        double* z, double* xn, const AdochArgs& a, hipStream_t s) {
+    if (!A.h) adoch_mv_go<VT, float, false, RR>(A, grid, x, xp, zp, z, xn, a, s);
+    else if (A.ht == ISING_F64) adoch_mv_go<VT, double, true, RR>(A, grid, x, xp, zp, z, xn, a, s);
+    else adoch_mv_go<VT, float, true, RR>(A, grid, x, xp, zp, z, xn, a, s);
 }
 
 hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, const double* zp,
-                           double* z, const AdochArgs& a, hipStream_t s) {
+                           double* z, double* xn, const AdochArgs& a, hipStream_t s) {
     const int grid = grid_rows(A.n);
     DOCH_ADOCH_R(a.R, {
-        if (A.vt == ISING_I16) adoch_mv_vt<int16_t, RR>(A, grid, x, xp, zp, z, a, s);
-        else if (A.vt == ISING_F64) adoch_mv_vt<double, RR>(A, grid, x, xp, zp, z, a, s);
-        else adoch_mv_vt<float, RR>(A, grid, x, xp, zp, z, a, s);
+        if (A.vt == ISING_I16) adoch_mv_vt<int16_t, RR>(A, grid, x, xp, zp, z, xn, a, s);
+        else if (A.vt == ISING_F64) adoch_mv_vt<double, RR>(A, grid, x, xp, zp, z, xn, a, s);
+        else adoch_mv_vt<float, RR>(A, grid, x, xp, zp, z, xn, a, s);
     });
     return hipGetLastError();
 }
 
 hipError_t launch_adoch_update(int64_t np, const double* x, const double* xp, const double* z,
-                               const double* zp, double* xn, const AdochArgs& a, hipStream_t s) {
+                               const double* zp, double* xn, const AdochArgs& a, bool fixup, hipStream_t s) {
     const int grid = grid_rows(np * a.R);
     DOCH_ADOCH_R(a.R, {
-        hipLaunchKernelGGL(adoch_update_kernel<RR>, dim3(grid), dim3(NT), 0, s, np, x, xp, z, zp, xn, a);
+        if (fixup)
+            hipLaunchKernelGGL((adoch_update_kernel<RR, true>), dim3(grid), dim3(NT), 0, s, np, x, xp, z, zp, xn, a);
+        else
+            hipLaunchKernelGGL((adoch_update_kernel<RR, false>), dim3(grid), dim3(NT), 0, s, np, x, xp, z, zp, xn,
+                               a);
     });
     return hipGetLastError();
 }

@@ -145,6 +145,36 @@ def test_adoch_csr_restarts_stop_each_on_its_own():
                   acc[:k, rr], k, False, end_fixed_point=False)
 
 
+def test_adoch_csr_rejections_mixed_across_restarts():
+    """The CSR product writes x^(k+1) = T(y) before the acceptance test and
+    a second launch repairs only the restarts whose y was rejected.  With
+    eta = 0.25 the lattice with its field rejects y often before H settles,
+    in different iterations for different restarts: every restart must
+    follow its own oracle run through those iterations (field spin
+    included) and reach the same fixed point."""
+    import paper_2509_01928_amd as L
+    from tests._util import GpuProblem
+    A = gen.torus_csr(40, 133, h_std=0.1)
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B, 0.25)
+    R, q, iters = 4, 5, 300
+    X0 = gen.uniform_x0(B.n, R, 135)
+    trs = [orc.adoch(B, X0[:, rr], alpha, beta, iters, q) for rr in range(R)]
+    clear = [np.abs(t.Hy - t.Hmax) > TIE_RTOL * (np.abs(t.Hy) + np.abs(t.Hmax)) for t in trs]
+    rej = np.array([(t.accept == 0) & c for t, c in zip(trs, clear)])
+    assert all(rj.sum() >= 10 for rj in rej), "the seeded restarts should reject y often"
+    assert (rej.any(axis=0) & ~rej.all(axis=0)).sum() >= 10, "rejections should differ across restarts"
+    P = GpuProblem(A=A)
+    try:
+        x, s, st, logs, acc = run_gpu(P.ctx, L, X0, R, iters, alpha, beta, q, 0.0, B.n, A.n)
+    finally:
+        P.close()
+    for rr in range(R):
+        assert st[rr].iters_done == iters, rr
+        check_run(f"lattice restart {rr}", trs[rr], x[:, rr], s[:, rr], logs[rr][0], logs[rr][1],
+                  acc[:, rr], iters, True)
+
+
 def test_adoch_refused_shapes():
     import torch
     import paper_2509_01928_amd as L
