@@ -61,7 +61,8 @@ def parse():
                     help="batch512: launch shape 'rj,wg,chunk_rows' instead of the autotuner's")
     ap.add_argument("--lowp-shape", default="",
                     help="dense4096: bn,splits,stage_bytes,depth of the matrix-core product instead of the "
-                         "tuned one (splits 0: the fused iteration)")
+                         "tuned one (splits 0: the fused iteration, -1: resident, -2: J held in LDS); "
+                         "'BF16 shape/FP8 shape' to give each format its own")
     ap.add_argument("--tune-cache",
                     default=os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
                                          "paper_2509_01928_amd", "launch_shapes.json"),
@@ -518,7 +519,9 @@ def bench_dense4096(args):
         Hf = torch.empty(R, dtype=torch.float64, device=d)
         Eb = torch.empty(R, dtype=torch.float64, device=d)
         if args.lowp_shape:
-            shape = tuple(int(v) for v in args.lowp_shape.split(","))
+            spec = args.lowp_shape.split("/")
+            spec = spec[0] if name == "bf16" or len(spec) == 1 else spec[1]
+            shape = tuple(int(v) for v in spec.split(","))
             L.ising_set_lowp_shape(ctx, *shape)
             tune = {"source": "flag"}
         else:
@@ -564,11 +567,10 @@ def bench_dense4096(args):
                    "restarts": nplain, "mean": float(g64.mean()), "min": float(g64.min()),
                    "max": float(g64.max()), "lower_or_equal_fraction": float(np.mean(g64 <= 0))},
                "launch_shape": {"bn": shape[0], "splits": shape[1], "stage_bytes": shape[2], "depth": shape[3],
-                                "kind": "fused" if shape[1] == 0 else "split product + update"},
+                                "kind": LOWP_KIND[min(shape[1], 1)]},
                "autotune": tune,
                "roofline": {"bound": "mfma",
-                            "kernel": ("lowp_fused_kernel" if shape[1] == 0 else
-                                       "lowp_gemm_kernel + lowp_update_kernel"),
+                            "kernel": LOWP_KERNEL[min(shape[1], 1)],
                             "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak,
                             "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / peak}}
         if E_or is not None:
@@ -583,6 +585,13 @@ def bench_dense4096(args):
     out["vs_fp64_plain"] = out["bf16"]["restarts_per_s"] / out["fp64_plain"]["restarts_per_s"]
     print(json.dumps(out), flush=True)
     L.ising_destroy(ctx)
+
+
+# launch shapes of the dense low-precision path, by their splits field
+LOWP_KIND = {-2: "J held in LDS, resident (split k over the device, two grid barriers per iteration)",
+             -1: "fused, resident", 0: "fused (a launch per iteration)", 1: "split product + update"}
+LOWP_KERNEL = {-2: "lowp_held_kernel", -1: "lowp_resident_kernel", 0: "lowp_fused_kernel",
+               1: "lowp_gemm_kernel + lowp_update_kernel"}
 
 
 def bench_batch512(args):

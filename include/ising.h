@@ -320,29 +320,41 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
  * splits = -1 runs that iteration resident, every iteration in one
  * cooperative launch with grid barriers between them (depth 2; when its
  * grid does not fit on the device at once, or for more than 10^8
- * iterations, the call runs the fused launches instead).  All shapes compute the same products, in a different
- * order of FP32 additions; the resident run and the fused launches are
- * identical bit for bit.  bn = 0 restores the default, the fused iteration
- * (depth 3 in BF16 where the padded order holds three stages, else 2).  A shape that does not fit a later call (bn not
- * dividing the padded restart count, or a split holding fewer than `depth`
- * whole stages) falls back to the default for that call.  The shape changes
- * the order of the FP32 additions, nothing else.
- * Errors: ISING_E_INVALID_ARG for a value outside those sets, or for
- * splits 0 or -1 with bn != 64 or stage_bytes != 256. */
+ * iterations, the call runs the fused launches instead).  splits = -2
+ * holds J in LDS for the whole run (bn 128, depth 1): one cooperative
+ * launch of a workgroup per (128-row block, k slice of stage_bytes = 256,
+ * 512 or 1024 bytes per row, at most 8 slices); per iteration every
+ * workgroup multiplies its slice with the restart copy into FP32 partial
+ * products, a grid barrier, the update adds the slices in order, a grid
+ * barrier (when the workgroups do not fit on the device at once, or the run
+ * is too long for the barrier's 32-bit counts -- 2 x iters x workgroups / 8
+ * must stay below 2^31 -- the call runs the fused launches instead).  All
+ * shapes compute the same products, in a different order of FP32
+ * additions; the resident run and the fused launches are identical bit for
+ * bit.  bn = 0 restores the default, the fused iteration (depth 3 in BF16
+ * where the padded order holds three stages, else 2).  A shape that does
+ * not fit a later call (bn not dividing the padded restart count, a split
+ * holding fewer than `depth` whole stages, a held slice not dividing the
+ * padded row or more than 8 slices) falls back to the default for that
+ * call.  The shape changes the order of the FP32 additions, nothing else.
+ * Errors: ISING_E_INVALID_ARG for a value outside those sets, for splits 0
+ * or -1 with bn != 64 or stage_bytes != 256, or for splits -2 with bn !=
+ * 128, depth != 1 or another slice width. */
 ising_status ising_set_lowp_shape(ising_ctx* ctx, int32_t bn, int32_t splits, int32_t stage_bytes,
                                   int32_t depth);
 
 /* Choose the shape of ising_solve_lowp for this context, restart count and
- * format by timing: every shape of ising_set_lowp_shape that fits (the
- * fused iteration as launches and as a resident run, and the split product
- * over tile widths, splits, stage widths and depths) runs `iters`
+ * format by timing: every shape of ising_set_lowp_shape that fits (J held
+ * in LDS over its slice widths, the fused iteration as launches and as a
+ * resident run, and the split product over tile widths, splits, stage
+ * widths and depths) runs `iters`
  * iterations from x0_dev twice, the second timed on `stream`; the fastest
  * becomes this context's shape.  With
  * cache_path non-NULL the choice is looked up first and stored after tuning
  * in a JSON file of one entry per line, keyed by device name, compute-unit
  * count, format, padded order, padded restart count and iters.
- *   shape_out       NULL or int32[4]: bn, splits (0 fused, -1 resident),
- *                   stage_bytes, depth
+ *   shape_out       NULL or int32[4]: bn, splits (0 fused, -1 resident,
+ *                   -2 J held in LDS), stage_bytes, depth
  *   ms_out          NULL or the chosen shape's time for `iters` iterations
  *   from_cache_out  NULL or 1 when the shape came from the cache
  * The context's last-solve state (logs, statistics) is overwritten.

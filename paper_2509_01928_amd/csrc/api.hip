@@ -1379,7 +1379,7 @@ ising_status ising_autotune_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R
     const int np = (n + npg - 1) / npg * npg;
     const int Rp = (R + 63) / 64 * 64;
     char kb[256];
-    std::snprintf(kb, sizeof(kb), "lowp-v1|%s|cus=%d|%s|np=%d|Rp=%d|iters=%lld", prop.gcnArchName,
+    std::snprintf(kb, sizeof(kb), "lowp-v2|%s|cus=%d|%s|np=%d|Rp=%d|iters=%lld", prop.gcnArchName,
                   prop.multiProcessorCount, prec == 0 ? "bf16" : "fp8", np, Rp, static_cast<long long>(iters));
     const std::string key(kb);
     auto report = [&](const doch::LowpShape& sh, double ms, int cached) {
@@ -1406,9 +1406,18 @@ ising_status ising_autotune_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R
             return ISING_OK;
         }
     }
-    // candidates: the fused iteration, and the split product over tile
-    // widths, splits, stage widths and depths, as far as they fit
+    // candidates: J held in LDS over its slice widths, the fused iteration,
+    // and the split product over tile widths, splits, stage widths and
+    // depths, as far as they fit
     std::vector<doch::LowpShape> cand;
+    for (int sb : {1024, 512, 256}) {
+        doch::LowpShape sh;
+        sh.bn = 128;
+        sh.splits = -2;
+        sh.sb = sb;
+        sh.depth = 1;
+        if (doch::lowp_shape_valid(prec, np, Rp, sh)) cand.push_back(sh);
+    }
     for (int mode : {-1, 0})
         for (int d : {2, 3}) {
             doch::LowpShape sh;
@@ -1489,8 +1498,15 @@ ising_status ising_set_lowp_shape(ising_ctx* ctx, int32_t bn, int32_t splits, in
     // the values the library is built for; whether they fit a problem is
     // checked per call
     if (bn != 64 && bn != 128) return fail(ISING_E_INVALID_ARG, "bn must be 0, 64 or 128");
-    if (splits != -1 && splits != 0 && splits != 1 && splits != 2 && splits != 4 && splits != 8)
-        return fail(ISING_E_INVALID_ARG, "splits must be -1, 0, 1, 2, 4 or 8");
+    if (splits != -2 && splits != -1 && splits != 0 && splits != 1 && splits != 2 && splits != 4 && splits != 8)
+        return fail(ISING_E_INVALID_ARG, "splits must be -2, -1, 0, 1, 2, 4 or 8");
+    if (splits == -2) {
+        if (bn != 128 || depth != 1 || (stage_bytes != 256 && stage_bytes != 512 && stage_bytes != 1024))
+            return fail(ISING_E_INVALID_ARG, "J held in LDS (splits -2) takes bn 128, depth 1 and slices of "
+                                             "256, 512 or 1024 bytes");
+        ctx->lp_shape = sh;
+        return ISING_OK;
+    }
     if (stage_bytes != 128 && stage_bytes != 256) return fail(ISING_E_INVALID_ARG, "stage_bytes must be 128 or 256");
     if (depth != 2 && depth != 3) return fail(ISING_E_INVALID_ARG, "depth must be 2 or 3");
     if (splits <= 0 && (bn != 64 || stage_bytes != 256))
@@ -1792,7 +1808,7 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
         HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
         shape = doch::lowp_default_shape(prec, np, Rp, cus);
     }
-    HIP_OK(ensure(&ctx->lp_P, &ctx->lp_Pbytes, doch::lowp_product_bytes(np, Rp, shape)), "hipMalloc(products)");
+    HIP_OK(ensure(&ctx->lp_P, &ctx->lp_Pbytes, doch::lowp_product_bytes(prec, np, Rp, shape)), "hipMalloc(products)");
     if (!ctx->ticket) {
         HIP_OK(dev_alloc(&ctx->ticket, (kMaxR + 8 * doch::kSchedStride) * sizeof(unsigned int)), "hipMalloc(ticket)");
         HIP_OK(dev_alloc(&ctx->state, kMaxR * sizeof(RestartState)), "hipMalloc(state)");
@@ -1814,9 +1830,37 @@ ising_status ising_solve_lowp(ising_ctx* ctx, const double* x0_dev, int32_t R, i
             HIP_OK(hipMemcpyAsync(cs[b], cs[0], kMaxR * sizeof(float), hipMemcpyDeviceToDevice, s), "copy scales");
     }
     bool resident_done = false;
-    // the resident run counts barrier arrivals (iterations x workgroups per
-    // group) in 32-bit words: longer runs take the same iteration as launches
+    auto fused_shape = [&]() {
+        int cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+        return doch::lowp_default_shape(prec, np, Rp, cus);
+    };
+    // the resident runs count barrier arrivals (barriers x workgroups per
+    // XCD) in 32-bit words: longer runs take the fused iteration as launches
     if (shape.splits == -1 && iters > 100000000) shape.splits = 0;
+    if (shape.splits == -2) {
+        const int64_t groups = static_cast<int64_t>(np / 128) * (static_cast<int64_t>(np) * esz / shape.sb);
+        if (iters * 2 * ((groups + 7) / 8) >= (int64_t{1} << 31)) shape = fused_shape();
+    }
+    if (shape.splits == -2 && iters > 0) {
+        // J held in LDS for the whole run, or the fused iteration a launch at
+        // a time when the workgroups do not fit on the device at once
+        if (!ctx->rsync) HIP_OK(dev_alloc(&ctx->rsync, sizeof(doch::ResidentSync)), "hipMalloc(sync)");
+        HIP_OK(doch::launch_resident_reset(ctx->rsync, s), "reset");
+        double* parts[2] = {ctx->lp_partials, ctx->lp_partials + pstride};
+        void* ubs[3] = {ctx->lp_ub[0], ctx->lp_ub[1], ctx->lp_ub[2]};
+        const hipError_t e = doch::launch_lowp_held(prec, np, Rp, shape, iters, ctx->jq[prec], ctx->rscale, ctx->lp_u,
+                                                    ubs, cs, ctx->lp_rho_q, p.alpha, p.beta, p.eps, R, ctx->lp_P,
+                                                    parts, ctx->log, ctx->state, ctx->rsync, s);
+        if (e == hipSuccess) {
+            resident_done = true;
+        } else if (e == hipErrorCooperativeLaunchTooLarge) {
+            (void)hipGetLastError();
+            shape = fused_shape();
+        } else {
+            return hip_fail(e, "low-precision run with J held in LDS");
+        }
+    }
     if (shape.splits == -1 && iters > 0) {
         // the whole run in one cooperative launch, or the same iteration a
         // launch at a time when its grid does not fit on the device at once

@@ -450,10 +450,13 @@ hipError_t launch_lowp_load(int prec, const double* x0, int n, int R, int np, in
 // (64 or 128), `splits` equal parts of the k range (1, 2, 4 or 8), stages of
 // sb bytes per row (128 or 256) with `depth` stages in flight (2 or 3).
 // Valid when the tiles divide the padded problem and every split holds at
-// least `depth` whole stages.
+// least `depth` whole stages.  splits 0 / -1: the fused iteration (64 x 64
+// tiles, a launch per iteration / resident); splits -2: J held in LDS (bn
+// 128 rows per block, sb = 256, 512 or 1024 k bytes per row per slice,
+// depth 1), resident.
 bool lowp_shape_valid(int prec, int np, int Rp, const LowpShape& sh);
 LowpShape lowp_default_shape(int prec, int np, int Rp, int cus);
-size_t lowp_product_bytes(int np, int Rp, const LowpShape& sh);   // the split partial tiles P
+size_t lowp_product_bytes(int prec, int np, int Rp, const LowpShape& sh);   // the partial products P
 // One iteration of the restart block: the split product into P, whose
 // extra workgroups close iteration k - 1 from partials_prev (k > 0), then the
 // update.  A stopped restart is never written, so its last iterate stays
@@ -473,6 +476,18 @@ hipError_t launch_lowp_resident(int prec, int np, int Rp, const LowpShape& sh, i
                                 const float* rscale, float* const* U, void* const* Ub, float* const* cs,
                                 double rho_q, double alpha, double beta, double eps, int R, double* const* partials,
                                 double* log, RestartState* state, ResidentSync* sync, hipStream_t s);
+// The whole run with J held in LDS (shape splits -2) in one cooperative
+// launch: per iteration the split product into P, the closing of the
+// previous iteration, a grid barrier, the update, a grid barrier.  P holds
+// lowp_product_bytes; sync must be zeroed (launch_resident_reset); barrier
+// arrivals are counted in 32-bit words (2 per iteration per workgroup of an
+// XCD's share), so the caller keeps iters well below 2^31 / (workgroups /
+// 8).  hipErrorCooperativeLaunchTooLarge when the workgroups do not fit on
+// the device at once.
+hipError_t launch_lowp_held(int prec, int np, int Rp, const LowpShape& sh, int64_t iters, const void* Jq,
+                            const float* rscale, float* const* U, void* const* Ub, float* const* cs, double rho_q,
+                            double alpha, double beta, double eps, int R, float* P, double* const* partials,
+                            double* log, RestartState* state, ResidentSync* sync, hipStream_t s);
 // Close iteration kk (the last one, after the final step).
 hipError_t launch_lowp_close(int np, int Rp, int R, int64_t kk, const double* partials, double alpha,
                              double beta, double eps, double* log, RestartState* state, hipStream_t s);

@@ -17,20 +17,23 @@
 // large starting points (u = sqrt(beta) x is large when beta is) never reach
 // the format's overflow, and later steps keep its full relative precision.
 //
-// Three shapes of one iteration (chosen per problem by the caller or by
+// Four shapes of one iteration (chosen per problem by the caller or by
 // timing them):
 //   fused      one launch per iteration; a workgroup owns a 64 x 64 tile of
 //              Z over the whole k range and updates it in place;
 //   resident   the fused tile body for every iteration in one cooperative
 //              launch, grid barriers between iterations;
 //   split      128 x bn tiles over 1..8 splits of the k range into FP32
-//              partial tiles, then an update kernel that adds them.
-// Every shape stages the k range through LDS in stages of whole cache lines
-// and ends an iteration the same way: the update (z + alpha u in FP64, its
-// cube root in FP32, the precision u is stored in), both copies stored, the
-// restart's FP64 partial sums per row tile, and extra workgroups closing the
-// iteration for their restarts (H, r, freezing at r < eps) while the next
-// one runs.
+//              partial tiles, then an update kernel that adds them;
+//   held       one cooperative launch whose workgroups keep a 128-row k
+//              slice of J in LDS for the whole run: split products, a grid
+//              barrier, the update, a grid barrier per iteration.
+// The first three stage the k range through LDS in stages of whole cache
+// lines; every shape ends an iteration the same way: the update (z + alpha
+// u in FP64, its cube root in FP32, the precision u is stored in), both
+// copies stored, the restart's FP64 partial sums per row tile, and the
+// iteration closed for every restart (H, r, freezing at r < eps) while the
+// next one runs.
 #include "device_common.h"
 #include "ising_internal.h"
 
@@ -737,7 +740,7 @@ struct LowpResArgs {
 
 constexpr unsigned int kLowpSpinLimit = 1u << 22;
 
-__device__ bool lowp_barrier(ResidentSync* sy, unsigned int gen, RestartState* st, int R, FusedLds& L) {
+__device__ bool lowp_barrier(ResidentSync* sy, unsigned int gen, RestartState* st, int R, int* flag) {
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -775,10 +778,10 @@ __device__ bool lowp_barrier(ResidentSync* sy, unsigned int gen, RestartState* s
             __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        L.flag = ok;
+        *flag = ok;
     }
     __syncthreads();
-    return L.flag != 0;
+    return *flag != 0;
 }
 
 template <int PREC, int DEPTH>
@@ -802,7 +805,7 @@ __global__ __launch_bounds__(MT) void lowp_resident_kernel(LowpResArgs a) {
     i32x4 ring[DEPTH][8];
     for (int64_t k = 0; k < a.iters; ++k) {
         const int o = static_cast<int>(k % 3), n = static_cast<int>((k + 1) % 3);
-        if (k > 0 && !lowp_barrier(a.sync, static_cast<unsigned int>(k), a.state, a.R, L)) return;
+        if (k > 0 && !lowp_barrier(a.sync, static_cast<unsigned int>(k), a.state, a.R, &L.flag)) return;
         const FusedSlab sl = fused_slab<PREC>(a.np, row0, col0, Jq, static_cast<const T*>(a.Ub[o]));
         const FusedClose fc{k > 0 ? a.partials[(k - 1) & 1] : nullptr, k - 1, a.beta, a.eps, a.log, a.state};
         fused_tile<PREC, DEPTH, true, true>(L, ring, k > 0, sl, a.Rp, row0, col0, tx, a.rscale, a.U[o], a.U[n],
@@ -812,6 +815,342 @@ __global__ __launch_bounds__(MT) void lowp_resident_kernel(LowpResArgs a) {
 #pragma unroll
             for (int p = 0; p < DEPTH; ++p) fused_fetch_j<DEPTH>(ring[p], sl, p);
         }
+    }
+}
+
+// ---- J held in LDS: the product split over k across the device ----------
+//
+// One cooperative launch for the whole run, one workgroup of eight
+// wavefronts per compute unit.  Workgroup (rb, kb) holds rows 128 rb ..
+// 128 rb + 127 of J, k bytes [KSB kb, KSB (kb + 1)), in LDS from its start
+// to its end (128 KB at KSB = 1024), so an iteration streams only the
+// low-precision restart copy (L2-resident: 2 MB at n = 4096, 256 restarts)
+// instead of a J slab per output tile.  An iteration:
+//   product   every wavefront owns 32-restart blocks (wave, wave + 8, ...)
+//             and, per block, the 128 x 32 FP32 partial product over the
+//             slice: 4 MFMA chains of 32 rows, A from LDS, B straight from
+//             memory (each copy row read by one wavefront only), written to
+//             P[kb] (np x Rp, FP32);
+//   closing   of the previous iteration: restarts b, b + G, ... of
+//             workgroup b, the row tiles' sums added in tile order as
+//             lowp_close does;
+//   barrier
+//   update    the 64 x 64 tiles of rows 128 rb .. 128 rb + 127, split over
+//             the workgroups of row block rb: the KB partial products added
+//             in slice order, the update, the FP32 master and the
+//             low-precision copy, the row tile's FP64 partial sums;
+//   barrier   (before the next product reads the new copy).
+// A row block's workgroups sit on one XCD when the row blocks split evenly
+// over the eight XCDs (workgroup b on XCD b mod 8), so the partial products
+// an update tile adds were written through its own L2.
+//
+// k order inside the product: the slice's rows are read in 128-byte groups;
+// lane half h of a group holds bytes 64 h .. 64 h + 63 of its row, in 16-byte
+// (BF16) or 32-byte (FP8) pieces, one per MFMA step, and reads A the same
+// way, so k pairs with k.  Every lane loads its 64 bytes of a group as four
+// 16-byte pieces of one row segment, D groups ahead.
+constexpr int HT = 512;                        // threads per workgroup
+constexpr int kHeldRows = 128;
+
+template <int NG>
+struct HeldLds {
+    static constexpr int kPitch = NG * 128 + 16;
+    __attribute__((aligned(16))) char J[kHeldRows * kPitch];
+    // update: [8][64][4] doubles of partial sums, then the transposed copy;
+    // closing: 512 staged sums and the closed restarts' totals
+    __attribute__((aligned(16))) char scratch[16384];
+    int dead[64];
+    int flag;
+};
+
+struct LowpHeldArgs {
+    int np, Rp, R, rblocks, kslices;
+    int64_t iters;
+    const void* Jq;
+    const float* rscale;
+    float* U[3];
+    void* Ub[3];
+    float* cs[3];
+    double rho_q, alpha, beta, eps;
+    float* P;
+    double* partials[2];
+    double* log;
+    RestartState* state;
+    ResidentSync* sync;
+};
+
+// One 64 x 64 update tile (row tile rt, column block cb) with 512 threads:
+// lane l of wavefront w holds restart 64 cb + l and rows 64 rt + 8 w ..
+// 64 rt + 8 w + 7.  The S partial products are added in slice order, then
+// as lowp_update_kernel.
+template <int PREC>
+__device__ __forceinline__ void held_update_tile(char* scratch, int* sdead, int np, int Rp, int S, int rt, int cb,
+                                                 const float* __restrict__ P, const float* __restrict__ rscale,
+                                                 const float* __restrict__ U_old, float* __restrict__ U_new,
+                                                 typename Prec<PREC>::T* __restrict__ Ub_new,
+                                                 const float* __restrict__ cs_old, float* __restrict__ cs_new,
+                                                 double rho_q, double alpha, int R, double* __restrict__ partials,
+                                                 const RestartState* __restrict__ state) {
+    using T = typename Prec<PREC>::T;
+    constexpr int TROW = 64 + 16 / static_cast<int>(sizeof(T));
+    const int tid = threadIdx.x;
+    const int jl = tid & 63, rg = tid >> 6;
+    const int row0 = rt * 64, col0 = cb * 64;
+    const int j = col0 + jl;
+    const int i0 = row0 + rg * 8;
+    const size_t base = static_cast<size_t>(i0) * Rp + j;
+    const size_t pstride = static_cast<size_t>(np) * Rp;
+    float uo[8], zs[8][8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) uo[v] = U_old[base + static_cast<size_t>(v) * Rp];
+#pragma unroll
+    for (int sp = 0; sp < 8; ++sp)
+        if (sp < S) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) zs[sp][v] = P[sp * pstride + base + static_cast<size_t>(v) * Rp];
+        }
+    const int dead = j < R ? state[j].done : 1;
+    if (tid < 64) sdead[tid] = dead;
+    const bool live = !dead;
+    float c_in = 1.0f, c_out = 1.0f, inv_c = 1.0f;
+    if constexpr (PREC == 1) {
+        c_in = cs_old[j];
+        c_out = live ? next_colscale(c_in, rho_q, alpha) : c_in;
+        // the copy is u times a reciprocal of its scale (v_rcp_f32, within an
+        // ulp); the carried bound has a margin far beyond an ulp
+        inv_c = __builtin_amdgcn_rcpf(c_out);
+        if (row0 == 0 && rg == 0) cs_new[j] = c_out;
+    }
+    double part[4] = {0.0, 0.0, 0.0, 0.0};      // u^4, u^2, u z, (du)^2
+    T low[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int i = i0 + v;
+        float z32 = zs[0][v];
+#pragma unroll
+        for (int sp = 1; sp < 8; ++sp)
+            if (sp < S) z32 += zs[sp][v];
+        const double u = static_cast<double>(uo[v]);
+        double z = static_cast<double>(z32);
+        if (PREC == 1) z = dmul(dmul(z, static_cast<double>(rscale[i])), static_cast<double>(c_in));
+        float un = uo[v];
+        if (live) {
+            // the argument in FP64, its cube root in FP32
+            un = cbrtf(static_cast<float>(dadd(z, dmul(alpha, u))));
+            const double d = dsub(static_cast<double>(un), u);
+            const double u2 = dmul(u, u);
+            part[0] = dadd(part[0], dmul(u2, u2));
+            part[1] = dadd(part[1], u2);
+            part[2] = dadd(part[2], dmul(u, z));
+            part[3] = dadd(part[3], dmul(d, d));
+            U_new[base + static_cast<size_t>(v) * Rp] = un;
+        }
+        low[v] = to_lowp<PREC>(PREC == 1 ? un * inv_c : un);
+    }
+    double (*red)[64][4] = reinterpret_cast<double (*)[64][4]>(scratch);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[rg][jl][q] = part[q];
+    __syncthreads();
+    // the row tile's partial sums (row groups in order)
+    if (tid < 64) {
+        double* p = partials + (static_cast<size_t>(rt) * Rp + col0 + tid) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double sum = red[0][tid][q];
+#pragma unroll
+            for (int g = 1; g < 8; ++g) sum = dadd(sum, red[g][tid][q]);
+            p[q] = sum;
+        }
+    }
+    __syncthreads();
+    T* tileT = reinterpret_cast<T*>(scratch);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) tileT[jl * TROW + rg * 8 + v] = low[v];
+    __syncthreads();
+    {
+        // 64 restart rows of 64 * sizeof(T) bytes, in 16-byte chunks
+        constexpr int CPR = 64 * static_cast<int>(sizeof(T)) / 16;
+        for (int c = tid; c < 64 * CPR; c += HT) {
+            const int r = c / CPR, ch = c % CPR;
+            if (sdead[r]) continue;
+            const i32x4 val = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(tileT + r * TROW) + ch * 16);
+            *reinterpret_cast<i32x4*>(reinterpret_cast<char*>(Ub_new + static_cast<size_t>(col0 + r) * np + row0) +
+                                      ch * 16) = val;
+        }
+    }
+    __syncthreads();                            // scratch and sdead are reused
+}
+
+template <int PREC, int NG>
+__global__ __launch_bounds__(HT) void lowp_held_kernel(LowpHeldArgs a) {
+    using T = typename Prec<PREC>::T;
+    using M = Mfma<PREC>;
+    constexpr int KSB = NG * 128;               // k bytes per row held
+    constexpr int PITCH = HeldLds<NG>::kPitch;
+    constexpr int D = NG < 4 ? NG : 4;          // groups in flight per lane
+    constexpr int FB = M::kBytes / 2;           // fragment bytes per lane
+    constexpr int KPG = 64 / FB;                // MFMA steps per 128-byte group
+    __shared__ HeldLds<NG> L;
+    const int b = blockIdx.x, G = gridDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int np = a.np, Rp = a.Rp, KB = a.kslices;
+    int rb, kb;
+    if (a.rblocks % 8 == 0 && G % 8 == 0) {
+        const int x = b & 7, m = b >> 3;
+        rb = x * (a.rblocks / 8) + m / KB;
+        kb = m % KB;
+    } else {
+        rb = b / KB;
+        kb = b % KB;
+    }
+    const uint32_t rowb = static_cast<uint32_t>(np) * sizeof(T);
+    {
+        const char* src = static_cast<const char*>(a.Jq) + static_cast<size_t>(rb) * kHeldRows * rowb +
+                          static_cast<size_t>(kb) * KSB;
+        for (int c = tid; c < kHeldRows * (KSB / 16); c += HT) {
+            const int r = c / (KSB / 16), ch = c % (KSB / 16);
+            *reinterpret_cast<i32x4*>(L.J + r * PITCH + ch * 16) =
+                *reinterpret_cast<const i32x4*>(src + static_cast<size_t>(r) * rowb + ch * 16);
+        }
+    }
+    __syncthreads();
+    // restarts this workgroup closes: b + G m, m < nres
+    const int nres = b < Rp ? (Rp - b + G - 1) / G : 0;
+    const int tiles = np / 64;
+    const int ncl = nres * tiles * 4;
+    const int CB = Rp / 64;
+    const int fo = (lane & 31) * PITCH + (lane >> 5) * 64;
+    for (int64_t k = 0; k < a.iters; ++k) {
+        const int o = static_cast<int>(k % 3), n = static_cast<int>((k + 1) % 3);
+        const double* pprev = a.partials[(k + 1) & 1];
+        // the first 512 sums this workgroup closes, requested now and added
+        // after the product (value (t nres + m) 4 + q: row tile t, restart
+        // b + G m, quantity q)
+        double clv = 0.0;
+        if (k > 0 && tid < ncl) {
+            const int t = tid / (nres * 4), m = (tid >> 2) % nres, q = tid & 3;
+            clv = pprev[(static_cast<size_t>(t) * Rp + b + G * m) * 4 + q];
+        }
+        // ---- product
+        const __amdgpu_buffer_rsrc_t rU = slab_rsrc(a.Ub[o], static_cast<uint32_t>(Rp) * rowb);
+        const __amdgpu_buffer_rsrc_t rP =
+            slab_rsrc(a.P + static_cast<size_t>(kb) * np * Rp, static_cast<uint32_t>(np) * static_cast<uint32_t>(Rp) * 4u);
+        for (int blk = wave; blk < Rp / 32; blk += 8) {
+            const uint32_t voff = static_cast<uint32_t>(blk * 32 + (lane & 31)) * rowb +
+                                  static_cast<uint32_t>(kb * KSB + (lane >> 5) * 64);
+            i32x4 ring[D][4];
+#pragma unroll
+            for (int p = 0; p < D; ++p)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    ring[p][c] = __builtin_amdgcn_raw_buffer_load_b128(rU, voff + p * 128 + c * 16, 0, 0);
+            f32x16 acc[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = f32x16{};
+            // D groups per trip, the ring slot of each known at compile time;
+            // the A fragments of the next MFMA step are read while this
+            // step's four MFMAs run, and the scheduler is kept from hoisting
+            // further reads (which would only take registers)
+            typename M::frag af[2][4];
+            auto read_a = [&](typename M::frag (&d)[4], int g, int c) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d[r] = M::load(L.J + r * 32 * PITCH + fo + g * 128 + c * FB);
+            };
+            read_a(af[0], 0, 0);
+#pragma unroll 1
+            for (int g0 = 0; g0 < NG; g0 += D) {
+                const bool refetch = g0 + D < NG;
+#pragma unroll
+                for (int p = 0; p < D; ++p) {
+                    const int g = g0 + p;
+                    i32x4 (&bq)[4] = ring[p];
+#pragma unroll
+                    for (int c = 0; c < KPG; ++c) {
+                        const int cur = (p * KPG + c) & 1;
+                        // the next step: (g, c + 1) or (g + 1, 0); past the
+                        // slice end it rereads the first step, unused
+                        const int gn = c + 1 < KPG ? g : g + 1;
+                        const int cn = c + 1 < KPG ? c + 1 : 0;
+                        read_a(af[cur ^ 1], gn < NG ? gn : 0, cn);
+                        typename M::frag bf;
+                        if constexpr (PREC == 0) bf = __builtin_bit_cast(bf16x8, bq[c]);
+                        else bf = __builtin_shufflevector(bq[2 * c], bq[2 * c + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r] = M::step(af[cur][r], bf, acc[r]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if (refetch) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            bq[c] = __builtin_amdgcn_raw_buffer_load_b128(rU, voff + (g + D) * 128 + c * 16, 0, 0);
+                    }
+                }
+            }
+            // C layout: lane column l % 32, rows 8 (v / 4) + 4 (l / 32) + v % 4;
+            // the row step in the scalar offset, so no store needs an
+            // address register of its own
+            const uint32_t Rp4 = static_cast<uint32_t>(Rp) * 4u;
+            const uint32_t vo = static_cast<uint32_t>(rb * kHeldRows + 4 * (lane >> 5)) * Rp4 +
+                                static_cast<uint32_t>(blk * 32 + (lane & 31)) * 4u;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    // the element is read into a scalar first: a bit cast of
+                    // the vector element itself was compiled as element 0
+                    const float e = acc[r][v];
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(e), rP,
+                                                          vo + static_cast<uint32_t>(r * 32) * Rp4,
+                                                          static_cast<uint32_t>(8 * (v >> 2) + (v & 3)) * Rp4, 0);
+                }
+        }
+        // ---- closing of iteration k - 1 (the order of lowp_close)
+        if (k > 0 && nres > 0) {
+            double* cv = reinterpret_cast<double*>(L.scratch);
+            double* tot = cv + HT;
+            const int m = tid >> 2, q = tid & 3;
+            const bool summer = tid < nres * 4;
+            double run = 0.0;
+            for (int base = 0; base < ncl; base += HT) {
+                double v = clv;
+                if (base > 0) {
+                    v = 0.0;
+                    const int idx = base + tid;
+                    if (idx < ncl) {
+                        const int t = idx / (nres * 4), mm = (idx >> 2) % nres, qq = idx & 3;
+                        v = pprev[(static_cast<size_t>(t) * Rp + b + G * mm) * 4 + qq];
+                    }
+                }
+                __syncthreads();
+                cv[tid] = v;
+                __syncthreads();
+                if (summer && ncl <= HT) {
+#pragma unroll 16
+                    for (int t = 0; t < tiles; ++t) run = dadd(run, cv[(t * nres + m) * 4 + q]);
+                } else if (summer) {
+                    const int t0 = base / (nres * 4);
+                    const int t1 = (base + HT + nres * 4 - 1) / (nres * 4);
+                    for (int t = t0; t < t1 && t < tiles; ++t) {
+                        const int idx = (t * nres + m) * 4 + q;
+                        if (idx >= base && idx < base + HT) run = dadd(run, cv[idx - base]);
+                    }
+                }
+            }
+            if (summer) tot[tid] = run;
+            __syncthreads();
+            if (tid < nres) {
+                const double S[4] = {tot[tid * 4], tot[tid * 4 + 1], tot[tid * 4 + 2], tot[tid * 4 + 3]};
+                lowp_close_restart(S, b + G * tid, a.R, k - 1, a.alpha, a.beta, a.eps, a.log, a.state);
+            }
+        }
+        if (!lowp_barrier(a.sync, static_cast<unsigned int>(2 * k + 1), a.state, a.R, &L.flag)) return;
+        // ---- update: tiles 2 rb + l % 2 (row) x l / 2 (column block), l = kb, kb + KB, ...
+        for (int l = kb; l < 2 * CB; l += KB)
+            held_update_tile<PREC>(L.scratch, L.dead, np, Rp, KB, 2 * rb + (l & 1), l >> 1, a.P, a.rscale, a.U[o],
+                                   a.U[n], static_cast<T*>(a.Ub[n]), a.cs[o], a.cs[n], a.rho_q, a.alpha, a.R,
+                                   a.partials[k & 1], a.state);
+        if (k + 1 < a.iters && !lowp_barrier(a.sync, static_cast<unsigned int>(2 * k + 2), a.state, a.R, &L.flag))
+            return;
     }
 }
 
@@ -1169,6 +1508,19 @@ bool lowp_shape_valid(int prec, int np, int Rp, const LowpShape& sh) {
     if (sh.splits == 0 || sh.splits == -1)
         return sh.bn == 64 && sh.sb == 256 && (sh.depth == 2 || (sh.depth == 3 && prec == 0 && sh.splits == 0)) &&
                Rp % 64 == 0 && np % 64 == 0 && np * (prec == 0 ? 2 : 1) / 256 >= sh.depth;
+    if (sh.splits == -2) {
+        // J held in LDS: 128-row blocks, k slices of sb bytes per row (at
+        // most 8 of them, the update adds their products in registers), one
+        // 8-wavefront workgroup per (row block, slice); every workgroup closes
+        // at most 128 restarts
+        const int rowb = np * (prec == 0 ? 2 : 1);
+        if (sh.bn != 128 || sh.depth != 1) return false;
+        if (sh.sb != 256 && sh.sb != 512 && sh.sb != 1024) return false;
+        if (np % kHeldRows != 0 || rowb % sh.sb != 0 || Rp % 64 != 0) return false;
+        const int kb = rowb / sh.sb;
+        const int G = np / kHeldRows * kb;
+        return kb <= 8 && Rp <= 128 * G;
+    }
     if (sh.bn != 64 && sh.bn != 128) return false;
     if (sh.sb != 128 && sh.sb != 256) return false;
     if (sh.depth != 2 && sh.depth != 3) return false;
@@ -1190,8 +1542,10 @@ LowpShape lowp_default_shape(int prec, int np, int Rp, int cus) {
     return sh;
 }
 
-size_t lowp_product_bytes(int np, int Rp, const LowpShape& sh) {
-    // the fused iteration (splits 0 or -1) keeps no partial tiles
+size_t lowp_product_bytes(int prec, int np, int Rp, const LowpShape& sh) {
+    // the fused iteration (splits 0 or -1) keeps no partial tiles; J held in
+    // LDS (splits -2) keeps one per k slice
+    if (sh.splits == -2) return static_cast<size_t>(np) * (prec == 0 ? 2 : 1) / sh.sb * np * Rp * sizeof(float);
     return sh.splits > 0 ? static_cast<size_t>(sh.splits) * np * Rp * sizeof(float) : 0;
 }
 
@@ -1354,6 +1708,69 @@ hipError_t launch_lowp_resident(int prec, int np, int Rp, const LowpShape& sh, i
     a.sync = sync;
     if (prec == 0) return launch_resident_one<0, 2>(a, s);
     return launch_resident_one<1, 2>(a, s);
+}
+
+namespace {
+
+template <int PREC, int NG>
+hipError_t launch_held_one(const LowpHeldArgs& a, hipStream_t s) {
+    static int cap = 0;           // workgroups of this kernel the device holds at once
+    auto kern = lowp_held_kernel<PREC, NG>;
+    if (cap == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, HT, 0);
+        if (e != hipSuccess) return e;
+        cap = cus * occ;
+    }
+    const int groups = a.rblocks * a.kslices;
+    if (groups > cap) return hipErrorCooperativeLaunchTooLarge;
+    LowpHeldArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(groups), dim3(HT), args, 0, s);
+}
+
+}  // namespace
+
+hipError_t launch_lowp_held(int prec, int np, int Rp, const LowpShape& sh, int64_t iters, const void* Jq,
+                            const float* rscale, float* const* U, void* const* Ub, float* const* cs, double rho_q,
+                            double alpha, double beta, double eps, int R, float* P, double* const* partials,
+                            double* log, RestartState* state, ResidentSync* sync, hipStream_t s) {
+    if (sh.splits != -2 || !lowp_shape_valid(prec, np, Rp, sh)) return hipErrorInvalidValue;
+    LowpHeldArgs a{};
+    a.np = np;
+    a.Rp = Rp;
+    a.R = R;
+    a.rblocks = np / kHeldRows;
+    a.kslices = np * (prec == 0 ? 2 : 1) / sh.sb;
+    a.iters = iters;
+    a.Jq = Jq;
+    a.rscale = rscale;
+    for (int i = 0; i < 3; ++i) {
+        a.U[i] = U[i];
+        a.Ub[i] = Ub[i];
+        a.cs[i] = cs[i];
+    }
+    a.rho_q = rho_q;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.eps = eps;
+    a.P = P;
+    a.partials[0] = partials[0];
+    a.partials[1] = partials[1];
+    a.log = log;
+    a.state = state;
+    a.sync = sync;
+    const int ng = sh.sb / 128;
+    if (prec == 0) {
+        if (ng == 2) return launch_held_one<0, 2>(a, s);
+        if (ng == 4) return launch_held_one<0, 4>(a, s);
+        return launch_held_one<0, 8>(a, s);
+    }
+    if (ng == 2) return launch_held_one<1, 2>(a, s);
+    if (ng == 4) return launch_held_one<1, 4>(a, s);
+    return launch_held_one<1, 8>(a, s);
 }
 
 hipError_t launch_lowp_close(int np, int Rp, int R, int64_t kk, const double* partials, double alpha,

@@ -69,12 +69,14 @@ def test_lowp_zero_coupling_closed_form(prec_name, n, R):
         np.testing.assert_array_equal(S, np.where(X >= 0, 1, -1))
 
 
-# (bn, splits, stage_bytes, depth): the fused iteration and a split product
-# that fits n = 512 with 32 restarts in both formats
-SHAPES = {"fused": (64, 0, 256, 2), "split": (64, 2, 128, 2), "resident": (64, -1, 256, 2)}
+# (bn, splits, stage_bytes, depth): the fused iteration, a split product,
+# the resident fused iteration and J held in LDS (256-byte k slices) that
+# fit n = 512 with 32 restarts in both formats
+SHAPES = {"fused": (64, 0, 256, 2), "split": (64, 2, 128, 2), "resident": (64, -1, 256, 2),
+          "held": (128, -2, 256, 1)}
 
 
-@pytest.mark.parametrize("shape_name", ["fused", "split", "resident"])
+@pytest.mark.parametrize("shape_name", ["fused", "split", "resident", "held"])
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
 def test_lowp_energy_gap_and_final_objective(prec_name, shape_name):
     """SK n = 512, 32 restarts.  H_final is eq:Hamilton of the returned
@@ -110,7 +112,7 @@ def test_lowp_energy_gap_and_final_objective(prec_name, shape_name):
     assert np.abs(E - E64).max() < 0.15 * scale
 
 
-@pytest.mark.parametrize("shape_name", ["fused", "resident"])
+@pytest.mark.parametrize("shape_name", ["fused", "resident", "held"])
 @pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
 def test_lowp_freezes_converged_restarts(prec_name, shape_name):
     """Restarts stop on their own; each returns the iterate of the iteration
@@ -150,6 +152,11 @@ def lowp_shapes(prec_name, n, R):
     out = [(64, -1, 256, 2), (64, 0, 256, 2)]
     if prec_name == "bf16" and np_ * esz // 256 >= 3:
         out.append((64, 0, 256, 3))
+    for sb in (1024, 512, 256):
+        # J held in LDS: 128-row blocks, at most 8 k slices of sb bytes per row
+        kb = np_ * esz // sb
+        if np_ % 128 == 0 and np_ * esz % sb == 0 and kb <= 8 and Rp <= 128 * (np_ // 128) * kb:
+            out.append((128, -2, sb, 1))
     for bn in (128, 64):
         for S in (1, 2, 4, 8):
             for sb in (128, 256):
@@ -210,7 +217,7 @@ def test_lowp_autotune_and_cache(tmp_path):
             st = L.ising_solve_lowp(ctx, xd, R, 20, p, prec)
             assert all(s.iters_done == 20 and s.nonfinite == 0 for s in st)
         text = open(cache).read()
-        assert text.count("lowp-v1|") == 2 and '"splits": ' in text
+        assert text.count("lowp-v2|") == 2 and '"splits": ' in text
     finally:
         L.ising_destroy(ctx)
 
@@ -239,3 +246,78 @@ def test_lowp_resident_matches_launches_bitwise(prec_name):
     assert np.array_equal(Ha, Hb)
     for a_, b_ in zip(La, Lb):
         assert np.array_equal(a_, b_)
+
+
+def held_logs(J, X0, alpha, beta, iters, prec, sb):
+    """Every restart's (H, r) log of a run with J held in LDS."""
+    import torch
+    import paper_2509_01928_amd as L
+    n, R = X0.shape
+    ctx, keep = dense_ctx(J)
+    try:
+        L.ising_set_lowp_shape(ctx, 128, -2, sb, 1)
+        p = L.ising_params()
+        p.alpha, p.beta, p.eps, p.algo, p.q, p.x_dtype, p.reserved = alpha, beta, 0.0, 0, 5, L.ISING_F64, 0
+        xd = torch.from_numpy(np.ascontiguousarray(X0)).to("cuda:0")
+        xo = torch.empty_like(xd)
+        st = L.ising_solve_lowp(ctx, xd, R, iters, p, prec, xo)
+        logs = [L.ising_get_log(ctx, r, 0, iters) for r in range(R)]
+        torch.cuda.synchronize()
+        return xo.cpu().numpy(), st, logs
+    finally:
+        L.ising_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
+def test_lowp_held_closing_matches_final_close(prec_name):
+    """With J held in LDS the workgroups close iteration k - 1 inside the run
+    (workgroup b: restarts b, b + G, ...), and the kernel that runs after
+    the last iteration closes it alone; both add the row tiles' sums in tile
+    order, so iteration m - 1 of a run of m + 1 iterations (closed inside)
+    and of a run of m iterations (closed after) log the same H and r bit for
+    bit.  n = 512 with 128 restarts and one k slice gives 4 workgroups
+    closing 32 restarts each: 1024 staged sums, more than one pass of 512."""
+    import paper_2509_01928_amd as L
+    prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
+    n, R, m = 512, 128, 12
+    sb = 1024 if prec_name == "bf16" else 512
+    J = gen.sk_dense(n, 4009)
+    X0 = gen.uniform_x0(n, R, 5009)
+    alpha = -np.linalg.eigvalsh(J)[0]
+    beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    Xa, sta, La = held_logs(J, X0, alpha, beta, m, prec, sb)
+    Xb, stb, Lb = held_logs(J, X0, alpha, beta, m + 1, prec, sb)
+    assert all(s.iters_done == m for s in sta) and all(s.iters_done == m + 1 for s in stb)
+    for r in range(R):
+        assert np.array_equal(La[r][0], Lb[r][0][:m]), r
+        assert np.array_equal(La[r][1], Lb[r][1][:m]), r
+    # H decreases over the run, as the FP64 iteration's does
+    H = np.array([l_[0] for l_ in Lb])
+    assert (H[:, -1] <= H[:, 0]).all()
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
+def test_lowp_held_full_size_step(prec_name):
+    """The dense n = 4096, 256-restart workload: J held in LDS over 256
+    workgroups (32 row blocks x 8 k slices, each row block's slices on one
+    XCD) against the fused iteration, one step, within the FP32 summation
+    bound of the every-shape test; then 100 iterations of each end at the
+    same energies up to the spread that rounding order gives."""
+    import paper_2509_01928_amd as L
+    prec = L.ISING_BF16 if prec_name == "bf16" else L.ISING_FP8_E4M3
+    n, R = 4096, 256
+    sb = 1024 if prec_name == "bf16" else 512
+    J = gen.sk_dense(n, 4010)
+    X0 = gen.uniform_x0(n, R, 5010)
+    alpha = float(2.0 * math.sqrt(n) * np.abs(J).mean())
+    beta = n ** 1.5 * (alpha + np.abs(J).sum(axis=1).max())
+    sq = math.sqrt(beta)
+    bound = 3 * n * 2.0 ** -24 * (np.abs(J) @ np.abs(sq * X0))
+    W_ref = (sq * run_lowp(J, X0, alpha, beta, 1, prec, shape=(64, 0, 256, 2))[0]) ** 3
+    W = (sq * run_lowp(J, X0, alpha, beta, 1, prec, shape=(128, -2, sb, 1))[0]) ** 3
+    excess = np.abs(W - W_ref) - (bound + 8 * 2.0 ** -24 * np.abs(W_ref))
+    assert excess.max() <= 0.0, excess.max()
+    Ea = run_lowp(J, X0, alpha, beta, 100, prec, shape=(64, 0, 256, 2))[3]
+    Eb = run_lowp(J, X0, alpha, beta, 100, prec, shape=(128, -2, sb, 1))[3]
+    scale = abs(Ea.mean())
+    assert abs(Ea.mean() - Eb.mean()) < 0.01 * scale, (Ea.mean(), Eb.mean())
