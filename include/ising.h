@@ -218,7 +218,12 @@ ising_status ising_solve(ising_ctx* ctx, const double* x0_dev, int32_t R,
  * otherwise); params->q >= 1 is the look-back window.  Every restart keeps
  * its own window, decisions and stopping (Remark S2 with params->eps), and
  * ising_get_log(restart) reads its H and r.  It still costs one matvec per
- * iteration: J y is formed from J x^(k) and J x^(k-1).
+ * iteration: J y is formed from J x^(k) and J x^(k-1).  One restart on a
+ * stored dense matrix of order <= 2048 without a field, q <= 63 and at most
+ * 10^7 iterations runs resident (one cooperative launch for the whole run)
+ * unless ising_set_geometry chose geometry 0; the first call with more
+ * iterations than any before on the context synchronises the stream (the
+ * momentum weights are uploaded once).
  * ising_get_accept_log copies, for the last ADOCH solve, whether iteration
  * first + i of restart r took the extrapolated point (1) or x^(k) (0), at
  * accept_host[i * R + r] (count * R entries).  Synchronous. */

@@ -219,6 +219,7 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->ad_ring);
     dev_free(c->ad_accept);
     dev_free(c->ad_acclog);
+    dev_free(c->ad_cseq);
     if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
     if (c->bgraph_src) (void)hipGraphDestroy(c->bgraph_src);
     delete c;
@@ -395,6 +396,15 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
     if (!ctx->ad_accept) HIP_OK(dev_alloc(&ctx->ad_accept, 512), "hipMalloc(accept)");
     HIP_OK(ensure(&ctx->ad_acclog, &ctx->ad_acclog_bytes, static_cast<size_t>(std::max<int64_t>(iters, 1)) * R),
            "hipMalloc(accept log)");
+    // momentum sequence of Alg. 2: t_0 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+    // c_k = (t_k - 1) / t_{k+1} (0 at k = 0: y^(0) = x^(0))
+    auto momentum = [](int64_t k, double* t) {
+        const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * *t * *t)) / 2.0;
+        const double c = (*t - 1.0) / t_next;
+        *t = t_next;
+        (void)k;
+        return c;
+    };
     const int mv_grid = ctx->dense ? doch::adoch_dense_grid(dense_view(ctx)) : doch::adoch_grid(ctx->n);
     const int up_grid = doch::adoch_grid(ctx->np * R);
     const size_t pd = std::max(static_cast<size_t>(mv_grid) * 8 * R, static_cast<size_t>(up_grid) * 2 * R);
@@ -406,6 +416,62 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
     }
     HIP_OK(ensure(&ctx->log, &ctx->log_bytes,
                   static_cast<size_t>(std::max<int64_t>(iters, 1)) * R * 2 * sizeof(double)), "hipMalloc(log)");
+    // a stored dense matrix of order <= 2048 without a field, one restart:
+    // the whole run in one cooperative launch, unless another geometry was
+    // set (barrier arrivals are counted in 32-bit words: at most 10^7
+    // iterations)
+    if (ctx->dense && ctx->proc_kind == 0 && !ctx->has_field && R == 1 && ctx->n <= doch::kResidentMaxDense &&
+        p.q + 1 <= doch::kAdochResMaxW && iters > 0 && iters <= 10000000 &&
+        (ctx->geometry == doch::kGeometryResident || ctx->geometry < 0)) {
+        const int64_t xstride = (ctx->np * 8 + 255) / 256 * 256 / 8;
+        HIP_OK(ensure(&ctx->rx, &ctx->rx_bytes, 3 * static_cast<size_t>(xstride) * 8), "hipMalloc(x)");
+        double* rx = static_cast<double*>(ctx->rx);
+        const int G = doch::resident_row_groups(true, ctx->n);
+        HIP_OK(ensure(&ctx->partials, &ctx->partials_bytes,
+                      3 * static_cast<size_t>(G) * doch::kAdochResPartials * sizeof(double)), "hipMalloc(partials)");
+        // c_0 .. c_{iters-1}, kept on the device for later runs (the whole
+        // allocation always holds the sequence from k = 0)
+        const size_t cbytes = static_cast<size_t>(iters) * sizeof(double);
+        if (!ctx->ad_cseq || ctx->ad_cseq_bytes < cbytes) {
+            std::vector<double> cs(static_cast<size_t>(iters));
+            double t = 1.0;
+            for (int64_t k = 0; k < iters; ++k) cs[static_cast<size_t>(k)] = momentum(k, &t);
+            HIP_OK(ensure(&ctx->ad_cseq, &ctx->ad_cseq_bytes, cbytes), "hipMalloc(c)");
+            HIP_OK(hipMemcpyAsync(ctx->ad_cseq, cs.data(), cbytes, hipMemcpyHostToDevice, s), "copy c");
+            HIP_OK(hipStreamSynchronize(s), "sync");        // cs is released here
+        }
+        if (!ctx->rsync) HIP_OK(dev_alloc(&ctx->rsync, sizeof(doch::ResidentSync)), "hipMalloc(sync)");
+        HIP_OK(doch::launch_init_state(ctx->state, 1, ctx->ticket, nullptr, s), "init");
+        HIP_OK(doch::launch_resident_reset(ctx->rsync, s), "reset");
+        HIP_OK(hipMemcpyAsync(rx, x0_dev, bytes, hipMemcpyDeviceToDevice, s), "load x0");
+        doch::AdochResArgs ra;
+        ra.x = rx;
+        ra.xstride = xstride;
+        ra.row_groups = G;
+        ra.alpha = p.alpha;
+        ra.beta = p.beta;
+        ra.eps = p.eps;
+        ra.q = p.q;
+        ra.iters = iters;
+        ra.cseq = ctx->ad_cseq;
+        ra.partials = ctx->partials;
+        ra.log = ctx->log;
+        ra.accept_log = ctx->ad_acclog;
+        ra.state = ctx->state;
+        ra.sync = ctx->rsync;
+        const hipError_t e = doch::launch_resident_adoch_dense(dense_view(ctx), ra, s);
+        if (e == hipSuccess) {
+            ctx->last_R = 1;
+            ctx->last_iters = iters;
+            ctx->last_adoch = true;
+            if (x_out_dev || s_out_dev)
+                HIP_OK(doch::launch_adoch_finish(rx, rx + xstride, rx + 2 * xstride, ctx->state, ctx->n, ctx->np, 1,
+                                                 false, x_out_dev, s_out_dev, s), "finish");
+            return read_stats(ctx, 1, stats_host, s);
+        }
+        if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "resident ADOCH launch");
+        (void)hipGetLastError();
+    }
     HIP_OK(doch::launch_init_state(ctx->state, R, ctx->ticket, nullptr, s), "init");
     HIP_OK(hipMemsetAsync(ctx->ad_accept, 0, 512, s), "clear flags");
     HIP_OK(hipMemcpyAsync(ctx->ad_x[0], x0_dev, bytes, hipMemcpyDeviceToDevice, s), "load x0");
@@ -428,10 +494,9 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
     a.state = ctx->state;
     const CsrView cv = csr_view(ctx);
     const DenseView dv = dense_view(ctx);
-    double t = 1.0;                                   // momentum sequence of Alg. 2: t_0 = 1
+    double t = 1.0;
     for (int64_t k = 0; k < iters; ++k) {
-        const double t_next = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;   // t_{k+1} of Alg. 2
-        a.c = (t - 1.0) / t_next;                                           // 0 at k = 0: y = x
+        a.c = momentum(k, &t);
         a.k = k;
         const double* x = ctx->ad_x[k % 3];
         const double* xp = k == 0 ? ctx->ad_x[0] : ctx->ad_x[(k + 2) % 3];
@@ -445,7 +510,6 @@ static ising_status solve_adoch(ising_ctx* ctx, const double* x0_dev, int R, int
         else
             HIP_OK(doch::launch_adoch_mv(cv, x, xp, zp, z, xn, a, s), "ADOCH matvec");
         HIP_OK(doch::launch_adoch_update(ctx->np, x, xp, z, zp, xn, a, !ctx->dense, s), "ADOCH update");
-        t = t_next;
     }
     ctx->last_R = R;
     ctx->last_iters = iters;

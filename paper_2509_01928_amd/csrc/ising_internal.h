@@ -142,6 +142,25 @@ struct ResidentArgs {
     ResidentSync* sync;
 };
 
+// ADOCH (Alg. 2) on a stored dense matrix without a field, one restart, the
+// whole run in one cooperative launch (kernels_resident.hip).
+constexpr int kAdochResMaxW = 64;           // longest window q + 1 it keeps
+constexpr int kAdochResPartials = 8;        // per workgroup: 7 sums, then 2
+struct AdochResArgs {
+    double* x;              // three FP64 iterate buffers, xstride apart; x^(k) in buffer k mod 3
+    int64_t xstride;
+    int row_groups;
+    double alpha, beta, eps;
+    int q;
+    int64_t iters;
+    const double* cseq;     // [iters] momentum weights c_k of Alg. 2
+    double* partials;       // [3][row_groups][kAdochResPartials]
+    double* log;            // [iters][2]: (H(x^(k)), r^(k))
+    int8_t* accept_log;     // [iters]
+    RestartState* state;
+    ResidentSync* sync;
+};
+
 // ---- eta sweeps as restarts of one pass (kernels_sweep.hip) ----
 constexpr int kSweepMaxR = 8;
 struct SweepArgs {
@@ -367,6 +386,8 @@ struct ising_ctx {
     int* ad_accept = nullptr;
     int8_t* ad_acclog = nullptr;
     size_t ad_acclog_bytes = 0;
+    double* ad_cseq = nullptr;           // momentum weights of a resident run
+    size_t ad_cseq_bytes = 0;
     bool last_adoch = false;
     // resident solve: three iterate buffers and the barrier words
     void* rx = nullptr;
@@ -510,6 +531,9 @@ hipError_t launch_adoch_dense_mv(const DenseView& A, const double* x, const doub
                                  double* z, const AdochArgs& a, hipStream_t s);
 hipError_t launch_adoch_update(int64_t np, const double* x, const double* xp, const double* z,
                                const double* zp, double* xn, const AdochArgs& a, bool fixup, hipStream_t s);
+// The resident ADOCH run above; hipErrorCooperativeLaunchTooLarge when its
+// workgroups do not fit on the device at once.  sync must be zeroed.
+hipError_t launch_resident_adoch_dense(const DenseView& A, const AdochResArgs& a, hipStream_t s);
 hipError_t launch_adoch_finish(const double* b0, const double* b1, const double* b2,
                                const RestartState* st, int64_t n, int64_t np, int R, bool field,
                                double* x_out, int8_t* s_out, hipStream_t s);

@@ -378,6 +378,237 @@ __global__ __launch_bounds__(NT) void resident_csr_kernel(int64_t n, const int32
     }
 }
 
+// ---- ADOCH (Alg. 2) resident: stored dense J, no field, one restart ----
+//
+// Rows as in resident_dense_kernel (a wavefront per row, the row in
+// registers, x^(k) staged in LDS from the point of coherence).  The row's
+// owner lane keeps x^(k-1)_i and z_{k-1,i} in registers, so of the vectors
+// only x^(k) crosses workgroups.  Iteration k:
+//   1. z_k,i = (J x^(k))_i; y_i = x_i + c_k (x_i - x^(k-1)_i), (J y)_i =
+//      (1 + c_k) z_k,i - c_k z_{k-1,i}; x^(k+1)_i = T(y)_i written before the
+//      acceptance test is known; the workgroup's sums of x^4, x^2, x z,
+//      y^4, y^2, y (J y), (T(y) - x)^2;
+//   2. grid barrier;
+//   3. every workgroup adds the G workgroups' sums in the same order,
+//      forms H(x^(k)), H(y^(k)), keeps its own copy of the window of the
+//      last q + 1 values of H(x) and takes the same decision; workgroup 0
+//      logs it;
+//   4. y accepted: r^(k) from the sums, Remark S2's test; rejected:
+//      x^(k+1)_i = T(x)_i rewritten, its sums, a second barrier, r^(k);
+//      H(x^(k)) not finite: x^(k) copied forward and the run ends.
+// Every workgroup reaches the same stop at the same iteration, so the loop
+// ends without a published stop; barrier waits are bounded as in the DOCH
+// run.
+template <int NQ>
+__device__ void sum_adoch_partials(const double* __restrict__ p, int G, double (&out)[NQ], double* lds) {
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) out[j] = 0.0;
+    for (int g0 = 0; g0 < G; g0 += 4 * NT) {
+        double v[4][NQ];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int g = g0 + b * NT + static_cast<int>(threadIdx.x);
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+                v[b][j] = g < G ? ld_coh(p + static_cast<size_t>(g) * kAdochResPartials + j) : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) out[j] = dadd(out[j], v[b][j]);
+    }
+    block_sum<NQ, NT>(out, lds);
+}
+
+template <int JC>
+__global__ __launch_bounds__(NT) void resident_adoch_dense_kernel(int64_t n, const double* __restrict__ J, int64_t ld,
+                                                                  AdochResArgs a) {
+    __shared__ double xs[64 * JC];
+    __shared__ double red[kAdochResPartials * NW];
+    __shared__ double ring[kAdochResMaxW];
+    __shared__ int dec[2];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int G = a.row_groups;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * NW + wave;
+    const bool own = i < n;
+    const bool owner = own && lane == 0;
+    double jr[JC];
+#pragma unroll
+    for (int u = 0; u < JC; ++u) {
+        const int64_t j = lane + u * kWave;
+        jr[u] = (own && j < n) ? J[i * ld + j] : 0.0;
+    }
+    auto xb = [&](int64_t k) { return a.x + (k % 3) * a.xstride; };
+    const double b4 = ddiv(a.beta, 4.0), a2 = ddiv(a.alpha, 2.0);
+    const int W = a.q + 1;
+    double xprev = owner ? ld_coh(xb(0) + i) : 0.0;   // x^(k-1)_i (x^(-1) = x^(0): c_0 = 0)
+    double zprev = 0.0;                               // z_{k-1,i}
+    unsigned int gen = 0;
+    constexpr int PER = (64 * JC + NT - 1) / NT;
+    bool staged = false;                // x^(k) already in xs (y accepted last time)
+    for (int64_t k = 0; k < a.iters; ++k) {
+        const double c = a.cseq[k];
+        const double* xo = xb(k);
+        double* xn = xb(k + 1);
+        double v[PER];
+        if (!staged) {
+#pragma unroll
+            for (int b = 0; b < PER; ++b) {
+                const int64_t j = threadIdx.x + b * NT;
+                v[b] = j < n ? ld_coh(xo + j) : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < PER; ++b) {
+                const int j = threadIdx.x + b * NT;
+                if (j < 64 * JC) xs[j] = v[b];
+            }
+            __syncthreads();
+        }
+        double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double xi = 0.0, zi = 0.0;
+        if (own) {
+            double p = 0.0;
+#pragma unroll
+            for (int u = 0; u < JC; ++u) {
+                const int64_t j = lane + u * kWave;
+                if (j < n) p = dadd(p, dmul(jr[u], xs[j]));
+            }
+            const double z0 = wave_sum(p);
+            if (owner) {
+                xi = xs[i];
+                zi = z0;
+                const double yi = dadd(xi, dmul(c, dsub(xi, xprev)));
+                const double jy = dsub(dmul(dadd(1.0, c), zi), dmul(c, zprev));
+                const double x2 = dmul(xi, xi), y2 = dmul(yi, yi);
+                acc[0] = dmul(x2, x2);
+                acc[1] = x2;
+                acc[2] = dmul(xi, zi);
+                acc[3] = dmul(y2, y2);
+                acc[4] = y2;
+                acc[5] = dmul(yi, jy);
+                const double ty = cbrt(ddiv(dadd(jy, dmul(a.alpha, yi)), a.beta));
+                st_coh(xn + i, ty);
+                const double d = dsub(ty, xi);
+                acc[6] = dmul(d, d);
+            }
+        }
+        block_sum<7, NT>(acc, red);
+        double* pk = a.partials + static_cast<size_t>(k & 1) * G * kAdochResPartials;
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int q = 0; q < 7; ++q) store_agent(pk + static_cast<size_t>(blockIdx.x) * kAdochResPartials + q, acc[q]);
+        if (!grid_barrier(a.sync, ++gen, a.state)) return;
+        // x^(k+1) = T(y) is requested with the sums: it is the next iterate
+        // whenever y is accepted
+#pragma unroll
+        for (int b = 0; b < PER; ++b) {
+            const int64_t j = threadIdx.x + b * NT;
+            v[b] = j < n ? ld_coh(xn + j) : 0.0;
+        }
+        double S[7];
+        sum_adoch_partials<7>(pk, G, S, red);
+        if (threadIdx.x == 0) {
+            const double Hx = dsub(dsub(dmul(b4, S[0]), dmul(a2, S[1])), dmul(0.5, S[2]));
+            const double Hy = dsub(dsub(dmul(b4, S[3]), dmul(a2, S[4])), dmul(0.5, S[5]));
+            ring[k % W] = Hx;
+            const int64_t j0 = k - a.q > 0 ? k - a.q : 0;
+            double hmax = Hx;
+            for (int64_t j = j0; j <= k; ++j) hmax = fmax(hmax, ring[j % W]);
+            const int accept = Hy <= hmax ? 1 : 0;
+            int code = isfinite(Hx) ? (accept ? 0 : 1) : 2;
+            int stop = code == 2;
+            double r = 0.0;
+            if (code == 0) {
+                r = S[1] == 0.0 ? 0.0 : ddiv(sqrt(S[6]), sqrt(S[1]));
+                stop = !isfinite(r) || (a.eps > 0.0 && r < a.eps);
+            }
+            if (blockIdx.x == 0) {
+                RestartState* st = a.state;
+                a.log[2 * k] = Hx;
+                a.accept_log[k] = static_cast<int8_t>(accept);
+                st->H_last = Hx;
+                if (code == 2) {
+                    st->nonfinite = 1;
+                    st->done = 1;
+                    st->iters_done = k + 1;
+                } else if (code == 0) {
+                    a.log[2 * k + 1] = r;
+                    st->iters_done = k + 1;
+                    st->r_last = r;
+                    if (!isfinite(r)) {
+                        st->nonfinite = 1;
+                        st->done = 1;
+                    } else if (a.eps > 0.0 && r < a.eps) {
+                        st->converged = 1;
+                        st->done = 1;
+                    }
+                }
+            }
+            dec[0] = code;
+            dec[1] = stop;
+        }
+        __syncthreads();
+        const int code = dec[0];
+        int stop = dec[1];
+        if (code == 2) {
+            if (owner) st_coh(xn + i, xi);
+            return;
+        }
+        if (code == 1) {
+            double acc2[2] = {0.0, 0.0};
+            if (owner) {
+                const double tx = cbrt(ddiv(dadd(zi, dmul(a.alpha, xi)), a.beta));
+                st_coh(xn + i, tx);
+                const double d = dsub(tx, xi);
+                acc2[0] = dmul(d, d);
+                acc2[1] = dmul(xi, xi);
+            }
+            block_sum<2, NT>(acc2, red);
+            double* p2 = a.partials + static_cast<size_t>(2) * G * kAdochResPartials;
+            if (threadIdx.x == 0)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) store_agent(p2 + static_cast<size_t>(blockIdx.x) * kAdochResPartials + q, acc2[q]);
+            if (!grid_barrier(a.sync, ++gen, a.state)) return;
+            double S2[2];
+            sum_adoch_partials<2>(p2, G, S2, red);
+            if (threadIdx.x == 0) {
+                const double r = S2[1] == 0.0 ? 0.0 : ddiv(sqrt(S2[0]), sqrt(S2[1]));
+                if (blockIdx.x == 0) {
+                    RestartState* st = a.state;
+                    a.log[2 * k + 1] = r;
+                    st->iters_done = k + 1;
+                    st->r_last = r;
+                    if (!isfinite(r)) {
+                        st->nonfinite = 1;
+                        st->done = 1;
+                    } else if (a.eps > 0.0 && r < a.eps) {
+                        st->converged = 1;
+                        st->done = 1;
+                    }
+                }
+                dec[1] = !isfinite(r) || (a.eps > 0.0 && r < a.eps);
+            }
+            __syncthreads();
+            stop = dec[1];
+        }
+        if (stop) return;
+        xprev = xi;
+        zprev = zi;
+        // every read of xs and dec of this iteration is behind the block
+        // sums above; an accepted y leaves x^(k+1) staged for the next one
+        staged = code == 0;
+        if (staged) {
+#pragma unroll
+            for (int b = 0; b < PER; ++b) {
+                const int j = threadIdx.x + b * NT;
+                if (j < 64 * JC) xs[j] = v[b];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void resident_reset_kernel(ResidentSync* sy) {
     unsigned int* w = reinterpret_cast<unsigned int*>(sy);
     for (unsigned int t = threadIdx.x; t < sizeof(ResidentSync) / sizeof(unsigned int); t += blockDim.x) w[t] = 0u;
@@ -448,7 +679,33 @@ hipError_t launch_csr_x(const CsrView& A, const ResidentArgs& a, hipStream_t s) 
     return launch_csr_c<VT, HT, 0>(A, a, s);
 }
 
+template <int JC>
+hipError_t launch_adoch_dense_t(const DenseView& A, AdochResArgs a, hipStream_t s) {
+    static int cap = 0;
+    int64_t n = A.n;
+    const double* J = A.J;
+    int64_t ld = A.ld;
+    void* args[] = {&n, &J, &ld, &a};
+    auto kern = resident_adoch_dense_kernel<JC>;
+    if (cap == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, 0);
+        if (e != hipSuccess) return e;
+        cap = cus * occ;
+    }
+    if (a.row_groups > cap) return hipErrorCooperativeLaunchTooLarge;
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(a.row_groups), dim3(NT), args, 0, s);
+}
+
 }  // namespace
+
+hipError_t launch_resident_adoch_dense(const DenseView& A, const AdochResArgs& a, hipStream_t s) {
+    if (A.n > kResidentMaxDense || A.proc_kind != 0 || A.h || a.q + 1 > kAdochResMaxW) return hipErrorInvalidValue;
+    if (A.n <= 1024) return launch_adoch_dense_t<16>(A, a, s);
+    return launch_adoch_dense_t<32>(A, a, s);
+}
 
 int resident_row_groups(bool dense, int64_t n) {
     if (dense) return static_cast<int>((n + NW - 1) / NW);

@@ -97,6 +97,58 @@ def test_adoch_dense_stored(R, field):
                   acc[:, rr], iters, field, r_rtol=R_RTOL_DENSE)
 
 
+@pytest.mark.parametrize("n,iters", [(1024, 600), (1500, 300)])
+def test_adoch_dense_resident_and_launches(n, iters):
+    """One restart on stored dense couplings without a field runs resident
+    (one cooperative launch: every workgroup takes the acceptance decision
+    from the same sums; x^(k+1) = T(y) written before it, T(x) rewritten on
+    rejection); geometry 0 forces a launch per step.  Both against the
+    oracle's ADOCH (n = 1024: 16 row chunks per lane; n = 1500: 32, the
+    last one ragged)."""
+    import torch
+    import paper_2509_01928_amd as L
+    q = 5
+    J, h, B = dense_case(n, 7350 + n, False)
+    alpha, beta, _ = orc.default_params(B, 1.0, method="power")
+    X0 = gen.uniform_x0(n, 1, 7351 + n)
+    tr = orc.adoch(B, X0[:, 0], alpha, beta, iters, q)
+    assert (tr.accept == 0).any(), "the seeded case should reject y at least once"
+    Jd = torch.from_numpy(J).to("cuda:0")
+    for geometry in (-1, 0):
+        ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
+        try:
+            L.ising_set_geometry(ctx, geometry, 0)
+            x, s, st, logs, acc = run_gpu(ctx, L, X0, 1, iters, alpha, beta, q, 0.0, n, n)
+        finally:
+            L.ising_destroy(ctx)
+        assert st[0].iters_done == iters
+        check_run(f"dense n={n} geometry {geometry}", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0],
+                  iters, False, r_rtol=R_RTOL_DENSE)
+
+
+def test_adoch_dense_resident_stops_with_oracle():
+    """eps = 1e-3: the resident run stops at the oracle's iteration, every
+    workgroup at the same one, and returns that iteration's iterate."""
+    import torch
+    import paper_2509_01928_amd as L
+    n, q = 800, 5
+    J, h, B = dense_case(n, 7360, False)
+    alpha, beta, _ = orc.default_params(B, 1.0, method="power")
+    X0 = gen.uniform_x0(n, 1, 7361)
+    tr = orc.adoch(B, X0[:, 0], alpha, beta, 3000, q, eps=1e-3)
+    assert tr.iters < 3000
+    Jd = torch.from_numpy(J).to("cuda:0")
+    ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
+    try:
+        x, s, st, logs, acc = run_gpu(ctx, L, X0, 1, 3000, alpha, beta, q, 1e-3, n, n)
+    finally:
+        L.ising_destroy(ctx)
+    assert st[0].iters_done == tr.iters and st[0].converged == 1
+    k = tr.iters
+    check_run("dense n=800 eps", tr, x[:, 0], s[:, 0], logs[0][0][:k], logs[0][1][:k], acc[:k, 0], k, False,
+              end_fixed_point=False, r_rtol=R_RTOL_DENSE)
+
+
 @pytest.mark.parametrize("R", [1, 8])
 def test_adoch_procedural(R):
     """Couplings sin(i j + 7) generated on the fly (n = 700), against the
