@@ -97,33 +97,60 @@ def test_adoch_dense_stored(R, field):
                   acc[:, rr], iters, field, r_rtol=R_RTOL_DENSE)
 
 
-@pytest.mark.parametrize("n,iters", [(1024, 600), (1500, 300)])
-def test_adoch_dense_resident_and_launches(n, iters):
+@pytest.mark.parametrize("n,iters,R", [(1024, 600, 1), (1500, 300, 1), (1024, 300, 8)])
+def test_adoch_dense_resident_and_launches(n, iters, R):
     """One restart on stored dense couplings without a field runs resident
     (one cooperative launch: every workgroup takes the acceptance decision
     from the same sums; x^(k+1) = T(y) written before it, T(x) rewritten on
-    rejection); geometry 0 forces a launch per step.  Both against the
-    oracle's ADOCH (n = 1024: 16 row chunks per lane; n = 1500: 32, the
-    last one ragged)."""
+    rejection); geometry 0, and more restarts, take a launch per step.  Both
+    against the oracle's ADOCH per restart (n = 1024: 16 row chunks per
+    lane; n = 1500: 32, the last one ragged; eight restarts with their own
+    windows on the launches)."""
     import torch
     import paper_2509_01928_amd as L
     q = 5
     J, h, B = dense_case(n, 7350 + n, False)
     alpha, beta, _ = orc.default_params(B, 1.0, method="power")
-    X0 = gen.uniform_x0(n, 1, 7351 + n)
-    tr = orc.adoch(B, X0[:, 0], alpha, beta, iters, q)
-    assert (tr.accept == 0).any(), "the seeded case should reject y at least once"
+    X0 = gen.uniform_x0(n, R, 7351 + n)
+    trs = [orc.adoch(B, X0[:, rr], alpha, beta, iters, q) for rr in range(R)]
+    assert any((t.accept == 0).any() for t in trs), "the seeded case should reject y at least once"
     Jd = torch.from_numpy(J).to("cuda:0")
     for geometry in (-1, 0):
         ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
         try:
             L.ising_set_geometry(ctx, geometry, 0)
-            x, s, st, logs, acc = run_gpu(ctx, L, X0, 1, iters, alpha, beta, q, 0.0, n, n)
+            x, s, st, logs, acc = run_gpu(ctx, L, X0, R, iters, alpha, beta, q, 0.0, n, n)
         finally:
             L.ising_destroy(ctx)
-        assert st[0].iters_done == iters
-        check_run(f"dense n={n} geometry {geometry}", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0],
-                  iters, False, r_rtol=R_RTOL_DENSE)
+        for rr in range(R):
+            assert st[rr].iters_done == iters
+            check_run(f"dense n={n} R={R} geometry {geometry} restart {rr}", trs[rr], x[:, rr], s[:, rr],
+                      logs[rr][0], logs[rr][1], acc[:, rr], iters, False, r_rtol=R_RTOL_DENSE)
+
+
+def test_adoch_dense_restarts_stop_each_on_its_own():
+    """Four restarts on stored dense couplings under eps = 1e-3: each stops
+    at its own oracle iteration and keeps its iterate while the others go
+    on."""
+    import torch
+    import paper_2509_01928_amd as L
+    n, R, q = 600, 4, 5
+    J, h, B = dense_case(n, 7370, False)
+    alpha, beta, _ = orc.default_params(B, 1.0, method="power")
+    X0 = gen.uniform_x0(n, R, 7371)
+    trs = [orc.adoch(B, X0[:, rr], alpha, beta, 3000, q, eps=1e-3) for rr in range(R)]
+    assert len({t.iters for t in trs}) > 1, "the seeded restarts should stop at different iterations"
+    Jd = torch.from_numpy(J).to("cuda:0")
+    ctx = L.ising_create_dense(n, Jd, L.ISING_F64, n)
+    try:
+        x, s, st, logs, acc = run_gpu(ctx, L, X0, R, 3000, alpha, beta, q, 1e-3, n, n)
+    finally:
+        L.ising_destroy(ctx)
+    for rr in range(R):
+        k = trs[rr].iters
+        assert st[rr].iters_done == k and st[rr].converged == 1, rr
+        check_run(f"dense restart {rr}", trs[rr], x[:, rr], s[:, rr], logs[rr][0][:k], logs[rr][1][:k],
+                  acc[:k, rr], k, False, end_fixed_point=False, r_rtol=R_RTOL_DENSE)
 
 
 def test_adoch_dense_resident_stops_with_oracle():
