@@ -1209,7 +1209,7 @@ def main():
         ingest_flops(args.ingest_flops, args.proc_n)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding is a "
                                    "design note, not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload != "torus":

@@ -45,7 +45,7 @@ typedef enum {
     ISING_E_NOT_SYMMETRIC = 3,   /* J != J^T (checked by ising_check_symmetric) */
     ISING_E_OUT_OF_MEMORY = 4,
     ISING_E_HIP = 5,             /* a HIP runtime call failed               */
-    ISING_E_UNSUPPORTED = 6,     /* valid request this build does not serve */
+    ISING_E_UNSUPPORTED = 6,     /* valid request the library does not serve */
     ISING_E_NONFINITE = 7        /* H or r became non-finite during a solve */
 } ising_status;
 

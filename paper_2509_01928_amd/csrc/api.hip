@@ -2019,7 +2019,7 @@ ising_status energy_plan(const ising_ctx* ctx, const int8_t* s_dev, int32_t R, c
     if (R < 1 || R > kMaxR) return fail(ISING_E_INVALID_ARG, "R=%d out of range", R);
     if (!E_dev && !E_int_dev) return fail(ISING_E_INVALID_ARG, "no output requested");
     if (E_int_dev && !ctx->integer_J) return fail(ISING_E_UNSUPPORTED, "integer energy needs integer couplings");
-    if (E_int_dev && ctx->dense) return fail(ISING_E_UNSUPPORTED, "integer energy is CSR-only in this build");
+    if (E_int_dev && ctx->dense) return fail(ISING_E_UNSUPPORTED, "integer energy is computed for CSR contexts only");
     if (ctx->dense && !E_dev) return fail(ISING_E_INVALID_ARG, "E is NULL");
     const int grid = ctx->dense ? std::min<int64_t>(1024, (ctx->n + 3) / 4)
                                 : std::min<int64_t>(1024, (ctx->n + 255) / 256);
