@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6          # FP64 vector peak (FMA = 2 flops)
+METHOD_FLOPS_PER_COUPLING = 2.0  # J_ij x_j: one multiply, one add
 DENSE_SOURCES = ("kernels_dense.hip", "step_common.h", "device_common.h")
 SWEEP_SOURCES = ("kernels_sweep.hip", "step_common.h", "device_common.h")
 
@@ -1024,15 +1025,18 @@ def bench_procedural(args):
     it_us = 1e3 * float(np.mean([a.elapsed_time(b) for a, b in solve_ms[args.warmup:]])) / iters
     couplings = n * (n - 1)
     flops = load_flops("dense_step_kernel", f"procedural{n}")
+    # the method's arithmetic: one multiply and one add per coupling
+    # (J_ij x_j); how J_ij is produced is the implementation's, so the
+    # counted flops (generator included) are reported as issue efficiency
+    achieved = METHOD_FLOPS_PER_COUPLING * couplings / (it_us * 1e-6) / 1e12
     roof = {"kernel": "dense_step_kernel<double, double, false, SinJ>", "bound": "alu",
-            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "achieved": achieved,
+            "frac": achieved / FP64_PEAK_TFLOPS, "method_flops_per_coupling": METHOD_FLOPS_PER_COUPLING,
             "couplings_per_s": couplings / (it_us * 1e-6)}
     if flops:
-        achieved = flops["fp64_flops_per_coupling"] * couplings / (it_us * 1e-6) / 1e12
-        roof.update({"achieved": achieved, "frac": achieved / FP64_PEAK_TFLOPS,
-                     "fp64_flops_per_coupling": flops["fp64_flops_per_coupling"]})
-    else:
-        roof.update({"achieved": None, "frac": None})
+        counted = flops["fp64_flops_per_coupling"] * couplings / (it_us * 1e-6) / 1e12
+        roof["issue"] = {"fp64_flops_per_coupling_counted": flops["fp64_flops_per_coupling"],
+                         "achieved": counted, "frac": counted / FP64_PEAK_TFLOPS}
     print(json.dumps({
         "metric": "edge-updates/s", "value": couplings * iters / dt, "unit": "edge-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
@@ -1118,13 +1122,15 @@ def bench_tune_eta(args):
         # the wall time of whole sweeps (energies and setup included)
         fl = load_flops("dense_sin_sweep_kernel", f"sweep_procedural{n}_R{len(etas)}", SWEEP_SOURCES)
         cps = nnz * len(etas) * probe / dt
+        ach = METHOD_FLOPS_PER_COUPLING * cps / 1e12
         sweep_roof = {"kernel": f"dense_sin_sweep_kernel<{len(etas)}>", "bound": "alu",
                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "coupling_probes_per_s": cps,
-                      "achieved": None, "frac": None}
+                      "achieved": ach, "frac": ach / FP64_PEAK_TFLOPS,
+                      "method_flops_per_coupling_probe": METHOD_FLOPS_PER_COUPLING}
         if fl:
-            ach = fl["fp64_flops_per_coupling"] * cps / 1e12
-            sweep_roof.update({"achieved": ach, "frac": ach / FP64_PEAK_TFLOPS,
-                               "fp64_flops_per_coupling_probe": fl["fp64_flops_per_coupling"]})
+            counted = fl["fp64_flops_per_coupling"] * cps / 1e12
+            sweep_roof["issue"] = {"fp64_flops_per_coupling_probe_counted": fl["fp64_flops_per_coupling"],
+                                   "achieved": counted, "frac": counted / FP64_PEAK_TFLOPS}
     print(json.dumps({
         "metric": "eta candidates/s", "value": len(etas) / dt, "unit": "candidates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
