@@ -105,9 +105,15 @@ __global__ __launch_bounds__(NT) void adoch_mv_kernel(
                 zr = dadd(zr, dmul(hi, tx[r]));
                 acc[S * r + 6] = dadd(acc[S * r + 6], dmul(hi, xi));
             }
-            z[t] = zr;
-            const double yi = dadd(xi, dmul(c, dsub(xi, xp[t])));
-            const double jy = dsub(dmul(dadd(1.0, c), zr), dmul(c, zp[t]));
+            // x^(k-1), z_(k-1) and z_k are streamed (read or written once
+            // per iteration); x^(k) is also gathered by other rows and stays
+            // cached
+            if constexpr (OPT) __builtin_nontemporal_store(zr, z + t);
+            else z[t] = zr;
+            const double xpt = OPT ? ld_stream(xp + t) : xp[t];
+            const double zpt = OPT ? ld_stream(zp + t) : zp[t];
+            const double yi = dadd(xi, dmul(c, dsub(xi, xpt)));
+            const double jy = dsub(dmul(dadd(1.0, c), zr), dmul(c, zpt));
             const double x2 = dmul(xi, xi), y2 = dmul(yi, yi);
             acc[S * r + 0] = dadd(acc[S * r + 0], dmul(x2, x2));
             acc[S * r + 1] = dadd(acc[S * r + 1], x2);
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(NT) void adoch_mv_kernel(
                     const double d = dsub(nx, xi);
                     acc[S * r + 7] = dadd(acc[S * r + 7], dmul(d, d));
                 }
-                xn[t] = nx;
+                __builtin_nontemporal_store(nx, xn + t);
             }
         }
     }
