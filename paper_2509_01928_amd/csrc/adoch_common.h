@@ -50,81 +50,99 @@ __device__ __forceinline__ void adoch_mv_close(double (&acc)[(OPT ? 8 : 7) * R],
 #pragma unroll
         for (int q = 0; q < K; ++q) u[q] = dadd(u[q], load_agent(a.partials + static_cast<size_t>(g) * K + q));
     block_sum<K, NT>(u, red);
-    if (threadIdx.x != 0) return;
-    const double c = a.c;
-    const double b4 = ddiv(a.beta, 4.0), a2 = ddiv(a.alpha, 2.0);
-    const int W = a.q + 1;
-    int pending = 0, all = 1;
-    for (int r = 0; r < R; ++r) {
+    // the totals to LDS, then one thread per restart: each restart's closing
+    // is a chain of dependent global accesses (state, window, logs), so the
+    // restarts run side by side instead of one after another
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) red[q] = u[q];
+    __syncthreads();
+    __shared__ int flags[2 * R];                // per restart: pending fix-up, stopped
+    const int r = threadIdx.x;
+    if (r < R) {
+        const double c = a.c;
+        const double b4 = ddiv(a.beta, 4.0), a2 = ddiv(a.alpha, 2.0);
+        const int W = a.q + 1;
+        int pending = 0;
         RestartState& st = a.state[r];
         if (OPT) a.fix[r] = 0;
         if (st.done) {
             if (OPT && FIELD) xn[n * R + r] = x[n * R + r];
-            continue;
-        }
-        double* ur = u + S * r;
-        if (FIELD) {
-            // the extra spin's row: z_n = sum_i h_i x_i, and its share of every sum
-            const int64_t tn = n * R + r;
-            const double tx = x[tn];
-            const double zn = ur[6];
-            z[tn] = zn;
-            const double yn = dadd(tx, dmul(c, dsub(tx, xp[tn])));
-            const double jyn = dsub(dmul(dadd(1.0, c), zn), dmul(c, zp[tn]));
-            const double t2 = dmul(tx, tx), y2 = dmul(yn, yn);
-            ur[0] = dadd(ur[0], dmul(t2, t2));
-            ur[1] = dadd(ur[1], t2);
-            ur[2] = dadd(ur[2], dmul(tx, zn));
-            ur[3] = dadd(ur[3], dmul(y2, y2));
-            ur[4] = dadd(ur[4], y2);
-            ur[5] = dadd(ur[5], dmul(yn, jyn));
-            if (OPT) {
-                const double nx = cbrt(ddiv(dadd(jyn, dmul(a.alpha, yn)), a.beta));
-                xn[tn] = nx;
-                const double d = dsub(nx, tx);
-                ur[7] = dadd(ur[7], dmul(d, d));
+        } else {
+            double ur[8];                       // the eighth sum only with OPT
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ur[q] = q < S ? red[S * r + q] : 0.0;
+            if (FIELD) {
+                // the extra spin's row: z_n = sum_i h_i x_i, and its share of every sum
+                const int64_t tn = n * R + r;
+                const double tx = x[tn];
+                const double zn = ur[6];
+                z[tn] = zn;
+                const double yn = dadd(tx, dmul(c, dsub(tx, xp[tn])));
+                const double jyn = dsub(dmul(dadd(1.0, c), zn), dmul(c, zp[tn]));
+                const double t2 = dmul(tx, tx), y2 = dmul(yn, yn);
+                ur[0] = dadd(ur[0], dmul(t2, t2));
+                ur[1] = dadd(ur[1], t2);
+                ur[2] = dadd(ur[2], dmul(tx, zn));
+                ur[3] = dadd(ur[3], dmul(y2, y2));
+                ur[4] = dadd(ur[4], y2);
+                ur[5] = dadd(ur[5], dmul(yn, jyn));
+                if (OPT) {
+                    const double nx = cbrt(ddiv(dadd(jyn, dmul(a.alpha, yn)), a.beta));
+                    xn[tn] = nx;
+                    const double d = dsub(nx, tx);
+                    ur[7] = dadd(ur[7], dmul(d, d));
+                }
             }
-        }
-        const double Hx = dsub(dsub(dmul(b4, ur[0]), dmul(a2, ur[1])), dmul(0.5, ur[2]));
-        const double Hy = dsub(dsub(dmul(b4, ur[3]), dmul(a2, ur[4])), dmul(0.5, ur[5]));
-        // window of H(x^(j)), max(0, k - q) <= j <= k
-        double* ring = a.ring + static_cast<size_t>(r) * W;
-        ring[a.k % W] = Hx;
-        const int64_t j0 = a.k - a.q > 0 ? a.k - a.q : 0;
-        double hmax = Hx;
-        for (int64_t j = j0; j <= a.k; ++j) hmax = fmax(hmax, ring[j % W]);
-        const int accept = Hy <= hmax ? 1 : 0;
-        a.accept[r] = accept;
-        a.log[(static_cast<size_t>(a.k) * R + r) * 2] = Hx;
-        a.accept_log[static_cast<size_t>(a.k) * R + r] = static_cast<int8_t>(accept);
-        st.H_last = Hx;
-        if (!isfinite(Hx)) {
-            st.nonfinite = 1;
-            st.done = 1;
-            st.iters_done = a.k + 1;
-            if (OPT) {
-                a.fix[r] = 2;
-                pending = 1;
-            }
-        } else if (OPT && !accept) {
-            a.fix[r] = 1;
-            pending = 1;
-        } else if (OPT) {
-            const double rr = ur[1] == 0.0 ? 0.0 : ddiv(sqrt(ur[7]), sqrt(ur[1]));
-            a.log[(static_cast<size_t>(a.k) * R + r) * 2 + 1] = rr;
-            st.iters_done = a.k + 1;
-            st.r_last = rr;
-            if (!isfinite(rr)) {
+            const double Hx = dsub(dsub(dmul(b4, ur[0]), dmul(a2, ur[1])), dmul(0.5, ur[2]));
+            const double Hy = dsub(dsub(dmul(b4, ur[3]), dmul(a2, ur[4])), dmul(0.5, ur[5]));
+            // window of H(x^(j)), max(0, k - q) <= j <= k
+            double* ring = a.ring + static_cast<size_t>(r) * W;
+            ring[a.k % W] = Hx;
+            const int64_t j0 = a.k - a.q > 0 ? a.k - a.q : 0;
+            double hmax = Hx;
+            for (int64_t j = j0; j < a.k; ++j) hmax = fmax(hmax, ring[j % W]);
+            const int accept = Hy <= hmax ? 1 : 0;
+            a.accept[r] = accept;
+            a.log[(static_cast<size_t>(a.k) * R + r) * 2] = Hx;
+            a.accept_log[static_cast<size_t>(a.k) * R + r] = static_cast<int8_t>(accept);
+            st.H_last = Hx;
+            if (!isfinite(Hx)) {
                 st.nonfinite = 1;
                 st.done = 1;
-            } else if (a.eps > 0.0 && rr < a.eps) {
-                st.converged = 1;
-                st.done = 1;
+                st.iters_done = a.k + 1;
+                if (OPT) {
+                    a.fix[r] = 2;
+                    pending = 1;
+                }
+            } else if (OPT && !accept) {
+                a.fix[r] = 1;
+                pending = 1;
+            } else if (OPT) {
+                const double rr = ur[1] == 0.0 ? 0.0 : ddiv(sqrt(ur[7]), sqrt(ur[1]));
+                a.log[(static_cast<size_t>(a.k) * R + r) * 2 + 1] = rr;
+                st.iters_done = a.k + 1;
+                st.r_last = rr;
+                if (!isfinite(rr)) {
+                    st.nonfinite = 1;
+                    st.done = 1;
+                } else if (a.eps > 0.0 && rr < a.eps) {
+                    st.converged = 1;
+                    st.done = 1;
+                }
             }
         }
-        all &= st.done;
+        flags[r] = pending;
+        flags[R + r] = st.done;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     if (OPT) {
+        int pending = 0, all = 1;
+        for (int q = 0; q < R; ++q) {
+            pending |= flags[q];
+            all &= flags[R + q];
+        }
         a.fix[8] = pending;
         if (!pending && all) *a.all_done = 1;
     }

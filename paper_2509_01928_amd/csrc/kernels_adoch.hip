@@ -204,14 +204,20 @@ __global__ __launch_bounds__(NT) void adoch_update_kernel(
 #pragma unroll
         for (int q = 0; q < 2 * R; ++q) u[q] = dadd(u[q], load_agent(a.partials + static_cast<size_t>(g) * 2 * R + q));
     block_sum<2 * R, NT>(u, red);
-    if (threadIdx.x != 0) return;
-    int all = 1;
-    for (int r = 0; r < R; ++r) {
+    // one thread per restart (each closing is a chain of global accesses)
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 2 * R; ++q) red[q] = u[q];
+    __syncthreads();
+    __shared__ int rdone[R];
+    const int r = threadIdx.x;
+    if (r < R) {
         RestartState* st = a.state + r;
         const bool mine = FIXUP ? a.fix[r] == 1 : !st->done;
         if (FIXUP) a.fix[r] = 0;
         if (mine) {
-            const double rr = u[2 * r + 1] == 0.0 ? 0.0 : ddiv(sqrt(u[2 * r]), sqrt(u[2 * r + 1]));
+            const double d2 = red[2 * r], x2 = red[2 * r + 1];
+            const double rr = x2 == 0.0 ? 0.0 : ddiv(sqrt(d2), sqrt(x2));
             a.log[(static_cast<size_t>(a.k) * R + r) * 2 + 1] = rr;
             st->iters_done = a.k + 1;
             st->r_last = rr;
@@ -223,8 +229,12 @@ __global__ __launch_bounds__(NT) void adoch_update_kernel(
                 st->done = 1;
             }
         }
-        all &= st->done;
+        rdone[r] = st->done;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int all = 1;
+    for (int q = 0; q < R; ++q) all &= rdone[q];
     if (FIXUP) a.fix[8] = 0;
     if (all) *a.all_done = 1;
     reset_ticket(a.ticket);
