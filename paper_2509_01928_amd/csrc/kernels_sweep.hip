@@ -312,7 +312,18 @@ int grid_rows8(int64_t n) {
 
 template <typename VT, typename HT, bool FIELD>
 hipError_t launch_sweep_f(const CsrView& A, const SweepArgs& a, hipStream_t s) {
-    const int grid = sweep_grid(A.n);
+    int grid = sweep_grid(A.n);
+    if (A.row_len == 4) {
+        // rows of 4 entries with implicit offsets (no dependent load chain to
+        // hide) stream best with four workgroups per compute unit (measured
+        // on the 10^8-spin lattice, 8 probes: 78.9 ms per sweep against 95.8
+        // with 16 per CU, 87.0 with 8 and 87.6 with 2)
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&
+            grid > 4 * cus)
+            grid = 4 * cus;
+    }
     switch (a.R) {
 #define DOCH_SWEEP_R(RR)                                                                                   \
     case RR:                                                                                               \
