@@ -254,6 +254,29 @@ def test_adoch_csr_rejections_mixed_across_restarts():
                   acc[:, rr], iters, True)
 
 
+def test_adoch_lattice_rows_per_lane():
+    """The lattice with its field at 160 000 rows: the product on rows of 4
+    entries runs two workgroups per CU, so every lane walks several rows;
+    30 iterations against the oracle's ADOCH (decisions, H and r logs,
+    iterates)."""
+    import paper_2509_01928_amd as L
+    from tests._util import GpuProblem
+    A = gen.torus_csr(400, 7381, h_std=0.1)
+    B = orc.problem_matrix(A)
+    alpha, beta, _ = orc.default_params(B, 1.0)
+    q, iters = 5, 30
+    X0 = gen.uniform_x0(B.n, 1, 7382)
+    tr = orc.adoch(B, X0[:, 0], alpha, beta, iters, q)
+    P = GpuProblem(A=A)
+    try:
+        x, s, st, logs, acc = run_gpu(P.ctx, L, X0, 1, iters, alpha, beta, q, 0.0, B.n, A.n)
+    finally:
+        P.close()
+    assert st[0].iters_done == iters
+    check_run("lattice L=400", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0], iters, True,
+              end_fixed_point=False)
+
+
 def test_adoch_refused_shapes():
     import torch
     import paper_2509_01928_amd as L

@@ -680,7 +680,7 @@ def test_constant_row_length_detected():
 
 
 # ------------------------------------------------------ eta tuning (Supp. Note 6)
-@pytest.mark.parametrize("case", ["er", "torus_field", "er_two_groups", "er_lone", "single"])
+@pytest.mark.parametrize("case", ["er", "torus_field", "er_two_groups", "er_lone", "single", "torus_large"])
 def test_tune_eta_matches_oracle_probes(case):
     """Short probe runs per eta: every probe energy and the chosen eta agree
     with the oracle's own probe runs (parameters by eq:alphabeta).  On CSR
@@ -705,6 +705,12 @@ def test_tune_eta_matches_oracle_probes(case):
         A = gen.er_csr(500, 4.0, 207)
         x0 = gen.uniform_x0(A.n, 1, 208)[:, 0]
         etas, probe = [1.3], 1
+    elif case == "torus_large":
+        # 90 000 rows: more than four workgroups per CU hold, so every lane
+        # group of the sweep walks several rows
+        A = gen.torus_csr(300, 209, h_std=0.5)
+        x0 = gen.uniform_x0(A.n + 1, 1, 210)[:, 0]
+        probe = 6
     else:
         A = gen.torus_csr(40, 203, h_std=1.0)
         x0 = gen.uniform_x0(A.n + 1, 1, 204)[:, 0]
