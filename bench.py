@@ -70,6 +70,8 @@ def parse():
                     help="JSON cache of the launch-shape autotuners (batch512, dense4096)")
     ap.add_argument("--ingest-pmc", nargs=4, metavar="CSV",
                     help="record HBM traffic from rocprofv3 counter files and exit")
+    ap.add_argument("--pmc-family", choices=["step", "adoch"], default="step",
+                    help="--ingest-pmc: the lattice step kernel, or the ADOCH product (workload adoch)")
     ap.add_argument("--tune-instance", choices=["torus", "s5", "procedural"], default="torus",
                     help="tune_eta: the lattice, the Supp. Alg. S5 instance or the procedural "
                          "sin(ij+100) couplings (--proc-n spins)")
@@ -107,7 +109,12 @@ def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False
     return f"{name}<{xt}, float, float, true, {tail}>"
 
 
-def load_traffic(kernel: str, workload: str):
+# the sources whose hash a counter record of each kernel family is kept under
+STEP_SOURCES = ("kernels_csr.hip", "step_common.h", "device_common.h")
+ADOCH_SOURCES = ("kernels_adoch.hip", "adoch_common.h", "device_common.h")
+
+
+def load_traffic(kernel: str, workload: str, sources=STEP_SOURCES):
     """HBM bytes per launch measured by rocprofv3 counters, if they were taken
     on this kernel instance and on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -115,7 +122,7 @@ def load_traffic(kernel: str, workload: str):
         return None
     with open(path) as f:
         rec = json.load(f).get(workload)
-    if not rec or rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernel", ""):
+    if not rec or rec.get("source_hash") != kernel_source_hash(sources) or kernel not in rec.get("kernel", ""):
         return None
     return rec
 
@@ -170,12 +177,13 @@ def ingest_flops(path, n):
         json.dump(data, f, indent=1)
 
 
-def ingest_pmc(paths, workload):
+def ingest_pmc(paths, workload, family="step"):
     """Turn four rocprofv3 --pmc counter_collection.csv files (step kernel
     FETCH_SIZE, step kernel WRITE_SIZE, copy kernel FETCH_SIZE, copy kernel
     WRITE_SIZE; values in KiB per dispatch) into HBM bytes per launch of the
-    step kernel, scaled by what the counters read for a copy of known size,
-    and store them in profiles/traffic.json under the current source hash."""
+    step kernel (family "step") or of the ADOCH product (family "adoch"),
+    scaled by what the counters read for a copy of known size, and store them
+    in profiles/traffic.json under the hash of that kernel's sources."""
     import csv
     from collections import defaultdict
 
@@ -197,13 +205,15 @@ def ingest_pmc(paths, workload):
     copy_bytes = float(1024 * 1024 * 1024)
     fetch_scale = copy_bytes / (1024.0 * sum(cf[copy_name]) / len(cf[copy_name]))
     write_scale = copy_bytes / (1024.0 * sum(cw[copy_name]) / len(cw[copy_name]))
-    # the timed kernel is the step-kernel variant dispatched most often
-    steps = [k for k in fetch if "csr_step_kernel" in k or "csr_rowlane_kernel" in k]
+    # the timed kernel is the variant of the family dispatched most often
+    names = ("adoch_mv_kernel",) if family == "adoch" else ("csr_step_kernel", "csr_rowlane_kernel")
+    sources = ADOCH_SOURCES if family == "adoch" else STEP_SOURCES
+    steps = [k for k in fetch if any(m in k for m in names)]
     step = max(steps, key=lambda k: len(fetch[k]))
     f_kib = sum(fetch[step]) / len(fetch[step])
     w_kib = sum(write[step]) / len(write[step])
     rec = {
-        "kernel": step, "source_hash": kernel_source_hash(),
+        "kernel": step, "source_hash": kernel_source_hash(sources),
         "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
         "fetch_scale": fetch_scale, "write_scale": write_scale,
         "hbm_bytes_per_launch": 1024.0 * (f_kib * fetch_scale + w_kib * write_scale),
@@ -868,6 +878,8 @@ def bench_adoch(args):
     #   repair : x^(k), z_k read, x^(k+1) = T(x) written, rejected
     #            iterations only
     rejected = float(np.mean(acc == 0))
+    traffic = load_traffic("adoch_mv_kernel<float, float, true, 4, 1, true>", f"adoch_torus{args.L}",
+                           ADOCH_SOURCES)
     prod = 4 * (n + 1) + 8 * nnz + 4 * n + 5 * 8 * np1
     upd = 3 * 8 * np1
     bytes_iter = prod + rejected * upd
@@ -885,7 +897,10 @@ def bench_adoch(args):
         "accepted_fraction": float(np.mean(acc)),
         "roofline": {"kernel": "adoch_mv_kernel<float, float, true, 4, 1, true> + adoch_update_kernel<1, true>",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     # HBM bytes per launch of the product (rocprofv3 counters
+                     # scaled by a copy of known size), if taken on this source
+                     "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
                      "algorithmic_bytes_per_iteration": bytes_iter,
                      "bytes_product": prod, "bytes_repair": upd, "rejected_fraction": rejected},
     }), flush=True)
@@ -1209,7 +1224,10 @@ def full_scale_parity(orc, B, x0, alpha, beta, iters, tr, gpu_par):
 def main():
     args = parse()
     if args.ingest_pmc:
-        ingest_pmc(args.ingest_pmc, f"torus{args.L}_{args.x_dtype}")
+        if args.pmc_family == "adoch":
+            ingest_pmc(args.ingest_pmc, f"adoch_torus{args.L}", "adoch")
+        else:
+            ingest_pmc(args.ingest_pmc, f"torus{args.L}_{args.x_dtype}")
         return
     if args.ingest_flops:
         ingest_flops(args.ingest_flops, args.proc_n)
