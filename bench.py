@@ -98,15 +98,19 @@ _GEOMETRY_KERNEL = {0: ("csr_step_kernel", "1, 1, false"), 1: ("csr_step_kernel"
                     6: ("csr_step_kernel", "2, 2, true"), 7: ("csr_step_kernel", "4, 2, true")}
 
 
-def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False) -> str:
-    """Kernel instance timed on the lattice (FP32 couplings and field)."""
+def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False,
+                     val_bytes: int = 4) -> str:
+    """Kernel instance timed on the lattice (FP32 couplings and field; the
+    lane-per-row kernels read the 8-bit copy of small-integer values)."""
     xt = "float" if x_dtype == "f32" else "double"
     if geometry == 8:                                      # the single-launch solve
         return f"resident_csr_kernel<{xt}, float, float, true>"
     name, tail = _GEOMETRY_KERNEL[geometry]
+    vt = "float"
     if name == "csr_rowlane_kernel":
         tail += ", 4" if implicit_offsets else ", 0"      # the lattice's rows hold 4 entries
-    return f"{name}<{xt}, float, float, true, {tail}>"
+        vt = "signed char" if val_bytes == 1 else "float"
+    return f"{name}<{xt}, {vt}, float, true, {tail}>"
 
 
 # the sources whose hash a counter record of each kernel family is kept under
@@ -334,7 +338,9 @@ def bench_er20000(args):
     e1.record()
     torch.cuda.synchronize()
     it_us = 1e3 * e0.elapsed_time(e1) / iters
-    bytes_iter = 4 * (A.n + 1) + 8 * A.nnz + 16 * A.n
+    # the lane-per-row geometries stream the 8-bit copy of the +-1 values
+    vb = L.ising_get_info(ctx).step_val_bytes if g in (3, 4) else 4
+    bytes_iter = 4 * (A.n + 1) + (4 + vb) * A.nnz + 16 * A.n
     extra = {}
     if not args.no_cpu_baseline:
         import oracle as orc
@@ -366,7 +372,7 @@ def bench_er20000(args):
                                         "kernel_geometry": g, "workgroups_per_cu": w},
         "iteration_us": it_us, "energy_int64": int(E.cpu()[0]),
         "autotune_us_per_iteration": {str(k): round(m * 1e3, 2) for k, m in enumerate(ms) if m > 0},
-        "roofline": {"kernel": "resident_csr_kernel" if g == 8 else step_kernel_name(g, "f64"),
+        "roofline": {"kernel": "resident_csr_kernel" if g == 8 else step_kernel_name(g, "f64", False, vb),
                      "bound": "latency", "achieved": bytes_iter / (it_us * 1e-6) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bytes_iter / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
@@ -1267,8 +1273,9 @@ def main():
     s_out = torch.empty(A.n, dtype=torch.int8, device=dev)
     E = torch.empty(1, dtype=torch.float64, device=dev)
     x_dtype = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
-    row_len = L.ising_get_info(ctx).row_len
-    log(f"context created (constant row length {row_len})" if row_len else "context created")
+    info = L.ising_get_info(ctx)
+    row_len, val_bytes = info.row_len, info.step_val_bytes
+    log(f"context created (constant row length {row_len}, {val_bytes} B per value in the lane-per-row step)")
     # launch-shape tuning is setup, outside the timed region
     if args.geometry >= -1:
         L.ising_set_geometry(ctx, args.geometry, args.wg_per_cu)
@@ -1320,14 +1327,17 @@ def main():
     bytes_iter = 4 * (n + 1) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
     csr_gbs = bytes_iter / (per_iter_ms * 1e-3) / 1e9
     # with a constant row length the lane-per-row kernels compute the row
-    # offsets instead of reading them, so the bytes the step needs are 11 B
-    # per edge-update; the headline fraction is taken on those, the CSR-format
-    # figure is kept beside it
-    implicit = row_len > 0 and geometry in (3, 4)
-    kernel_bytes = bytes_iter - (4 * (n + 1) if implicit else 0)
+    # offsets instead of reading them, and with small-integer values (the
+    # lattice's +-1) they stream the library's exact 8-bit copy of the values,
+    # so the bytes the step needs are 8 B per edge-update; the headline
+    # fraction is taken on those, the CSR-format figure is kept beside it
+    rowlane = geometry in (3, 4)
+    implicit = row_len > 0 and rowlane
+    vb = val_bytes if rowlane else 4
+    kernel_bytes = bytes_iter - (4 * (n + 1) if implicit else 0) - (4 - vb) * nnz
     achieved = kernel_bytes / (per_iter_ms * 1e-3) / 1e9
     workload = f"torus{args.L}"
-    kernel = step_kernel_name(geometry, args.x_dtype, implicit)
+    kernel = step_kernel_name(geometry, args.x_dtype, implicit, vb)
     traffic = load_traffic(kernel, f"{workload}_{args.x_dtype}")
     edge_updates = float(nnz) * args.iters * args.steps
     out = {
@@ -1353,6 +1363,8 @@ def main():
             "arithmetic": "f64", "parallelism": "single GPU",
             "kernel_geometry": geometry, "workgroups_per_cu": wg_per_cu,
             "row_offsets": (f"implicit (every row holds {row_len} entries)" if implicit else "read"),
+            "values_streamed": ("8-bit copy (every value an integer in [-128, 127])" if vb == 1
+                                else "f32 as stored"),
         },
         "iteration_us": per_iter_ms * 1e3,
         "energy": energy,

@@ -96,6 +96,12 @@ typedef struct {
     int32_t geometry;      /* geometry single-restart solves use (see
                               ising_set_geometry): 0..8 for CSR; -1
                               (automatic), 0 or 8 for dense; -1 for batches */
+    int32_t step_val_bytes; /* bytes per coupling value the lane-per-row
+                              CSR step (geometries 3, 4) streams: 1 when
+                              every value is an integer in [-128, 127] (the
+                              library then keeps an exact 8-bit copy beside
+                              the values, nnz more bytes of device memory),
+                              else the size of val_dtype; 8 for dense      */
 } ising_info;
 
 /* ---------------------------------------------------------------- create

@@ -98,6 +98,7 @@ CsrView csr_view(const ising_ctx* c) {
     v.h = c->h;
     v.ht = c->ht;
     v.row_len = c->row_len;
+    v.val8 = c->val8;
     return v;
 }
 
@@ -182,6 +183,7 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->rp);
     dev_free(c->col);
     dev_free(c->val);
+    dev_free(c->val8);
     dev_free(c->h);
     dev_free(c->J);
     for (auto& p : c->plans) dev_free(p.binfo);
@@ -628,6 +630,14 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
         for (int64_t i = 0; i <= n && regular; ++i) regular = rp_host[i] == d * i;
         c->row_len = regular ? static_cast<int32_t>(d) : 0;
     }
+    // every value an integer in [-128, 127] (the lattice's +-1 among them):
+    // an exact 8-bit copy that the lane-per-row step streams instead
+    if (nnz > 0 && !flags[3]) {
+        if ((e = dev_alloc(&c->val8, padded)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(val8)"));
+        if ((e = hipMemsetAsync(c->val8 + nnz, 0, doch::kCsrPad, s)) != hipSuccess) return bail(hip_fail(e, "memset pad"));
+        if ((e = doch::launch_csr_pack_i8(csr_view(c), c->val8, s)) != hipSuccess) return bail(hip_fail(e, "pack values"));
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sync"));
+    }
     c->rp_host = std::move(rp_host);
     c->geometry = default_geometry(n, nnz);
     c->wg_per_cu = default_wg_per_cu(c->geometry, c->row_len);
@@ -728,6 +738,7 @@ ising_status ising_get_info(const ising_ctx* ctx, ising_info* out) {
     out->val_dtype = ctx->vt;
     out->row_len = ctx->row_len;
     out->geometry = ctx->batch ? -1 : ctx->geometry;
+    out->step_val_bytes = ctx->val8 ? 1 : static_cast<int32_t>(ctx->dense ? 8 : dtype_size(ctx->vt));
     return ISING_OK;
 }
 

@@ -18,7 +18,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Vec4;
 typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef signed char i8x4 __attribute__((ext_vector_type(4)));
 template <> struct Vec4<int> { using type = i32x4; };
+template <> struct Vec4<int8_t> { using type = i8x4; };
 template <> struct Vec4<int16_t> { using type = i16x4; };
 template <> struct Vec4<float> { using type = f32x4; };
 template <> struct Vec4<double> { using type = f64x4; };

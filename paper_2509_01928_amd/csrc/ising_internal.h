@@ -57,6 +57,8 @@ struct CsrView {
     const void* h;          // nullptr: no field
     int ht;
     int row_len;            // d > 0: every row holds d entries, row i starts at d i
+    const int8_t* val8 = nullptr;  // the values as 8-bit integers when every one is an
+                            // integer in [-128, 127] (padded like val), else nullptr
 };
 
 struct DenseView {
@@ -305,6 +307,7 @@ struct ising_ctx {
     int32_t* rp = nullptr;
     int32_t* col = nullptr;
     void* val = nullptr;
+    int8_t* val8 = nullptr;  // 8-bit copy of val read by the lane-per-row step
     int vt = ISING_F32;
     void* h = nullptr;
     int ht = ISING_F32;
@@ -403,6 +406,9 @@ namespace doch {
 
 // ---- launchers (kernels_csr.hip) ----
 hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s);
+// out[0, nnz) = the values as 8-bit integers (valid when csr_validate
+// raised no flags[3]); out must hold nnz + kCsrPad bytes
+hipError_t launch_csr_pack_i8(const CsrView& A, int8_t* out, hipStream_t s);
 void csr_geometry(int geometry, int* rows, int* span);
 hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs& a,
                            hipStream_t s);

@@ -504,7 +504,8 @@ __global__ __launch_bounds__(NT) void csr_energy8_kernel(
 
 // ------------------------------------------------------------ validation
 // flags[0]: malformed CSR, flags[1]: nonzero diagonal, flags[2]: a value is
-// not an integer of magnitude < 2^31.
+// not an integer of magnitude < 2^31, flags[3]: a value is not an integer in
+// [-128, 127].
 template <typename VT>
 __global__ __launch_bounds__(NT) void csr_validate_kernel(
     int64_t n, int64_t nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -524,6 +525,7 @@ __global__ __launch_bounds__(NT) void csr_validate_kernel(
             const double v = static_cast<double>(val[e]);
             if (c == i && v != 0.0) atomicOr(flags + 1, 1);
             if (!(v == floor(v)) || fabs(v) >= 2147483648.0) atomicOr(flags + 2, 1);
+            if (!(v == floor(v)) || v < -128.0 || v > 127.0) atomicOr(flags + 3, 1);
         }
     }
 }
@@ -799,6 +801,20 @@ hipError_t launch_step_geo(const CsrView& A, const CsrPlan& plan, const StepArgs
     }
 }
 
+template <typename XT, typename HT, bool FIELD>
+hipError_t launch_rowlane_i8_f(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    CsrView B = A;
+    B.val = A.val8;
+    if (plan.geometry == 3) return launch_rowlane_t<XT, int8_t, HT, FIELD, 1, 1>(B, plan, a, s);
+    return launch_rowlane_t<XT, int8_t, HT, FIELD, 1, 2>(B, plan, a, s);
+}
+
+template <typename XT, typename HT>
+hipError_t launch_rowlane_i8(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    if (A.h) return launch_rowlane_i8_f<XT, HT, true>(A, plan, a, s);
+    return launch_rowlane_i8_f<XT, HT, false>(A, plan, a, s);
+}
+
 template <typename XT, typename VT, typename HT>
 hipError_t launch_step_field(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
     if (A.h) return launch_step_geo<XT, VT, HT, true>(A, plan, a, s);
@@ -817,6 +833,15 @@ void csr_geometry(int geometry, int* rows, int* span) {
 }
 
 hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
+    // small-integer couplings: the lane-per-row kernels stream the 8-bit copy
+    // (a quarter of the FP32 value bytes; the products are the same, since
+    // each value converts exactly)
+    if (A.val8 && (plan.geometry == 3 || plan.geometry == 4)) {
+        const bool f64x = a.x_dtype == ISING_F64;
+        if (A.ht == ISING_F64)
+            return f64x ? launch_rowlane_i8<double, double>(A, plan, a, s) : launch_rowlane_i8<float, double>(A, plan, a, s);
+        return f64x ? launch_rowlane_i8<double, float>(A, plan, a, s) : launch_rowlane_i8<float, float>(A, plan, a, s);
+    }
     DOCH_DISPATCH_VT_HT(A, {
         if (a.x_dtype == ISING_F64) return launch_step_field<double, VT, HT>(A, plan, a, s);
         return launch_step_field<float, VT, HT>(A, plan, a, s);
@@ -899,6 +924,33 @@ hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s) 
     else
         hipLaunchKernelGGL(csr_validate_kernel<float>, dim3(grid), dim3(NT), 0, s, A.n, A.nnz,
                            A.rp, A.col, static_cast<const float*>(A.val), flags);
+    return hipGetLastError();
+}
+
+namespace {
+// out[e] = val[e] for values already checked to be integers in [-128, 127],
+// so the conversion is exact.
+template <typename VT>
+__global__ __launch_bounds__(NT) void csr_pack_i8_kernel(int64_t nnz, const VT* __restrict__ val,
+                                                         int8_t* __restrict__ out) {
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; e < nnz;
+         e += static_cast<int64_t>(gridDim.x) * NT)
+        out[e] = static_cast<int8_t>(static_cast<int>(val[e]));
+}
+}  // namespace
+
+hipError_t launch_csr_pack_i8(const CsrView& A, int8_t* out, hipStream_t s) {
+    if (A.nnz <= 0) return hipSuccess;
+    const int grid = grid_for_rows(A.nnz);
+    if (A.vt == ISING_F64)
+        hipLaunchKernelGGL(csr_pack_i8_kernel<double>, dim3(grid), dim3(NT), 0, s, A.nnz,
+                           static_cast<const double*>(A.val), out);
+    else if (A.vt == ISING_I16)
+        hipLaunchKernelGGL(csr_pack_i8_kernel<int16_t>, dim3(grid), dim3(NT), 0, s, A.nnz,
+                           static_cast<const int16_t*>(A.val), out);
+    else
+        hipLaunchKernelGGL(csr_pack_i8_kernel<float>, dim3(grid), dim3(NT), 0, s, A.nnz,
+                           static_cast<const float*>(A.val), out);
     return hipGetLastError();
 }
 

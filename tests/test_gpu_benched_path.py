@@ -105,3 +105,69 @@ def test_read_offsets_multi_trip():
         info, x, s, st, H, r = _run(case, geometry, wpc, "f64")
         assert info.row_len == 0
         _check(case, f"ER n=300000 geometry {geometry} wg/CU {wpc}", info, x, s, st, H, r, "f64")
+
+
+def _symmetric_values(A, fn):
+    """Replace the values by fn(min(i, j), max(i, j)), keeping J symmetric."""
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+    cols = A.col.astype(np.int64)
+    A.val = fn(np.minimum(rows, cols), np.maximum(rows, cols)).astype(np.float32)
+    return A
+
+
+@pytest.fixture(scope="module")
+def torus600_int8():
+    # integer couplings over the whole 8-bit range: the lane-per-row step
+    # streams the library's 8-bit copy of them; 360 001 rows, more than the
+    # 262 144 lanes at 4 workgroups per CU
+    A = gen.torus_csr(600, 1106, h_std=0.1)
+    A = _symmetric_values(A, lambda a, b: ((a * 2654435761 + b * 40503) >> 9) % 256 - 128)
+    assert A.val.min() == -128 and A.val.max() == 127
+    return _case(A, 2106)
+
+
+@pytest.fixture(scope="module")
+def torus600_frac():
+    # non-integer couplings: the lane-per-row step streams the FP32 values
+    A = gen.torus_csr(600, 1107, h_std=0.1)
+    A.val = A.val * np.float32(0.37)
+    return _case(A, 2107)
+
+
+@pytest.mark.parametrize("x_dtype", ["f32", "f64"])
+@pytest.mark.parametrize("geometry,wg_per_cu", [(3, 4), (4, 0)])
+def test_lattice_rowlane_8bit_values(torus600_int8, geometry, wg_per_cu, x_dtype):
+    info, x, s, st, H, r = _run(torus600_int8, geometry, wg_per_cu, x_dtype)
+    assert info.row_len == 4 and info.step_val_bytes == 1
+    _check(torus600_int8, f"torus L=600 values in [-128, 127] geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
+           info, x, s, st, H, r, x_dtype)
+
+
+@pytest.mark.parametrize("x_dtype", ["f32", "f64"])
+@pytest.mark.parametrize("geometry,wg_per_cu", [(3, 4), (4, 0)])
+def test_lattice_rowlane_fp32_values(torus600_frac, geometry, wg_per_cu, x_dtype):
+    info, x, s, st, H, r = _run(torus600_frac, geometry, wg_per_cu, x_dtype)
+    assert info.row_len == 4 and info.step_val_bytes == 4
+    _check(torus600_frac, f"torus L=600 values 0.37 * (+-1) geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
+           info, x, s, st, H, r, x_dtype)
+
+
+def test_8bit_copy_only_for_8bit_integers():
+    """The 8-bit copy is kept exactly when every value is an integer in
+    [-128, 127]; one value outside (128, or 0.5) keeps the stored values."""
+    import paper_2509_01928_amd as Lb
+    base = gen.er_csr(3000, 5.0, 1108)
+    for top, want in ((127.0, 1), (128.0, 4), (-128.0, 1), (0.5, 4)):
+        A = gen.er_csr(3000, 5.0, 1108)
+        # the first stored pair (i, j) and its mirror (j, i) take the value `top`
+        i0 = 0
+        j0 = int(base.col[base.row_ptr[0]])
+        A.val[base.row_ptr[i0]] = top
+        k = base.row_ptr[j0] + int(np.searchsorted(base.col[base.row_ptr[j0]:base.row_ptr[j0 + 1]], i0))
+        assert base.col[k] == i0
+        A.val[k] = top
+        P = GpuProblem(A=A)
+        try:
+            assert Lb.ising_get_info(P.ctx).step_val_bytes == want, top
+        finally:
+            P.close()
