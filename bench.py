@@ -878,15 +878,18 @@ def bench_adoch(args):
     n, nnz, np1 = A.n, A.nnz, A.n + 1
     # one pass over the vectors when y is accepted, a second one only when
     # it is rejected (the acceptance test is a global reduction):
-    #   product: offsets, indices, values, field, x^(k) (read with its
+    #   product: indices, values, field, x^(k) (read with its
     #            gathers), x^(k-1), z_(k-1) read, z_k and x^(k+1) = T(y)
     #            written
     #   repair : x^(k), z_k read, x^(k+1) = T(x) written, rejected
     #            iterations only
     rejected = float(np.mean(acc == 0))
-    traffic = load_traffic("adoch_mv_kernel<float, float, true, 4, 1, true>", f"adoch_torus{args.L}",
-                           ADOCH_SOURCES)
-    prod = 4 * (n + 1) + 8 * nnz + 4 * n + 5 * 8 * np1
+    # the product on 4-entry rows computes the row starts and streams the
+    # library's 8-bit copy of the +-1 values
+    vb = L.ising_get_info(ctx).step_val_bytes
+    kname = f"adoch_mv_kernel<{'signed char' if vb == 1 else 'float'}, float, true, 4, 1, true>"
+    traffic = load_traffic(kname, f"adoch_torus{args.L}", ADOCH_SOURCES)
+    prod = (4 + vb) * nnz + 4 * n + 5 * 8 * np1
     upd = 3 * 8 * np1
     bytes_iter = prod + rejected * upd
     achieved = bytes_iter / (it_us * 1e-6) / 1e9
@@ -901,7 +904,7 @@ def bench_adoch(args):
                    "n": n, "nnz": nnz, "iters": iters, "x_storage": "f64", "q": 5},
         "iteration_us": it_us, "energy": float(E.cpu()[0]),
         "accepted_fraction": float(np.mean(acc)),
-        "roofline": {"kernel": "adoch_mv_kernel<float, float, true, 4, 1, true> + adoch_update_kernel<1, true>",
+        "roofline": {"kernel": kname + " + adoch_update_kernel<1, true>",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      # HBM bytes per launch of the product (rocprofv3 counters
@@ -1129,14 +1132,19 @@ def bench_tune_eta(args):
     # (the 8-restart energy adds its workgroups' sums in another order)
     assert np.allclose(np.array(out["e"]), energies, rtol=1e-12, atol=1e-6), "batched and sequential probes differ"
     n, nnz = A.n, A.nnz
-    vb = 2 if args.tune_instance == "s5" else 4
-    # one pass per probe iteration for all 8 probes: offsets, indices and
-    # values, the field, and 8 FP64 iterates read and written (the
-    # procedural couplings are generated, not read)
+    # one pass per probe iteration for all 8 probes: offsets (not read with
+    # 4-entry rows, whose starts are computed), indices and values (the
+    # library's 8-bit copy of the lattice's +-1 on 4-entry rows), the field,
+    # and 8 FP64 iterates read and written (the procedural couplings are
+    # generated, not read)
     if args.tune_instance == "procedural":
         bytes_iter = 2 * 8 * len(etas) * n
     else:
-        bytes_iter = 4 * (n + 1) + (4 + vb) * nnz + (4 * n if field else 0) + 2 * 8 * len(etas) * (n + 1)
+        info = L.ising_get_info(ctx)
+        four = info.row_len == 4
+        vb = info.step_val_bytes if four else (2 if args.tune_instance == "s5" else 4)
+        bytes_iter = ((0 if four else 4 * (n + 1)) + (4 + vb) * nnz + (4 * n if field else 0)
+                      + 2 * 8 * len(etas) * (n + 1))
     sweep_bytes = bytes_iter * probe
     if args.tune_instance == "procedural":
         # FP64 flops per coupling and probe, counted on the sweep kernel, over
@@ -1166,7 +1174,8 @@ def bench_tune_eta(args):
         # the batched pass's algorithmic bytes over the wall time of whole
         # sweeps (energies and parameter setting included)
         "roofline": (sweep_roof if args.tune_instance == "procedural" else
-                     {"kernel": "csr_sweep_kernel", "bound": "hbm",
+                     {"kernel": "csr_sweep_kernel" + ("<signed char, float, true, 8, 4>" if field and vb == 1 else ""),
+                      "bound": "hbm",
                       "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,
                       "algorithmic_bytes_per_iteration": bytes_iter}),

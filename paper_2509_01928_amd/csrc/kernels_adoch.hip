@@ -329,8 +329,14 @@ hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, 
             grid > 2 * cus)
             grid = 2 * cus;
     }
+    // small-integer couplings on 4-entry rows: the library's exact 8-bit
+    // copy of the values is streamed instead (a quarter of the FP32 bytes)
+    const bool i8 = A.val8 && A.row_len == 4;
+    CsrView B = A;
+    if (i8) B.val = A.val8;
     DOCH_ADOCH_R(a.R, {
-        if (A.vt == ISING_I16) adoch_mv_vt<int16_t, RR>(A, grid, x, xp, zp, z, xn, a, s);
+        if (i8) adoch_mv_vt<int8_t, RR>(B, grid, x, xp, zp, z, xn, a, s);
+        else if (A.vt == ISING_I16) adoch_mv_vt<int16_t, RR>(A, grid, x, xp, zp, z, xn, a, s);
         else if (A.vt == ISING_F64) adoch_mv_vt<double, RR>(A, grid, x, xp, zp, z, xn, a, s);
         else adoch_mv_vt<float, RR>(A, grid, x, xp, zp, z, xn, a, s);
     });

@@ -13,6 +13,8 @@
 // (eq:Hamilton, Remark S2, Supp. Note 1).
 #include "device_common.h"
 #include "ising_internal.h"
+
+#include <type_traits>
 #include "step_common.h"
 
 namespace doch {
@@ -310,6 +312,23 @@ int grid_rows8(int64_t n) {
     return static_cast<int>(g);
 }
 
+// the 8-bit copy of the values is only streamed on 4-entry rows
+template <typename VT, typename HT, bool FIELD, int RR>
+void sweep_go(const CsrView& A, int grid, const SweepArgs& a, hipStream_t s) {
+    const VT* v = static_cast<const VT*>(A.val);
+    const HT* h = static_cast<const HT*>(A.h);
+    if constexpr (std::is_same<VT, int8_t>::value) {
+        hipLaunchKernelGGL((csr_sweep_kernel<VT, HT, FIELD, RR, 4>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, a);
+    } else if (A.row_len == 4) {
+        hipLaunchKernelGGL((csr_sweep_kernel<VT, HT, FIELD, RR, 4>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, a);
+    } else {
+        hipLaunchKernelGGL((csr_sweep_kernel<VT, HT, FIELD, RR, 0>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
+                           A.col, v, h, a);
+    }
+}
+
 template <typename VT, typename HT, bool FIELD>
 hipError_t launch_sweep_f(const CsrView& A, const SweepArgs& a, hipStream_t s) {
     int grid = sweep_grid(A.n);
@@ -325,14 +344,9 @@ hipError_t launch_sweep_f(const CsrView& A, const SweepArgs& a, hipStream_t s) {
             grid = 4 * cus;
     }
     switch (a.R) {
-#define DOCH_SWEEP_R(RR)                                                                                   \
-    case RR:                                                                                               \
-        if (A.row_len == 4)                                                                                \
-            hipLaunchKernelGGL((csr_sweep_kernel<VT, HT, FIELD, RR, 4>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,  \
-                               A.col, static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), a);          \
-        else                                                                                               \
-            hipLaunchKernelGGL((csr_sweep_kernel<VT, HT, FIELD, RR, 0>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,  \
-                               A.col, static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), a);          \
+#define DOCH_SWEEP_R(RR)                          \
+    case RR:                                      \
+        sweep_go<VT, HT, FIELD, RR>(A, grid, a, s); \
         break;
         DOCH_SWEEP_R(1)
         DOCH_SWEEP_R(2)
@@ -390,6 +404,13 @@ hipError_t launch_dense_sin_sweep(int64_t n, double seed, const SweepArgs& a, hi
 
 hipError_t launch_sweep_step(const CsrView& A, const SweepArgs& a, hipStream_t s) {
     const bool h64 = A.h && A.ht == ISING_F64;
+    // small-integer couplings on 4-entry rows: stream the library's exact
+    // 8-bit copy of the values (a quarter of the FP32 bytes)
+    if (A.val8 && A.row_len == 4) {
+        CsrView B = A;
+        B.val = A.val8;
+        return h64 ? launch_sweep_v<int8_t, double>(B, a, s) : launch_sweep_v<int8_t, float>(B, a, s);
+    }
     if (A.vt == ISING_I16) return h64 ? launch_sweep_v<int16_t, double>(A, a, s) : launch_sweep_v<int16_t, float>(A, a, s);
     if (A.vt == ISING_F64) return h64 ? launch_sweep_v<double, double>(A, a, s) : launch_sweep_v<double, float>(A, a, s);
     return h64 ? launch_sweep_v<float, double>(A, a, s) : launch_sweep_v<float, float>(A, a, s);

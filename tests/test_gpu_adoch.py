@@ -254,14 +254,22 @@ def test_adoch_csr_rejections_mixed_across_restarts():
                   acc[:, rr], iters, True)
 
 
-def test_adoch_lattice_rows_per_lane():
+@pytest.mark.parametrize("values,val_bytes", [("pm1", 1), ("int8", 1), ("frac", 4)])
+def test_adoch_lattice_rows_per_lane(values, val_bytes):
     """The lattice with its field at 160 000 rows: the product on rows of 4
     entries runs two workgroups per CU, so every lane walks several rows;
     30 iterations against the oracle's ADOCH (decisions, H and r logs,
-    iterates)."""
+    iterates).  Couplings +-1 or integers over [-128, 127] (the product
+    streams the library's 8-bit copy), or 0.37 * (+-1) (the FP32 values)."""
     import paper_2509_01928_amd as L
     from tests._util import GpuProblem
     A = gen.torus_csr(400, 7381, h_std=0.1)
+    if values == "int8":
+        rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+        a, b = np.minimum(rows, A.col.astype(np.int64)), np.maximum(rows, A.col.astype(np.int64))
+        A.val = ((((a * 2654435761 + b * 40503) >> 9) % 256) - 128).astype(np.float32)
+    elif values == "frac":
+        A.val = A.val * np.float32(0.37)
     B = orc.problem_matrix(A)
     alpha, beta, _ = orc.default_params(B, 1.0)
     q, iters = 5, 30
@@ -269,11 +277,12 @@ def test_adoch_lattice_rows_per_lane():
     tr = orc.adoch(B, X0[:, 0], alpha, beta, iters, q)
     P = GpuProblem(A=A)
     try:
+        assert L.ising_get_info(P.ctx).step_val_bytes == val_bytes
         x, s, st, logs, acc = run_gpu(P.ctx, L, X0, 1, iters, alpha, beta, q, 0.0, B.n, A.n)
     finally:
         P.close()
     assert st[0].iters_done == iters
-    check_run("lattice L=400", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0], iters, True,
+    check_run(f"lattice L=400 values {values}", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0], iters, True,
               end_fixed_point=False)
 
 
