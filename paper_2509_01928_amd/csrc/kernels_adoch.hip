@@ -317,21 +317,23 @@ static void adoch_mv_vt(const CsrView& A, int grid, const double* x, const doubl
 hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, const double* zp,
                            double* z, double* xn, const AdochArgs& a, hipStream_t s) {
     int grid = grid_rows(A.n);
-    if (A.row_len == 4) {
-        // rows of 4 entries with implicit offsets stream best with two
-        // workgroups per compute unit, each lane walking many rows
-        // (measured on the 10^8-spin lattice, one restart: 1395 us per
-        // iteration against 1789 us with 8 per CU, 1522 with 4, 1658 with
-        // 1.5 and 1947 with 1)
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&
-            grid > 2 * cus)
-            grid = 2 * cus;
-    }
     // small-integer couplings on 4-entry rows: the library's exact 8-bit
     // copy of the values is streamed instead (a quarter of the FP32 bytes)
     const bool i8 = A.val8 && A.row_len == 4;
+    if (A.row_len == 4) {
+        // rows of 4 entries with implicit offsets stream best with few
+        // workgroups per compute unit, each lane walking many rows
+        // (measured on the 10^8-spin lattice, one restart; FP32 values:
+        // 1395 us per iteration with 2 per CU against 1789 with 8, 1522
+        // with 4, 1658 with 1.5 and 1947 with 1; 8-bit values: 1201 us with
+        // 3 against 1275 with 2 and 1237 with 4)
+        const int wpc = i8 ? 3 : 2;
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&
+            grid > wpc * cus)
+            grid = wpc * cus;
+    }
     CsrView B = A;
     if (i8) B.val = A.val8;
     DOCH_ADOCH_R(a.R, {

@@ -336,7 +336,8 @@ hipError_t launch_sweep_f(const CsrView& A, const SweepArgs& a, hipStream_t s) {
         // rows of 4 entries with implicit offsets (no dependent load chain to
         // hide) stream best with four workgroups per compute unit (measured
         // on the 10^8-spin lattice, 8 probes: 78.9 ms per sweep against 95.8
-        // with 16 per CU, 87.0 with 8 and 87.6 with 2)
+        // with 16 per CU, 87.0 with 8 and 87.6 with 2; with the 8-bit value
+        // copy 74.6 ms against 73.9 with 3, 82.9 with 8, 87.4 with 2)
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&

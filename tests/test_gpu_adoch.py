@@ -256,14 +256,15 @@ def test_adoch_csr_rejections_mixed_across_restarts():
 
 @pytest.mark.parametrize("values,val_bytes", [("pm1", 1), ("int8", 1), ("frac", 4)])
 def test_adoch_lattice_rows_per_lane(values, val_bytes):
-    """The lattice with its field at 160 000 rows: the product on rows of 4
-    entries runs two workgroups per CU, so every lane walks several rows;
+    """The lattice with its field at 409 600 rows: the product on rows of 4
+    entries runs two (FP32 values) or three (8-bit values) workgroups per
+    CU, 131 072 or 196 608 lanes, so every lane walks several rows;
     30 iterations against the oracle's ADOCH (decisions, H and r logs,
     iterates).  Couplings +-1 or integers over [-128, 127] (the product
     streams the library's 8-bit copy), or 0.37 * (+-1) (the FP32 values)."""
     import paper_2509_01928_amd as L
     from tests._util import GpuProblem
-    A = gen.torus_csr(400, 7381, h_std=0.1)
+    A = gen.torus_csr(640, 7381, h_std=0.1)
     if values == "int8":
         rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
         a, b = np.minimum(rows, A.col.astype(np.int64)), np.maximum(rows, A.col.astype(np.int64))
@@ -282,7 +283,7 @@ def test_adoch_lattice_rows_per_lane(values, val_bytes):
     finally:
         P.close()
     assert st[0].iters_done == iters
-    check_run(f"lattice L=400 values {values}", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0], iters, True,
+    check_run(f"lattice L=640 values {values}", tr, x[:, 0], s[:, 0], logs[0][0], logs[0][1], acc[:, 0], iters, True,
               end_fixed_point=False)
 
 
