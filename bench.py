@@ -99,9 +99,10 @@ _GEOMETRY_KERNEL = {0: ("csr_step_kernel", "1, 1, false"), 1: ("csr_step_kernel"
 
 
 def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False,
-                     val_bytes: int = 4) -> str:
+                     val_bytes: int = 4, col_bytes: int = 4) -> str:
     """Kernel instance timed on the lattice (FP32 couplings and field; the
-    lane-per-row kernels read the 8-bit copy of small-integer values)."""
+    lane-per-row kernels read the 8-bit copy of small-integer values and,
+    on 4-entry rows, the 16-bit cyclic column offsets)."""
     xt = "float" if x_dtype == "f32" else "double"
     if geometry == 8:                                      # the single-launch solve
         return f"resident_csr_kernel<{xt}, float, float, true>"
@@ -110,6 +111,8 @@ def step_kernel_name(geometry: int, x_dtype: str, implicit_offsets: bool = False
     if name == "csr_rowlane_kernel":
         tail += ", 4" if implicit_offsets else ", 0"      # the lattice's rows hold 4 entries
         vt = "signed char" if val_bytes == 1 else "float"
+        if col_bytes == 2:
+            tail += ", short"
     return f"{name}<{xt}, {vt}, float, true, {tail}>"
 
 
@@ -1283,7 +1286,7 @@ def main():
     E = torch.empty(1, dtype=torch.float64, device=dev)
     x_dtype = L.ISING_F32 if args.x_dtype == "f32" else L.ISING_F64
     info = L.ising_get_info(ctx)
-    row_len, val_bytes = info.row_len, info.step_val_bytes
+    row_len, val_bytes, col_bytes = info.row_len, info.step_val_bytes, info.step_col_bytes
     log(f"context created (constant row length {row_len}, {val_bytes} B per value in the lane-per-row step)")
     # launch-shape tuning is setup, outside the timed region
     if args.geometry >= -1:
@@ -1336,17 +1339,20 @@ def main():
     bytes_iter = 4 * (n + 1) + 4 * nnz + 4 * nnz + xb * np1 + xb * np1 + 4 * n
     csr_gbs = bytes_iter / (per_iter_ms * 1e-3) / 1e9
     # with a constant row length the lane-per-row kernels compute the row
-    # offsets instead of reading them, and with small-integer values (the
-    # lattice's +-1) they stream the library's exact 8-bit copy of the values,
-    # so the bytes the step needs are 8 B per edge-update; the headline
-    # fraction is taken on those, the CSR-format figure is kept beside it
+    # offsets instead of reading them; with small-integer values (the
+    # lattice's +-1) they stream the library's exact 8-bit copy of the
+    # values, and on 4-entry rows whose columns lie within 32767 of their row
+    # (cyclically) the 16-bit column offsets, so the bytes the step needs
+    # are 6 B per edge-update; the headline fraction is taken on those, the
+    # CSR-format figure is kept beside it
     rowlane = geometry in (3, 4)
     implicit = row_len > 0 and rowlane
     vb = val_bytes if rowlane else 4
-    kernel_bytes = bytes_iter - (4 * (n + 1) if implicit else 0) - (4 - vb) * nnz
+    cb = col_bytes if rowlane else 4
+    kernel_bytes = bytes_iter - (4 * (n + 1) if implicit else 0) - (4 - vb) * nnz - (4 - cb) * nnz
     achieved = kernel_bytes / (per_iter_ms * 1e-3) / 1e9
     workload = f"torus{args.L}"
-    kernel = step_kernel_name(geometry, args.x_dtype, implicit, vb)
+    kernel = step_kernel_name(geometry, args.x_dtype, implicit, vb, cb)
     traffic = load_traffic(kernel, f"{workload}_{args.x_dtype}")
     edge_updates = float(nnz) * args.iters * args.steps
     out = {
@@ -1374,6 +1380,8 @@ def main():
             "row_offsets": (f"implicit (every row holds {row_len} entries)" if implicit else "read"),
             "values_streamed": ("8-bit copy (every value an integer in [-128, 127])" if vb == 1
                                 else "f32 as stored"),
+            "columns_streamed": ("16-bit cyclic offsets col - i (every one within 32767)" if cb == 2
+                                 else "int32 as stored"),
         },
         "iteration_us": per_iter_ms * 1e3,
         "energy": energy,

@@ -102,6 +102,12 @@ typedef struct {
                               library then keeps an exact 8-bit copy beside
                               the values, nnz more bytes of device memory),
                               else the size of val_dtype; 8 for dense      */
+    int32_t step_col_bytes; /* bytes per column index that step streams: 2
+                              when every row holds 4 entries, the 8-bit
+                              value copy is kept and every column lies
+                              within 32767 of its row modulo n (the library
+                              then keeps each entry's offset col - i as 16
+                              bits, 2 nnz more bytes); else 4; 0 for dense */
 } ising_info;
 
 /* ---------------------------------------------------------------- create
@@ -465,7 +471,9 @@ ising_status ising_autotune_batch(ising_ctx* ctx, const double* x0_dev, int32_t 
  * one row per lane with the whole grid sweeping the rows together, rows of
  * up to one (3) or two (4) aligned 4-entry chunks loaded at once (longer rows
  * take a slower path; with a constant row length, see ising_info.row_len,
- * the row offsets are implicit and not read); 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in
+ * the row offsets are implicit and not read; with small-integer values they
+ * stream the library's compact copies, see ising_info.step_val_bytes and
+ * step_col_bytes); 5, 6, 7 = geometries 0, 1, 2 with blocks handed out in
  * order from a per-XCD counter; 8 = resident: the whole single-restart DOCH
  * solve runs in one cooperative launch, with a grid-wide barrier between
  * iterations instead of a launch per iteration (for problems whose

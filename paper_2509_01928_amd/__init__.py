@@ -60,7 +60,7 @@ class ising_info(ctypes.Structure):
                 ("is_dense", ctypes.c_int32), ("has_field", ctypes.c_int32),
                 ("integer_J", ctypes.c_int32), ("val_dtype", ctypes.c_int32),
                 ("row_len", ctypes.c_int32), ("geometry", ctypes.c_int32),
-                ("step_val_bytes", ctypes.c_int32)]
+                ("step_val_bytes", ctypes.c_int32), ("step_col_bytes", ctypes.c_int32)]
 
 
 class IsingError(RuntimeError):

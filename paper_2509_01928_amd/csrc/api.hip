@@ -99,6 +99,7 @@ CsrView csr_view(const ising_ctx* c) {
     v.ht = c->ht;
     v.row_len = c->row_len;
     v.val8 = c->val8;
+    v.col16 = c->col16;
     return v;
 }
 
@@ -153,10 +154,13 @@ int default_geometry(int64_t n, int64_t nnz) {
 
 // Kernels that read row offsets hide their dependent load chains with as
 // many resident workgroups as fit; with 4-entry rows and implicit offsets
-// (no chain) four per CU stream fastest (measured on gfx950, 10^8-spin
-// lattice: 795 us against 878 us with all that fit).
-int default_wg_per_cu(int geometry, int row_len) {
-    return ((geometry == 3 || geometry == 4) && row_len == 4) ? 4 : 0;
+// (no chain) four per CU stream fastest with 32-bit column indices
+// (measured on gfx950, 10^8-spin lattice: 795 us against 878 us with all
+// that fit; 624 against 628 with 8-bit values), but with the 16-bit column
+// offsets all that fit are fastest again (546 us against 554 with six, 580
+// with five, 628 with four).
+int default_wg_per_cu(int geometry, int row_len, bool col16) {
+    return ((geometry == 3 || geometry == 4) && row_len == 4 && !col16) ? 4 : 0;
 }
 
 ising_status ensure_plan(ising_ctx* c, int geometry, doch::CsrPlan** out) {
@@ -184,6 +188,7 @@ void free_ctx(ising_ctx* c) {
     dev_free(c->col);
     dev_free(c->val);
     dev_free(c->val8);
+    dev_free(c->col16);
     dev_free(c->h);
     dev_free(c->J);
     for (auto& p : c->plans) dev_free(p.binfo);
@@ -636,11 +641,21 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
         if ((e = dev_alloc(&c->val8, padded)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(val8)"));
         if ((e = hipMemsetAsync(c->val8 + nnz, 0, doch::kCsrPad, s)) != hipSuccess) return bail(hip_fail(e, "memset pad"));
         if ((e = doch::launch_csr_pack_i8(csr_view(c), c->val8, s)) != hipSuccess) return bail(hip_fail(e, "pack values"));
+        // 4-entry rows (the lattice) whose columns all lie within 32767 of
+        // their row, cyclically: the indices as 16-bit offsets too
+        if (c->row_len == 4 && !flags[4]) {
+            if ((e = dev_alloc(&c->col16, padded * sizeof(int16_t))) != hipSuccess)
+                return bail(hip_fail(e, "hipMalloc(col16)"));
+            if ((e = hipMemsetAsync(c->col16 + nnz, 0, doch::kCsrPad * sizeof(int16_t), s)) != hipSuccess)
+                return bail(hip_fail(e, "memset pad"));
+            if ((e = doch::launch_csr_pack_col16(csr_view(c), c->col16, s)) != hipSuccess)
+                return bail(hip_fail(e, "pack columns"));
+        }
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sync"));
     }
     c->rp_host = std::move(rp_host);
     c->geometry = default_geometry(n, nnz);
-    c->wg_per_cu = default_wg_per_cu(c->geometry, c->row_len);
+    c->wg_per_cu = default_wg_per_cu(c->geometry, c->row_len, c->col16 != nullptr);
     doch::CsrPlan* plan = nullptr;
     if (c->geometry != doch::kGeometryResident && (st = ensure_plan(c, c->geometry, &plan)) != ISING_OK)
         return bail(st);
@@ -739,6 +754,7 @@ ising_status ising_get_info(const ising_ctx* ctx, ising_info* out) {
     out->row_len = ctx->row_len;
     out->geometry = ctx->batch ? -1 : ctx->geometry;
     out->step_val_bytes = ctx->val8 ? 1 : static_cast<int32_t>(ctx->dense ? 8 : dtype_size(ctx->vt));
+    out->step_col_bytes = ctx->col16 ? 2 : (ctx->dense ? 0 : 4);
     return ISING_OK;
 }
 
@@ -968,7 +984,7 @@ ising_status ising_set_geometry(ising_ctx* ctx, int32_t geometry, int32_t wg_per
         if (st != ISING_OK) return st;
     }
     ctx->geometry = g;
-    ctx->wg_per_cu = geometry < 0 ? default_wg_per_cu(g, ctx->row_len) : wg_per_cu;
+    ctx->wg_per_cu = geometry < 0 ? default_wg_per_cu(g, ctx->row_len, ctx->col16 != nullptr) : wg_per_cu;
     return ISING_OK;
 }
 

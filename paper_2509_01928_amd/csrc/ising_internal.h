@@ -59,6 +59,10 @@ struct CsrView {
     int row_len;            // d > 0: every row holds d entries, row i starts at d i
     const int8_t* val8 = nullptr;  // the values as 8-bit integers when every one is an
                             // integer in [-128, 127] (padded like val), else nullptr
+    const int16_t* col16 = nullptr;  // each entry's cyclic column offset col - i,
+                            // taken into [-32768, 32767] modulo n, when every row
+                            // holds 4 entries, val8 is kept and every offset fits
+                            // (padded like col), else nullptr
 };
 
 struct DenseView {
@@ -308,6 +312,7 @@ struct ising_ctx {
     int32_t* col = nullptr;
     void* val = nullptr;
     int8_t* val8 = nullptr;  // 8-bit copy of val read by the lane-per-row step
+    int16_t* col16 = nullptr;  // 16-bit cyclic column offsets read by that step
     int vt = ISING_F32;
     void* h = nullptr;
     int ht = ISING_F32;
@@ -409,6 +414,9 @@ hipError_t launch_csr_validate(const CsrView& A, int32_t* flags, hipStream_t s);
 // out[0, nnz) = the values as 8-bit integers (valid when csr_validate
 // raised no flags[3]); out must hold nnz + kCsrPad bytes
 hipError_t launch_csr_pack_i8(const CsrView& A, int8_t* out, hipStream_t s);
+// out[0, nnz) = every entry's cyclic column offset (valid when csr_validate
+// raised no flags[4]); out must hold nnz + kCsrPad entries
+hipError_t launch_csr_pack_col16(const CsrView& A, int16_t* out, hipStream_t s);
 void csr_geometry(int geometry, int* rows, int* span);
 hipError_t launch_csr_step(const CsrView& A, const CsrPlan& plan, const StepArgs& a,
                            hipStream_t s);

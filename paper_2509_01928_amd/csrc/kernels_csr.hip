@@ -258,9 +258,11 @@ __global__ __launch_bounds__(NT) void csr_step_kernel(
 // RL: 0 = row offsets read from rp; -1 = every row holds row_len entries
 // (row i starts at row_len i, rp not read); d > 0 = the same with row_len = d
 // known at compile time (d = 4: the 4-neighbour lattice).
-template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC, int RL>
+// CT: int32_t = column indices; int16_t = each entry's cyclic column offset
+// (col - i taken into [-32768, 32767] modulo n), decoded back to the column.
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC, int RL, typename CT = int32_t>
 __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
-    int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    int64_t n, const int32_t* __restrict__ rp, const CT* __restrict__ col,
     const VT* __restrict__ val, const HT* __restrict__ h, int row_len, StepArgs a) {
     if (a.state->done) return;
     __shared__ double red[kNumPartials * NW];
@@ -274,11 +276,22 @@ __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
     const int64_t hi = n;
     const int64_t first = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * NT;
+    // column of row i's entry whose stored index is c
+    auto column = [n](int64_t i, int c) -> int64_t {
+        if constexpr (sizeof(CT) == 4) {
+            return c;
+        } else {
+            int64_t j = i + c;
+            j += j < 0 ? n : 0;
+            j -= j >= n ? n : 0;
+            return j;
+        }
+    };
     for (int64_t base = first; base < hi; base += stride * U) {
         int s[U], e[U], a0[U];
         XT xi[U];
         HT hv[U];
-        typename Vec4<int>::type cv[U][MAXC];
+        typename Vec4<CT>::type cv[U][MAXC];
         typename Vec4<VT>::type vv[U][MAXC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -322,7 +335,7 @@ __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
                         const int cc[4] = {cv[u][c].x, cv[u][c].y, cv[u][c].z, cv[u][c].w};
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            if (b0 + q >= s[u] && b0 + q < e[u]) g[u][c][q] = x[cc[q]];
+                            if (b0 + q >= s[u] && b0 + q < e[u]) g[u][c][q] = x[column(i, cc[q])];
                     }
                 }
             }
@@ -345,7 +358,7 @@ __global__ __launch_bounds__(NT) void csr_rowlane_kernel(
                     }
                 } else {
                     for (int k = s[u]; k < e[u]; ++k)
-                        z = dadd(z, dmul(static_cast<double>(val[k]), static_cast<double>(x[col[k]])));
+                        z = dadd(z, dmul(static_cast<double>(val[k]), static_cast<double>(x[column(i, col[k])])));
                 }
                 const double hq = FIELD ? static_cast<double>(hv[u]) : 0.0;
                 if (FIELD) z = dadd(z, dmul(hq, t_old));
@@ -505,7 +518,8 @@ __global__ __launch_bounds__(NT) void csr_energy8_kernel(
 // ------------------------------------------------------------ validation
 // flags[0]: malformed CSR, flags[1]: nonzero diagonal, flags[2]: a value is
 // not an integer of magnitude < 2^31, flags[3]: a value is not an integer in
-// [-128, 127].
+// [-128, 127], flags[4]: an entry's cyclic column offset (col - i modulo n,
+// taken into [-32768, 32767]) does not fit 16 bits.
 template <typename VT>
 __global__ __launch_bounds__(NT) void csr_validate_kernel(
     int64_t n, int64_t nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -526,6 +540,10 @@ __global__ __launch_bounds__(NT) void csr_validate_kernel(
             if (c == i && v != 0.0) atomicOr(flags + 1, 1);
             if (!(v == floor(v)) || fabs(v) >= 2147483648.0) atomicOr(flags + 2, 1);
             if (!(v == floor(v)) || v < -128.0 || v > 127.0) atomicOr(flags + 3, 1);
+            int64_t d = static_cast<int64_t>(c) - i;
+            if (d > 32767) d -= n;
+            else if (d < -32768) d += n;
+            if (d > 32767 || d < -32768) atomicOr(flags + 4, 1);
         }
     }
 }
@@ -752,9 +770,12 @@ hipError_t launch_step_t(const CsrView& A, const CsrPlan& plan, const StepArgs& 
     return hipGetLastError();
 }
 
-template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC, int RL>
+template <typename XT, typename VT, typename HT, bool FIELD, int U, int MAXC, int RL, typename CT = int32_t>
 hipError_t launch_rowlane_r(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
-    auto kern = csr_rowlane_kernel<XT, VT, HT, FIELD, U, MAXC, RL>;
+    auto kern = csr_rowlane_kernel<XT, VT, HT, FIELD, U, MAXC, RL, CT>;
+    const CT* colp;
+    if constexpr (sizeof(CT) == 2) colp = A.col16;
+    else colp = A.col;
     static int per_cu = 0;
     static int cus = 0;
     if (per_cu == 0) {
@@ -775,7 +796,7 @@ hipError_t launch_rowlane_r(const CsrView& A, const CsrPlan& plan, const StepArg
     if (grid > need) grid = need;
     if (grid >= 8) grid &= ~static_cast<int64_t>(7);
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NT), 0, s, A.n, A.rp, A.col,
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NT), 0, s, A.n, A.rp, colp,
                        static_cast<const VT*>(A.val), static_cast<const HT*>(A.h), A.row_len, a);
     return hipGetLastError();
 }
@@ -805,6 +826,12 @@ template <typename XT, typename HT, bool FIELD>
 hipError_t launch_rowlane_i8_f(const CsrView& A, const CsrPlan& plan, const StepArgs& a, hipStream_t s) {
     CsrView B = A;
     B.val = A.val8;
+    // 4-entry rows whose cyclic column offsets fit 16 bits: indices streamed
+    // as those offsets too
+    if (A.col16 && A.row_len == 4) {
+        if (plan.geometry == 3) return launch_rowlane_r<XT, int8_t, HT, FIELD, 1, 1, 4, int16_t>(B, plan, a, s);
+        return launch_rowlane_r<XT, int8_t, HT, FIELD, 1, 2, 4, int16_t>(B, plan, a, s);
+    }
     if (plan.geometry == 3) return launch_rowlane_t<XT, int8_t, HT, FIELD, 1, 1>(B, plan, a, s);
     return launch_rowlane_t<XT, int8_t, HT, FIELD, 1, 2>(B, plan, a, s);
 }
@@ -938,6 +965,28 @@ __global__ __launch_bounds__(NT) void csr_pack_i8_kernel(int64_t nnz, const VT* 
         out[e] = static_cast<int8_t>(static_cast<int>(val[e]));
 }
 }  // namespace
+
+namespace {
+// out[e] = row i's cyclic column offset of entry e (checked to fit 16 bits)
+__global__ __launch_bounds__(NT) void csr_pack_col16_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            int16_t* __restrict__ out) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * NT) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int64_t d = static_cast<int64_t>(col[e]) - i;
+            if (d > 32767) d -= n;
+            else if (d < -32768) d += n;
+            out[e] = static_cast<int16_t>(d);
+        }
+    }
+}
+}  // namespace
+
+hipError_t launch_csr_pack_col16(const CsrView& A, int16_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(csr_pack_col16_kernel, dim3(grid_for_rows(A.n)), dim3(NT), 0, s, A.n, A.rp, A.col, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_csr_pack_i8(const CsrView& A, int8_t* out, hipStream_t s) {
     if (A.nnz <= 0) return hipSuccess;

@@ -82,6 +82,7 @@ def test_lattice_rowlane_multi_trip(torus1024, geometry, wg_per_cu, x_dtype):
     configuration of the 10^8-spin lattice."""
     info, x, s, st, H, r = _run(torus1024, geometry, wg_per_cu, x_dtype)
     assert info.row_len == 4          # implicit offsets, compile-time length
+    assert info.step_val_bytes == 1 and info.step_col_bytes == 2
     _check(torus1024, f"torus L=1024 geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
            info, x, s, st, H, r, x_dtype)
 
@@ -138,7 +139,7 @@ def torus600_frac():
 @pytest.mark.parametrize("geometry,wg_per_cu", [(3, 4), (4, 0)])
 def test_lattice_rowlane_8bit_values(torus600_int8, geometry, wg_per_cu, x_dtype):
     info, x, s, st, H, r = _run(torus600_int8, geometry, wg_per_cu, x_dtype)
-    assert info.row_len == 4 and info.step_val_bytes == 1
+    assert info.row_len == 4 and info.step_val_bytes == 1 and info.step_col_bytes == 2
     _check(torus600_int8, f"torus L=600 values in [-128, 127] geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
            info, x, s, st, H, r, x_dtype)
 
@@ -147,7 +148,7 @@ def test_lattice_rowlane_8bit_values(torus600_int8, geometry, wg_per_cu, x_dtype
 @pytest.mark.parametrize("geometry,wg_per_cu", [(3, 4), (4, 0)])
 def test_lattice_rowlane_fp32_values(torus600_frac, geometry, wg_per_cu, x_dtype):
     info, x, s, st, H, r = _run(torus600_frac, geometry, wg_per_cu, x_dtype)
-    assert info.row_len == 4 and info.step_val_bytes == 4
+    assert info.row_len == 4 and info.step_val_bytes == 4 and info.step_col_bytes == 4
     _check(torus600_frac, f"torus L=600 values 0.37 * (+-1) geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
            info, x, s, st, H, r, x_dtype)
 
@@ -169,5 +170,36 @@ def test_8bit_copy_only_for_8bit_integers():
         P = GpuProblem(A=A)
         try:
             assert Lb.ising_get_info(P.ctx).step_val_bytes == want, top
+        finally:
+            P.close()
+
+
+@pytest.fixture(scope="module")
+def circulant_far():
+    # 4-entry rows, +-1 values, columns 40 000 away: the 8-bit values are
+    # streamed with the int32 column indices (the offsets do not fit 16 bits)
+    return _case(gen.circulant_csr(300_000, [1, 40_000], 1109, h_std=0.1), 2109)
+
+
+@pytest.mark.parametrize("x_dtype", ["f32", "f64"])
+@pytest.mark.parametrize("geometry,wg_per_cu", [(3, 4), (4, 0)])
+def test_rowlane_8bit_values_int32_columns(circulant_far, geometry, wg_per_cu, x_dtype):
+    info, x, s, st, H, r = _run(circulant_far, geometry, wg_per_cu, x_dtype)
+    assert info.row_len == 4 and info.step_val_bytes == 1 and info.step_col_bytes == 4
+    _check(circulant_far, f"circulant offsets 1, 40000 geometry {geometry} wg/CU {wg_per_cu} {x_dtype}",
+           info, x, s, st, H, r, x_dtype)
+
+
+def test_16bit_column_offsets_only_when_they_fit():
+    """Offsets of 32767 (and the wrap-around ones of the lattice) fit 16
+    bits; an offset of 32768 does not, since +32768 is out of range."""
+    import paper_2509_01928_amd as Lb
+    for offs, want in (([1, 32767], 2), ([1, 32768], 4), ([3, 32000], 2)):
+        A = gen.circulant_csr(70_000, offs, 1110)
+        P = GpuProblem(A=A)
+        try:
+            info = Lb.ising_get_info(P.ctx)
+            assert info.row_len == 4 and info.step_val_bytes == 1
+            assert info.step_col_bytes == want, offs
         finally:
             P.close()
