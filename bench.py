@@ -888,11 +888,13 @@ def bench_adoch(args):
     #            iterations only
     rejected = float(np.mean(acc == 0))
     # the product on 4-entry rows computes the row starts and streams the
-    # library's 8-bit copy of the +-1 values
-    vb = L.ising_get_info(ctx).step_val_bytes
-    kname = f"adoch_mv_kernel<{'signed char' if vb == 1 else 'float'}, float, true, 4, 1, true>"
+    # library's 8-bit copy of the +-1 values and 16-bit column offsets
+    info = L.ising_get_info(ctx)
+    vb, cb = info.step_val_bytes, info.step_col_bytes
+    kname = (f"adoch_mv_kernel<{'signed char' if vb == 1 else 'float'}, float, true, 4, 1, true"
+             + (", short>" if cb == 2 else ">"))
     traffic = load_traffic(kname, f"adoch_torus{args.L}", ADOCH_SOURCES)
-    prod = (4 + vb) * nnz + 4 * n + 5 * 8 * np1
+    prod = (cb + vb) * nnz + 4 * n + 5 * 8 * np1
     upd = 3 * 8 * np1
     bytes_iter = prod + rejected * upd
     achieved = bytes_iter / (it_us * 1e-6) / 1e9

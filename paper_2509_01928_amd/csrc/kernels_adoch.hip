@@ -22,6 +22,8 @@
 // restart is copied forward unchanged.  Iterates rotate through three
 // buffers (x^(k-1), x^(k), x^(k+1)), products through two.  FP64 throughout.
 #include "adoch_common.h"
+
+#include <type_traits>
 #include "device_common.h"
 #include "ising_internal.h"
 
@@ -44,9 +46,11 @@ constexpr int NW = NT / kWave;
 // ends: the second pass over x^(k), x^(k-1), z_k, z_(k-1) and x^(k+1) is
 // made only for a rejected restart (adoch_update_kernel's fix-up mode).
 // The value written is the one the update would write, bit for bit.
-template <typename VT, typename HT, bool FIELD, int RL, int R, bool OPT>
+// CT: int32_t = column indices; int16_t (4-entry rows only) = each entry's
+// cyclic column offset col - i, taken into [-32768, 32767] modulo n.
+template <typename VT, typename HT, bool FIELD, int RL, int R, bool OPT, typename CT = int32_t>
 __global__ __launch_bounds__(NT) void adoch_mv_kernel(
-    int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    int64_t n, const int32_t* __restrict__ rp, const CT* __restrict__ col,
     const VT* __restrict__ val, const HT* __restrict__ h, const double* __restrict__ x,
     const double* __restrict__ xp, const double* __restrict__ zp, double* __restrict__ z,
     double* __restrict__ xn, AdochArgs a) {
@@ -75,14 +79,22 @@ __global__ __launch_bounds__(NT) void adoch_mv_kernel(
         if constexpr (RL == 4) {
             const auto cv = ld_stream4(col + 4 * i);
             const auto vv = ld_stream4(val + 4 * i);
-            const int cc[4] = {cv.x, cv.y, cv.z, cv.w};
+            int64_t cc[4] = {cv.x, cv.y, cv.z, cv.w};
+            if constexpr (sizeof(CT) == 2) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    cc[q] += i;
+                    cc[q] += cc[q] < 0 ? n : 0;
+                    cc[q] -= cc[q] >= n ? n : 0;
+                }
+            }
             const double v[4] = {static_cast<double>(vv.x), static_cast<double>(vv.y),
                                  static_cast<double>(vv.z), static_cast<double>(vv.w)};
             double g[4][R];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int r = 0; r < R; ++r) g[q][r] = x[static_cast<int64_t>(cc[q]) * R + r];
+                for (int r = 0; r < R; ++r) g[q][r] = x[cc[q] * R + r];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -292,6 +304,18 @@ static void adoch_mv_go(const CsrView& A, int grid, const double* x, const doubl
                         double* z, double* xn, const AdochArgs& a, hipStream_t s) {
     const VT* v = static_cast<const VT*>(A.val);
     const HT* h = static_cast<const HT*>(A.h);
+    if constexpr (std::is_same<VT, int8_t>::value) {
+        // 4-entry rows with the 16-bit column offsets (kept with the 8-bit values)
+        if (A.col16 && A.row_len == 4) {
+            if (xn)
+                hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4, RR, true, int16_t>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, A.rp, A.col16, v, h, x, xp, zp, z, xn, a);
+            else
+                hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4, RR, false, int16_t>), dim3(grid), dim3(NT), 0, s,
+                                   A.n, A.rp, A.col16, v, h, x, xp, zp, z, xn, a);
+            return;
+        }
+    }
     if (A.row_len == 4 && xn)
         hipLaunchKernelGGL((adoch_mv_kernel<VT, HT, F, 4, RR, true>), dim3(grid), dim3(NT), 0, s, A.n, A.rp,
                            A.col, v, h, x, xp, zp, z, xn, a);

@@ -278,7 +278,8 @@ def test_adoch_lattice_rows_per_lane(values, val_bytes):
     tr = orc.adoch(B, X0[:, 0], alpha, beta, iters, q)
     P = GpuProblem(A=A)
     try:
-        assert L.ising_get_info(P.ctx).step_val_bytes == val_bytes
+        info = L.ising_get_info(P.ctx)
+        assert info.step_val_bytes == val_bytes and info.step_col_bytes == (2 if val_bytes == 1 else 4)
         x, s, st, logs, acc = run_gpu(P.ctx, L, X0, 1, iters, alpha, beta, q, 0.0, B.n, A.n)
     finally:
         P.close()
