@@ -636,16 +636,23 @@ ising_status ising_create_csr(int64_t n, int64_t nnz, const int32_t* row_ptr_dev
         c->row_len = regular ? static_cast<int32_t>(d) : 0;
     }
     // every value an integer in [-128, 127] (the lattice's +-1 among them):
-    // an exact 8-bit copy that the lane-per-row step streams instead
-    if (nnz > 0 && !flags[3]) {
-        if ((e = dev_alloc(&c->val8, padded)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(val8)"));
+    // an exact 8-bit copy that the lane-per-row step streams instead; the
+    // compact copies are an optimisation, so a device too full to hold
+    // them runs without them
+    if (nnz > 0 && !flags[3] && dev_alloc(&c->val8, padded) != hipSuccess) {
+        c->val8 = nullptr;
+        (void)hipGetLastError();
+    }
+    if (c->val8) {
         if ((e = hipMemsetAsync(c->val8 + nnz, 0, doch::kCsrPad, s)) != hipSuccess) return bail(hip_fail(e, "memset pad"));
         if ((e = doch::launch_csr_pack_i8(csr_view(c), c->val8, s)) != hipSuccess) return bail(hip_fail(e, "pack values"));
         // 4-entry rows (the lattice) whose columns all lie within 32767 of
         // their row, cyclically: the indices as 16-bit offsets too
-        if (c->row_len == 4 && !flags[4]) {
-            if ((e = dev_alloc(&c->col16, padded * sizeof(int16_t))) != hipSuccess)
-                return bail(hip_fail(e, "hipMalloc(col16)"));
+        if (c->row_len == 4 && !flags[4] && dev_alloc(&c->col16, padded * sizeof(int16_t)) != hipSuccess) {
+            c->col16 = nullptr;
+            (void)hipGetLastError();
+        }
+        if (c->col16) {
             if ((e = hipMemsetAsync(c->col16 + nnz, 0, doch::kCsrPad * sizeof(int16_t), s)) != hipSuccess)
                 return bail(hip_fail(e, "memset pad"));
             if ((e = doch::launch_csr_pack_col16(csr_view(c), c->col16, s)) != hipSuccess)
