@@ -1148,7 +1148,8 @@ def bench_tune_eta(args):
         info = L.ising_get_info(ctx)
         four = info.row_len == 4
         vb = info.step_val_bytes if four else (2 if args.tune_instance == "s5" else 4)
-        bytes_iter = ((0 if four else 4 * (n + 1)) + (4 + vb) * nnz + (4 * n if field else 0)
+        cb = 4                  # the sweep keeps the int32 column indices
+        bytes_iter = ((0 if four else 4 * (n + 1)) + (cb + vb) * nnz + (4 * n if field else 0)
                       + 2 * 8 * len(etas) * (n + 1))
     sweep_bytes = bytes_iter * probe
     if args.tune_instance == "procedural":
@@ -1179,7 +1180,8 @@ def bench_tune_eta(args):
         # the batched pass's algorithmic bytes over the wall time of whole
         # sweeps (energies and parameter setting included)
         "roofline": (sweep_roof if args.tune_instance == "procedural" else
-                     {"kernel": "csr_sweep_kernel" + ("<signed char, float, true, 8, 4>" if field and vb == 1 else ""),
+                     {"kernel": "csr_sweep_kernel" + (f"<signed char, float, true, 8, 4{', short' if cb == 2 else ''}>"
+                                                      if field and vb == 1 else ""),
                       "bound": "hbm",
                       "achieved": sweep_bytes / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": sweep_bytes / dt / 1e9 / HBM_PEAK_GBS,

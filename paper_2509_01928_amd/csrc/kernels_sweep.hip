@@ -337,7 +337,10 @@ hipError_t launch_sweep_f(const CsrView& A, const SweepArgs& a, hipStream_t s) {
         // hide) stream best with four workgroups per compute unit (measured
         // on the 10^8-spin lattice, 8 probes: 78.9 ms per sweep against 95.8
         // with 16 per CU, 87.0 with 8 and 87.6 with 2; with the 8-bit value
-        // copy 74.6 ms against 73.9 with 3, 82.9 with 8, 87.4 with 2)
+        // copy 74.6 ms against 73.9 with 3, 82.9 with 8, 87.4 with 2).  The
+        // 16-bit column offsets are not used here: decoding them in all
+        // eight lanes of a row cost more than the bytes saved (79.2 against
+        // 74.8 ms per sweep on one box)
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&
