@@ -350,8 +350,10 @@ hipError_t launch_adoch_mv(const CsrView& A, const double* x, const double* xp, 
         // (measured on the 10^8-spin lattice, one restart; FP32 values:
         // 1395 us per iteration with 2 per CU against 1789 with 8, 1522
         // with 4, 1658 with 1.5 and 1947 with 1; 8-bit values: 1201 us with
-        // 3 against 1275 with 2 and 1237 with 4)
-        const int wpc = i8 ? 3 : 2;
+        // 3 against 1275 with 2 and 1237 with 4; 8-bit values and 16-bit
+        // column offsets: 1101 us with 4 against 1117 with 3, 1203 with 6
+        // and 1399 with 8)
+        const int wpc = i8 ? (A.col16 ? 4 : 3) : 2;
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&

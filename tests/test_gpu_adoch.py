@@ -257,8 +257,9 @@ def test_adoch_csr_rejections_mixed_across_restarts():
 @pytest.mark.parametrize("values,val_bytes", [("pm1", 1), ("int8", 1), ("frac", 4)])
 def test_adoch_lattice_rows_per_lane(values, val_bytes):
     """The lattice with its field at 409 600 rows: the product on rows of 4
-    entries runs two (FP32 values) or three (8-bit values) workgroups per
-    CU, 131 072 or 196 608 lanes, so every lane walks several rows;
+    entries runs two (FP32 values), three (8-bit values) or four (8-bit
+    values and 16-bit column offsets) workgroups per CU, at most 262 144
+    lanes, so every lane walks several rows;
     30 iterations against the oracle's ADOCH (decisions, H and r logs,
     iterates).  Couplings +-1 or integers over [-128, 127] (the product
     streams the library's 8-bit copy), or 0.37 * (+-1) (the FP32 values)."""
