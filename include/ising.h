@@ -100,14 +100,17 @@ typedef struct {
                               CSR step (geometries 3, 4) streams: 1 when
                               every value is an integer in [-128, 127] (the
                               library then keeps an exact 8-bit copy beside
-                              the values, nnz more bytes of device memory),
-                              else the size of val_dtype; 8 for dense      */
+                              the values, nnz more bytes of device memory;
+                              the ADOCH product and the eta sweep on rows of
+                              4 entries read it too), else the size of
+                              val_dtype; 8 for dense                       */
     int32_t step_col_bytes; /* bytes per column index that step streams: 2
                               when every row holds 4 entries, the 8-bit
                               value copy is kept and every column lies
                               within 32767 of its row modulo n (the library
                               then keeps each entry's offset col - i as 16
-                              bits, 2 nnz more bytes); else 4; 0 for dense */
+                              bits, 2 nnz more bytes; the ADOCH product
+                              reads it too); else 4; 0 for dense           */
 } ising_info;
 
 /* ---------------------------------------------------------------- create
